@@ -1,0 +1,123 @@
+/*
+ * bmhss -- MI355X (gfx950) library for the weakly singular Burton-Miller (WSBM)
+ * Nystrom system of 2D TE-mode transmission scattering and its proxy-surface
+ * HSS fast direct solver.
+ *
+ * Paper: "Proxy-surface-based fast direct solver for TE-mode scattering problems
+ * on distributed memory systems" (Matsumoto, Yokota).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Complex numbers are interleaved FP64 (re, im), the layout of
+ *    torch.complex128 / std::complex<double>.
+ *  - Unknowns are node-interleaved: unknown 2j is u_j (the field), unknown 2j+1
+ *    is q_j (the scaled normal derivative, Sec. II).  Row 2i holds the first
+ *    row of Eq. (3) at node i, row 2i+1 the second row.
+ *  - Matrices are row-major; `ld` is the leading dimension in complex elements.
+ *  - Array arguments documented as "device" must be device pointers (HIP
+ *    memory of the current device); "host" arguments are host pointers.  The
+ *    caller owns every array; the library owns the opaque handles it creates
+ *    and keeps its own device copy of the node data.
+ *  - Device work is enqueued on the caller's stream and is asynchronous unless
+ *    stated otherwise.  A handle must not be used from several host threads at
+ *    once without external synchronisation.
+ *  - Every call returns a status code.  On BM_EINVAL nothing has been enqueued.
+ *    bm_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef BMHSS_H
+#define BMHSS_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BM_OK = 0,
+    BM_EINVAL = 1,    /* bad shape, non-finite input, clockwise curve, k <= 0, ... */
+    BM_ENOMEM = 2,    /* device or host allocation failed */
+    BM_EHIP = 3,      /* HIP runtime error */
+    BM_ESINGULAR = 4, /* zero pivot in an LU factorisation */
+    BM_ESTATE = 5     /* handle in the wrong state */
+};
+
+typedef struct bm_geom bm_geom;
+typedef struct bm_problem bm_problem;
+
+/* Material constants: wavenumbers k_j = omega sqrt(eps_j mu_j) and permittivities
+ * of the exterior (0) and interior (1) media (Sec. II, Table I).  The
+ * Burton-Miller constant is alpha = i/k0 (stated after Eq. (2)). */
+typedef struct {
+    double k0, k1, eps0, eps1;
+} bm_media;
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* bm_last_error(void);
+
+/* ---- Boundary discretisation (Sec. II; Nystrom method with trapezoidal nodes) ----
+ * ncurves closed curves, curve c sampled at n_per_curve[c] >= 8 equispaced
+ * parameter values t_j = 2 pi j / n_c, counter-clockwise.  xyd is a 6 x N_total
+ * row-major FP64 array: rows x, y, x'(t), y'(t), x''(t), y''(t); curves are
+ * concatenated.  xyd is a device pointer if on_device != 0, else a host pointer.
+ * The library computes, on the device, outward normals n = (y', -x')/|x'|,
+ * weights w = (2 pi/n_c)|x'| and curvature, and keeps them.  Validation (finite
+ * values, non-degenerate speed, counter-clockwise orientation) is done on the
+ * host; this call synchronises `stream`.  Returns BM_EINVAL on bad input. */
+int bm_geom_create(int ncurves, const int64_t* n_per_curve, const double* xyd, int on_device,
+                   hipStream_t stream, bm_geom** out);
+int bm_geom_destroy(bm_geom* g);
+/* Total number of nodes, or -1 for a null handle. */
+int64_t bm_geom_size(const bm_geom* g);
+/* Copy the node data to `soa` (device, 6 x N row-major: x, y, nx, ny, w, kappa). */
+int bm_geom_nodes(const bm_geom* g, double* soa, hipStream_t stream);
+
+/* ---- Problem: geometry + media.  The geometry must outlive the problem. ---- */
+int bm_problem_create(const bm_geom* g, const bm_media* media, bm_problem** out);
+int bm_problem_destroy(bm_problem* p);
+
+/* ---- Right-hand side of Eq. (3) for a plane wave (Sec. IV) ----
+ * u_in = exp(i k0 (cos angle, sin angle) . x); rhs (device, 2N complex):
+ * rhs[2i] = 0, rhs[2i+1] = -u_in(x_i) - alpha du_in/dn(x_i). */
+int bm_rhs_plane_wave(const bm_problem* p, double angle, double* rhs, hipStream_t stream);
+
+/* ---- Matrix entries: Eq. (3) / Eq. (5), one-point corrected diagonal ----
+ * Full matrix (device, 2N x 2N complex, row-major, ld >= 2N). */
+int bm_assemble_dense(const bm_problem* p, double* A, int64_t ld, hipStream_t stream);
+
+/* Block A(rows, cols) for node index lists (device int64 arrays, values in
+ * [0, N)); out (device) is 2nr x 2nc complex with leading dimension ld >= 2nc.
+ * Pairs with rows[a] == cols[b] get the corrected diagonal block of Eq. (5)
+ * (delta_ij = 1).  Indices are not validated on the device: out-of-range
+ * values are the caller's error. */
+int bm_assemble_block(const bm_problem* p, const int64_t* rows, int64_t nr, const int64_t* cols,
+                      int64_t nc, double* out, int64_t ld, hipStream_t stream);
+
+/* Proxy blocks for the proxy-surface compression (Sec. I and III; the proxy
+ * method of Martinsson-Rokhlin).  Proxy points are pseudo-nodes given by pts
+ * (device, 5 x P row-major: x, y, nx, ny, w).  The same pair formula is used
+ * with no diagonal term.  dir = 0: node targets x proxy sources, out is
+ * 2n x 2P (ld >= 2P); dir = 1: proxy targets x node sources, out is 2P x 2n
+ * (ld >= 2n).  nodes: device int64 list of node indices.  Proxy points must
+ * not coincide with nodes. */
+int bm_assemble_proxy(const bm_problem* p, const int64_t* nodes, int64_t n, const double* pts,
+                      int64_t P, int dir, double* out, int64_t ld, hipStream_t stream);
+
+/* y = A x without storing A (device, 2N complex each): the matrix entries are
+ * generated on the fly and reduced. */
+int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t stream);
+
+/* Far field of the scattered field from a solution phi = (u_0, q_0, u_1, ...)
+ * (device, 2N complex), at nang observation angles (device FP64); uinf (device,
+ * nang complex).  u_sc(x) ~ exp(i k0 |x|)/sqrt(|x|) uinf(x/|x|), from the
+ * exterior representation u_sc = D_k0[u] - S_k0[eps0 q] (remark after Eq. (3)). */
+int bm_far_field(const bm_problem* p, const double* phi, const double* angles, int64_t nang,
+                 double* uinf, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMHSS_H */

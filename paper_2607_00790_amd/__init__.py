@@ -1,0 +1,29 @@
+"""MI355X (gfx950) library for the weakly singular Burton-Miller Nystrom system
+of 2D TE-mode transmission scattering, with a proxy-surface HSS direct solver.
+
+This module is a thin ctypes binding of the C-ABI in include/bmhss.h: the
+functions carry the same names and only marshal arguments (torch tensors supply
+device memory and the current HIP stream).  Every computation runs in the HIP
+kernels of libbmhss.so; if the library is not built, calls raise RuntimeError.
+"""
+from ._binding import (  # noqa: F401
+    BmError,
+    Geometry,
+    HSS,
+    Problem,
+    bm_assemble_block,
+    bm_assemble_dense,
+    bm_assemble_proxy,
+    bm_far_field,
+    bm_geom_create,
+    bm_geom_nodes,
+    bm_geom_size,
+    bm_matvec,
+    bm_problem_create,
+    bm_rhs_plane_wave,
+    bm_hss_build,
+    bm_hss_solve,
+    bm_hss_stats,
+    lib_path,
+    load,
+)

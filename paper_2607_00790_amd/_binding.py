@@ -1,0 +1,294 @@
+"""ctypes marshalling for libbmhss.so (include/bmhss.h).  No arithmetic here."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+c_i64 = ctypes.c_int64
+c_dbl = ctypes.c_double
+c_vp = ctypes.c_void_p
+
+
+class BmError(RuntimeError):
+    """A non-zero status from the library, with bm_last_error()'s message."""
+
+    def __init__(self, code, msg):
+        super().__init__(f"bmhss error {code}: {msg}")
+        self.code = code
+
+
+class _Media(ctypes.Structure):
+    _fields_ = [("k0", c_dbl), ("k1", c_dbl), ("eps0", c_dbl), ("eps1", c_dbl)]
+
+
+class _HssOpts(ctypes.Structure):
+    _fields_ = [("leaf", c_i64), ("proxy_ratio", c_dbl), ("proxy_points", c_i64),
+                ("id_tol", c_dbl)]
+
+
+class _HssStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("root_size", ctypes.c_int32),
+                ("max_rank", c_i64), ("entries", c_i64), ("seconds_generate", c_dbl),
+                ("seconds_total", c_dbl)]
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libbmhss.so")
+
+
+def load():
+    """Load libbmhss.so (built in-tree by paper_2607_00790_amd.build)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2607_00790_amd.build`")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "bm_last_error": (ctypes.c_char_p, []),
+        "bm_geom_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(c_i64), c_vp, ctypes.c_int,
+                                          c_vp, ctypes.POINTER(c_vp)]),
+        "bm_geom_destroy": (ctypes.c_int, [c_vp]),
+        "bm_geom_size": (c_i64, [c_vp]),
+        "bm_geom_nodes": (ctypes.c_int, [c_vp, c_vp, c_vp]),
+        "bm_problem_create": (ctypes.c_int, [c_vp, ctypes.POINTER(_Media), ctypes.POINTER(c_vp)]),
+        "bm_problem_destroy": (ctypes.c_int, [c_vp]),
+        "bm_rhs_plane_wave": (ctypes.c_int, [c_vp, c_dbl, c_vp, c_vp]),
+        "bm_assemble_dense": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp]),
+        "bm_assemble_block": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp]),
+        "bm_assemble_proxy": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, ctypes.c_int, c_vp,
+                                             c_i64, c_vp]),
+        "bm_matvec": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp]),
+        "bm_far_field": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]),
+    }
+    optional = {
+        "bm_hss_build": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssOpts), c_vp, ctypes.POINTER(c_vp)]),
+        "bm_hss_solve": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp]),
+        "bm_hss_stats": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssStats)]),
+        "bm_hss_destroy": (ctypes.c_int, [c_vp]),
+    }
+    for name, (res, args) in list(sig.items()) + list(optional.items()):
+        if name in optional and not hasattr(lib, name):
+            continue
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(code):
+    if code != 0:
+        raise BmError(code, _LIB.bm_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_vp(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return c_vp(t.data_ptr())
+
+
+class Geometry:
+    """Handle of a discretised boundary (bm_geom)."""
+
+    def __init__(self, handle, sizes):
+        self._h = handle
+        self.sizes = list(sizes)
+
+    @property
+    def n(self) -> int:
+        return int(_LIB.bm_geom_size(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.bm_geom_destroy(self._h)
+            self._h = None
+
+
+class Problem:
+    """Handle of a geometry + media (bm_problem); keeps its geometry alive."""
+
+    def __init__(self, handle, geom, media):
+        self._h = handle
+        self.geom = geom
+        self.media = media
+
+    @property
+    def n(self) -> int:
+        return self.geom.n
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.bm_problem_destroy(self._h)
+            self._h = None
+
+
+class HSS:
+    """Handle of a built HSS factorisation (bm_hss); keeps its problem alive."""
+
+    def __init__(self, handle, prob):
+        self._h = handle
+        self.prob = prob
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.bm_hss_destroy(self._h)
+            self._h = None
+
+
+def bm_geom_create(n_per_curve, xyd, stream=None) -> Geometry:
+    """xyd: (6, N) float64, host numpy array or device tensor (see bmhss.h)."""
+    load()
+    sizes = np.ascontiguousarray(np.asarray(n_per_curve, dtype=np.int64))
+    torch = _torch()
+    out = c_vp()
+    if isinstance(xyd, torch.Tensor) and xyd.is_cuda:
+        ptr, on_dev = _dev_ptr(xyd, torch.float64, "xyd"), 1
+        keep = xyd
+        if tuple(xyd.shape) != (6, int(sizes.sum())):
+            raise ValueError("xyd must have shape (6, sum(n_per_curve))")
+    else:
+        keep = np.ascontiguousarray(np.asarray(xyd, dtype=np.float64))
+        if keep.shape != (6, int(sizes.sum())):
+            raise ValueError("xyd must have shape (6, sum(n_per_curve))")
+        ptr, on_dev = c_vp(keep.ctypes.data), 0
+    _check(_LIB.bm_geom_create(len(sizes), sizes.ctypes.data_as(ctypes.POINTER(c_i64)), ptr, on_dev,
+                               _stream(stream), ctypes.byref(out)))
+    del keep
+    return Geometry(out, sizes)
+
+
+def bm_geom_size(g: Geometry) -> int:
+    return g.n
+
+
+def bm_geom_nodes(g: Geometry, stream=None):
+    """(6, N) float64 device tensor: x, y, nx, ny, w, kappa."""
+    torch = _torch()
+    out = torch.empty((6, g.n), dtype=torch.float64, device="cuda")
+    _check(_LIB.bm_geom_nodes(g._h, _dev_ptr(out), _stream(stream)))
+    return out
+
+
+def bm_problem_create(g: Geometry, k0, k1, eps0, eps1) -> Problem:
+    load()
+    m = _Media(float(k0), float(k1), float(eps0), float(eps1))
+    out = c_vp()
+    _check(_LIB.bm_problem_create(g._h, ctypes.byref(m), ctypes.byref(out)))
+    return Problem(out, g, (float(k0), float(k1), float(eps0), float(eps1)))
+
+
+def bm_rhs_plane_wave(p: Problem, angle: float, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(2 * p.n, dtype=torch.complex128, device="cuda")
+    _check(_LIB.bm_rhs_plane_wave(p._h, float(angle), _dev_ptr(out, torch.complex128, "out"),
+                                  _stream(stream)))
+    return out
+
+
+def bm_assemble_dense(p: Problem, out=None, stream=None):
+    torch = _torch()
+    n2 = 2 * p.n
+    if out is None:
+        out = torch.empty((n2, n2), dtype=torch.complex128, device="cuda")
+    if out.dim() != 2 or out.shape[0] != n2 or out.shape[1] < n2:
+        raise ValueError("out must be (2N, >=2N)")
+    _check(_LIB.bm_assemble_dense(p._h, _dev_ptr(out, torch.complex128, "out"), out.stride(0),
+                                  _stream(stream)))
+    return out
+
+
+def bm_assemble_block(p: Problem, rows, cols, out=None, stream=None):
+    torch = _torch()
+    rows = rows.to(device="cuda", dtype=torch.int64).contiguous()
+    cols = cols.to(device="cuda", dtype=torch.int64).contiguous()
+    nr, nc = rows.numel(), cols.numel()
+    if out is None:
+        out = torch.empty((2 * nr, 2 * nc), dtype=torch.complex128, device="cuda")
+    _check(_LIB.bm_assemble_block(p._h, _dev_ptr(rows), nr, _dev_ptr(cols), nc,
+                                  _dev_ptr(out, torch.complex128, "out"), out.stride(0),
+                                  _stream(stream)))
+    return out
+
+
+def bm_assemble_proxy(p: Problem, nodes, pts, direction: int, out=None, stream=None):
+    """pts: (5, P) float64 device tensor (x, y, nx, ny, w)."""
+    torch = _torch()
+    nodes = nodes.to(device="cuda", dtype=torch.int64).contiguous()
+    n, P = nodes.numel(), pts.shape[1]
+    shape = (2 * n, 2 * P) if direction == 0 else (2 * P, 2 * n)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    _check(_LIB.bm_assemble_proxy(p._h, _dev_ptr(nodes), n, _dev_ptr(pts, torch.float64, "pts"), P,
+                                  int(direction), _dev_ptr(out, torch.complex128, "out"),
+                                  out.stride(0), _stream(stream)))
+    return out
+
+
+def bm_matvec(p: Problem, x, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(2 * p.n, dtype=torch.complex128, device="cuda")
+    _check(_LIB.bm_matvec(p._h, _dev_ptr(x, torch.complex128, "x"),
+                          _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
+    return out
+
+
+def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
+    torch = _torch()
+    angles = angles.to(device="cuda", dtype=torch.float64).contiguous()
+    if out is None:
+        out = torch.empty(angles.numel(), dtype=torch.complex128, device="cuda")
+    _check(_LIB.bm_far_field(p._h, _dev_ptr(phi, torch.complex128, "phi"), _dev_ptr(angles),
+                             angles.numel(), _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
+    return out
+
+
+def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10,
+                 stream=None) -> HSS:
+    if not hasattr(_LIB, "bm_hss_build"):
+        raise RuntimeError("this libbmhss.so has no HSS solver")
+    opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol))
+    out = c_vp()
+    _check(_LIB.bm_hss_build(p._h, ctypes.byref(opts), _stream(stream), ctypes.byref(out)))
+    return HSS(out, p)
+
+
+def bm_hss_solve(h: HSS, b, out=None, stream=None):
+    """b: (2N,) or (nrhs, 2N) complex128 device tensor (each right-hand side contiguous)."""
+    torch = _torch()
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    if out is None:
+        out = torch.empty_like(b)
+    _check(_LIB.bm_hss_solve(h._h, _dev_ptr(b, torch.complex128, "b"),
+                             _dev_ptr(out, torch.complex128, "out"), nrhs, _stream(stream)))
+    return out
+
+
+def bm_hss_stats(h: HSS) -> dict:
+    s = _HssStats()
+    _check(_LIB.bm_hss_stats(h._h, ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in _HssStats._fields_}

@@ -1,0 +1,298 @@
+// Entry-generation kernels for the WSBM Nystrom matrix (paper Eq. (3)/(5)),
+// plus the boundary discretisation, plane-wave right-hand side, matrix-free
+// product and far field.
+//
+// Layout choices for gfx950 (64-wide wavefronts):
+//  * lanes run along the SOURCE index j, so a wavefront writes 64 consecutive
+//    2x2 blocks = two contiguous 2 KiB row segments (rows 2i and 2i+1) of the
+//    row-major complex matrix: fully coalesced 16-byte stores;
+//  * a workgroup covers one TARGET i and kThreads consecutive sources; the
+//    target's node data are wave-uniform and come through the scalar cache,
+//    each lane loads its own source node.  No LDS staging is needed: the only
+//    shared operand is the uniform target.
+//  * one pair per thread and no loop: the ~120 FP64 polynomial coefficients of
+//    the Bessel functions stay scalar operands materialised at their use
+//    (a loop lets the compiler hoist them into vector registers, which drops
+//    the occupancy to one wave per SIMD).
+#include "internal.hpp"
+
+namespace bm {
+
+namespace {
+
+constexpr int kThreads = 256;   // 4 wavefronts
+
+__global__ void __launch_bounds__(kThreads)
+k_geometry(const double* __restrict__ xyd, const int64_t* __restrict__ offsets, int ncurves,
+           int64_t n, double* __restrict__ soa, int32_t* __restrict__ curve) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (j >= n) return;
+    int c = 0;
+    while (c + 1 < ncurves && offsets[c + 1] <= j) ++c;
+    const double nc = static_cast<double>(offsets[c + 1] - offsets[c]);
+    const double dx = xyd[2 * n + j], dy = xyd[3 * n + j];
+    const double ddx = xyd[4 * n + j], ddy = xyd[5 * n + j];
+    const double s = sqrt(dx * dx + dy * dy);
+    const double is = 1.0 / s;
+    soa[j] = xyd[j];
+    soa[n + j] = xyd[n + j];
+    soa[2 * n + j] = dy * is;
+    soa[3 * n + j] = -dx * is;
+    soa[4 * n + j] = (2.0 * kPi / nc) * s;
+    soa[5 * n + j] = (dx * ddy - dy * ddx) * is * is * is;
+    curve[j] = c;
+}
+
+__device__ __forceinline__ void store_block(double* __restrict__ out, int64_t ld, int64_t row,
+                                            int64_t col, const Block& b) {
+    // complex (row, col) lives at doubles 2*(row*ld + col)
+    double2* r0 = reinterpret_cast<double2*>(out) + (2 * row) * ld + 2 * col;
+    double2* r1 = r0 + ld;
+    r0[0] = make_double2(b.v[0], b.v[1]);
+    r0[1] = make_double2(b.v[2], b.v[3]);
+    r1[0] = make_double2(b.v[4], b.v[5]);
+    r1[1] = make_double2(b.v[6], b.v[7]);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    return x;
+}
+
+// Block-wide sum of NV values per thread; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&acc)[NV]) {
+    __shared__ double red[NV][kThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) red[q][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0;
+            for (int w = 0; w < kThreads / 64; ++w) s += red[q][w];
+            acc[q] = s;
+        }
+    }
+}
+
+// Full matrix: workgroup b covers target i = b / ntj and sources
+// [jt*kThreads, (jt+1)*kThreads), jt = b % ntj.
+__global__ void __launch_bounds__(kThreads)
+k_dense(NodeView v, int64_t n, int64_t ntj, Media m, double* __restrict__ A, int64_t ld) {
+    const int64_t i = blockIdx.x / ntj;
+    const int64_t j = (blockIdx.x % ntj) * kThreads + threadIdx.x;
+    if (j >= n) return;
+    Block b;
+    if (i == j) {
+        b = diag_block(v.w[j], v.kappa[j], m);
+    } else {
+        b = pair_block(v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j], v.w[j],
+                       m, v.curve[i] == v.curve[j]);
+    }
+    store_block(A, ld, i, j, b);
+}
+
+// Block for node index lists: workgroup b covers row a = b / ntj.
+__global__ void __launch_bounds__(kThreads)
+k_block(NodeView v, Media m, const int64_t* __restrict__ rows, const int64_t* __restrict__ cols,
+        int64_t nc, int64_t ntj, double* __restrict__ out, int64_t ld) {
+    const int64_t a = blockIdx.x / ntj;
+    const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
+    if (c >= nc) return;
+    const int64_t i = rows[a], j = cols[c];
+    Block b;
+    if (i == j) {
+        b = diag_block(v.w[j], v.kappa[j], m);
+    } else {
+        b = pair_block(v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j], v.w[j],
+                       m, v.curve[i] == v.curve[j]);
+    }
+    store_block(out, ld, a, c, b);
+}
+
+// Proxy blocks.  dir 0: node targets (rows) x proxy sources (cols);
+// dir 1: proxy targets (rows) x node sources (cols).
+__global__ void __launch_bounds__(kThreads)
+k_proxy(NodeView v, Media m, const int64_t* __restrict__ nodes, int64_t n,
+        const double* __restrict__ pts, int64_t P, int dir, int64_t ntj, double* __restrict__ out,
+        int64_t ld) {
+    const int64_t ncol = dir == 0 ? P : n;
+    const int64_t a = blockIdx.x / ntj;
+    const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
+    if (c >= ncol) return;
+    double tx, ty, tnx, tny, sx, sy, snx, sny, sw;
+    if (dir == 0) {
+        const int64_t i = nodes[a];
+        tx = v.x[i]; ty = v.y[i]; tnx = v.nx[i]; tny = v.ny[i];
+        sx = pts[c]; sy = pts[P + c]; snx = pts[2 * P + c]; sny = pts[3 * P + c];
+        sw = pts[4 * P + c];
+    } else {
+        const int64_t j = nodes[c];
+        tx = pts[a]; ty = pts[P + a]; tnx = pts[2 * P + a]; tny = pts[3 * P + a];
+        sx = v.x[j]; sy = v.y[j]; snx = v.nx[j]; sny = v.ny[j]; sw = v.w[j];
+    }
+    const Block b = pair_block(tx, ty, tnx, tny, sx, sy, snx, sny, sw, m, true);
+    store_block(out, ld, a, c, b);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_rhs_plane_wave(NodeView v, int64_t n, Media m, double dx, double dy, double2* __restrict__ rhs) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n) return;
+    double s, c;
+    sincos(m.k0 * (dx * v.x[i] + dy * v.y[i]), &s, &c);
+    // -u_in - alpha du_in/dn = -u_in (1 + (i/k0)(i k0 d.n)) = -u_in (1 - d.n)
+    const double f = -(1.0 - (dx * v.nx[i] + dy * v.ny[i]));
+    rhs[2 * i] = make_double2(0.0, 0.0);
+    rhs[2 * i + 1] = make_double2(f * c, f * s);
+}
+
+// y = A x, stage 1: workgroup b covers target i = b / ntj and one source tile;
+// it writes the tile's partial sums of rows 2i, 2i+1 to part[b] (4 doubles).
+__global__ void __launch_bounds__(kThreads)
+k_matvec_partial(NodeView v, int64_t n, int64_t ntj, Media m, const double2* __restrict__ x,
+                 double4* __restrict__ part) {
+    const int64_t i = blockIdx.x / ntj;
+    const int64_t j = (blockIdx.x % ntj) * kThreads + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (j < n) {
+        Block b;
+        if (i == j) {
+            b = diag_block(v.w[j], v.kappa[j], m);
+        } else {
+            b = pair_block(v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j],
+                           v.w[j], m, v.curve[i] == v.curve[j]);
+        }
+        const double2 xu = x[2 * j], xq = x[2 * j + 1];
+        // row 2i: A00 xu + A01 xq ; row 2i+1: A10 xu + A11 xq
+        acc[0] = b.v[0] * xu.x - b.v[1] * xu.y + b.v[2] * xq.x - b.v[3] * xq.y;
+        acc[1] = b.v[0] * xu.y + b.v[1] * xu.x + b.v[2] * xq.y + b.v[3] * xq.x;
+        acc[2] = b.v[4] * xu.x - b.v[5] * xu.y + b.v[6] * xq.x - b.v[7] * xq.y;
+        acc[3] = b.v[4] * xu.y + b.v[5] * xu.x + b.v[6] * xq.y + b.v[7] * xq.x;
+    }
+    block_sum<4>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double4(acc[0], acc[1], acc[2], acc[3]);
+}
+
+// y = A x, stage 2: sum the ntj partials of each target in a fixed order.
+__global__ void __launch_bounds__(kThreads)
+k_matvec_reduce(int64_t n, int64_t ntj, const double4* __restrict__ part, double2* __restrict__ y) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n) return;
+    double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int64_t t = 0; t < ntj; ++t) {
+        const double4 p = part[i * ntj + t];
+        s.x += p.x; s.y += p.y; s.z += p.z; s.w += p.w;
+    }
+    y[2 * i] = make_double2(s.x, s.y);
+    y[2 * i + 1] = make_double2(s.z, s.w);
+}
+
+// Far field: one workgroup per observation angle.
+__global__ void __launch_bounds__(kThreads)
+k_far_field(NodeView v, int64_t n, Media m, const double2* __restrict__ phi,
+            const double* __restrict__ angles, double2* __restrict__ uinf) {
+    const int64_t a = blockIdx.x;
+    double sa, ca;
+    sincos(angles[a], &sa, &ca);
+    double acc[2] = {0.0, 0.0};
+    for (int64_t j = threadIdx.x; j < n; j += kThreads) {
+        const double2 u = phi[2 * j], q = phi[2 * j + 1];
+        const double xn = ca * v.nx[j] + sa * v.ny[j];
+        // density = -i k0 (xhat.n) u - eps0 q
+        const double d_re = m.k0 * xn * u.y - m.eps0 * q.x;
+        const double d_im = -m.k0 * xn * u.x - m.eps0 * q.y;
+        double s, c;
+        sincos(-m.k0 * (ca * v.x[j] + sa * v.y[j]), &s, &c);
+        const double w = v.w[j];
+        acc[0] += w * (d_re * c - d_im * s);
+        acc[1] += w * (d_re * s + d_im * c);
+    }
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        // e^{i pi/4} / sqrt(8 pi k0)
+        const double f = 1.0 / sqrt(8.0 * kPi * m.k0);
+        const double cr = f * kSqrtHalf, ci = f * kSqrtHalf;
+        uinf[a] = make_double2(cr * acc[0] - ci * acc[1], cr * acc[1] + ci * acc[0]);
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int per) {
+    return static_cast<unsigned>((n + per - 1) / per);
+}
+
+}  // namespace
+
+hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurves, int64_t n,
+                           double* soa, int32_t* curve, hipStream_t s) {
+    hipLaunchKernelGGL(k_geometry, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, xyd,
+                       offsets, ncurves, n, soa, curve);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense(const NodeView& v, int64_t n, const Media& m, double* A, int64_t ld,
+                        hipStream_t s) {
+    const int64_t ntj = (n + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_dense, dim3(static_cast<unsigned>(n * ntj)), dim3(kThreads), 0, s, v, n,
+                       ntj, m, A, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_block(const NodeView& v, const Media& m, const int64_t* rows, int64_t nr,
+                        const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s) {
+    if (nr == 0 || nc == 0) return hipSuccess;
+    const int64_t ntj = (nc + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_block, dim3(static_cast<unsigned>(nr * ntj)), dim3(kThreads), 0, s, v, m,
+                       rows, cols, nc, ntj, out, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_proxy(const NodeView& v, const Media& m, const int64_t* nodes, int64_t n,
+                        const double* pts, int64_t P, int dir, double* out, int64_t ld,
+                        hipStream_t s) {
+    if (n == 0 || P == 0) return hipSuccess;
+    const int64_t ncol = dir == 0 ? P : n, nrow = dir == 0 ? n : P;
+    const int64_t ntj = (ncol + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_proxy, dim3(static_cast<unsigned>(nrow * ntj)), dim3(kThreads), 0, s, v,
+                       m, nodes, n, pts, P, dir, ntj, out, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media& m, double angle,
+                                 double* rhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_rhs_plane_wave, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, v, n,
+                       m, std::cos(angle), std::sin(angle), reinterpret_cast<double2*>(rhs));
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec(const NodeView& v, int64_t n, const Media& m, const double* x,
+                         double* y, double* work, hipStream_t s) {
+    const int64_t ntj = (n + kThreads - 1) / kThreads;
+    double4* part = reinterpret_cast<double4*>(work);
+    hipLaunchKernelGGL(k_matvec_partial, dim3(static_cast<unsigned>(n * ntj)), dim3(kThreads), 0,
+                       s, v, n, ntj, m, reinterpret_cast<const double2*>(x), part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_matvec_reduce, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, n,
+                       ntj, part, reinterpret_cast<double2*>(y));
+    return hipGetLastError();
+}
+
+int64_t matvec_work_doubles(int64_t n) { return 4 * n * ((n + kThreads - 1) / kThreads); }
+
+hipError_t launch_far_field(const NodeView& v, int64_t n, const Media& m, const double* phi,
+                            const double* angles, int64_t nang, double* uinf, hipStream_t s) {
+    if (nang == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_far_field, dim3(static_cast<unsigned>(nang)), dim3(kThreads), 0, s, v, n,
+                       m, reinterpret_cast<const double2*>(phi), angles,
+                       reinterpret_cast<double2*>(uinf));
+    return hipGetLastError();
+}
+
+}  // namespace bm

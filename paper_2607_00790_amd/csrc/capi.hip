@@ -1,0 +1,225 @@
+// C-ABI entry points declared in include/bmhss.h: argument validation, handle
+// management and error reporting.  All arithmetic runs in the HIP kernels.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace bm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? BM_ENOMEM : BM_EHIP;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+namespace {
+
+bool finite_media(const bm_media* m) {
+    return std::isfinite(m->k0) && std::isfinite(m->k1) && std::isfinite(m->eps0) &&
+           std::isfinite(m->eps1) && m->k0 > 0 && m->k1 > 0 && m->eps0 > 0 && m->eps1 > 0;
+}
+
+constexpr int64_t kMaxGrid = 0xFFFFFFFFll;   // workgroups per 1D launch
+
+}  // namespace
+}  // namespace bm
+
+using namespace bm;
+
+extern "C" {
+
+const char* bm_last_error(void) { return g_last_error.c_str(); }
+
+int bm_geom_create(int ncurves, const int64_t* n_per_curve, const double* xyd, int on_device,
+                   hipStream_t stream, bm_geom** out) {
+    clear_error();
+    if (!out) return fail(BM_EINVAL, "bm_geom_create: out is null");
+    *out = nullptr;
+    if (ncurves <= 0 || !n_per_curve || !xyd)
+        return fail(BM_EINVAL, "bm_geom_create: need ncurves > 0 and non-null arrays");
+    std::vector<int64_t> offsets(ncurves + 1, 0);
+    for (int c = 0; c < ncurves; ++c) {
+        if (n_per_curve[c] < 8)
+            return fail(BM_EINVAL, "bm_geom_create: every curve needs at least 8 nodes");
+        offsets[c + 1] = offsets[c] + n_per_curve[c];
+    }
+    const int64_t n = offsets[ncurves];
+    if (n > (int64_t{1} << 31))
+        return fail(BM_EINVAL, "bm_geom_create: more than 2^31 nodes");
+    // host copy for validation
+    std::vector<double> h(6 * static_cast<size_t>(n));
+    if (on_device) {
+        BM_HIP(hipMemcpyAsync(h.data(), xyd, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              stream));
+        BM_HIP(hipStreamSynchronize(stream));
+    } else {
+        std::memcpy(h.data(), xyd, h.size() * sizeof(double));
+    }
+    for (double v : h)
+        if (!std::isfinite(v)) return fail(BM_EINVAL, "bm_geom_create: non-finite coordinates");
+    for (int c = 0; c < ncurves; ++c) {
+        // signed area (shoelace on the trapezoidal rule) must be positive: ccw
+        double area = 0;
+        for (int64_t j = offsets[c]; j < offsets[c + 1]; ++j) {
+            const double s2 = h[2 * n + j] * h[2 * n + j] + h[3 * n + j] * h[3 * n + j];
+            if (!(s2 > 0)) return fail(BM_EINVAL, "bm_geom_create: zero speed |x'(t)|");
+            area += h[j] * h[3 * n + j] - h[n + j] * h[2 * n + j];
+        }
+        if (!(area > 0))
+            return fail(BM_EINVAL, "bm_geom_create: curve " + std::to_string(c) +
+                                       " is not counter-clockwise");
+    }
+    bm_geom* g = new (std::nothrow) bm_geom;
+    if (!g) return fail(BM_ENOMEM, "bm_geom_create: host allocation");
+    g->n = n;
+    g->ncurves = ncurves;
+    (void)hipGetDevice(&g->device);
+    double* d_xyd = nullptr;
+    int64_t* d_off = nullptr;
+    hipError_t e = hipMalloc(&g->soa, 6 * n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&g->curve, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&d_xyd, 6 * n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_off, (ncurves + 1) * sizeof(int64_t));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_xyd, h.data(), 6 * n * sizeof(double), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_off, offsets.data(), (ncurves + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_geometry(d_xyd, d_off, ncurves, n, g->soa, g->curve, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(d_xyd);
+    (void)hipFree(d_off);
+    if (e != hipSuccess) {
+        bm_geom_destroy(g);
+        return hip_fail(e, "bm_geom_create");
+    }
+    *out = g;
+    return BM_OK;
+}
+
+int bm_geom_destroy(bm_geom* g) {
+    if (!g) return BM_OK;
+    (void)hipFree(g->soa);
+    (void)hipFree(g->curve);
+    delete g;
+    return BM_OK;
+}
+
+int64_t bm_geom_size(const bm_geom* g) { return g ? g->n : -1; }
+
+int bm_geom_nodes(const bm_geom* g, double* soa, hipStream_t stream) {
+    clear_error();
+    if (!g || !soa) return fail(BM_EINVAL, "bm_geom_nodes: null argument");
+    BM_HIP(hipMemcpyAsync(soa, g->soa, 6 * g->n * sizeof(double), hipMemcpyDeviceToDevice,
+                          stream));
+    return BM_OK;
+}
+
+int bm_problem_create(const bm_geom* g, const bm_media* media, bm_problem** out) {
+    clear_error();
+    if (!out) return fail(BM_EINVAL, "bm_problem_create: out is null");
+    *out = nullptr;
+    if (!g || !media) return fail(BM_EINVAL, "bm_problem_create: null argument");
+    if (!finite_media(media))
+        return fail(BM_EINVAL, "bm_problem_create: wavenumbers and permittivities must be finite and > 0");
+    bm_problem* p = new (std::nothrow) bm_problem;
+    if (!p) return fail(BM_ENOMEM, "bm_problem_create: host allocation");
+    p->g = g;
+    p->media = Media{media->k0, media->k1, media->eps0, media->eps1};
+    *out = p;
+    return BM_OK;
+}
+
+int bm_problem_destroy(bm_problem* p) {
+    delete p;
+    return BM_OK;
+}
+
+int bm_rhs_plane_wave(const bm_problem* p, double angle, double* rhs, hipStream_t stream) {
+    clear_error();
+    if (!p || !rhs) return fail(BM_EINVAL, "bm_rhs_plane_wave: null argument");
+    if (!std::isfinite(angle)) return fail(BM_EINVAL, "bm_rhs_plane_wave: non-finite angle");
+    BM_HIP(launch_rhs_plane_wave(view(p->g), p->g->n, p->media, angle, rhs, stream));
+    return BM_OK;
+}
+
+int bm_assemble_dense(const bm_problem* p, double* A, int64_t ld, hipStream_t stream) {
+    clear_error();
+    if (!p || !A) return fail(BM_EINVAL, "bm_assemble_dense: null argument");
+    const int64_t n = p->g->n;
+    if (ld < 2 * n) return fail(BM_EINVAL, "bm_assemble_dense: ld < 2N");
+    if (n * ((n + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_dense: N too large");
+    BM_HIP(launch_dense(view(p->g), n, p->media, A, ld, stream));
+    return BM_OK;
+}
+
+int bm_assemble_block(const bm_problem* p, const int64_t* rows, int64_t nr, const int64_t* cols,
+                      int64_t nc, double* out, int64_t ld, hipStream_t stream) {
+    clear_error();
+    if (!p) return fail(BM_EINVAL, "bm_assemble_block: null problem");
+    if (nr < 0 || nc < 0) return fail(BM_EINVAL, "bm_assemble_block: negative size");
+    if (nr == 0 || nc == 0) return BM_OK;
+    if (!rows || !cols || !out) return fail(BM_EINVAL, "bm_assemble_block: null array");
+    if (ld < 2 * nc) return fail(BM_EINVAL, "bm_assemble_block: ld < 2 nc");
+    if (nr * ((nc + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_block: too large");
+    BM_HIP(launch_block(view(p->g), p->media, rows, nr, cols, nc, out, ld, stream));
+    return BM_OK;
+}
+
+int bm_assemble_proxy(const bm_problem* p, const int64_t* nodes, int64_t n, const double* pts,
+                      int64_t P, int dir, double* out, int64_t ld, hipStream_t stream) {
+    clear_error();
+    if (!p) return fail(BM_EINVAL, "bm_assemble_proxy: null problem");
+    if (n < 0 || P < 0) return fail(BM_EINVAL, "bm_assemble_proxy: negative size");
+    if (dir != 0 && dir != 1) return fail(BM_EINVAL, "bm_assemble_proxy: dir must be 0 or 1");
+    if (n == 0 || P == 0) return BM_OK;
+    if (!nodes || !pts || !out) return fail(BM_EINVAL, "bm_assemble_proxy: null array");
+    const int64_t ncol = dir == 0 ? P : n, nrow = dir == 0 ? n : P;
+    if (ld < 2 * ncol) return fail(BM_EINVAL, "bm_assemble_proxy: ld too small");
+    if (nrow * ((ncol + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_proxy: too large");
+    BM_HIP(launch_proxy(view(p->g), p->media, nodes, n, pts, P, dir, out, ld, stream));
+    return BM_OK;
+}
+
+int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t stream) {
+    clear_error();
+    if (!p || !x || !y) return fail(BM_EINVAL, "bm_matvec: null argument");
+    if (x == y) return fail(BM_EINVAL, "bm_matvec: x and y must not alias");
+    if (p->g->n * ((p->g->n + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_matvec: N too large");
+    const int64_t n = p->g->n;
+    double* work = nullptr;
+    BM_HIP(hipMallocAsync(reinterpret_cast<void**>(&work),
+                          matvec_work_doubles(n) * sizeof(double), stream));
+    const hipError_t e = launch_matvec(view(p->g), n, p->media, x, y, work, stream);
+    const hipError_t e2 = hipFreeAsync(work, stream);
+    if (e != hipSuccess) return hip_fail(e, "bm_matvec");
+    if (e2 != hipSuccess) return hip_fail(e2, "bm_matvec: free");
+    return BM_OK;
+}
+
+int bm_far_field(const bm_problem* p, const double* phi, const double* angles, int64_t nang,
+                 double* uinf, hipStream_t stream) {
+    clear_error();
+    if (!p || nang < 0) return fail(BM_EINVAL, "bm_far_field: bad argument");
+    if (nang == 0) return BM_OK;
+    if (!phi || !angles || !uinf) return fail(BM_EINVAL, "bm_far_field: null array");
+    if (nang > (int64_t{1} << 31)) return fail(BM_EINVAL, "bm_far_field: too many angles");
+    BM_HIP(launch_far_field(view(p->g), p->g->n, p->media, phi, angles, nang, uinf, stream));
+    return BM_OK;
+}
+
+}  // extern "C"

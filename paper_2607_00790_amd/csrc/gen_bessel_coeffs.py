@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Generate the coefficient tables of the library's FP64 Bessel functions.
+
+Writes ``bessel_coeffs.h`` next to this file.  The approximations are derived
+here from the mathematics, with mpmath (40 digits) as the source of truth:
+
+Region A, 0 < z < ZA (ascending series, A&S 9.1.10/9.1.11 structure).
+    J0(z)  = PA_J0(w)                          w = z^2
+    J1(z)  = z PA_J1(w)
+    Y0(z)  = (2/pi) ln(z/2) J0(z) + PA_R0(w)
+    Y1r(z) := Y1(z) + 2/(pi z) = (2/pi) ln(z/2) J1(z) + z PA_R1(w)
+  The four functions of w are entire; each is replaced by its least-squares
+  polynomial on Chebyshev points of [0, ZA^2] (near-minimax).
+
+Region B, ZA <= z < ZC (piecewise local polynomials).
+  [ZA, ZC) is cut into intervals of width HB; on each, J0, Y0, J1 and Y1r are
+  least-squares polynomials in s = z - centre.
+
+Region C, z >= ZC (Hankel's large-argument form, A&S 9.2.5-9.2.10 structure).
+    H_n(z) = sqrt(2/(pi z)) (P_n(z) + i Q_n(z)) exp(i (z - (2n+1) pi/4)),  n = 0, 1
+  P_n and z Q_n are smooth in u = (ZC/z)^2 on [0, 1] and are replaced by their
+  least-squares polynomials in u.
+
+The script reports the worst relative error of H0 and H1 (complex, relative to
+|H|) of a float64 Horner evaluation over 0 < z <= 1e4.
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import mpmath as mp
+import numpy as np
+
+mp.mp.dps = 40
+
+ZA = 4.0
+ZC = 8.0
+HB = 0.5
+DEG_A = 16
+DEG_B = 11
+DEG_C = 11
+
+
+def _j(n, z):
+    return mp.besselj(n, z)
+
+
+def _y(n, z):
+    return mp.bessely(n, z)
+
+
+def fa(which, w):
+    z = mp.sqrt(w) if w > 0 else mp.mpf(0)
+    if w == 0:
+        g = mp.euler
+        return {"J0": mp.mpf(1), "J1": mp.mpf(1) / 2,
+                "R0": 2 / mp.pi * (g), "R1": (2 * g - 1) / (2 * mp.pi)}[which]
+    lg = 2 / mp.pi * mp.log(z / 2)
+    if which == "J0":
+        return _j(0, z)
+    if which == "J1":
+        return _j(1, z) / z
+    if which == "R0":
+        return _y(0, z) - lg * _j(0, z)
+    if which == "R1":
+        return (_y(1, z) + 2 / (mp.pi * z) - lg * _j(1, z)) / z
+    raise KeyError(which)
+
+
+def fb(which, z):
+    if which == "J0":
+        return _j(0, z)
+    if which == "Y0":
+        return _y(0, z)
+    if which == "J1":
+        return _j(1, z)
+    if which == "Y1r":
+        return _y(1, z) + 2 / (mp.pi * z)
+    raise KeyError(which)
+
+
+def fc(which, u):
+    z = ZC / mp.sqrt(u)
+    n = 0 if which in ("P0", "Q0") else 1
+    h = _j(n, z) + 1j * _y(n, z)
+    v = h * mp.exp(-1j * (z - (2 * n + 1) * mp.pi / 4)) * mp.sqrt(mp.pi * z / 2)
+    return v.real if which[0] == "P" else v.imag * z
+
+
+def lsq_poly(f, a, b, deg, npts=None):
+    """Least-squares polynomial (monomial coefficients in x - a0) on Chebyshev points."""
+    npts = npts or 3 * deg + 30
+    xs = [(a + b) / 2 + (b - a) / 2 * mp.cos(mp.pi * (k + mp.mpf(1) / 2) / npts) for k in range(npts)]
+    ys = [f(x) for x in xs]
+    # scaled variable for conditioning, then expand back to the unscaled monomials
+    c, h = (a + b) / 2, (b - a) / 2
+    V = mp.matrix([[((x - c) / h) ** k for k in range(deg + 1)] for x in xs])
+    coef = mp.lu_solve(V.T * V, V.T * mp.matrix(ys))
+    return [coef[k] for k in range(deg + 1)], c, h
+
+
+def to_monomial(coef_scaled, c, h, shift):
+    """Coefficients of p((x - c)/h) as a polynomial in (x - shift)."""
+    deg = len(coef_scaled) - 1
+    # p(x) = sum a_k ((x - shift + shift - c)/h)^k
+    d = (mp.mpf(shift) - c) / h
+    out = [mp.mpf(0)] * (deg + 1)
+    for k, a in enumerate(coef_scaled):
+        # ((t + d*h)/h)^k with t = x - shift = sum_j C(k,j) t^j d^(k-j) / h^j
+        for j in range(k + 1):
+            out[j] += a * mp.binomial(k, j) * d ** (k - j) / h ** j
+    return out
+
+
+def build():
+    tables = {}
+    for name in ("J0", "J1", "R0", "R1"):
+        cs, c, h = lsq_poly(lambda w, n=name: fa(n, w), mp.mpf(0), mp.mpf(ZA) ** 2, DEG_A)
+        tables["A_" + name] = to_monomial(cs, c, h, 0)
+    nint = int(round((ZC - ZA) / HB))
+    btab = []
+    for i in range(nint):
+        lo = mp.mpf(ZA) + i * mp.mpf(HB)
+        hi = lo + mp.mpf(HB)
+        row = []
+        for name in ("J0", "Y0", "J1", "Y1r"):
+            cs, c, h = lsq_poly(lambda z, n=name: fb(n, z), lo, hi, DEG_B)
+            row.append(to_monomial(cs, c, h, c))
+        btab.append(row)
+    tables["B"] = btab
+    for name in ("P0", "Q0", "P1", "Q1"):
+        eps = mp.mpf("1e-40")
+        cs, c, h = lsq_poly(lambda u, n=name: fc(n, u if u > eps else eps), mp.mpf(0), mp.mpf(1), DEG_C)
+        tables["C_" + name] = to_monomial(cs, c, h, 0)
+    return tables
+
+
+# ----------------------------------------------------------------------------
+# float64 model of the device evaluation (used only to report the error here)
+
+def _horner(c, x):
+    acc = np.zeros_like(x) + float(c[-1])
+    for a in reversed(c[:-1]):
+        acc = acc * x + float(a)
+    return acc
+
+
+def eval_f64(t, z):
+    z = np.asarray(z, dtype=np.float64)
+    out = np.empty((2,) + z.shape, dtype=np.complex128)
+    A = z < ZA
+    C = z >= ZC
+    B = ~A & ~C
+    if A.any():
+        za = z[A]
+        w = za * za
+        j0 = _horner(t["A_J0"], w)
+        j1 = za * _horner(t["A_J1"], w)
+        lg = (2 / np.pi) * np.log(0.5 * za)
+        y0 = lg * j0 + _horner(t["A_R0"], w)
+        y1 = lg * j1 + za * _horner(t["A_R1"], w) - 2 / (np.pi * za)
+        out[0, A], out[1, A] = j0 + 1j * y0, j1 + 1j * y1
+    if B.any():
+        zb = z[B]
+        idx = np.minimum(((zb - ZA) / HB).astype(int), len(t["B"]) - 1)
+        res = np.empty((4, zb.size))
+        for q in range(zb.size):
+            row = t["B"][idx[q]]
+            s = zb[q] - (ZA + (idx[q] + 0.5) * HB)
+            res[:, q] = [_horner(row[f], np.array(s)) for f in range(4)]
+        out[0, B] = res[0] + 1j * res[1]
+        out[1, B] = res[2] + 1j * (res[3] - 2 / (np.pi * zb))
+    if C.any():
+        zc = z[C]
+        u = (ZC / zc) ** 2
+        amp = np.sqrt(2 / (np.pi * zc))
+        # exp(i (z - pi/4)) = (cos z + sin z + i (sin z - cos z)) / sqrt 2
+        cz, sz = np.cos(zc), np.sin(zc)
+        ph = ((cz + sz) + 1j * (sz - cz)) * np.sqrt(0.5)
+        out[0, C] = amp * (_horner(t["C_P0"], u) + 1j * _horner(t["C_Q0"], u) / zc) * ph
+        out[1, C] = amp * (_horner(t["C_P1"], u) + 1j * _horner(t["C_Q1"], u) / zc) * ph * (-1j)
+    return out
+
+
+def report(t):
+    zs = np.concatenate([np.geomspace(1e-3, 1e4, 4000), np.linspace(3.5, 8.5, 1001)])
+    got = eval_f64(t, zs)
+    worst = {}
+    for q, z in enumerate(zs):
+        reg = "A" if z < ZA else ("B" if z < ZC else "C")
+        for n in (0, 1):
+            ref = complex(mp.besselj(n, z) + 1j * mp.bessely(n, z))
+            e = abs(got[n, q] - ref) / abs(ref)
+            worst[(reg, n)] = max(worst.get((reg, n), 0.0), e)
+    return worst
+
+
+def emit(t, path):
+    def arr(name, vals):
+        body = ",\n    ".join(mp.nstr(v, 21, min_fixed=-1, max_fixed=-1).replace("e", "e") for v in vals)
+        return f"constexpr double {name}[{len(vals)}] = {{\n    {body}\n}};\n"
+
+    lines = ["// Generated by gen_bessel_coeffs.py from mpmath (40 digits). Do not edit.",
+             "// Polynomial coefficients are listed from degree 0 upwards.",
+             "#pragma once", "",
+             "namespace bm_bessel_coef {", "",
+             f"constexpr double ZA = {ZA!r};   // series region: 0 < z < ZA",
+             f"constexpr double ZC = {ZC!r};   // large-argument region: z >= ZC",
+             f"constexpr double HB = {HB!r};   // width of the piecewise intervals in [ZA, ZC)",
+             f"constexpr int NB = {len(t['B'])};        // number of intervals",
+             f"constexpr int DB = {DEG_B + 1};       // coefficients per interval polynomial", ""]
+    for name in ("A_J0", "A_J1", "A_R0", "A_R1", "C_P0", "C_Q0", "C_P1", "C_Q1"):
+        lines.append(arr(name, t[name]))
+    flat = []
+    for row in t["B"]:
+        for f in row:
+            flat.extend(f)
+    lines.append("// [interval][J0, Y0, J1, Y1 + 2/(pi z)][coefficient in s = z - centre]")
+    lines.append(arr("B_TAB", flat))
+    lines.append("}  // namespace bm_bessel_coef")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def main():
+    t = build()
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bessel_coeffs.h")
+    emit(t, out)
+    w = report(t)
+    print(f"wrote {out}; float64 model, max relative error of H_n by region:")
+    for key in sorted(w):
+        print(f"  region {key[0]} H{key[1]}: {w[key]:.2e}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

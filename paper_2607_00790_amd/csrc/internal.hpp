@@ -1,0 +1,76 @@
+// Library-internal declarations shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/bmhss.h"
+#include "wsbm_pair.hpp"
+
+// Device node data of a discretised boundary: six FP64 rows of length n
+// (x, y, nx, ny, w, kappa) and the index of the closed curve of each node.
+struct bm_geom {
+    int64_t n = 0;
+    int ncurves = 0;
+    double* soa = nullptr;    // device, 6 * n
+    int32_t* curve = nullptr; // device, n
+    int device = 0;
+};
+
+struct bm_problem {
+    const bm_geom* g = nullptr;
+    bm::Media media{};
+};
+
+namespace bm {
+
+// thread-local error reporting
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+void clear_error();
+
+#define BM_HIP(call)                                                   \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return ::bm::hip_fail(e_, #call);        \
+    } while (0)
+
+// Node fields as separate row pointers.
+struct NodeView {
+    const double* x;
+    const double* y;
+    const double* nx;
+    const double* ny;
+    const double* w;
+    const double* kappa;
+    const int32_t* curve;
+};
+
+inline NodeView view(const bm_geom* g) {
+    const int64_t n = g->n;
+    return NodeView{g->soa, g->soa + n, g->soa + 2 * n, g->soa + 3 * n,
+                    g->soa + 4 * n, g->soa + 5 * n, g->curve};
+}
+
+// Kernel launchers (assemble.hip)
+hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurves, int64_t n,
+                           double* soa, int32_t* curve, hipStream_t s);
+hipError_t launch_dense(const NodeView& v, int64_t n, const Media& m, double* A, int64_t ld,
+                        hipStream_t s);
+hipError_t launch_block(const NodeView& v, const Media& m, const int64_t* rows, int64_t nr,
+                        const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s);
+hipError_t launch_proxy(const NodeView& v, const Media& m, const int64_t* nodes, int64_t n,
+                        const double* pts, int64_t P, int dir, double* out, int64_t ld,
+                        hipStream_t s);
+hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media& m, double angle,
+                                 double* rhs, hipStream_t s);
+// matrix-free product; `work` is a device buffer of matvec_work_doubles(n) doubles
+hipError_t launch_matvec(const NodeView& v, int64_t n, const Media& m, const double* x,
+                         double* y, double* work, hipStream_t s);
+int64_t matvec_work_doubles(int64_t n);
+hipError_t launch_far_field(const NodeView& v, int64_t n, const Media& m, const double* phi,
+                            const double* angles, int64_t nang, double* uinf, hipStream_t s);
+
+}  // namespace bm

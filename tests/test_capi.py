@@ -1,0 +1,99 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point that
+include/bmhss.h declares, and rejects bad arguments on the host (BM_EINVAL)
+before any device work is enqueued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scatterers as sc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bmhss.h")
+LIB = os.path.join(ROOT, "paper_2607_00790_amd", "libbmhss.so")
+
+BM_EINVAL = 1
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bm_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libbmhss.so not built")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("bm_geom_create", "bm_problem_create", "bm_assemble_dense", "bm_assemble_block",
+                     "bm_assemble_proxy", "bm_rhs_plane_wave", "bm_far_field", "bm_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _geom_create(lib, sizes, xyd):
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.bm_geom_create.argtypes = [ctypes.c_int, ctypes.POINTER(i64), vp, ctypes.c_int, vp,
+                                   ctypes.POINTER(vp)]
+    lib.bm_last_error.restype = ctypes.c_char_p
+    sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+    xyd = np.ascontiguousarray(xyd, dtype=np.float64)
+    out = vp()
+    code = lib.bm_geom_create(len(sizes), sizes.ctypes.data_as(ctypes.POINTER(i64)),
+                              xyd.ctypes.data, 0, None, ctypes.byref(out))
+    return code, lib.bm_last_error().decode(), out
+
+
+def test_geom_create_rejects_too_few_nodes(lib):
+    xyd, s = sc.sample_curves([sc.circle()], [6])
+    code, msg, out = _geom_create(lib, s, xyd)
+    assert code == BM_EINVAL and "8 nodes" in msg and not out.value
+
+
+def test_geom_create_rejects_non_finite(lib):
+    xyd, s = sc.sample_curves([sc.circle()], [16])
+    xyd[0, 3] = np.nan
+    code, msg, _ = _geom_create(lib, s, xyd)
+    assert code == BM_EINVAL and "non-finite" in msg
+
+
+def test_geom_create_rejects_clockwise_curve(lib):
+    xyd, s = sc.sample_curves([sc.circle(), sc.star(0.3, 5, 1.0, (4, 0))], [16, 32])
+    # reverse the orientation of the second curve: t -> -t flips x' and keeps x''
+    xyd[:, 16:] = xyd[:, 16:][:, ::-1]
+    xyd[2:4, 16:] *= -1
+    code, msg, _ = _geom_create(lib, s, xyd)
+    assert code == BM_EINVAL and "curve 1" in msg and "counter-clockwise" in msg
+
+
+def test_problem_create_rejects_bad_media(lib):
+    vp = ctypes.c_void_p
+
+    class Media(ctypes.Structure):
+        _fields_ = [("k0", ctypes.c_double), ("k1", ctypes.c_double), ("eps0", ctypes.c_double),
+                    ("eps1", ctypes.c_double)]
+
+    lib.bm_problem_create.argtypes = [vp, ctypes.POINTER(Media), ctypes.POINTER(vp)]
+    out = vp()
+    m = Media(-1.0, 15.0, 1.0, 2.25)
+    assert lib.bm_problem_create(vp(1), ctypes.byref(m), ctypes.byref(out)) == BM_EINVAL
+    assert lib.bm_problem_create(None, ctypes.byref(m), ctypes.byref(out)) == BM_EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_2607_00790_amd._binding as b
+    monkeypatch.setattr(b, "_LIB", None)
+    monkeypatch.setattr(b, "lib_path", lambda: str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        b.load()

@@ -1,0 +1,182 @@
+"""GPU parity of the HIP entry-generation path against the CPU oracle, called
+through the C-ABI (Python binding of include/bmhss.h).
+
+Bar (FP64): per 2x2 component of a block, max|diff| <= 1e-10 max|ref|, and
+per-entry relative error <= 1e-10 wherever |ref| >= 1e-6 max|ref|.  Sizes span
+several 256-wide tiles with ragged tails; the full-size star workload
+(N = 16384, k0 = 50, n = 1.5) is checked on sampled rows."""
+import sys
+
+import numpy as np
+import pytest
+
+import scatterers as sc
+from oracle import geometry, mie, wsbm
+
+from parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def case(curves, sizes):
+    xyd, s = sc.sample_curves(curves, sizes)
+    return xyd, s, geometry.discretize(xyd, s)
+
+
+def gpu_problem(bm, xyd, sizes, media):
+    g = bm.bm_geom_create(sizes, xyd)
+    return bm.bm_problem_create(g, media.k0, media.k1, media.eps0, media.eps1)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_geometry_nodes(gpu_lib):
+    bm = gpu_lib
+    note("geometry: star + circle")
+    xyd, s, nd = case([sc.star(0.3, 5), sc.circle(0.4, (3, 0))], [777, 64])
+    g = bm.bm_geom_create(s, xyd)
+    soa = to_np(bm.bm_geom_nodes(g))
+    ref = np.stack([nd.x[:, 0], nd.x[:, 1], nd.n[:, 0], nd.n[:, 1], nd.w, nd.kappa])
+    np.testing.assert_allclose(soa, ref, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["circle512", "star1000", "two_curves_ragged"])
+def test_dense_matches_oracle(gpu_lib, name):
+    bm = gpu_lib
+    note(f"dense parity: {name}")
+    if name == "circle512":
+        wl = sc.circle_workload(512)
+        xyd, s, nd = case(wl.curves, wl.sizes)
+        media = wl.media
+    elif name == "star1000":
+        xyd, s, nd = case([sc.star(0.3, 5)], [1000])
+        media = sc.media_from_index(50.0, 1.5)
+    else:
+        xyd, s, nd = case([sc.star(0.2, 4), sc.star(0.25, 3, 1.0, (3.0, 0.5))], [301, 197])
+        media = sc.media_from_index(20.0, 2.0)
+    p = gpu_problem(bm, xyd, s, media)
+    A = to_np(bm.bm_assemble_dense(p))
+    ref = wsbm.assemble_dense(nd, media)
+    assert_parity(A, ref)
+
+
+def test_dense_full_size_star_sampled_rows(gpu_lib):
+    """Full star workload, same launch as the benchmark's dense sweep."""
+    import torch
+    bm = gpu_lib
+    note("dense parity: star N=16384 sampled rows")
+    wl = sc.star_workload()
+    xyd, s, nd = case(wl.curves, wl.sizes)
+    p = gpu_problem(bm, xyd, s, wl.media)
+    A = bm.bm_assemble_dense(p)
+    rng = np.random.default_rng(7)
+    nodes = np.unique(np.concatenate([[0, 1, 255, 256, 8191, 16383], rng.integers(0, 16384, 26)]))
+    rows = torch.from_numpy(np.sort(np.concatenate([2 * nodes, 2 * nodes + 1]))).cuda()
+    got = to_np(A.index_select(0, rows))
+    ref = wsbm.assemble_rows(nd, wl.media, nodes)
+    assert_parity(got, ref)
+
+
+def test_block_index_lists(gpu_lib):
+    import torch
+    bm = gpu_lib
+    note("block parity: index lists with diagonal pairs, ragged")
+    xyd, s, nd = case([sc.star(0.3, 5)], [2000])
+    media = sc.media_from_index(50.0, 1.5)
+    p = gpu_problem(bm, xyd, s, media)
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([np.arange(100, 140), rng.integers(0, 2000, 27)])
+    cols = np.concatenate([np.arange(90, 150), rng.integers(0, 2000, 300)])
+    got = to_np(bm.bm_assemble_block(p, torch.from_numpy(rows), torch.from_numpy(cols)))
+    ref = wsbm.system_blocks(nd, media, rows, cols).reshape(2 * len(rows), 2 * len(cols))
+    assert_parity(got, ref)
+    # empty lists are a no-op
+    out = bm.bm_assemble_block(p, torch.zeros(0, dtype=torch.int64), torch.from_numpy(cols))
+    assert out.shape == (0, 2 * len(cols))
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_proxy_blocks(gpu_lib, direction):
+    import torch
+    bm = gpu_lib
+    note(f"proxy parity: dir {direction}")
+    xyd, s, nd = case([sc.star(0.3, 5)], [4096])
+    media = sc.media_from_index(50.0, 1.5)
+    p = gpu_problem(bm, xyd, s, media)
+    box = np.arange(1000, 1128)
+    c = nd.x[box].mean(0)
+    R = np.max(np.hypot(*(nd.x[box] - c).T))
+    P = 70
+    th = 2 * np.pi * np.arange(P) / P
+    px = c[None, :] + 1.5 * R * np.stack([np.cos(th), np.sin(th)], 1)
+    pn = np.stack([np.cos(th), np.sin(th)], 1)
+    pw = np.full(P, 2 * np.pi * 1.5 * R / P)
+    pts = torch.from_numpy(np.stack([px[:, 0], px[:, 1], pn[:, 0], pn[:, 1], pw])).cuda()
+    got = to_np(bm.bm_assemble_proxy(p, torch.from_numpy(box), pts, direction))
+    if direction == 0:
+        ref = wsbm.pair_blocks(nd.x[box], nd.n[box], px, pn, pw, media)
+        ref = ref.reshape(2 * len(box), 2 * P)
+    else:
+        ref = wsbm.pair_blocks(px, pn, nd.x[box], nd.n[box], nd.w[box], media)
+        ref = ref.reshape(2 * P, 2 * len(box))
+    assert_parity(got, ref)
+
+
+def test_rhs_matvec_far_field(gpu_lib):
+    import torch
+    bm = gpu_lib
+    note("rhs / matvec / far field parity")
+    xyd, s, nd = case([sc.star(0.3, 5)], [700])
+    media = sc.media_from_index(30.0, 1.5)
+    p = gpu_problem(bm, xyd, s, media)
+    rhs = to_np(bm.bm_rhs_plane_wave(p, 0.7))
+    ref = wsbm.rhs_plane_wave(nd, media, 0.7)
+    assert np.abs(rhs - ref).max() <= 1e-13 * np.abs(ref).max()
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(1400) + 1j * rng.standard_normal(1400)
+    y = to_np(bm.bm_matvec(p, torch.from_numpy(x).cuda()))
+    yref = wsbm.assemble_dense(nd, media) @ x
+    assert np.abs(y - yref).max() <= 1e-12 * np.abs(yref).max()
+    ang = np.linspace(0, 2 * np.pi, 37)
+    ff = to_np(bm.bm_far_field(p, torch.from_numpy(x).cuda(), torch.from_numpy(ang)))
+    ffref = wsbm.far_field(nd, media, x, ang)
+    assert np.abs(ff - ffref).max() <= 1e-12 * np.abs(ffref).max()
+
+
+def test_dense_solution_vs_oracle_and_mie(gpu_lib):
+    """Plain dense workload: GPU-assembled matrix, LU on the device; the
+    solution matches the oracle's to 1e-10 and its Mie error is within 2x."""
+    import torch
+    bm = gpu_lib
+    note("dense solve: circle N=512 vs oracle and Mie")
+    wl = sc.circle_workload(512)
+    xyd, s, nd = case(wl.curves, wl.sizes)
+    p = gpu_problem(bm, xyd, s, wl.media)
+    A = bm.bm_assemble_dense(p)
+    b = bm.bm_rhs_plane_wave(p, 0.0)
+    phi = to_np(torch.linalg.solve(A, b))
+    ref = wsbm.solve_dense(wsbm.assemble_dense(nd, wl.media), wsbm.rhs_plane_wave(nd, wl.media, 0.0))
+    assert np.linalg.norm(phi - ref) <= 1e-10 * np.linalg.norm(ref)
+    t = 2 * np.pi * np.arange(512) / 512
+    u, _ = mie.boundary_values(wl.media, t)
+    e_gpu = np.linalg.norm(phi[0::2].real - u.real) / np.linalg.norm(u.real)
+    e_ora = np.linalg.norm(ref[0::2].real - u.real) / np.linalg.norm(u.real)
+    assert e_gpu <= 2 * e_ora
+
+
+def test_invalid_arguments_enqueue_nothing(gpu_lib):
+    import torch
+    bm = gpu_lib
+    xyd, s, _ = case([sc.circle()], [64])
+    p = gpu_problem(bm, xyd, s, sc.media_from_index(10, 1.5))
+    with pytest.raises((bm.BmError, ValueError)):
+        bm.bm_assemble_dense(p, out=torch.empty((128, 100), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(bm.BmError):
+        bm.bm_assemble_proxy(p, torch.arange(4), torch.zeros((5, 3), dtype=torch.float64).cuda(), 2)
