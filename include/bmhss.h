@@ -46,6 +46,7 @@ enum {
 
 typedef struct bm_geom bm_geom;
 typedef struct bm_problem bm_problem;
+typedef struct bm_hss bm_hss;
 
 /* Material constants: wavenumbers k_j = omega sqrt(eps_j mu_j) and permittivities
  * of the exterior (0) and interior (1) media (Sec. II, Table I).  The
@@ -115,6 +116,51 @@ int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t strea
  * exterior representation u_sc = D_k0[u] - S_k0[eps0 q] (remark after Eq. (3)). */
 int bm_far_field(const bm_problem* p, const double* phi, const double* angles, int64_t nang,
                  double* uinf, hipStream_t stream);
+
+/* ---- Proxy-surface HSS direct solver (Sec. III) ----
+ * The boundary nodes are split by a perfect binary tree of contiguous index
+ * ranges (Fig. 2) down to leaves of about `leaf` nodes.  At every level each
+ * box is compressed by an interpolative decomposition (ID) of its interactions
+ * with the near boxes (other boxes' active unknowns inside its proxy circle)
+ * and with `proxy_points` pseudo-nodes on a circle of radius
+ * proxy_ratio * (box radius).  The ID is column-pivoted QR with relative
+ * tolerance id_tol; skeletons are sets of unknowns shared by rows and columns.
+ * The factorisation is the Martinsson-Rokhlin recursion: per box
+ * Dhat = (T^T D^-1 T)^-1, E = D^-1 T Dhat, F^T = Dhat T^T D^-1,
+ * G = D^-1 - D^-1 T Dhat T^T D^-1, and a dense LU at the root. */
+typedef struct {
+    int64_t leaf;          /* target leaf size in nodes (>= 4) */
+    double proxy_ratio;    /* proxy circle radius / box radius (> 1) */
+    int64_t proxy_points;  /* points per proxy circle (>= 8) */
+    double id_tol;         /* relative ID tolerance (0 < tol < 1) */
+} bm_hss_opts;
+
+typedef struct {
+    int32_t levels;            /* tree depth: the leaves are level `levels` */
+    int32_t compressed_levels; /* levels compressed by the proxy ID */
+    int32_t root_size;         /* unknowns of the dense root system */
+    int32_t reserved;
+    int64_t max_rank;          /* largest skeleton (unknowns) over all boxes */
+    int64_t entries;           /* matrix entries generated during the build */
+    int64_t pairs;             /* node pairs evaluated (each gives a 2x2 block) */
+    double seconds_generate;   /* time in entry-generation kernels (HIP events) */
+    double seconds_compress;   /* time in the ID kernels (HIP events) */
+    double seconds_factor;     /* time in inversion and GEMM kernels (HIP events) */
+    double seconds_total;      /* wall time of bm_hss_build */
+} bm_hss_stats_t;
+
+/* Build the factorisation; synchronises `stream` once per level to read the
+ * ranks back, and returns after the whole build has completed on the stream. */
+int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t stream, bm_hss** out);
+/* x = A^{-1} b for nrhs right-hand sides (device, 2N x nrhs complex, each
+ * right-hand side contiguous: b[r*2N + i]).  x may alias b.  The solve is an
+ * upward sweep F^T b, a dense product with the inverted root system and a
+ * downward sweep G b + E x.  Returns after the solve has completed on the
+ * stream. */
+int bm_hss_solve(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t stream);
+int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out);
+int bm_hss_destroy(bm_hss* h);
+
 
 #ifdef __cplusplus
 }

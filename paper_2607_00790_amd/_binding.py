@@ -32,9 +32,11 @@ class _HssOpts(ctypes.Structure):
 
 
 class _HssStats(ctypes.Structure):
-    _fields_ = [("levels", ctypes.c_int32), ("root_size", ctypes.c_int32),
-                ("max_rank", c_i64), ("entries", c_i64), ("seconds_generate", c_dbl),
-                ("seconds_total", c_dbl)]
+    _fields_ = [("levels", ctypes.c_int32), ("compressed_levels", ctypes.c_int32),
+                ("root_size", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_rank", c_i64), ("entries", c_i64), ("pairs", c_i64),
+                ("seconds_generate", c_dbl), ("seconds_compress", c_dbl),
+                ("seconds_factor", c_dbl), ("seconds_total", c_dbl)]
 
 
 def lib_path() -> str:
@@ -67,15 +69,13 @@ def load():
         "bm_matvec": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp]),
         "bm_far_field": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]),
     }
-    optional = {
+    sig.update({
         "bm_hss_build": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssOpts), c_vp, ctypes.POINTER(c_vp)]),
         "bm_hss_solve": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp]),
         "bm_hss_stats": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssStats)]),
         "bm_hss_destroy": (ctypes.c_int, [c_vp]),
-    }
-    for name, (res, args) in list(sig.items()) + list(optional.items()):
-        if name in optional and not hasattr(lib, name):
-            continue
+    })
+    for name, (res, args) in sig.items():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
@@ -269,8 +269,6 @@ def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
 
 def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10,
                  stream=None) -> HSS:
-    if not hasattr(_LIB, "bm_hss_build"):
-        raise RuntimeError("this libbmhss.so has no HSS solver")
     opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol))
     out = c_vp()
     _check(_LIB.bm_hss_build(p._h, ctypes.byref(opts), _stream(stream), ctypes.byref(out)))

@@ -1,0 +1,743 @@
+// Host driver of the proxy-surface HSS build and solve (C-ABI bm_hss_*).
+//
+// Tree (paper Sec. III, Fig. 2): a perfect binary tree of contiguous node
+// ranges; level l has 2^l boxes, box b covers nodes [b N / 2^l, (b+1) N / 2^l).
+// Per compressed level, leaves first:
+//   1. box centres/radii and proxy circles               (k_box_geometry)
+//   2. near sets: other boxes' active unknowns inside the proxy circle
+//                                                        (k_near_count/list)
+//   3. M_b = [A(U_b, near) | A(near, U_b)^T | A(U_b, proxy) | A(proxy, U_b)^T]
+//      for every box in ONE generation launch            (k_gen_jobs)
+//   4. ID of the rows of M_b: CPQR of M_b^T, skeleton J_b, interpolation T_b
+//                                                        (k_cpqr, k_interp)
+//   5. D_b: leaf A(U_b, U_b); above, [[Dhat_a, A(J_a,J_b)], [A(J_b,J_a), Dhat_b]]
+//   6. Martinsson-Rokhlin factors Dhat, E, F^T, G        (k_gauss_jordan, k_gemm)
+// The reduced system above the last compressed level is inverted densely.
+// The host only does index bookkeeping (slot lists, offsets); it reads back the
+// near counts and the ranks once per level to size the next buffers.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <cmath>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "hss_internal.hpp"
+
+using namespace bm;
+using namespace bm::hss;
+
+namespace {
+
+struct LevelFactor {
+    int nb = 0;
+    std::vector<int64_t> n, k;       // unknowns and ranks per box
+    std::vector<int64_t> uoff, koff; // prefix sums of n and k
+    std::vector<int64_t> nkoff, nnoff;
+    int64_t nu = 0, nk = 0;
+    double2* E = nullptr;   // per box n x k
+    double2* Ft = nullptr;  // per box k x n
+    double2* G = nullptr;   // per box n x n
+};
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device temporaries and host staging that live until the next sync point.
+struct Scratch {
+    hipStream_t s;
+    std::vector<void*> dev;
+    std::vector<std::shared_ptr<std::vector<char>>> host;
+    explicit Scratch(hipStream_t st) : s(st) {}
+    template <class T>
+    hipError_t alloc(T** p, size_t count) {
+        *p = nullptr;
+        hipError_t e = hipMallocAsync(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T), s);
+        if (e == hipSuccess) dev.push_back(*p);
+        return e;
+    }
+    template <class T>
+    hipError_t upload(T** p, const std::vector<T>& v) {
+        hipError_t e = alloc(p, v.size());
+        if (e != hipSuccess || v.empty()) return e;
+        auto h = std::make_shared<std::vector<char>>(v.size() * sizeof(T));
+        std::memcpy(h->data(), v.data(), h->size());
+        host.push_back(h);
+        return hipMemcpyAsync(*p, h->data(), h->size(), hipMemcpyHostToDevice, s);
+    }
+    void release() {
+        for (void* p : dev) (void)hipFreeAsync(p, s);
+        dev.clear();
+    }
+    void drop_host() { host.clear(); }
+};
+
+hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
+                      const PointTable& pt, const Media& m, double2* out) {
+    if (jobs.empty()) return hipSuccess;
+    std::vector<int64_t> toff(jobs.size() + 1, 0);
+    for (size_t j = 0; j < jobs.size(); ++j)
+        toff[j + 1] = toff[j] + ceil_div(static_cast<int64_t>(jobs[j].nt) * jobs[j].ns, kThreads);
+    if (toff.back() == 0) return hipSuccess;
+    GenJob* dj;
+    int64_t* dt;
+    hipError_t e = sc.upload(&dj, jobs);
+    if (e == hipSuccess) e = sc.upload(&dt, toff);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gen_jobs, dim3(static_cast<unsigned>(toff.back())), dim3(kThreads), 0, sc.s,
+                       dj, dt, static_cast<int>(jobs.size()), slots, pt, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
+    if (jobs.empty()) return hipSuccess;
+    std::vector<int64_t> toff(jobs.size() + 1, 0);
+    for (size_t j = 0; j < jobs.size(); ++j)
+        toff[j + 1] = toff[j] + ceil_div(jobs[j].M, 32) * ceil_div(jobs[j].N, 32);
+    if (toff.back() == 0) return hipSuccess;
+    GemmJob* dj;
+    int64_t* dt;
+    hipError_t e = sc.upload(&dj, jobs);
+    if (e == hipSuccess) e = sc.upload(&dt, toff);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gemm, dim3(static_cast<unsigned>(toff.back())), dim3(kThreads), 0, sc.s, dj,
+                       dt, static_cast<int>(jobs.size()));
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(Scratch& sc, const std::vector<CopyJob>& jobs) {
+    if (jobs.empty()) return hipSuccess;
+    CopyJob* dj;
+    hipError_t e = sc.upload(&dj, jobs);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copy_blocks, dim3(64, static_cast<unsigned>(jobs.size())), dim3(kThreads), 0,
+                       sc.s, dj);
+    return hipGetLastError();
+}
+
+constexpr int kBatchedInverseMax = 320;   // larger matrices use the multi-workgroup path
+
+// Invert the given matrices in place; a zero pivot sets the job's status flag.
+// Jobs with n <= kBatchedInverseMax run one workgroup each in one launch;
+// larger ones use two launches per elimination step over the whole device.
+hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
+    std::vector<InvJob> small;
+    int nmax = 0;
+    hipError_t e = hipSuccess;
+    for (const InvJob& j : jobs) {
+        if (j.n == 0) continue;
+        if (j.n <= kBatchedInverseMax) {
+            small.push_back(j);
+            nmax = std::max(nmax, j.n);
+            continue;
+        }
+        double2* col;
+        if ((e = sc.alloc(&col, j.n)) != hipSuccess) return e;
+        for (int k = 0; k < j.n; ++k) {
+            hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kThreads), 0, sc.s, j.a, j.n, k, j.piv, col, j.status);
+            hipLaunchKernelGGL(k_gj_eliminate, dim3(static_cast<unsigned>(j.n)), dim3(kThreads), 0, sc.s, j.a,
+                               j.n, k, col, j.status);
+        }
+        hipLaunchKernelGGL(k_gj_unscramble, dim3(static_cast<unsigned>(ceil_div(j.n, kThreads))), dim3(kThreads),
+                           0, sc.s, j.a, j.n, j.piv, j.status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!small.empty()) {
+        InvJob* dj;
+        if ((e = sc.upload(&dj, small)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(static_cast<unsigned>(small.size())), dim3(kThreads),
+                           static_cast<size_t>(nmax) * sizeof(double2), sc.s, dj);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+GemmJob gemm(const double2* a, int64_t a_rs, int64_t a_cs, const double2* b, int64_t b_rs,
+             int64_t b_cs, double2* c, int64_t c_rs, int64_t c_cs, int64_t M, int64_t N, int64_t K,
+             double2 alpha = make_double2(1.0, 0.0), double2 beta = make_double2(0.0, 0.0)) {
+    GemmJob g;
+    g.a = a; g.b = b; g.c = c;
+    g.a_rs = a_rs; g.a_cs = a_cs; g.b_rs = b_rs; g.b_cs = b_cs; g.c_rs = c_rs; g.c_cs = c_cs;
+    g.alpha = alpha; g.beta = beta;
+    g.M = static_cast<int32_t>(M); g.N = static_cast<int32_t>(N); g.K = static_cast<int32_t>(K);
+    return g;
+}
+
+// Slots of an unknown list (global unknown ids): one slot per node in order of
+// first appearance, with the positions of its u / q unknowns in the list.
+void make_slots(const std::vector<int32_t>& U, std::vector<Slot>& out) {
+    std::vector<std::pair<int32_t, int32_t>> seen;   // node -> slot index (small linear map)
+    const size_t first = out.size();
+    for (size_t p = 0; p < U.size(); ++p) {
+        const int32_t node = U[p] >> 1;
+        const int comp = U[p] & 1;
+        int32_t si = -1;
+        // the u and q of one node are usually adjacent in the list
+        if (out.size() > first && out.back().pt == node) si = static_cast<int32_t>(out.size() - 1);
+        if (si < 0) {
+            for (const auto& pr : seen)
+                if (pr.first == node) { si = pr.second; break; }
+        }
+        if (si < 0) {
+            out.push_back(Slot{node, -1, -1});
+            si = static_cast<int32_t>(out.size() - 1);
+            seen.emplace_back(node, si);
+        }
+        if (comp == 0) out[si].pos0 = static_cast<int32_t>(p);
+        else out[si].pos1 = static_cast<int32_t>(p);
+    }
+}
+
+int count_unknowns(const Slot* s, size_t n) {
+    int c = 0;
+    for (size_t i = 0; i < n; ++i) c += (s[i].pos0 >= 0) + (s[i].pos1 >= 0);
+    return c;
+}
+
+}  // namespace
+
+struct bm_hss {
+    const bm_problem* p = nullptr;
+    bm_hss_opts opts{};
+    int64_t N = 0;
+    int levels = 0;
+    std::vector<LevelFactor> lv;   // compressed levels, leaves first
+    int64_t K = 0;                 // root size
+    double2* Rinv = nullptr;
+    std::vector<int64_t> root_off; // not used by the solve; kept for stats
+    bm_hss_stats_t stats{};
+};
+
+namespace {
+
+void free_factor(LevelFactor& f) {
+    (void)hipFree(f.E);
+    (void)hipFree(f.Ft);
+    (void)hipFree(f.G);
+    f.E = f.Ft = f.G = nullptr;
+}
+
+struct EventTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    hipError_t start(hipStream_t s, hipEvent_t& a) {
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        return e;
+    }
+    hipError_t stop(hipStream_t s, hipEvent_t a) {
+        hipEvent_t b;
+        hipError_t e = hipEventCreate(&b);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        ev.emplace_back(a, b);
+        return e;
+    }
+    double seconds() {
+        double t = 0;
+        for (auto& pr : ev) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) t += ms * 1e-3;
+        }
+        return t;
+    }
+    ~EventTimer() {
+        for (auto& pr : ev) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    }
+};
+
+int build_impl(bm_hss* h, hipStream_t s) {
+    const bm_problem* p = h->p;
+    const bm_geom* g = p->g;
+    const int64_t N = g->n;
+    const int P = static_cast<int>(h->opts.proxy_points);
+    const double tol = h->opts.id_tol;
+    int L = 0;
+    while ((N >> (L + 1)) >= h->opts.leaf && L < 30) ++L;
+    h->levels = L;
+    const NodeView nv = view(g);
+    EventTimer t_gen, t_cmp, t_fac;
+
+    // point table: nodes, then P proxy points per box of the current level
+    const int64_t npts = N + (int64_t{1} << L) * P;
+    PointTable pt{};
+    double* ptd = nullptr;
+    BM_HIP(hipMalloc(reinterpret_cast<void**>(&ptd), 6 * npts * sizeof(double)));
+    std::unique_ptr<double, void (*)(double*)> ptd_guard(ptd, [](double* q) { (void)hipFree(q); });
+    int32_t* ptc = nullptr;
+    BM_HIP(hipMalloc(reinterpret_cast<void**>(&ptc), npts * sizeof(int32_t)));
+    std::unique_ptr<int32_t, void (*)(int32_t*)> ptc_guard(ptc, [](int32_t* q) { (void)hipFree(q); });
+    pt.x = ptd; pt.y = ptd + npts; pt.nx = ptd + 2 * npts; pt.ny = ptd + 3 * npts;
+    pt.w = ptd + 4 * npts; pt.kappa = ptd + 5 * npts; pt.curve = ptc;
+    for (int r = 0; r < 6; ++r)
+        BM_HIP(hipMemcpyAsync(ptd + r * npts, g->soa + r * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    BM_HIP(hipMemcpyAsync(ptc, g->curve, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+
+    // active unknowns per box (global ids), leaves first
+    std::vector<std::vector<int32_t>> U(size_t{1} << L);
+    for (int64_t b = 0; b < (int64_t{1} << L); ++b) {
+        const int64_t lo = (b * N) >> L, hi = ((b + 1) * N) >> L;
+        for (int64_t i = lo; i < hi; ++i) {
+            U[b].push_back(static_cast<int32_t>(2 * i));
+            U[b].push_back(static_cast<int32_t>(2 * i + 1));
+        }
+    }
+    std::vector<int64_t> split_slots;     // per box: slots belonging to the first child
+    double2* Dhat_prev = nullptr;          // children's Dhat, packed per box (k x k)
+    std::vector<int64_t> dhat_prev_off;    // offsets per child box
+    std::vector<int64_t> k_prev;           // children's ranks
+    std::vector<int32_t*> status_bufs;
+    auto cleanup_status = [&]() { for (auto q : status_bufs) (void)hipFree(q); };
+    int64_t entries = 0, pairs = 0, max_rank = 0;
+
+    int compressed = 0;
+    for (int l = L; l >= 1; --l) {
+        const int nb = 1 << l;
+        Scratch sc(s);
+        // ---- box geometry and proxy points
+        std::vector<int64_t> lo(nb), hi(nb);
+        for (int b = 0; b < nb; ++b) {
+            lo[b] = (static_cast<int64_t>(b) * N) >> l;
+            hi[b] = (static_cast<int64_t>(b + 1) * N) >> l;
+        }
+        int64_t *dlo, *dhi;
+        double* box_c;
+        hipError_t e = sc.upload(&dlo, lo);
+        if (e == hipSuccess) e = sc.upload(&dhi, hi);
+        if (e == hipSuccess) e = sc.alloc(&box_c, 3 * nb);
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: level setup"); }
+        hipLaunchKernelGGL(k_box_geometry, dim3(nb), dim3(kThreads), 0, s, nv, dlo, dhi,
+                           h->opts.proxy_ratio, P, N, box_c, pt);
+        // ---- active slots
+        std::vector<Slot> act;
+        std::vector<int64_t> soff(nb + 1, 0), n(nb);
+        std::vector<int32_t> sbox;
+        for (int b = 0; b < nb; ++b) {
+            make_slots(U[b], act);
+            soff[b + 1] = static_cast<int64_t>(act.size());
+            n[b] = static_cast<int64_t>(U[b].size());
+            for (int64_t q = soff[b]; q < soff[b + 1]; ++q) sbox.push_back(b);
+        }
+        const int64_t nact = soff[nb];
+        int64_t* dcounts;
+        Slot* dact;
+        int32_t* dsbox;
+        e = sc.upload(&dact, act);
+        if (e == hipSuccess) e = sc.upload(&dsbox, sbox);
+        if (e == hipSuccess) e = sc.alloc(&dcounts, 2 * nb);
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slots"); }
+        hipLaunchKernelGGL(k_near_count, dim3(nb), dim3(kThreads), 0, s, pt, dact, dsbox, nact, box_c, dcounts);
+        std::vector<int64_t> counts(2 * nb);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), dcounts, counts.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        sc.drop_host();
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: near counts"); }
+        int64_t total_u = 0;
+        for (int b = 0; b < nb; ++b) total_u += n[b];
+        bool far_ok = true;
+        for (int b = 0; b < nb; ++b)
+            if (total_u - n[b] - counts[2 * b + 1] <= 0) far_ok = false;
+        if (!far_ok) { sc.release(); break; }   // this level is the root level
+
+        // ---- slot buffer: [active | near | proxy]
+        std::vector<int64_t> nsoff(nb + 1, 0), nearu(nb);
+        for (int b = 0; b < nb; ++b) {
+            nsoff[b + 1] = nsoff[b] + counts[2 * b];
+            nearu[b] = counts[2 * b + 1];
+        }
+        const int64_t near_base = nact, prox_base = nact + nsoff[nb];
+        const int64_t nslots_all = prox_base + static_cast<int64_t>(nb) * P;
+        Slot* dslots;
+        if ((e = sc.alloc(&dslots, nslots_all)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slot buffer"); }
+        e = hipMemcpyAsync(dslots, dact, nact * sizeof(Slot), hipMemcpyDeviceToDevice, s);
+        std::vector<Slot> prox(static_cast<size_t>(nb) * P);
+        for (int b = 0; b < nb; ++b)
+            for (int q = 0; q < P; ++q)
+                prox[static_cast<size_t>(b) * P + q] = Slot{static_cast<int32_t>(N + static_cast<int64_t>(b) * P + q), 2 * q, 2 * q + 1};
+        Slot* dprox;
+        if (e == hipSuccess) e = sc.upload(&dprox, prox);
+        if (e == hipSuccess) e = hipMemcpyAsync(dslots + prox_base, dprox, prox.size() * sizeof(Slot), hipMemcpyDeviceToDevice, s);
+        int64_t* dnsoff;
+        if (e == hipSuccess) e = sc.upload(&dnsoff, std::vector<int64_t>(nsoff.begin(), nsoff.end() - 1));
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slot upload"); }
+        hipLaunchKernelGGL(k_near_list, dim3(nb), dim3(kThreads), 0, s, pt, dact, dsbox, nact, box_c, dnsoff,
+                           dslots + near_base);
+
+        // ---- M_b for all boxes in one generation launch
+        std::vector<int64_t> m(nb), mo(nb + 1, 0);
+        for (int b = 0; b < nb; ++b) {
+            m[b] = 2 * nearu[b] + 4 * P;
+            mo[b + 1] = mo[b] + n[b] * m[b];
+        }
+        double2* M;
+        if ((e = sc.alloc(&M, mo[nb])) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: M"); }
+        std::vector<GenJob> jobs;
+        for (int b = 0; b < nb; ++b) {
+            const int32_t na = static_cast<int32_t>(soff[b + 1] - soff[b]);
+            const int32_t nn = static_cast<int32_t>(nsoff[b + 1] - nsoff[b]);
+            const int64_t base = mo[b];
+            jobs.push_back(GenJob{soff[b], near_base + nsoff[b], base, m[b], 1, na, nn});
+            jobs.push_back(GenJob{near_base + nsoff[b], soff[b], base + nearu[b], 1, m[b], nn, na});
+            jobs.push_back(GenJob{soff[b], prox_base + static_cast<int64_t>(b) * P, base + 2 * nearu[b], m[b], 1, na, P});
+            jobs.push_back(GenJob{prox_base + static_cast<int64_t>(b) * P, soff[b], base + 2 * nearu[b] + 2 * P, 1, m[b], P, na});
+            entries += n[b] * m[b];
+            pairs += 2 * static_cast<int64_t>(na) * (nn + P);
+        }
+        hipEvent_t ev;
+        if ((e = t_gen.start(s, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->media, M);
+        if (e == hipSuccess) e = t_gen.stop(s, ev);
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: generate M"); }
+
+        // ---- ID: CPQR of M_b^T
+        std::vector<int64_t> uoff(nb + 1, 0);
+        for (int b = 0; b < nb; ++b) uoff[b + 1] = uoff[b] + n[b];
+        int32_t *dperm, *dranks;
+        double2* drdiag;
+        e = sc.alloc(&dperm, uoff[nb]);
+        if (e == hipSuccess) e = sc.alloc(&drdiag, uoff[nb]);
+        if (e == hipSuccess) e = sc.alloc(&dranks, nb);
+        std::vector<CpqrJob> cj(nb);
+        int64_t nmax = 0;
+        for (int b = 0; b < nb; ++b) {
+            cj[b] = CpqrJob{M + mo[b], dperm + uoff[b], drdiag + uoff[b], static_cast<int32_t>(n[b]), static_cast<int32_t>(m[b])};
+            nmax = std::max(nmax, n[b]);
+        }
+        CpqrJob* dcj;
+        if (e == hipSuccess) e = sc.upload(&dcj, cj);
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: cpqr setup"); }
+        if ((e = t_cmp.start(s, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        hipLaunchKernelGGL(k_cpqr, dim3(nb), dim3(kThreads), static_cast<size_t>(nmax) * sizeof(double), s, dcj, tol, dranks);
+        std::vector<int32_t> ranks(nb), perm(uoff[nb]);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(ranks.data(), dranks, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        sc.drop_host();
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: cpqr"); }
+        std::vector<int64_t> k(nb), koff(nb + 1, 0), nkoff(nb + 1, 0), nnoff(nb + 1, 0), kkoff(nb + 1, 0);
+        for (int b = 0; b < nb; ++b) {
+            k[b] = ranks[b];
+            max_rank = std::max(max_rank, k[b]);
+            koff[b + 1] = koff[b] + k[b];
+            nkoff[b + 1] = nkoff[b] + n[b] * k[b];
+            nnoff[b + 1] = nnoff[b] + n[b] * n[b];
+            kkoff[b + 1] = kkoff[b] + k[b] * k[b];
+        }
+        double2* T;
+        e = sc.alloc(&T, nkoff[nb]);
+        if (e == hipSuccess) e = hipMemsetAsync(T, 0, std::max<int64_t>(nkoff[nb], 1) * sizeof(double2), s);
+        int64_t* dtoff;
+        if (e == hipSuccess) e = sc.upload(&dtoff, std::vector<int64_t>(nkoff.begin(), nkoff.end() - 1));
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: T"); }
+        hipLaunchKernelGGL(k_interp, dim3(nb), dim3(kThreads), 0, s, dcj, dranks, dtoff, T);
+        if ((e = t_cmp.stop(s, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+
+        // ---- diagonal blocks D_b (become G_b in place)
+        LevelFactor f;
+        f.nb = nb; f.n = n; f.k = k; f.uoff = uoff; f.koff = koff; f.nkoff = nkoff; f.nnoff = nnoff;
+        f.nu = uoff[nb]; f.nk = koff[nb];
+        e = hipMalloc(reinterpret_cast<void**>(&f.G), std::max<int64_t>(nnoff[nb], 1) * sizeof(double2));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&f.E), std::max<int64_t>(nkoff[nb], 1) * sizeof(double2));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&f.Ft), std::max<int64_t>(nkoff[nb], 1) * sizeof(double2));
+        if (e != hipSuccess) { free_factor(f); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factors"); }
+        h->lv.push_back(f);   // owned by h from here on
+        LevelFactor& F = h->lv.back();
+        jobs.clear();
+        std::vector<CopyJob> copies;
+        for (int b = 0; b < nb; ++b) {
+            const int32_t na = static_cast<int32_t>(soff[b + 1] - soff[b]);
+            if (l == L) {
+                jobs.push_back(GenJob{soff[b], soff[b], nnoff[b], n[b], 1, na, na});
+                entries += n[b] * n[b];
+                pairs += static_cast<int64_t>(na) * na;
+            } else {
+                const int64_t sa = split_slots[b];
+                const int32_t n1 = static_cast<int32_t>(sa), n2 = na - n1;
+                jobs.push_back(GenJob{soff[b], soff[b] + sa, nnoff[b], n[b], 1, n1, n2});
+                jobs.push_back(GenJob{soff[b] + sa, soff[b], nnoff[b], n[b], 1, n2, n1});
+                const int64_t ka = k_prev[2 * b], kb = k_prev[2 * b + 1];
+                entries += 2 * ka * kb;
+                pairs += 2 * static_cast<int64_t>(n1) * n2;
+                copies.push_back(CopyJob{Dhat_prev + dhat_prev_off[2 * b], F.G + nnoff[b], ka, 1, n[b], 1,
+                                         static_cast<int32_t>(ka), static_cast<int32_t>(ka)});
+                copies.push_back(CopyJob{Dhat_prev + dhat_prev_off[2 * b + 1], F.G + nnoff[b] + ka * n[b] + ka, kb, 1,
+                                         n[b], 1, static_cast<int32_t>(kb), static_cast<int32_t>(kb)});
+            }
+        }
+        if ((e = t_gen.start(s, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->media, F.G);
+        if (e == hipSuccess) e = t_gen.stop(s, ev);
+        if (e == hipSuccess) e = launch_copy(sc, copies);
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: D blocks"); }
+
+        // ---- Martinsson-Rokhlin factors
+        double2 *Y, *Wt, *S;
+        int32_t* piv;
+        e = sc.alloc(&Y, nkoff[nb]);
+        if (e == hipSuccess) e = sc.alloc(&Wt, nkoff[nb]);
+        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&S), std::max<int64_t>(kkoff[nb], 1) * sizeof(double2), s);
+        if (e == hipSuccess) e = sc.alloc(&piv, uoff[nb]);
+        int32_t* st = nullptr;
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&st), 2 * nb * sizeof(int32_t));
+        if (e == hipSuccess) { status_bufs.push_back(st); e = hipMemsetAsync(st, 0, 2 * nb * sizeof(int32_t), s); }
+        if (e != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor buffers"); }
+        if ((e = t_fac.start(s, ev)) != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        std::vector<InvJob> inv(nb);
+        for (int b = 0; b < nb; ++b) inv[b] = InvJob{F.G + nnoff[b], piv + uoff[b], st + b, static_cast<int32_t>(n[b])};
+        e = launch_inverse(sc, inv);
+        std::vector<GemmJob> g1, g2, g3, g4;
+        const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
+        for (int b = 0; b < nb; ++b) {
+            const int64_t nn = n[b], kk = k[b];
+            const double2* Di = F.G + nnoff[b];
+            const double2* Tb = T + nkoff[b];
+            // Y = D^-1 T (n x k); Wt = T^T D^-1 (k x n)
+            g1.push_back(gemm(Di, nn, 1, Tb, kk, 1, Y + nkoff[b], kk, 1, nn, kk, nn));
+            g1.push_back(gemm(Tb, 1, kk, Di, nn, 1, Wt + nkoff[b], nn, 1, kk, nn, nn));
+        }
+        if (e == hipSuccess) e = launch_gemm(sc, g1);
+        for (int b = 0; b < nb; ++b) {
+            const int64_t nn = n[b], kk = k[b];
+            // S = Wt T (k x k)
+            g2.push_back(gemm(Wt + nkoff[b], nn, 1, T + nkoff[b], kk, 1, S + kkoff[b], kk, 1, kk, kk, nn));
+        }
+        if (e == hipSuccess) e = launch_gemm(sc, g2);
+        std::vector<InvJob> inv2(nb);
+        for (int b = 0; b < nb; ++b) inv2[b] = InvJob{S + kkoff[b], piv + uoff[b], st + nb + b, static_cast<int32_t>(k[b])};
+        if (e == hipSuccess) e = launch_inverse(sc, inv2);
+        for (int b = 0; b < nb; ++b) {
+            const int64_t nn = n[b], kk = k[b];
+            // E = Y Dhat (n x k); Ft = Dhat Wt (k x n)
+            g3.push_back(gemm(Y + nkoff[b], kk, 1, S + kkoff[b], kk, 1, F.E + nkoff[b], kk, 1, nn, kk, kk));
+            g3.push_back(gemm(S + kkoff[b], kk, 1, Wt + nkoff[b], nn, 1, F.Ft + nkoff[b], nn, 1, kk, nn, kk));
+        }
+        if (e == hipSuccess) e = launch_gemm(sc, g3);
+        for (int b = 0; b < nb; ++b) {
+            const int64_t nn = n[b], kk = k[b];
+            // G = D^-1 - E Wt (in place)
+            g4.push_back(gemm(F.E + nkoff[b], kk, 1, Wt + nkoff[b], nn, 1, F.G + nnoff[b], nn, 1, nn, nn, kk, mone, one));
+        }
+        if (e == hipSuccess) e = launch_gemm(sc, g4);
+        if (e == hipSuccess) e = t_fac.stop(s, ev);
+        if (e != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor"); }
+
+        // ---- next level: U(parent) = J(first child) then J(second child)
+        if (Dhat_prev) (void)hipFreeAsync(Dhat_prev, s);
+        Dhat_prev = S;
+        dhat_prev_off.assign(kkoff.begin(), kkoff.end() - 1);
+        k_prev = k;
+        std::vector<std::vector<int32_t>> J(nb);
+        for (int b = 0; b < nb; ++b) {
+            J[b].resize(k[b]);
+            for (int64_t i = 0; i < k[b]; ++i) J[b][i] = U[b][perm[uoff[b] + i]];
+        }
+        U.assign(nb / 2, {});
+        split_slots.assign(nb / 2, 0);
+        for (int q = 0; q < nb / 2; ++q) {
+            U[q] = J[2 * q];
+            std::vector<Slot> tmp;
+            make_slots(J[2 * q], tmp);
+            split_slots[q] = static_cast<int64_t>(tmp.size());
+            U[q].insert(U[q].end(), J[2 * q + 1].begin(), J[2 * q + 1].end());
+        }
+        e = hipStreamSynchronize(s);   // the level's temporaries may be released now
+        sc.drop_host();
+        sc.release();
+        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: level end"); }
+        ++compressed;
+    }
+
+    // ---- root: the reduced system over the current active unknowns
+    {
+        Scratch sc(s);
+        std::vector<int32_t> Ur;
+        std::vector<int64_t> boff;   // start of each current box in Ur
+        for (auto& u : U) {
+            boff.push_back(static_cast<int64_t>(Ur.size()));
+            Ur.insert(Ur.end(), u.begin(), u.end());
+        }
+        const int64_t K = static_cast<int64_t>(Ur.size());
+        h->K = K;
+        std::vector<Slot> rs;
+        make_slots(Ur, rs);
+        Slot* drs;
+        hipError_t e = sc.upload(&drs, rs);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->Rinv), std::max<int64_t>(K * K, 1) * sizeof(double2));
+        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: root"); }
+        std::vector<GenJob> jobs{GenJob{0, 0, 0, K, 1, static_cast<int32_t>(rs.size()), static_cast<int32_t>(rs.size())}};
+        entries += K * K;
+        pairs += static_cast<int64_t>(rs.size()) * rs.size();
+        hipEvent_t ev;
+        if ((e = t_gen.start(s, ev)) == hipSuccess) e = launch_gen(sc, jobs, drs, pt, p->media, h->Rinv);
+        if (e == hipSuccess) e = t_gen.stop(s, ev);
+        // diagonal blocks of the last compressed level's boxes are their Dhat
+        std::vector<CopyJob> copies;
+        if (compressed > 0) {
+            int64_t off = 0;
+            for (size_t c = 0; c < k_prev.size(); ++c) {
+                copies.push_back(CopyJob{Dhat_prev + dhat_prev_off[c], h->Rinv + off * K + off, k_prev[c], 1, K, 1,
+                                         static_cast<int32_t>(k_prev[c]), static_cast<int32_t>(k_prev[c])});
+                off += k_prev[c];
+            }
+        }
+        if (e == hipSuccess) e = launch_copy(sc, copies);
+        int32_t *piv, *st;
+        if (e == hipSuccess) e = sc.alloc(&piv, K);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&st), sizeof(int32_t));
+        if (e == hipSuccess) { status_bufs.push_back(st); e = hipMemsetAsync(st, 0, sizeof(int32_t), s); }
+        if (e == hipSuccess && (e = t_fac.start(s, ev)) == hipSuccess) {
+            e = launch_inverse(sc, {InvJob{h->Rinv, piv, st, static_cast<int32_t>(K)}});
+            if (e == hipSuccess) e = t_fac.stop(s, ev);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        sc.drop_host();
+        sc.release();
+        if (Dhat_prev) (void)hipFreeAsync(Dhat_prev, s);
+        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: root factor"); }
+    }
+    // ---- statuses of every inversion
+    for (size_t q = 0; q < status_bufs.size(); ++q) {
+        const int cnt = (q + 1 == status_bufs.size()) ? 1 : 2 * h->lv[q].nb;
+        std::vector<int32_t> hs(cnt);
+        hipError_t e = hipMemcpy(hs.data(), status_bufs[q], cnt * sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: status"); }
+        for (int32_t v : hs)
+            if (v) { cleanup_status(); return fail(BM_ESINGULAR, "bm_hss_build: singular block in the HSS factorisation"); }
+    }
+    cleanup_status();
+    h->stats.levels = L;
+    h->stats.compressed_levels = compressed;
+    h->stats.root_size = static_cast<int32_t>(h->K);
+    h->stats.max_rank = max_rank;
+    h->stats.entries = entries;
+    h->stats.pairs = pairs;
+    h->stats.seconds_generate = t_gen.seconds();
+    h->stats.seconds_compress = t_cmp.seconds();
+    h->stats.seconds_factor = t_fac.seconds();
+    return BM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t stream, bm_hss** out) {
+    clear_error();
+    if (!out) return fail(BM_EINVAL, "bm_hss_build: out is null");
+    *out = nullptr;
+    if (!p || !opts) return fail(BM_EINVAL, "bm_hss_build: null argument");
+    if (opts->leaf < 4 || !(opts->proxy_ratio > 1.0) || opts->proxy_points < 8 ||
+        !(opts->id_tol > 0.0 && opts->id_tol < 1.0) || !std::isfinite(opts->proxy_ratio))
+        return fail(BM_EINVAL, "bm_hss_build: need leaf >= 4, proxy_ratio > 1, proxy_points >= 8, 0 < id_tol < 1");
+    if (p->g->n > (int64_t{1} << 30)) return fail(BM_EINVAL, "bm_hss_build: N too large");
+    const auto t0 = std::chrono::steady_clock::now();
+    bm_hss* h = new (std::nothrow) bm_hss;
+    if (!h) return fail(BM_ENOMEM, "bm_hss_build: host allocation");
+    h->p = p;
+    h->opts = *opts;
+    h->N = p->g->n;
+    int rc;
+    try {
+        rc = build_impl(h, stream);
+    } catch (const std::bad_alloc&) {
+        rc = fail(BM_ENOMEM, "bm_hss_build: host allocation");
+    }
+    if (rc != BM_OK) {
+        (void)hipStreamSynchronize(stream);
+        bm_hss_destroy(h);
+        return rc;
+    }
+    h->stats.seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return BM_OK;
+}
+
+int bm_hss_solve(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t s) {
+    clear_error();
+    if (!h || !b || !x) return fail(BM_EINVAL, "bm_hss_solve: null argument");
+    if (nrhs < 1 || nrhs > (int64_t{1} << 20)) return fail(BM_EINVAL, "bm_hss_solve: nrhs out of range");
+    const int nl = static_cast<int>(h->lv.size());
+    const int64_t N2 = 2 * h->N;
+    Scratch sc(s);
+    std::vector<double2*> bt(nl), xl(nl);
+    hipError_t e = hipSuccess;
+    for (int li = 0; li < nl && e == hipSuccess; ++li) {
+        e = sc.alloc(&bt[li], h->lv[li].nk * nrhs);
+        if (e == hipSuccess) e = sc.alloc(&xl[li], h->lv[li].nu * nrhs);
+    }
+    double2* xroot;
+    if (e == hipSuccess) e = sc.alloc(&xroot, h->K * nrhs);
+    if (e != hipSuccess) { sc.release(); return hip_fail(e, "bm_hss_solve: buffers"); }
+    const double2* bin = reinterpret_cast<const double2*>(b);
+    auto level_in = [&](int li, const double2** ptr, int64_t* ld) {
+        if (li == 0) { *ptr = bin; *ld = N2; }
+        else { *ptr = bt[li - 1]; *ld = h->lv[li - 1].nk; }
+    };
+    // upward: bt = F^T in
+    for (int li = 0; li < nl && e == hipSuccess; ++li) {
+        const LevelFactor& f = h->lv[li];
+        const double2* in;
+        int64_t ldin;
+        level_in(li, &in, &ldin);
+        std::vector<GemmJob> gj;
+        for (int q = 0; q < f.nb; ++q)
+            gj.push_back(gemm(f.Ft + f.nkoff[q], f.n[q], 1, in + f.uoff[q], 1, ldin, bt[li] + f.koff[q], 1, f.nk,
+                              f.k[q], nrhs, f.n[q]));
+        e = launch_gemm(sc, gj);
+    }
+    // root
+    {
+        const double2* in;
+        int64_t ldin;
+        if (nl == 0) { in = bin; ldin = N2; }
+        else { in = bt[nl - 1]; ldin = h->lv[nl - 1].nk; }
+        if (e == hipSuccess)
+            e = launch_gemm(sc, {gemm(h->Rinv, h->K, 1, in, 1, ldin, xroot, 1, h->K, h->K, nrhs, h->K)});
+    }
+    // downward: x = G in + E xt
+    for (int li = nl - 1; li >= 0 && e == hipSuccess; --li) {
+        const LevelFactor& f = h->lv[li];
+        const double2* in;
+        int64_t ldin;
+        level_in(li, &in, &ldin);
+        const double2* xt = (li == nl - 1) ? xroot : xl[li + 1];
+        const int64_t ldxt = (li == nl - 1) ? h->K : h->lv[li + 1].nu;
+        std::vector<GemmJob> g1, g2;
+        for (int q = 0; q < f.nb; ++q) {
+            g1.push_back(gemm(f.G + f.nnoff[q], f.n[q], 1, in + f.uoff[q], 1, ldin, xl[li] + f.uoff[q], 1, f.nu,
+                              f.n[q], nrhs, f.n[q]));
+            g2.push_back(gemm(f.E + f.nkoff[q], f.k[q], 1, xt + f.koff[q], 1, ldxt, xl[li] + f.uoff[q], 1, f.nu,
+                              f.n[q], nrhs, f.k[q], make_double2(1.0, 0.0), make_double2(1.0, 0.0)));
+        }
+        e = launch_gemm(sc, g1);
+        if (e == hipSuccess) e = launch_gemm(sc, g2);
+    }
+    if (e == hipSuccess) {
+        const double2* res = nl > 0 ? xl[0] : xroot;
+        e = hipMemcpyAsync(x, res, N2 * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    }
+    // the job descriptors are staged from host memory: finish before releasing them
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    sc.drop_host();
+    sc.release();
+    if (e != hipSuccess) return hip_fail(e, "bm_hss_solve");
+    return BM_OK;
+}
+
+int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out) {
+    clear_error();
+    if (!h || !out) return fail(BM_EINVAL, "bm_hss_stats: null argument");
+    *out = h->stats;
+    return BM_OK;
+}
+
+int bm_hss_destroy(bm_hss* h) {
+    if (!h) return BM_OK;
+    for (auto& f : h->lv) free_factor(f);
+    (void)hipFree(h->Rinv);
+    delete h;
+    return BM_OK;
+}
+
+}  // extern "C"

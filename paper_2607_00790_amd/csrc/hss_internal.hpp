@@ -1,0 +1,101 @@
+// Data structures shared by the HSS kernels and their host driver.
+#pragma once
+
+#include "internal.hpp"
+
+namespace bm {
+namespace hss {
+
+constexpr int kThreads = 256;
+
+// Point table of a level: the N boundary nodes followed by the proxy points of
+// every box (curve = -1 marks a proxy point).
+struct PointTable {
+    double* x;
+    double* y;
+    double* nx;
+    double* ny;
+    double* w;
+    double* kappa;
+    int32_t* curve;
+};
+
+// A point with up to two unknowns (u at pos0, q at pos1; -1 when absent).
+// Positions index the rows or columns of the block being generated.
+struct Slot {
+    int32_t pt;
+    int32_t pos0;
+    int32_t pos1;
+};
+
+// Generate A(targets, sources) for slot lists [tslot, tslot + nt) x
+// [sslot, sslot + ns); entry (row position r, column position c) goes to
+// out[off + r*rs + c*cs] (complex elements).
+struct GenJob {
+    int64_t tslot;
+    int64_t sslot;
+    int64_t out;
+    int64_t rs;
+    int64_t cs;
+    int32_t nt;
+    int32_t ns;
+};
+
+// Column-pivoted QR of an m x n column-major complex matrix x (columns are the
+// candidate unknowns of a box).
+struct CpqrJob {
+    double2* x;
+    int32_t* perm;
+    double2* rdiag;
+    int32_t n;
+    int32_t m;
+};
+
+struct InvJob {
+    double2* a;       // n x n row-major, inverted in place
+    int32_t* piv;     // n
+    int32_t* status;  // set to 1 on a zero pivot (caller zeroes it)
+    int32_t n;
+};
+
+// C = alpha A B + beta C, element (i, j) of X at X[i*rs + j*cs].
+struct GemmJob {
+    const double2* a;
+    const double2* b;
+    double2* c;
+    int64_t a_rs, a_cs, b_rs, b_cs, c_rs, c_cs;
+    double2 alpha, beta;
+    int32_t M, N, K;
+};
+
+struct CopyJob {
+    const double2* src;
+    double2* dst;
+    int64_t src_rs, src_cs, dst_rs, dst_cs;
+    int32_t rows, cols;
+};
+
+__global__ void k_box_geometry(NodeView v, const int64_t* lo, const int64_t* hi,
+                               double proxy_ratio, int P, int64_t nnodes, double* box_c,
+                               PointTable pt);
+__global__ void k_near_count(PointTable pt, const Slot* slots, const int32_t* slot_box,
+                             int64_t nslots, const double* box_c, int64_t* counts);
+__global__ void k_near_list(PointTable pt, const Slot* slots, const int32_t* slot_box,
+                            int64_t nslots, const double* box_c, const int64_t* slot_off,
+                            Slot* out);
+__global__ void k_gen_jobs(const GenJob* jobs, const int64_t* tile_off, int njobs,
+                           const Slot* slots, PointTable pt, Media m, double2* out);
+__global__ void k_cpqr(const CpqrJob* jobs, double tol, int32_t* rank_out);
+__global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
+                         double2* Tbuf);
+__global__ void k_gauss_jordan(const InvJob* jobs);
+__global__ void k_gj_pivot(double2* A, int n, int k, int32_t* piv, double2* colbuf,
+                           int32_t* status);
+__global__ void k_gj_eliminate(double2* A, int n, int k, const double2* colbuf,
+                               const int32_t* status);
+__global__ void k_gj_unscramble(double2* A, int n, const int32_t* piv, const int32_t* status);
+__global__ void k_gemm(const GemmJob* jobs, const int64_t* tile_off, int njobs);
+__global__ void k_copy_blocks(const CopyJob* jobs);
+
+}  // namespace hss
+}  // namespace bm

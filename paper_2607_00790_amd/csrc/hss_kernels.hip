@@ -1,0 +1,616 @@
+// Batched device kernels of the proxy-surface HSS build and solve.
+//
+//   k_box_geometry   centre and radius of every box of a level (contiguous node
+//                    ranges of the binary tree), and its proxy circle points
+//   k_near_count     per box: active unknowns of other boxes inside its proxy
+//   k_near_list      ... and their compacted slot lists
+//   k_gen_jobs       one launch generates every WSBM block a level needs
+//                    (near, proxy, diagonal and skeleton blocks of all boxes),
+//                    one node pair per thread, masked 2x2 writes
+//   k_cpqr           column-pivoted Householder QR of M_b^T, one workgroup per
+//                    box, with the relative rank rule |R_kk| > tol |R_11|
+//   k_interp         T_b = [I; (R11^-1 R12)^T] in pivoted order
+//   k_gauss_jordan   batched in-place inverse with row pivoting
+//   k_gemm           batched strided complex GEMM
+#include "hss_internal.hpp"
+
+namespace bm {
+namespace hss {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {   // a*b + c
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 cconj_mul(double2 a, double2 b) {   // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Block-wide argmax of (value, index); ties go to the lowest index.
+__device__ void block_argmax(double& v, int& idx, double* sv, int* si) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    if (lane == 0) { sv[wid] = v; si[wid] = idx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w)
+            if (sv[w] > sv[0] || (sv[w] == sv[0] && si[w] < si[0])) { sv[0] = sv[w]; si[0] = si[w]; }
+    }
+    __syncthreads();
+    v = sv[0];
+    idx = si[0];
+    __syncthreads();
+}
+
+__device__ double block_sum(double v, double* sv) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) sv[wid] = v;
+    __syncthreads();
+    double s = 0;
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) s += sv[w];
+    __syncthreads();
+    return s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Box geometry: one workgroup per box; box b of the level covers nodes
+// [lo[b], hi[b]).  Writes centre, radius and the P proxy points of the box into
+// the point table at index nnodes + b*P + p.
+__global__ void __launch_bounds__(kThreads)
+k_box_geometry(NodeView v, const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
+               double proxy_ratio, int P, int64_t nnodes, double* __restrict__ box_c,
+               PointTable pt) {
+    __shared__ double red[kThreads / 64];
+    const int b = blockIdx.x;
+    const int64_t a = lo[b], e = hi[b];
+    double sx = 0, sy = 0;
+    for (int64_t j = a + threadIdx.x; j < e; j += kThreads) { sx += v.x[j]; sy += v.y[j]; }
+    const double cnt = static_cast<double>(e - a);
+    const double cx = block_sum(sx, red) / cnt;
+    const double cy = block_sum(sy, red) / cnt;
+    double r2 = 0;
+    for (int64_t j = a + threadIdx.x; j < e; j += kThreads) {
+        const double dx = v.x[j] - cx, dy = v.y[j] - cy;
+        r2 = fmax(r2, dx * dx + dy * dy);
+    }
+    // max-reduction through the sum helper's storage
+    {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) r2 = fmax(r2, __shfl_xor(r2, off, 64));
+        if (lane == 0) red[wid] = r2;
+        __syncthreads();
+        for (int w = 0; w < kThreads / 64; ++w) r2 = fmax(r2, red[w]);
+        __syncthreads();
+    }
+    const double rp = proxy_ratio * sqrt(r2);
+    if (threadIdx.x == 0) {
+        box_c[3 * b] = cx;
+        box_c[3 * b + 1] = cy;
+        box_c[3 * b + 2] = rp;
+    }
+    for (int p = threadIdx.x; p < P; p += kThreads) {
+        double s, c;
+        sincospi(2.0 * p / P, &s, &c);
+        const int64_t q = nnodes + static_cast<int64_t>(b) * P + p;
+        pt.x[q] = cx + rp * c;
+        pt.y[q] = cy + rp * s;
+        pt.nx[q] = c;
+        pt.ny[q] = s;
+        pt.w[q] = 2.0 * kPi * rp / P;
+        pt.kappa[q] = 0.0;
+        pt.curve[q] = -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Near sets.  Candidates are the active slots of all boxes of the level
+// (slot_box[s] = owning box).  A slot is near box b if it belongs to another box
+// and its node lies strictly inside b's proxy circle.
+__device__ __forceinline__ bool is_near(const PointTable& pt, const Slot& s, int owner, int b,
+                                        const double* box_c) {
+    if (owner == b) return false;
+    const double dx = pt.x[s.pt] - box_c[3 * b], dy = pt.y[s.pt] - box_c[3 * b + 1];
+    const double r = box_c[3 * b + 2];
+    return dx * dx + dy * dy < r * r;
+}
+
+__device__ __forceinline__ int slot_unknowns(const Slot& s) {
+    return (s.pos0 >= 0 ? 1 : 0) + (s.pos1 >= 0 ? 1 : 0);
+}
+
+// counts[2b] = near slots of box b, counts[2b+1] = near unknowns of box b.
+__global__ void __launch_bounds__(kThreads)
+k_near_count(PointTable pt, const Slot* __restrict__ slots, const int32_t* __restrict__ slot_box,
+             int64_t nslots, const double* __restrict__ box_c, int64_t* __restrict__ counts) {
+    __shared__ double red[kThreads / 64];
+    const int b = blockIdx.x;
+    double ns = 0, nu = 0;
+    for (int64_t s = threadIdx.x; s < nslots; s += kThreads) {
+        const Slot sl = slots[s];
+        if (is_near(pt, sl, slot_box[s], b, box_c)) {
+            ns += 1;
+            nu += slot_unknowns(sl);
+        }
+    }
+    ns = block_sum(ns, red);
+    nu = block_sum(nu, red);
+    if (threadIdx.x == 0) {
+        counts[2 * b] = static_cast<int64_t>(ns);
+        counts[2 * b + 1] = static_cast<int64_t>(nu);
+    }
+}
+
+// Writes box b's near slots at out + slot_off[b], with unknown positions
+// renumbered 0..(near unknowns - 1) in candidate order.
+__global__ void __launch_bounds__(kThreads)
+k_near_list(PointTable pt, const Slot* __restrict__ slots, const int32_t* __restrict__ slot_box,
+            int64_t nslots, const double* __restrict__ box_c, const int64_t* __restrict__ slot_off,
+            Slot* __restrict__ out) {
+    __shared__ int scan_s[kThreads];
+    __shared__ int scan_u[kThreads];
+    __shared__ int base[2];
+    const int b = blockIdx.x;
+    if (threadIdx.x == 0) { base[0] = 0; base[1] = 0; }
+    __syncthreads();
+    for (int64_t s0 = 0; s0 < nslots; s0 += kThreads) {
+        const int64_t s = s0 + threadIdx.x;
+        Slot sl{0, -1, -1};
+        bool nearb = false;
+        if (s < nslots) {
+            sl = slots[s];
+            nearb = is_near(pt, sl, slot_box[s], b, box_c);
+        }
+        const int fs = nearb ? 1 : 0;
+        const int fu = nearb ? slot_unknowns(sl) : 0;
+        scan_s[threadIdx.x] = fs;
+        scan_u[threadIdx.x] = fu;
+        __syncthreads();
+        // inclusive Hillis-Steele scans
+        for (int off = 1; off < kThreads; off <<= 1) {
+            const int vs = threadIdx.x >= off ? scan_s[threadIdx.x - off] : 0;
+            const int vu = threadIdx.x >= off ? scan_u[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan_s[threadIdx.x] += vs;
+            scan_u[threadIdx.x] += vu;
+            __syncthreads();
+        }
+        if (nearb) {
+            const int is = base[0] + scan_s[threadIdx.x] - fs;
+            int pu = base[1] + scan_u[threadIdx.x] - fu;
+            Slot o{sl.pt, -1, -1};
+            if (sl.pos0 >= 0) o.pos0 = pu++;
+            if (sl.pos1 >= 0) o.pos1 = pu++;
+            out[slot_off[b] + is] = o;
+        }
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1) {
+            base[0] += scan_s[kThreads - 1];
+            base[1] += scan_u[kThreads - 1];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Entry generation for a batch of jobs.  Job j covers nt x ns slot pairs, tiles
+// of kThreads pairs; tile_off is the exclusive prefix sum of the tile counts.
+// One pair per thread, no loop (the Bessel coefficients stay scalar operands).
+__global__ void __launch_bounds__(kThreads)
+k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
+           const Slot* __restrict__ slots, PointTable pt, Media m, double2* __restrict__ out) {
+    int lo = 0, hi = njobs;
+    const int64_t tile = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= tile) lo = mid; else hi = mid;
+    }
+    const GenJob jb = jobs[lo];
+    const int64_t q = (tile - tile_off[lo]) * kThreads + threadIdx.x;
+    if (q >= static_cast<int64_t>(jb.nt) * jb.ns) return;
+    const int t = static_cast<int>(q / jb.ns);
+    const int s = static_cast<int>(q - static_cast<int64_t>(t) * jb.ns);
+    const Slot ts = slots[jb.tslot + t];
+    const Slot ss = slots[jb.sslot + s];
+    const int32_t i = ts.pt, j = ss.pt;
+    Block b;
+    if (i == j) {
+        b = diag_block(pt.w[j], pt.kappa[j], m);
+    } else {
+        const int32_t ci = pt.curve[i], cj = pt.curve[j];
+        b = pair_block(pt.x[i], pt.y[i], pt.nx[i], pt.ny[i], pt.x[j], pt.y[j], pt.nx[j], pt.ny[j],
+                       pt.w[j], m, ci == cj || ci < 0 || cj < 0);
+    }
+    double2* o = out + jb.out;
+    const int32_t r[2] = {ts.pos0, ts.pos1};
+    const int32_t c[2] = {ss.pos0, ss.pos1};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        if (r[a] < 0) continue;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (c[e] < 0) continue;
+            o[r[a] * jb.rs + c[e] * jb.cs] = make_double2(b.v[4 * a + 2 * e], b.v[4 * a + 2 * e + 1]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column-pivoted Householder QR of X_b = M_b^T for every box b.  X_b is stored
+// column-major (column j = row j of M_b, length m), n columns.  On exit:
+//   rank[b]; perm (n entries, pivot order); X holds R above the diagonal in its
+//   first rank rows (R[i][j] at X[j*m + i], i < j) and rdiag[i] = R_ii.
+// The relative rank rule keeps step k while |R_kk| > tol |R_00|.  Column norms
+// are recomputed exactly in every update pass (no downdating).
+__global__ void __launch_bounds__(kThreads)
+k_cpqr(const CpqrJob* __restrict__ jobs, double tol, int32_t* __restrict__ rank_out) {
+    extern __shared__ double dyn_lds[];
+    const CpqrJob jb = jobs[blockIdx.x];
+    const int n = jb.n, m = jb.m;
+    double2* X = jb.x;
+    int32_t* perm = jb.perm;
+    double2* rdiag = jb.rdiag;
+    double* nrm = dyn_lds;                    // n column norms^2
+    __shared__ double sv[kThreads / 64];
+    __shared__ int si[kThreads / 64];
+    __shared__ double2 sh_beta_alpha[2];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
+    for (int j = threadIdx.x; j < n; j += kThreads) perm[j] = j;
+    // initial norms: one wave per column
+    for (int j = wid; j < n; j += nw) {
+        double s = 0;
+        for (int r = lane; r < m; r += 64) s += cabs2(X[static_cast<int64_t>(j) * m + r]);
+        s = wave_sum(s);
+        if (lane == 0) nrm[j] = s;
+    }
+    __syncthreads();
+    const int kmax = n < m ? n : m;
+    double ref = 0;
+    int k = 0;
+    for (; k < kmax; ++k) {
+        double bv = -1;
+        int bi = n;
+        for (int j = k + threadIdx.x; j < n; j += kThreads)
+            if (nrm[j] > bv) { bv = nrm[j]; bi = j; }
+        block_argmax(bv, bi, sv, si);
+        const int p = bi;
+        if (k == 0) ref = sqrt(bv);
+        if (!(sqrt(bv) > tol * ref) || ref == 0) break;
+        // swap columns k and p
+        if (p != k) {
+            double2* ck = X + static_cast<int64_t>(k) * m;
+            double2* cp = X + static_cast<int64_t>(p) * m;
+            for (int r = threadIdx.x; r < m; r += kThreads) {
+                const double2 t = ck[r];
+                ck[r] = cp[r];
+                cp[r] = t;
+            }
+            if (threadIdx.x == 0) {
+                const int t = perm[k]; perm[k] = perm[p]; perm[p] = t;
+                const double tn = nrm[k]; nrm[k] = nrm[p]; nrm[p] = tn;
+            }
+        }
+        __syncthreads();
+        // Householder vector w = x - alpha e1 in place of column k (rows k..m-1)
+        double2* ck = X + static_cast<int64_t>(k) * m;
+        if (threadIdx.x == 0) {
+            const double xn = sqrt(nrm[k]);   // exact: recomputed in the previous pass
+            const double2 x0 = ck[k];
+            const double a0 = sqrt(cabs2(x0));
+            const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
+            const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
+            ck[k] = make_double2(x0.x - alpha.x, x0.y - alpha.y);
+            const double beta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
+            sh_beta_alpha[0] = make_double2(beta, 0.0);
+            sh_beta_alpha[1] = alpha;
+            rdiag[k] = alpha;
+        }
+        __syncthreads();
+        const double beta = sh_beta_alpha[0].x;
+        // apply H = I - beta w w^H to columns j > k; recompute their norms (rows > k)
+        for (int j = k + 1 + wid; j < n; j += nw) {
+            double2* cj = X + static_cast<int64_t>(j) * m;
+            double gr = 0, gi = 0;
+            for (int r = k + lane; r < m; r += 64) {
+                const double2 t = cconj_mul(ck[r], cj[r]);
+                gr += t.x;
+                gi += t.y;
+            }
+            gr = wave_sum(gr) * beta;
+            gi = wave_sum(gi) * beta;
+            double s = 0;
+            for (int r = k + lane; r < m; r += 64) {
+                const double2 w = ck[r];
+                double2 y = cj[r];
+                y.x -= gr * w.x - gi * w.y;
+                y.y -= gr * w.y + gi * w.x;
+                cj[r] = y;
+                if (r > k) s += cabs2(y);
+            }
+            s = wave_sum(s);
+            if (lane == 0) nrm[j] = s;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rank_out[blockIdx.x] = k;
+}
+
+// T_b (n x k, row-major) from the CPQR result: rows perm[0..k) are the
+// identity, row perm[k + c] holds column c of Z = R11^-1 R12, found by back
+// substitution by one thread per column (the thread's own row of T is its
+// workspace, so every value it reads back it wrote itself).  T must be zeroed
+// beforehand.
+__global__ void __launch_bounds__(kThreads)
+k_interp(const CpqrJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
+         const int64_t* __restrict__ t_off, double2* __restrict__ Tbuf) {
+    const CpqrJob jb = jobs[blockIdx.x];
+    const int n = jb.n, m = jb.m, k = ranks[blockIdx.x];
+    double2* T = Tbuf + t_off[blockIdx.x];
+    const double2* X = jb.x;
+    for (int i = threadIdx.x; i < k; i += kThreads)
+        T[static_cast<int64_t>(jb.perm[i]) * k + i] = make_double2(1.0, 0.0);
+    for (int c = threadIdx.x; c < n - k; c += kThreads) {
+        const double2* rc = X + static_cast<int64_t>(k + c) * m;   // column k+c of R (rows < k)
+        double2* z = T + static_cast<int64_t>(jb.perm[k + c]) * k;
+        for (int i = k - 1; i >= 0; --i) {
+            double2 num = rc[i];
+            for (int l = i + 1; l < k; ++l) {
+                const double2 t = cmul(X[static_cast<int64_t>(l) * m + i], z[l]);
+                num.x -= t.x;
+                num.y -= t.y;
+            }
+            const double2 d = jb.rdiag[i];
+            const double dd = cabs2(d);
+            z[i] = make_double2((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched in-place inverse by Gauss-Jordan elimination with row pivoting; one
+// workgroup per matrix (row-major, ld = n).  status[b] = 1 on a zero pivot.
+__global__ void __launch_bounds__(kThreads)
+k_gauss_jordan(const InvJob* __restrict__ jobs) {
+    extern __shared__ double dyn_lds[];
+    double2* col = reinterpret_cast<double2*>(dyn_lds);   // n entries: saved pivot column
+    __shared__ double sv[kThreads / 64];
+    __shared__ int si[kThreads / 64];
+    const InvJob jb = jobs[blockIdx.x];
+    const int n = jb.n;
+    double2* A = jb.a;
+    int32_t* piv = jb.piv;
+    int bad = 0;
+    for (int k = 0; k < n; ++k) {
+        double bv = -1;
+        int bi = n;
+        for (int i = k + threadIdx.x; i < n; i += kThreads) {
+            const double v = cabs2(A[static_cast<int64_t>(i) * n + k]);
+            if (v > bv) { bv = v; bi = i; }
+        }
+        block_argmax(bv, bi, sv, si);
+        if (!(bv > 0)) { bad = 1; break; }
+        const int p = bi;
+        if (threadIdx.x == 0) piv[k] = p;
+        if (p != k) {
+            for (int j = threadIdx.x; j < n; j += kThreads) {
+                const double2 t = A[static_cast<int64_t>(k) * n + j];
+                A[static_cast<int64_t>(k) * n + j] = A[static_cast<int64_t>(p) * n + j];
+                A[static_cast<int64_t>(p) * n + j] = t;
+            }
+        }
+        __syncthreads();
+        const double2 d = A[static_cast<int64_t>(k) * n + k];
+        const double dd = cabs2(d);
+        const double2 inv = make_double2(d.x / dd, -d.y / dd);
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+            col[i] = A[static_cast<int64_t>(i) * n + k];
+            A[static_cast<int64_t>(i) * n + k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += kThreads)
+            A[static_cast<int64_t>(k) * n + j] = cmul(A[static_cast<int64_t>(k) * n + j], inv);
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * n; e += kThreads) {
+            const int i = static_cast<int>(e / n);
+            if (i == k) continue;
+            const int j = static_cast<int>(e - static_cast<int64_t>(i) * n);
+            const double2 f = col[i];
+            const double2 rk = A[static_cast<int64_t>(k) * n + j];
+            double2 a = A[e];
+            a.x -= f.x * rk.x - f.y * rk.y;
+            a.y -= f.x * rk.y + f.y * rk.x;
+            A[e] = a;
+        }
+        __syncthreads();
+    }
+    if (!bad) {
+        for (int k = n - 1; k >= 0; --k) {
+            const int p = piv[k];
+            if (p != k) {
+                for (int i = threadIdx.x; i < n; i += kThreads) {
+                    const double2 t = A[static_cast<int64_t>(i) * n + k];
+                    A[static_cast<int64_t>(i) * n + k] = A[static_cast<int64_t>(i) * n + p];
+                    A[static_cast<int64_t>(i) * n + p] = t;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0 && bad) *jb.status = 1;
+}
+
+// Large single matrix: one Gauss-Jordan step k split over two launches.
+// Step A (one workgroup): pivot search, row swap, scaling of row k, saving
+// column k into colbuf.
+__global__ void __launch_bounds__(kThreads)
+k_gj_pivot(double2* __restrict__ A, int n, int k, int32_t* __restrict__ piv,
+           double2* __restrict__ colbuf, int32_t* __restrict__ status) {
+    __shared__ double sv[kThreads / 64];
+    __shared__ int si[kThreads / 64];
+    if (*status) return;
+    double bv = -1;
+    int bi = n;
+    for (int i = k + threadIdx.x; i < n; i += kThreads) {
+        const double v = cabs2(A[static_cast<int64_t>(i) * n + k]);
+        if (v > bv) { bv = v; bi = i; }
+    }
+    block_argmax(bv, bi, sv, si);
+    if (!(bv > 0)) {
+        if (threadIdx.x == 0) *status = 1;
+        return;
+    }
+    const int p = bi;
+    if (threadIdx.x == 0) piv[k] = p;
+    if (p != k) {
+        for (int j = threadIdx.x; j < n; j += kThreads) {
+            const double2 t = A[static_cast<int64_t>(k) * n + j];
+            A[static_cast<int64_t>(k) * n + j] = A[static_cast<int64_t>(p) * n + j];
+            A[static_cast<int64_t>(p) * n + j] = t;
+        }
+    }
+    __syncthreads();
+    const double2 d = A[static_cast<int64_t>(k) * n + k];
+    const double dd = cabs2(d);
+    const double2 inv = make_double2(d.x / dd, -d.y / dd);
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        colbuf[i] = A[static_cast<int64_t>(i) * n + k];
+        A[static_cast<int64_t>(i) * n + k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += kThreads)
+        A[static_cast<int64_t>(k) * n + j] = cmul(A[static_cast<int64_t>(k) * n + j], inv);
+}
+
+// Step B (grid over rows): eliminate column k from every row i != k.
+__global__ void __launch_bounds__(kThreads)
+k_gj_eliminate(double2* __restrict__ A, int n, int k, const double2* __restrict__ colbuf,
+               const int32_t* __restrict__ status) {
+    if (*status) return;
+    const int i = blockIdx.x;
+    if (i == k) return;
+    const double2 f = colbuf[i];
+    if (f.x == 0.0 && f.y == 0.0) return;
+    for (int j = threadIdx.x; j < n; j += kThreads) {
+        const double2 rk = A[static_cast<int64_t>(k) * n + j];
+        double2 a = A[static_cast<int64_t>(i) * n + j];
+        a.x -= f.x * rk.x - f.y * rk.y;
+        a.y -= f.x * rk.y + f.y * rk.x;
+        A[static_cast<int64_t>(i) * n + j] = a;
+    }
+}
+
+// Column unscrambling after the large Gauss-Jordan: one thread per row.
+__global__ void __launch_bounds__(kThreads)
+k_gj_unscramble(double2* __restrict__ A, int n, const int32_t* __restrict__ piv,
+                const int32_t* __restrict__ status) {
+    if (*status) return;
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    double2* row = A + static_cast<int64_t>(i) * n;
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = piv[k];
+        if (p != k) {
+            const double2 t = row[k];
+            row[k] = row[p];
+            row[p] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched strided complex GEMM: C = alpha A B + beta C with element (i, j) of X
+// at X[i*rs + j*cs].  32 x 32 output tile per workgroup, K in steps of 16.
+constexpr int TM = 32, TN = 32, TK = 16;
+
+__global__ void __launch_bounds__(kThreads)
+k_gemm(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
+    __shared__ double2 As[TM][TK + 1];
+    __shared__ double2 Bs[TK][TN + 1];
+    int lo = 0, hi = njobs;
+    const int64_t tile = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= tile) lo = mid; else hi = mid;
+    }
+    const GemmJob g = jobs[lo];
+    const int64_t local = tile - tile_off[lo];
+    const int tiles_n = (g.N + TN - 1) / TN;
+    const int i0 = static_cast<int>(local / tiles_n) * TM;
+    const int j0 = static_cast<int>(local % tiles_n) * TN;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;   // 16 x 16 threads, 2 x 2 outputs
+    double2 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+        for (int e = threadIdx.x; e < TM * TK; e += kThreads) {
+            const int r = e / TK, c = e % TK;
+            const int gi = i0 + r, gk = k0 + c;
+            As[r][c] = (gi < g.M && gk < g.K) ? g.a[gi * g.a_rs + gk * g.a_cs] : make_double2(0.0, 0.0);
+        }
+        for (int e = threadIdx.x; e < TK * TN; e += kThreads) {
+            const int r = e / TN, c = e % TN;
+            const int gk = k0 + r, gj = j0 + c;
+            Bs[r][c] = (gk < g.K && gj < g.N) ? g.b[gk * g.b_rs + gj * g.b_cs] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < TK; ++kk) {
+            const double2 a0 = As[ty][kk], a1 = As[ty + 16][kk];
+            const double2 b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
+            acc[0][0] = cfma(a0, b0, acc[0][0]);
+            acc[0][1] = cfma(a0, b1, acc[0][1]);
+            acc[1][0] = cfma(a1, b0, acc[1][0]);
+            acc[1][1] = cfma(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int gi = i0 + ty + 16 * a;
+        if (gi >= g.M) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int gj = j0 + tx + 16 * b;
+            if (gj >= g.N) continue;
+            double2* cp = g.c + gi * g.c_rs + gj * g.c_cs;
+            double2 r = cmul(g.alpha, acc[a][b]);
+            if (g.beta.x != 0.0 || g.beta.y != 0.0) r = cfma(g.beta, *cp, r);
+            *cp = r;
+        }
+    }
+}
+
+// Strided complex block copy: dst(i, j) = src(i, j) for i < rows, j < cols.
+__global__ void __launch_bounds__(kThreads)
+k_copy_blocks(const CopyJob* __restrict__ jobs) {
+    const CopyJob c = jobs[blockIdx.y];
+    const int64_t total = static_cast<int64_t>(c.rows) * c.cols;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const int i = static_cast<int>(e / c.cols), j = static_cast<int>(e % c.cols);
+        c.dst[i * c.dst_rs + j * c.dst_cs] = c.src[i * c.src_rs + j * c.src_cs];
+    }
+}
+
+}  // namespace hss
+}  // namespace bm

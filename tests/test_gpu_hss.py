@@ -1,0 +1,132 @@
+"""GPU tests of the proxy-surface HSS direct solver (build + solve through the
+C-ABI) against the oracle's dense solution.
+
+The HSS solution approximates the dense one to the ID tolerance times a modest
+growth factor; with id_tol = 1e-10 the bar here is 1e-7 relative (2-norm).
+On the circle the solution must also keep the dense solver's accuracy against
+the Mie series (within 2x of the oracle's error)."""
+import sys
+
+import numpy as np
+import pytest
+
+import scatterers as sc
+from oracle import geometry, mie, wsbm
+
+pytestmark = pytest.mark.gpu
+
+HSS_BAR = 1e-7
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def setup(bm, curves, sizes, media):
+    xyd, s = sc.sample_curves(curves, sizes)
+    g = bm.bm_geom_create(s, xyd)
+    p = bm.bm_problem_create(g, media.k0, media.k1, media.eps0, media.eps1)
+    return p, geometry.discretize(xyd, s)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_hss_circle_plain_workload(gpu_lib):
+    import torch
+    bm = gpu_lib
+    note("hss: circle N=512, k0=10, n=1.5, leaf 64")
+    wl = sc.circle_workload(512)
+    p, nd = setup(bm, wl.curves, wl.sizes, wl.media)
+    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
+    st = bm.bm_hss_stats(h)
+    note(f"  stats {st}")
+    assert st["compressed_levels"] >= 1
+    b = bm.bm_rhs_plane_wave(p, 0.0)
+    x = bm.bm_hss_solve(h, b).cpu().numpy()
+    ref = wsbm.solve_dense(wsbm.assemble_dense(nd, wl.media), wsbm.rhs_plane_wave(nd, wl.media, 0.0))
+    assert rel(x, ref) < HSS_BAR
+    t = 2 * np.pi * np.arange(512) / 512
+    u, _ = mie.boundary_values(wl.media, t)
+    e_hss = np.linalg.norm(x[0::2].real - u.real) / np.linalg.norm(u.real)
+    e_ora = np.linalg.norm(ref[0::2].real - u.real) / np.linalg.norm(u.real)
+    assert e_hss <= 2 * e_ora
+
+
+def test_hss_star_multiple_rhs_in_place(gpu_lib):
+    import torch
+    bm = gpu_lib
+    note("hss: star N=2048, k0=50, n=1.5, 3 right-hand sides, x aliases b")
+    media = sc.media_from_index(50.0, 1.5)
+    p, nd = setup(bm, [sc.star(0.3, 5)], [2048], media)
+    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
+    note(f"  stats {bm.bm_hss_stats(h)}")
+    angles = [0.0, 1.1, 4.0]
+    B = torch.stack([bm.bm_rhs_plane_wave(p, a) for a in angles]).contiguous()
+    Bh = B.cpu().numpy()
+    bm.bm_hss_solve(h, B, out=B)
+    X = B.cpu().numpy()
+    A = wsbm.assemble_dense(nd, media)
+    for r, a in enumerate(angles):
+        ref = wsbm.solve_dense(A, wsbm.rhs_plane_wave(nd, media, a))
+        assert np.abs(Bh[r] - wsbm.rhs_plane_wave(nd, media, a)).max() < 1e-12
+        assert rel(X[r], ref) < HSS_BAR, (r, rel(X[r], ref))
+
+
+def test_hss_two_scatterers_ragged_sizes(gpu_lib):
+    bm = gpu_lib
+    note("hss: two stars N=601+423, k0=20, n=2")
+    media = sc.media_from_index(20.0, 2.0)
+    p, nd = setup(bm, [sc.star(0.2, 4), sc.star(0.25, 3, 1.0, (3.0, 0.5))], [601, 423], media)
+    h = bm.bm_hss_build(p, leaf=40, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
+    note(f"  stats {bm.bm_hss_stats(h)}")
+    b = bm.bm_rhs_plane_wave(p, 0.3)
+    x = bm.bm_hss_solve(h, b).cpu().numpy()
+    ref = wsbm.solve_dense(wsbm.assemble_dense(nd, media), wsbm.rhs_plane_wave(nd, media, 0.3))
+    assert rel(x, ref) < HSS_BAR
+
+
+def test_hss_tiny_problem_is_a_dense_solve(gpu_lib):
+    """N below two leaves: no level is compressed, the root is the whole system."""
+    bm = gpu_lib
+    note("hss: tiny N=40 (root only)")
+    media = sc.media_from_index(10.0, 1.5)
+    p, nd = setup(bm, [sc.star(0.3, 5)], [40], media)
+    h = bm.bm_hss_build(p, leaf=32)
+    st = bm.bm_hss_stats(h)
+    assert st["compressed_levels"] == 0 and st["root_size"] == 80
+    x = bm.bm_hss_solve(h, bm.bm_rhs_plane_wave(p, 0.0)).cpu().numpy()
+    ref = wsbm.solve_dense(wsbm.assemble_dense(nd, media), wsbm.rhs_plane_wave(nd, media, 0.0))
+    assert rel(x, ref) < 1e-12
+
+
+def test_hss_full_size_star_sampled_residual(gpu_lib):
+    """Full star workload (N = 16384, k0 = 50, n = 1.5, leaf 64, 64 proxy points,
+    tol 1e-10), the configuration the benchmark times: the residual of the HSS
+    solution on sampled rows of the oracle's matrix."""
+    bm = gpu_lib
+    note("hss: star N=16384 (benchmark workload), sampled residual")
+    wl = sc.star_workload()
+    p, nd = setup(bm, wl.curves, wl.sizes, wl.media)
+    h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points,
+                        id_tol=wl.id_tol)
+    note(f"  stats {bm.bm_hss_stats(h)}")
+    b = bm.bm_rhs_plane_wave(p, wl.theta_inc)
+    x = bm.bm_hss_solve(h, b).cpu().numpy()
+    rows = np.arange(0, wl.n, 257)
+    Ar = wsbm.assemble_rows(nd, wl.media, rows)
+    br = wsbm.rhs_plane_wave(nd, wl.media, wl.theta_inc).reshape(-1, 2)[rows].reshape(-1)
+    res = np.linalg.norm(Ar @ x - br) / np.linalg.norm(br)
+    note(f"  sampled relative residual {res:.3e}")
+    assert res < 1e-6
+
+
+def test_hss_rejects_bad_options(gpu_lib):
+    bm = gpu_lib
+    media = sc.media_from_index(10.0, 1.5)
+    p, _ = setup(bm, [sc.circle()], [64], media)
+    for kw in ({"leaf": 2}, {"proxy_ratio": 1.0}, {"proxy_points": 4}, {"id_tol": 0.0}):
+        with pytest.raises(bm.BmError):
+            bm.bm_hss_build(p, **kw)
