@@ -9,7 +9,7 @@
 //   3. M_b = [A(U_b, near) | A(near, U_b)^T | A(U_b, proxy) | A(proxy, U_b)^T]
 //      for every box in ONE generation launch            (k_gen_jobs)
 //   4. ID of the rows of M_b: CPQR of M_b^T, skeleton J_b, interpolation T_b
-//                                                        (k_cpqr, k_interp)
+//                                                        (k_cpqr_*, k_interp)
 //   5. D_b: leaf A(U_b, U_b); above, [[Dhat_a, A(J_a,J_b)], [A(J_b,J_a), Dhat_b]]
 //   6. Martinsson-Rokhlin factors Dhat, E, F^T, G        (k_gauss_jordan, k_gemm)
 // The reduced system above the last compressed level is inverted densely.
@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <functional>
 #include <cmath>
 #include <memory>
 #include <new>
@@ -43,12 +44,33 @@ struct LevelFactor {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Device temporaries and host staging that live until the next sync point.
+// Device temporaries, staged descriptor uploads and recorded stream commands
+// of one phase of the build or solve.  upload() copies a host array into a
+// staging chunk whose device address is known at once; stream work is recorded
+// with rec(); flush() issues one host-to-device copy per chunk and then replays
+// the recorded commands in order, so a phase costs a handful of copies however
+// many small descriptor arrays it uses.  Everything is released after the
+// stream has been synchronised.
 struct Scratch {
     hipStream_t s;
     std::vector<void*> dev;
-    std::vector<std::shared_ptr<std::vector<char>>> host;
+    struct Chunk {
+        char* d;
+        std::shared_ptr<std::vector<char>> h;
+        size_t used, flushed;
+    };
+    std::vector<Chunk> chunks;
+    std::vector<std::function<hipError_t()>> cmds;
+    bool pending = false;   // copies issued from host staging not yet known complete
+    static constexpr size_t kChunk = size_t{1} << 20;
+
     explicit Scratch(hipStream_t st) : s(st) {}
+    Scratch(const Scratch&) = delete;
+    Scratch& operator=(const Scratch&) = delete;
+    ~Scratch() {
+        if (pending) (void)hipStreamSynchronize(s);
+        release();
+    }
     template <class T>
     hipError_t alloc(T** p, size_t count) {
         *p = nullptr;
@@ -58,18 +80,52 @@ struct Scratch {
     }
     template <class T>
     hipError_t upload(T** p, const std::vector<T>& v) {
-        hipError_t e = alloc(p, v.size());
-        if (e != hipSuccess || v.empty()) return e;
-        auto h = std::make_shared<std::vector<char>>(v.size() * sizeof(T));
-        std::memcpy(h->data(), v.data(), h->size());
-        host.push_back(h);
-        return hipMemcpyAsync(*p, h->data(), h->size(), hipMemcpyHostToDevice, s);
+        const size_t bytes = std::max<size_t>((v.size() * sizeof(T) + 15) / 16 * 16, 16);
+        Chunk* c = nullptr;
+        for (Chunk& q : chunks)
+            if (q.h->size() - q.used >= bytes) { c = &q; break; }
+        if (!c) {
+            const size_t cap = std::max(kChunk, bytes);
+            char* d = nullptr;
+            hipError_t e = alloc(&d, cap);
+            if (e != hipSuccess) return e;
+            chunks.push_back(Chunk{d, std::make_shared<std::vector<char>>(cap), 0, 0});
+            c = &chunks.back();
+        }
+        if (!v.empty()) std::memcpy(c->h->data() + c->used, v.data(), v.size() * sizeof(T));
+        *p = reinterpret_cast<T*>(c->d + c->used);
+        c->used += bytes;
+        return hipSuccess;
     }
+    void rec(std::function<hipError_t()> f) { cmds.push_back(std::move(f)); }
+    hipError_t flush() {
+        for (Chunk& c : chunks) {
+            if (c.used > c.flushed) {
+                hipError_t e = hipMemcpyAsync(c.d + c.flushed, c.h->data() + c.flushed, c.used - c.flushed,
+                                              hipMemcpyHostToDevice, s);
+                if (e != hipSuccess) return e;
+                c.flushed = c.used;
+                pending = true;
+            }
+        }
+        for (auto& f : cmds) {
+            hipError_t e = f();
+            if (e != hipSuccess) {
+                cmds.clear();
+                return e;
+            }
+        }
+        cmds.clear();
+        return hipSuccess;
+    }
+    // After a stream synchronisation: staging may be reused.
+    void synced() { pending = false; }
     void release() {
+        cmds.clear();
         for (void* p : dev) (void)hipFreeAsync(p, s);
         dev.clear();
+        chunks.clear();
     }
-    void drop_host() { host.clear(); }
 };
 
 hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
@@ -84,9 +140,16 @@ hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* 
     hipError_t e = sc.upload(&dj, jobs);
     if (e == hipSuccess) e = sc.upload(&dt, toff);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gen_jobs, dim3(static_cast<unsigned>(toff.back())), dim3(kThreads), 0, sc.s,
-                       dj, dt, static_cast<int>(jobs.size()), slots, pt, m, out);
-    return hipGetLastError();
+    const unsigned grid = static_cast<unsigned>(toff.back());
+    const int nj = static_cast<int>(jobs.size());
+    const PointTable ptc = pt;
+    const Media mc = m;
+    hipStream_t st = sc.s;
+    sc.rec([=]() {
+        hipLaunchKernelGGL(k_gen_jobs, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, mc, out);
+        return hipGetLastError();
+    });
+    return hipSuccess;
 }
 
 hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
@@ -100,9 +163,14 @@ hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
     hipError_t e = sc.upload(&dj, jobs);
     if (e == hipSuccess) e = sc.upload(&dt, toff);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gemm, dim3(static_cast<unsigned>(toff.back())), dim3(kThreads), 0, sc.s, dj,
-                       dt, static_cast<int>(jobs.size()));
-    return hipGetLastError();
+    const unsigned grid = static_cast<unsigned>(toff.back());
+    const int nj = static_cast<int>(jobs.size());
+    hipStream_t st = sc.s;
+    sc.rec([=]() {
+        hipLaunchKernelGGL(k_gemm, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj);
+        return hipGetLastError();
+    });
+    return hipSuccess;
 }
 
 hipError_t launch_copy(Scratch& sc, const std::vector<CopyJob>& jobs) {
@@ -110,46 +178,13 @@ hipError_t launch_copy(Scratch& sc, const std::vector<CopyJob>& jobs) {
     CopyJob* dj;
     hipError_t e = sc.upload(&dj, jobs);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_copy_blocks, dim3(64, static_cast<unsigned>(jobs.size())), dim3(kThreads), 0,
-                       sc.s, dj);
-    return hipGetLastError();
-}
-
-constexpr int kBatchedInverseMax = 320;   // larger matrices use the multi-workgroup path
-
-// Invert the given matrices in place; a zero pivot sets the job's status flag.
-// Jobs with n <= kBatchedInverseMax run one workgroup each in one launch;
-// larger ones use two launches per elimination step over the whole device.
-hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
-    std::vector<InvJob> small;
-    int nmax = 0;
-    hipError_t e = hipSuccess;
-    for (const InvJob& j : jobs) {
-        if (j.n == 0) continue;
-        if (j.n <= kBatchedInverseMax) {
-            small.push_back(j);
-            nmax = std::max(nmax, j.n);
-            continue;
-        }
-        double2* col;
-        if ((e = sc.alloc(&col, j.n)) != hipSuccess) return e;
-        for (int k = 0; k < j.n; ++k) {
-            hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kThreads), 0, sc.s, j.a, j.n, k, j.piv, col, j.status);
-            hipLaunchKernelGGL(k_gj_eliminate, dim3(static_cast<unsigned>(j.n)), dim3(kThreads), 0, sc.s, j.a,
-                               j.n, k, col, j.status);
-        }
-        hipLaunchKernelGGL(k_gj_unscramble, dim3(static_cast<unsigned>(ceil_div(j.n, kThreads))), dim3(kThreads),
-                           0, sc.s, j.a, j.n, j.piv, j.status);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (!small.empty()) {
-        InvJob* dj;
-        if ((e = sc.upload(&dj, small)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gauss_jordan, dim3(static_cast<unsigned>(small.size())), dim3(kThreads),
-                           static_cast<size_t>(nmax) * sizeof(double2), sc.s, dj);
-        e = hipGetLastError();
-    }
-    return e;
+    const unsigned nj = static_cast<unsigned>(jobs.size());
+    hipStream_t st = sc.s;
+    sc.rec([=]() {
+        hipLaunchKernelGGL(k_copy_blocks, dim3(64, nj), dim3(kThreads), 0, st, dj);
+        return hipGetLastError();
+    });
+    return hipSuccess;
 }
 
 GemmJob gemm(const double2* a, int64_t a_rs, int64_t a_cs, const double2* b, int64_t b_rs,
@@ -161,6 +196,155 @@ GemmJob gemm(const double2* a, int64_t a_rs, int64_t a_cs, const double2* b, int
     g.alpha = alpha; g.beta = beta;
     g.M = static_cast<int32_t>(M); g.N = static_cast<int32_t>(N); g.K = static_cast<int32_t>(K);
     return g;
+}
+
+// Inversion of a batch of matrices.  Blocks with n <= kGjBase are inverted by
+// pivoted Gauss-Jordan, one workgroup each, in a single launch.  Larger
+// matrices are split 2 x 2, [[A, B], [C, D]], and inverted through the Schur
+// complement S = D - C A^-1 B:
+//   X = A^-1 B,  Yt = C A^-1,  B <- -X S^-1,  C <- -S^-1 Yt,  A <- A^-1 - X C,
+// with A^-1 and S^-1 found recursively (batched over the whole batch at each
+// recursion stage).  Pivoting is within the Gauss-Jordan blocks only.
+// Largest block inverted by the LDS-resident Gauss-Jordan kernel on this
+// device (from its per-workgroup LDS limit); 0 falls back to the global-memory
+// kernel with blocks of kGjBaseGlobal.
+constexpr int kGjBaseGlobal = 128;
+
+int gj_lds_base() {
+    static int cached = -1;
+    if (cached >= 0) return cached;
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds = 0;
+    const size_t budget = lds > 2048 ? static_cast<size_t>(lds) - 1024 : 0;   // static LDS of the kernel
+    int n = 0;
+    while (n < 160 && gj_lds_bytes(n + 1) <= budget) ++n;
+    if (n >= 16 && budget > 65536) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_gauss_jordan_lds),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(gj_lds_bytes(n))) != hipSuccess)
+            n = 0;
+    }
+    cached = n >= 16 ? n : 0;
+    (void)hipGetLastError();
+    return cached;
+}
+
+hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
+    const int lds_base = gj_lds_base();
+    const int base_n = lds_base > 0 ? lds_base : kGjBaseGlobal;
+    std::vector<InvJob> base, split;
+    int nbase = 0;
+    for (const InvJob& j : jobs) {
+        if (j.n == 0) continue;
+        if (j.n <= base_n) {
+            base.push_back(j);
+            nbase = std::max(nbase, j.n);
+        } else {
+            split.push_back(j);
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!base.empty()) {
+        InvJob* dj;
+        if ((e = sc.upload(&dj, base)) != hipSuccess) return e;
+        const unsigned nj = static_cast<unsigned>(base.size());
+        hipStream_t st = sc.s;
+        const size_t lds = lds_base > 0 ? gj_lds_bytes(nbase) : static_cast<size_t>(nbase) * sizeof(double2);
+        sc.rec([=]() {
+            if (lds_base > 0)
+                hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(nj), dim3(kThreads), lds, st, dj);
+            else
+                hipLaunchKernelGGL(k_gauss_jordan, dim3(nj), dim3(kThreads), lds, st, dj);
+            return hipGetLastError();
+        });
+    }
+    if (split.empty()) return e;
+    const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0), zero = make_double2(0.0, 0.0);
+    std::vector<InvJob> Aj, Sj;
+    std::vector<int64_t> xoff(split.size() + 1, 0);
+    for (size_t q = 0; q < split.size(); ++q) {
+        const InvJob& j = split[q];
+        const int n1 = j.n / 2, n2 = j.n - n1;
+        Aj.push_back(InvJob{j.a, j.piv, j.status, j.ld, n1});
+        Sj.push_back(InvJob{j.a + n1 * j.ld + n1, j.piv + n1, j.status, j.ld, n2});
+        xoff[q + 1] = xoff[q] + static_cast<int64_t>(n1) * n2;
+    }
+    if ((e = launch_inverse(sc, Aj)) != hipSuccess) return e;
+    double2 *X, *Yt;
+    if ((e = sc.alloc(&X, xoff.back())) != hipSuccess) return e;
+    if ((e = sc.alloc(&Yt, xoff.back())) != hipSuccess) return e;
+    std::vector<GemmJob> g1, g2, g3, g4;
+    for (size_t q = 0; q < split.size(); ++q) {
+        const InvJob& j = split[q];
+        const int64_t n1 = j.n / 2, n2 = j.n - n1, ld = j.ld;
+        double2 *A = j.a, *B = j.a + n1, *C = j.a + n1 * ld, *D = j.a + n1 * ld + n1;
+        double2 *x = X + xoff[q], *yt = Yt + xoff[q];
+        g1.push_back(gemm(A, ld, 1, B, ld, 1, x, n2, 1, n1, n2, n1));            // X = A^-1 B
+        g1.push_back(gemm(C, ld, 1, A, ld, 1, yt, n1, 1, n2, n1, n1));           // Yt = C A^-1
+        g2.push_back(gemm(C, ld, 1, x, n2, 1, D, ld, 1, n2, n2, n1, mone, one)); // S = D - C X
+        g3.push_back(gemm(x, n2, 1, D, ld, 1, B, ld, 1, n1, n2, n2, mone, zero)); // B = -X S^-1
+        g3.push_back(gemm(D, ld, 1, yt, n1, 1, C, ld, 1, n2, n1, n2, mone, zero)); // C = -S^-1 Yt
+        g4.push_back(gemm(x, n2, 1, C, ld, 1, A, ld, 1, n1, n1, n2, mone, one));  // A = A^-1 - X C
+    }
+    if ((e = launch_gemm(sc, g1)) != hipSuccess) return e;
+    if ((e = launch_gemm(sc, g2)) != hipSuccess) return e;
+    if ((e = launch_inverse(sc, Sj)) != hipSuccess) return e;
+    if ((e = launch_gemm(sc, g3)) != hipSuccess) return e;
+    return launch_gemm(sc, g4);
+}
+
+// Column-pivoted QR of every box of a level, step-wise over many workgroups
+// per box; ranks[] is copied back (the caller synchronises).
+hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, int32_t* dranks,
+                    double tol, std::vector<int32_t>& ranks) {
+    const int nb = static_cast<int>(cj.size());
+    int nmax = 0, kmax = 0;
+    for (const CpqrJob& j : cj) {
+        nmax = std::max(nmax, j.n);
+        kmax = std::max(kmax, std::min(j.n, j.m));
+    }
+    hipError_t e = hipSuccess;
+    double* nrm;
+    int32_t* used;
+    CpqrState* st;
+    int64_t tot = 0;
+    for (const CpqrJob& j : cj) tot += j.n;
+    if ((e = sc.alloc(&nrm, 2 * tot)) != hipSuccess) return e;
+    if ((e = sc.alloc(&used, tot)) != hipSuccess) return e;
+    if ((e = sc.alloc(&st, nb)) != hipSuccess) return e;
+    int64_t off = 0;
+    for (int b = 0; b < nb; ++b) {
+        cj[b].nrm = nrm + 2 * off;
+        cj[b].used = used + off;
+        cj[b].st = st + b;
+        off += cj[b].n;
+    }
+    if ((e = sc.upload(dcj_out, cj)) != hipSuccess) return e;
+    CpqrJob* dcj = *dcj_out;
+    int32_t* active;
+    if ((e = sc.alloc(&active, 1)) != hipSuccess) return e;
+    if ((e = sc.flush()) != hipSuccess) return e;
+    const unsigned chunks = static_cast<unsigned>(ceil_div(std::max(nmax, 1), kThreads / 64));
+    hipLaunchKernelGGL(k_cpqr_init, dim3(chunks, nb), dim3(kThreads), 0, sc.s, dcj);
+    for (int k = 0; k <= kmax; ++k) {
+        hipLaunchKernelGGL(k_cpqr_step, dim3(chunks, nb), dim3(kThreads), 0, sc.s, dcj, k, tol);
+        if (k % 32 == 31 && k < kmax) {
+            int32_t h_active = 1;
+            hipLaunchKernelGGL(k_cpqr_ranks, dim3(1), dim3(64), 0, sc.s, dcj, nb, dranks, active);
+            e = hipMemcpyAsync(&h_active, active, sizeof(int32_t), hipMemcpyDeviceToHost, sc.s);
+            if (e == hipSuccess) e = hipStreamSynchronize(sc.s);
+            if (e != hipSuccess) return e;
+            sc.synced();
+            if (h_active == 0) break;
+        }
+    }
+    hipLaunchKernelGGL(k_cpqr_finish, dim3(nb), dim3(kThreads), 0, sc.s, dcj);
+    hipLaunchKernelGGL(k_cpqr_ranks, dim3(1), dim3(64), 0, sc.s, dcj, nb, dranks, active);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = hipMemcpyAsync(ranks.data(), dranks, nb * sizeof(int32_t), hipMemcpyDeviceToHost, sc.s);
+    return e;
 }
 
 // Slots of an unknown list (global unknown ids): one slot per node in order of
@@ -219,16 +403,23 @@ void free_factor(LevelFactor& f) {
 
 struct EventTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-    hipError_t start(hipStream_t s, hipEvent_t& a) {
+    hipError_t start(Scratch& sc, hipEvent_t& a) {
         hipError_t e = hipEventCreate(&a);
-        if (e == hipSuccess) e = hipEventRecord(a, s);
+        if (e == hipSuccess) {
+            hipStream_t st = sc.s;
+            hipEvent_t ea = a;
+            sc.rec([=]() { return hipEventRecord(ea, st); });
+        }
         return e;
     }
-    hipError_t stop(hipStream_t s, hipEvent_t a) {
+    hipError_t stop(Scratch& sc, hipEvent_t a) {
         hipEvent_t b;
         hipError_t e = hipEventCreate(&b);
-        if (e == hipSuccess) e = hipEventRecord(b, s);
-        ev.emplace_back(a, b);
+        if (e == hipSuccess) {
+            hipStream_t st = sc.s;
+            sc.rec([=]() { return hipEventRecord(b, st); });
+            ev.emplace_back(a, b);
+        }
         return e;
     }
     double seconds() {
@@ -307,8 +498,14 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = sc.upload(&dhi, hi);
         if (e == hipSuccess) e = sc.alloc(&box_c, 3 * nb);
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: level setup"); }
-        hipLaunchKernelGGL(k_box_geometry, dim3(nb), dim3(kThreads), 0, s, nv, dlo, dhi,
-                           h->opts.proxy_ratio, P, N, box_c, pt);
+        {
+            const double ratio = h->opts.proxy_ratio;
+            sc.rec([=]() {
+                hipLaunchKernelGGL(k_box_geometry, dim3(nb), dim3(kThreads), 0, s, nv, dlo, dhi, ratio, P, N,
+                                   box_c, pt);
+                return hipGetLastError();
+            });
+        }
         // ---- active slots
         std::vector<Slot> act;
         std::vector<int64_t> soff(nb + 1, 0), n(nb);
@@ -327,12 +524,15 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = sc.upload(&dsbox, sbox);
         if (e == hipSuccess) e = sc.alloc(&dcounts, 2 * nb);
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slots"); }
-        hipLaunchKernelGGL(k_near_count, dim3(nb), dim3(kThreads), 0, s, pt, dact, dsbox, nact, box_c, dcounts);
+        sc.rec([=]() {
+            hipLaunchKernelGGL(k_near_count, dim3(nb), dim3(kThreads), 0, s, pt, dact, dsbox, nact, box_c, dcounts);
+            return hipGetLastError();
+        });
         std::vector<int64_t> counts(2 * nb);
-        e = hipGetLastError();
+        e = sc.flush();
         if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), dcounts, counts.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        sc.drop_host();
+        sc.synced();
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: near counts"); }
         int64_t total_u = 0;
         for (int b = 0; b < nb; ++b) total_u += n[b];
@@ -351,19 +551,25 @@ int build_impl(bm_hss* h, hipStream_t s) {
         const int64_t nslots_all = prox_base + static_cast<int64_t>(nb) * P;
         Slot* dslots;
         if ((e = sc.alloc(&dslots, nslots_all)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slot buffer"); }
-        e = hipMemcpyAsync(dslots, dact, nact * sizeof(Slot), hipMemcpyDeviceToDevice, s);
+        sc.rec([=]() { return hipMemcpyAsync(dslots, dact, nact * sizeof(Slot), hipMemcpyDeviceToDevice, s); });
         std::vector<Slot> prox(static_cast<size_t>(nb) * P);
         for (int b = 0; b < nb; ++b)
             for (int q = 0; q < P; ++q)
                 prox[static_cast<size_t>(b) * P + q] = Slot{static_cast<int32_t>(N + static_cast<int64_t>(b) * P + q), 2 * q, 2 * q + 1};
         Slot* dprox;
         if (e == hipSuccess) e = sc.upload(&dprox, prox);
-        if (e == hipSuccess) e = hipMemcpyAsync(dslots + prox_base, dprox, prox.size() * sizeof(Slot), hipMemcpyDeviceToDevice, s);
+        {
+            const size_t pbytes = prox.size() * sizeof(Slot);
+            sc.rec([=]() { return hipMemcpyAsync(dslots + prox_base, dprox, pbytes, hipMemcpyDeviceToDevice, s); });
+        }
         int64_t* dnsoff;
         if (e == hipSuccess) e = sc.upload(&dnsoff, std::vector<int64_t>(nsoff.begin(), nsoff.end() - 1));
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slot upload"); }
-        hipLaunchKernelGGL(k_near_list, dim3(nb), dim3(kThreads), 0, s, pt, dact, dsbox, nact, box_c, dnsoff,
-                           dslots + near_base);
+        sc.rec([=]() {
+            hipLaunchKernelGGL(k_near_list, dim3(nb), dim3(kThreads), 0, s, pt, dact, dsbox, nact, box_c, dnsoff,
+                               dslots + near_base);
+            return hipGetLastError();
+        });
 
         // ---- M_b for all boxes in one generation launch
         std::vector<int64_t> m(nb), mo(nb + 1, 0);
@@ -386,8 +592,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
             pairs += 2 * static_cast<int64_t>(na) * (nn + P);
         }
         hipEvent_t ev;
-        if ((e = t_gen.start(s, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->media, M);
-        if (e == hipSuccess) e = t_gen.stop(s, ev);
+        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->media, M);
+        if (e == hipSuccess) e = t_gen.stop(sc, ev);
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: generate M"); }
 
         // ---- ID: CPQR of M_b^T
@@ -399,22 +605,17 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = sc.alloc(&drdiag, uoff[nb]);
         if (e == hipSuccess) e = sc.alloc(&dranks, nb);
         std::vector<CpqrJob> cj(nb);
-        int64_t nmax = 0;
-        for (int b = 0; b < nb; ++b) {
-            cj[b] = CpqrJob{M + mo[b], dperm + uoff[b], drdiag + uoff[b], static_cast<int32_t>(n[b]), static_cast<int32_t>(m[b])};
-            nmax = std::max(nmax, n[b]);
-        }
-        CpqrJob* dcj;
-        if (e == hipSuccess) e = sc.upload(&dcj, cj);
+        for (int b = 0; b < nb; ++b)
+            cj[b] = CpqrJob{M + mo[b], dperm + uoff[b], drdiag + uoff[b], nullptr, nullptr, nullptr,
+                            static_cast<int32_t>(n[b]), static_cast<int32_t>(m[b])};
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: cpqr setup"); }
-        if ((e = t_cmp.start(s, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
-        hipLaunchKernelGGL(k_cpqr, dim3(nb), dim3(kThreads), static_cast<size_t>(nmax) * sizeof(double), s, dcj, tol, dranks);
+        if ((e = t_cmp.start(sc, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        CpqrJob* dcj = nullptr;
         std::vector<int32_t> ranks(nb), perm(uoff[nb]);
-        e = hipGetLastError();
-        if (e == hipSuccess) e = hipMemcpyAsync(ranks.data(), dranks, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks);
         if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        sc.drop_host();
+        sc.synced();
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: cpqr"); }
         std::vector<int64_t> k(nb), koff(nb + 1, 0), nkoff(nb + 1, 0), nnoff(nb + 1, 0), kkoff(nb + 1, 0);
         for (int b = 0; b < nb; ++b) {
@@ -427,12 +628,23 @@ int build_impl(bm_hss* h, hipStream_t s) {
         }
         double2* T;
         e = sc.alloc(&T, nkoff[nb]);
-        if (e == hipSuccess) e = hipMemsetAsync(T, 0, std::max<int64_t>(nkoff[nb], 1) * sizeof(double2), s);
+        {
+            const size_t tbytes = std::max<int64_t>(nkoff[nb], 1) * sizeof(double2);
+            sc.rec([=]() { return hipMemsetAsync(T, 0, tbytes, s); });
+        }
         int64_t* dtoff;
         if (e == hipSuccess) e = sc.upload(&dtoff, std::vector<int64_t>(nkoff.begin(), nkoff.end() - 1));
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: T"); }
-        hipLaunchKernelGGL(k_interp, dim3(nb), dim3(kThreads), 0, s, dcj, dranks, dtoff, T);
-        if ((e = t_cmp.stop(s, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        int64_t cmax = 1;
+        for (int b = 0; b < nb; ++b) cmax = std::max(cmax, n[b] - k[b]);
+        {
+            const unsigned cx = static_cast<unsigned>(ceil_div(cmax, kThreads / 64));
+            sc.rec([=]() {
+                hipLaunchKernelGGL(k_interp, dim3(cx, nb), dim3(kThreads), 0, s, dcj, dranks, dtoff, T);
+                return hipGetLastError();
+            });
+        }
+        if ((e = t_cmp.stop(sc, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
 
         // ---- diagonal blocks D_b (become G_b in place)
         LevelFactor f;
@@ -466,8 +678,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
                                          n[b], 1, static_cast<int32_t>(kb), static_cast<int32_t>(kb)});
             }
         }
-        if ((e = t_gen.start(s, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->media, F.G);
-        if (e == hipSuccess) e = t_gen.stop(s, ev);
+        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->media, F.G);
+        if (e == hipSuccess) e = t_gen.stop(sc, ev);
         if (e == hipSuccess) e = launch_copy(sc, copies);
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: D blocks"); }
 
@@ -480,11 +692,14 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = sc.alloc(&piv, uoff[nb]);
         int32_t* st = nullptr;
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&st), 2 * nb * sizeof(int32_t));
-        if (e == hipSuccess) { status_bufs.push_back(st); e = hipMemsetAsync(st, 0, 2 * nb * sizeof(int32_t), s); }
+        if (e == hipSuccess) {
+            status_bufs.push_back(st);
+            sc.rec([=]() { return hipMemsetAsync(st, 0, 2 * nb * sizeof(int32_t), s); });
+        }
         if (e != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor buffers"); }
-        if ((e = t_fac.start(s, ev)) != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        if ((e = t_fac.start(sc, ev)) != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "event"); }
         std::vector<InvJob> inv(nb);
-        for (int b = 0; b < nb; ++b) inv[b] = InvJob{F.G + nnoff[b], piv + uoff[b], st + b, static_cast<int32_t>(n[b])};
+        for (int b = 0; b < nb; ++b) inv[b] = InvJob{F.G + nnoff[b], piv + uoff[b], st + b, n[b], static_cast<int32_t>(n[b])};
         e = launch_inverse(sc, inv);
         std::vector<GemmJob> g1, g2, g3, g4;
         const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
@@ -504,7 +719,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
         }
         if (e == hipSuccess) e = launch_gemm(sc, g2);
         std::vector<InvJob> inv2(nb);
-        for (int b = 0; b < nb; ++b) inv2[b] = InvJob{S + kkoff[b], piv + uoff[b], st + nb + b, static_cast<int32_t>(k[b])};
+        for (int b = 0; b < nb; ++b) inv2[b] = InvJob{S + kkoff[b], piv + uoff[b], st + nb + b, k[b], static_cast<int32_t>(k[b])};
         if (e == hipSuccess) e = launch_inverse(sc, inv2);
         for (int b = 0; b < nb; ++b) {
             const int64_t nn = n[b], kk = k[b];
@@ -519,7 +734,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
             g4.push_back(gemm(F.E + nkoff[b], kk, 1, Wt + nkoff[b], nn, 1, F.G + nnoff[b], nn, 1, nn, nn, kk, mone, one));
         }
         if (e == hipSuccess) e = launch_gemm(sc, g4);
-        if (e == hipSuccess) e = t_fac.stop(s, ev);
+        if (e == hipSuccess) e = t_fac.stop(sc, ev);
         if (e != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor"); }
 
         // ---- next level: U(parent) = J(first child) then J(second child)
@@ -541,8 +756,9 @@ int build_impl(bm_hss* h, hipStream_t s) {
             split_slots[q] = static_cast<int64_t>(tmp.size());
             U[q].insert(U[q].end(), J[2 * q + 1].begin(), J[2 * q + 1].end());
         }
-        e = hipStreamSynchronize(s);   // the level's temporaries may be released now
-        sc.drop_host();
+        e = sc.flush();
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // the level's temporaries may be released now
+        sc.synced();
         sc.release();
         if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: level end"); }
         ++compressed;
@@ -569,8 +785,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
         entries += K * K;
         pairs += static_cast<int64_t>(rs.size()) * rs.size();
         hipEvent_t ev;
-        if ((e = t_gen.start(s, ev)) == hipSuccess) e = launch_gen(sc, jobs, drs, pt, p->media, h->Rinv);
-        if (e == hipSuccess) e = t_gen.stop(s, ev);
+        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, drs, pt, p->media, h->Rinv);
+        if (e == hipSuccess) e = t_gen.stop(sc, ev);
         // diagonal blocks of the last compressed level's boxes are their Dhat
         std::vector<CopyJob> copies;
         if (compressed > 0) {
@@ -585,13 +801,17 @@ int build_impl(bm_hss* h, hipStream_t s) {
         int32_t *piv, *st;
         if (e == hipSuccess) e = sc.alloc(&piv, K);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&st), sizeof(int32_t));
-        if (e == hipSuccess) { status_bufs.push_back(st); e = hipMemsetAsync(st, 0, sizeof(int32_t), s); }
-        if (e == hipSuccess && (e = t_fac.start(s, ev)) == hipSuccess) {
-            e = launch_inverse(sc, {InvJob{h->Rinv, piv, st, static_cast<int32_t>(K)}});
-            if (e == hipSuccess) e = t_fac.stop(s, ev);
+        if (e == hipSuccess) {
+            status_bufs.push_back(st);
+            sc.rec([=]() { return hipMemsetAsync(st, 0, sizeof(int32_t), s); });
         }
+        if (e == hipSuccess && (e = t_fac.start(sc, ev)) == hipSuccess) {
+            e = launch_inverse(sc, {InvJob{h->Rinv, piv, st, K, static_cast<int32_t>(K)}});
+            if (e == hipSuccess) e = t_fac.stop(sc, ev);
+        }
+        if (e == hipSuccess) e = sc.flush();
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        sc.drop_host();
+        sc.synced();
         sc.release();
         if (Dhat_prev) (void)hipFreeAsync(Dhat_prev, s);
         if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: root factor"); }
@@ -715,11 +935,13 @@ int bm_hss_solve(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipS
     }
     if (e == hipSuccess) {
         const double2* res = nl > 0 ? xl[0] : xroot;
-        e = hipMemcpyAsync(x, res, N2 * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, s);
+        const size_t bytes = N2 * nrhs * sizeof(double2);
+        sc.rec([=]() { return hipMemcpyAsync(x, res, bytes, hipMemcpyDeviceToDevice, s); });
+        e = sc.flush();
     }
     // the job descriptors are staged from host memory: finish before releasing them
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    sc.drop_host();
+    sc.synced();
     sc.release();
     if (e != hipSuccess) return hip_fail(e, "bm_hss_solve");
     return BM_OK;

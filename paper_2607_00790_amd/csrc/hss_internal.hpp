@@ -41,20 +41,34 @@ struct GenJob {
     int32_t ns;
 };
 
+struct CpqrState {
+    double ref;    // |R_00|
+    double beta;   // scale of the current Householder reflector
+    int32_t rank;
+    int32_t done;
+};
+
 // Column-pivoted QR of an m x n column-major complex matrix x (columns are the
-// candidate unknowns of a box).
+// candidate unknowns of a box).  nrm and st are used by the step-wise kernels.
+// The step kernels pivot logically and need nrm (2n doubles, double-buffered),
+// used (n flags) and st; k_interp also accepts physically pivoted columns
+// (used == nullptr).
 struct CpqrJob {
     double2* x;
     int32_t* perm;
     double2* rdiag;
+    double* nrm;
+    int32_t* used;
+    CpqrState* st;
     int32_t n;
     int32_t m;
 };
 
 struct InvJob {
-    double2* a;       // n x n row-major, inverted in place
+    double2* a;       // n x n, row-major with leading dimension ld, inverted in place
     int32_t* piv;     // n
     int32_t* status;  // set to 1 on a zero pivot (caller zeroes it)
+    int64_t ld;
     int32_t n;
 };
 
@@ -85,15 +99,19 @@ __global__ void k_near_list(PointTable pt, const Slot* slots, const int32_t* slo
                             Slot* out);
 __global__ void k_gen_jobs(const GenJob* jobs, const int64_t* tile_off, int njobs,
                            const Slot* slots, PointTable pt, Media m, double2* out);
-__global__ void k_cpqr(const CpqrJob* jobs, double tol, int32_t* rank_out);
 __global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
                          double2* Tbuf);
 __global__ void k_gauss_jordan(const InvJob* jobs);
-__global__ void k_gj_pivot(double2* A, int n, int k, int32_t* piv, double2* colbuf,
-                           int32_t* status);
-__global__ void k_gj_eliminate(double2* A, int n, int k, const double2* colbuf,
-                               const int32_t* status);
-__global__ void k_gj_unscramble(double2* A, int n, const int32_t* piv, const int32_t* status);
+__global__ void k_gauss_jordan_lds(const InvJob* jobs);
+// bytes of dynamic LDS k_gauss_jordan_lds needs for an n x n block
+inline size_t gj_lds_bytes(int n) {
+    return (static_cast<size_t>(n) * (n + 1) + n) * sizeof(double2) + static_cast<size_t>(n) * sizeof(int);
+}
+__global__ void k_cpqr_init(const CpqrJob* jobs);
+__global__ void k_cpqr_step(const CpqrJob* jobs, int k, double tol);
+__global__ void k_cpqr_finish(const CpqrJob* jobs);
+__global__ void k_cpqr_ranks(const CpqrJob* jobs, int nb, int32_t* ranks, int32_t* active);
+
 __global__ void k_gemm(const GemmJob* jobs, const int64_t* tile_off, int njobs);
 __global__ void k_copy_blocks(const CopyJob* jobs);
 

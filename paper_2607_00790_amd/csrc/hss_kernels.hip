@@ -7,10 +7,12 @@
 //   k_gen_jobs       one launch generates every WSBM block a level needs
 //                    (near, proxy, diagonal and skeleton blocks of all boxes),
 //                    one node pair per thread, masked 2x2 writes
-//   k_cpqr           column-pivoted Householder QR of M_b^T, one workgroup per
-//                    box, with the relative rank rule |R_kk| > tol |R_11|
+//   k_cpqr_*         column-pivoted Householder QR of M_b^T for all boxes of a
+//                    level, one launch per elimination step, with the relative
+//                    rank rule |R_kk| > tol |R_00|
 //   k_interp         T_b = [I; (R11^-1 R12)^T] in pivoted order
-//   k_gauss_jordan   batched in-place inverse with row pivoting
+//   k_gauss_jordan*  batched in-place inverse with row pivoting (LDS-resident
+//                    for blocks that fit)
 //   k_gemm           batched strided complex GEMM
 #include "hss_internal.hpp"
 
@@ -254,147 +256,205 @@ k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off
 }
 
 // ---------------------------------------------------------------------------
-// Column-pivoted Householder QR of X_b = M_b^T for every box b.  X_b is stored
-// column-major (column j = row j of M_b, length m), n columns.  On exit:
-//   rank[b]; perm (n entries, pivot order); X holds R above the diagonal in its
-//   first rank rows (R[i][j] at X[j*m + i], i < j) and rdiag[i] = R_ii.
-// The relative rank rule keeps step k while |R_kk| > tol |R_00|.  Column norms
-// are recomputed exactly in every update pass (no downdating).
+// Level-batched CPQR by steps, for levels with few, large boxes: per
+// elimination step k one launch of k_cpqr_pivot (one workgroup per box: pivot,
+// column swap, Householder vector) and one of k_cpqr_update (many workgroups
+// per box, one wave per trailing column).  State per box lives in global
+// memory: column norms, the reference |R_00|, the Householder scale, rank, done.
 __global__ void __launch_bounds__(kThreads)
-k_cpqr(const CpqrJob* __restrict__ jobs, double tol, int32_t* __restrict__ rank_out) {
-    extern __shared__ double dyn_lds[];
-    const CpqrJob jb = jobs[blockIdx.x];
-    const int n = jb.n, m = jb.m;
-    double2* X = jb.x;
-    int32_t* perm = jb.perm;
-    double2* rdiag = jb.rdiag;
-    double* nrm = dyn_lds;                    // n column norms^2
+k_cpqr_init(const CpqrJob* __restrict__ jobs) {
+    const CpqrJob jb = jobs[blockIdx.y];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
+    const int j = blockIdx.x * nw + wid;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        jb.st->ref = 0;
+        jb.st->beta = 0;
+        jb.st->rank = 0;
+        jb.st->done = 0;
+    }
+    if (j >= jb.n) return;
+    if (lane == 0) {
+        jb.perm[j] = j;
+        jb.used[j] = 0;
+    }
+    double s = 0;
+    for (int r = lane; r < jb.m; r += 64) s += cabs2(jb.x[static_cast<int64_t>(j) * jb.m + r]);
+    s = wave_sum(s);
+    if (lane == 0) jb.nrm[j] = s;
+}
+
+// One elimination step k of the level-batched CPQR, fused into one launch.
+// Pivoting is logical: columns stay in place, perm[k] records the k-th pivot
+// and used[] marks retired columns (the pivot of step k-1 is excluded
+// explicitly, since its used[] entry is written during this launch).  Column
+// norms are double-buffered (read nrm[k % 2], write nrm[(k+1) % 2]), so every
+// workgroup of a box computes the same pivot from the same data.  Grid: (box,
+// chunk of kThreads/64 columns), one wave per column.
+__global__ void __launch_bounds__(kThreads)
+k_cpqr_step(const CpqrJob* __restrict__ jobs, int k, double tol) {
     __shared__ double sv[kThreads / 64];
     __shared__ int si[kThreads / 64];
-    __shared__ double2 sh_beta_alpha[2];
+    const CpqrJob jb = jobs[blockIdx.y];
+    CpqrState* st = jb.st;
+    if (st->done) return;
+    const int n = jb.n, m = jb.m;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (k >= (n < m ? n : m)) {
+        if (lead) { st->rank = k; st->done = 1; }
+        return;
+    }
+    const double* __restrict__ nin = jb.nrm + (k & 1) * n;
+    double* __restrict__ nout = jb.nrm + ((k + 1) & 1) * n;
+    const int prev = k > 0 ? jb.perm[k - 1] : -1;
+    double bv = -1;
+    int bi = n;
+    for (int j = threadIdx.x; j < n; j += kThreads)
+        if (!jb.used[j] && j != prev && nin[j] > bv) { bv = nin[j]; bi = j; }
+    block_argmax(bv, bi, sv, si);
+    const double ref = k == 0 ? sqrt(bv) : st->ref;
+    if (!(sqrt(bv) > tol * ref) || ref == 0 || bi >= n) {
+        if (lead) { st->rank = k; st->done = 1; }
+        return;
+    }
+    const int p = bi;
+    const double2* __restrict__ w = jb.x + static_cast<int64_t>(p) * m;   // rows >= k
+    const double xn = sqrt(nin[p]);
+    const double2 x0 = w[k];
+    const double a0 = sqrt(cabs2(x0));
+    const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
+    const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
+    const double2 w0 = make_double2(x0.x - alpha.x, x0.y - alpha.y);   // first entry of w
+    const double beta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
+    if (lead) {
+        jb.perm[k] = p;
+        jb.rdiag[k] = alpha;
+        if (prev >= 0) jb.used[prev] = 1;
+        if (k == 0) st->ref = ref;
+    }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
-    for (int j = threadIdx.x; j < n; j += kThreads) perm[j] = j;
-    // initial norms: one wave per column
-    for (int j = wid; j < n; j += nw) {
-        double s = 0;
-        for (int r = lane; r < m; r += 64) s += cabs2(X[static_cast<int64_t>(j) * m + r]);
-        s = wave_sum(s);
-        if (lane == 0) nrm[j] = s;
+    const int j = blockIdx.x * nw + wid;
+    if (j >= n || j == p || j == prev || jb.used[j]) return;
+    double2* __restrict__ cj = jb.x + static_cast<int64_t>(j) * m;
+    double gr = 0, gi = 0;
+    for (int r = k + lane; r < m; r += 64) {
+        const double2 t = cconj_mul(r == k ? w0 : w[r], cj[r]);
+        gr += t.x;
+        gi += t.y;
     }
+    gr = wave_sum(gr) * beta;
+    gi = wave_sum(gi) * beta;
+    double s = 0;
+    for (int r = k + lane; r < m; r += 64) {
+        const double2 wr = r == k ? w0 : w[r];
+        double2 y = cj[r];
+        y.x -= gr * wr.x - gi * wr.y;
+        y.y -= gr * wr.y + gi * wr.x;
+        cj[r] = y;
+        if (r > k) s += cabs2(y);
+    }
+    s = wave_sum(s);
+    if (lane == 0) nout[j] = s;
+}
+
+// After the step-wise CPQR: mark the last pivot used and list the remaining
+// columns after the pivots, perm[rank..n) in increasing order.  One workgroup
+// per box.
+__global__ void __launch_bounds__(kThreads)
+k_cpqr_finish(const CpqrJob* __restrict__ jobs) {
+    __shared__ int scan[kThreads];
+    __shared__ int base;
+    const CpqrJob jb = jobs[blockIdx.x];
+    const int n = jb.n, r = jb.st->rank;
+    if (threadIdx.x == 0) base = r;
+    for (int i = threadIdx.x; i < r; i += kThreads) jb.used[jb.perm[i]] = 1;
     __syncthreads();
-    const int kmax = n < m ? n : m;
-    double ref = 0;
-    int k = 0;
-    for (; k < kmax; ++k) {
-        double bv = -1;
-        int bi = n;
-        for (int j = k + threadIdx.x; j < n; j += kThreads)
-            if (nrm[j] > bv) { bv = nrm[j]; bi = j; }
-        block_argmax(bv, bi, sv, si);
-        const int p = bi;
-        if (k == 0) ref = sqrt(bv);
-        if (!(sqrt(bv) > tol * ref) || ref == 0) break;
-        // swap columns k and p
-        if (p != k) {
-            double2* ck = X + static_cast<int64_t>(k) * m;
-            double2* cp = X + static_cast<int64_t>(p) * m;
-            for (int r = threadIdx.x; r < m; r += kThreads) {
-                const double2 t = ck[r];
-                ck[r] = cp[r];
-                cp[r] = t;
-            }
-            if (threadIdx.x == 0) {
-                const int t = perm[k]; perm[k] = perm[p]; perm[p] = t;
-                const double tn = nrm[k]; nrm[k] = nrm[p]; nrm[p] = tn;
-            }
-        }
+    for (int j0 = 0; j0 < n; j0 += kThreads) {
+        const int j = j0 + threadIdx.x;
+        const int f = (j < n && !jb.used[j]) ? 1 : 0;
+        scan[threadIdx.x] = f;
         __syncthreads();
-        // Householder vector w = x - alpha e1 in place of column k (rows k..m-1)
-        double2* ck = X + static_cast<int64_t>(k) * m;
-        if (threadIdx.x == 0) {
-            const double xn = sqrt(nrm[k]);   // exact: recomputed in the previous pass
-            const double2 x0 = ck[k];
-            const double a0 = sqrt(cabs2(x0));
-            const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
-            const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
-            ck[k] = make_double2(x0.x - alpha.x, x0.y - alpha.y);
-            const double beta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
-            sh_beta_alpha[0] = make_double2(beta, 0.0);
-            sh_beta_alpha[1] = alpha;
-            rdiag[k] = alpha;
+        for (int off = 1; off < kThreads; off <<= 1) {
+            const int v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
         }
+        if (f) jb.perm[base + scan[threadIdx.x] - 1] = j;
         __syncthreads();
-        const double beta = sh_beta_alpha[0].x;
-        // apply H = I - beta w w^H to columns j > k; recompute their norms (rows > k)
-        for (int j = k + 1 + wid; j < n; j += nw) {
-            double2* cj = X + static_cast<int64_t>(j) * m;
-            double gr = 0, gi = 0;
-            for (int r = k + lane; r < m; r += 64) {
-                const double2 t = cconj_mul(ck[r], cj[r]);
-                gr += t.x;
-                gi += t.y;
-            }
-            gr = wave_sum(gr) * beta;
-            gi = wave_sum(gi) * beta;
-            double s = 0;
-            for (int r = k + lane; r < m; r += 64) {
-                const double2 w = ck[r];
-                double2 y = cj[r];
-                y.x -= gr * w.x - gi * w.y;
-                y.y -= gr * w.y + gi * w.x;
-                cj[r] = y;
-                if (r > k) s += cabs2(y);
-            }
-            s = wave_sum(s);
-            if (lane == 0) nrm[j] = s;
-        }
+        if (threadIdx.x == kThreads - 1) base += scan[kThreads - 1];
         __syncthreads();
     }
-    if (threadIdx.x == 0) rank_out[blockIdx.x] = k;
+}
+
+// Ranks of the step-wise CPQR.
+__global__ void k_cpqr_ranks(const CpqrJob* __restrict__ jobs, int nb, int32_t* __restrict__ ranks,
+                             int32_t* __restrict__ active) {
+    int cnt = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        ranks[b] = jobs[b].st->rank;
+        cnt += jobs[b].st->done ? 0 : 1;
+    }
+    cnt = static_cast<int>(wave_sum(static_cast<double>(cnt)));
+    if (threadIdx.x == 0) *active = cnt;
 }
 
 // T_b (n x k, row-major) from the CPQR result: rows perm[0..k) are the
-// identity, row perm[k + c] holds column c of Z = R11^-1 R12, found by back
-// substitution by one thread per column (the thread's own row of T is its
-// workspace, so every value it reads back it wrote itself).  T must be zeroed
-// beforehand.
+// identity, row perm[k + c] holds column c of Z = R11^-1 R12.  Back
+// substitution by one wave per column: lane l owns the entries z_i with
+// i = l (mod 64) and keeps them in the column's own row of T, so a lane only
+// ever reads values it wrote itself; the partial dot products are combined by
+// a butterfly sum, after which every lane knows the new z_i.  T must be zeroed
+// beforehand.  Grid: (box, column chunk of kThreads/64 columns).
 __global__ void __launch_bounds__(kThreads)
 k_interp(const CpqrJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
          const int64_t* __restrict__ t_off, double2* __restrict__ Tbuf) {
-    const CpqrJob jb = jobs[blockIdx.x];
-    const int n = jb.n, m = jb.m, k = ranks[blockIdx.x];
-    double2* T = Tbuf + t_off[blockIdx.x];
+    const CpqrJob jb = jobs[blockIdx.y];
+    const int n = jb.n, m = jb.m, k = ranks[blockIdx.y];
+    double2* T = Tbuf + t_off[blockIdx.y];
     const double2* X = jb.x;
-    for (int i = threadIdx.x; i < k; i += kThreads)
-        T[static_cast<int64_t>(jb.perm[i]) * k + i] = make_double2(1.0, 0.0);
-    for (int c = threadIdx.x; c < n - k; c += kThreads) {
-        const double2* rc = X + static_cast<int64_t>(k + c) * m;   // column k+c of R (rows < k)
-        double2* z = T + static_cast<int64_t>(jb.perm[k + c]) * k;
-        for (int i = k - 1; i >= 0; --i) {
-            double2 num = rc[i];
-            for (int l = i + 1; l < k; ++l) {
-                const double2 t = cmul(X[static_cast<int64_t>(l) * m + i], z[l]);
-                num.x -= t.x;
-                num.y -= t.y;
-            }
-            const double2 d = jb.rdiag[i];
-            const double dd = cabs2(d);
-            z[i] = make_double2((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < k; i += kThreads)
+            T[static_cast<int64_t>(jb.perm[i]) * k + i] = make_double2(1.0, 0.0);
+    const int c = blockIdx.x * nw + wid;
+    if (c >= n - k) return;
+    // column of X holding pivot l: l after physical swaps, perm[l] with logical pivoting
+    const bool logical = jb.used != nullptr;
+    const double2* rc = X + static_cast<int64_t>(logical ? jb.perm[k + c] : k + c) * m;
+    double2* z = T + static_cast<int64_t>(jb.perm[k + c]) * k;
+    for (int i = k - 1; i >= 0; --i) {
+        double sr = 0, si = 0;
+        for (int l = i + 1 + ((lane - i - 1) & 63); l < k; l += 64) {   // l = lane (mod 64)
+            const int64_t cl = logical ? jb.perm[l] : l;
+            const double2 t = cmul(X[cl * m + i], z[l]);
+            sr += t.x;
+            si += t.y;
         }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        const double2 num = make_double2(rc[i].x - sr, rc[i].y - si);
+        const double2 d = jb.rdiag[i];
+        const double dd = cabs2(d);
+        if ((i & 63) == lane)
+            z[i] = make_double2((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Batched in-place inverse by Gauss-Jordan elimination with row pivoting; one
-// workgroup per matrix (row-major, ld = n).  status[b] = 1 on a zero pivot.
+// workgroup per matrix (row-major, leading dimension ld).  A zero pivot sets
+// the job's status flag.  Used for blocks of moderate size; larger matrices
+// are reduced to such blocks by 2 x 2 block (Schur complement) recursion on
+// the host side.
 __global__ void __launch_bounds__(kThreads)
 k_gauss_jordan(const InvJob* __restrict__ jobs) {
-    extern __shared__ double dyn_lds[];
+    extern __shared__ __attribute__((aligned(16))) double dyn_lds[];
     double2* col = reinterpret_cast<double2*>(dyn_lds);   // n entries: saved pivot column
     __shared__ double sv[kThreads / 64];
     __shared__ int si[kThreads / 64];
     const InvJob jb = jobs[blockIdx.x];
     const int n = jb.n;
+    const int64_t ld = jb.ld;
     double2* A = jb.a;
     int32_t* piv = jb.piv;
     int bad = 0;
@@ -402,7 +462,7 @@ k_gauss_jordan(const InvJob* __restrict__ jobs) {
         double bv = -1;
         int bi = n;
         for (int i = k + threadIdx.x; i < n; i += kThreads) {
-            const double v = cabs2(A[static_cast<int64_t>(i) * n + k]);
+            const double v = cabs2(A[i * ld + k]);
             if (v > bv) { bv = v; bi = i; }
         }
         block_argmax(bv, bi, sv, si);
@@ -411,33 +471,38 @@ k_gauss_jordan(const InvJob* __restrict__ jobs) {
         if (threadIdx.x == 0) piv[k] = p;
         if (p != k) {
             for (int j = threadIdx.x; j < n; j += kThreads) {
-                const double2 t = A[static_cast<int64_t>(k) * n + j];
-                A[static_cast<int64_t>(k) * n + j] = A[static_cast<int64_t>(p) * n + j];
-                A[static_cast<int64_t>(p) * n + j] = t;
+                const double2 t = A[k * ld + j];
+                A[k * ld + j] = A[p * ld + j];
+                A[p * ld + j] = t;
             }
         }
         __syncthreads();
-        const double2 d = A[static_cast<int64_t>(k) * n + k];
+        const double2 d = A[k * ld + k];
         const double dd = cabs2(d);
         const double2 inv = make_double2(d.x / dd, -d.y / dd);
+        __syncthreads();
         for (int i = threadIdx.x; i < n; i += kThreads) {
-            col[i] = A[static_cast<int64_t>(i) * n + k];
-            A[static_cast<int64_t>(i) * n + k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
+            col[i] = A[i * ld + k];
+            A[i * ld + k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < n; j += kThreads)
-            A[static_cast<int64_t>(k) * n + j] = cmul(A[static_cast<int64_t>(k) * n + j], inv);
+        for (int j = threadIdx.x; j < n; j += kThreads) A[k * ld + j] = cmul(A[k * ld + j], inv);
         __syncthreads();
-        for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * n; e += kThreads) {
-            const int i = static_cast<int>(e / n);
+        // one wave per row, lanes along the row (coalesced)
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        for (int i = wid; i < n; i += kThreads / 64) {
             if (i == k) continue;
-            const int j = static_cast<int>(e - static_cast<int64_t>(i) * n);
             const double2 f = col[i];
-            const double2 rk = A[static_cast<int64_t>(k) * n + j];
-            double2 a = A[e];
-            a.x -= f.x * rk.x - f.y * rk.y;
-            a.y -= f.x * rk.y + f.y * rk.x;
-            A[e] = a;
+            if (f.x == 0.0 && f.y == 0.0) continue;
+            double2* ri = A + i * ld;
+            const double2* rk = A + k * ld;
+            for (int j = lane; j < n; j += 64) {
+                const double2 r = rk[j];
+                double2 a = ri[j];
+                a.x -= f.x * r.x - f.y * r.y;
+                a.y -= f.x * r.y + f.y * r.x;
+                ri[j] = a;
+            }
         }
         __syncthreads();
     }
@@ -446,9 +511,9 @@ k_gauss_jordan(const InvJob* __restrict__ jobs) {
             const int p = piv[k];
             if (p != k) {
                 for (int i = threadIdx.x; i < n; i += kThreads) {
-                    const double2 t = A[static_cast<int64_t>(i) * n + k];
-                    A[static_cast<int64_t>(i) * n + k] = A[static_cast<int64_t>(i) * n + p];
-                    A[static_cast<int64_t>(i) * n + p] = t;
+                    const double2 t = A[i * ld + k];
+                    A[i * ld + k] = A[i * ld + p];
+                    A[i * ld + p] = t;
                 }
             }
             __syncthreads();
@@ -457,82 +522,109 @@ k_gauss_jordan(const InvJob* __restrict__ jobs) {
     if (threadIdx.x == 0 && bad) *jb.status = 1;
 }
 
-// Large single matrix: one Gauss-Jordan step k split over two launches.
-// Step A (one workgroup): pivot search, row swap, scaling of row k, saving
-// column k into colbuf.
+// LDS-resident variant for blocks that fit the workgroup's LDS: the matrix is
+// staged with a padded row stride (n + 1), the pivot search runs in wave 0
+// without block barriers, and every elimination step touches LDS only.
 __global__ void __launch_bounds__(kThreads)
-k_gj_pivot(double2* __restrict__ A, int n, int k, int32_t* __restrict__ piv,
-           double2* __restrict__ colbuf, int32_t* __restrict__ status) {
-    __shared__ double sv[kThreads / 64];
-    __shared__ int si[kThreads / 64];
-    if (*status) return;
-    double bv = -1;
-    int bi = n;
-    for (int i = k + threadIdx.x; i < n; i += kThreads) {
-        const double v = cabs2(A[static_cast<int64_t>(i) * n + k]);
-        if (v > bv) { bv = v; bi = i; }
+k_gauss_jordan_lds(const InvJob* __restrict__ jobs) {
+    extern __shared__ __attribute__((aligned(16))) double dyn_lds[];
+    __shared__ int sh_piv;
+    const InvJob jb = jobs[blockIdx.x];
+    const int n = jb.n, sn = n + 1;
+    const int64_t ld = jb.ld;
+    double2* S = reinterpret_cast<double2*>(dyn_lds);   // n x (n+1)
+    double2* col = S + n * sn;                           // n
+    int* piv = reinterpret_cast<int*>(col + n);          // n
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
+    for (int i = wid; i < n; i += nw)
+        for (int j = lane; j < n; j += 64) S[i * sn + j] = jb.a[i * ld + j];
+    __syncthreads();
+    int bad = 0;
+    for (int k = 0; k < n; ++k) {
+        if (wid == 0) {
+            double bv = -1;
+            int bi = n;
+            for (int i = k + lane; i < n; i += 64) {
+                const double v = cabs2(S[i * sn + k]);
+                if (v > bv) { bv = v; bi = i; }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            if (lane == 0) sh_piv = bv > 0 ? bi : -1;
+        }
+        __syncthreads();
+        const int p = sh_piv;
+        if (p < 0) { bad = 1; break; }
+        if (threadIdx.x == 0) piv[k] = p;
+        if (p != k) {
+            for (int j = threadIdx.x; j < n; j += kThreads) {
+                const double2 t = S[k * sn + j];
+                S[k * sn + j] = S[p * sn + j];
+                S[p * sn + j] = t;
+            }
+        }
+        __syncthreads();
+        const double2 d = S[k * sn + k];
+        const double dd = cabs2(d);
+        const double2 inv = make_double2(d.x / dd, -d.y / dd);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+            col[i] = S[i * sn + k];
+            S[i * sn + k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += kThreads) S[k * sn + j] = cmul(S[k * sn + j], inv);
+        __syncthreads();
+        // rows k' = wid + nw*t, columns lane and lane + 64 (n <= 128): row k is
+        // held in registers and four rows are loaded before any is stored
+        const bool c1 = lane + 64 < n;
+        const double2 r0 = lane < n ? S[k * sn + lane] : make_double2(0.0, 0.0);
+        const double2 r1 = c1 ? S[k * sn + lane + 64] : make_double2(0.0, 0.0);
+        for (int i0 = wid; i0 < n; i0 += 4 * nw) {
+            double2 a0[4], a1[4], f[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q * nw;
+                f[q] = (i < n && i != k) ? col[i] : make_double2(0.0, 0.0);
+                a0[q] = (i < n && lane < n) ? S[i * sn + lane] : make_double2(0.0, 0.0);
+                a1[q] = (i < n && c1) ? S[i * sn + lane + 64] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q * nw;
+                if (i >= n || i == k) continue;
+                a0[q].x -= f[q].x * r0.x - f[q].y * r0.y;
+                a0[q].y -= f[q].x * r0.y + f[q].y * r0.x;
+                a1[q].x -= f[q].x * r1.x - f[q].y * r1.y;
+                a1[q].y -= f[q].x * r1.y + f[q].y * r1.x;
+                if (lane < n) S[i * sn + lane] = a0[q];
+                if (c1) S[i * sn + lane + 64] = a1[q];
+            }
+        }
+        __syncthreads();
     }
-    block_argmax(bv, bi, sv, si);
-    if (!(bv > 0)) {
-        if (threadIdx.x == 0) *status = 1;
+    if (bad) {
+        if (threadIdx.x == 0) *jb.status = 1;
         return;
     }
-    const int p = bi;
-    if (threadIdx.x == 0) piv[k] = p;
-    if (p != k) {
-        for (int j = threadIdx.x; j < n; j += kThreads) {
-            const double2 t = A[static_cast<int64_t>(k) * n + j];
-            A[static_cast<int64_t>(k) * n + j] = A[static_cast<int64_t>(p) * n + j];
-            A[static_cast<int64_t>(p) * n + j] = t;
-        }
-    }
-    __syncthreads();
-    const double2 d = A[static_cast<int64_t>(k) * n + k];
-    const double dd = cabs2(d);
-    const double2 inv = make_double2(d.x / dd, -d.y / dd);
-    for (int i = threadIdx.x; i < n; i += kThreads) {
-        colbuf[i] = A[static_cast<int64_t>(i) * n + k];
-        A[static_cast<int64_t>(i) * n + k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += kThreads)
-        A[static_cast<int64_t>(k) * n + j] = cmul(A[static_cast<int64_t>(k) * n + j], inv);
-}
-
-// Step B (grid over rows): eliminate column k from every row i != k.
-__global__ void __launch_bounds__(kThreads)
-k_gj_eliminate(double2* __restrict__ A, int n, int k, const double2* __restrict__ colbuf,
-               const int32_t* __restrict__ status) {
-    if (*status) return;
-    const int i = blockIdx.x;
-    if (i == k) return;
-    const double2 f = colbuf[i];
-    if (f.x == 0.0 && f.y == 0.0) return;
-    for (int j = threadIdx.x; j < n; j += kThreads) {
-        const double2 rk = A[static_cast<int64_t>(k) * n + j];
-        double2 a = A[static_cast<int64_t>(i) * n + j];
-        a.x -= f.x * rk.x - f.y * rk.y;
-        a.y -= f.x * rk.y + f.y * rk.x;
-        A[static_cast<int64_t>(i) * n + j] = a;
-    }
-}
-
-// Column unscrambling after the large Gauss-Jordan: one thread per row.
-__global__ void __launch_bounds__(kThreads)
-k_gj_unscramble(double2* __restrict__ A, int n, const int32_t* __restrict__ piv,
-                const int32_t* __restrict__ status) {
-    if (*status) return;
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    double2* row = A + static_cast<int64_t>(i) * n;
+    // undo the row interchanges on the columns, then write back
     for (int k = n - 1; k >= 0; --k) {
         const int p = piv[k];
         if (p != k) {
-            const double2 t = row[k];
-            row[k] = row[p];
-            row[p] = t;
+            for (int i = threadIdx.x; i < n; i += kThreads) {
+                const double2 t = S[i * sn + k];
+                S[i * sn + k] = S[i * sn + p];
+                S[i * sn + p] = t;
+            }
         }
+        __syncthreads();
     }
+    for (int i = wid; i < n; i += nw)
+        for (int j = lane; j < n; j += 64) jb.a[i * ld + j] = S[i * sn + j];
 }
 
 // ---------------------------------------------------------------------------
