@@ -167,10 +167,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", choices=["hss", "dense"], default="hss")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the run, copy this many MiB device-to-device once (a plain copy "
+                         "kernel of known size, to scale HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         return 2
+    if args.calib_copy_mib > 0:
+        import torch
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     out, wl = run_hss(args) if args.mode == "hss" else run_dense(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
