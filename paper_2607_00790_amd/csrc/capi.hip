@@ -201,13 +201,11 @@ int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t strea
     if (x == y) return fail(BM_EINVAL, "bm_matvec: x and y must not alias");
     if (p->g->n * ((p->g->n + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_matvec: N too large");
     const int64_t n = p->g->n;
-    double* work = nullptr;
-    BM_HIP(hipMallocAsync(reinterpret_cast<void**>(&work),
-                          matvec_work_doubles(n) * sizeof(double), stream));
-    const hipError_t e = launch_matvec(view(p->g), n, p->media, x, y, work, stream);
-    const hipError_t e2 = hipFreeAsync(work, stream);
+    void* work = nullptr;
+    BM_HIP(dev_alloc(&work, matvec_work_doubles(n) * sizeof(double), stream));
+    const hipError_t e = launch_matvec(view(p->g), n, p->media, x, y, static_cast<double*>(work), stream);
+    dev_free(work, stream);
     if (e != hipSuccess) return hip_fail(e, "bm_matvec");
-    if (e2 != hipSuccess) return hip_fail(e2, "bm_matvec: free");
     return BM_OK;
 }
 

@@ -1,0 +1,84 @@
+// Caching device allocator for the library's temporaries and factors.
+//
+// Driver allocations and frees are slow on this stack (a free costs hundreds
+// of microseconds and synchronises), and one HSS build allocates and releases
+// dozens of buffers per tree level.  Blocks are therefore kept in per-device
+// size-class bins after their first allocation and never returned to the
+// driver.  A freed block is tagged with the stream it was released on and is
+// only handed out again for work on that same stream, so stream order
+// guarantees its previous users have finished.
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace bm {
+
+namespace {
+
+struct CachedBlock {
+    void* p;
+    hipStream_t s;
+};
+
+struct DeviceCache {
+    std::map<size_t, std::vector<CachedBlock>> free_bins;   // size class -> free blocks
+    std::unordered_map<void*, size_t> size_of;        // live and cached blocks
+};
+
+std::mutex g_mu;
+std::unordered_map<int, DeviceCache> g_cache;
+
+size_t size_class(size_t bytes) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t c = size_class(bytes == 0 ? 1 : bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DeviceCache& dc = g_cache[dev];
+        auto it = dc.free_bins.find(c);
+        if (it != dc.free_bins.end()) {
+            std::vector<CachedBlock>& v = it->second;
+            for (size_t i = v.size(); i-- > 0;) {
+                if (v[i].s == s) {
+                    *p = v[i].p;
+                    v.erase(v.begin() + static_cast<std::ptrdiff_t>(i));
+                    return hipSuccess;
+                }
+            }
+        }
+    }
+    e = hipMalloc(p, c);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[dev].size_of[*p] = c;
+    return hipSuccess;
+}
+
+void dev_free(void* p, hipStream_t s) {
+    if (!p) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCache& dc = g_cache[dev];
+    auto it = dc.size_of.find(p);
+    if (it == dc.size_of.end()) return;   // not ours
+    dc.free_bins[it->second].push_back(CachedBlock{p, s});
+}
+
+}  // namespace bm

@@ -21,6 +21,7 @@
 #include <functional>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -44,6 +45,38 @@ struct LevelFactor {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Pinned host staging chunks are expensive to allocate, so they are kept in
+// a process-wide cache and reused by later phases and builds.
+struct PinnedCache {
+    std::mutex mu;
+    std::vector<std::pair<char*, size_t>> free_list;
+    char* get(size_t bytes, size_t* cap) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (size_t i = 0; i < free_list.size(); ++i) {
+                if (free_list[i].second >= bytes) {
+                    char* p = free_list[i].first;
+                    *cap = free_list[i].second;
+                    free_list.erase(free_list.begin() + static_cast<std::ptrdiff_t>(i));
+                    return p;
+                }
+            }
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        *cap = bytes;
+        return static_cast<char*>(p);
+    }
+    void put(char* p, size_t cap) {
+        std::lock_guard<std::mutex> lk(mu);
+        free_list.emplace_back(p, cap);
+    }
+};
+PinnedCache& pinned_cache() {
+    static PinnedCache* c = new PinnedCache;   // never destroyed: pinned memory lives until exit
+    return *c;
+}
+
 // Device temporaries, staged descriptor uploads and recorded stream commands
 // of one phase of the build or solve.  upload() copies a host array into a
 // staging chunk whose device address is known at once; stream work is recorded
@@ -55,9 +88,9 @@ struct Scratch {
     hipStream_t s;
     std::vector<void*> dev;
     struct Chunk {
-        char* d;
-        std::shared_ptr<std::vector<char>> h;
-        size_t used, flushed;
+        char* d;      // device
+        char* h;      // pinned host
+        size_t cap, used, flushed;
     };
     std::vector<Chunk> chunks;
     std::vector<std::function<hipError_t()>> cmds;
@@ -67,15 +100,14 @@ struct Scratch {
     explicit Scratch(hipStream_t st) : s(st) {}
     Scratch(const Scratch&) = delete;
     Scratch& operator=(const Scratch&) = delete;
-    ~Scratch() {
-        if (pending) (void)hipStreamSynchronize(s);
-        release();
-    }
+    ~Scratch() { release(); }
     template <class T>
     hipError_t alloc(T** p, size_t count) {
         *p = nullptr;
-        hipError_t e = hipMallocAsync(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T), s);
-        if (e == hipSuccess) dev.push_back(*p);
+        void* q = nullptr;
+        hipError_t e = dev_alloc(&q, std::max<size_t>(count, 1) * sizeof(T), s);
+        *p = static_cast<T*>(q);
+        if (e == hipSuccess) dev.push_back(q);
         return e;
     }
     template <class T>
@@ -83,16 +115,21 @@ struct Scratch {
         const size_t bytes = std::max<size_t>((v.size() * sizeof(T) + 15) / 16 * 16, 16);
         Chunk* c = nullptr;
         for (Chunk& q : chunks)
-            if (q.h->size() - q.used >= bytes) { c = &q; break; }
+            if (q.cap - q.used >= bytes) { c = &q; break; }
         if (!c) {
-            const size_t cap = std::max(kChunk, bytes);
+            size_t cap = 0;
+            char* hp = pinned_cache().get(std::max(kChunk, bytes), &cap);
+            if (!hp) return hipErrorOutOfMemory;
             char* d = nullptr;
             hipError_t e = alloc(&d, cap);
-            if (e != hipSuccess) return e;
-            chunks.push_back(Chunk{d, std::make_shared<std::vector<char>>(cap), 0, 0});
+            if (e != hipSuccess) {
+                pinned_cache().put(hp, cap);
+                return e;
+            }
+            chunks.push_back(Chunk{d, hp, cap, 0, 0});
             c = &chunks.back();
         }
-        if (!v.empty()) std::memcpy(c->h->data() + c->used, v.data(), v.size() * sizeof(T));
+        if (!v.empty()) std::memcpy(c->h + c->used, v.data(), v.size() * sizeof(T));
         *p = reinterpret_cast<T*>(c->d + c->used);
         c->used += bytes;
         return hipSuccess;
@@ -101,7 +138,7 @@ struct Scratch {
     hipError_t flush() {
         for (Chunk& c : chunks) {
             if (c.used > c.flushed) {
-                hipError_t e = hipMemcpyAsync(c.d + c.flushed, c.h->data() + c.flushed, c.used - c.flushed,
+                hipError_t e = hipMemcpyAsync(c.d + c.flushed, c.h + c.flushed, c.used - c.flushed,
                                               hipMemcpyHostToDevice, s);
                 if (e != hipSuccess) return e;
                 c.flushed = c.used;
@@ -120,10 +157,15 @@ struct Scratch {
     }
     // After a stream synchronisation: staging may be reused.
     void synced() { pending = false; }
+    // Frees are stream-ordered; the pinned chunks go back to the cache only when
+    // no copy from them can still be pending.
     void release() {
         cmds.clear();
-        for (void* p : dev) (void)hipFreeAsync(p, s);
+        if (pending) (void)hipStreamSynchronize(s);
+        pending = false;
+        for (void* p : dev) dev_free(p, s);
         dev.clear();
+        for (Chunk& c : chunks) pinned_cache().put(c.h, c.cap);
         chunks.clear();
     }
 };
@@ -382,6 +424,7 @@ int count_unknowns(const Slot* s, size_t n) {
 
 struct bm_hss {
     const bm_problem* p = nullptr;
+    hipStream_t stream = nullptr;   // build stream: the factors' memory is tied to it
     bm_hss_opts opts{};
     int64_t N = 0;
     int levels = 0;
@@ -394,10 +437,20 @@ struct bm_hss {
 
 namespace {
 
-void free_factor(LevelFactor& f) {
-    (void)hipFree(f.E);
-    (void)hipFree(f.Ft);
-    (void)hipFree(f.G);
+// Persistent buffers come from the caching allocator on the build stream and
+// go back to it on that stream.
+template <class T>
+hipError_t palloc(T** p, int64_t count, hipStream_t s) {
+    void* q = nullptr;
+    hipError_t e = dev_alloc(&q, static_cast<size_t>(std::max<int64_t>(count, 1)) * sizeof(T), s);
+    *p = static_cast<T*>(q);
+    return e;
+}
+
+void free_factor(LevelFactor& f, hipStream_t s) {
+    dev_free(f.E, s);
+    dev_free(f.Ft, s);
+    dev_free(f.G, s);
     f.E = f.Ft = f.G = nullptr;
 }
 
@@ -454,11 +507,10 @@ int build_impl(bm_hss* h, hipStream_t s) {
     const int64_t npts = N + (int64_t{1} << L) * P;
     PointTable pt{};
     double* ptd = nullptr;
-    BM_HIP(hipMalloc(reinterpret_cast<void**>(&ptd), 6 * npts * sizeof(double)));
-    std::unique_ptr<double, void (*)(double*)> ptd_guard(ptd, [](double* q) { (void)hipFree(q); });
+    Scratch persist(s);   // point table: freed (stream-ordered) when the build returns
+    BM_HIP(persist.alloc(&ptd, 6 * npts));
     int32_t* ptc = nullptr;
-    BM_HIP(hipMalloc(reinterpret_cast<void**>(&ptc), npts * sizeof(int32_t)));
-    std::unique_ptr<int32_t, void (*)(int32_t*)> ptc_guard(ptc, [](int32_t* q) { (void)hipFree(q); });
+    BM_HIP(persist.alloc(&ptc, npts));
     pt.x = ptd; pt.y = ptd + npts; pt.nx = ptd + 2 * npts; pt.ny = ptd + 3 * npts;
     pt.w = ptd + 4 * npts; pt.kappa = ptd + 5 * npts; pt.curve = ptc;
     for (int r = 0; r < 6; ++r)
@@ -479,7 +531,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
     std::vector<int64_t> dhat_prev_off;    // offsets per child box
     std::vector<int64_t> k_prev;           // children's ranks
     std::vector<int32_t*> status_bufs;
-    auto cleanup_status = [&]() { for (auto q : status_bufs) (void)hipFree(q); };
+    auto cleanup_status = [&]() { for (auto q : status_bufs) dev_free(q, s); status_bufs.clear(); };
+    std::unique_ptr<Scratch> prev;   // previous level's scratch, released after the next sync
     int64_t entries = 0, pairs = 0, max_rank = 0;
 
     int compressed = 0;
@@ -533,6 +586,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), dcounts, counts.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         sc.synced();
+        prev.reset();
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: near counts"); }
         int64_t total_u = 0;
         for (int b = 0; b < nb; ++b) total_u += n[b];
@@ -650,10 +704,10 @@ int build_impl(bm_hss* h, hipStream_t s) {
         LevelFactor f;
         f.nb = nb; f.n = n; f.k = k; f.uoff = uoff; f.koff = koff; f.nkoff = nkoff; f.nnoff = nnoff;
         f.nu = uoff[nb]; f.nk = koff[nb];
-        e = hipMalloc(reinterpret_cast<void**>(&f.G), std::max<int64_t>(nnoff[nb], 1) * sizeof(double2));
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&f.E), std::max<int64_t>(nkoff[nb], 1) * sizeof(double2));
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&f.Ft), std::max<int64_t>(nkoff[nb], 1) * sizeof(double2));
-        if (e != hipSuccess) { free_factor(f); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factors"); }
+        e = palloc(&f.G, nnoff[nb], s);
+        if (e == hipSuccess) e = palloc(&f.E, nkoff[nb], s);
+        if (e == hipSuccess) e = palloc(&f.Ft, nkoff[nb], s);
+        if (e != hipSuccess) { free_factor(f, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factors"); }
         h->lv.push_back(f);   // owned by h from here on
         LevelFactor& F = h->lv.back();
         jobs.clear();
@@ -688,16 +742,16 @@ int build_impl(bm_hss* h, hipStream_t s) {
         int32_t* piv;
         e = sc.alloc(&Y, nkoff[nb]);
         if (e == hipSuccess) e = sc.alloc(&Wt, nkoff[nb]);
-        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&S), std::max<int64_t>(kkoff[nb], 1) * sizeof(double2), s);
+        if (e == hipSuccess) e = palloc(&S, kkoff[nb], s);
         if (e == hipSuccess) e = sc.alloc(&piv, uoff[nb]);
         int32_t* st = nullptr;
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&st), 2 * nb * sizeof(int32_t));
+        if (e == hipSuccess) e = palloc(&st, 2 * nb, s);
         if (e == hipSuccess) {
             status_bufs.push_back(st);
             sc.rec([=]() { return hipMemsetAsync(st, 0, 2 * nb * sizeof(int32_t), s); });
         }
-        if (e != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor buffers"); }
-        if ((e = t_fac.start(sc, ev)) != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        if (e != hipSuccess) { dev_free(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor buffers"); }
+        if ((e = t_fac.start(sc, ev)) != hipSuccess) { dev_free(S, s); sc.release(); cleanup_status(); return hip_fail(e, "event"); }
         std::vector<InvJob> inv(nb);
         for (int b = 0; b < nb; ++b) inv[b] = InvJob{F.G + nnoff[b], piv + uoff[b], st + b, n[b], static_cast<int32_t>(n[b])};
         e = launch_inverse(sc, inv);
@@ -735,10 +789,10 @@ int build_impl(bm_hss* h, hipStream_t s) {
         }
         if (e == hipSuccess) e = launch_gemm(sc, g4);
         if (e == hipSuccess) e = t_fac.stop(sc, ev);
-        if (e != hipSuccess) { (void)hipFreeAsync(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor"); }
+        if (e != hipSuccess) { dev_free(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor"); }
 
         // ---- next level: U(parent) = J(first child) then J(second child)
-        if (Dhat_prev) (void)hipFreeAsync(Dhat_prev, s);
+        if (Dhat_prev) dev_free(Dhat_prev, s);
         Dhat_prev = S;
         dhat_prev_off.assign(kkoff.begin(), kkoff.end() - 1);
         k_prev = k;
@@ -757,10 +811,13 @@ int build_impl(bm_hss* h, hipStream_t s) {
             U[q].insert(U[q].end(), J[2 * q + 1].begin(), J[2 * q + 1].end());
         }
         e = sc.flush();
-        if (e == hipSuccess) e = hipStreamSynchronize(s);   // the level's temporaries may be released now
-        sc.synced();
-        sc.release();
         if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: level end"); }
+        // keep this level's staging alive until the next synchronisation
+        prev.reset(new Scratch(s));
+        std::swap(prev->dev, sc.dev);
+        std::swap(prev->chunks, sc.chunks);
+        prev->pending = sc.pending;
+        sc.pending = false;
         ++compressed;
     }
 
@@ -779,7 +836,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
         make_slots(Ur, rs);
         Slot* drs;
         hipError_t e = sc.upload(&drs, rs);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->Rinv), std::max<int64_t>(K * K, 1) * sizeof(double2));
+        if (e == hipSuccess) e = palloc(&h->Rinv, K * K, s);
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: root"); }
         std::vector<GenJob> jobs{GenJob{0, 0, 0, K, 1, static_cast<int32_t>(rs.size()), static_cast<int32_t>(rs.size())}};
         entries += K * K;
@@ -800,7 +857,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = launch_copy(sc, copies);
         int32_t *piv, *st;
         if (e == hipSuccess) e = sc.alloc(&piv, K);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&st), sizeof(int32_t));
+        if (e == hipSuccess) e = palloc(&st, 1, s);
         if (e == hipSuccess) {
             status_bufs.push_back(st);
             sc.rec([=]() { return hipMemsetAsync(st, 0, sizeof(int32_t), s); });
@@ -812,15 +869,17 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = sc.flush();
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         sc.synced();
+        prev.reset();
         sc.release();
-        if (Dhat_prev) (void)hipFreeAsync(Dhat_prev, s);
+        if (Dhat_prev) dev_free(Dhat_prev, s);
         if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: root factor"); }
     }
     // ---- statuses of every inversion
     for (size_t q = 0; q < status_bufs.size(); ++q) {
         const int cnt = (q + 1 == status_bufs.size()) ? 1 : 2 * h->lv[q].nb;
         std::vector<int32_t> hs(cnt);
-        hipError_t e = hipMemcpy(hs.data(), status_bufs[q], cnt * sizeof(int32_t), hipMemcpyDeviceToHost);
+        hipError_t e = hipMemcpyAsync(hs.data(), status_bufs[q], cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: status"); }
         for (int32_t v : hs)
             if (v) { cleanup_status(); return fail(BM_ESINGULAR, "bm_hss_build: singular block in the HSS factorisation"); }
@@ -855,6 +914,7 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
     bm_hss* h = new (std::nothrow) bm_hss;
     if (!h) return fail(BM_ENOMEM, "bm_hss_build: host allocation");
     h->p = p;
+    h->stream = stream;
     h->opts = *opts;
     h->N = p->g->n;
     int rc;
@@ -956,8 +1016,10 @@ int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out) {
 
 int bm_hss_destroy(bm_hss* h) {
     if (!h) return BM_OK;
-    for (auto& f : h->lv) free_factor(f);
-    (void)hipFree(h->Rinv);
+    // the blocks return to the allocator tagged with the build stream, so work
+    // still queued on that stream finishes before any reuse
+    for (auto& f : h->lv) free_factor(f, h->stream);
+    dev_free(h->Rinv, h->stream);
     delete h;
     return BM_OK;
 }

@@ -54,6 +54,11 @@ inline NodeView view(const bm_geom* g) {
                     g->soa + 4 * n, g->soa + 5 * n, g->curve};
 }
 
+// Caching device allocator (devmem.hip): blocks are reused only on the stream
+// they were released on.
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
 // Kernel launchers (assemble.hip)
 hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurves, int64_t n,
                            double* soa, int32_t* curve, hipStream_t s);
