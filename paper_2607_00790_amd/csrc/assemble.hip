@@ -54,6 +54,26 @@ __device__ __forceinline__ void store_block(double* __restrict__ out, int64_t ld
     r1[1] = make_double2(b.v[6], b.v[7]);
 }
 
+// Off-diagonal pair written row by row: row 2i needs only the interior (k1)
+// kernels, so it is stored before the exterior (k0) Bessel functions are
+// evaluated and its write overlaps the rest of the arithmetic.
+__device__ __forceinline__ void emit_pair(double* __restrict__ out, int64_t ld, int64_t row,
+                                          int64_t col, double tx, double ty, double tnx, double tny,
+                                          double sx, double sy, double snx, double sny, double sw,
+                                          const Media& m, bool interior) {
+    double2* r0 = reinterpret_cast<double2*>(out) + (2 * row) * ld + 2 * col;
+    double2* r1 = r0 + ld;
+    const PairGeom g = pair_geom(tx, ty, tnx, tny, sx, sy, snx, sny);
+    const KernelParts p1 = pair_interior(g, m, interior);
+    double o[4];
+    pair_row0(p1, sw, m, o);
+    r0[0] = make_double2(o[0], o[1]);
+    r0[1] = make_double2(o[2], o[3]);
+    pair_row1(g, p1, sw, m, interior, o);
+    r1[0] = make_double2(o[0], o[1]);
+    r1[1] = make_double2(o[2], o[3]);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -88,14 +108,12 @@ k_dense(NodeView v, int64_t n, int64_t ntj, Media m, double* __restrict__ A, int
     const int64_t i = blockIdx.x / ntj;
     const int64_t j = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     if (j >= n) return;
-    Block b;
     if (i == j) {
-        b = diag_block(v.w[j], v.kappa[j], m);
+        store_block(A, ld, i, j, diag_block(v.w[j], v.kappa[j], m));
     } else {
-        b = pair_block(v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j], v.w[j],
-                       m, v.curve[i] == v.curve[j]);
+        emit_pair(A, ld, i, j, v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j],
+                  v.w[j], m, v.curve[i] == v.curve[j]);
     }
-    store_block(A, ld, i, j, b);
 }
 
 // Block for node index lists: workgroup b covers row a = b / ntj.
@@ -106,14 +124,12 @@ k_block(NodeView v, Media m, const int64_t* __restrict__ rows, const int64_t* __
     const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     if (c >= nc) return;
     const int64_t i = rows[a], j = cols[c];
-    Block b;
     if (i == j) {
-        b = diag_block(v.w[j], v.kappa[j], m);
+        store_block(out, ld, a, c, diag_block(v.w[j], v.kappa[j], m));
     } else {
-        b = pair_block(v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j], v.w[j],
-                       m, v.curve[i] == v.curve[j]);
+        emit_pair(out, ld, a, c, v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j],
+                  v.w[j], m, v.curve[i] == v.curve[j]);
     }
-    store_block(out, ld, a, c, b);
 }
 
 // Proxy blocks.  dir 0: node targets (rows) x proxy sources (cols);
@@ -137,8 +153,7 @@ k_proxy(NodeView v, Media m, const int64_t* __restrict__ nodes, int64_t n,
         tx = pts[a]; ty = pts[P + a]; tnx = pts[2 * P + a]; tny = pts[3 * P + a];
         sx = v.x[j]; sy = v.y[j]; snx = v.nx[j]; sny = v.ny[j]; sw = v.w[j];
     }
-    const Block b = pair_block(tx, ty, tnx, tny, sx, sy, snx, sny, sw, m, true);
-    store_block(out, ld, a, c, b);
+    emit_pair(out, ld, a, c, tx, ty, tnx, tny, sx, sy, snx, sny, sw, m, true);
 }
 
 __global__ void __launch_bounds__(kThreads)

@@ -2,7 +2,9 @@
 // management and error reporting.  All arithmetic runs in the HIP kernels.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -27,6 +29,32 @@ int hip_fail(hipError_t e, const char* what) {
 void clear_error() { g_last_error.clear(); }
 
 namespace {
+
+// The coefficient table, copied once to every device the library runs on.
+std::mutex g_table_mu;
+std::unordered_map<int, BesselTable*> g_tables;
+
+hipError_t device_table(const BesselTable** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    auto it = g_tables.find(dev);
+    if (it != g_tables.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    BesselTable* d = nullptr;
+    e = hipMalloc(reinterpret_cast<void**>(&d), sizeof(BesselTable));
+    if (e == hipSuccess) e = hipMemcpy(d, &bm_bessel_coef::kTable, sizeof(BesselTable), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return e;
+    }
+    g_tables[dev] = d;
+    *out = d;
+    return hipSuccess;
+}
 
 bool finite_media(const bm_media* m) {
     return std::isfinite(m->k0) && std::isfinite(m->k1) && std::isfinite(m->eps0) &&
@@ -136,10 +164,12 @@ int bm_problem_create(const bm_geom* g, const bm_media* media, bm_problem** out)
     if (!g || !media) return fail(BM_EINVAL, "bm_problem_create: null argument");
     if (!finite_media(media))
         return fail(BM_EINVAL, "bm_problem_create: wavenumbers and permittivities must be finite and > 0");
+    const BesselTable* tab = nullptr;
+    BM_HIP(device_table(&tab));
     bm_problem* p = new (std::nothrow) bm_problem;
     if (!p) return fail(BM_ENOMEM, "bm_problem_create: host allocation");
     p->g = g;
-    p->media = Media{media->k0, media->k1, media->eps0, media->eps1};
+    p->media = make_media(media->k0, media->k1, media->eps0, media->eps1, tab);
     *out = p;
     return BM_OK;
 }

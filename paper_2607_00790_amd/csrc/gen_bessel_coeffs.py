@@ -21,6 +21,13 @@ Region C, z >= ZC (Hankel's large-argument form, A&S 9.2.5-9.2.10 structure).
   P_n and z Q_n are smooth in u = (ZC/z)^2 on [0, 1] and are replaced by their
   least-squares polynomials in u.
 
+Sine and cosine for the large-argument region (Cody and Waite's argument
+reduction): x = k pi/2 + r with pi/2 split into three doubles C1 + C2 + C3,
+C1 and C2 carrying 33 significant bits so that k C1 and k C2 are exact for
+|k| < 2^20; then on |r| <= pi/4
+    sin r = r + r w PS(w),   cos r = 1 - w/2 + w^2 PC(w),   w = r^2,
+with PS, PC least-squares polynomials in w.
+
 The script reports the worst relative error of H0 and H1 (complex, relative to
 |H|) of a float64 Horner evaluation over 0 < z <= 1e4.
 """
@@ -40,6 +47,7 @@ HB = 0.5
 DEG_A = 16
 DEG_B = 11
 DEG_C = 11
+DEG_TRIG = 7
 
 
 def _j(n, z):
@@ -133,6 +141,36 @@ def build():
         eps = mp.mpf("1e-40")
         cs, c, h = lsq_poly(lambda u, n=name: fc(n, u if u > eps else eps), mp.mpf(0), mp.mpf(1), DEG_C)
         tables["C_" + name] = to_monomial(cs, c, h, 0)
+    # sine / cosine on |r| <= pi/4, as polynomials in w = r^2
+    wmax = (mp.pi / 4) ** 2
+    tiny = mp.mpf("1e-30")
+
+    def fsin(w):
+        w = w if w > tiny else tiny
+        r = mp.sqrt(w)
+        return (mp.sin(r) / r - 1) / w
+
+    def fcos(w):
+        w = w if w > tiny else tiny
+        r = mp.sqrt(w)
+        return (mp.cos(r) - 1 + w / 2) / (w * w)
+
+    cs, c, h = lsq_poly(fsin, mp.mpf(0), wmax, DEG_TRIG)
+    tables["T_SIN"] = to_monomial(cs, c, h, 0)
+    cs, c, h = lsq_poly(fcos, mp.mpf(0), wmax, DEG_TRIG)
+    tables["T_COS"] = to_monomial(cs, c, h, 0)
+    # Cody-Waite split of pi/2: C1, C2 with 33 significant bits, C3 the rest
+    half_pi = mp.pi / 2
+
+    def round_bits(x, bits):
+        e = mp.floor(mp.log(abs(x), 2))
+        q = mp.mpf(2) ** (e - bits + 1)
+        return mp.nint(x / q) * q
+
+    c1 = round_bits(half_pi, 33)
+    c2 = round_bits(half_pi - c1, 33)
+    c3 = mp.mpf(float(half_pi - c1 - c2))
+    tables["T_CW"] = [c1, c2, c3]
     return tables
 
 
@@ -144,6 +182,20 @@ def _horner(c, x):
     for a in reversed(c[:-1]):
         acc = acc * x + float(a)
     return acc
+
+
+def model_sincos(t, x):
+    """float64 model of the Cody-Waite sine/cosine used by the kernels."""
+    c1, c2, c3 = (float(v) for v in t["T_CW"])
+    k = np.rint(x * (2 / np.pi))
+    r = ((x - k * c1) - k * c2) - k * c3
+    w = r * r
+    sr = r + r * w * _horner(t["T_SIN"], w)
+    cr = (1.0 - 0.5 * w) + w * w * _horner(t["T_COS"], w)
+    q = k.astype(np.int64) & 3
+    s = np.select([q == 0, q == 1, q == 2, q == 3], [sr, cr, -sr, -cr])
+    c = np.select([q == 0, q == 1, q == 2, q == 3], [cr, -sr, -cr, sr])
+    return s, c
 
 
 def eval_f64(t, z):
@@ -176,7 +228,7 @@ def eval_f64(t, z):
         u = (ZC / zc) ** 2
         amp = np.sqrt(2 / (np.pi * zc))
         # exp(i (z - pi/4)) = (cos z + sin z + i (sin z - cos z)) / sqrt 2
-        cz, sz = np.cos(zc), np.sin(zc)
+        sz, cz = model_sincos(t, zc)
         ph = ((cz + sz) + 1j * (sz - cz)) * np.sqrt(0.5)
         out[0, C] = amp * (_horner(t["C_P0"], u) + 1j * _horner(t["C_Q0"], u) / zc) * ph
         out[1, C] = amp * (_horner(t["C_P1"], u) + 1j * _horner(t["C_Q1"], u) / zc) * ph * (-1j)
@@ -197,10 +249,14 @@ def report(t):
 
 
 def emit(t, path):
-    def arr(name, vals):
-        body = ",\n    ".join(mp.nstr(v, 21, min_fixed=-1, max_fixed=-1).replace("e", "e") for v in vals)
-        return f"constexpr double {name}[{len(vals)}] = {{\n    {body}\n}};\n"
+    def arr(vals):
+        return ",\n        ".join(mp.nstr(v, 21, min_fixed=-1, max_fixed=-1) for v in vals)
 
+    names = ("A_J0", "A_J1", "A_R0", "A_R1", "C_P0", "C_Q0", "C_P1", "C_Q1", "T_SIN", "T_COS", "T_CW")
+    flat = []
+    for row in t["B"]:
+        for f in row:
+            flat.extend(f)
     lines = ["// Generated by gen_bessel_coeffs.py from mpmath (40 digits). Do not edit.",
              "// Polynomial coefficients are listed from degree 0 upwards.",
              "#pragma once", "",
@@ -209,15 +265,21 @@ def emit(t, path):
              f"constexpr double ZC = {ZC!r};   // large-argument region: z >= ZC",
              f"constexpr double HB = {HB!r};   // width of the piecewise intervals in [ZA, ZC)",
              f"constexpr int NB = {len(t['B'])};        // number of intervals",
-             f"constexpr int DB = {DEG_B + 1};       // coefficients per interval polynomial", ""]
-    for name in ("A_J0", "A_J1", "A_R0", "A_R1", "C_P0", "C_Q0", "C_P1", "C_Q1"):
-        lines.append(arr(name, t[name]))
-    flat = []
-    for row in t["B"]:
-        for f in row:
-            flat.extend(f)
-    lines.append("// [interval][J0, Y0, J1, Y1 + 2/(pi z)][coefficient in s = z - centre]")
-    lines.append(arr("B_TAB", flat))
+             f"constexpr int DB = {DEG_B + 1};       // coefficients per interval polynomial",
+             f"constexpr int NA = {DEG_A + 1};       // coefficients of the series-region polynomials",
+             f"constexpr int NC = {DEG_C + 1};       // coefficients of the large-argument polynomials", "",
+             "// All coefficients in one table; kernels read it through a pointer.",
+             "struct Table {"]
+    for name in names:
+        lines.append(f"    double {name}[{len(t[name])}];")
+    lines.append(f"    double B_TAB[{len(flat)}];   // [interval][J0, Y0, J1, Y1 + 2/(pi z)][coefficient in s = z - centre]")
+    lines.append("};")
+    lines.append("")
+    lines.append("constexpr Table kTable = {")
+    for name in names:
+        lines.append(f"    {{{arr(t[name])}}},")
+    lines.append(f"    {{{arr(flat)}}}}};")
+    lines.append("")
     lines.append("}  // namespace bm_bessel_coef")
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -228,6 +290,10 @@ def main():
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bessel_coeffs.h")
     emit(t, out)
     w = report(t)
+    xs = np.linspace(-1e4, 1e4, 200001)
+    sm, cm = model_sincos(t, xs)
+    werr = max(np.max(np.abs(sm - np.sin(xs))), np.max(np.abs(cm - np.cos(xs))))
+    print(f"sine/cosine model on [-1e4, 1e4]: max abs error {werr:.2e}")
     print(f"wrote {out}; float64 model, max relative error of H_n by region:")
     for key in sorted(w):
         print(f"  region {key[0]} H{key[1]}: {w[key]:.2e}")

@@ -10,7 +10,14 @@ extern "C" {
 // out[4*q + {0,1,2,3}] = J0, Y0, J1, Y1 + 2/(pi z) at z[q].
 int bmh_bessel01(const double* z, int64_t n, double* out) {
     for (int64_t q = 0; q < n; ++q)
-        bm::bessel01(z[q], out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+        bm::bessel01(z[q], 1.0 / z[q], &bm_bessel_coef::kTable, out[4 * q], out[4 * q + 1],
+                     out[4 * q + 2], out[4 * q + 3]);
+    return 0;
+}
+
+// out[2*q + {0,1}] = sin, cos of x[q] by the kernels' Cody-Waite routine.
+int bmh_sincos(const double* x, int64_t n, double* out) {
+    for (int64_t q = 0; q < n; ++q) bm::sincos_cw(x[q], &bm_bessel_coef::kTable, out[2 * q], out[2 * q + 1]);
     return 0;
 }
 
@@ -20,7 +27,7 @@ int bmh_bessel01(const double* z, int64_t n, double* out) {
 int bmh_system_blocks(const double* soa, const int32_t* curve, int64_t N, const int64_t* rows,
                       int64_t nr, const int64_t* cols, int64_t nc, const double* media,
                       double* out) {
-    const bm::Media m{media[0], media[1], media[2], media[3]};
+    const bm::Media m = bm::make_media(media[0], media[1], media[2], media[3], &bm_bessel_coef::kTable);
     const double *x = soa, *y = soa + N, *nx = soa + 2 * N, *ny = soa + 3 * N, *w = soa + 4 * N,
                  *kap = soa + 5 * N;
     const int64_t ld = 2 * nc;

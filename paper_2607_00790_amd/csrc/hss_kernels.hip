@@ -233,25 +233,34 @@ k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off
     const Slot ts = slots[jb.tslot + t];
     const Slot ss = slots[jb.sslot + s];
     const int32_t i = ts.pt, j = ss.pt;
-    Block b;
-    if (i == j) {
-        b = diag_block(pt.w[j], pt.kappa[j], m);
-    } else {
-        const int32_t ci = pt.curve[i], cj = pt.curve[j];
-        b = pair_block(pt.x[i], pt.y[i], pt.nx[i], pt.ny[i], pt.x[j], pt.y[j], pt.nx[j], pt.ny[j],
-                       pt.w[j], m, ci == cj || ci < 0 || cj < 0);
-    }
     double2* o = out + jb.out;
-    const int32_t r[2] = {ts.pos0, ts.pos1};
-    const int32_t c[2] = {ss.pos0, ss.pos1};
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        if (r[a] < 0) continue;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            if (c[e] < 0) continue;
-            o[r[a] * jb.rs + c[e] * jb.cs] = make_double2(b.v[4 * a + 2 * e], b.v[4 * a + 2 * e + 1]);
-        }
+    // one row of the 2x2 block (v: re/im of the u and q columns) to the selected columns
+    auto put = [&](int32_t row, const double (&v)[4]) {
+        if (ss.pos0 >= 0) o[row * jb.rs + ss.pos0 * jb.cs] = make_double2(v[0], v[1]);
+        if (ss.pos1 >= 0) o[row * jb.rs + ss.pos1 * jb.cs] = make_double2(v[2], v[3]);
+    };
+    if (i == j) {
+        const Block b = diag_block(pt.w[j], pt.kappa[j], m);
+        if (ts.pos0 >= 0) put(ts.pos0, {b.v[0], b.v[1], b.v[2], b.v[3]});
+        if (ts.pos1 >= 0) put(ts.pos1, {b.v[4], b.v[5], b.v[6], b.v[7]});
+        return;
+    }
+    // Rows are formed separately: row 2i needs only the interior kernels, and
+    // when a skeleton keeps row 2i alone the exterior ones are never evaluated.
+    const int32_t ci = pt.curve[i], cj = pt.curve[j];
+    const bool interior = ci == cj || ci < 0 || cj < 0;
+    const double sw = pt.w[j];
+    const PairGeom g = pair_geom(pt.x[i], pt.y[i], pt.nx[i], pt.ny[i], pt.x[j], pt.y[j], pt.nx[j],
+                                 pt.ny[j]);
+    const KernelParts p1 = pair_interior(g, m, interior);
+    double v[4];
+    if (ts.pos0 >= 0) {
+        pair_row0(p1, sw, m, v);
+        put(ts.pos0, v);
+    }
+    if (ts.pos1 >= 0) {
+        pair_row1(g, p1, sw, m, interior, v);
+        put(ts.pos1, v);
     }
 }
 

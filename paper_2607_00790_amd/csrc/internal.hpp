@@ -6,7 +6,7 @@
 #include <cstdint>
 #include <string>
 
-#include "../../include/bmhss.h"
+#include "bmhss.h"
 #include "wsbm_pair.hpp"
 
 // Device node data of a discretised boundary: six FP64 rows of length n

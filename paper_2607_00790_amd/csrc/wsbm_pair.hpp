@@ -33,7 +33,13 @@ namespace bm {
 
 struct Media {
     double k0, k1, eps0, eps1;
+    double ik0, ik1;              // 1/k0, 1/k1
+    const BesselTable* tab;       // Bessel / sine-cosine coefficients (device memory in kernels)
 };
+
+inline Media make_media(double k0, double k1, double eps0, double eps1, const BesselTable* tab) {
+    return Media{k0, k1, eps0, eps1, 1.0 / k0, 1.0 / k1, tab};
+}
 
 // Output: blk[0..7] = re/im of A(2i,2j), A(2i,2j+1), A(2i+1,2j), A(2i+1,2j+1).
 struct Block {
@@ -48,12 +54,13 @@ struct KernelParts {
     double nr_re, nr_im;   // Nr_k (regular part of N_k)
 };
 
-__host__ __device__ __forceinline__ KernelParts kernel_parts(double k, double r, double ir, double ar,
-                                                            double br, double cr, double abr2) {
+__host__ __device__ __forceinline__ KernelParts kernel_parts(double k, double ik, double r, double ir,
+                                                            double ar, double br, double cr, double abr2,
+                                                            const BesselTable* __restrict__ tab) {
     const double z = k * r;
+    const double iz = ir * ik;                      // 1/z
     double j0, y0, j1, y1r;
-    bessel01(z, j0, y0, j1, y1r);
-    const double iz = ir / k;                       // 1/z
+    bessel01(z, iz, tab, j0, y0, j1, y1r);
     const double y1 = y1r - kTwoOverPi * iz;        // Y1
     KernelParts p;
     p.s_re = -0.25 * y0;
@@ -74,46 +81,80 @@ __host__ __device__ __forceinline__ KernelParts kernel_parts(double k, double r,
     return p;
 }
 
-// Off-diagonal block (the points must not coincide).
-__host__ __device__ __forceinline__ Block pair_block(double tx, double ty, double tnx, double tny,
-                                                     double sx, double sy, double snx, double sny,
-                                                     double sw, const Media& m, bool interior) {
+// Geometry of one off-diagonal pair (the points must not coincide).
+struct PairGeom {
+    double r, ir, ar, br, cr, abr2;
+};
+
+__host__ __device__ __forceinline__ PairGeom pair_geom(double tx, double ty, double tnx, double tny,
+                                                       double sx, double sy, double snx, double sny) {
     const double rx = tx - sx, ry = ty - sy;
     const double r2 = rx * rx + ry * ry;
-    const double r = sqrt(r2);
-    const double ir = 1.0 / r;
+    PairGeom g;
+    g.ir = rsqrt_pos(r2);
+    g.r = r2 * g.ir;
     const double a = rx * tnx + ry * tny;
     const double b = rx * snx + ry * sny;
     const double c = tnx * snx + tny * sny;
-    const double ar = a * ir, br = b * ir, cr = c * ir;
-    const double abr2 = ar * br;
-    const KernelParts p0 = kernel_parts(m.k0, r, ir, ar, br, cr, abr2);
-    double s1_re = 0, s1_im = 0, d1_re = 0, d1_im = 0, ds1_re = 0, ds1_im = 0;
+    g.ar = a * g.ir;
+    g.br = b * g.ir;
+    g.cr = c * g.ir;
+    g.abr2 = g.ar * g.br;
+    return g;
+}
+
+// Interior-medium (k1) parts of a pair; all zero for pairs on different curves.
+__host__ __device__ __forceinline__ KernelParts pair_interior(const PairGeom& g, const Media& m,
+                                                              bool interior) {
+    if (interior) return kernel_parts(m.k1, m.ik1, g.r, g.ir, g.ar, g.br, g.cr, g.abr2, m.tab);
+    return KernelParts{0, 0, 0, 0, 0, 0, 0, 0};
+}
+
+// Row 2i of the block: re/im of A(2i,2j) = D_k1 w_j and A(2i,2j+1) = -eps1 S_k1 w_j.
+__host__ __device__ __forceinline__ void pair_row0(const KernelParts& p1, double sw, const Media& m,
+                                                   double (&o)[4]) {
+    o[0] = sw * p1.d_re;
+    o[1] = sw * p1.d_im;
+    o[2] = -sw * m.eps1 * p1.s_re;
+    o[3] = -sw * m.eps1 * p1.s_im;
+}
+
+// Row 2i+1: A(2i+1,2j) = D_k0 + alpha (N_k0 - N_k1), A(2i+1,2j+1) = -eps0 S_k0 - alpha (eps0 D*_k0 - eps1 D*_k1).
+__host__ __device__ __forceinline__ void pair_row1(const PairGeom& g, const KernelParts& p1, double sw,
+                                                   const Media& m, bool interior, double (&o)[4]) {
+    const KernelParts p0 = kernel_parts(m.k0, m.ik0, g.r, g.ir, g.ar, g.br, g.cr, g.abr2, m.tab);
     double nd_re, nd_im;
     if (interior) {
-        const KernelParts p1 = kernel_parts(m.k1, r, ir, ar, br, cr, abr2);
-        s1_re = p1.s_re; s1_im = p1.s_im;
-        d1_re = p1.d_re; d1_im = p1.d_im;
-        ds1_re = p1.ds_re; ds1_im = p1.ds_im;
         nd_re = p0.nr_re - p1.nr_re;
         nd_im = p0.nr_im - p1.nr_im;
     } else {
         // N_k0 alone: add back the k-independent singular parts
-        nd_re = p0.nr_re + (0.5 / kPi) * cr * ir - (1.0 / kPi) * abr2 * ir * ir;
+        nd_re = p0.nr_re + (0.5 / kPi) * g.cr * g.ir - (1.0 / kPi) * g.abr2 * g.ir * g.ir;
         nd_im = p0.nr_im;
     }
-    const double ik0 = 1.0 / m.k0;   // alpha = i/k0: alpha (x + i y) = (-y + i x)/k0
+    const double ik0 = m.ik0;   // alpha = i/k0: alpha (x + i y) = (-y + i x)/k0
+    o[0] = sw * (p0.d_re - nd_im * ik0);
+    o[1] = sw * (p0.d_im + nd_re * ik0);
+    const double t_re = m.eps0 * p0.ds_re - m.eps1 * p1.ds_re;
+    const double t_im = m.eps0 * p0.ds_im - m.eps1 * p1.ds_im;
+    o[2] = sw * (-m.eps0 * p0.s_re + t_im * ik0);
+    o[3] = sw * (-m.eps0 * p0.s_im - t_re * ik0);
+}
+
+// Whole off-diagonal block (the points must not coincide).
+__host__ __device__ __forceinline__ Block pair_block(double tx, double ty, double tnx, double tny,
+                                                     double sx, double sy, double snx, double sny,
+                                                     double sw, const Media& m, bool interior) {
+    const PairGeom g = pair_geom(tx, ty, tnx, tny, sx, sy, snx, sny);
+    const KernelParts p1 = pair_interior(g, m, interior);
+    double r0[4], r1[4];
+    pair_row0(p1, sw, m, r0);
+    pair_row1(g, p1, sw, m, interior, r1);
     Block o;
-    o.v[0] = sw * d1_re;
-    o.v[1] = sw * d1_im;
-    o.v[2] = -sw * m.eps1 * s1_re;
-    o.v[3] = -sw * m.eps1 * s1_im;
-    o.v[4] = sw * (p0.d_re - nd_im * ik0);
-    o.v[5] = sw * (p0.d_im + nd_re * ik0);
-    const double t_re = m.eps0 * p0.ds_re - m.eps1 * ds1_re;
-    const double t_im = m.eps0 * p0.ds_im - m.eps1 * ds1_im;
-    o.v[6] = sw * (-m.eps0 * p0.s_re + t_im * ik0);
-    o.v[7] = sw * (-m.eps0 * p0.s_im - t_re * ik0);
+    for (int q = 0; q < 4; ++q) {
+        o.v[q] = r0[q];
+        o.v[4 + q] = r1[q];
+    }
     return o;
 }
 
@@ -130,7 +171,7 @@ __host__ __device__ __forceinline__ Block diag_block(double w, double kappa, con
     const double kk0 = m.k0 * m.k0, kk1 = m.k1 * m.k1;
     const double nd_re = -w * inv4pi * (kk0 * (L0 - 0.5) - kk1 * (L1 - 0.5));
     const double nd_im = 0.125 * w * (kk0 - kk1);
-    const double ik0 = 1.0 / m.k0;
+    const double ik0 = m.ik0;
     Block o;
     o.v[0] = dd + 0.5;
     o.v[1] = 0.0;

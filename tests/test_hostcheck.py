@@ -25,6 +25,7 @@ def hc():
     lib = ctypes.CDLL(LIB)
     vp, i64 = ctypes.c_void_p, ctypes.c_int64
     lib.bmh_bessel01.argtypes = [vp, i64, vp]
+    lib.bmh_sincos.argtypes = [vp, i64, vp]
     lib.bmh_system_blocks.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
     return lib
 
@@ -55,6 +56,24 @@ def test_bessel_against_mpmath(hc):
         y1r = float(y1 + 2 / (mp.pi * zm))
         assert abs(got[q, 3] - y1r) <= 4e-15 * abs(h1) + 1e-300
     assert worst < 4e-15, worst
+
+
+def test_sincos_against_mpmath(hc):
+    """The kernels' own sine/cosine (Cody-Waite reduction + polynomials) against
+    40-digit values, over the argument range k r takes (up to 1e4) and near
+    multiples of pi/2, where the reduction must not lose digits."""
+    mp.mp.dps = 40
+    rng = np.random.default_rng(1)
+    near = np.array([k * np.pi / 2 + d for k in (1, 2, 3, 7, 100, 6365) for d in (-1e-9, 0.0, 1e-9)])
+    x = np.concatenate([rng.uniform(-10, 10, 300), rng.uniform(8, 1e4, 600),
+                        np.geomspace(1e-8, 1e4, 200), near, [0.0, np.pi / 4, -np.pi / 4]])
+    out = np.empty((x.size, 2))
+    hc.bmh_sincos(np.ascontiguousarray(x).ctypes.data, x.size, out.ctypes.data)
+    worst = 0.0
+    for q, xx in enumerate(x):
+        xm = mp.mpf(xx)
+        worst = max(worst, abs(out[q, 0] - float(mp.sin(xm))), abs(out[q, 1] - float(mp.cos(xm))))
+    assert worst < 3.5e-16, worst
 
 
 def test_bessel_wronskian(hc):
