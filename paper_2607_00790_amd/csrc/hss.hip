@@ -240,47 +240,19 @@ GemmJob gemm(const double2* a, int64_t a_rs, int64_t a_cs, const double2* b, int
     return g;
 }
 
-// Inversion of a batch of matrices.  Blocks with n <= kGjBase are inverted by
+// Inversion of a batch of matrices.  Blocks with n <= kGjMax are inverted by
 // pivoted Gauss-Jordan, one workgroup each, in a single launch.  Larger
 // matrices are split 2 x 2, [[A, B], [C, D]], and inverted through the Schur
 // complement S = D - C A^-1 B:
 //   X = A^-1 B,  Yt = C A^-1,  B <- -X S^-1,  C <- -S^-1 Yt,  A <- A^-1 - X C,
 // with A^-1 and S^-1 found recursively (batched over the whole batch at each
 // recursion stage).  Pivoting is within the Gauss-Jordan blocks only.
-// Largest block inverted by the LDS-resident Gauss-Jordan kernel on this
-// device (from its per-workgroup LDS limit); 0 falls back to the global-memory
-// kernel with blocks of kGjBaseGlobal.
-constexpr int kGjBaseGlobal = 128;
-
-int gj_lds_base() {
-    static int cached = -1;
-    if (cached >= 0) return cached;
-    int dev = 0, lds = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        lds = 0;
-    const size_t budget = lds > 2048 ? static_cast<size_t>(lds) - 1024 : 0;   // static LDS of the kernel
-    int n = 0;
-    while (n < 160 && gj_lds_bytes(n + 1) <= budget) ++n;
-    if (n >= 16 && budget > 65536) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_gauss_jordan_lds),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                static_cast<int>(gj_lds_bytes(n))) != hipSuccess)
-            n = 0;
-    }
-    cached = n >= 16 ? n : 0;
-    (void)hipGetLastError();
-    return cached;
-}
-
 hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
-    const int lds_base = gj_lds_base();
-    const int base_n = lds_base > 0 ? lds_base : kGjBaseGlobal;
     std::vector<InvJob> base, split;
     int nbase = 0;
     for (const InvJob& j : jobs) {
         if (j.n == 0) continue;
-        if (j.n <= base_n) {
+        if (j.n <= kGjMax) {
             base.push_back(j);
             nbase = std::max(nbase, j.n);
         } else {
@@ -293,12 +265,13 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
         if ((e = sc.upload(&dj, base)) != hipSuccess) return e;
         const unsigned nj = static_cast<unsigned>(base.size());
         hipStream_t st = sc.s;
-        const size_t lds = lds_base > 0 ? gj_lds_bytes(nbase) : static_cast<size_t>(nbase) * sizeof(double2);
         sc.rec([=]() {
-            if (lds_base > 0)
-                hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(nj), dim3(kThreads), lds, st, dj);
+            if (nbase <= 32)
+                hipLaunchKernelGGL(k_gauss_jordan_8, dim3(nj), dim3(64), 0, st, dj);
+            else if (nbase <= 64)
+                hipLaunchKernelGGL(k_gauss_jordan_16, dim3(nj), dim3(256), 0, st, dj);
             else
-                hipLaunchKernelGGL(k_gauss_jordan, dim3(nj), dim3(kThreads), lds, st, dj);
+                hipLaunchKernelGGL(k_gauss_jordan_32, dim3(nj), dim3(1024), 0, st, dj);
             return hipGetLastError();
         });
     }
@@ -309,8 +282,8 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
     for (size_t q = 0; q < split.size(); ++q) {
         const InvJob& j = split[q];
         const int n1 = j.n / 2, n2 = j.n - n1;
-        Aj.push_back(InvJob{j.a, j.piv, j.status, j.ld, n1});
-        Sj.push_back(InvJob{j.a + n1 * j.ld + n1, j.piv + n1, j.status, j.ld, n2});
+        Aj.push_back(InvJob{j.a, j.status, j.ld, n1});
+        Sj.push_back(InvJob{j.a + n1 * j.ld + n1, j.status, j.ld, n2});
         xoff[q + 1] = xoff[q] + static_cast<int64_t>(n1) * n2;
     }
     if ((e = launch_inverse(sc, Aj)) != hipSuccess) return e;
@@ -491,6 +464,77 @@ struct EventTimer {
     }
 };
 
+// Second stream of a build: the factorisation of level l runs on it while
+// the compression of level l+1 proceeds on the caller's stream (the ID of a
+// level needs only the skeletons of the level below, not its factors).  The
+// streams are non-blocking, default priority, and kept per device for reuse.
+struct AuxStreams {
+    std::mutex mu;
+    std::vector<std::pair<int, hipStream_t>> free_list;
+    hipError_t get(hipStream_t* out) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (size_t i = 0; i < free_list.size(); ++i)
+                if (free_list[i].first == dev) {
+                    *out = free_list[i].second;
+                    free_list.erase(free_list.begin() + static_cast<std::ptrdiff_t>(i));
+                    return hipSuccess;
+                }
+        }
+        return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
+    }
+    void put(hipStream_t st) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return;
+        std::lock_guard<std::mutex> lk(mu);
+        free_list.emplace_back(dev, st);
+    }
+};
+AuxStreams& aux_streams() {
+    static AuxStreams* a = new AuxStreams;
+    return *a;
+}
+
+// Buffers of a level whose factorisation may still be running on the second
+// stream: the compression scratch (T, slot lists, read by the factorisation)
+// and the factorisation's own temporaries.  Released once `done` has fired.
+struct PendingLevel {
+    std::unique_ptr<Scratch> cmp, fac;
+    hipEvent_t ready = nullptr, done = nullptr;
+};
+
+struct Pipeline {
+    hipStream_t s, s2 = nullptr;
+    std::vector<PendingLevel> pending;
+    explicit Pipeline(hipStream_t st) : s(st) {}
+    // release the levels whose factorisation has completed (all of them if wait)
+    void reap(bool wait) {
+        for (size_t i = 0; i < pending.size();) {
+            PendingLevel& pl = pending[i];
+            bool fin = true;
+            if (pl.done) {
+                const hipError_t q = wait ? hipEventSynchronize(pl.done) : hipEventQuery(pl.done);
+                fin = (q == hipSuccess) || (wait && q != hipErrorNotReady);
+            }
+            if (!fin) { ++i; continue; }
+            if (pl.cmp) { pl.cmp->pending = false; pl.cmp->release(); }
+            if (pl.fac) { pl.fac->pending = false; pl.fac->release(); }
+            if (pl.ready) (void)hipEventDestroy(pl.ready);
+            if (pl.done) (void)hipEventDestroy(pl.done);
+            pending.erase(pending.begin() + static_cast<std::ptrdiff_t>(i));
+        }
+    }
+    ~Pipeline() {
+        if (s2) (void)hipStreamSynchronize(s2);
+        (void)hipStreamSynchronize(s);
+        reap(true);
+        if (s2) aux_streams().put(s2);
+    }
+};
+
 int build_impl(bm_hss* h, hipStream_t s) {
     const bm_problem* p = h->p;
     const bm_geom* g = p->g;
@@ -516,6 +560,11 @@ int build_impl(bm_hss* h, hipStream_t s) {
     for (int r = 0; r < 6; ++r)
         BM_HIP(hipMemcpyAsync(ptd + r * npts, g->soa + r * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     BM_HIP(hipMemcpyAsync(ptc, g->curve, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    // declared after the point table: on every return it first drains both
+    // streams, so the table outlives the factorisation kernels that read it
+    Pipeline pl(s);
+    BM_HIP(aux_streams().get(&pl.s2));
+    const hipStream_t s2 = pl.s2;
 
     // active unknowns per box (global ids), leaves first
     std::vector<std::vector<int32_t>> U(size_t{1} << L);
@@ -531,14 +580,14 @@ int build_impl(bm_hss* h, hipStream_t s) {
     std::vector<int64_t> dhat_prev_off;    // offsets per child box
     std::vector<int64_t> k_prev;           // children's ranks
     std::vector<int32_t*> status_bufs;
-    auto cleanup_status = [&]() { for (auto q : status_bufs) dev_free(q, s); status_bufs.clear(); };
-    std::unique_ptr<Scratch> prev;   // previous level's scratch, released after the next sync
+    auto cleanup_status = [&]() { for (auto q : status_bufs) dev_free(q, s2); status_bufs.clear(); };
     int64_t entries = 0, pairs = 0, max_rank = 0;
 
     int compressed = 0;
     for (int l = L; l >= 1; --l) {
         const int nb = 1 << l;
-        Scratch sc(s);
+        auto scp = std::make_unique<Scratch>(s);   // compression scratch of this level
+        Scratch& sc = *scp;
         // ---- box geometry and proxy points
         std::vector<int64_t> lo(nb), hi(nb);
         for (int b = 0; b < nb; ++b) {
@@ -586,7 +635,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), dcounts, counts.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         sc.synced();
-        prev.reset();
+        pl.reap(false);
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: near counts"); }
         int64_t total_u = 0;
         for (int b = 0; b < nb; ++b) total_u += n[b];
@@ -700,14 +749,35 @@ int build_impl(bm_hss* h, hipStream_t s) {
         }
         if ((e = t_cmp.stop(sc, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
 
+        // ---- hand over to the second stream: everything below reads T, the
+        // slot lists and the point table, and runs concurrently with the next
+        // level's compression on the caller's stream
+        hipEvent_t ready = nullptr, done = nullptr;
+        e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (ready) (void)hipEventDestroy(ready);
+            sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: events");
+        }
+        sc.rec([=]() { return hipEventRecord(ready, s); });
+        e = sc.flush();
+        pl.pending.emplace_back();
+        pl.pending.back().cmp = std::move(scp);
+        pl.pending.back().ready = ready;
+        pl.pending.back().done = done;
+        pl.pending.back().fac = std::make_unique<Scratch>(s2);
+        Scratch& fs = *pl.pending.back().fac;
+        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: compression"); }
+        fs.rec([=]() { return hipStreamWaitEvent(s2, ready, 0); });
+
         // ---- diagonal blocks D_b (become G_b in place)
         LevelFactor f;
         f.nb = nb; f.n = n; f.k = k; f.uoff = uoff; f.koff = koff; f.nkoff = nkoff; f.nnoff = nnoff;
         f.nu = uoff[nb]; f.nk = koff[nb];
-        e = palloc(&f.G, nnoff[nb], s);
-        if (e == hipSuccess) e = palloc(&f.E, nkoff[nb], s);
-        if (e == hipSuccess) e = palloc(&f.Ft, nkoff[nb], s);
-        if (e != hipSuccess) { free_factor(f, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factors"); }
+        e = palloc(&f.G, nnoff[nb], s2);
+        if (e == hipSuccess) e = palloc(&f.E, nkoff[nb], s2);
+        if (e == hipSuccess) e = palloc(&f.Ft, nkoff[nb], s2);
+        if (e != hipSuccess) { free_factor(f, s2); cleanup_status(); return hip_fail(e, "bm_hss_build: factors"); }
         h->lv.push_back(f);   // owned by h from here on
         LevelFactor& F = h->lv.back();
         jobs.clear();
@@ -732,29 +802,28 @@ int build_impl(bm_hss* h, hipStream_t s) {
                                          n[b], 1, static_cast<int32_t>(kb), static_cast<int32_t>(kb)});
             }
         }
-        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->media, F.G);
-        if (e == hipSuccess) e = t_gen.stop(sc, ev);
-        if (e == hipSuccess) e = launch_copy(sc, copies);
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: D blocks"); }
+        if ((e = t_gen.start(fs, ev)) == hipSuccess) e = launch_gen(fs, jobs, dslots, pt, p->media, F.G);
+        if (e == hipSuccess) e = t_gen.stop(fs, ev);
+        if (e == hipSuccess) e = launch_copy(fs, copies);
+        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: D blocks"); }
 
         // ---- Martinsson-Rokhlin factors
         double2 *Y, *Wt, *S;
-        int32_t* piv;
-        e = sc.alloc(&Y, nkoff[nb]);
-        if (e == hipSuccess) e = sc.alloc(&Wt, nkoff[nb]);
-        if (e == hipSuccess) e = palloc(&S, kkoff[nb], s);
-        if (e == hipSuccess) e = sc.alloc(&piv, uoff[nb]);
+        S = nullptr;
+        e = fs.alloc(&Y, nkoff[nb]);
+        if (e == hipSuccess) e = fs.alloc(&Wt, nkoff[nb]);
+        if (e == hipSuccess) e = palloc(&S, kkoff[nb], s2);
         int32_t* st = nullptr;
-        if (e == hipSuccess) e = palloc(&st, 2 * nb, s);
+        if (e == hipSuccess) e = palloc(&st, 2 * nb, s2);
         if (e == hipSuccess) {
             status_bufs.push_back(st);
-            sc.rec([=]() { return hipMemsetAsync(st, 0, 2 * nb * sizeof(int32_t), s); });
+            fs.rec([=]() { return hipMemsetAsync(st, 0, 2 * nb * sizeof(int32_t), s2); });
         }
-        if (e != hipSuccess) { dev_free(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor buffers"); }
-        if ((e = t_fac.start(sc, ev)) != hipSuccess) { dev_free(S, s); sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        if (e != hipSuccess) { dev_free(S, s2); cleanup_status(); return hip_fail(e, "bm_hss_build: factor buffers"); }
+        if ((e = t_fac.start(fs, ev)) != hipSuccess) { dev_free(S, s2); cleanup_status(); return hip_fail(e, "event"); }
         std::vector<InvJob> inv(nb);
-        for (int b = 0; b < nb; ++b) inv[b] = InvJob{F.G + nnoff[b], piv + uoff[b], st + b, n[b], static_cast<int32_t>(n[b])};
-        e = launch_inverse(sc, inv);
+        for (int b = 0; b < nb; ++b) inv[b] = InvJob{F.G + nnoff[b], st + b, n[b], static_cast<int32_t>(n[b])};
+        e = launch_inverse(fs, inv);
         std::vector<GemmJob> g1, g2, g3, g4;
         const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
         for (int b = 0; b < nb; ++b) {
@@ -765,34 +834,38 @@ int build_impl(bm_hss* h, hipStream_t s) {
             g1.push_back(gemm(Di, nn, 1, Tb, kk, 1, Y + nkoff[b], kk, 1, nn, kk, nn));
             g1.push_back(gemm(Tb, 1, kk, Di, nn, 1, Wt + nkoff[b], nn, 1, kk, nn, nn));
         }
-        if (e == hipSuccess) e = launch_gemm(sc, g1);
+        if (e == hipSuccess) e = launch_gemm(fs, g1);
         for (int b = 0; b < nb; ++b) {
             const int64_t nn = n[b], kk = k[b];
             // S = Wt T (k x k)
             g2.push_back(gemm(Wt + nkoff[b], nn, 1, T + nkoff[b], kk, 1, S + kkoff[b], kk, 1, kk, kk, nn));
         }
-        if (e == hipSuccess) e = launch_gemm(sc, g2);
+        if (e == hipSuccess) e = launch_gemm(fs, g2);
         std::vector<InvJob> inv2(nb);
-        for (int b = 0; b < nb; ++b) inv2[b] = InvJob{S + kkoff[b], piv + uoff[b], st + nb + b, k[b], static_cast<int32_t>(k[b])};
-        if (e == hipSuccess) e = launch_inverse(sc, inv2);
+        for (int b = 0; b < nb; ++b) inv2[b] = InvJob{S + kkoff[b], st + nb + b, k[b], static_cast<int32_t>(k[b])};
+        if (e == hipSuccess) e = launch_inverse(fs, inv2);
         for (int b = 0; b < nb; ++b) {
             const int64_t nn = n[b], kk = k[b];
             // E = Y Dhat (n x k); Ft = Dhat Wt (k x n)
             g3.push_back(gemm(Y + nkoff[b], kk, 1, S + kkoff[b], kk, 1, F.E + nkoff[b], kk, 1, nn, kk, kk));
             g3.push_back(gemm(S + kkoff[b], kk, 1, Wt + nkoff[b], nn, 1, F.Ft + nkoff[b], nn, 1, kk, nn, kk));
         }
-        if (e == hipSuccess) e = launch_gemm(sc, g3);
+        if (e == hipSuccess) e = launch_gemm(fs, g3);
         for (int b = 0; b < nb; ++b) {
             const int64_t nn = n[b], kk = k[b];
             // G = D^-1 - E Wt (in place)
             g4.push_back(gemm(F.E + nkoff[b], kk, 1, Wt + nkoff[b], nn, 1, F.G + nnoff[b], nn, 1, nn, nn, kk, mone, one));
         }
-        if (e == hipSuccess) e = launch_gemm(sc, g4);
-        if (e == hipSuccess) e = t_fac.stop(sc, ev);
-        if (e != hipSuccess) { dev_free(S, s); sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: factor"); }
+        if (e == hipSuccess) e = launch_gemm(fs, g4);
+        if (e == hipSuccess) e = t_fac.stop(fs, ev);
+        if (e == hipSuccess) {
+            fs.rec([=]() { return hipEventRecord(done, s2); });
+            e = fs.flush();
+        }
+        if (e != hipSuccess) { dev_free(S, s2); cleanup_status(); return hip_fail(e, "bm_hss_build: factor"); }
 
         // ---- next level: U(parent) = J(first child) then J(second child)
-        if (Dhat_prev) dev_free(Dhat_prev, s);
+        if (Dhat_prev) dev_free(Dhat_prev, s2);   // its last reader is already on s2
         Dhat_prev = S;
         dhat_prev_off.assign(kkoff.begin(), kkoff.end() - 1);
         k_prev = k;
@@ -810,20 +883,18 @@ int build_impl(bm_hss* h, hipStream_t s) {
             split_slots[q] = static_cast<int64_t>(tmp.size());
             U[q].insert(U[q].end(), J[2 * q + 1].begin(), J[2 * q + 1].end());
         }
-        e = sc.flush();
-        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: level end"); }
-        // keep this level's staging alive until the next synchronisation
-        prev.reset(new Scratch(s));
-        std::swap(prev->dev, sc.dev);
-        std::swap(prev->chunks, sc.chunks);
-        prev->pending = sc.pending;
-        sc.pending = false;
         ++compressed;
     }
 
-    // ---- root: the reduced system over the current active unknowns
+    // ---- root: the reduced system over the current active unknowns, on the
+    // second stream after the last compression
     {
-        Scratch sc(s);
+        hipEvent_t rready = nullptr;
+        BM_HIP(hipEventCreateWithFlags(&rready, hipEventDisableTiming));
+        const hipError_t er = hipEventRecord(rready, s);
+        if (er != hipSuccess) { (void)hipEventDestroy(rready); cleanup_status(); return hip_fail(er, "bm_hss_build: root"); }
+        Scratch sc(s2);
+        sc.rec([=]() { return hipStreamWaitEvent(s2, rready, 0); });
         std::vector<int32_t> Ur;
         std::vector<int64_t> boff;   // start of each current box in Ur
         for (auto& u : U) {
@@ -836,8 +907,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
         make_slots(Ur, rs);
         Slot* drs;
         hipError_t e = sc.upload(&drs, rs);
-        if (e == hipSuccess) e = palloc(&h->Rinv, K * K, s);
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: root"); }
+        if (e == hipSuccess) e = palloc(&h->Rinv, K * K, s2);
+        if (e != hipSuccess) { sc.release(); (void)hipEventDestroy(rready); cleanup_status(); return hip_fail(e, "bm_hss_build: root"); }
         std::vector<GenJob> jobs{GenJob{0, 0, 0, K, 1, static_cast<int32_t>(rs.size()), static_cast<int32_t>(rs.size())}};
         entries += K * K;
         pairs += static_cast<int64_t>(rs.size()) * rs.size();
@@ -855,23 +926,23 @@ int build_impl(bm_hss* h, hipStream_t s) {
             }
         }
         if (e == hipSuccess) e = launch_copy(sc, copies);
-        int32_t *piv, *st;
-        if (e == hipSuccess) e = sc.alloc(&piv, K);
-        if (e == hipSuccess) e = palloc(&st, 1, s);
+        int32_t* st = nullptr;
+        if (e == hipSuccess) e = palloc(&st, 1, s2);
         if (e == hipSuccess) {
             status_bufs.push_back(st);
-            sc.rec([=]() { return hipMemsetAsync(st, 0, sizeof(int32_t), s); });
+            sc.rec([=]() { return hipMemsetAsync(st, 0, sizeof(int32_t), s2); });
         }
         if (e == hipSuccess && (e = t_fac.start(sc, ev)) == hipSuccess) {
-            e = launch_inverse(sc, {InvJob{h->Rinv, piv, st, K, static_cast<int32_t>(K)}});
+            e = launch_inverse(sc, {InvJob{h->Rinv, st, K, static_cast<int32_t>(K)}});
             if (e == hipSuccess) e = t_fac.stop(sc, ev);
         }
         if (e == hipSuccess) e = sc.flush();
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s2);
         sc.synced();
-        prev.reset();
         sc.release();
-        if (Dhat_prev) dev_free(Dhat_prev, s);
+        (void)hipEventDestroy(rready);
+        pl.reap(true);
+        if (Dhat_prev) dev_free(Dhat_prev, s2);
         if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: root factor"); }
     }
     // ---- statuses of every inversion

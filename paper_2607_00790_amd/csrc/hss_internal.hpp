@@ -66,7 +66,6 @@ struct CpqrJob {
 
 struct InvJob {
     double2* a;       // n x n, row-major with leading dimension ld, inverted in place
-    int32_t* piv;     // n
     int32_t* status;  // set to 1 on a zero pivot (caller zeroes it)
     int64_t ld;
     int32_t n;
@@ -101,12 +100,11 @@ __global__ void k_gen_jobs(const GenJob* jobs, const int64_t* tile_off, int njob
                            const Slot* slots, PointTable pt, Media m, double2* out);
 __global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
                          double2* Tbuf);
-__global__ void k_gauss_jordan(const InvJob* jobs);
-__global__ void k_gauss_jordan_lds(const InvJob* jobs);
-// bytes of dynamic LDS k_gauss_jordan_lds needs for an n x n block
-inline size_t gj_lds_bytes(int n) {
-    return (static_cast<size_t>(n) * (n + 1) + n) * sizeof(double2) + static_cast<size_t>(n) * sizeof(int);
-}
+// in-place inverse of n x n blocks, n <= 32 / 64 / 128; blockDim 64 / 256 / 1024
+__global__ void k_gauss_jordan_8(const InvJob* jobs);
+__global__ void k_gauss_jordan_16(const InvJob* jobs);
+__global__ void k_gauss_jordan_32(const InvJob* jobs);
+constexpr int kGjMax = 128;
 __global__ void k_cpqr_init(const CpqrJob* jobs);
 __global__ void k_cpqr_step(const CpqrJob* jobs, int k, double tol);
 __global__ void k_cpqr_finish(const CpqrJob* jobs);

@@ -11,8 +11,8 @@
 //                    level, one launch per elimination step, with the relative
 //                    rank rule |R_kk| > tol |R_00|
 //   k_interp         T_b = [I; (R11^-1 R12)^T] in pivoted order
-//   k_gauss_jordan*  batched in-place inverse with row pivoting (LDS-resident
-//                    for blocks that fit)
+//   k_gauss_jordan_* batched in-place inverse with partial row pivoting, the
+//                    block held in registers (4 x 4 complex tile per thread)
 //   k_gemm           batched strided complex GEMM
 #include "hss_internal.hpp"
 
@@ -450,190 +450,180 @@ k_interp(const CpqrJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
 }
 
 // ---------------------------------------------------------------------------
-// Batched in-place inverse by Gauss-Jordan elimination with row pivoting; one
-// workgroup per matrix (row-major, leading dimension ld).  A zero pivot sets
-// the job's status flag.  Used for blocks of moderate size; larger matrices
-// are reduced to such blocks by 2 x 2 block (Schur complement) recursion on
-// the host side.
-__global__ void __launch_bounds__(kThreads)
-k_gauss_jordan(const InvJob* __restrict__ jobs) {
-    extern __shared__ __attribute__((aligned(16))) double dyn_lds[];
-    double2* col = reinterpret_cast<double2*>(dyn_lds);   // n entries: saved pivot column
-    __shared__ double sv[kThreads / 64];
-    __shared__ int si[kThreads / 64];
-    const InvJob jb = jobs[blockIdx.x];
-    const int n = jb.n;
-    const int64_t ld = jb.ld;
-    double2* A = jb.a;
-    int32_t* piv = jb.piv;
-    int bad = 0;
-    for (int k = 0; k < n; ++k) {
-        double bv = -1;
-        int bi = n;
-        for (int i = k + threadIdx.x; i < n; i += kThreads) {
-            const double v = cabs2(A[i * ld + k]);
-            if (v > bv) { bv = v; bi = i; }
-        }
-        block_argmax(bv, bi, sv, si);
-        if (!(bv > 0)) { bad = 1; break; }
-        const int p = bi;
-        if (threadIdx.x == 0) piv[k] = p;
-        if (p != k) {
-            for (int j = threadIdx.x; j < n; j += kThreads) {
-                const double2 t = A[k * ld + j];
-                A[k * ld + j] = A[p * ld + j];
-                A[p * ld + j] = t;
-            }
-        }
-        __syncthreads();
-        const double2 d = A[k * ld + k];
-        const double dd = cabs2(d);
-        const double2 inv = make_double2(d.x / dd, -d.y / dd);
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kThreads) {
-            col[i] = A[i * ld + k];
-            A[i * ld + k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
-        }
-        __syncthreads();
-        for (int j = threadIdx.x; j < n; j += kThreads) A[k * ld + j] = cmul(A[k * ld + j], inv);
-        __syncthreads();
-        // one wave per row, lanes along the row (coalesced)
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-        for (int i = wid; i < n; i += kThreads / 64) {
-            if (i == k) continue;
-            const double2 f = col[i];
-            if (f.x == 0.0 && f.y == 0.0) continue;
-            double2* ri = A + i * ld;
-            const double2* rk = A + k * ld;
-            for (int j = lane; j < n; j += 64) {
-                const double2 r = rk[j];
-                double2 a = ri[j];
-                a.x -= f.x * r.x - f.y * r.y;
-                a.y -= f.x * r.y + f.y * r.x;
-                ri[j] = a;
-            }
-        }
-        __syncthreads();
-    }
-    if (!bad) {
-        for (int k = n - 1; k >= 0; --k) {
-            const int p = piv[k];
-            if (p != k) {
-                for (int i = threadIdx.x; i < n; i += kThreads) {
-                    const double2 t = A[i * ld + k];
-                    A[i * ld + k] = A[i * ld + p];
-                    A[i * ld + p] = t;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    if (threadIdx.x == 0 && bad) *jb.status = 1;
+// Batched in-place inverse by Gauss-Jordan elimination with partial row
+// pivoting, one workgroup of TG x TG threads per matrix (n <= 4 TG, row-major,
+// leading dimension ld).  Thread (ty, tx) keeps the 4 x 4 complex tile of rows
+// 4ty.., columns 4tx.. in registers for the whole elimination; a step moves
+// one column (for the pivot search and the multipliers) and the pivot row
+// through LDS, with two barriers.
+//
+// Pivoting is logical: rows stay in place, every wave finds the same pivot
+// from the same column copy and keeps the same mask of used rows, and the
+// permutation is applied on the way out.  With p_k the pivot row of step k the
+// in-place result S satisfies  A^-1[k][p_j] = S[p_k][j].  The pivot is the
+// unused row of largest |a_ik|^2, compared with the last 7 bits of its binary
+// representation replaced by the row index, so that magnitudes within a
+// relative 2^-45 count as ties and ties go to the lowest row.  A zero or
+// non-finite pivot sets the job's status flag and leaves the block unspecified.
+namespace {
+
+// Maximum over the wave of an unsigned 64-bit key, by DPP row shifts and row
+// broadcasts (no LDS traffic); the result is wave-uniform.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp_max_step(uint64_t key) {
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(key), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(key >> 32), CTRL, ROW_MASK, 0xF, false);
+    const uint64_t o = (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+    return o > key ? o : key;
 }
 
-// LDS-resident variant for blocks that fit the workgroup's LDS: the matrix is
-// staged with a padded row stride (n + 1), the pivot search runs in wave 0
-// without block barriers, and every elimination step touches LDS only.
-__global__ void __launch_bounds__(kThreads)
-k_gauss_jordan_lds(const InvJob* __restrict__ jobs) {
-    extern __shared__ __attribute__((aligned(16))) double dyn_lds[];
-    __shared__ int sh_piv;
-    const InvJob jb = jobs[blockIdx.x];
-    const int n = jb.n, sn = n + 1;
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t key) {
+    key = dpp_max_step<0x111, 0xF>(key);   // row_shr:1
+    key = dpp_max_step<0x112, 0xF>(key);   // row_shr:2
+    key = dpp_max_step<0x114, 0xF>(key);   // row_shr:4
+    key = dpp_max_step<0x118, 0xF>(key);   // row_shr:8   -> lane 15 of each row: row maximum
+    key = dpp_max_step<0x142, 0xA>(key);   // row_bcast:15 -> lanes 31, 63: two rows each
+    key = dpp_max_step<0x143, 0xC>(key);   // row_bcast:31 -> lane 63: all four rows
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(key), 63);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(key >> 32), 63);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+template <int TG>
+__device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
+    constexpr int NMAX = 4 * TG;
+    constexpr int NWORD = (NMAX + 63) / 64;
+    static_assert(NMAX <= 128, "row index must fit the 7 low key bits");
+    __shared__ double2 colbuf[2][NMAX];
+    __shared__ double2 urow[NMAX];
+    __shared__ int perm[NMAX], pinv[NMAX];
+    const int n = jb.n;
     const int64_t ld = jb.ld;
-    double2* S = reinterpret_cast<double2*>(dyn_lds);   // n x (n+1)
-    double2* col = S + n * sn;                           // n
-    int* piv = reinterpret_cast<int*>(col + n);          // n
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
-    for (int i = wid; i < n; i += nw)
-        for (int j = lane; j < n; j += 64) S[i * sn + j] = jb.a[i * ld + j];
+    const int tid = threadIdx.x, ty = tid / TG, tx = tid % TG, lane = tid & 63;
+    const int r0 = 4 * ty, c0 = 4 * tx;
+    double2 S[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = r0 + r, j = c0 + c;
+            S[r][c] = (i < n && j < n) ? jb.a[i * ld + j] : make_double2(0.0, 0.0);
+        }
+    if (tx == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) colbuf[0][r0 + r] = S[r][0];
+    }
     __syncthreads();
-    int bad = 0;
+    uint64_t used[NWORD];
+#pragma unroll
+    for (int q = 0; q < NWORD; ++q) used[q] = 0;
     for (int k = 0; k < n; ++k) {
-        if (wid == 0) {
-            double bv = -1;
-            int bi = n;
-            for (int i = k + lane; i < n; i += 64) {
-                const double v = cabs2(S[i * sn + k]);
-                if (v > bv) { bv = v; bi = i; }
+        const double2* col = colbuf[k & 1];
+        uint64_t key = 0;
+        double2 cv[NWORD];
+#pragma unroll
+        for (int q = 0; q < NWORD; ++q) {
+            const int i = lane + 64 * q;
+            cv[q] = i < n ? col[i] : make_double2(0.0, 0.0);
+            if (i < n && !((used[q] >> lane) & 1)) {
+                const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(cabs2(cv[q])));
+                const uint64_t kq = (bits & ~0x7Full) | static_cast<uint64_t>(0x7F - i);
+                key = kq > key ? kq : key;
+            }
+        }
+        key = wave_max_u64(key);
+        const int p = 0x7F - static_cast<int>(key & 0x7F);
+        // the pivot row, unscaled, to LDS first: its readers scale it, so the
+        // reciprocal of the pivot is off the path to the barrier
+        const int rp = p - r0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (r == rp) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) urow[c0 + c] = S[r][c];
+            }
+        // pivot value from the lane that loaded it
+        double2 pv = cv[0];
+#pragma unroll
+        for (int q = 1; q < NWORD; ++q)
+            if ((p >> 6) == q) pv = cv[q];
+        pv.x = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(pv.x), p & 63),
+                                __builtin_amdgcn_readlane(__double2loint(pv.x), p & 63));
+        pv.y = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(pv.y), p & 63),
+                                __builtin_amdgcn_readlane(__double2loint(pv.y), p & 63));
+        const double pd = cabs2(pv);
+        if ((key >> 7) == 0 || !(pd > 0.0) || !(pd < INFINITY)) {
+            if (tid == 0) *jb.status = 1;
+            return;   // key and pd are the same in every wave: the whole workgroup leaves
+        }
+        used[p >> 6] |= 1ull << (p & 63);
+        const double rpd = recip(pd);
+        const double2 inv = make_double2(pv.x * rpd, -pv.y * rpd);
+        if (tid == 0) {
+            perm[k] = p;
+            pinv[p] = k;
+        }
+        __syncthreads();
+        // multipliers f (column k) and the scaled pivot row u; u[k] = 1/pivot
+        double2 f[4], u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f[q] = col[r0 + q];
+            u[q] = (c0 + q == k) ? inv : cmul(urow[c0 + q], inv);
+        }
+        const int ck = k - c0, cn = k + 1 - c0;
+        // update the tile column by column (column k becomes -f inv); the
+        // owners of column k+1 publish it as soon as it is done, so that its
+        // LDS write overlaps the rest of the update
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c == ck) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) S[r][c] = make_double2(0.0, 0.0);
             }
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(bv, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            for (int r = 0; r < 4; ++r) {
+                S[r][c].x = fma(-f[r].x, u[c].x, fma(f[r].y, u[c].y, S[r][c].x));
+                S[r][c].y = fma(-f[r].x, u[c].y, fma(-f[r].y, u[c].x, S[r][c].y));
             }
-            if (lane == 0) sh_piv = bv > 0 ? bi : -1;
-        }
-        __syncthreads();
-        const int p = sh_piv;
-        if (p < 0) { bad = 1; break; }
-        if (threadIdx.x == 0) piv[k] = p;
-        if (p != k) {
-            for (int j = threadIdx.x; j < n; j += kThreads) {
-                const double2 t = S[k * sn + j];
-                S[k * sn + j] = S[p * sn + j];
-                S[p * sn + j] = t;
-            }
-        }
-        __syncthreads();
-        const double2 d = S[k * sn + k];
-        const double dd = cabs2(d);
-        const double2 inv = make_double2(d.x / dd, -d.y / dd);
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kThreads) {
-            col[i] = S[i * sn + k];
-            S[i * sn + k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
-        }
-        __syncthreads();
-        for (int j = threadIdx.x; j < n; j += kThreads) S[k * sn + j] = cmul(S[k * sn + j], inv);
-        __syncthreads();
-        // rows k' = wid + nw*t, columns lane and lane + 64 (n <= 128): row k is
-        // held in registers and four rows are loaded before any is stored
-        const bool c1 = lane + 64 < n;
-        const double2 r0 = lane < n ? S[k * sn + lane] : make_double2(0.0, 0.0);
-        const double2 r1 = c1 ? S[k * sn + lane + 64] : make_double2(0.0, 0.0);
-        for (int i0 = wid; i0 < n; i0 += 4 * nw) {
-            double2 a0[4], a1[4], f[4];
+            if (c == cn) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + q * nw;
-                f[q] = (i < n && i != k) ? col[i] : make_double2(0.0, 0.0);
-                a0[q] = (i < n && lane < n) ? S[i * sn + lane] : make_double2(0.0, 0.0);
-                a1[q] = (i < n && c1) ? S[i * sn + lane + 64] : make_double2(0.0, 0.0);
-            }
+                for (int r = 0; r < 4; ++r)
+                    if (r == rp) S[r][c] = u[c];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + q * nw;
-                if (i >= n || i == k) continue;
-                a0[q].x -= f[q].x * r0.x - f[q].y * r0.y;
-                a0[q].y -= f[q].x * r0.y + f[q].y * r0.x;
-                a1[q].x -= f[q].x * r1.x - f[q].y * r1.y;
-                a1[q].y -= f[q].x * r1.y + f[q].y * r1.x;
-                if (lane < n) S[i * sn + lane] = a0[q];
-                if (c1) S[i * sn + lane + 64] = a1[q];
+                for (int r = 0; r < 4; ++r) colbuf[(k + 1) & 1][r0 + r] = S[r][c];
             }
         }
-        __syncthreads();
-    }
-    if (bad) {
-        if (threadIdx.x == 0) *jb.status = 1;
-        return;
-    }
-    // undo the row interchanges on the columns, then write back
-    for (int k = n - 1; k >= 0; --k) {
-        const int p = piv[k];
-        if (p != k) {
-            for (int i = threadIdx.x; i < n; i += kThreads) {
-                const double2 t = S[i * sn + k];
-                S[i * sn + k] = S[i * sn + p];
-                S[i * sn + p] = t;
+        // row p becomes u
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (r == rp) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) S[r][c] = u[c];
             }
-        }
         __syncthreads();
     }
-    for (int i = wid; i < n; i += nw)
-        for (int j = lane; j < n; j += 64) jb.a[i * ld + j] = S[i * sn + j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = r0 + r;
+        if (i >= n) continue;
+        double2* out = jb.a + pinv[i] * ld;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c0 + c < n) out[perm[c0 + c]] = S[r][c];
+    }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(64) k_gauss_jordan_8(const InvJob* __restrict__ jobs) {
+    gauss_jordan_tiles<8>(jobs[blockIdx.x]);
+}
+__global__ void __launch_bounds__(256) k_gauss_jordan_16(const InvJob* __restrict__ jobs) {
+    gauss_jordan_tiles<16>(jobs[blockIdx.x]);
+}
+__global__ void __launch_bounds__(1024) k_gauss_jordan_32(const InvJob* __restrict__ jobs) {
+    gauss_jordan_tiles<32>(jobs[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
