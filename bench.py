@@ -33,6 +33,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TF = 78.6      # MI355X FP64 vector, TFLOP/s
 BYTES_PER_PAIR = 64             # 4 complex128 entries written per (target, source) pair
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (separate
+# runs), scaled by what the same counters read for a plain 1 GiB device copy
+# (FETCH x 2.0, WRITE x 1.0); profiles/pmc_counters_star16384.txt.  Valid for
+# the kernels and workloads those counters were taken on.
+# FP64 operations per pair of the entry kernel, from rocprofv3 --pmc
+# SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 over the dense sweep (FMA counted as 2)
+FLOP_PER_PAIR = 474.1
+MEASURED_TRAFFIC = {
+    "k_cpqr_step": (2.0 * 1.163e7 + 1.715e7) * 1024 / 864,   # one HSS build: 864 launches
+    "k_dense": (2.0 * 5027 + 1.678e7) * 1024,                # one sweep: one launch
+}
 
 
 def cpu_baseline(wl, rows: int = 256):
@@ -80,6 +91,7 @@ def run_dense(args):
     pairs = n * n
     entries = 4 * pairs
     gbs = BYTES_PER_PAIR * pairs / (ms * 1e-3) / 1e9
+    tf = FLOP_PER_PAIR * pairs / (ms * 1e-3) / 1e12
     out = {
         "metric": "Gentries/s Burton-Miller blocks (frac FP64 peak); HSS build+solve s at N=16384",
         "value": entries / (ms * 1e-3) / 1e9,
@@ -91,8 +103,11 @@ def run_dense(args):
         "config": {"workload": f"dense WSBM sweep, {wl.name}", "n_nodes": n, "pairs": pairs,
                    "entries": entries, "theta_inc": wl.theta_inc},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_dense",
-                     "avg_launch_ms": ms},
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get("k_dense"),
+                     "kernel": "k_dense", "avg_launch_ms": ms,
+                     "algorithmic_bytes_per_launch": BYTES_PER_PAIR * pairs},
+        "fp64": {"flop_per_pair": FLOP_PER_PAIR, "tflops": tf, "peak_tflops": FP64_VECTOR_PEAK_TF,
+                 "frac": tf / FP64_VECTOR_PEAK_TF},
     }
     return out, wl
 
@@ -110,12 +125,17 @@ def run_hss(args):
     b = torch.empty(2 * wl.n, dtype=torch.complex128, device="cuda")
     x = torch.empty_like(b)
 
+    levels = []
+
     def step():
         h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio,
-                            proxy_points=wl.proxy_points, id_tol=wl.id_tol)
+                            proxy_points=wl.proxy_points, id_tol=wl.id_tol, sketch=args.sketch)
         bm.bm_rhs_plane_wave(p, wl.theta_inc, out=b)
         bm.bm_hss_solve(h, b, out=x)
-        return bm.bm_hss_stats(h)
+        st = bm.bm_hss_stats(h)
+        if not levels:
+            levels.extend(bm.bm_hss_level(h, l) for l in range(st["compressed_levels"]))
+        return st
 
     for _ in range(args.warmup):
         step()
@@ -132,9 +152,18 @@ def run_hss(args):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
     st = stats[-1]
-    gen_s = sum(q["seconds_generate"] for q in stats) / len(stats)
+
+    def avg(key):
+        return sum(q[key] for q in stats) / len(stats)
+
+    gen_s = avg("seconds_generate")
     entries = st["entries"]
-    gen_gbs = 16 * entries / gen_s / 1e9
+    # dominant kernel of the step: the CPQR step kernel of the ID
+    launches = st["cpqr_launches"]
+    cq_s = avg("seconds_cpqr")
+    cq_bytes = st["cpqr_bytes"]
+    cq_gbs = cq_bytes / cq_s / 1e9
+    traffic = MEASURED_TRAFFIC.get("k_cpqr_step") if args.sketch == 0 else None
     out = {
         "metric": "Gentries/s Burton-Miller blocks (frac FP64 peak); HSS build+solve s at N=16384",
         "value": entries / (ms * 1e-3) / 1e9,
@@ -145,17 +174,24 @@ def run_hss(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"HSS build+solve, {wl.name}", "n_nodes": wl.n, "leaf": wl.leaf,
                    "proxy_points": wl.proxy_points, "proxy_ratio": wl.proxy_ratio,
-                   "id_tol": wl.id_tol, "theta_inc": wl.theta_inc},
+                   "id_tol": wl.id_tol, "theta_inc": wl.theta_inc,
+                   "id": "cpqr" if args.sketch == 0 else f"gaussian sketch, unknowns+{args.sketch} rows"},
         "hss_build_solve_s": ms * 1e-3,
         "hss": {"entries": entries, "pairs": st["pairs"], "levels": st["levels"],
                 "compressed_levels": st["compressed_levels"], "root_size": st["root_size"],
                 "max_rank": st["max_rank"],
+                "seconds_build_wall": avg("seconds_total"),
                 "seconds_generate": gen_s,
-                "seconds_compress": sum(q["seconds_compress"] for q in stats) / len(stats),
-                "seconds_factor": sum(q["seconds_factor"] for q in stats) / len(stats),
-                "generation_Gentries_s": entries / gen_s / 1e9},
-        "roofline": {"bound": "hbm", "achieved": gen_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gen_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_gen_jobs"},
+                "seconds_compress": avg("seconds_compress"),
+                "seconds_cpqr": cq_s,
+                "seconds_factor": avg("seconds_factor"),
+                "generation_Gentries_s": entries / gen_s / 1e9,
+                "per_level": levels},
+        "roofline": {"bound": "hbm", "achieved": cq_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": cq_gbs / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "k_cpqr_step",
+                     "launches": launches, "algorithmic_bytes_per_launch": cq_bytes / launches,
+                     "avg_launch_ms": cq_s / launches * 1e3},
     }
     return out, wl
 
@@ -166,6 +202,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", choices=["hss", "dense"], default="hss")
+    ap.add_argument("--sketch", type=int, default=0,
+                    help="HSS: p > 0 runs the ID on a Gaussian sketch with unknowns + p rows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device once (a plain copy "

@@ -124,7 +124,8 @@ int bm_far_field(const bm_problem* p, const double* phi, const double* angles, i
  * with the near boxes (other boxes' active unknowns inside its proxy circle)
  * and with `proxy_points` pseudo-nodes on a circle of radius
  * proxy_ratio * (box radius).  The ID is column-pivoted QR with relative
- * tolerance id_tol; skeletons are sets of unknowns shared by rows and columns.
+ * tolerance id_tol, of the stacked matrix or of a random sketch of it (opts
+ * sketch); skeletons are sets of unknowns shared by rows and columns.
  * The factorisation is the Martinsson-Rokhlin recursion: per box
  * Dhat = (T^T D^-1 T)^-1, E = D^-1 T Dhat, F^T = Dhat T^T D^-1,
  * G = D^-1 - D^-1 T Dhat T^T D^-1, and a dense LU at the root. */
@@ -133,6 +134,9 @@ typedef struct {
     double proxy_ratio;    /* proxy circle radius / box radius (> 1) */
     int64_t proxy_points;  /* points per proxy circle (>= 8) */
     double id_tol;         /* relative ID tolerance (0 < tol < 1) */
+    int64_t sketch;        /* 0: CPQR of each box's stacked near/proxy matrix;
+                              p > 0: CPQR of a Gaussian sketch of it with
+                              min(rows, unknowns + p) rows (randomized ID) */
 } bm_hss_opts;
 
 typedef struct {
@@ -147,6 +151,14 @@ typedef struct {
     double seconds_compress;   /* time in the ID kernels (HIP events) */
     double seconds_factor;     /* time in inversion and GEMM kernels (HIP events) */
     double seconds_total;      /* wall time of bm_hss_build */
+    /* the step-wise CPQR (the ID): launches of its step kernel, the bytes each
+     * executed step must move at least (the trailing columns read and written
+     * once, the Householder column and the column norms), and the time from
+     * the first to the last step launch of every level (HIP events on the
+     * build stream, so launch gaps are included) */
+    int64_t cpqr_launches;
+    double cpqr_bytes;
+    double seconds_cpqr;
 } bm_hss_stats_t;
 
 /* Build the factorisation; synchronises `stream` once per level to read the
@@ -159,6 +171,20 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
  * stream. */
 int bm_hss_solve(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t stream);
 int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out);
+
+/* Per compressed level (0 = leaves, up to compressed_levels - 1): sizes of the
+ * ID problems and the ranks found.  EINVAL for a level out of range. */
+typedef struct {
+    int32_t boxes;          /* boxes on the level */
+    int32_t max_unknowns;   /* largest box: active unknowns (columns of the ID) */
+    int32_t max_rows;       /* largest stacked matrix: near + proxy rows per box */
+    int32_t id_rows;        /* rows the CPQR ran on (max over boxes): the sketch
+                               height, or max_rows without a sketch */
+    int32_t min_rank;       /* smallest and largest skeleton, in unknowns */
+    int32_t max_rank;
+} bm_hss_level_t;
+int bm_hss_level(const bm_hss* h, int level, bm_hss_level_t* out);
+
 int bm_hss_destroy(bm_hss* h);
 
 

@@ -24,6 +24,7 @@ from ._binding import (  # noqa: F401
     bm_hss_build,
     bm_hss_solve,
     bm_hss_stats,
+    bm_hss_level,
     lib_path,
     load,
 )

@@ -28,7 +28,7 @@ class _Media(ctypes.Structure):
 
 class _HssOpts(ctypes.Structure):
     _fields_ = [("leaf", c_i64), ("proxy_ratio", c_dbl), ("proxy_points", c_i64),
-                ("id_tol", c_dbl)]
+                ("id_tol", c_dbl), ("sketch", c_i64)]
 
 
 class _HssStats(ctypes.Structure):
@@ -36,7 +36,14 @@ class _HssStats(ctypes.Structure):
                 ("root_size", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("max_rank", c_i64), ("entries", c_i64), ("pairs", c_i64),
                 ("seconds_generate", c_dbl), ("seconds_compress", c_dbl),
-                ("seconds_factor", c_dbl), ("seconds_total", c_dbl)]
+                ("seconds_factor", c_dbl), ("seconds_total", c_dbl),
+                ("cpqr_launches", c_i64), ("cpqr_bytes", c_dbl), ("seconds_cpqr", c_dbl)]
+
+
+class _HssLevel(ctypes.Structure):
+    _fields_ = [("boxes", ctypes.c_int32), ("max_unknowns", ctypes.c_int32),
+                ("max_rows", ctypes.c_int32), ("id_rows", ctypes.c_int32),
+                ("min_rank", ctypes.c_int32), ("max_rank", ctypes.c_int32)]
 
 
 def lib_path() -> str:
@@ -73,6 +80,7 @@ def load():
         "bm_hss_build": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssOpts), c_vp, ctypes.POINTER(c_vp)]),
         "bm_hss_solve": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp]),
         "bm_hss_stats": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssStats)]),
+        "bm_hss_level": (ctypes.c_int, [c_vp, ctypes.c_int, ctypes.POINTER(_HssLevel)]),
         "bm_hss_destroy": (ctypes.c_int, [c_vp]),
     })
     for name, (res, args) in sig.items():
@@ -268,8 +276,10 @@ def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
 
 
 def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10,
-                 stream=None) -> HSS:
-    opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol))
+                 sketch=0, stream=None) -> HSS:
+    """sketch = p > 0: run the ID on a Gaussian sketch of each box's stacked
+    matrix with (unknowns + p) rows, when that is fewer than the matrix has."""
+    opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol), int(sketch))
     out = c_vp()
     _check(_LIB.bm_hss_build(p._h, ctypes.byref(opts), _stream(stream), ctypes.byref(out)))
     return HSS(out, p)
@@ -290,3 +300,10 @@ def bm_hss_stats(h: HSS) -> dict:
     s = _HssStats()
     _check(_LIB.bm_hss_stats(h._h, ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in _HssStats._fields_}
+
+
+def bm_hss_level(h: HSS, level: int) -> dict:
+    """Sizes and ranks of compressed level `level` (0 = leaves)."""
+    s = _HssLevel()
+    _check(_LIB.bm_hss_level(h._h, int(level), ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in _HssLevel._fields_}

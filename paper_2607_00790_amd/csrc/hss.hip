@@ -17,12 +17,14 @@
 // near counts and the ranks once per level to size the next buffers.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cstring>
 #include <functional>
 #include <cmath>
 #include <memory>
 #include <mutex>
 #include <new>
+#include <random>
 #include <vector>
 
 #include "hss_internal.hpp"
@@ -229,6 +231,70 @@ hipError_t launch_copy(Scratch& sc, const std::vector<CopyJob>& jobs) {
     return hipSuccess;
 }
 
+// The sketching matrix: one real Gaussian matrix per device (fixed seed),
+// regenerated larger when a level needs more rows or columns.  Replaced
+// buffers are kept, since queued work may still read them.
+struct OmegaCache {
+    struct Entry { int dev; double* p; int64_t rows, cols; };
+    std::mutex mu;
+    std::vector<Entry> bufs;
+};
+OmegaCache& omega_cache() {
+    static OmegaCache* c = new OmegaCache;
+    return *c;
+}
+
+hipError_t omega_device(int64_t rows, int64_t cols, const double** out, int64_t* ld) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    OmegaCache& oc = omega_cache();
+    std::lock_guard<std::mutex> lk(oc.mu);
+    for (auto it = oc.bufs.rbegin(); it != oc.bufs.rend(); ++it)
+        if (it->dev == dev && it->rows >= rows && it->cols >= cols) {
+            *out = it->p;
+            *ld = it->cols;
+            return hipSuccess;
+        }
+    const int64_t R = std::max<int64_t>(rows, 512), C = std::max<int64_t>(cols, 2048);
+    std::vector<double> hbuf(static_cast<size_t>(R * C));
+    std::mt19937_64 gen(0x5eedULL + static_cast<uint64_t>(R) * 7919 + static_cast<uint64_t>(C));
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (double& v : hbuf) v = nd(gen);
+    double* d = nullptr;
+    e = hipMalloc(reinterpret_cast<void**>(&d), hbuf.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(d, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return e;
+    }
+    oc.bufs.push_back(OmegaCache::Entry{dev, d, R, C});
+    *out = d;
+    *ld = C;
+    return hipSuccess;
+}
+
+hipError_t launch_sketch(Scratch& sc, const std::vector<SketchJob>& jobs, const double* omega, int64_t ldo) {
+    if (jobs.empty()) return hipSuccess;
+    std::vector<int64_t> toff(jobs.size() + 1, 0);
+    for (size_t j = 0; j < jobs.size(); ++j)
+        toff[j + 1] = toff[j] + ceil_div(jobs[j].l, 64) * ceil_div(jobs[j].n, 64);
+    if (toff.back() == 0) return hipSuccess;
+    SketchJob* dj;
+    int64_t* dt;
+    hipError_t e = sc.upload(&dj, jobs);
+    if (e == hipSuccess) e = sc.upload(&dt, toff);
+    if (e != hipSuccess) return e;
+    const unsigned grid = static_cast<unsigned>(toff.back());
+    const int nj = static_cast<int>(jobs.size());
+    hipStream_t st = sc.s;
+    sc.rec([=]() {
+        hipLaunchKernelGGL(k_sketch, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, omega, ldo);
+        return hipGetLastError();
+    });
+    return hipSuccess;
+}
+
 GemmJob gemm(const double2* a, int64_t a_rs, int64_t a_cs, const double2* b, int64_t b_rs,
              int64_t b_cs, double2* c, int64_t c_rs, int64_t c_cs, int64_t M, int64_t N, int64_t K,
              double2 alpha = make_double2(1.0, 0.0), double2 beta = make_double2(0.0, 0.0)) {
@@ -313,7 +379,8 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
 // Column-pivoted QR of every box of a level, step-wise over many workgroups
 // per box; ranks[] is copied back (the caller synchronises).
 hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, int32_t* dranks,
-                    double tol, std::vector<int32_t>& ranks) {
+                    double tol, std::vector<int32_t>& ranks, hipEvent_t ev0, hipEvent_t ev1,
+                    int64_t* launches) {
     const int nb = static_cast<int>(cj.size());
     int nmax = 0, kmax = 0;
     for (const CpqrJob& j : cj) {
@@ -343,8 +410,10 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
     if ((e = sc.flush()) != hipSuccess) return e;
     const unsigned chunks = static_cast<unsigned>(ceil_div(std::max(nmax, 1), kThreads / 64));
     hipLaunchKernelGGL(k_cpqr_init, dim3(chunks, nb), dim3(kThreads), 0, sc.s, dcj);
+    if ((e = hipEventRecord(ev0, sc.s)) != hipSuccess) return e;
     for (int k = 0; k <= kmax; ++k) {
         hipLaunchKernelGGL(k_cpqr_step, dim3(chunks, nb), dim3(kThreads), 0, sc.s, dcj, k, tol);
+        ++*launches;
         if (k % 32 == 31 && k < kmax) {
             int32_t h_active = 1;
             hipLaunchKernelGGL(k_cpqr_ranks, dim3(1), dim3(64), 0, sc.s, dcj, nb, dranks, active);
@@ -355,6 +424,7 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
             if (h_active == 0) break;
         }
     }
+    if ((e = hipEventRecord(ev1, sc.s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cpqr_finish, dim3(nb), dim3(kThreads), 0, sc.s, dcj);
     hipLaunchKernelGGL(k_cpqr_ranks, dim3(1), dim3(64), 0, sc.s, dcj, nb, dranks, active);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -406,6 +476,7 @@ struct bm_hss {
     double2* Rinv = nullptr;
     std::vector<int64_t> root_off; // not used by the solve; kept for stats
     bm_hss_stats_t stats{};
+    std::vector<bm_hss_level_t> level_info;   // per compressed level, leaves first
 };
 
 namespace {
@@ -581,7 +652,18 @@ int build_impl(bm_hss* h, hipStream_t s) {
     std::vector<int64_t> k_prev;           // children's ranks
     std::vector<int32_t*> status_bufs;
     auto cleanup_status = [&]() { for (auto q : status_bufs) dev_free(q, s2); status_bufs.clear(); };
-    int64_t entries = 0, pairs = 0, max_rank = 0;
+    int64_t entries = 0, pairs = 0, max_rank = 0, cpqr_launches = 0;
+    double cpqr_bytes = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> cpqr_events;
+    struct EventPairs {   // destroyed on every return
+        std::vector<std::pair<hipEvent_t, hipEvent_t>>& v;
+        ~EventPairs() {
+            for (auto& pr : v) {
+                if (pr.first) (void)hipEventDestroy(pr.first);
+                if (pr.second) (void)hipEventDestroy(pr.second);
+            }
+        }
+    } cpqr_events_guard{cpqr_events};
 
     int compressed = 0;
     for (int l = L; l >= 1; --l) {
@@ -699,7 +781,41 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = t_gen.stop(sc, ev);
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: generate M"); }
 
-        // ---- ID: CPQR of M_b^T
+        // ---- optional sketch: Y_b = Omega M_b^T with min(rows, unknowns + p)
+        // rows; the CPQR and the interpolation matrix then come from Y_b
+        // (randomized ID).  The p extra rows keep Omega well conditioned on the
+        // column space of M_b^T even when a box is close to full rank.
+        std::vector<int64_t> idm(m), yo(nb + 1, 0);
+        double2* Y_sk = nullptr;
+        if (h->opts.sketch) {
+            int64_t lmax = 0, mmax = 0;
+            for (int b = 0; b < nb; ++b) {
+                idm[b] = std::min(m[b], n[b] + h->opts.sketch);
+                yo[b + 1] = yo[b] + idm[b] * n[b];
+                lmax = std::max(lmax, idm[b]);
+                mmax = std::max(mmax, m[b]);
+            }
+            if (yo[nb] < mo[nb]) {
+                const double* omega = nullptr;
+                int64_t ldo = 0;
+                e = omega_device(lmax, mmax, &omega, &ldo);
+                if (e == hipSuccess) e = sc.alloc(&Y_sk, yo[nb]);
+                std::vector<SketchJob> sj(nb);
+                for (int b = 0; b < nb; ++b)
+                    sj[b] = SketchJob{M + mo[b], Y_sk + yo[b], static_cast<int32_t>(m[b]),
+                                      static_cast<int32_t>(n[b]), static_cast<int32_t>(idm[b])};
+                if (e == hipSuccess && (e = t_cmp.start(sc, ev)) == hipSuccess) {
+                    e = launch_sketch(sc, sj, omega, ldo);
+                    if (e == hipSuccess) e = t_cmp.stop(sc, ev);
+                }
+                if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: sketch"); }
+            } else {
+                idm = m;
+                Y_sk = nullptr;
+            }
+        }
+
+        // ---- ID: CPQR of M_b^T (or of its sketch)
         std::vector<int64_t> uoff(nb + 1, 0);
         for (int b = 0; b < nb; ++b) uoff[b + 1] = uoff[b] + n[b];
         int32_t *dperm, *dranks;
@@ -709,17 +825,51 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = sc.alloc(&dranks, nb);
         std::vector<CpqrJob> cj(nb);
         for (int b = 0; b < nb; ++b)
-            cj[b] = CpqrJob{M + mo[b], dperm + uoff[b], drdiag + uoff[b], nullptr, nullptr, nullptr,
-                            static_cast<int32_t>(n[b]), static_cast<int32_t>(m[b])};
+            cj[b] = CpqrJob{Y_sk ? Y_sk + yo[b] : M + mo[b], dperm + uoff[b], drdiag + uoff[b], nullptr,
+                            nullptr, nullptr, static_cast<int32_t>(n[b]),
+                            static_cast<int32_t>(Y_sk ? idm[b] : m[b])};
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: cpqr setup"); }
         if ((e = t_cmp.start(sc, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
         CpqrJob* dcj = nullptr;
         std::vector<int32_t> ranks(nb), perm(uoff[nb]);
-        e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks);
+        hipEvent_t c0 = nullptr, c1 = nullptr;
+        e = hipEventCreate(&c0);
+        if (e == hipSuccess) e = hipEventCreate(&c1);
+        if (e == hipSuccess) {
+            cpqr_events.emplace_back(c0, c1);
+            e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks, c0, c1, &cpqr_launches);
+        }
         if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         sc.synced();
         if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: cpqr"); }
+        {
+            bm_hss_level_t li{};
+            li.boxes = nb;
+            li.min_rank = INT32_MAX;
+            for (int b = 0; b < nb; ++b) {
+                li.max_unknowns = std::max<int32_t>(li.max_unknowns, static_cast<int32_t>(n[b]));
+                li.max_rows = std::max<int32_t>(li.max_rows, static_cast<int32_t>(m[b]));
+                li.min_rank = std::min<int32_t>(li.min_rank, ranks[b]);
+                li.max_rank = std::max<int32_t>(li.max_rank, ranks[b]);
+            }
+            li.id_rows = 0;
+            for (int b = 0; b < nb; ++b)
+                li.id_rows = std::max<int32_t>(li.id_rows, static_cast<int32_t>(Y_sk ? idm[b] : m[b]));
+            // algorithmic bytes of the executed CPQR steps: at step k the trailing
+            // columns (n - k - 1 of them, rows k..m) are read and written once, the
+            // Householder column (rows k..m) and the n norms are read, and the
+            // trailing norms written; the step that finds the rank reads the norms
+            for (int b = 0; b < nb; ++b) {
+                const double rows = static_cast<double>(Y_sk ? idm[b] : m[b]), cols = static_cast<double>(n[b]);
+                for (int64_t kk = 0; kk < ranks[b]; ++kk) {
+                    const double r = rows - kk, c = cols - kk - 1;
+                    cpqr_bytes += 32.0 * r * c + 16.0 * r + 8.0 * cols + 8.0 * c;
+                }
+                cpqr_bytes += 8.0 * cols;
+            }
+            h->level_info.push_back(li);
+        }
         std::vector<int64_t> k(nb), koff(nb + 1, 0), nkoff(nb + 1, 0), nnoff(nb + 1, 0), kkoff(nb + 1, 0);
         for (int b = 0; b < nb; ++b) {
             k[b] = ranks[b];
@@ -965,6 +1115,14 @@ int build_impl(bm_hss* h, hipStream_t s) {
     h->stats.seconds_generate = t_gen.seconds();
     h->stats.seconds_compress = t_cmp.seconds();
     h->stats.seconds_factor = t_fac.seconds();
+    h->stats.cpqr_launches = cpqr_launches;
+    h->stats.cpqr_bytes = cpqr_bytes;
+    double tcq = 0;
+    for (auto& pr : cpqr_events) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) tcq += ms * 1e-3;
+    }
+    h->stats.seconds_cpqr = tcq;
     return BM_OK;
 }
 
@@ -978,8 +1136,10 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
     *out = nullptr;
     if (!p || !opts) return fail(BM_EINVAL, "bm_hss_build: null argument");
     if (opts->leaf < 4 || !(opts->proxy_ratio > 1.0) || opts->proxy_points < 8 ||
-        !(opts->id_tol > 0.0 && opts->id_tol < 1.0) || !std::isfinite(opts->proxy_ratio))
-        return fail(BM_EINVAL, "bm_hss_build: need leaf >= 4, proxy_ratio > 1, proxy_points >= 8, 0 < id_tol < 1");
+        !(opts->id_tol > 0.0 && opts->id_tol < 1.0) || !std::isfinite(opts->proxy_ratio) ||
+        opts->sketch < 0 || opts->sketch > (int64_t{1} << 20))
+        return fail(BM_EINVAL, "bm_hss_build: need leaf >= 4, proxy_ratio > 1, proxy_points >= 8, "
+                               "0 < id_tol < 1, 0 <= sketch <= 2^20");
     if (p->g->n > (int64_t{1} << 30)) return fail(BM_EINVAL, "bm_hss_build: N too large");
     const auto t0 = std::chrono::steady_clock::now();
     bm_hss* h = new (std::nothrow) bm_hss;
@@ -1082,6 +1242,15 @@ int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out) {
     clear_error();
     if (!h || !out) return fail(BM_EINVAL, "bm_hss_stats: null argument");
     *out = h->stats;
+    return BM_OK;
+}
+
+int bm_hss_level(const bm_hss* h, int level, bm_hss_level_t* out) {
+    clear_error();
+    if (!h || !out) return fail(BM_EINVAL, "bm_hss_level: null argument");
+    if (level < 0 || level >= static_cast<int>(h->level_info.size()))
+        return fail(BM_EINVAL, "bm_hss_level: level out of range");
+    *out = h->level_info[level];
     return BM_OK;
 }
 

@@ -81,6 +81,15 @@ struct GemmJob {
     int32_t M, N, K;
 };
 
+// Y = Omega X for one box: X (m x n, column j at x + j*m), Omega the leading
+// l x m block of a real matrix (row-major, leading dimension ldo), Y (l x n,
+// column j at y + j*l).
+struct SketchJob {
+    const double2* x;
+    double2* y;
+    int32_t m, n, l;
+};
+
 struct CopyJob {
     const double2* src;
     double2* dst;
@@ -111,6 +120,9 @@ __global__ void k_cpqr_finish(const CpqrJob* jobs);
 __global__ void k_cpqr_ranks(const CpqrJob* jobs, int nb, int32_t* ranks, int32_t* active);
 
 __global__ void k_gemm(const GemmJob* jobs, const int64_t* tile_off, int njobs);
+// 64 x 64 tiles of Y per workgroup (kThreads threads)
+__global__ void k_sketch(const SketchJob* jobs, const int64_t* tile_off, int njobs,
+                         const double* omega, int64_t ldo);
 __global__ void k_copy_blocks(const CopyJob* jobs);
 
 }  // namespace hss

@@ -627,6 +627,82 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan_32(const InvJob* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Batched sketch Y = Omega X with a real Omega and complex X (randomized ID:
+// the CPQR then runs on the l x n sketch instead of the m x n stacked matrix).
+// Workgroup: a 64 x 64 tile of one job's Y, K in steps of 16 through LDS;
+// thread t owns rows r0 + (t % 16) + 16a and columns c0 + (t / 16) + 16b
+// (a, b < 4), so consecutive threads write consecutive rows of a column.
+__global__ void __launch_bounds__(kThreads)
+k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
+         const double* __restrict__ omega, int64_t ldo) {
+    constexpr int T = 64, KS = 16;
+    __shared__ double Os[KS][T];
+    __shared__ double2 Xs[KS][T];
+    int lo = 0, hi = njobs;
+    const int64_t tile = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= tile) lo = mid; else hi = mid;
+    }
+    const SketchJob jb = jobs[lo];
+    const int64_t local = tile - tile_off[lo];
+    const int tiles_c = (jb.n + T - 1) / T;
+    const int r0 = static_cast<int>(local / tiles_c) * T;
+    const int c0 = static_cast<int>(local % tiles_c) * T;
+    const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
+    double2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int l0 = 0; l0 < jb.m; l0 += KS) {
+        // Omega tile (64 rows x 16): thread loads rows tid/16 + 16q, column tid%16
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int rr = tid / 16 + 16 * q, kk = tid % 16;
+            const int r = r0 + rr, l = l0 + kk;
+            Os[kk][rr] = (r < jb.l && l < jb.m) ? omega[static_cast<int64_t>(r) * ldo + l] : 0.0;
+        }
+        // X tile (16 x 64 columns): 16 consecutive threads read one column's 16 rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jj = tid / 16 + 16 * q, kk = tid % 16;
+            const int j = c0 + jj, l = l0 + kk;
+            Xs[kk][jj] = (j < jb.n && l < jb.m) ? jb.x[static_cast<int64_t>(j) * jb.m + l]
+                                                : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            double o[4];
+            double2 xv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) o[a] = Os[kk][tr + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) xv[b] = Xs[kk][tc + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    acc[a][b].x = fma(o[a], xv[b].x, acc[a][b].x);
+                    acc[a][b].y = fma(o[a], xv[b].y, acc[a][b].y);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int j = c0 + tc + 16 * b;
+        if (j >= jb.n) continue;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int r = r0 + tr + 16 * a;
+            if (r < jb.l) jb.y[static_cast<int64_t>(j) * jb.l + r] = acc[a][b];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batched strided complex GEMM: C = alpha A B + beta C with element (i, j) of X
 // at X[i*rs + j*cs].  32 x 32 output tile per workgroup, K in steps of 16.
 constexpr int TM = 32, TN = 32, TK = 16;

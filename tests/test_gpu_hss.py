@@ -34,13 +34,17 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_hss_circle_plain_workload(gpu_lib):
+SKETCH = [pytest.param(0, id="cpqr"), pytest.param(128, id="sketch128")]
+
+
+@pytest.mark.parametrize("sketch", SKETCH)
+def test_hss_circle_plain_workload(gpu_lib, sketch):
     import torch
     bm = gpu_lib
-    note("hss: circle N=512, k0=10, n=1.5, leaf 64")
+    note(f"hss: circle N=512, k0=10, n=1.5, leaf 64, sketch={sketch}")
     wl = sc.circle_workload(512)
     p, nd = setup(bm, wl.curves, wl.sizes, wl.media)
-    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
+    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch)
     st = bm.bm_hss_stats(h)
     note(f"  stats {st}")
     assert st["compressed_levels"] >= 1
@@ -55,13 +59,14 @@ def test_hss_circle_plain_workload(gpu_lib):
     assert e_hss <= 2 * e_ora
 
 
-def test_hss_star_multiple_rhs_in_place(gpu_lib):
+@pytest.mark.parametrize("sketch", SKETCH)
+def test_hss_star_multiple_rhs_in_place(gpu_lib, sketch):
     import torch
     bm = gpu_lib
-    note("hss: star N=2048, k0=50, n=1.5, 3 right-hand sides, x aliases b")
+    note(f"hss: star N=2048, k0=50, n=1.5, 3 right-hand sides, x aliases b, sketch={sketch}")
     media = sc.media_from_index(50.0, 1.5)
     p, nd = setup(bm, [sc.star(0.3, 5)], [2048], media)
-    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
+    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch)
     note(f"  stats {bm.bm_hss_stats(h)}")
     angles = [0.0, 1.1, 4.0]
     B = torch.stack([bm.bm_rhs_plane_wave(p, a) for a in angles]).contiguous()
@@ -75,12 +80,13 @@ def test_hss_star_multiple_rhs_in_place(gpu_lib):
         assert rel(X[r], ref) < HSS_BAR, (r, rel(X[r], ref))
 
 
-def test_hss_two_scatterers_ragged_sizes(gpu_lib):
+@pytest.mark.parametrize("sketch", SKETCH)
+def test_hss_two_scatterers_ragged_sizes(gpu_lib, sketch):
     bm = gpu_lib
-    note("hss: two stars N=601+423, k0=20, n=2")
+    note(f"hss: two stars N=601+423, k0=20, n=2, sketch={sketch}")
     media = sc.media_from_index(20.0, 2.0)
     p, nd = setup(bm, [sc.star(0.2, 4), sc.star(0.25, 3, 1.0, (3.0, 0.5))], [601, 423], media)
-    h = bm.bm_hss_build(p, leaf=40, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
+    h = bm.bm_hss_build(p, leaf=40, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch)
     note(f"  stats {bm.bm_hss_stats(h)}")
     b = bm.bm_rhs_plane_wave(p, 0.3)
     x = bm.bm_hss_solve(h, b).cpu().numpy()
@@ -102,17 +108,31 @@ def test_hss_tiny_problem_is_a_dense_solve(gpu_lib):
     assert rel(x, ref) < 1e-12
 
 
-def test_hss_full_size_star_sampled_residual(gpu_lib):
+@pytest.mark.parametrize("sketch", SKETCH)
+def test_hss_full_size_star_sampled_residual(gpu_lib, sketch):
     """Full star workload (N = 16384, k0 = 50, n = 1.5, leaf 64, 64 proxy points,
     tol 1e-10), the configuration the benchmark times: the residual of the HSS
-    solution on sampled rows of the oracle's matrix."""
+    solution on sampled rows of the oracle's matrix, and the per-level sizes."""
     bm = gpu_lib
-    note("hss: star N=16384 (benchmark workload), sampled residual")
+    note(f"hss: star N=16384 (benchmark workload), sampled residual, sketch={sketch}")
     wl = sc.star_workload()
     p, nd = setup(bm, wl.curves, wl.sizes, wl.media)
     h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points,
-                        id_tol=wl.id_tol)
-    note(f"  stats {bm.bm_hss_stats(h)}")
+                        id_tol=wl.id_tol, sketch=sketch)
+    st = bm.bm_hss_stats(h)
+    note(f"  stats {st}")
+    for l in range(st["compressed_levels"]):
+        lv = bm.bm_hss_level(h, l)
+        note(f"  level {l}: {lv}")
+        assert lv["boxes"] == 2 ** (st["levels"] - l)
+        assert 0 < lv["min_rank"] <= lv["max_rank"] <= lv["max_unknowns"]
+        if sketch:
+            assert lv["id_rows"] <= min(lv["max_rows"], lv["max_unknowns"] + sketch)
+        else:
+            assert lv["id_rows"] == lv["max_rows"]
+        assert lv["max_rank"] <= lv["id_rows"]
+    with pytest.raises(bm.BmError):
+        bm.bm_hss_level(h, st["compressed_levels"])
     b = bm.bm_rhs_plane_wave(p, wl.theta_inc)
     x = bm.bm_hss_solve(h, b).cpu().numpy()
     rows = np.arange(0, wl.n, 257)
@@ -130,3 +150,12 @@ def test_hss_rejects_bad_options(gpu_lib):
     for kw in ({"leaf": 2}, {"proxy_ratio": 1.0}, {"proxy_points": 4}, {"id_tol": 0.0}):
         with pytest.raises(bm.BmError):
             bm.bm_hss_build(p, **kw)
+    with pytest.raises(bm.BmError):
+        bm.bm_hss_build(p, sketch=-1)
+    # the same through the C-ABI directly: nothing is built
+    import ctypes
+    from paper_2607_00790_amd import _binding as B
+    opts = B._HssOpts(64, 1.5, 64, 1e-10, -5)
+    out = ctypes.c_void_p()
+    assert B._LIB.bm_hss_build(p._h, ctypes.byref(opts), None, ctypes.byref(out)) == 1
+    assert out.value is None
