@@ -39,7 +39,9 @@ BYTES_PER_PAIR = 64             # 4 complex128 entries written per (target, sour
 # the kernels and workloads those counters were taken on.
 # FP64 operations per pair of the entry kernel, from rocprofv3 --pmc
 # SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 over the dense sweep (FMA counted as 2)
-FLOP_PER_PAIR = 474.1
+FLOP_PER_PAIR = 400.3
+# the same for the generate-and-reduce kernel (entries times x, block sums)
+FLOP_PER_PAIR_MATVEC = 456.3
 MEASURED_TRAFFIC = {
     "k_cpqr_step": (2.0 * 1.163e7 + 1.715e7) * 1024 / 864,   # one HSS build: 864 launches
     "k_dense": (2.0 * 5027 + 1.678e7) * 1024,                # one sweep: one launch
@@ -108,6 +110,54 @@ def run_dense(args):
                      "algorithmic_bytes_per_launch": BYTES_PER_PAIR * pairs},
         "fp64": {"flop_per_pair": FLOP_PER_PAIR, "tflops": tf, "peak_tflops": FP64_VECTOR_PEAK_TF,
                  "frac": tf / FP64_VECTOR_PEAK_TF},
+    }
+    return out, wl
+
+
+def run_matvec(args):
+    """Generate-and-reduce: y = A x with every entry evaluated on the fly and
+    nothing written but y (the entry kernel's arithmetic roof)."""
+    import torch
+    import scatterers as sc
+    import paper_2607_00790_amd as bm
+
+    wl = sc.star_workload()
+    xyd, sizes = wl.xyd()
+    g = bm.bm_geom_create(sizes, torch.from_numpy(xyd).cuda())
+    p = bm.bm_problem_create(g, wl.media.k0, wl.media.k1, wl.media.eps0, wl.media.eps1)
+    n = wl.n
+    x = bm.bm_rhs_plane_wave(p, wl.theta_inc)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        bm.bm_matvec(p, x, out=y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        bm.bm_matvec(p, x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    pairs = n * n
+    entries = 4 * pairs
+    tf = FLOP_PER_PAIR_MATVEC * pairs / (ms * 1e-3) / 1e12
+    out = {
+        "metric": "Gentries/s Burton-Miller blocks (frac FP64 peak); HSS build+solve s at N=16384",
+        "value": entries / (ms * 1e-3) / 1e9,
+        "unit": "Gentries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "wall_s_timed": wall,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"matrix-free y = A x (generate and reduce), {wl.name}", "n_nodes": n,
+                   "pairs": pairs, "entries": entries},
+        "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
+                     "frac": tf / FP64_VECTOR_PEAK_TF, "traffic": None, "kernel": "k_matvec_partial",
+                     "flop_per_pair": FLOP_PER_PAIR_MATVEC, "avg_launch_ms": ms},
     }
     return out, wl
 
@@ -201,7 +251,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["hss", "dense"], default="hss")
+    ap.add_argument("--mode", choices=["hss", "dense", "matvec"], default="hss")
     ap.add_argument("--sketch", type=int, default=0,
                     help="HSS: p > 0 runs the ID on a Gaussian sketch with unknowns + p rows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -220,7 +270,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    out, wl = run_hss(args) if args.mode == "hss" else run_dense(args)
+    out, wl = {"hss": run_hss, "dense": run_dense, "matvec": run_matvec}[args.mode](args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -103,7 +103,7 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV]) {
 
 // Full matrix: workgroup b covers target i = b / ntj and sources
 // [jt*kThreads, (jt+1)*kThreads), jt = b % ntj.
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_dense(NodeView v, int64_t n, int64_t ntj, Media m, double* __restrict__ A, int64_t ld) {
     const int64_t i = blockIdx.x / ntj;
     const int64_t j = (blockIdx.x % ntj) * kThreads + threadIdx.x;
@@ -117,7 +117,7 @@ k_dense(NodeView v, int64_t n, int64_t ntj, Media m, double* __restrict__ A, int
 }
 
 // Block for node index lists: workgroup b covers row a = b / ntj.
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_block(NodeView v, Media m, const int64_t* __restrict__ rows, const int64_t* __restrict__ cols,
         int64_t nc, int64_t ntj, double* __restrict__ out, int64_t ld) {
     const int64_t a = blockIdx.x / ntj;
@@ -170,7 +170,7 @@ k_rhs_plane_wave(NodeView v, int64_t n, Media m, double dx, double dy, double2* 
 
 // y = A x, stage 1: workgroup b covers target i = b / ntj and one source tile;
 // it writes the tile's partial sums of rows 2i, 2i+1 to part[b] (4 doubles).
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_matvec_partial(NodeView v, int64_t n, int64_t ntj, Media m, const double2* __restrict__ x,
                  double4* __restrict__ part) {
     const int64_t i = blockIdx.x / ntj;

@@ -216,7 +216,7 @@ k_near_list(PointTable pt, const Slot* __restrict__ slots, const int32_t* __rest
 // Entry generation for a batch of jobs.  Job j covers nt x ns slot pairs, tiles
 // of kThreads pairs; tile_off is the exclusive prefix sum of the tile counts.
 // One pair per thread, no loop (the Bessel coefficients stay scalar operands).
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
            const Slot* __restrict__ slots, PointTable pt, Media m, double2* __restrict__ out) {
     int lo = 0, hi = njobs;

@@ -31,6 +31,12 @@
 
 namespace bm {
 
+// Minimum waves per SIMD requested for the kernels that evaluate pair blocks
+// (launch bound): the pair arithmetic fits in ~62 VGPRs without spills, and
+// the extra waves hide the store and scalar-load latency of the
+// compute-then-store pattern.
+constexpr int kPairWavesPerSimd = 6;
+
 struct Media {
     double k0, k1, eps0, eps1;
     double ik0, ik1;              // 1/k0, 1/k1
