@@ -77,6 +77,16 @@ int bm_geom_nodes(const bm_geom* g, double* soa, hipStream_t stream);
 
 /* ---- Problem: geometry + media.  The geometry must outlive the problem. ---- */
 int bm_problem_create(const bm_geom* g, const bm_media* media, bm_problem** out);
+/* Several independent scatterers in one problem (the batched workload): the
+ * curves are split into nbodies bodies, body_of_curve[c] (host) giving the
+ * body of curve c; it must run 0, .., 0, 1, .., nbodies - 1 (consecutive curves,
+ * every body at least one curve).  media[b] (host) are body b's media.  The
+ * system is block diagonal: pairs in different bodies are zero blocks, every
+ * body has its own incident field and far field, and the HSS build factors the
+ * bodies as a forest (one tree per body, the levels of all trees batched).
+ * bm_problem_create(g, media) is the one-body case. */
+int bm_problem_create_bodies(const bm_geom* g, int nbodies, const int32_t* body_of_curve,
+                             const bm_media* media, bm_problem** out);
 int bm_problem_destroy(bm_problem* p);
 
 /* ---- Right-hand side of Eq. (3) for a plane wave (Sec. IV) ----
@@ -112,8 +122,10 @@ int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t strea
 
 /* Far field of the scattered field from a solution phi = (u_0, q_0, u_1, ...)
  * (device, 2N complex), at nang observation angles (device FP64); uinf (device,
- * nang complex).  u_sc(x) ~ exp(i k0 |x|)/sqrt(|x|) uinf(x/|x|), from the
- * exterior representation u_sc = D_k0[u] - S_k0[eps0 q] (remark after Eq. (3)). */
+ * nbodies * nang complex, body b's far field at uinf[b * nang + a], each body
+ * about the origin with its own k0).  u_sc(x) ~ exp(i k0 |x|)/sqrt(|x|)
+ * uinf(x/|x|), from the exterior representation u_sc = D_k0[u] - S_k0[eps0 q]
+ * (remark after Eq. (3)). */
 int bm_far_field(const bm_problem* p, const double* phi, const double* angles, int64_t nang,
                  double* uinf, hipStream_t stream);
 

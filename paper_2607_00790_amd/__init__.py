@@ -20,6 +20,7 @@ from ._binding import (  # noqa: F401
     bm_geom_size,
     bm_matvec,
     bm_problem_create,
+    bm_problem_create_bodies,
     bm_rhs_plane_wave,
     bm_hss_build,
     bm_hss_solve,

@@ -68,6 +68,7 @@ def load():
         "bm_geom_nodes": (ctypes.c_int, [c_vp, c_vp, c_vp]),
         "bm_problem_create": (ctypes.c_int, [c_vp, ctypes.POINTER(_Media), ctypes.POINTER(c_vp)]),
         "bm_problem_destroy": (ctypes.c_int, [c_vp]),
+        "bm_problem_create_bodies": (ctypes.c_int, [c_vp, ctypes.c_int, c_vp, c_vp, ctypes.POINTER(c_vp)]),
         "bm_rhs_plane_wave": (ctypes.c_int, [c_vp, c_dbl, c_vp, c_vp]),
         "bm_assemble_dense": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp]),
         "bm_assemble_block": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp]),
@@ -138,10 +139,11 @@ class Geometry:
 class Problem:
     """Handle of a geometry + media (bm_problem); keeps its geometry alive."""
 
-    def __init__(self, handle, geom, media):
+    def __init__(self, handle, geom, media, nbodies=1):
         self._h = handle
         self.geom = geom
         self.media = media
+        self.nbodies = nbodies
 
     @property
     def n(self) -> int:
@@ -208,6 +210,18 @@ def bm_problem_create(g: Geometry, k0, k1, eps0, eps1) -> Problem:
     return Problem(out, g, (float(k0), float(k1), float(eps0), float(eps1)))
 
 
+def bm_problem_create_bodies(g: Geometry, body_of_curve, media) -> Problem:
+    """Independent bodies: body_of_curve[c] = body of curve c (0, .., 0, 1, ..);
+    media = one (k0, k1, eps0, eps1) per body."""
+    load()
+    boc = (ctypes.c_int32 * len(body_of_curve))(*[int(b) for b in body_of_curve])
+    nb = len(media)
+    arr = (_Media * nb)(*[_Media(*(float(v) for v in m)) for m in media])
+    out = c_vp()
+    _check(_LIB.bm_problem_create_bodies(g._h, nb, boc, arr, ctypes.byref(out)))
+    return Problem(out, g, [tuple(float(v) for v in m) for m in media], nbodies=nb)
+
+
 def bm_rhs_plane_wave(p: Problem, angle: float, out=None, stream=None):
     torch = _torch()
     if out is None:
@@ -269,7 +283,7 @@ def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
     torch = _torch()
     angles = angles.to(device="cuda", dtype=torch.float64).contiguous()
     if out is None:
-        out = torch.empty(angles.numel(), dtype=torch.complex128, device="cuda")
+        out = torch.empty(p.nbodies * angles.numel(), dtype=torch.complex128, device="cuda")
     _check(_LIB.bm_far_field(p._h, _dev_ptr(phi, torch.complex128, "phi"), _dev_ptr(angles),
                              angles.numel(), _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
     return out

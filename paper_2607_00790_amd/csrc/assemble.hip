@@ -74,6 +74,19 @@ __device__ __forceinline__ void emit_pair(double* __restrict__ out, int64_t ld, 
     r1[1] = make_double2(o[2], o[3]);
 }
 
+__device__ __forceinline__ int body_of(const NodeView& v, int64_t i) { return v.body ? v.body[i] : 0; }
+
+// Zero 2x2 block (a pair in two different bodies).
+__device__ __forceinline__ void store_zero(double* __restrict__ out, int64_t ld, int64_t row, int64_t col) {
+    double2* r0 = reinterpret_cast<double2*>(out) + (2 * row) * ld + 2 * col;
+    double2* r1 = r0 + ld;
+    const double2 z = make_double2(0.0, 0.0);
+    r0[0] = z;
+    r0[1] = z;
+    r1[0] = z;
+    r1[1] = z;
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -104,11 +117,16 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV]) {
 // Full matrix: workgroup b covers target i = b / ntj and sources
 // [jt*kThreads, (jt+1)*kThreads), jt = b % ntj.
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
-k_dense(NodeView v, int64_t n, int64_t ntj, Media m, double* __restrict__ A, int64_t ld) {
+k_dense(NodeView v, int64_t n, int64_t ntj, const Media* __restrict__ media, double* __restrict__ A,
+        int64_t ld) {
     const int64_t i = blockIdx.x / ntj;
     const int64_t j = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     if (j >= n) return;
-    if (i == j) {
+    const int bi = body_of(v, i);   // wave-uniform: the media come through the scalar cache
+    const Media m = media[bi];
+    if (body_of(v, j) != bi) {
+        store_zero(A, ld, i, j);
+    } else if (i == j) {
         store_block(A, ld, i, j, diag_block(v.w[j], v.kappa[j], m));
     } else {
         emit_pair(A, ld, i, j, v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j],
@@ -118,13 +136,17 @@ k_dense(NodeView v, int64_t n, int64_t ntj, Media m, double* __restrict__ A, int
 
 // Block for node index lists: workgroup b covers row a = b / ntj.
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
-k_block(NodeView v, Media m, const int64_t* __restrict__ rows, const int64_t* __restrict__ cols,
-        int64_t nc, int64_t ntj, double* __restrict__ out, int64_t ld) {
+k_block(NodeView v, const Media* __restrict__ media, const int64_t* __restrict__ rows,
+        const int64_t* __restrict__ cols, int64_t nc, int64_t ntj, double* __restrict__ out, int64_t ld) {
     const int64_t a = blockIdx.x / ntj;
     const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     if (c >= nc) return;
     const int64_t i = rows[a], j = cols[c];
-    if (i == j) {
+    const int bi = body_of(v, i);
+    const Media m = media[bi];
+    if (body_of(v, j) != bi) {
+        store_zero(out, ld, a, c);
+    } else if (i == j) {
         store_block(out, ld, a, c, diag_block(v.w[j], v.kappa[j], m));
     } else {
         emit_pair(out, ld, a, c, v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j],
@@ -135,7 +157,7 @@ k_block(NodeView v, Media m, const int64_t* __restrict__ rows, const int64_t* __
 // Proxy blocks.  dir 0: node targets (rows) x proxy sources (cols);
 // dir 1: proxy targets (rows) x node sources (cols).
 __global__ void __launch_bounds__(kThreads)
-k_proxy(NodeView v, Media m, const int64_t* __restrict__ nodes, int64_t n,
+k_proxy(NodeView v, const Media* __restrict__ media, const int64_t* __restrict__ nodes, int64_t n,
         const double* __restrict__ pts, int64_t P, int dir, int64_t ntj, double* __restrict__ out,
         int64_t ld) {
     const int64_t ncol = dir == 0 ? P : n;
@@ -143,6 +165,8 @@ k_proxy(NodeView v, Media m, const int64_t* __restrict__ nodes, int64_t n,
     const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     if (c >= ncol) return;
     double tx, ty, tnx, tny, sx, sy, snx, sny, sw;
+    // the proxy point takes the media of the node it is paired with
+    const Media m = media[body_of(v, dir == 0 ? nodes[a] : nodes[c])];
     if (dir == 0) {
         const int64_t i = nodes[a];
         tx = v.x[i]; ty = v.y[i]; tnx = v.nx[i]; tny = v.ny[i];
@@ -157,9 +181,11 @@ k_proxy(NodeView v, Media m, const int64_t* __restrict__ nodes, int64_t n,
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_rhs_plane_wave(NodeView v, int64_t n, Media m, double dx, double dy, double2* __restrict__ rhs) {
+k_rhs_plane_wave(NodeView v, int64_t n, const Media* __restrict__ media, double dx, double dy,
+                 double2* __restrict__ rhs) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= n) return;
+    const Media m = media[body_of(v, i)];
     double s, c;
     sincos(m.k0 * (dx * v.x[i] + dy * v.y[i]), &s, &c);
     // -u_in - alpha du_in/dn = -u_in (1 + (i/k0)(i k0 d.n)) = -u_in (1 - d.n)
@@ -171,12 +197,14 @@ k_rhs_plane_wave(NodeView v, int64_t n, Media m, double dx, double dy, double2* 
 // y = A x, stage 1: workgroup b covers target i = b / ntj and one source tile;
 // it writes the tile's partial sums of rows 2i, 2i+1 to part[b] (4 doubles).
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
-k_matvec_partial(NodeView v, int64_t n, int64_t ntj, Media m, const double2* __restrict__ x,
-                 double4* __restrict__ part) {
+k_matvec_partial(NodeView v, int64_t n, int64_t ntj, const Media* __restrict__ media,
+                 const double2* __restrict__ x, double4* __restrict__ part) {
     const int64_t i = blockIdx.x / ntj;
     const int64_t j = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (j < n) {
+    const int bi = body_of(v, i);
+    const Media m = media[bi];
+    if (j < n && body_of(v, j) == bi) {
         Block b;
         if (i == j) {
             b = diag_block(v.w[j], v.kappa[j], m);
@@ -209,15 +237,19 @@ k_matvec_reduce(int64_t n, int64_t ntj, const double4* __restrict__ part, double
     y[2 * i + 1] = make_double2(s.z, s.w);
 }
 
-// Far field: one workgroup per observation angle.
+// Far field: one workgroup per (observation angle, body); a body's far field
+// sums over its own nodes with its own exterior wavenumber.
 __global__ void __launch_bounds__(kThreads)
-k_far_field(NodeView v, int64_t n, Media m, const double2* __restrict__ phi,
-            const double* __restrict__ angles, double2* __restrict__ uinf) {
+k_far_field(NodeView v, const int64_t* __restrict__ body_lo, const Media* __restrict__ media,
+            const double2* __restrict__ phi, const double* __restrict__ angles, int64_t nang,
+            double2* __restrict__ uinf) {
     const int64_t a = blockIdx.x;
+    const int b = blockIdx.y;
+    const Media m = media[b];
     double sa, ca;
     sincos(angles[a], &sa, &ca);
     double acc[2] = {0.0, 0.0};
-    for (int64_t j = threadIdx.x; j < n; j += kThreads) {
+    for (int64_t j = body_lo[b] + threadIdx.x; j < body_lo[b + 1]; j += kThreads) {
         const double2 u = phi[2 * j], q = phi[2 * j + 1];
         const double xn = ca * v.nx[j] + sa * v.ny[j];
         // density = -i k0 (xhat.n) u - eps0 q
@@ -234,7 +266,7 @@ k_far_field(NodeView v, int64_t n, Media m, const double2* __restrict__ phi,
         // e^{i pi/4} / sqrt(8 pi k0)
         const double f = 1.0 / sqrt(8.0 * kPi * m.k0);
         const double cr = f * kSqrtHalf, ci = f * kSqrtHalf;
-        uinf[a] = make_double2(cr * acc[0] - ci * acc[1], cr * acc[1] + ci * acc[0]);
+        uinf[b * nang + a] = make_double2(cr * acc[0] - ci * acc[1], cr * acc[1] + ci * acc[0]);
     }
 }
 
@@ -251,7 +283,7 @@ hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurve
     return hipGetLastError();
 }
 
-hipError_t launch_dense(const NodeView& v, int64_t n, const Media& m, double* A, int64_t ld,
+hipError_t launch_dense(const NodeView& v, int64_t n, const Media* m, double* A, int64_t ld,
                         hipStream_t s) {
     const int64_t ntj = (n + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_dense, dim3(static_cast<unsigned>(n * ntj)), dim3(kThreads), 0, s, v, n,
@@ -259,7 +291,7 @@ hipError_t launch_dense(const NodeView& v, int64_t n, const Media& m, double* A,
     return hipGetLastError();
 }
 
-hipError_t launch_block(const NodeView& v, const Media& m, const int64_t* rows, int64_t nr,
+hipError_t launch_block(const NodeView& v, const Media* m, const int64_t* rows, int64_t nr,
                         const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s) {
     if (nr == 0 || nc == 0) return hipSuccess;
     const int64_t ntj = (nc + kThreads - 1) / kThreads;
@@ -268,7 +300,7 @@ hipError_t launch_block(const NodeView& v, const Media& m, const int64_t* rows, 
     return hipGetLastError();
 }
 
-hipError_t launch_proxy(const NodeView& v, const Media& m, const int64_t* nodes, int64_t n,
+hipError_t launch_proxy(const NodeView& v, const Media* m, const int64_t* nodes, int64_t n,
                         const double* pts, int64_t P, int dir, double* out, int64_t ld,
                         hipStream_t s) {
     if (n == 0 || P == 0) return hipSuccess;
@@ -279,14 +311,14 @@ hipError_t launch_proxy(const NodeView& v, const Media& m, const int64_t* nodes,
     return hipGetLastError();
 }
 
-hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media& m, double angle,
+hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* m, double angle,
                                  double* rhs, hipStream_t s) {
     hipLaunchKernelGGL(k_rhs_plane_wave, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, v, n,
                        m, std::cos(angle), std::sin(angle), reinterpret_cast<double2*>(rhs));
     return hipGetLastError();
 }
 
-hipError_t launch_matvec(const NodeView& v, int64_t n, const Media& m, const double* x,
+hipError_t launch_matvec(const NodeView& v, int64_t n, const Media* m, const double* x,
                          double* y, double* work, hipStream_t s) {
     const int64_t ntj = (n + kThreads - 1) / kThreads;
     double4* part = reinterpret_cast<double4*>(work);
@@ -301,12 +333,13 @@ hipError_t launch_matvec(const NodeView& v, int64_t n, const Media& m, const dou
 
 int64_t matvec_work_doubles(int64_t n) { return 4 * n * ((n + kThreads - 1) / kThreads); }
 
-hipError_t launch_far_field(const NodeView& v, int64_t n, const Media& m, const double* phi,
-                            const double* angles, int64_t nang, double* uinf, hipStream_t s) {
+hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* m,
+                            const double* phi, const double* angles, int64_t nang, double* uinf,
+                            hipStream_t s) {
     if (nang == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_far_field, dim3(static_cast<unsigned>(nang)), dim3(kThreads), 0, s, v, n,
-                       m, reinterpret_cast<const double2*>(phi), angles,
-                       reinterpret_cast<double2*>(uinf));
+    hipLaunchKernelGGL(k_far_field, dim3(static_cast<unsigned>(nang), static_cast<unsigned>(nbodies)),
+                       dim3(kThreads), 0, s, v, body_lo, m, reinterpret_cast<const double2*>(phi), angles,
+                       nang, reinterpret_cast<double2*>(uinf));
     return hipGetLastError();
 }
 

@@ -115,6 +115,7 @@ int bm_geom_create(int ncurves, const int64_t* n_per_curve, const double* xyd, i
     if (!g) return fail(BM_ENOMEM, "bm_geom_create: host allocation");
     g->n = n;
     g->ncurves = ncurves;
+    g->curve_lo = offsets;
     (void)hipGetDevice(&g->device);
     double* d_xyd = nullptr;
     int64_t* d_off = nullptr;
@@ -157,24 +158,71 @@ int bm_geom_nodes(const bm_geom* g, double* soa, hipStream_t stream) {
     return BM_OK;
 }
 
-int bm_problem_create(const bm_geom* g, const bm_media* media, bm_problem** out) {
+int bm_problem_create_bodies(const bm_geom* g, int nbodies, const int32_t* body_of_curve,
+                             const bm_media* media, bm_problem** out) {
     clear_error();
     if (!out) return fail(BM_EINVAL, "bm_problem_create: out is null");
     *out = nullptr;
-    if (!g || !media) return fail(BM_EINVAL, "bm_problem_create: null argument");
-    if (!finite_media(media))
-        return fail(BM_EINVAL, "bm_problem_create: wavenumbers and permittivities must be finite and > 0");
+    if (!g || !media || (nbodies > 1 && !body_of_curve))
+        return fail(BM_EINVAL, "bm_problem_create: null argument");
+    if (nbodies < 1) return fail(BM_EINVAL, "bm_problem_create: need nbodies >= 1");
+    for (int b = 0; b < nbodies; ++b)
+        if (!finite_media(media + b))
+            return fail(BM_EINVAL, "bm_problem_create: wavenumbers and permittivities must be finite and > 0");
+    if (nbodies > g->ncurves)
+        return fail(BM_EINVAL, "bm_problem_create: more bodies than curves");
+    // bodies are consecutive runs of curves: body_of_curve = 0, .., 0, 1, .., nbodies - 1
+    std::vector<int64_t> lo(nbodies + 1, 0);
+    if (body_of_curve) {
+        if (body_of_curve[0] != 0 || body_of_curve[g->ncurves - 1] != nbodies - 1)
+            return fail(BM_EINVAL, "bm_problem_create: body_of_curve must run from 0 to nbodies - 1");
+        for (int c = 1; c < g->ncurves; ++c) {
+            const int32_t d = body_of_curve[c] - body_of_curve[c - 1];
+            if (d != 0 && d != 1)
+                return fail(BM_EINVAL, "bm_problem_create: body_of_curve must be non-decreasing in steps of 1");
+            if (d == 1) lo[body_of_curve[c]] = g->curve_lo[c];
+        }
+    }
+    lo[nbodies] = g->n;
     const BesselTable* tab = nullptr;
     BM_HIP(device_table(&tab));
     bm_problem* p = new (std::nothrow) bm_problem;
     if (!p) return fail(BM_ENOMEM, "bm_problem_create: host allocation");
     p->g = g;
-    p->media = make_media(media->k0, media->k1, media->eps0, media->eps1, tab);
+    p->nbodies = nbodies;
+    p->body_lo = lo;
+    for (int b = 0; b < nbodies; ++b)
+        p->media.push_back(make_media(media[b].k0, media[b].k1, media[b].eps0, media[b].eps1, tab));
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->d_media), nbodies * sizeof(Media));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_media, p->media.data(), nbodies * sizeof(Media), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_body_lo), (nbodies + 1) * sizeof(int64_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_body_lo, lo.data(), (nbodies + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nbodies > 1) {
+        std::vector<int32_t> nb(static_cast<size_t>(g->n));
+        for (int b = 0; b < nbodies; ++b)
+            for (int64_t i = lo[b]; i < lo[b + 1]; ++i) nb[i] = b;
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_body), g->n * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemcpy(p->d_body, nb.data(), g->n * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        bm_problem_destroy(p);
+        return hip_fail(e, "bm_problem_create");
+    }
     *out = p;
     return BM_OK;
 }
 
+int bm_problem_create(const bm_geom* g, const bm_media* media, bm_problem** out) {
+    return bm_problem_create_bodies(g, 1, nullptr, media, out);
+}
+
 int bm_problem_destroy(bm_problem* p) {
+    if (!p) return BM_OK;
+    (void)hipFree(p->d_media);
+    (void)hipFree(p->d_body);
+    (void)hipFree(p->d_body_lo);
     delete p;
     return BM_OK;
 }
@@ -183,7 +231,7 @@ int bm_rhs_plane_wave(const bm_problem* p, double angle, double* rhs, hipStream_
     clear_error();
     if (!p || !rhs) return fail(BM_EINVAL, "bm_rhs_plane_wave: null argument");
     if (!std::isfinite(angle)) return fail(BM_EINVAL, "bm_rhs_plane_wave: non-finite angle");
-    BM_HIP(launch_rhs_plane_wave(view(p->g), p->g->n, p->media, angle, rhs, stream));
+    BM_HIP(launch_rhs_plane_wave(view(p), p->g->n, p->d_media, angle, rhs, stream));
     return BM_OK;
 }
 
@@ -193,7 +241,7 @@ int bm_assemble_dense(const bm_problem* p, double* A, int64_t ld, hipStream_t st
     const int64_t n = p->g->n;
     if (ld < 2 * n) return fail(BM_EINVAL, "bm_assemble_dense: ld < 2N");
     if (n * ((n + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_dense: N too large");
-    BM_HIP(launch_dense(view(p->g), n, p->media, A, ld, stream));
+    BM_HIP(launch_dense(view(p), n, p->d_media, A, ld, stream));
     return BM_OK;
 }
 
@@ -206,7 +254,7 @@ int bm_assemble_block(const bm_problem* p, const int64_t* rows, int64_t nr, cons
     if (!rows || !cols || !out) return fail(BM_EINVAL, "bm_assemble_block: null array");
     if (ld < 2 * nc) return fail(BM_EINVAL, "bm_assemble_block: ld < 2 nc");
     if (nr * ((nc + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_block: too large");
-    BM_HIP(launch_block(view(p->g), p->media, rows, nr, cols, nc, out, ld, stream));
+    BM_HIP(launch_block(view(p), p->d_media, rows, nr, cols, nc, out, ld, stream));
     return BM_OK;
 }
 
@@ -221,7 +269,7 @@ int bm_assemble_proxy(const bm_problem* p, const int64_t* nodes, int64_t n, cons
     const int64_t ncol = dir == 0 ? P : n, nrow = dir == 0 ? n : P;
     if (ld < 2 * ncol) return fail(BM_EINVAL, "bm_assemble_proxy: ld too small");
     if (nrow * ((ncol + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_proxy: too large");
-    BM_HIP(launch_proxy(view(p->g), p->media, nodes, n, pts, P, dir, out, ld, stream));
+    BM_HIP(launch_proxy(view(p), p->d_media, nodes, n, pts, P, dir, out, ld, stream));
     return BM_OK;
 }
 
@@ -233,7 +281,7 @@ int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t strea
     const int64_t n = p->g->n;
     void* work = nullptr;
     BM_HIP(dev_alloc(&work, matvec_work_doubles(n) * sizeof(double), stream));
-    const hipError_t e = launch_matvec(view(p->g), n, p->media, x, y, static_cast<double*>(work), stream);
+    const hipError_t e = launch_matvec(view(p), n, p->d_media, x, y, static_cast<double*>(work), stream);
     dev_free(work, stream);
     if (e != hipSuccess) return hip_fail(e, "bm_matvec");
     return BM_OK;
@@ -246,7 +294,7 @@ int bm_far_field(const bm_problem* p, const double* phi, const double* angles, i
     if (nang == 0) return BM_OK;
     if (!phi || !angles || !uinf) return fail(BM_EINVAL, "bm_far_field: null array");
     if (nang > (int64_t{1} << 31)) return fail(BM_EINVAL, "bm_far_field: too many angles");
-    BM_HIP(launch_far_field(view(p->g), p->g->n, p->media, phi, angles, nang, uinf, stream));
+    BM_HIP(launch_far_field(view(p), p->nbodies, p->d_body_lo, p->d_media, phi, angles, nang, uinf, stream));
     return BM_OK;
 }
 

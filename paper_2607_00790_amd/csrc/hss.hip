@@ -34,15 +34,32 @@ using namespace bm::hss;
 
 namespace {
 
+// The factors of one iteration of the build (the boxes compressed together:
+// one level of every body's tree that is still compressing), and the offsets
+// the solve needs to move between iterations.
 struct LevelFactor {
     int nb = 0;
     std::vector<int64_t> n, k;       // unknowns and ranks per box
     std::vector<int64_t> uoff, koff; // prefix sums of n and k
     std::vector<int64_t> nkoff, nnoff;
     int64_t nu = 0, nk = 0;
+    std::vector<int64_t> in_off;     // input of the box: in the right-hand side (first
+                                     // iteration) or in the previous iteration's F^T output
+    std::vector<int64_t> xt_off;     // where the box's skeleton solution is found: in the
+    std::vector<int8_t> xt_root;     // next iteration's output (0) or the root solutions (1)
     double2* E = nullptr;   // per box n x k
     double2* Ft = nullptr;  // per box k x n
     double2* G = nullptr;   // per box n x n
+};
+
+// The root of one body: its reduced system, inverted densely.
+struct RootJob {
+    int body;
+    int64_t K, r_off, x_off;   // size; inverse at Rinv + r_off; solution at xroot + x_off
+    int stage;                 // iteration whose F^T output feeds it (-1: the right-hand side)
+    int64_t in_off;            // offset of its input in that vector
+    int64_t slot_off;          // its slots in the root slot list
+    int32_t nslots;
 };
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -173,7 +190,7 @@ struct Scratch {
 };
 
 hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
-                      const PointTable& pt, const Media& m, double2* out) {
+                      const PointTable& pt, const Media* media, double2* out) {
     if (jobs.empty()) return hipSuccess;
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
@@ -187,10 +204,9 @@ hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* 
     const unsigned grid = static_cast<unsigned>(toff.back());
     const int nj = static_cast<int>(jobs.size());
     const PointTable ptc = pt;
-    const Media mc = m;
     hipStream_t st = sc.s;
     sc.rec([=]() {
-        hipLaunchKernelGGL(k_gen_jobs, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, mc, out);
+        hipLaunchKernelGGL(k_gen_jobs, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, media, out);
         return hipGetLastError();
     });
     return hipSuccess;
@@ -471,10 +487,10 @@ struct bm_hss {
     bm_hss_opts opts{};
     int64_t N = 0;
     int levels = 0;
-    std::vector<LevelFactor> lv;   // compressed levels, leaves first
-    int64_t K = 0;                 // root size
-    double2* Rinv = nullptr;
-    std::vector<int64_t> root_off; // not used by the solve; kept for stats
+    std::vector<LevelFactor> lv;   // compressed iterations, leaves first
+    std::vector<RootJob> roots;    // one per body
+    int64_t Ktot = 0;              // total size of the roots
+    double2* Rinv = nullptr;       // the roots' inverses, packed
     bm_hss_stats_t stats{};
     std::vector<bm_hss_level_t> level_info;   // per compressed level, leaves first
 };
@@ -606,52 +622,84 @@ struct Pipeline {
     }
 };
 
+// One body's state during the forest build.
+struct BodyState {
+    int64_t nlo = 0, nn = 0;   // node range [nlo, nlo + nn)
+    int L = 0;                 // depth of its tree: the leaves are level L
+    int level = 0;             // level of its current boxes
+    bool active = true;        // still compressing (no root yet)
+    std::vector<std::vector<int32_t>> U;   // active unknowns (global ids) per current box
+    std::vector<int64_t> split_slots;      // per current box above the leaves: slots of the first child
+    int iter_prev = -1;        // last iteration that compressed this body's boxes
+    int kept_prev = -1;        // index of its first box among that iteration's boxes
+};
+
 int build_impl(bm_hss* h, hipStream_t s) {
     const bm_problem* p = h->p;
     const bm_geom* g = p->g;
     const int64_t N = g->n;
     const int P = static_cast<int>(h->opts.proxy_points);
     const double tol = h->opts.id_tol;
-    int L = 0;
-    while ((N >> (L + 1)) >= h->opts.leaf && L < 30) ++L;
-    h->levels = L;
-    const NodeView nv = view(g);
+    const int nbodies = p->nbodies;
+    const NodeView nv = view(p);
     EventTimer t_gen, t_cmp, t_fac;
 
-    // point table: nodes, then P proxy points per box of the current level
-    const int64_t npts = N + (int64_t{1} << L) * P;
+    // bodies and their trees
+    std::vector<BodyState> bodies(nbodies);
+    int64_t leaf_boxes = 0;
+    int Lmax = 0;
+    for (int q = 0; q < nbodies; ++q) {
+        BodyState& B = bodies[q];
+        B.nlo = p->body_lo[q];
+        B.nn = p->body_lo[q + 1] - p->body_lo[q];
+        while ((B.nn >> (B.L + 1)) >= h->opts.leaf && B.L < 30) ++B.L;
+        B.level = B.L;
+        Lmax = std::max(Lmax, B.L);
+        const int64_t nb = int64_t{1} << B.L;
+        leaf_boxes += nb;
+        B.U.resize(nb);
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t lo = B.nlo + ((b * B.nn) >> B.L), hi = B.nlo + (((b + 1) * B.nn) >> B.L);
+            for (int64_t i = lo; i < hi; ++i) {
+                B.U[b].push_back(static_cast<int32_t>(2 * i));
+                B.U[b].push_back(static_cast<int32_t>(2 * i + 1));
+            }
+        }
+    }
+    h->levels = Lmax;
+
+    // point table: nodes, then P proxy points per box of the current iteration
+    const int64_t npts = N + leaf_boxes * P;
     PointTable pt{};
     double* ptd = nullptr;
     Scratch persist(s);   // point table: freed (stream-ordered) when the build returns
     BM_HIP(persist.alloc(&ptd, 6 * npts));
     int32_t* ptc = nullptr;
-    BM_HIP(persist.alloc(&ptc, npts));
+    BM_HIP(persist.alloc(&ptc, 2 * npts));
     pt.x = ptd; pt.y = ptd + npts; pt.nx = ptd + 2 * npts; pt.ny = ptd + 3 * npts;
-    pt.w = ptd + 4 * npts; pt.kappa = ptd + 5 * npts; pt.curve = ptc;
+    pt.w = ptd + 4 * npts; pt.kappa = ptd + 5 * npts; pt.curve = ptc; pt.body = ptc + npts;
     for (int r = 0; r < 6; ++r)
         BM_HIP(hipMemcpyAsync(ptd + r * npts, g->soa + r * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     BM_HIP(hipMemcpyAsync(ptc, g->curve, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (p->d_body)
+        BM_HIP(hipMemcpyAsync(pt.body, p->d_body, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    else
+        BM_HIP(hipMemsetAsync(pt.body, 0, N * sizeof(int32_t), s));
     // declared after the point table: on every return it first drains both
     // streams, so the table outlives the factorisation kernels that read it
     Pipeline pl(s);
     BM_HIP(aux_streams().get(&pl.s2));
     const hipStream_t s2 = pl.s2;
 
-    // active unknowns per box (global ids), leaves first
-    std::vector<std::vector<int32_t>> U(size_t{1} << L);
-    for (int64_t b = 0; b < (int64_t{1} << L); ++b) {
-        const int64_t lo = (b * N) >> L, hi = ((b + 1) * N) >> L;
-        for (int64_t i = lo; i < hi; ++i) {
-            U[b].push_back(static_cast<int32_t>(2 * i));
-            U[b].push_back(static_cast<int32_t>(2 * i + 1));
-        }
-    }
-    std::vector<int64_t> split_slots;     // per box: slots belonging to the first child
-    double2* Dhat_prev = nullptr;          // children's Dhat, packed per box (k x k)
-    std::vector<int64_t> dhat_prev_off;    // offsets per child box
-    std::vector<int64_t> k_prev;           // children's ranks
+    std::vector<double2*> dhat;             // per iteration: Dhat of every kept box (k x k, packed)
+    std::vector<std::vector<int64_t>> dhat_off;
     std::vector<int32_t*> status_bufs;
-    auto cleanup_status = [&]() { for (auto q : status_bufs) dev_free(q, s2); status_bufs.clear(); };
+    auto cleanup = [&]() {
+        for (auto q : status_bufs) dev_free(q, s2);
+        status_bufs.clear();
+        for (auto q : dhat) dev_free(q, s2);
+        dhat.clear();
+    };
     int64_t entries = 0, pairs = 0, max_rank = 0, cpqr_launches = 0;
     double cpqr_bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> cpqr_events;
@@ -665,173 +713,264 @@ int build_impl(bm_hss* h, hipStream_t s) {
         }
     } cpqr_events_guard{cpqr_events};
 
-    int compressed = 0;
-    for (int l = L; l >= 1; --l) {
-        const int nb = 1 << l;
-        auto scp = std::make_unique<Scratch>(s);   // compression scratch of this level
-        Scratch& sc = *scp;
-        // ---- box geometry and proxy points
-        std::vector<int64_t> lo(nb), hi(nb);
-        for (int b = 0; b < nb; ++b) {
-            lo[b] = (static_cast<int64_t>(b) * N) >> l;
-            hi[b] = (static_cast<int64_t>(b + 1) * N) >> l;
+    // roots
+    std::vector<RootJob> roots;
+    std::vector<Slot> root_slots;
+    std::vector<CopyJob> root_copies;   // Dhat blocks on the roots' diagonals
+    std::vector<int64_t> root_copy_dst; // their offsets in the packed root inverses
+    int64_t Ktot = 0, Rtot = 0;
+    auto make_root = [&](int q) {
+        BodyState& B = bodies[q];
+        RootJob r{};
+        r.body = q;
+        std::vector<int32_t> Ur;
+        for (auto& u : B.U) Ur.insert(Ur.end(), u.begin(), u.end());
+        r.K = static_cast<int64_t>(Ur.size());
+        r.r_off = Rtot;
+        r.x_off = Ktot;
+        Rtot += r.K * r.K;
+        Ktot += r.K;
+        r.stage = B.iter_prev;
+        r.slot_off = static_cast<int64_t>(root_slots.size());
+        make_slots(Ur, root_slots);
+        r.nslots = static_cast<int32_t>(root_slots.size() - r.slot_off);
+        if (B.iter_prev >= 0) {
+            // the root is made of the skeletons of the boxes compressed last: two
+            // children per current box, U(box) = J(child 0) then J(child 1)
+            LevelFactor& F = h->lv[B.iter_prev];
+            r.in_off = F.koff[B.kept_prev];
+            int64_t off = 0;
+            for (size_t c = 0; c < 2 * B.U.size(); ++c) {
+                const int kb = B.kept_prev + static_cast<int>(c);
+                const int64_t kc = F.k[kb];
+                // source Dhat, destination offset in the root's inverse (pointer added later)
+                root_copies.push_back(CopyJob{dhat[B.iter_prev] + dhat_off[B.iter_prev][kb], nullptr, kc, 1, r.K,
+                                              1, static_cast<int32_t>(kc), static_cast<int32_t>(kc)});
+                root_copy_dst.push_back(r.r_off + off * r.K + off);
+                // the box's skeleton solution comes from the root
+                F.xt_root[kb] = 1;
+                F.xt_off[kb] = r.x_off + off;
+                off += kc;
+            }
+        } else {
+            r.in_off = 2 * B.nlo;
         }
+        roots.push_back(r);
+        B.active = false;
+    };
+
+    int iter = 0;
+    for (;; ++iter) {
+        // bodies that reached their top level become roots
+        for (int q = 0; q < nbodies; ++q)
+            if (bodies[q].active && bodies[q].level == 0) make_root(q);
+        // ---- the boxes of this iteration: every active body at its current level
+        struct Box { int body, local; int64_t lo, hi; };
+        std::vector<Box> boxes;
+        std::vector<int> bfirst(nbodies, -1);
+        for (int q = 0; q < nbodies; ++q) {
+            BodyState& B = bodies[q];
+            if (!B.active) continue;
+            bfirst[q] = static_cast<int>(boxes.size());
+            const int64_t nb = int64_t{1} << B.level;
+            for (int64_t b = 0; b < nb; ++b)
+                boxes.push_back(Box{q, static_cast<int>(b), B.nlo + ((b * B.nn) >> B.level),
+                                    B.nlo + (((b + 1) * B.nn) >> B.level)});
+        }
+        const int nbox = static_cast<int>(boxes.size());
+        if (nbox == 0) break;
+        auto scp = std::make_unique<Scratch>(s);   // compression scratch of this iteration
+        Scratch& sc = *scp;
+        std::vector<int64_t> lo(nbox), hi(nbox);
+        std::vector<int32_t> box_body(nbox);
+        for (int b = 0; b < nbox; ++b) { lo[b] = boxes[b].lo; hi[b] = boxes[b].hi; box_body[b] = boxes[b].body; }
         int64_t *dlo, *dhi;
+        int32_t* dbody;
         double* box_c;
         hipError_t e = sc.upload(&dlo, lo);
         if (e == hipSuccess) e = sc.upload(&dhi, hi);
-        if (e == hipSuccess) e = sc.alloc(&box_c, 3 * nb);
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: level setup"); }
+        if (e == hipSuccess) e = sc.upload(&dbody, box_body);
+        if (e == hipSuccess) e = sc.alloc(&box_c, 3 * nbox);
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: level setup"); }
         {
             const double ratio = h->opts.proxy_ratio;
             sc.rec([=]() {
-                hipLaunchKernelGGL(k_box_geometry, dim3(nb), dim3(kThreads), 0, s, nv, dlo, dhi, ratio, P, N,
-                                   box_c, pt);
+                hipLaunchKernelGGL(k_box_geometry, dim3(nbox), dim3(kThreads), 0, s, nv, dlo, dhi, dbody, ratio,
+                                   P, N, box_c, pt);
                 return hipGetLastError();
             });
         }
-        // ---- active slots
+        // ---- active slots; each box scans the slots of its own body
         std::vector<Slot> act;
-        std::vector<int64_t> soff(nb + 1, 0), n(nb);
+        std::vector<int64_t> soff(nbox + 1, 0), n(nbox), scan_lo(nbox), scan_hi(nbox);
         std::vector<int32_t> sbox;
-        for (int b = 0; b < nb; ++b) {
-            make_slots(U[b], act);
+        for (int b = 0; b < nbox; ++b) {
+            make_slots(bodies[boxes[b].body].U[boxes[b].local], act);
             soff[b + 1] = static_cast<int64_t>(act.size());
-            n[b] = static_cast<int64_t>(U[b].size());
+            n[b] = static_cast<int64_t>(bodies[boxes[b].body].U[boxes[b].local].size());
             for (int64_t q = soff[b]; q < soff[b + 1]; ++q) sbox.push_back(b);
         }
-        const int64_t nact = soff[nb];
-        int64_t* dcounts;
+        for (int b = 0; b < nbox; ++b) {
+            const int q = boxes[b].body;
+            const int first = bfirst[q], last = first + (1 << bodies[q].level);
+            scan_lo[b] = soff[first];
+            scan_hi[b] = soff[last];
+        }
+        const int64_t nact = soff[nbox];
+        int64_t *dcounts, *dscan_lo, *dscan_hi;
         Slot* dact;
         int32_t* dsbox;
         e = sc.upload(&dact, act);
         if (e == hipSuccess) e = sc.upload(&dsbox, sbox);
-        if (e == hipSuccess) e = sc.alloc(&dcounts, 2 * nb);
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slots"); }
+        if (e == hipSuccess) e = sc.upload(&dscan_lo, scan_lo);
+        if (e == hipSuccess) e = sc.upload(&dscan_hi, scan_hi);
+        if (e == hipSuccess) e = sc.alloc(&dcounts, 2 * nbox);
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: slots"); }
         sc.rec([=]() {
-            hipLaunchKernelGGL(k_near_count, dim3(nb), dim3(kThreads), 0, s, pt, dact, dsbox, nact, box_c, dcounts);
+            hipLaunchKernelGGL(k_near_count, dim3(nbox), dim3(kThreads), 0, s, pt, dact, dsbox, dscan_lo, dscan_hi,
+                               box_c, dcounts);
             return hipGetLastError();
         });
-        std::vector<int64_t> counts(2 * nb);
+        std::vector<int64_t> counts(2 * nbox);
         e = sc.flush();
         if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), dcounts, counts.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         sc.synced();
         pl.reap(false);
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: near counts"); }
-        int64_t total_u = 0;
-        for (int b = 0; b < nb; ++b) total_u += n[b];
-        bool far_ok = true;
-        for (int b = 0; b < nb; ++b)
-            if (total_u - n[b] - counts[2 * b + 1] <= 0) far_ok = false;
-        if (!far_ok) { sc.release(); break; }   // this level is the root level
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: near counts"); }
+        // ---- a body with a box that has no far unknowns stops: its current boxes form its root
+        {
+            std::vector<int64_t> total_u(nbodies, 0);
+            std::vector<char> stop(nbodies, 0);
+            for (int b = 0; b < nbox; ++b) total_u[boxes[b].body] += n[b];
+            for (int b = 0; b < nbox; ++b)
+                if (total_u[boxes[b].body] - n[b] - counts[2 * b + 1] <= 0) stop[boxes[b].body] = 1;
+            for (int q = 0; q < nbodies; ++q)
+                if (bodies[q].active && bfirst[q] >= 0 && stop[q]) make_root(q);
+        }
+        // ---- kept boxes: those of bodies that still compress
+        std::vector<int> kept;            // kept index -> box index
+        std::vector<int> kfirst(nbodies, -1);
+        for (int b = 0; b < nbox; ++b) {
+            const int q = boxes[b].body;
+            if (!bodies[q].active) continue;
+            if (boxes[b].local == 0) kfirst[q] = static_cast<int>(kept.size());
+            kept.push_back(b);
+        }
+        const int nk = static_cast<int>(kept.size());
+        if (nk == 0) { sc.release(); break; }
 
-        // ---- slot buffer: [active | near | proxy]
-        std::vector<int64_t> nsoff(nb + 1, 0), nearu(nb);
-        for (int b = 0; b < nb; ++b) {
+        // ---- slot buffer: [active | near (every box) | proxy (every box)]
+        std::vector<int64_t> nsoff(nbox + 1, 0), nearu(nbox);
+        for (int b = 0; b < nbox; ++b) {
             nsoff[b + 1] = nsoff[b] + counts[2 * b];
             nearu[b] = counts[2 * b + 1];
         }
-        const int64_t near_base = nact, prox_base = nact + nsoff[nb];
-        const int64_t nslots_all = prox_base + static_cast<int64_t>(nb) * P;
+        const int64_t near_base = nact, prox_base = nact + nsoff[nbox];
+        const int64_t nslots_all = prox_base + static_cast<int64_t>(nbox) * P;
         Slot* dslots;
-        if ((e = sc.alloc(&dslots, nslots_all)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slot buffer"); }
+        if ((e = sc.alloc(&dslots, nslots_all)) != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: slot buffer"); }
         sc.rec([=]() { return hipMemcpyAsync(dslots, dact, nact * sizeof(Slot), hipMemcpyDeviceToDevice, s); });
-        std::vector<Slot> prox(static_cast<size_t>(nb) * P);
-        for (int b = 0; b < nb; ++b)
+        std::vector<Slot> prox(static_cast<size_t>(nbox) * P);
+        for (int b = 0; b < nbox; ++b)
             for (int q = 0; q < P; ++q)
                 prox[static_cast<size_t>(b) * P + q] = Slot{static_cast<int32_t>(N + static_cast<int64_t>(b) * P + q), 2 * q, 2 * q + 1};
         Slot* dprox;
-        if (e == hipSuccess) e = sc.upload(&dprox, prox);
+        e = sc.upload(&dprox, prox);
         {
             const size_t pbytes = prox.size() * sizeof(Slot);
             sc.rec([=]() { return hipMemcpyAsync(dslots + prox_base, dprox, pbytes, hipMemcpyDeviceToDevice, s); });
         }
         int64_t* dnsoff;
         if (e == hipSuccess) e = sc.upload(&dnsoff, std::vector<int64_t>(nsoff.begin(), nsoff.end() - 1));
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: slot upload"); }
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: slot upload"); }
         sc.rec([=]() {
-            hipLaunchKernelGGL(k_near_list, dim3(nb), dim3(kThreads), 0, s, pt, dact, dsbox, nact, box_c, dnsoff,
-                               dslots + near_base);
+            hipLaunchKernelGGL(k_near_list, dim3(nbox), dim3(kThreads), 0, s, pt, dact, dsbox, dscan_lo, dscan_hi,
+                               box_c, dnsoff, dslots + near_base);
             return hipGetLastError();
         });
 
-        // ---- M_b for all boxes in one generation launch
-        std::vector<int64_t> m(nb), mo(nb + 1, 0);
-        for (int b = 0; b < nb; ++b) {
-            m[b] = 2 * nearu[b] + 4 * P;
-            mo[b + 1] = mo[b] + n[b] * m[b];
+        // ---- per kept box: sizes
+        std::vector<int64_t> kn(nk), km(nk), mo(nk + 1, 0);
+        for (int c = 0; c < nk; ++c) {
+            const int b = kept[c];
+            kn[c] = n[b];
+            km[c] = 2 * nearu[b] + 4 * P;
+            mo[c + 1] = mo[c] + kn[c] * km[c];
         }
+        // ---- M_b for every kept box in one generation launch
         double2* M;
-        if ((e = sc.alloc(&M, mo[nb])) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: M"); }
+        if ((e = sc.alloc(&M, mo[nk])) != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: M"); }
         std::vector<GenJob> jobs;
-        for (int b = 0; b < nb; ++b) {
+        for (int c = 0; c < nk; ++c) {
+            const int b = kept[c];
+            const int32_t body = boxes[b].body;
             const int32_t na = static_cast<int32_t>(soff[b + 1] - soff[b]);
             const int32_t nn = static_cast<int32_t>(nsoff[b + 1] - nsoff[b]);
-            const int64_t base = mo[b];
-            jobs.push_back(GenJob{soff[b], near_base + nsoff[b], base, m[b], 1, na, nn});
-            jobs.push_back(GenJob{near_base + nsoff[b], soff[b], base + nearu[b], 1, m[b], nn, na});
-            jobs.push_back(GenJob{soff[b], prox_base + static_cast<int64_t>(b) * P, base + 2 * nearu[b], m[b], 1, na, P});
-            jobs.push_back(GenJob{prox_base + static_cast<int64_t>(b) * P, soff[b], base + 2 * nearu[b] + 2 * P, 1, m[b], P, na});
-            entries += n[b] * m[b];
+            const int64_t base = mo[c], m = km[c];
+            jobs.push_back(GenJob{soff[b], near_base + nsoff[b], base, m, 1, na, nn, body});
+            jobs.push_back(GenJob{near_base + nsoff[b], soff[b], base + nearu[b], 1, m, nn, na, body});
+            jobs.push_back(GenJob{soff[b], prox_base + static_cast<int64_t>(b) * P, base + 2 * nearu[b], m, 1, na, P, body});
+            jobs.push_back(GenJob{prox_base + static_cast<int64_t>(b) * P, soff[b], base + 2 * nearu[b] + 2 * P, 1, m, P, na, body});
+            entries += kn[c] * m;
             pairs += 2 * static_cast<int64_t>(na) * (nn + P);
         }
         hipEvent_t ev;
-        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->media, M);
+        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->d_media, M);
         if (e == hipSuccess) e = t_gen.stop(sc, ev);
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: generate M"); }
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: generate M"); }
 
         // ---- optional sketch: Y_b = Omega M_b^T with min(rows, unknowns + p)
         // rows; the CPQR and the interpolation matrix then come from Y_b
         // (randomized ID).  The p extra rows keep Omega well conditioned on the
         // column space of M_b^T even when a box is close to full rank.
-        std::vector<int64_t> idm(m), yo(nb + 1, 0);
+        std::vector<int64_t> idm(km), yo(nk + 1, 0);
         double2* Y_sk = nullptr;
         if (h->opts.sketch) {
             int64_t lmax = 0, mmax = 0;
-            for (int b = 0; b < nb; ++b) {
-                idm[b] = std::min(m[b], n[b] + h->opts.sketch);
-                yo[b + 1] = yo[b] + idm[b] * n[b];
-                lmax = std::max(lmax, idm[b]);
-                mmax = std::max(mmax, m[b]);
+            for (int c = 0; c < nk; ++c) {
+                idm[c] = std::min(km[c], kn[c] + h->opts.sketch);
+                yo[c + 1] = yo[c] + idm[c] * kn[c];
+                lmax = std::max(lmax, idm[c]);
+                mmax = std::max(mmax, km[c]);
             }
-            if (yo[nb] < mo[nb]) {
+            if (yo[nk] < mo[nk]) {
                 const double* omega = nullptr;
                 int64_t ldo = 0;
                 e = omega_device(lmax, mmax, &omega, &ldo);
-                if (e == hipSuccess) e = sc.alloc(&Y_sk, yo[nb]);
-                std::vector<SketchJob> sj(nb);
-                for (int b = 0; b < nb; ++b)
-                    sj[b] = SketchJob{M + mo[b], Y_sk + yo[b], static_cast<int32_t>(m[b]),
-                                      static_cast<int32_t>(n[b]), static_cast<int32_t>(idm[b])};
+                if (e == hipSuccess) e = sc.alloc(&Y_sk, yo[nk]);
+                std::vector<SketchJob> sj(nk);
+                for (int c = 0; c < nk; ++c)
+                    sj[c] = SketchJob{M + mo[c], Y_sk + yo[c], static_cast<int32_t>(km[c]),
+                                      static_cast<int32_t>(kn[c]), static_cast<int32_t>(idm[c])};
                 if (e == hipSuccess && (e = t_cmp.start(sc, ev)) == hipSuccess) {
                     e = launch_sketch(sc, sj, omega, ldo);
                     if (e == hipSuccess) e = t_cmp.stop(sc, ev);
                 }
-                if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: sketch"); }
+                if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: sketch"); }
             } else {
-                idm = m;
+                idm = km;
                 Y_sk = nullptr;
             }
         }
 
         // ---- ID: CPQR of M_b^T (or of its sketch)
-        std::vector<int64_t> uoff(nb + 1, 0);
-        for (int b = 0; b < nb; ++b) uoff[b + 1] = uoff[b] + n[b];
+        std::vector<int64_t> uoff(nk + 1, 0);
+        for (int c = 0; c < nk; ++c) uoff[c + 1] = uoff[c] + kn[c];
         int32_t *dperm, *dranks;
         double2* drdiag;
-        e = sc.alloc(&dperm, uoff[nb]);
-        if (e == hipSuccess) e = sc.alloc(&drdiag, uoff[nb]);
-        if (e == hipSuccess) e = sc.alloc(&dranks, nb);
-        std::vector<CpqrJob> cj(nb);
-        for (int b = 0; b < nb; ++b)
-            cj[b] = CpqrJob{Y_sk ? Y_sk + yo[b] : M + mo[b], dperm + uoff[b], drdiag + uoff[b], nullptr,
-                            nullptr, nullptr, static_cast<int32_t>(n[b]),
-                            static_cast<int32_t>(Y_sk ? idm[b] : m[b])};
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: cpqr setup"); }
-        if ((e = t_cmp.start(sc, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        e = sc.alloc(&dperm, uoff[nk]);
+        if (e == hipSuccess) e = sc.alloc(&drdiag, uoff[nk]);
+        if (e == hipSuccess) e = sc.alloc(&dranks, nk);
+        std::vector<CpqrJob> cj(nk);
+        for (int c = 0; c < nk; ++c)
+            cj[c] = CpqrJob{Y_sk ? Y_sk + yo[c] : M + mo[c], dperm + uoff[c], drdiag + uoff[c], nullptr,
+                            nullptr, nullptr, static_cast<int32_t>(kn[c]),
+                            static_cast<int32_t>(Y_sk ? idm[c] : km[c])};
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: cpqr setup"); }
+        if ((e = t_cmp.start(sc, ev)) != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "event"); }
         CpqrJob* dcj = nullptr;
-        std::vector<int32_t> ranks(nb), perm(uoff[nb]);
+        std::vector<int32_t> ranks(nk), perm(uoff[nk]);
         hipEvent_t c0 = nullptr, c1 = nullptr;
         e = hipEventCreate(&c0);
         if (e == hipSuccess) e = hipEventCreate(&c1);
@@ -842,72 +981,103 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         sc.synced();
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: cpqr"); }
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: cpqr"); }
         {
             bm_hss_level_t li{};
-            li.boxes = nb;
+            li.boxes = nk;
             li.min_rank = INT32_MAX;
-            for (int b = 0; b < nb; ++b) {
-                li.max_unknowns = std::max<int32_t>(li.max_unknowns, static_cast<int32_t>(n[b]));
-                li.max_rows = std::max<int32_t>(li.max_rows, static_cast<int32_t>(m[b]));
-                li.min_rank = std::min<int32_t>(li.min_rank, ranks[b]);
-                li.max_rank = std::max<int32_t>(li.max_rank, ranks[b]);
+            for (int c = 0; c < nk; ++c) {
+                li.max_unknowns = std::max<int32_t>(li.max_unknowns, static_cast<int32_t>(kn[c]));
+                li.max_rows = std::max<int32_t>(li.max_rows, static_cast<int32_t>(km[c]));
+                li.id_rows = std::max<int32_t>(li.id_rows, static_cast<int32_t>(Y_sk ? idm[c] : km[c]));
+                li.min_rank = std::min<int32_t>(li.min_rank, ranks[c]);
+                li.max_rank = std::max<int32_t>(li.max_rank, ranks[c]);
             }
-            li.id_rows = 0;
-            for (int b = 0; b < nb; ++b)
-                li.id_rows = std::max<int32_t>(li.id_rows, static_cast<int32_t>(Y_sk ? idm[b] : m[b]));
+            h->level_info.push_back(li);
             // algorithmic bytes of the executed CPQR steps: at step k the trailing
             // columns (n - k - 1 of them, rows k..m) are read and written once, the
             // Householder column (rows k..m) and the n norms are read, and the
             // trailing norms written; the step that finds the rank reads the norms
-            for (int b = 0; b < nb; ++b) {
-                const double rows = static_cast<double>(Y_sk ? idm[b] : m[b]), cols = static_cast<double>(n[b]);
-                for (int64_t kk = 0; kk < ranks[b]; ++kk) {
-                    const double r = rows - kk, c = cols - kk - 1;
-                    cpqr_bytes += 32.0 * r * c + 16.0 * r + 8.0 * cols + 8.0 * c;
+            for (int c = 0; c < nk; ++c) {
+                const double rows = static_cast<double>(Y_sk ? idm[c] : km[c]), cols = static_cast<double>(kn[c]);
+                for (int64_t kk = 0; kk < ranks[c]; ++kk) {
+                    const double r = rows - kk, cc = cols - kk - 1;
+                    cpqr_bytes += 32.0 * r * cc + 16.0 * r + 8.0 * cols + 8.0 * cc;
                 }
                 cpqr_bytes += 8.0 * cols;
             }
-            h->level_info.push_back(li);
         }
-        std::vector<int64_t> k(nb), koff(nb + 1, 0), nkoff(nb + 1, 0), nnoff(nb + 1, 0), kkoff(nb + 1, 0);
-        for (int b = 0; b < nb; ++b) {
-            k[b] = ranks[b];
-            max_rank = std::max(max_rank, k[b]);
-            koff[b + 1] = koff[b] + k[b];
-            nkoff[b + 1] = nkoff[b] + n[b] * k[b];
-            nnoff[b + 1] = nnoff[b] + n[b] * n[b];
-            kkoff[b + 1] = kkoff[b] + k[b] * k[b];
+        std::vector<int64_t> k(nk), koff(nk + 1, 0), nkoff(nk + 1, 0), nnoff(nk + 1, 0), kkoff(nk + 1, 0);
+        for (int c = 0; c < nk; ++c) {
+            k[c] = ranks[c];
+            max_rank = std::max(max_rank, k[c]);
+            koff[c + 1] = koff[c] + k[c];
+            nkoff[c + 1] = nkoff[c] + kn[c] * k[c];
+            nnoff[c + 1] = nnoff[c] + kn[c] * kn[c];
+            kkoff[c + 1] = kkoff[c] + k[c] * k[c];
         }
         double2* T;
-        e = sc.alloc(&T, nkoff[nb]);
+        e = sc.alloc(&T, nkoff[nk]);
         {
-            const size_t tbytes = std::max<int64_t>(nkoff[nb], 1) * sizeof(double2);
+            const size_t tbytes = std::max<int64_t>(nkoff[nk], 1) * sizeof(double2);
             sc.rec([=]() { return hipMemsetAsync(T, 0, tbytes, s); });
         }
         int64_t* dtoff;
         if (e == hipSuccess) e = sc.upload(&dtoff, std::vector<int64_t>(nkoff.begin(), nkoff.end() - 1));
-        if (e != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: T"); }
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: T"); }
         int64_t cmax = 1;
-        for (int b = 0; b < nb; ++b) cmax = std::max(cmax, n[b] - k[b]);
+        for (int c = 0; c < nk; ++c) cmax = std::max(cmax, kn[c] - k[c]);
         {
             const unsigned cx = static_cast<unsigned>(ceil_div(cmax, kThreads / 64));
             sc.rec([=]() {
-                hipLaunchKernelGGL(k_interp, dim3(cx, nb), dim3(kThreads), 0, s, dcj, dranks, dtoff, T);
+                hipLaunchKernelGGL(k_interp, dim3(cx, nk), dim3(kThreads), 0, s, dcj, dranks, dtoff, T);
                 return hipGetLastError();
             });
         }
-        if ((e = t_cmp.stop(sc, ev)) != hipSuccess) { sc.release(); cleanup_status(); return hip_fail(e, "event"); }
+        if ((e = t_cmp.stop(sc, ev)) != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "event"); }
+
+        // ---- the factors of this iteration, and how the solve moves between stages
+        LevelFactor f;
+        f.nb = nk; f.n = kn; f.k = k; f.uoff = uoff; f.koff = koff; f.nkoff = nkoff; f.nnoff = nnoff;
+        f.nu = uoff[nk]; f.nk = koff[nk];
+        f.in_off.resize(nk);
+        f.xt_off.assign(nk, 0);
+        f.xt_root.assign(nk, -1);   // set when the parent iteration or the root is known
+        for (int c = 0; c < nk; ++c) {
+            const int b = kept[c];
+            const BodyState& B = bodies[boxes[b].body];
+            if (B.iter_prev < 0) {
+                f.in_off[c] = 2 * boxes[b].lo;   // leaves read the right-hand side
+            } else {
+                // the children are consecutive boxes of the previous iteration
+                const LevelFactor& Fp = h->lv[B.iter_prev];
+                const int child0 = B.kept_prev + 2 * boxes[b].local;
+                f.in_off[c] = Fp.koff[child0];
+            }
+        }
+        // the previous iteration's boxes of continuing bodies take their skeleton
+        // solution from their parent here: U(parent) = J(child 0) then J(child 1)
+        for (int c = 0; c < nk; ++c) {
+            const int b = kept[c];
+            const BodyState& B = bodies[boxes[b].body];
+            if (B.iter_prev < 0) continue;
+            LevelFactor& Fp = h->lv[B.iter_prev];
+            const int child0 = B.kept_prev + 2 * boxes[b].local;
+            Fp.xt_root[child0] = 0;
+            Fp.xt_off[child0] = uoff[c];
+            Fp.xt_root[child0 + 1] = 0;
+            Fp.xt_off[child0 + 1] = uoff[c] + Fp.k[child0];
+        }
 
         // ---- hand over to the second stream: everything below reads T, the
         // slot lists and the point table, and runs concurrently with the next
-        // level's compression on the caller's stream
+        // iteration's compression on the caller's stream
         hipEvent_t ready = nullptr, done = nullptr;
         e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
         if (e != hipSuccess) {
             if (ready) (void)hipEventDestroy(ready);
-            sc.release(); cleanup_status(); return hip_fail(e, "bm_hss_build: events");
+            sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: events");
         }
         sc.rec([=]() { return hipEventRecord(ready, s); });
         e = sc.flush();
@@ -917,94 +1087,100 @@ int build_impl(bm_hss* h, hipStream_t s) {
         pl.pending.back().done = done;
         pl.pending.back().fac = std::make_unique<Scratch>(s2);
         Scratch& fs = *pl.pending.back().fac;
-        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: compression"); }
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: compression"); }
         fs.rec([=]() { return hipStreamWaitEvent(s2, ready, 0); });
 
         // ---- diagonal blocks D_b (become G_b in place)
-        LevelFactor f;
-        f.nb = nb; f.n = n; f.k = k; f.uoff = uoff; f.koff = koff; f.nkoff = nkoff; f.nnoff = nnoff;
-        f.nu = uoff[nb]; f.nk = koff[nb];
-        e = palloc(&f.G, nnoff[nb], s2);
-        if (e == hipSuccess) e = palloc(&f.E, nkoff[nb], s2);
-        if (e == hipSuccess) e = palloc(&f.Ft, nkoff[nb], s2);
-        if (e != hipSuccess) { free_factor(f, s2); cleanup_status(); return hip_fail(e, "bm_hss_build: factors"); }
+        e = palloc(&f.G, nnoff[nk], s2);
+        if (e == hipSuccess) e = palloc(&f.E, nkoff[nk], s2);
+        if (e == hipSuccess) e = palloc(&f.Ft, nkoff[nk], s2);
+        if (e != hipSuccess) { free_factor(f, s2); cleanup(); return hip_fail(e, "bm_hss_build: factors"); }
         h->lv.push_back(f);   // owned by h from here on
         LevelFactor& F = h->lv.back();
         jobs.clear();
         std::vector<CopyJob> copies;
-        for (int b = 0; b < nb; ++b) {
+        for (int c = 0; c < nk; ++c) {
+            const int b = kept[c];
+            const BodyState& B = bodies[boxes[b].body];
+            const int32_t body = boxes[b].body;
             const int32_t na = static_cast<int32_t>(soff[b + 1] - soff[b]);
-            if (l == L) {
-                jobs.push_back(GenJob{soff[b], soff[b], nnoff[b], n[b], 1, na, na});
-                entries += n[b] * n[b];
+            if (B.iter_prev < 0) {
+                jobs.push_back(GenJob{soff[b], soff[b], nnoff[c], kn[c], 1, na, na, body});
+                entries += kn[c] * kn[c];
                 pairs += static_cast<int64_t>(na) * na;
             } else {
-                const int64_t sa = split_slots[b];
+                const int64_t sa = B.split_slots[boxes[b].local];
                 const int32_t n1 = static_cast<int32_t>(sa), n2 = na - n1;
-                jobs.push_back(GenJob{soff[b], soff[b] + sa, nnoff[b], n[b], 1, n1, n2});
-                jobs.push_back(GenJob{soff[b] + sa, soff[b], nnoff[b], n[b], 1, n2, n1});
-                const int64_t ka = k_prev[2 * b], kb = k_prev[2 * b + 1];
+                jobs.push_back(GenJob{soff[b], soff[b] + sa, nnoff[c], kn[c], 1, n1, n2, body});
+                jobs.push_back(GenJob{soff[b] + sa, soff[b], nnoff[c], kn[c], 1, n2, n1, body});
+                const LevelFactor& Fp = h->lv[B.iter_prev];
+                const int child0 = B.kept_prev + 2 * boxes[b].local;
+                const int64_t ka = Fp.k[child0], kb = Fp.k[child0 + 1];
                 entries += 2 * ka * kb;
                 pairs += 2 * static_cast<int64_t>(n1) * n2;
-                copies.push_back(CopyJob{Dhat_prev + dhat_prev_off[2 * b], F.G + nnoff[b], ka, 1, n[b], 1,
+                const double2* Dp = dhat[B.iter_prev];
+                copies.push_back(CopyJob{Dp + dhat_off[B.iter_prev][child0], F.G + nnoff[c], ka, 1, kn[c], 1,
                                          static_cast<int32_t>(ka), static_cast<int32_t>(ka)});
-                copies.push_back(CopyJob{Dhat_prev + dhat_prev_off[2 * b + 1], F.G + nnoff[b] + ka * n[b] + ka, kb, 1,
-                                         n[b], 1, static_cast<int32_t>(kb), static_cast<int32_t>(kb)});
+                copies.push_back(CopyJob{Dp + dhat_off[B.iter_prev][child0 + 1], F.G + nnoff[c] + ka * kn[c] + ka, kb, 1,
+                                         kn[c], 1, static_cast<int32_t>(kb), static_cast<int32_t>(kb)});
             }
         }
-        if ((e = t_gen.start(fs, ev)) == hipSuccess) e = launch_gen(fs, jobs, dslots, pt, p->media, F.G);
+        if ((e = t_gen.start(fs, ev)) == hipSuccess) e = launch_gen(fs, jobs, dslots, pt, p->d_media, F.G);
         if (e == hipSuccess) e = t_gen.stop(fs, ev);
         if (e == hipSuccess) e = launch_copy(fs, copies);
-        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: D blocks"); }
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: D blocks"); }
 
         // ---- Martinsson-Rokhlin factors
-        double2 *Y, *Wt, *S;
-        S = nullptr;
-        e = fs.alloc(&Y, nkoff[nb]);
-        if (e == hipSuccess) e = fs.alloc(&Wt, nkoff[nb]);
-        if (e == hipSuccess) e = palloc(&S, kkoff[nb], s2);
+        double2 *Y, *Wt, *S = nullptr;
+        e = fs.alloc(&Y, nkoff[nk]);
+        if (e == hipSuccess) e = fs.alloc(&Wt, nkoff[nk]);
+        if (e == hipSuccess) e = palloc(&S, kkoff[nk], s2);
+        if (e == hipSuccess) {
+            dhat.push_back(S);   // kept until the roots are built
+            dhat_off.emplace_back(kkoff.begin(), kkoff.end() - 1);
+        }
         int32_t* st = nullptr;
-        if (e == hipSuccess) e = palloc(&st, 2 * nb, s2);
+        if (e == hipSuccess) e = palloc(&st, 2 * nk, s2);
         if (e == hipSuccess) {
             status_bufs.push_back(st);
-            fs.rec([=]() { return hipMemsetAsync(st, 0, 2 * nb * sizeof(int32_t), s2); });
+            fs.rec([=]() { return hipMemsetAsync(st, 0, 2 * nk * sizeof(int32_t), s2); });
         }
-        if (e != hipSuccess) { dev_free(S, s2); cleanup_status(); return hip_fail(e, "bm_hss_build: factor buffers"); }
-        if ((e = t_fac.start(fs, ev)) != hipSuccess) { dev_free(S, s2); cleanup_status(); return hip_fail(e, "event"); }
-        std::vector<InvJob> inv(nb);
-        for (int b = 0; b < nb; ++b) inv[b] = InvJob{F.G + nnoff[b], st + b, n[b], static_cast<int32_t>(n[b])};
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: factor buffers"); }
+        if ((e = t_fac.start(fs, ev)) != hipSuccess) { cleanup(); return hip_fail(e, "event"); }
+        std::vector<InvJob> inv(nk);
+        for (int c = 0; c < nk; ++c) inv[c] = InvJob{F.G + nnoff[c], st + c, kn[c], static_cast<int32_t>(kn[c])};
         e = launch_inverse(fs, inv);
         std::vector<GemmJob> g1, g2, g3, g4;
         const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
-        for (int b = 0; b < nb; ++b) {
-            const int64_t nn = n[b], kk = k[b];
-            const double2* Di = F.G + nnoff[b];
-            const double2* Tb = T + nkoff[b];
+        for (int c = 0; c < nk; ++c) {
+            const int64_t nn = kn[c], kk = k[c];
+            const double2* Di = F.G + nnoff[c];
+            const double2* Tb = T + nkoff[c];
             // Y = D^-1 T (n x k); Wt = T^T D^-1 (k x n)
-            g1.push_back(gemm(Di, nn, 1, Tb, kk, 1, Y + nkoff[b], kk, 1, nn, kk, nn));
-            g1.push_back(gemm(Tb, 1, kk, Di, nn, 1, Wt + nkoff[b], nn, 1, kk, nn, nn));
+            g1.push_back(gemm(Di, nn, 1, Tb, kk, 1, Y + nkoff[c], kk, 1, nn, kk, nn));
+            g1.push_back(gemm(Tb, 1, kk, Di, nn, 1, Wt + nkoff[c], nn, 1, kk, nn, nn));
         }
         if (e == hipSuccess) e = launch_gemm(fs, g1);
-        for (int b = 0; b < nb; ++b) {
-            const int64_t nn = n[b], kk = k[b];
+        for (int c = 0; c < nk; ++c) {
+            const int64_t nn = kn[c], kk = k[c];
             // S = Wt T (k x k)
-            g2.push_back(gemm(Wt + nkoff[b], nn, 1, T + nkoff[b], kk, 1, S + kkoff[b], kk, 1, kk, kk, nn));
+            g2.push_back(gemm(Wt + nkoff[c], nn, 1, T + nkoff[c], kk, 1, S + kkoff[c], kk, 1, kk, kk, nn));
         }
         if (e == hipSuccess) e = launch_gemm(fs, g2);
-        std::vector<InvJob> inv2(nb);
-        for (int b = 0; b < nb; ++b) inv2[b] = InvJob{S + kkoff[b], st + nb + b, k[b], static_cast<int32_t>(k[b])};
+        std::vector<InvJob> inv2(nk);
+        for (int c = 0; c < nk; ++c) inv2[c] = InvJob{S + kkoff[c], st + nk + c, k[c], static_cast<int32_t>(k[c])};
         if (e == hipSuccess) e = launch_inverse(fs, inv2);
-        for (int b = 0; b < nb; ++b) {
-            const int64_t nn = n[b], kk = k[b];
+        for (int c = 0; c < nk; ++c) {
+            const int64_t nn = kn[c], kk = k[c];
             // E = Y Dhat (n x k); Ft = Dhat Wt (k x n)
-            g3.push_back(gemm(Y + nkoff[b], kk, 1, S + kkoff[b], kk, 1, F.E + nkoff[b], kk, 1, nn, kk, kk));
-            g3.push_back(gemm(S + kkoff[b], kk, 1, Wt + nkoff[b], nn, 1, F.Ft + nkoff[b], nn, 1, kk, nn, kk));
+            g3.push_back(gemm(Y + nkoff[c], kk, 1, S + kkoff[c], kk, 1, F.E + nkoff[c], kk, 1, nn, kk, kk));
+            g3.push_back(gemm(S + kkoff[c], kk, 1, Wt + nkoff[c], nn, 1, F.Ft + nkoff[c], nn, 1, kk, nn, kk));
         }
         if (e == hipSuccess) e = launch_gemm(fs, g3);
-        for (int b = 0; b < nb; ++b) {
-            const int64_t nn = n[b], kk = k[b];
+        for (int c = 0; c < nk; ++c) {
+            const int64_t nn = kn[c], kk = k[c];
             // G = D^-1 - E Wt (in place)
-            g4.push_back(gemm(F.E + nkoff[b], kk, 1, Wt + nkoff[b], nn, 1, F.G + nnoff[b], nn, 1, nn, nn, kk, mone, one));
+            g4.push_back(gemm(F.E + nkoff[c], kk, 1, Wt + nkoff[c], nn, 1, F.G + nnoff[c], nn, 1, nn, nn, kk, mone, one));
         }
         if (e == hipSuccess) e = launch_gemm(fs, g4);
         if (e == hipSuccess) e = t_fac.stop(fs, ev);
@@ -1012,78 +1188,74 @@ int build_impl(bm_hss* h, hipStream_t s) {
             fs.rec([=]() { return hipEventRecord(done, s2); });
             e = fs.flush();
         }
-        if (e != hipSuccess) { dev_free(S, s2); cleanup_status(); return hip_fail(e, "bm_hss_build: factor"); }
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: factor"); }
 
-        // ---- next level: U(parent) = J(first child) then J(second child)
-        if (Dhat_prev) dev_free(Dhat_prev, s2);   // its last reader is already on s2
-        Dhat_prev = S;
-        dhat_prev_off.assign(kkoff.begin(), kkoff.end() - 1);
-        k_prev = k;
-        std::vector<std::vector<int32_t>> J(nb);
-        for (int b = 0; b < nb; ++b) {
-            J[b].resize(k[b]);
-            for (int64_t i = 0; i < k[b]; ++i) J[b][i] = U[b][perm[uoff[b] + i]];
+        // ---- next level of every continuing body: U(parent) = J(first child) then J(second child)
+        for (int q = 0; q < nbodies; ++q) {
+            BodyState& B = bodies[q];
+            if (!B.active || kfirst[q] < 0) continue;
+            const int nbq = 1 << B.level;
+            std::vector<std::vector<int32_t>> J(nbq);
+            for (int lb = 0; lb < nbq; ++lb) {
+                const int c = kfirst[q] + lb;
+                J[lb].resize(k[c]);
+                for (int64_t i = 0; i < k[c]; ++i) J[lb][i] = B.U[lb][perm[uoff[c] + i]];
+            }
+            B.U.assign(nbq / 2, {});
+            B.split_slots.assign(nbq / 2, 0);
+            for (int pq = 0; pq < nbq / 2; ++pq) {
+                B.U[pq] = J[2 * pq];
+                std::vector<Slot> tmp;
+                make_slots(J[2 * pq], tmp);
+                B.split_slots[pq] = static_cast<int64_t>(tmp.size());
+                B.U[pq].insert(B.U[pq].end(), J[2 * pq + 1].begin(), J[2 * pq + 1].end());
+            }
+            B.iter_prev = iter;
+            B.kept_prev = kfirst[q];
+            B.level -= 1;
         }
-        U.assign(nb / 2, {});
-        split_slots.assign(nb / 2, 0);
-        for (int q = 0; q < nb / 2; ++q) {
-            U[q] = J[2 * q];
-            std::vector<Slot> tmp;
-            make_slots(J[2 * q], tmp);
-            split_slots[q] = static_cast<int64_t>(tmp.size());
-            U[q].insert(U[q].end(), J[2 * q + 1].begin(), J[2 * q + 1].end());
-        }
-        ++compressed;
     }
+    const int compressed = static_cast<int>(h->lv.size());
 
-    // ---- root: the reduced system over the current active unknowns, on the
-    // second stream after the last compression
+    // ---- roots: every body's reduced system, generated and inverted in one batch
+    // on the second stream after the last compression
     {
         hipEvent_t rready = nullptr;
         BM_HIP(hipEventCreateWithFlags(&rready, hipEventDisableTiming));
         const hipError_t er = hipEventRecord(rready, s);
-        if (er != hipSuccess) { (void)hipEventDestroy(rready); cleanup_status(); return hip_fail(er, "bm_hss_build: root"); }
+        if (er != hipSuccess) { (void)hipEventDestroy(rready); cleanup(); return hip_fail(er, "bm_hss_build: root"); }
         Scratch sc(s2);
         sc.rec([=]() { return hipStreamWaitEvent(s2, rready, 0); });
-        std::vector<int32_t> Ur;
-        std::vector<int64_t> boff;   // start of each current box in Ur
-        for (auto& u : U) {
-            boff.push_back(static_cast<int64_t>(Ur.size()));
-            Ur.insert(Ur.end(), u.begin(), u.end());
-        }
-        const int64_t K = static_cast<int64_t>(Ur.size());
-        h->K = K;
-        std::vector<Slot> rs;
-        make_slots(Ur, rs);
+        h->roots = roots;
+        h->Ktot = Ktot;
         Slot* drs;
-        hipError_t e = sc.upload(&drs, rs);
-        if (e == hipSuccess) e = palloc(&h->Rinv, K * K, s2);
-        if (e != hipSuccess) { sc.release(); (void)hipEventDestroy(rready); cleanup_status(); return hip_fail(e, "bm_hss_build: root"); }
-        std::vector<GenJob> jobs{GenJob{0, 0, 0, K, 1, static_cast<int32_t>(rs.size()), static_cast<int32_t>(rs.size())}};
-        entries += K * K;
-        pairs += static_cast<int64_t>(rs.size()) * rs.size();
-        hipEvent_t ev;
-        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, drs, pt, p->media, h->Rinv);
-        if (e == hipSuccess) e = t_gen.stop(sc, ev);
-        // diagonal blocks of the last compressed level's boxes are their Dhat
-        std::vector<CopyJob> copies;
-        if (compressed > 0) {
-            int64_t off = 0;
-            for (size_t c = 0; c < k_prev.size(); ++c) {
-                copies.push_back(CopyJob{Dhat_prev + dhat_prev_off[c], h->Rinv + off * K + off, k_prev[c], 1, K, 1,
-                                         static_cast<int32_t>(k_prev[c]), static_cast<int32_t>(k_prev[c])});
-                off += k_prev[c];
-            }
+        hipError_t e = sc.upload(&drs, root_slots);
+        if (e == hipSuccess) e = palloc(&h->Rinv, Rtot, s2);
+        if (e != hipSuccess) { sc.release(); (void)hipEventDestroy(rready); cleanup(); return hip_fail(e, "bm_hss_build: root"); }
+        std::vector<GenJob> jobs;
+        for (const RootJob& r : roots) {
+            jobs.push_back(GenJob{r.slot_off, r.slot_off, r.r_off, r.K, 1, r.nslots, r.nslots, r.body});
+            entries += r.K * r.K;
+            pairs += static_cast<int64_t>(r.nslots) * r.nslots;
         }
-        if (e == hipSuccess) e = launch_copy(sc, copies);
+        hipEvent_t ev;
+        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, drs, pt, p->d_media, h->Rinv);
+        if (e == hipSuccess) e = t_gen.stop(sc, ev);
+        // diagonal blocks of a root are the Dhat of the boxes it is made of
+        for (size_t c = 0; c < root_copies.size(); ++c) root_copies[c].dst = h->Rinv + root_copy_dst[c];
+        if (e == hipSuccess) e = launch_copy(sc, root_copies);
         int32_t* st = nullptr;
-        if (e == hipSuccess) e = palloc(&st, 1, s2);
+        if (e == hipSuccess) e = palloc(&st, static_cast<int64_t>(roots.size()), s2);
         if (e == hipSuccess) {
             status_bufs.push_back(st);
-            sc.rec([=]() { return hipMemsetAsync(st, 0, sizeof(int32_t), s2); });
+            const size_t nr = roots.size();
+            sc.rec([=]() { return hipMemsetAsync(st, 0, nr * sizeof(int32_t), s2); });
         }
         if (e == hipSuccess && (e = t_fac.start(sc, ev)) == hipSuccess) {
-            e = launch_inverse(sc, {InvJob{h->Rinv, st, K, static_cast<int32_t>(K)}});
+            std::vector<InvJob> inv;
+            for (size_t q = 0; q < roots.size(); ++q)
+                inv.push_back(InvJob{h->Rinv + roots[q].r_off, st + q, roots[q].K, static_cast<int32_t>(roots[q].K)});
+            e = launch_inverse(sc, inv);
             if (e == hipSuccess) e = t_fac.stop(sc, ev);
         }
         if (e == hipSuccess) e = sc.flush();
@@ -1092,23 +1264,26 @@ int build_impl(bm_hss* h, hipStream_t s) {
         sc.release();
         (void)hipEventDestroy(rready);
         pl.reap(true);
-        if (Dhat_prev) dev_free(Dhat_prev, s2);
-        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: root factor"); }
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: root factor"); }
     }
+    // every compressed box must know where its skeleton solution comes from
+    for (const LevelFactor& f : h->lv)
+        for (int8_t r : f.xt_root)
+            if (r < 0) { cleanup(); return fail(BM_ESTATE, "bm_hss_build: internal error (unlinked box)"); }
     // ---- statuses of every inversion
     for (size_t q = 0; q < status_bufs.size(); ++q) {
-        const int cnt = (q + 1 == status_bufs.size()) ? 1 : 2 * h->lv[q].nb;
+        const int64_t cnt = (q + 1 == status_bufs.size()) ? static_cast<int64_t>(roots.size()) : 2 * h->lv[q].nb;
         std::vector<int32_t> hs(cnt);
         hipError_t e = hipMemcpyAsync(hs.data(), status_bufs[q], cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { cleanup_status(); return hip_fail(e, "bm_hss_build: status"); }
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: status"); }
         for (int32_t v : hs)
-            if (v) { cleanup_status(); return fail(BM_ESINGULAR, "bm_hss_build: singular block in the HSS factorisation"); }
+            if (v) { cleanup(); return fail(BM_ESINGULAR, "bm_hss_build: singular block in the HSS factorisation"); }
     }
-    cleanup_status();
-    h->stats.levels = L;
+    cleanup();
+    h->stats.levels = Lmax;
     h->stats.compressed_levels = compressed;
-    h->stats.root_size = static_cast<int32_t>(h->K);
+    h->stats.root_size = static_cast<int32_t>(std::min<int64_t>(Ktot, INT32_MAX));
     h->stats.max_rank = max_rank;
     h->stats.entries = entries;
     h->stats.pairs = pairs;
@@ -1178,57 +1353,84 @@ int bm_hss_solve(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipS
         if (e == hipSuccess) e = sc.alloc(&xl[li], h->lv[li].nu * nrhs);
     }
     double2* xroot;
-    if (e == hipSuccess) e = sc.alloc(&xroot, h->K * nrhs);
+    if (e == hipSuccess) e = sc.alloc(&xroot, h->Ktot * nrhs);
     if (e != hipSuccess) { sc.release(); return hip_fail(e, "bm_hss_solve: buffers"); }
     const double2* bin = reinterpret_cast<const double2*>(b);
-    auto level_in = [&](int li, const double2** ptr, int64_t* ld) {
-        if (li == 0) { *ptr = bin; *ld = N2; }
-        else { *ptr = bt[li - 1]; *ld = h->lv[li - 1].nk; }
+    // input of iteration li: the right-hand side, or the previous iteration's F^T output
+    auto stage_in = [&](int li, const double2** ptr, int64_t* ld) {
+        if (li < 0) { *ptr = bin; *ld = N2; }
+        else { *ptr = bt[li]; *ld = h->lv[li].nk; }
     };
     // upward: bt = F^T in
     for (int li = 0; li < nl && e == hipSuccess; ++li) {
         const LevelFactor& f = h->lv[li];
         const double2* in;
         int64_t ldin;
-        level_in(li, &in, &ldin);
+        stage_in(li - 1, &in, &ldin);
         std::vector<GemmJob> gj;
         for (int q = 0; q < f.nb; ++q)
-            gj.push_back(gemm(f.Ft + f.nkoff[q], f.n[q], 1, in + f.uoff[q], 1, ldin, bt[li] + f.koff[q], 1, f.nk,
+            gj.push_back(gemm(f.Ft + f.nkoff[q], f.n[q], 1, in + f.in_off[q], 1, ldin, bt[li] + f.koff[q], 1, f.nk,
                               f.k[q], nrhs, f.n[q]));
         e = launch_gemm(sc, gj);
     }
-    // root
+    // roots: xroot = Rinv in, one product per body
     {
-        const double2* in;
-        int64_t ldin;
-        if (nl == 0) { in = bin; ldin = N2; }
-        else { in = bt[nl - 1]; ldin = h->lv[nl - 1].nk; }
-        if (e == hipSuccess)
-            e = launch_gemm(sc, {gemm(h->Rinv, h->K, 1, in, 1, ldin, xroot, 1, h->K, h->K, nrhs, h->K)});
+        std::vector<GemmJob> gj;
+        for (const RootJob& r : h->roots) {
+            const double2* in;
+            int64_t ldin;
+            stage_in(r.stage, &in, &ldin);
+            gj.push_back(gemm(h->Rinv + r.r_off, r.K, 1, in + r.in_off, 1, ldin, xroot + r.x_off, 1, h->Ktot,
+                              r.K, nrhs, r.K));
+        }
+        if (e == hipSuccess) e = launch_gemm(sc, gj);
     }
-    // downward: x = G in + E xt
+    // downward: x = G in + E xt, xt from the parent iteration or the body's root
     for (int li = nl - 1; li >= 0 && e == hipSuccess; --li) {
         const LevelFactor& f = h->lv[li];
         const double2* in;
         int64_t ldin;
-        level_in(li, &in, &ldin);
-        const double2* xt = (li == nl - 1) ? xroot : xl[li + 1];
-        const int64_t ldxt = (li == nl - 1) ? h->K : h->lv[li + 1].nu;
+        stage_in(li - 1, &in, &ldin);
         std::vector<GemmJob> g1, g2;
         for (int q = 0; q < f.nb; ++q) {
-            g1.push_back(gemm(f.G + f.nnoff[q], f.n[q], 1, in + f.uoff[q], 1, ldin, xl[li] + f.uoff[q], 1, f.nu,
+            const double2* xt = f.xt_root[q] ? xroot : xl[li + 1];
+            const int64_t ldxt = f.xt_root[q] ? h->Ktot : h->lv[li + 1].nu;
+            g1.push_back(gemm(f.G + f.nnoff[q], f.n[q], 1, in + f.in_off[q], 1, ldin, xl[li] + f.uoff[q], 1, f.nu,
                               f.n[q], nrhs, f.n[q]));
-            g2.push_back(gemm(f.E + f.nkoff[q], f.k[q], 1, xt + f.koff[q], 1, ldxt, xl[li] + f.uoff[q], 1, f.nu,
+            g2.push_back(gemm(f.E + f.nkoff[q], f.k[q], 1, xt + f.xt_off[q], 1, ldxt, xl[li] + f.uoff[q], 1, f.nu,
                               f.n[q], nrhs, f.k[q], make_double2(1.0, 0.0), make_double2(1.0, 0.0)));
         }
         e = launch_gemm(sc, g1);
         if (e == hipSuccess) e = launch_gemm(sc, g2);
     }
+    // the solution of every body in global unknown order: from the first
+    // iteration's output (its leaf boxes are contiguous and in node order), or
+    // from its root when the body was never compressed
     if (e == hipSuccess) {
-        const double2* res = nl > 0 ? xl[0] : xroot;
-        const size_t bytes = N2 * nrhs * sizeof(double2);
-        sc.rec([=]() { return hipMemcpyAsync(x, res, bytes, hipMemcpyDeviceToDevice, s); });
-        e = sc.flush();
+        std::vector<CopyJob> cp;
+        const bm_problem* p = h->p;
+        for (const RootJob& r : h->roots) {
+            const int64_t lo = p->body_lo[r.body], nn2 = 2 * (p->body_lo[r.body + 1] - lo);
+            const double2* src;
+            int64_t ld;
+            if (r.stage < 0) {
+                src = xroot + r.x_off;
+                ld = h->Ktot;
+            } else {
+                // the body's first leaf box: the first box of its in iteration 0 with in_off 2*lo
+                const LevelFactor& f0 = h->lv[0];
+                int64_t off = -1;
+                for (int q = 0; q < f0.nb; ++q)
+                    if (f0.in_off[q] == 2 * lo) { off = f0.uoff[q]; break; }
+                if (off < 0) { e = hipErrorInvalidValue; break; }
+                src = xl[0] + off;
+                ld = f0.nu;
+            }
+            cp.push_back(CopyJob{src, reinterpret_cast<double2*>(x) + 2 * lo, 1, ld, 1, N2,
+                                 static_cast<int32_t>(nn2), static_cast<int32_t>(nrhs)});
+        }
+        if (e == hipSuccess) e = launch_copy(sc, cp);
+        if (e == hipSuccess) e = sc.flush();
     }
     // the job descriptors are staged from host memory: finish before releasing them
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -9,7 +9,8 @@ namespace hss {
 constexpr int kThreads = 256;
 
 // Point table of a level: the N boundary nodes followed by the proxy points of
-// every box (curve = -1 marks a proxy point).
+// every box (curve = -1 marks a proxy point); body = the node's body, or the
+// body of the box a proxy point belongs to.
 struct PointTable {
     double* x;
     double* y;
@@ -18,6 +19,7 @@ struct PointTable {
     double* w;
     double* kappa;
     int32_t* curve;
+    int32_t* body;
 };
 
 // A point with up to two unknowns (u at pos0, q at pos1; -1 when absent).
@@ -39,6 +41,7 @@ struct GenJob {
     int64_t cs;
     int32_t nt;
     int32_t ns;
+    int32_t body;   // every point of the job belongs to this body (its media)
 };
 
 struct CpqrState {
@@ -98,15 +101,17 @@ struct CopyJob {
 };
 
 __global__ void k_box_geometry(NodeView v, const int64_t* lo, const int64_t* hi,
-                               double proxy_ratio, int P, int64_t nnodes, double* box_c,
-                               PointTable pt);
+                               const int32_t* box_body, double proxy_ratio, int P, int64_t nnodes,
+                               double* box_c, PointTable pt);
+// near sets: box b scans the candidate slots [scan_lo[b], scan_hi[b]) (its body's)
 __global__ void k_near_count(PointTable pt, const Slot* slots, const int32_t* slot_box,
-                             int64_t nslots, const double* box_c, int64_t* counts);
+                             const int64_t* scan_lo, const int64_t* scan_hi, const double* box_c,
+                             int64_t* counts);
 __global__ void k_near_list(PointTable pt, const Slot* slots, const int32_t* slot_box,
-                            int64_t nslots, const double* box_c, const int64_t* slot_off,
-                            Slot* out);
+                            const int64_t* scan_lo, const int64_t* scan_hi, const double* box_c,
+                            const int64_t* slot_off, Slot* out);
 __global__ void k_gen_jobs(const GenJob* jobs, const int64_t* tile_off, int njobs,
-                           const Slot* slots, PointTable pt, Media m, double2* out);
+                           const Slot* slots, PointTable pt, const Media* media, double2* out);
 __global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
                          double2* Tbuf);
 // in-place inverse of n x n blocks, n <= 32 / 64 / 128; blockDim 64 / 256 / 1024

@@ -78,8 +78,8 @@ __device__ double block_sum(double v, double* sv) {
 // the point table at index nnodes + b*P + p.
 __global__ void __launch_bounds__(kThreads)
 k_box_geometry(NodeView v, const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
-               double proxy_ratio, int P, int64_t nnodes, double* __restrict__ box_c,
-               PointTable pt) {
+               const int32_t* __restrict__ box_body, double proxy_ratio, int P, int64_t nnodes,
+               double* __restrict__ box_c, PointTable pt) {
     __shared__ double red[kThreads / 64];
     const int b = blockIdx.x;
     const int64_t a = lo[b], e = hi[b];
@@ -120,13 +120,15 @@ k_box_geometry(NodeView v, const int64_t* __restrict__ lo, const int64_t* __rest
         pt.w[q] = 2.0 * kPi * rp / P;
         pt.kappa[q] = 0.0;
         pt.curve[q] = -1;
+        pt.body[q] = box_body[b];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Near sets.  Candidates are the active slots of all boxes of the level
-// (slot_box[s] = owning box).  A slot is near box b if it belongs to another box
-// and its node lies strictly inside b's proxy circle.
+// Near sets.  Candidates are the active slots of the boxes of the level
+// (slot_box[s] = owning box); box b scans only [scan_lo[b], scan_hi[b]), the
+// slots of its own body.  A slot is near box b if it belongs to another box and
+// its node lies strictly inside b's proxy circle.
 __device__ __forceinline__ bool is_near(const PointTable& pt, const Slot& s, int owner, int b,
                                         const double* box_c) {
     if (owner == b) return false;
@@ -142,11 +144,12 @@ __device__ __forceinline__ int slot_unknowns(const Slot& s) {
 // counts[2b] = near slots of box b, counts[2b+1] = near unknowns of box b.
 __global__ void __launch_bounds__(kThreads)
 k_near_count(PointTable pt, const Slot* __restrict__ slots, const int32_t* __restrict__ slot_box,
-             int64_t nslots, const double* __restrict__ box_c, int64_t* __restrict__ counts) {
+             const int64_t* __restrict__ scan_lo, const int64_t* __restrict__ scan_hi,
+             const double* __restrict__ box_c, int64_t* __restrict__ counts) {
     __shared__ double red[kThreads / 64];
     const int b = blockIdx.x;
     double ns = 0, nu = 0;
-    for (int64_t s = threadIdx.x; s < nslots; s += kThreads) {
+    for (int64_t s = scan_lo[b] + threadIdx.x; s < scan_hi[b]; s += kThreads) {
         const Slot sl = slots[s];
         if (is_near(pt, sl, slot_box[s], b, box_c)) {
             ns += 1;
@@ -165,19 +168,21 @@ k_near_count(PointTable pt, const Slot* __restrict__ slots, const int32_t* __res
 // renumbered 0..(near unknowns - 1) in candidate order.
 __global__ void __launch_bounds__(kThreads)
 k_near_list(PointTable pt, const Slot* __restrict__ slots, const int32_t* __restrict__ slot_box,
-            int64_t nslots, const double* __restrict__ box_c, const int64_t* __restrict__ slot_off,
+            const int64_t* __restrict__ scan_lo, const int64_t* __restrict__ scan_hi,
+            const double* __restrict__ box_c, const int64_t* __restrict__ slot_off,
             Slot* __restrict__ out) {
     __shared__ int scan_s[kThreads];
     __shared__ int scan_u[kThreads];
     __shared__ int base[2];
     const int b = blockIdx.x;
+    const int64_t s_lo = scan_lo[b], s_hi = scan_hi[b];
     if (threadIdx.x == 0) { base[0] = 0; base[1] = 0; }
     __syncthreads();
-    for (int64_t s0 = 0; s0 < nslots; s0 += kThreads) {
+    for (int64_t s0 = s_lo; s0 < s_hi; s0 += kThreads) {
         const int64_t s = s0 + threadIdx.x;
         Slot sl{0, -1, -1};
         bool nearb = false;
-        if (s < nslots) {
+        if (s < s_hi) {
             sl = slots[s];
             nearb = is_near(pt, sl, slot_box[s], b, box_c);
         }
@@ -218,7 +223,8 @@ k_near_list(PointTable pt, const Slot* __restrict__ slots, const int32_t* __rest
 // One pair per thread, no loop (the Bessel coefficients stay scalar operands).
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
-           const Slot* __restrict__ slots, PointTable pt, Media m, double2* __restrict__ out) {
+           const Slot* __restrict__ slots, PointTable pt, const Media* __restrict__ media,
+           double2* __restrict__ out) {
     int lo = 0, hi = njobs;
     const int64_t tile = blockIdx.x;
     while (hi - lo > 1) {
@@ -226,6 +232,7 @@ k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off
         if (tile_off[mid] <= tile) lo = mid; else hi = mid;
     }
     const GenJob jb = jobs[lo];
+    const Media m = media[jb.body];
     const int64_t q = (tile - tile_off[lo]) * kThreads + threadIdx.x;
     if (q >= static_cast<int64_t>(jb.nt) * jb.ns) return;
     const int t = static_cast<int>(q / jb.ns);

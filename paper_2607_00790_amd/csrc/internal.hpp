@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "bmhss.h"
 #include "wsbm_pair.hpp"
@@ -17,11 +18,20 @@ struct bm_geom {
     double* soa = nullptr;    // device, 6 * n
     int32_t* curve = nullptr; // device, n
     int device = 0;
+    std::vector<int64_t> curve_lo;   // host: first node of each curve (ncurves + 1)
 };
 
+// A problem: one geometry split into independent bodies (consecutive runs of
+// curves), each with its own media.  Pairs in different bodies give zero
+// blocks, so the system is block diagonal over the bodies.
 struct bm_problem {
     const bm_geom* g = nullptr;
-    bm::Media media{};
+    int nbodies = 1;
+    std::vector<bm::Media> media;        // host, per body
+    std::vector<int64_t> body_lo;        // host, first node of each body (nbodies + 1)
+    bm::Media* d_media = nullptr;        // device copy of media
+    int32_t* d_body = nullptr;           // device, body of each node (nullptr: one body)
+    int64_t* d_body_lo = nullptr;        // device copy of body_lo
 };
 
 namespace bm {
@@ -46,13 +56,16 @@ struct NodeView {
     const double* w;
     const double* kappa;
     const int32_t* curve;
+    const int32_t* body;   // body of each node; nullptr when the problem has one body
 };
 
-inline NodeView view(const bm_geom* g) {
+inline NodeView view(const bm_geom* g, const int32_t* body = nullptr) {
     const int64_t n = g->n;
     return NodeView{g->soa, g->soa + n, g->soa + 2 * n, g->soa + 3 * n,
-                    g->soa + 4 * n, g->soa + 5 * n, g->curve};
+                    g->soa + 4 * n, g->soa + 5 * n, g->curve, body};
 }
+
+inline NodeView view(const bm_problem* p) { return view(p->g, p->d_body); }
 
 // Caching device allocator (devmem.hip): blocks are reused only on the stream
 // they were released on.
@@ -62,20 +75,23 @@ void dev_free(void* p, hipStream_t s);
 // Kernel launchers (assemble.hip)
 hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurves, int64_t n,
                            double* soa, int32_t* curve, hipStream_t s);
-hipError_t launch_dense(const NodeView& v, int64_t n, const Media& m, double* A, int64_t ld,
+// `media` is the device array of per-body media (NodeView::body selects).
+hipError_t launch_dense(const NodeView& v, int64_t n, const Media* media, double* A, int64_t ld,
                         hipStream_t s);
-hipError_t launch_block(const NodeView& v, const Media& m, const int64_t* rows, int64_t nr,
+hipError_t launch_block(const NodeView& v, const Media* media, const int64_t* rows, int64_t nr,
                         const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s);
-hipError_t launch_proxy(const NodeView& v, const Media& m, const int64_t* nodes, int64_t n,
+hipError_t launch_proxy(const NodeView& v, const Media* media, const int64_t* nodes, int64_t n,
                         const double* pts, int64_t P, int dir, double* out, int64_t ld,
                         hipStream_t s);
-hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media& m, double angle,
+hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* media, double angle,
                                  double* rhs, hipStream_t s);
 // matrix-free product; `work` is a device buffer of matvec_work_doubles(n) doubles
-hipError_t launch_matvec(const NodeView& v, int64_t n, const Media& m, const double* x,
+hipError_t launch_matvec(const NodeView& v, int64_t n, const Media* media, const double* x,
                          double* y, double* work, hipStream_t s);
 int64_t matvec_work_doubles(int64_t n);
-hipError_t launch_far_field(const NodeView& v, int64_t n, const Media& m, const double* phi,
-                            const double* angles, int64_t nang, double* uinf, hipStream_t s);
+// far field of every body: uinf[b * nang + a]; body_lo = first node of each body
+hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* media,
+                            const double* phi, const double* angles, int64_t nang, double* uinf,
+                            hipStream_t s);
 
 }  // namespace bm
