@@ -149,6 +149,9 @@ typedef struct {
     int64_t sketch;        /* 0: CPQR of each box's stacked near/proxy matrix;
                               p > 0: CPQR of a Gaussian sketch of it with
                               min(rows, unknowns + p) rows (randomized ID) */
+    int64_t proxy_adapt;   /* 0: proxy_points on every proxy circle; 1: per box
+                              max(proxy_points, ceil(2 k R_p) + 32), k the larger
+                              wavenumber of the box's body, R_p the proxy radius */
 } bm_hss_opts;
 
 typedef struct {

@@ -14,6 +14,8 @@
 //    the Bessel functions stay scalar operands materialised at their use
 //    (a loop lets the compiler hoist them into vector registers, which drops
 //    the occupancy to one wave per SIMD).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace bm {
@@ -197,14 +199,17 @@ k_rhs_plane_wave(NodeView v, int64_t n, const Media* __restrict__ media, double 
 // y = A x, stage 1: workgroup b covers target i = b / ntj and one source tile;
 // it writes the tile's partial sums of rows 2i, 2i+1 to part[b] (4 doubles).
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
-k_matvec_partial(NodeView v, int64_t n, int64_t ntj, const Media* __restrict__ media,
-                 const double2* __restrict__ x, double4* __restrict__ part) {
-    const int64_t i = blockIdx.x / ntj;
-    const int64_t j = (blockIdx.x % ntj) * kThreads + threadIdx.x;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+k_matvec_partial(NodeView v, const int64_t* __restrict__ body_lo, int64_t ntj, int64_t i0,
+                 const Media* __restrict__ media, const double2* __restrict__ x,
+                 double4* __restrict__ part) {
+    // tiles run over the target's own body only (the system is block diagonal);
+    // the launch covers targets i0, i0 + 1, ...
+    const int64_t i = i0 + blockIdx.x / ntj;
     const int bi = body_of(v, i);
+    const int64_t j = body_lo[bi] + (blockIdx.x % ntj) * kThreads + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const Media m = media[bi];
-    if (j < n && body_of(v, j) == bi) {
+    if (j < body_lo[bi + 1]) {
         Block b;
         if (i == j) {
             b = diag_block(v.w[j], v.kappa[j], m);
@@ -220,7 +225,7 @@ k_matvec_partial(NodeView v, int64_t n, int64_t ntj, const Media* __restrict__ m
         acc[3] = b.v[4] * xu.y + b.v[5] * xu.x + b.v[6] * xq.y + b.v[7] * xq.x;
     }
     block_sum<4>(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = make_double4(acc[0], acc[1], acc[2], acc[3]);
+    if (threadIdx.x == 0) part[i * ntj + blockIdx.x % ntj] = make_double4(acc[0], acc[1], acc[2], acc[3]);
 }
 
 // y = A x, stage 2: sum the ntj partials of each target in a fixed order.
@@ -318,20 +323,28 @@ hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* m, d
     return hipGetLastError();
 }
 
-hipError_t launch_matvec(const NodeView& v, int64_t n, const Media* m, const double* x,
-                         double* y, double* work, hipStream_t s) {
-    const int64_t ntj = (n + kThreads - 1) / kThreads;
+hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const int64_t* body_lo,
+                         const Media* m, const double* x, double* y, double* work, hipStream_t s) {
+    const int64_t ntj = (max_body + kThreads - 1) / kThreads;
     double4* part = reinterpret_cast<double4*>(work);
-    hipLaunchKernelGGL(k_matvec_partial, dim3(static_cast<unsigned>(n * ntj)), dim3(kThreads), 0,
-                       s, v, n, ntj, m, reinterpret_cast<const double2*>(x), part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // at most 2^24 - 1 workgroups (2^32 - 1 work-items) per launch
+    const int64_t chunk = std::max<int64_t>(1, (int64_t{0xFFFFFFFF} / kThreads) / ntj);
+    for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+        const int64_t nt = std::min(chunk, n - i0);
+        hipLaunchKernelGGL(k_matvec_partial, dim3(static_cast<unsigned>(nt * ntj)), dim3(kThreads), 0,
+                           s, v, body_lo, ntj, i0, m, reinterpret_cast<const double2*>(x), part);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipSuccess;
     hipLaunchKernelGGL(k_matvec_reduce, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, n,
                        ntj, part, reinterpret_cast<double2*>(y));
     return hipGetLastError();
 }
 
-int64_t matvec_work_doubles(int64_t n) { return 4 * n * ((n + kThreads - 1) / kThreads); }
+int64_t matvec_work_doubles(int64_t n, int64_t max_body) {
+    return 4 * n * ((max_body + kThreads - 1) / kThreads);
+}
 
 hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* m,
                             const double* phi, const double* angles, int64_t nang, double* uinf,

@@ -1,5 +1,6 @@
 // C-ABI entry points declared in include/bmhss.h: argument validation, handle
 // management and error reporting.  All arithmetic runs in the HIP kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -61,7 +62,9 @@ bool finite_media(const bm_media* m) {
            std::isfinite(m->eps1) && m->k0 > 0 && m->k1 > 0 && m->eps0 > 0 && m->eps1 > 0;
 }
 
-constexpr int64_t kMaxGrid = 0xFFFFFFFFll;   // workgroups per 1D launch
+// A 1D launch may not exceed 2^32 - 1 work-items: with 256-thread workgroups
+// that is 2^24 - 1 workgroups.
+constexpr int64_t kMaxGrid = 0xFFFFFFFFll / 256;
 
 }  // namespace
 }  // namespace bm
@@ -277,11 +280,14 @@ int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t strea
     clear_error();
     if (!p || !x || !y) return fail(BM_EINVAL, "bm_matvec: null argument");
     if (x == y) return fail(BM_EINVAL, "bm_matvec: x and y must not alias");
-    if (p->g->n * ((p->g->n + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_matvec: N too large");
+    int64_t max_body = 0;
+    for (int b = 0; b < p->nbodies; ++b) max_body = std::max(max_body, p->body_lo[b + 1] - p->body_lo[b]);
     const int64_t n = p->g->n;
+    if ((max_body + 255) / 256 > kMaxGrid) return fail(BM_EINVAL, "bm_matvec: body too large");
     void* work = nullptr;
-    BM_HIP(dev_alloc(&work, matvec_work_doubles(n) * sizeof(double), stream));
-    const hipError_t e = launch_matvec(view(p), n, p->d_media, x, y, static_cast<double*>(work), stream);
+    BM_HIP(dev_alloc(&work, matvec_work_doubles(n, max_body) * sizeof(double), stream));
+    const hipError_t e = launch_matvec(view(p), n, max_body, p->d_body_lo, p->d_media, x, y,
+                                       static_cast<double*>(work), stream);
     dev_free(work, stream);
     if (e != hipSuccess) return hip_fail(e, "bm_matvec");
     return BM_OK;

@@ -3,7 +3,7 @@
 // Tree (paper Sec. III, Fig. 2): a perfect binary tree of contiguous node
 // ranges; level l has 2^l boxes, box b covers nodes [b N / 2^l, (b+1) N / 2^l).
 // Per compressed level, leaves first:
-//   1. box centres/radii and proxy circles               (k_box_geometry)
+//   1. box centres/radii (host) and proxy circles        (k_proxy_points)
 //   2. near sets: other boxes' active unknowns inside the proxy circle
 //                                                        (k_near_count/list)
 //   3. M_b = [A(U_b, near) | A(near, U_b)^T | A(U_b, proxy) | A(proxy, U_b)^T]
@@ -189,8 +189,37 @@ struct Scratch {
     }
 };
 
+// A 1D launch may not exceed 2^32 - 1 work-items (2^24 - 1 workgroups of
+// kThreads): job lists whose tiles exceed that are launched in groups.
+constexpr int64_t kMaxBlocks = int64_t{0xFFFFFFFF} / kThreads;
+
+template <class Job, class Tiles, class Launch>
+hipError_t launch_in_groups(const std::vector<Job>& jobs, Tiles tiles, Launch launch) {
+    size_t a = 0;
+    while (a < jobs.size()) {
+        size_t b = a;
+        int64_t t = 0;
+        while (b < jobs.size() && (b == a || t + tiles(jobs[b]) <= kMaxBlocks)) t += tiles(jobs[b++]);
+        if (t > kMaxBlocks) return hipErrorInvalidValue;   // one job alone is too large
+        const hipError_t e = launch(std::vector<Job>(jobs.begin() + a, jobs.begin() + b));
+        if (e != hipSuccess) return e;
+        a = b;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
+                            const PointTable& pt, const Media* media, double2* out);
+
 hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
                       const PointTable& pt, const Media* media, double2* out) {
+    return launch_in_groups(
+        jobs, [](const GenJob& j) { return ceil_div(static_cast<int64_t>(j.nt) * j.ns, kThreads); },
+        [&](const std::vector<GenJob>& g) { return launch_gen_group(sc, g, slots, pt, media, out); });
+}
+
+hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
+                            const PointTable& pt, const Media* media, double2* out) {
     if (jobs.empty()) return hipSuccess;
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
@@ -212,7 +241,15 @@ hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* 
     return hipSuccess;
 }
 
+hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs);
+
 hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
+    return launch_in_groups(
+        jobs, [](const GemmJob& j) { return ceil_div(j.M, 32) * ceil_div(j.N, 32); },
+        [&](const std::vector<GemmJob>& g) { return launch_gemm_group(sc, g); });
+}
+
+hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs) {
     if (jobs.empty()) return hipSuccess;
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
@@ -290,7 +327,17 @@ hipError_t omega_device(int64_t rows, int64_t cols, const double** out, int64_t*
     return hipSuccess;
 }
 
+hipError_t launch_sketch_group(Scratch& sc, const std::vector<SketchJob>& jobs, const double* omega,
+                               int64_t ldo);
+
 hipError_t launch_sketch(Scratch& sc, const std::vector<SketchJob>& jobs, const double* omega, int64_t ldo) {
+    return launch_in_groups(
+        jobs, [](const SketchJob& j) { return ceil_div(j.l, 64) * ceil_div(j.n, 64); },
+        [&](const std::vector<SketchJob>& g) { return launch_sketch_group(sc, g, omega, ldo); });
+}
+
+hipError_t launch_sketch_group(Scratch& sc, const std::vector<SketchJob>& jobs, const double* omega,
+                               int64_t ldo) {
     if (jobs.empty()) return hipSuccess;
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
@@ -632,6 +679,8 @@ struct BodyState {
     std::vector<int64_t> split_slots;      // per current box above the leaves: slots of the first child
     int iter_prev = -1;        // last iteration that compressed this body's boxes
     int kept_prev = -1;        // index of its first box among that iteration's boxes
+    std::vector<std::vector<double>> box_c;   // per level: centre x, y and proxy radius per box
+    std::vector<std::vector<int32_t>> box_p;  // per level: proxy points per box
 };
 
 int build_impl(bm_hss* h, hipStream_t s) {
@@ -641,7 +690,6 @@ int build_impl(bm_hss* h, hipStream_t s) {
     const int P = static_cast<int>(h->opts.proxy_points);
     const double tol = h->opts.id_tol;
     const int nbodies = p->nbodies;
-    const NodeView nv = view(p);
     EventTimer t_gen, t_cmp, t_fac;
 
     // bodies and their trees
@@ -668,8 +716,48 @@ int build_impl(bm_hss* h, hipStream_t s) {
     }
     h->levels = Lmax;
 
-    // point table: nodes, then P proxy points per box of the current iteration
-    const int64_t npts = N + leaf_boxes * P;
+    // box centres (node means), proxy radii (proxy_ratio x the largest node
+    // distance) and proxy counts of every level of every body, from the nodes
+    std::vector<double> hx(static_cast<size_t>(N)), hy(static_cast<size_t>(N));
+    BM_HIP(hipMemcpyAsync(hx.data(), g->soa, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    BM_HIP(hipMemcpyAsync(hy.data(), g->soa + N, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    BM_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> proxies_at(Lmax + 1, 0);   // proxy points of iteration t (upper bound)
+    for (int q = 0; q < nbodies; ++q) {
+        BodyState& B = bodies[q];
+        const Media& md = p->media[q];
+        const double kmax = std::max(md.k0, md.k1);
+        B.box_c.resize(B.L + 1);
+        B.box_p.resize(B.L + 1);
+        for (int l = 1; l <= B.L; ++l) {
+            const int64_t nb = int64_t{1} << l;
+            B.box_c[l].resize(3 * nb);
+            B.box_p[l].resize(nb);
+            for (int64_t b = 0; b < nb; ++b) {
+                const int64_t lo = B.nlo + ((b * B.nn) >> l), hi = B.nlo + (((b + 1) * B.nn) >> l);
+                double cx = 0, cy = 0;
+                for (int64_t i = lo; i < hi; ++i) { cx += hx[i]; cy += hy[i]; }
+                cx /= static_cast<double>(hi - lo);
+                cy /= static_cast<double>(hi - lo);
+                double r2 = 0;
+                for (int64_t i = lo; i < hi; ++i)
+                    r2 = std::max(r2, (hx[i] - cx) * (hx[i] - cx) + (hy[i] - cy) * (hy[i] - cy));
+                const double rp = h->opts.proxy_ratio * std::sqrt(r2);
+                B.box_c[l][3 * b] = cx;
+                B.box_c[l][3 * b + 1] = cy;
+                B.box_c[l][3 * b + 2] = rp;
+                int64_t pb = P;
+                if (h->opts.proxy_adapt) pb = std::max<int64_t>(P, static_cast<int64_t>(std::ceil(2.0 * kmax * rp)) + 32);
+                B.box_p[l][b] = static_cast<int32_t>(std::min<int64_t>(pb, int64_t{1} << 20));
+                proxies_at[B.L - l] += B.box_p[l][b];
+            }
+        }
+    }
+    int64_t max_proxies = 0;
+    for (int64_t v : proxies_at) max_proxies = std::max(max_proxies, v);
+
+    // point table: nodes, then the proxy points of the boxes of the current iteration
+    const int64_t npts = N + max_proxies;
     PointTable pt{};
     double* ptd = nullptr;
     Scratch persist(s);   // point table: freed (stream-ordered) when the build returns
@@ -781,25 +869,28 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (nbox == 0) break;
         auto scp = std::make_unique<Scratch>(s);   // compression scratch of this iteration
         Scratch& sc = *scp;
-        std::vector<int64_t> lo(nbox), hi(nbox);
-        std::vector<int32_t> box_body(nbox);
-        for (int b = 0; b < nbox; ++b) { lo[b] = boxes[b].lo; hi[b] = boxes[b].hi; box_body[b] = boxes[b].body; }
-        int64_t *dlo, *dhi;
-        int32_t* dbody;
-        double* box_c;
-        hipError_t e = sc.upload(&dlo, lo);
-        if (e == hipSuccess) e = sc.upload(&dhi, hi);
-        if (e == hipSuccess) e = sc.upload(&dbody, box_body);
-        if (e == hipSuccess) e = sc.alloc(&box_c, 3 * nbox);
-        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: level setup"); }
-        {
-            const double ratio = h->opts.proxy_ratio;
-            sc.rec([=]() {
-                hipLaunchKernelGGL(k_box_geometry, dim3(nbox), dim3(kThreads), 0, s, nv, dlo, dhi, dbody, ratio,
-                                   P, N, box_c, pt);
-                return hipGetLastError();
-            });
+        std::vector<int32_t> box_body(nbox), pcount(nbox);
+        std::vector<int64_t> poff(nbox + 1, 0);
+        std::vector<double> hbox_c(3 * static_cast<size_t>(nbox));
+        for (int b = 0; b < nbox; ++b) {
+            const BodyState& B = bodies[boxes[b].body];
+            box_body[b] = boxes[b].body;
+            pcount[b] = B.box_p[B.level][boxes[b].local];
+            poff[b + 1] = poff[b] + pcount[b];
+            for (int r = 0; r < 3; ++r) hbox_c[3 * b + r] = B.box_c[B.level][3 * boxes[b].local + r];
         }
+        int64_t* dpoff;
+        int32_t *dbody, *dpcount;
+        double* box_c;
+        hipError_t e = sc.upload(&dbody, box_body);
+        if (e == hipSuccess) e = sc.upload(&dpcount, pcount);
+        if (e == hipSuccess) e = sc.upload(&dpoff, std::vector<int64_t>(poff.begin(), poff.end() - 1));
+        if (e == hipSuccess) e = sc.upload(&box_c, hbox_c);
+        if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: level setup"); }
+        sc.rec([=]() {
+            hipLaunchKernelGGL(k_proxy_points, dim3(nbox), dim3(kThreads), 0, s, box_c, dbody, dpoff, dpcount, N, pt);
+            return hipGetLastError();
+        });
         // ---- active slots; each box scans the slots of its own body
         std::vector<Slot> act;
         std::vector<int64_t> soff(nbox + 1, 0), n(nbox), scan_lo(nbox), scan_hi(nbox);
@@ -867,14 +958,14 @@ int build_impl(bm_hss* h, hipStream_t s) {
             nearu[b] = counts[2 * b + 1];
         }
         const int64_t near_base = nact, prox_base = nact + nsoff[nbox];
-        const int64_t nslots_all = prox_base + static_cast<int64_t>(nbox) * P;
+        const int64_t nslots_all = prox_base + poff[nbox];
         Slot* dslots;
         if ((e = sc.alloc(&dslots, nslots_all)) != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: slot buffer"); }
         sc.rec([=]() { return hipMemcpyAsync(dslots, dact, nact * sizeof(Slot), hipMemcpyDeviceToDevice, s); });
-        std::vector<Slot> prox(static_cast<size_t>(nbox) * P);
+        std::vector<Slot> prox(static_cast<size_t>(poff[nbox]));
         for (int b = 0; b < nbox; ++b)
-            for (int q = 0; q < P; ++q)
-                prox[static_cast<size_t>(b) * P + q] = Slot{static_cast<int32_t>(N + static_cast<int64_t>(b) * P + q), 2 * q, 2 * q + 1};
+            for (int q = 0; q < pcount[b]; ++q)
+                prox[poff[b] + q] = Slot{static_cast<int32_t>(N + poff[b] + q), 2 * q, 2 * q + 1};
         Slot* dprox;
         e = sc.upload(&dprox, prox);
         {
@@ -895,7 +986,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
         for (int c = 0; c < nk; ++c) {
             const int b = kept[c];
             kn[c] = n[b];
-            km[c] = 2 * nearu[b] + 4 * P;
+            km[c] = 2 * nearu[b] + 4 * static_cast<int64_t>(pcount[b]);
             mo[c + 1] = mo[c] + kn[c] * km[c];
         }
         // ---- M_b for every kept box in one generation launch
@@ -910,10 +1001,11 @@ int build_impl(bm_hss* h, hipStream_t s) {
             const int64_t base = mo[c], m = km[c];
             jobs.push_back(GenJob{soff[b], near_base + nsoff[b], base, m, 1, na, nn, body});
             jobs.push_back(GenJob{near_base + nsoff[b], soff[b], base + nearu[b], 1, m, nn, na, body});
-            jobs.push_back(GenJob{soff[b], prox_base + static_cast<int64_t>(b) * P, base + 2 * nearu[b], m, 1, na, P, body});
-            jobs.push_back(GenJob{prox_base + static_cast<int64_t>(b) * P, soff[b], base + 2 * nearu[b] + 2 * P, 1, m, P, na, body});
+            const int32_t pb = pcount[b];
+            jobs.push_back(GenJob{soff[b], prox_base + poff[b], base + 2 * nearu[b], m, 1, na, pb, body});
+            jobs.push_back(GenJob{prox_base + poff[b], soff[b], base + 2 * nearu[b] + 2 * pb, 1, m, pb, na, body});
             entries += kn[c] * m;
-            pairs += 2 * static_cast<int64_t>(na) * (nn + P);
+            pairs += 2 * static_cast<int64_t>(na) * (nn + pb);
         }
         hipEvent_t ev;
         if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->d_media, M);

@@ -100,9 +100,8 @@ struct CopyJob {
     int32_t rows, cols;
 };
 
-__global__ void k_box_geometry(NodeView v, const int64_t* lo, const int64_t* hi,
-                               const int32_t* box_body, double proxy_ratio, int P, int64_t nnodes,
-                               double* box_c, PointTable pt);
+__global__ void k_proxy_points(const double* box_c, const int32_t* box_body, const int64_t* poff,
+                               const int32_t* pcount, int64_t nnodes, PointTable pt);
 // near sets: box b scans the candidate slots [scan_lo[b], scan_hi[b]) (its body's)
 __global__ void k_near_count(PointTable pt, const Slot* slots, const int32_t* slot_box,
                              const int64_t* scan_lo, const int64_t* scan_hi, const double* box_c,

@@ -1,7 +1,7 @@
 // Batched device kernels of the proxy-surface HSS build and solve.
 //
-//   k_box_geometry   centre and radius of every box of a level (contiguous node
-//                    ranges of the binary tree), and its proxy circle points
+//   k_proxy_points   the proxy circle points of every box of a level (centres
+//                    and radii come from the host)
 //   k_near_count     per box: active unknowns of other boxes inside its proxy
 //   k_near_list      ... and their compacted slot lists
 //   k_gen_jobs       one launch generates every WSBM block a level needs
@@ -73,46 +73,21 @@ __device__ double block_sum(double v, double* sv) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Box geometry: one workgroup per box; box b of the level covers nodes
-// [lo[b], hi[b]).  Writes centre, radius and the P proxy points of the box into
-// the point table at index nnodes + b*P + p.
+// Proxy circles: one workgroup per box; box b (centre box_c[3b], box_c[3b+1],
+// proxy radius box_c[3b+2]) gets pcount[b] equispaced proxy points, written to
+// the point table at nnodes + poff[b] + p, with radial normals, weights
+// 2 pi R_p / P_b and the box's body.
 __global__ void __launch_bounds__(kThreads)
-k_box_geometry(NodeView v, const int64_t* __restrict__ lo, const int64_t* __restrict__ hi,
-               const int32_t* __restrict__ box_body, double proxy_ratio, int P, int64_t nnodes,
-               double* __restrict__ box_c, PointTable pt) {
-    __shared__ double red[kThreads / 64];
+k_proxy_points(const double* __restrict__ box_c, const int32_t* __restrict__ box_body,
+               const int64_t* __restrict__ poff, const int32_t* __restrict__ pcount, int64_t nnodes,
+               PointTable pt) {
     const int b = blockIdx.x;
-    const int64_t a = lo[b], e = hi[b];
-    double sx = 0, sy = 0;
-    for (int64_t j = a + threadIdx.x; j < e; j += kThreads) { sx += v.x[j]; sy += v.y[j]; }
-    const double cnt = static_cast<double>(e - a);
-    const double cx = block_sum(sx, red) / cnt;
-    const double cy = block_sum(sy, red) / cnt;
-    double r2 = 0;
-    for (int64_t j = a + threadIdx.x; j < e; j += kThreads) {
-        const double dx = v.x[j] - cx, dy = v.y[j] - cy;
-        r2 = fmax(r2, dx * dx + dy * dy);
-    }
-    // max-reduction through the sum helper's storage
-    {
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) r2 = fmax(r2, __shfl_xor(r2, off, 64));
-        if (lane == 0) red[wid] = r2;
-        __syncthreads();
-        for (int w = 0; w < kThreads / 64; ++w) r2 = fmax(r2, red[w]);
-        __syncthreads();
-    }
-    const double rp = proxy_ratio * sqrt(r2);
-    if (threadIdx.x == 0) {
-        box_c[3 * b] = cx;
-        box_c[3 * b + 1] = cy;
-        box_c[3 * b + 2] = rp;
-    }
+    const double cx = box_c[3 * b], cy = box_c[3 * b + 1], rp = box_c[3 * b + 2];
+    const int P = pcount[b];
     for (int p = threadIdx.x; p < P; p += kThreads) {
         double s, c;
         sincospi(2.0 * p / P, &s, &c);
-        const int64_t q = nnodes + static_cast<int64_t>(b) * P + p;
+        const int64_t q = nnodes + poff[b] + p;
         pt.x[q] = cx + rp * c;
         pt.y[q] = cy + rp * s;
         pt.nx[q] = c;

@@ -85,10 +85,12 @@ hipError_t launch_proxy(const NodeView& v, const Media* media, const int64_t* no
                         hipStream_t s);
 hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* media, double angle,
                                  double* rhs, hipStream_t s);
-// matrix-free product; `work` is a device buffer of matvec_work_doubles(n) doubles
-hipError_t launch_matvec(const NodeView& v, int64_t n, const Media* media, const double* x,
-                         double* y, double* work, hipStream_t s);
-int64_t matvec_work_doubles(int64_t n);
+// matrix-free product over the bodies' diagonal blocks (max_body = largest body
+// in nodes, body_lo = device node offsets of the bodies); `work` is a device
+// buffer of matvec_work_doubles(n, max_body) doubles
+hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const int64_t* body_lo,
+                         const Media* media, const double* x, double* y, double* work, hipStream_t s);
+int64_t matvec_work_doubles(int64_t n, int64_t max_body);
 // far field of every body: uinf[b * nang + a]; body_lo = first node of each body
 hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* media,
                             const double* phi, const double* angles, int64_t nang, double* uinf,

@@ -143,6 +143,25 @@ def test_hss_full_size_star_sampled_residual(gpu_lib, sketch):
     assert res < 1e-6
 
 
+def test_hss_adaptive_proxy_count_high_wavenumber(gpu_lib):
+    """A star at k0 = 79.8, n = 1.98 (k1 = 158): 64 points per proxy circle
+    cannot represent the far field of the larger boxes; the adaptive count
+    max(64, ceil(2 k R_p) + 32) restores the ID tolerance's accuracy."""
+    bm = gpu_lib
+    note("hss: high-wavenumber star N=3774, fixed vs adaptive proxy counts")
+    media = sc.media_from_index(79.8, 158.4 / 79.8)
+    p, nd = setup(bm, [sc.star(0.223, 7)], [3774], media)
+    ref = wsbm.solve_dense(wsbm.assemble_dense(nd, media), wsbm.rhs_plane_wave(nd, media, 0.0))
+    errs = {}
+    for adapt in (False, True):
+        h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, proxy_adapt=adapt)
+        x = bm.bm_hss_solve(h, bm.bm_rhs_plane_wave(p, 0.0)).cpu().numpy()
+        errs[adapt] = rel(x, ref)
+        note(f"  proxy_adapt={adapt}: stats {bm.bm_hss_stats(h)}, error {errs[adapt]:.2e}")
+    assert errs[True] < HSS_BAR
+    assert errs[True] < errs[False]
+
+
 def test_hss_rejects_bad_options(gpu_lib):
     bm = gpu_lib
     media = sc.media_from_index(10.0, 1.5)
