@@ -14,9 +14,14 @@ Contents (each function cites the passage of the paper it follows):
   mie       -- closed forms for a dielectric circle: separation-of-variables
                (Mie) solution and the eigenvalues of each layer potential
   brute     -- the same entries evaluated with mpmath at 30 digits (tiny N)
+  shape     -- the backscatter intensity of a Fourier-parametrised boundary and
+               its derivative with respect to the coefficients, by Richardson
+               central differences of J or of the pieces of the adjoint identity
 
 Readings where the paper is silent (fundamental solution, normal-derivative
 definitions, the meaning of q, the one-point correction constants, the
 multi-scatterer coupling) are listed in the module docstrings; every one of
-them is pinned by a closed form in tests/test_oracle_pins.py.
+them is pinned by a closed form in tests/test_oracle_pins.py; the shape
+derivative's readings are in oracle/shape.py, pinned in
+tests/test_oracle_shape_pins.py.
 """

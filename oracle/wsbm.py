@@ -214,3 +214,19 @@ def far_field(nodes: Nodes, media, phi: np.ndarray, angles) -> np.ndarray:
     ph = np.exp(-1j * k0 * (xh @ nodes.x.T))                       # (nang, N)
     dens = (-1j * k0 * (xh @ nodes.n.T)) * u[None, :] - media.eps0 * q[None, :]
     return np.exp(0.25j * np.pi) / np.sqrt(8 * np.pi * k0) * np.sum(dens * ph * nodes.w[None, :], axis=1)
+
+
+def far_field_weights(nodes: Nodes, media, angle: float) -> np.ndarray:
+    """The weights g (2N complex) with u_inf(angle) = sum_k g_k phi_k, i.e. the
+    far_field formula above written per unknown:
+        g[2j]   = c (-i k0 xhat.n_j) exp(-i k0 xhat.x_j) w_j,
+        g[2j+1] = c (-eps0)          exp(-i k0 xhat.x_j) w_j,
+    c = e^{i pi/4}/sqrt(8 pi k0)."""
+    xh = np.array([np.cos(angle), np.sin(angle)])
+    k0 = media.k0
+    c = np.exp(0.25j * np.pi) / np.sqrt(8 * np.pi * k0)
+    ph = c * np.exp(-1j * k0 * (nodes.x @ xh)) * nodes.w
+    g = np.empty(2 * nodes.size, dtype=np.complex128)
+    g[0::2] = -1j * k0 * (nodes.n @ xh) * ph
+    g[1::2] = -media.eps0 * ph
+    return g
