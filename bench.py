@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the Burton-Miller entry generation on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode hss|dense]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode hss|dense|matvec|batch|adjoint]
 
 Workload: the star r = 1 + 0.3 cos 5 theta, N = 16384 nodes, k_ext = 50,
 n = 1.5, plane wave at a seeded angle; HSS leaf 64, proxy circle 1.5 x box
@@ -331,12 +331,108 @@ def run_hss(args):
     return out, wl
 
 
+# FP64 operations per ordered pair of the shape-derivative pair kernel, from
+# rocprofv3 --pmc SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 (FMA counted as 2),
+# profiles/pmc_counters_fourier8192.txt
+FLOP_PER_PAIR_ADJOINT = 728.6
+
+
+def run_adjoint(args):
+    """Shape gradient of the backscatter intensity J = |u_inf(-d)|^2 with respect
+    to the 64 Fourier coefficients of r = 1 + sum_{j<=32} (a_j cos jt + b_j sin jt)
+    (coefficients ~ N(0, 0.01^2), N = 8192, k0 = 40, n = 1.5): a step is the
+    forward solve (boundary samples, geometry, HSS build, solve, far field) and
+    the backward pass (far-field weights, transposed HSS solve, pair-derivative
+    contraction, chain rule to the coefficients), through the autograd Function."""
+    import numpy as np
+    import torch
+    import scatterers as sc
+    import paper_2607_00790_amd as bm
+
+    wl = sc.fourier_workload()
+    crv = wl.curves[0]
+    c0 = torch.from_numpy(np.concatenate([crv.a, crv.b])).cuda()
+    md, n = wl.media, wl.n
+    opts = dict(leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=args.id_tol)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        coef = c0.clone().requires_grad_(True)
+        J = bm.backscatter_intensity(coef, n, md.k0, md.k1, md.eps0, md.eps1, theta_inc=wl.theta_inc, **opts)
+        J.backward()
+        return coef.grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    # the phases of one step, each timed alone with events on the same stream
+    xyd = bm.bm_fourier_curve(c0, n)
+    g = bm.bm_geom_create([n], xyd)
+    p = bm.bm_problem_create(g, md.k0, md.k1, md.eps0, md.eps1)
+    obs = wl.theta_inc + np.pi
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps, r
+
+    build_ms, h = timed(lambda: bm.bm_hss_build(p, **opts), 2)
+    rhs = bm.bm_rhs_plane_wave(p, wl.theta_inc)
+    solve_ms, phi = timed(lambda: bm.bm_hss_solve(h, rhs), 3)
+    gw = bm.bm_far_field_weights(p, obs)
+    tsolve_ms, lam = timed(lambda: bm.bm_hss_solve_transpose(h, gw), 3)
+    g6 = torch.empty((6, n), dtype=torch.float64, device="cuda")
+    deriv_ms, _ = timed(lambda: bm.bm_shape_derivative(p, phi, lam, wl.theta_inc, obs, out=g6), 5)
+    pairs = n * (n - 1)
+    out = {
+        "metric": "shape gradients/s of the backscatter intensity (64 Fourier coefficients, N=8192)",
+        "value": 1e3 / ms,
+        "unit": "gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "wall_s_timed": wall,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"shape gradient, {wl.name}, J = |u_inf(-d)|^2", "n_nodes": n,
+                   "coefficients": 64, "k0": md.k0, "k1": md.k1, "theta_inc": wl.theta_inc, **opts},
+        "phases_ms": {"hss_build": build_ms, "hss_solve": solve_ms, "hss_solve_transpose": tsolve_ms,
+                      "shape_derivative": deriv_ms},
+    }
+    roof = {"bound": "alu", "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s", "traffic": None,
+            "kernel": "k_shape_pairs", "pairs": pairs, "avg_launch_ms": deriv_ms,
+            "note": "launch time of bm_shape_derivative (zeroing, pair kernel, node kernel)"}
+    if FLOP_PER_PAIR_ADJOINT:
+        tf = FLOP_PER_PAIR_ADJOINT * pairs / (deriv_ms * 1e-3) / 1e12
+        roof.update(achieved=tf, frac=tf / FP64_VECTOR_PEAK_TF, flop_per_pair=FLOP_PER_PAIR_ADJOINT)
+    else:
+        roof.update(achieved=None, frac=None, flop_per_pair=None,
+                    pairs_per_s=pairs / (deriv_ms * 1e-3))
+    out["roofline"] = roof
+    return out, wl
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["hss", "dense", "matvec", "batch"], default="hss")
+    ap.add_argument("--mode", choices=["hss", "dense", "matvec", "batch", "adjoint"], default="hss")
+    ap.add_argument("--id-tol", type=float, default=1e-12, help="adjoint mode: HSS ID tolerance")
     ap.add_argument("--batch", type=int, default=256, help="batch mode: number of stars")
     ap.add_argument("--proxy-adapt", type=int, choices=[0, 1], default=1,
                     help="batch mode: proxy points per circle max(64, ceil(2 k R_p) + 32)")
@@ -358,7 +454,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    out, wl = {"hss": run_hss, "dense": run_dense, "matvec": run_matvec, "batch": run_batch}[args.mode](args)
+    out, wl = {"hss": run_hss, "dense": run_dense, "matvec": run_matvec, "batch": run_batch,
+               "adjoint": run_adjoint}[args.mode](args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -185,6 +185,13 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
  * downward sweep G b + E x.  Returns after the solve has completed on the
  * stream. */
 int bm_hss_solve(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t stream);
+/* x = A^{-T} b (plain transpose, no conjugation; same layout as bm_hss_solve),
+ * from the same factors: the solve's data flow reversed with every factor
+ * transposed (y_0 = b, G^T and E^T per box from the leaves up, the transposed
+ * root inverse, then (F^T)^T per box from the root down).  This is the adjoint
+ * solve A^T lam = g of a shape derivative.  x may alias b.  Returns after the
+ * solve has completed on the stream. */
+int bm_hss_solve_transpose(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t stream);
 int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out);
 
 /* Per compressed level (0 = leaves, up to compressed_levels - 1): sizes of the
@@ -201,7 +208,41 @@ typedef struct {
 int bm_hss_level(const bm_hss* h, int level, bm_hss_level_t* out);
 
 int bm_hss_destroy(bm_hss* h);
+/* ---- Shape derivatives of far-field objectives (adjoint method) ----
+ * The paper solves Eq. (3) for a fixed boundary; these entry points
+ * differentiate the discrete solution with respect to the boundary samples.
+ *
+ * Far-field weights: g (device, 2N complex) such that body b's far field at
+ * `angle` is u_inf,b = sum over b's unknowns k of g_k phi_k (the formula of
+ * bm_far_field written per unknown). */
+int bm_far_field_weights(const bm_problem* p, double angle, double* g, hipStream_t stream);
 
+/* Derivative of L_b = g_b^T phi + lam^T (rhs - A phi) over each body b, with
+ * phi and lam fixed, with respect to the six samples (x, y, x', y', x'', y'')
+ * of every node, through the positions, normals, weights and curvatures the
+ * geometry derives from them (Sec. II) and the one-point corrected diagonal:
+ *   grad[q*N + i] = Re(coef_b dL_b / d s_q(i))   (device, 6 x N FP64 output),
+ * g = far-field weights at obs_angle, rhs = the plane wave at inc_angle
+ * (bm_rhs_plane_wave).  For phi = A^-1 rhs and A^T lam = g, dL_b is the
+ * derivative of u_inf,b(obs_angle); coef (device, nbodies complex) weights
+ * the bodies, e.g. coef_b = 2 conj(u_inf,b) for |u_inf,b|^2.  coef = NULL
+ * takes that weight: grad is then the gradient of sum_b |u_inf,b(obs_angle)|^2.
+ * phi, lam: device, 2N complex.  The pair sums use FP64 atomic additions, so
+ * the last bits may differ between runs.  Asynchronous on `stream`. */
+int bm_shape_derivative(const bm_problem* p, const double* phi, const double* lam, double inc_angle,
+                        double obs_angle, const double* coef, double* grad, hipStream_t stream);
+
+/* Samples of the closed curve x(t) = (cx, cy) + radius r(t) (cos t, sin t),
+ * r(t) = 1 + sum_{j=1..M} (a_j cos jt + b_j sin jt), at t_i = 2 pi i / n:
+ * xyd (device, 6 x n, the layout bm_geom_create takes); coef (device, 2M FP64)
+ * = a_1..a_M, b_1..b_M.  The curve must stay star-shaped (r > 0) for the
+ * geometry to be valid; that is checked by bm_geom_create. */
+int bm_fourier_curve(const double* coef, int nmodes, double radius, double cx, double cy, int64_t n,
+                     double* xyd, hipStream_t stream);
+/* The chain rule of bm_fourier_curve: out[m] = sum over i and rows q of
+ * grad[q*n + i] d xyd[q*n + i] / d coef_m (device, 2M FP64), e.g. a shape
+ * derivative from bm_shape_derivative turned into d/d(a_1..a_M, b_1..b_M). */
+int bm_fourier_chain(const double* grad, int64_t n, int nmodes, double radius, double* out, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -80,27 +80,35 @@ def gradient_fd(coef, n: int, media, theta_inc: float, h: float = 1e-4) -> np.nd
     return g
 
 
-def _matvec_rows(nd, media, x, chunk=256):
+def _row_block(args):
+    """Rows of A for the node range [r0, r1) (times x when x is given)."""
+    nd, media, r0, r1, x = args
+    blk = wsbm.assemble_rows(nd, media, np.arange(r0, r1))
+    return blk if x is None else blk @ x
+
+
+def _row_jobs(nd, media, x, chunk):
+    return [(nd, media, r0, min(nd.size, r0 + chunk), x) for r0 in range(0, nd.size, chunk)]
+
+
+def _matvec_rows(nd, media, x, chunk=256, mapper=map):
     """A x assembled a block of rows at a time (nothing of size N^2 is kept)."""
-    y = np.empty(2 * nd.size, dtype=np.complex128)
-    for r0 in range(0, nd.size, chunk):
-        rows = np.arange(r0, min(nd.size, r0 + chunk))
-        y[2 * r0:2 * rows[-1] + 2] = wsbm.assemble_rows(nd, media, rows) @ x
-    return y
+    return np.concatenate(list(mapper(_row_block, _row_jobs(nd, media, x, chunk))))
 
 
 def directional_derivative(coef, v, n: int, media, theta_inc: float, h: float = 1e-4,
-                           chunk: int = 256):
+                           chunk: int = 256, mapper=map):
     """(u_inf, J, dJ.v) from one dense LU and differentiated pieces (see the module
-    docstring).  Assembly goes by blocks of rows, so N in the thousands fits."""
+    docstring).  Assembly goes by blocks of rows, so N in the thousands fits;
+    `mapper` (e.g. a process pool's map) may evaluate the blocks in parallel."""
     coef = np.asarray(coef, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
     obs = theta_inc + np.pi
     nd = nodes_of(coef, n)
     A = np.empty((2 * n, 2 * n), dtype=np.complex128)
-    for r0 in range(0, n, chunk):
-        rows = np.arange(r0, min(n, r0 + chunk))
-        A[2 * r0:2 * rows[-1] + 2] = wsbm.assemble_rows(nd, media, rows)
+    for (_, _, r0, r1, _), blk in zip(_row_jobs(nd, media, None, chunk),
+                                      mapper(_row_block, _row_jobs(nd, media, None, chunk))):
+        A[2 * r0:2 * r1] = blk
     b = wsbm.rhs_plane_wave(nd, media, theta_inc)
     g = wsbm.far_field_weights(nd, media, obs)
     lu = scipy.linalg.lu_factor(A, overwrite_a=True, check_finite=False)
@@ -115,6 +123,6 @@ def directional_derivative(coef, v, n: int, media, theta_inc: float, h: float = 
 
     d_gphi = _richardson(lambda s: wsbm.far_field_weights(moved(s), media, obs) @ phi, h)
     d_b = _richardson(lambda s: wsbm.rhs_plane_wave(moved(s), media, theta_inc), h)
-    d_aphi = _richardson(lambda s: _matvec_rows(moved(s), media, phi, chunk), h)
+    d_aphi = _richardson(lambda s: _matvec_rows(moved(s), media, phi, chunk, mapper), h)
     du = d_gphi + lam @ (d_b - d_aphi)
     return u, abs(u) ** 2, 2.0 * np.real(np.conj(u) * du)

@@ -26,6 +26,20 @@ from ._binding import (  # noqa: F401
     bm_hss_solve,
     bm_hss_stats,
     bm_hss_level,
+    bm_hss_solve_transpose,
+    bm_far_field_weights,
+    bm_shape_derivative,
+    bm_fourier_curve,
+    bm_fourier_chain,
     lib_path,
     load,
 )
+from .shape import backscatter_intensity  # noqa: F401
+
+
+def __getattr__(name):
+    # the torch.autograd.Function subclass, created on first use
+    if name == "BackscatterIntensity":
+        from .shape import _function_class
+        return _function_class()
+    raise AttributeError(name)

@@ -80,6 +80,11 @@ def load():
     sig.update({
         "bm_hss_build": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssOpts), c_vp, ctypes.POINTER(c_vp)]),
         "bm_hss_solve": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp]),
+        "bm_hss_solve_transpose": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp]),
+        "bm_far_field_weights": (ctypes.c_int, [c_vp, c_dbl, c_vp, c_vp]),
+        "bm_shape_derivative": (ctypes.c_int, [c_vp, c_vp, c_vp, c_dbl, c_dbl, c_vp, c_vp, c_vp]),
+        "bm_fourier_curve": (ctypes.c_int, [c_vp, ctypes.c_int, c_dbl, c_dbl, c_dbl, c_i64, c_vp, c_vp]),
+        "bm_fourier_chain": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_dbl, c_vp, c_vp]),
         "bm_hss_stats": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssStats)]),
         "bm_hss_level": (ctypes.c_int, [c_vp, ctypes.c_int, ctypes.POINTER(_HssLevel)]),
         "bm_hss_destroy": (ctypes.c_int, [c_vp]),
@@ -184,7 +189,7 @@ def bm_geom_create(n_per_curve, xyd, stream=None) -> Geometry:
         if keep.shape != (6, int(sizes.sum())):
             raise ValueError("xyd must have shape (6, sum(n_per_curve))")
         ptr, on_dev = c_vp(keep.ctypes.data), 0
-    _check(_LIB.bm_geom_create(len(sizes), sizes.ctypes.data_as(ctypes.POINTER(c_i64)), ptr, on_dev,
+    _check(load().bm_geom_create(len(sizes), sizes.ctypes.data_as(ctypes.POINTER(c_i64)), ptr, on_dev,
                                _stream(stream), ctypes.byref(out)))
     del keep
     return Geometry(out, sizes)
@@ -198,7 +203,7 @@ def bm_geom_nodes(g: Geometry, stream=None):
     """(6, N) float64 device tensor: x, y, nx, ny, w, kappa."""
     torch = _torch()
     out = torch.empty((6, g.n), dtype=torch.float64, device="cuda")
-    _check(_LIB.bm_geom_nodes(g._h, _dev_ptr(out), _stream(stream)))
+    _check(load().bm_geom_nodes(g._h, _dev_ptr(out), _stream(stream)))
     return out
 
 
@@ -206,7 +211,7 @@ def bm_problem_create(g: Geometry, k0, k1, eps0, eps1) -> Problem:
     load()
     m = _Media(float(k0), float(k1), float(eps0), float(eps1))
     out = c_vp()
-    _check(_LIB.bm_problem_create(g._h, ctypes.byref(m), ctypes.byref(out)))
+    _check(load().bm_problem_create(g._h, ctypes.byref(m), ctypes.byref(out)))
     return Problem(out, g, (float(k0), float(k1), float(eps0), float(eps1)))
 
 
@@ -218,7 +223,7 @@ def bm_problem_create_bodies(g: Geometry, body_of_curve, media) -> Problem:
     nb = len(media)
     arr = (_Media * nb)(*[_Media(*(float(v) for v in m)) for m in media])
     out = c_vp()
-    _check(_LIB.bm_problem_create_bodies(g._h, nb, boc, arr, ctypes.byref(out)))
+    _check(load().bm_problem_create_bodies(g._h, nb, boc, arr, ctypes.byref(out)))
     return Problem(out, g, [tuple(float(v) for v in m) for m in media], nbodies=nb)
 
 
@@ -226,7 +231,7 @@ def bm_rhs_plane_wave(p: Problem, angle: float, out=None, stream=None):
     torch = _torch()
     if out is None:
         out = torch.empty(2 * p.n, dtype=torch.complex128, device="cuda")
-    _check(_LIB.bm_rhs_plane_wave(p._h, float(angle), _dev_ptr(out, torch.complex128, "out"),
+    _check(load().bm_rhs_plane_wave(p._h, float(angle), _dev_ptr(out, torch.complex128, "out"),
                                   _stream(stream)))
     return out
 
@@ -238,7 +243,7 @@ def bm_assemble_dense(p: Problem, out=None, stream=None):
         out = torch.empty((n2, n2), dtype=torch.complex128, device="cuda")
     if out.dim() != 2 or out.shape[0] != n2 or out.shape[1] < n2:
         raise ValueError("out must be (2N, >=2N)")
-    _check(_LIB.bm_assemble_dense(p._h, _dev_ptr(out, torch.complex128, "out"), out.stride(0),
+    _check(load().bm_assemble_dense(p._h, _dev_ptr(out, torch.complex128, "out"), out.stride(0),
                                   _stream(stream)))
     return out
 
@@ -250,7 +255,7 @@ def bm_assemble_block(p: Problem, rows, cols, out=None, stream=None):
     nr, nc = rows.numel(), cols.numel()
     if out is None:
         out = torch.empty((2 * nr, 2 * nc), dtype=torch.complex128, device="cuda")
-    _check(_LIB.bm_assemble_block(p._h, _dev_ptr(rows), nr, _dev_ptr(cols), nc,
+    _check(load().bm_assemble_block(p._h, _dev_ptr(rows), nr, _dev_ptr(cols), nc,
                                   _dev_ptr(out, torch.complex128, "out"), out.stride(0),
                                   _stream(stream)))
     return out
@@ -264,7 +269,7 @@ def bm_assemble_proxy(p: Problem, nodes, pts, direction: int, out=None, stream=N
     shape = (2 * n, 2 * P) if direction == 0 else (2 * P, 2 * n)
     if out is None:
         out = torch.empty(shape, dtype=torch.complex128, device="cuda")
-    _check(_LIB.bm_assemble_proxy(p._h, _dev_ptr(nodes), n, _dev_ptr(pts, torch.float64, "pts"), P,
+    _check(load().bm_assemble_proxy(p._h, _dev_ptr(nodes), n, _dev_ptr(pts, torch.float64, "pts"), P,
                                   int(direction), _dev_ptr(out, torch.complex128, "out"),
                                   out.stride(0), _stream(stream)))
     return out
@@ -274,7 +279,7 @@ def bm_matvec(p: Problem, x, out=None, stream=None):
     torch = _torch()
     if out is None:
         out = torch.empty(2 * p.n, dtype=torch.complex128, device="cuda")
-    _check(_LIB.bm_matvec(p._h, _dev_ptr(x, torch.complex128, "x"),
+    _check(load().bm_matvec(p._h, _dev_ptr(x, torch.complex128, "x"),
                           _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
     return out
 
@@ -284,7 +289,7 @@ def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
     angles = angles.to(device="cuda", dtype=torch.float64).contiguous()
     if out is None:
         out = torch.empty(p.nbodies * angles.numel(), dtype=torch.complex128, device="cuda")
-    _check(_LIB.bm_far_field(p._h, _dev_ptr(phi, torch.complex128, "phi"), _dev_ptr(angles),
+    _check(load().bm_far_field(p._h, _dev_ptr(phi, torch.complex128, "phi"), _dev_ptr(angles),
                              angles.numel(), _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
     return out
 
@@ -297,7 +302,7 @@ def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1
     opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol), int(sketch),
                     int(bool(proxy_adapt)))
     out = c_vp()
-    _check(_LIB.bm_hss_build(p._h, ctypes.byref(opts), _stream(stream), ctypes.byref(out)))
+    _check(load().bm_hss_build(p._h, ctypes.byref(opts), _stream(stream), ctypes.byref(out)))
     return HSS(out, p)
 
 
@@ -307,19 +312,83 @@ def bm_hss_solve(h: HSS, b, out=None, stream=None):
     nrhs = 1 if b.dim() == 1 else b.shape[0]
     if out is None:
         out = torch.empty_like(b)
-    _check(_LIB.bm_hss_solve(h._h, _dev_ptr(b, torch.complex128, "b"),
+    _check(load().bm_hss_solve(h._h, _dev_ptr(b, torch.complex128, "b"),
                              _dev_ptr(out, torch.complex128, "out"), nrhs, _stream(stream)))
     return out
 
 
 def bm_hss_stats(h: HSS) -> dict:
     s = _HssStats()
-    _check(_LIB.bm_hss_stats(h._h, ctypes.byref(s)))
+    _check(load().bm_hss_stats(h._h, ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in _HssStats._fields_}
 
 
 def bm_hss_level(h: HSS, level: int) -> dict:
     """Sizes and ranks of compressed level `level` (0 = leaves)."""
     s = _HssLevel()
-    _check(_LIB.bm_hss_level(h._h, int(level), ctypes.byref(s)))
+    _check(load().bm_hss_level(h._h, int(level), ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in _HssLevel._fields_}
+
+
+def bm_hss_solve_transpose(h: HSS, b, out=None, stream=None):
+    """x = A^{-T} b with the factors of bm_hss_build; b as in bm_hss_solve."""
+    torch = _torch()
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    if out is None:
+        out = torch.empty_like(b)
+    _check(load().bm_hss_solve_transpose(h._h, _dev_ptr(b, torch.complex128, "b"),
+                                       _dev_ptr(out, torch.complex128, "out"), nrhs, _stream(stream)))
+    return out
+
+
+def bm_far_field_weights(p: Problem, angle: float, out=None, stream=None):
+    """g (2N complex): body b's far field at `angle` is the sum of g_k phi_k over its unknowns."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(2 * p.n, dtype=torch.complex128, device="cuda")
+    _check(load().bm_far_field_weights(p._h, float(angle), _dev_ptr(out, torch.complex128, "out"),
+                                     _stream(stream)))
+    return out
+
+
+def bm_shape_derivative(p: Problem, phi, lam, inc_angle: float, obs_angle: float, coef=None, out=None,
+                        stream=None):
+    """(6, N) float64: Re(coef_b dL_b/d samples), L_b = g_b.phi + lam.(rhs - A phi);
+    coef None: coef_b = 2 conj(u_inf,b(obs_angle)), the gradient of sum_b |u_inf,b|^2."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((6, p.n), dtype=torch.float64, device="cuda")
+    cptr = c_vp(None) if coef is None else _dev_ptr(coef, torch.complex128, "coef")
+    if coef is not None and coef.numel() != p.nbodies:
+        raise ValueError("coef needs one complex value per body")
+    _check(load().bm_shape_derivative(p._h, _dev_ptr(phi, torch.complex128, "phi"),
+                                    _dev_ptr(lam, torch.complex128, "lam"), float(inc_angle),
+                                    float(obs_angle), cptr, _dev_ptr(out, torch.float64, "out"),
+                                    _stream(stream)))
+    return out
+
+
+def bm_fourier_curve(coef, n: int, radius: float = 1.0, center=(0.0, 0.0), out=None, stream=None):
+    """(6, n) float64 samples of r(t) = 1 + sum_j (a_j cos jt + b_j sin jt);
+    coef: device float64 (a_1..a_M, b_1..b_M)."""
+    torch = _torch()
+    M = coef.numel() // 2
+    if coef.numel() != 2 * M:
+        raise ValueError("coef must hold a_1..a_M, b_1..b_M")
+    if out is None:
+        out = torch.empty((6, int(n)), dtype=torch.float64, device="cuda")
+    cptr = _dev_ptr(coef, torch.float64, "coef") if M > 0 else c_vp(None)
+    _check(load().bm_fourier_curve(cptr, M, float(radius), float(center[0]), float(center[1]), int(n),
+                                 _dev_ptr(out, torch.float64, "out"), _stream(stream)))
+    return out
+
+
+def bm_fourier_chain(grad, nmodes: int, radius: float = 1.0, out=None, stream=None):
+    """(2 nmodes,) float64: a (6, n) sample gradient turned into d/d(a_1..a_M, b_1..b_M)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(2 * int(nmodes), dtype=torch.float64, device="cuda")
+    n = grad.shape[-1]
+    _check(load().bm_fourier_chain(_dev_ptr(grad, torch.float64, "grad"), int(n), int(nmodes), float(radius),
+                                 _dev_ptr(out, torch.float64, "out"), _stream(stream)))
+    return out

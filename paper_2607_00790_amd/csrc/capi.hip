@@ -133,7 +133,7 @@ int bm_geom_create(int ncurves, const int64_t* n_per_curve, const double* xyd, i
                            hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = launch_geometry(d_xyd, d_off, ncurves, n, g->soa, g->curve, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    (void)hipFree(d_xyd);
+    g->xyd = d_xyd;   // kept: the shape derivative's chain rule needs the samples
     (void)hipFree(d_off);
     if (e != hipSuccess) {
         bm_geom_destroy(g);
@@ -147,6 +147,7 @@ int bm_geom_destroy(bm_geom* g) {
     if (!g) return BM_OK;
     (void)hipFree(g->soa);
     (void)hipFree(g->curve);
+    (void)hipFree(g->xyd);
     delete g;
     return BM_OK;
 }
@@ -187,6 +188,8 @@ int bm_problem_create_bodies(const bm_geom* g, int nbodies, const int32_t* body_
         }
     }
     lo[nbodies] = g->n;
+    std::vector<int64_t> tiles(nbodies + 1, 0);
+    for (int b = 0; b < nbodies; ++b) tiles[b + 1] = tiles[b] + pair_tiles(lo[b + 1] - lo[b]);
     const BesselTable* tab = nullptr;
     BM_HIP(device_table(&tab));
     bm_problem* p = new (std::nothrow) bm_problem;
@@ -194,6 +197,7 @@ int bm_problem_create_bodies(const bm_geom* g, int nbodies, const int32_t* body_
     p->g = g;
     p->nbodies = nbodies;
     p->body_lo = lo;
+    p->tile_off = tiles;
     for (int b = 0; b < nbodies; ++b)
         p->media.push_back(make_media(media[b].k0, media[b].k1, media[b].eps0, media[b].eps1, tab));
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->d_media), nbodies * sizeof(Media));
@@ -202,6 +206,9 @@ int bm_problem_create_bodies(const bm_geom* g, int nbodies, const int32_t* body_
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_body_lo), (nbodies + 1) * sizeof(int64_t));
     if (e == hipSuccess)
         e = hipMemcpy(p->d_body_lo, lo.data(), (nbodies + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_tile_off), (nbodies + 1) * sizeof(int64_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_tile_off, tiles.data(), (nbodies + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && nbodies > 1) {
         std::vector<int32_t> nb(static_cast<size_t>(g->n));
         for (int b = 0; b < nbodies; ++b)
@@ -226,6 +233,7 @@ int bm_problem_destroy(bm_problem* p) {
     (void)hipFree(p->d_media);
     (void)hipFree(p->d_body);
     (void)hipFree(p->d_body_lo);
+    (void)hipFree(p->d_tile_off);
     delete p;
     return BM_OK;
 }
@@ -301,6 +309,54 @@ int bm_far_field(const bm_problem* p, const double* phi, const double* angles, i
     if (!phi || !angles || !uinf) return fail(BM_EINVAL, "bm_far_field: null array");
     if (nang > (int64_t{1} << 31)) return fail(BM_EINVAL, "bm_far_field: too many angles");
     BM_HIP(launch_far_field(view(p), p->nbodies, p->d_body_lo, p->d_media, phi, angles, nang, uinf, stream));
+    return BM_OK;
+}
+
+int bm_far_field_weights(const bm_problem* p, double angle, double* g, hipStream_t stream) {
+    clear_error();
+    if (!p || !g) return fail(BM_EINVAL, "bm_far_field_weights: null argument");
+    if (!std::isfinite(angle)) return fail(BM_EINVAL, "bm_far_field_weights: non-finite angle");
+    BM_HIP(launch_far_weights(view(p), p->g->n, p->d_media, angle, g, stream));
+    return BM_OK;
+}
+
+int bm_shape_derivative(const bm_problem* p, const double* phi, const double* lam, double inc_angle,
+                        double obs_angle, const double* coef, double* grad, hipStream_t stream) {
+    clear_error();
+    if (!p || !phi || !lam || !grad) return fail(BM_EINVAL, "bm_shape_derivative: null argument");
+    if (!std::isfinite(inc_angle) || !std::isfinite(obs_angle))
+        return fail(BM_EINVAL, "bm_shape_derivative: non-finite angle");
+    const int64_t n = p->g->n;
+    const int64_t ntiles = p->tile_off[p->nbodies];
+    void* work = nullptr;
+    BM_HIP(dev_alloc(&work, shape_work_doubles(n, p->nbodies) * sizeof(double), stream));
+    const hipError_t e = launch_shape_derivative(view(p), p->g->xyd, n, p->nbodies, p->d_body_lo, p->d_tile_off,
+                                                 ntiles, p->d_media, p->media[0].tab, phi, lam, inc_angle,
+                                                 obs_angle, coef, grad,
+                                                 static_cast<double*>(work), stream);
+    dev_free(work, stream);
+    if (e != hipSuccess) return hip_fail(e, "bm_shape_derivative");
+    return BM_OK;
+}
+
+int bm_fourier_curve(const double* coef, int nmodes, double radius, double cx, double cy, int64_t n,
+                     double* xyd, hipStream_t stream) {
+    clear_error();
+    if (!xyd || (nmodes > 0 && !coef)) return fail(BM_EINVAL, "bm_fourier_curve: null argument");
+    if (nmodes < 0 || n < 1 || n > (int64_t{1} << 31) || !(radius > 0) || !std::isfinite(radius) ||
+        !std::isfinite(cx) || !std::isfinite(cy))
+        return fail(BM_EINVAL, "bm_fourier_curve: need nmodes >= 0, 1 <= n <= 2^31, finite radius > 0");
+    BM_HIP(launch_fourier_curve(coef, nmodes, radius, cx, cy, n, xyd, stream));
+    return BM_OK;
+}
+
+int bm_fourier_chain(const double* grad, int64_t n, int nmodes, double radius, double* out, hipStream_t stream) {
+    clear_error();
+    if (!grad || !out) return fail(BM_EINVAL, "bm_fourier_chain: null argument");
+    if (nmodes < 1 || nmodes > (1 << 20) || n < 1 || n > (int64_t{1} << 31) || !(radius > 0) ||
+        !std::isfinite(radius))
+        return fail(BM_EINVAL, "bm_fourier_chain: need 1 <= nmodes <= 2^20, 1 <= n <= 2^31, finite radius > 0");
+    BM_HIP(launch_fourier_chain(grad, n, nmodes, radius, out, stream));
     return BM_OK;
 }
 

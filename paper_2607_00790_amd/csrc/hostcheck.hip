@@ -1,9 +1,11 @@
 // Host-compiled instances of the device math (bessel.hpp, wsbm_pair.hpp) for
 // CPU unit tests.  This library is loaded only by the test suite, to check the
 // kernels' arithmetic without a GPU; the product library never calls it.
+#include <cmath>
 #include <cstdint>
+#include <vector>
 
-#include "wsbm_pair.hpp"
+#include "wsbm_adjoint.hpp"
 
 extern "C" {
 
@@ -45,6 +47,88 @@ int bmh_system_blocks(const double* soa, const int32_t* curve, int64_t N, const 
                 r1[q] = blk.v[4 + q];
             }
         }
+    }
+    return 0;
+}
+
+// Pair derivatives of lam_i^T A_ij phi_j as the shape-derivative kernel forms
+// them.  Per pair q: in[16*q ..]: tx, ty, tnx, tny, l0 (re, im), l1 (re, im),
+// sx, sy, snx, sny, sw, interior (0/1), unused x2; phi[4*q ..] = u (re, im),
+// q (re, im); out[14*q ..] = re/im of d/drho (x, y), d/dn_i (x, y), d/dn_j (x, y), d/dw_j.
+int bmh_pair_adjoint(const double* in, const double* phi, int64_t n, const double* media, double* out) {
+    const bm::Media m = bm::make_media(media[0], media[1], media[2], media[3], &bm_bessel_coef::kTable);
+    for (int64_t q = 0; q < n; ++q) {
+        const double* a = in + 16 * q;
+        const double* f = phi + 4 * q;
+        const bm::PairAdjoint pa = bm::pair_adjoint(a[0], a[1], a[2], a[3], make_double2(a[4], a[5]),
+                                                    make_double2(a[6], a[7]), a[8], a[9], a[10], a[11], a[12],
+                                                    make_double2(f[0], f[1]), make_double2(f[2], f[3]), m,
+                                                    a[13] != 0.0);
+        const double2 v[7] = {pa.g_rho[0], pa.g_rho[1], pa.g_ni[0], pa.g_ni[1], pa.g_nj[0], pa.g_nj[1], pa.g_w};
+        for (int c = 0; c < 7; ++c) {
+            out[14 * q + 2 * c] = v[c].x;
+            out[14 * q + 2 * c + 1] = v[c].y;
+        }
+    }
+    return 0;
+}
+
+// Derivatives of lam_i^T A_ii phi_i with respect to w and kappa.  in[8*q ..]:
+// w, kappa, l0 (re, im), l1 (re, im), unused x2; phi as above;
+// out[4*q ..] = d/dw (re, im), d/dkappa (re, im).
+int bmh_diag_adjoint(const double* in, const double* phi, int64_t n, const double* media, double* out) {
+    const bm::Media m = bm::make_media(media[0], media[1], media[2], media[3], &bm_bessel_coef::kTable);
+    for (int64_t q = 0; q < n; ++q) {
+        const double* a = in + 8 * q;
+        const double* f = phi + 4 * q;
+        double2 gw, gk;
+        bm::diag_adjoint(a[0], a[1], m, make_double2(a[2], a[3]), make_double2(a[4], a[5]),
+                         make_double2(f[0], f[1]), make_double2(f[2], f[3]), gw, gk);
+        out[4 * q] = gw.x;
+        out[4 * q + 1] = gw.y;
+        out[4 * q + 2] = gk.x;
+        out[4 * q + 3] = gk.y;
+    }
+    return 0;
+}
+
+// The whole shape derivative of one body on the host, with the kernels' pair
+// and node arithmetic: soa 6 x N (x, y, nx, ny, w, kappa), xyd 6 x N samples,
+// curve ids, lam and phi 2N complex (interleaved), coef complex, inc/obs
+// angles; grad 6 x N.
+int bmh_shape_derivative(const double* soa, const double* xyd, const int32_t* curve, int64_t N,
+                         const double* media, const double* lam, const double* phi, double inc, double obs,
+                         const double* coef, double* grad) {
+    const bm::Media m = bm::make_media(media[0], media[1], media[2], media[3], &bm_bessel_coef::kTable);
+    const double *x = soa, *y = soa + N, *nx = soa + 2 * N, *ny = soa + 3 * N, *w = soa + 4 * N,
+                 *kap = soa + 5 * N;
+    auto c2 = [](const double* p, int64_t k) { return make_double2(p[2 * k], p[2 * k + 1]); };
+    std::vector<double> acc(18 * N, 0.0);
+    for (int64_t i = 0; i < N; ++i) {
+        for (int64_t j = 0; j < N; ++j) {
+            if (i == j) continue;
+            const bm::PairAdjoint pa = bm::pair_adjoint(x[i], y[i], nx[i], ny[i], c2(lam, 2 * i), c2(lam, 2 * i + 1),
+                                                        x[j], y[j], nx[j], ny[j], w[j], c2(phi, 2 * j),
+                                                        c2(phi, 2 * j + 1), m, curve[i] == curve[j]);
+            const double2 t[4] = {pa.g_rho[0], pa.g_rho[1], pa.g_ni[0], pa.g_ni[1]};
+            const double2 u[5] = {pa.g_rho[0], pa.g_rho[1], pa.g_nj[0], pa.g_nj[1], pa.g_w};
+            for (int c = 0; c < 4; ++c) {
+                acc[18 * i + 2 * c] += t[c].x;
+                acc[18 * i + 2 * c + 1] += t[c].y;
+            }
+            for (int c = 0; c < 5; ++c) {
+                acc[18 * j + 8 + 2 * c] += u[c].x;
+                acc[18 * j + 8 + 2 * c + 1] += u[c].y;
+            }
+        }
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        double g[6];
+        bm::node_adjoint(x[i], y[i], nx[i], ny[i], w[i], kap[i], xyd[2 * N + i], xyd[3 * N + i], xyd[4 * N + i],
+                         xyd[5 * N + i], m, c2(lam, 2 * i), c2(lam, 2 * i + 1), c2(phi, 2 * i), c2(phi, 2 * i + 1),
+                         acc.data() + 18 * i, std::cos(inc), std::sin(inc), std::cos(obs), std::sin(obs),
+                         make_double2(coef[0], coef[1]), g);
+        for (int q = 0; q < 6; ++q) grad[q * N + i] = g[q];
     }
     return 0;
 }

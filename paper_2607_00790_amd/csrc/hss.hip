@@ -1393,6 +1393,195 @@ int build_impl(bm_hss* h, hipStream_t s) {
     return BM_OK;
 }
 
+// The solution operator x = M b of the factorisation (M ~ A^-1):
+//   upward    v_l = F_l^T v_{l-1}            (v_{-1} = b, per box: its input slice)
+//   roots     xr = Rinv v_stage
+//   downward  y_l = G_l v_{l-1} + E_l y_{l+1} (y_{l+1} of the parent, or xr)
+//   x = y_0 (or xr for a body that was never compressed).
+// trans = true applies M^T (plain transpose, no conjugation), reusing the same
+// factors with every edge of that data flow reversed:
+//   y_0 = c;  for l = 0, 1, ..: v_{l-1} = G_l^T y_l  and  y_{l+1} (or xr) = E_l^T y_l
+//   v_stage = Rinv^T xr;  for l = .., 1, 0: v_{l-1} += F_l v_l;  result v_{-1}.
+// Every slice of a y or v vector is written by exactly one box (a parent's
+// unknowns are its children's skeletons; an iteration's output feeds either
+// the next iteration or a root), so the first write of each slice overwrites.
+int solve_impl(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t s, bool trans) {
+    const int nl = static_cast<int>(h->lv.size());
+    const int64_t N2 = 2 * h->N;
+    Scratch sc(s);
+    std::vector<double2*> bt(nl), xl(nl);
+    hipError_t e = hipSuccess;
+    for (int li = 0; li < nl && e == hipSuccess; ++li) {
+        e = sc.alloc(&bt[li], h->lv[li].nk * nrhs);
+        if (e == hipSuccess) e = sc.alloc(&xl[li], h->lv[li].nu * nrhs);
+    }
+    double2* xroot;
+    if (e == hipSuccess) e = sc.alloc(&xroot, h->Ktot * nrhs);
+    if (e != hipSuccess) { sc.release(); return hip_fail(e, "bm_hss_solve: buffers"); }
+    const double2* bin = reinterpret_cast<const double2*>(b);
+    if (trans) {
+        double2* z = reinterpret_cast<double2*>(x);
+        // output of iteration li's transposed G / F^T products: the result, or
+        // the adjoint of the previous iteration's F^T output
+        auto stage_out = [&](int li, double2** ptr, int64_t* ld) {
+            if (li < 0) { *ptr = z; *ld = N2; }
+            else { *ptr = bt[li]; *ld = h->lv[li].nk; }
+        };
+        // y_0 = c per body: into the first iteration's output, or the root of
+        // a body that was never compressed
+        {
+            std::vector<CopyJob> cp;
+            const bm_problem* p = h->p;
+            for (const RootJob& r : h->roots) {
+                const int64_t lo = p->body_lo[r.body], nn2 = 2 * (p->body_lo[r.body + 1] - lo);
+                double2* dst;
+                int64_t ld;
+                if (r.stage < 0) {
+                    dst = xroot + r.x_off;
+                    ld = h->Ktot;
+                } else {
+                    const LevelFactor& f0 = h->lv[0];
+                    int64_t off = -1;
+                    for (int q = 0; q < f0.nb; ++q)
+                        if (f0.in_off[q] == 2 * lo) { off = f0.uoff[q]; break; }
+                    if (off < 0) { e = hipErrorInvalidValue; break; }
+                    dst = xl[0] + off;
+                    ld = f0.nu;
+                }
+                cp.push_back(CopyJob{bin + 2 * lo, dst, 1, N2, 1, ld, static_cast<int32_t>(nn2),
+                                     static_cast<int32_t>(nrhs)});
+            }
+            if (e == hipSuccess) e = launch_copy(sc, cp);
+        }
+        // reversed downward sweep: G^T into the stage below, E^T into the parent
+        for (int li = 0; li < nl && e == hipSuccess; ++li) {
+            const LevelFactor& f = h->lv[li];
+            double2* out;
+            int64_t ldout;
+            stage_out(li - 1, &out, &ldout);
+            std::vector<GemmJob> gj;
+            for (int q = 0; q < f.nb; ++q) {
+                double2* xt = f.xt_root[q] ? xroot : xl[li + 1];
+                const int64_t ldxt = f.xt_root[q] ? h->Ktot : h->lv[li + 1].nu;
+                const double2* y = xl[li] + f.uoff[q];
+                gj.push_back(gemm(f.G + f.nnoff[q], 1, f.n[q], y, 1, f.nu, out + f.in_off[q], 1, ldout,
+                                  f.n[q], nrhs, f.n[q]));
+                gj.push_back(gemm(f.E + f.nkoff[q], 1, f.k[q], y, 1, f.nu, xt + f.xt_off[q], 1, ldxt,
+                                  f.k[q], nrhs, f.n[q]));
+            }
+            e = launch_gemm(sc, gj);
+        }
+        // roots: v_stage = Rinv^T xr
+        if (e == hipSuccess) {
+            std::vector<GemmJob> gj;
+            for (const RootJob& r : h->roots) {
+                double2* out;
+                int64_t ldout;
+                stage_out(r.stage, &out, &ldout);
+                gj.push_back(gemm(h->Rinv + r.r_off, 1, r.K, xroot + r.x_off, 1, h->Ktot, out + r.in_off, 1, ldout,
+                                  r.K, nrhs, r.K));
+            }
+            e = launch_gemm(sc, gj);
+        }
+        // reversed upward sweep: v_{l-1} += (F^T)^T v_l, top iteration first
+        for (int li = nl - 1; li >= 0 && e == hipSuccess; --li) {
+            const LevelFactor& f = h->lv[li];
+            double2* out;
+            int64_t ldout;
+            stage_out(li - 1, &out, &ldout);
+            std::vector<GemmJob> gj;
+            for (int q = 0; q < f.nb; ++q)
+                gj.push_back(gemm(f.Ft + f.nkoff[q], 1, f.n[q], bt[li] + f.koff[q], 1, f.nk, out + f.in_off[q], 1,
+                                  ldout, f.n[q], nrhs, f.k[q], make_double2(1.0, 0.0), make_double2(1.0, 0.0)));
+            e = launch_gemm(sc, gj);
+        }
+        if (e == hipSuccess) e = sc.flush();
+    } else {
+        // input of iteration li: the right-hand side, or the previous iteration's F^T output
+        auto stage_in = [&](int li, const double2** ptr, int64_t* ld) {
+            if (li < 0) { *ptr = bin; *ld = N2; }
+            else { *ptr = bt[li]; *ld = h->lv[li].nk; }
+        };
+        // upward: bt = F^T in
+        for (int li = 0; li < nl && e == hipSuccess; ++li) {
+            const LevelFactor& f = h->lv[li];
+            const double2* in;
+            int64_t ldin;
+            stage_in(li - 1, &in, &ldin);
+            std::vector<GemmJob> gj;
+            for (int q = 0; q < f.nb; ++q)
+                gj.push_back(gemm(f.Ft + f.nkoff[q], f.n[q], 1, in + f.in_off[q], 1, ldin, bt[li] + f.koff[q], 1, f.nk,
+                                  f.k[q], nrhs, f.n[q]));
+            e = launch_gemm(sc, gj);
+        }
+        // roots: xroot = Rinv in, one product per body
+        {
+            std::vector<GemmJob> gj;
+            for (const RootJob& r : h->roots) {
+                const double2* in;
+                int64_t ldin;
+                stage_in(r.stage, &in, &ldin);
+                gj.push_back(gemm(h->Rinv + r.r_off, r.K, 1, in + r.in_off, 1, ldin, xroot + r.x_off, 1, h->Ktot,
+                                  r.K, nrhs, r.K));
+            }
+            if (e == hipSuccess) e = launch_gemm(sc, gj);
+        }
+        // downward: x = G in + E xt, xt from the parent iteration or the body's root
+        for (int li = nl - 1; li >= 0 && e == hipSuccess; --li) {
+            const LevelFactor& f = h->lv[li];
+            const double2* in;
+            int64_t ldin;
+            stage_in(li - 1, &in, &ldin);
+            std::vector<GemmJob> g1, g2;
+            for (int q = 0; q < f.nb; ++q) {
+                const double2* xt = f.xt_root[q] ? xroot : xl[li + 1];
+                const int64_t ldxt = f.xt_root[q] ? h->Ktot : h->lv[li + 1].nu;
+                g1.push_back(gemm(f.G + f.nnoff[q], f.n[q], 1, in + f.in_off[q], 1, ldin, xl[li] + f.uoff[q], 1, f.nu,
+                                  f.n[q], nrhs, f.n[q]));
+                g2.push_back(gemm(f.E + f.nkoff[q], f.k[q], 1, xt + f.xt_off[q], 1, ldxt, xl[li] + f.uoff[q], 1, f.nu,
+                                  f.n[q], nrhs, f.k[q], make_double2(1.0, 0.0), make_double2(1.0, 0.0)));
+            }
+            e = launch_gemm(sc, g1);
+            if (e == hipSuccess) e = launch_gemm(sc, g2);
+        }
+        // the solution of every body in global unknown order: from the first
+        // iteration's output (its leaf boxes are contiguous and in node order), or
+        // from its root when the body was never compressed
+        if (e == hipSuccess) {
+            std::vector<CopyJob> cp;
+            const bm_problem* p = h->p;
+            for (const RootJob& r : h->roots) {
+                const int64_t lo = p->body_lo[r.body], nn2 = 2 * (p->body_lo[r.body + 1] - lo);
+                const double2* src;
+                int64_t ld;
+                if (r.stage < 0) {
+                    src = xroot + r.x_off;
+                    ld = h->Ktot;
+                } else {
+                    // the body's first leaf box: the first box of its in iteration 0 with in_off 2*lo
+                    const LevelFactor& f0 = h->lv[0];
+                    int64_t off = -1;
+                    for (int q = 0; q < f0.nb; ++q)
+                        if (f0.in_off[q] == 2 * lo) { off = f0.uoff[q]; break; }
+                    if (off < 0) { e = hipErrorInvalidValue; break; }
+                    src = xl[0] + off;
+                    ld = f0.nu;
+                }
+                cp.push_back(CopyJob{src, reinterpret_cast<double2*>(x) + 2 * lo, 1, ld, 1, N2,
+                                     static_cast<int32_t>(nn2), static_cast<int32_t>(nrhs)});
+            }
+            if (e == hipSuccess) e = launch_copy(sc, cp);
+            if (e == hipSuccess) e = sc.flush();
+        }
+    }
+    // the job descriptors are staged from host memory: finish before releasing them
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    sc.synced();
+    sc.release();
+    if (e != hipSuccess) return hip_fail(e, trans ? "bm_hss_solve_transpose" : "bm_hss_solve");
+    return BM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1435,101 +1624,15 @@ int bm_hss_solve(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipS
     clear_error();
     if (!h || !b || !x) return fail(BM_EINVAL, "bm_hss_solve: null argument");
     if (nrhs < 1 || nrhs > (int64_t{1} << 20)) return fail(BM_EINVAL, "bm_hss_solve: nrhs out of range");
-    const int nl = static_cast<int>(h->lv.size());
-    const int64_t N2 = 2 * h->N;
-    Scratch sc(s);
-    std::vector<double2*> bt(nl), xl(nl);
-    hipError_t e = hipSuccess;
-    for (int li = 0; li < nl && e == hipSuccess; ++li) {
-        e = sc.alloc(&bt[li], h->lv[li].nk * nrhs);
-        if (e == hipSuccess) e = sc.alloc(&xl[li], h->lv[li].nu * nrhs);
-    }
-    double2* xroot;
-    if (e == hipSuccess) e = sc.alloc(&xroot, h->Ktot * nrhs);
-    if (e != hipSuccess) { sc.release(); return hip_fail(e, "bm_hss_solve: buffers"); }
-    const double2* bin = reinterpret_cast<const double2*>(b);
-    // input of iteration li: the right-hand side, or the previous iteration's F^T output
-    auto stage_in = [&](int li, const double2** ptr, int64_t* ld) {
-        if (li < 0) { *ptr = bin; *ld = N2; }
-        else { *ptr = bt[li]; *ld = h->lv[li].nk; }
-    };
-    // upward: bt = F^T in
-    for (int li = 0; li < nl && e == hipSuccess; ++li) {
-        const LevelFactor& f = h->lv[li];
-        const double2* in;
-        int64_t ldin;
-        stage_in(li - 1, &in, &ldin);
-        std::vector<GemmJob> gj;
-        for (int q = 0; q < f.nb; ++q)
-            gj.push_back(gemm(f.Ft + f.nkoff[q], f.n[q], 1, in + f.in_off[q], 1, ldin, bt[li] + f.koff[q], 1, f.nk,
-                              f.k[q], nrhs, f.n[q]));
-        e = launch_gemm(sc, gj);
-    }
-    // roots: xroot = Rinv in, one product per body
-    {
-        std::vector<GemmJob> gj;
-        for (const RootJob& r : h->roots) {
-            const double2* in;
-            int64_t ldin;
-            stage_in(r.stage, &in, &ldin);
-            gj.push_back(gemm(h->Rinv + r.r_off, r.K, 1, in + r.in_off, 1, ldin, xroot + r.x_off, 1, h->Ktot,
-                              r.K, nrhs, r.K));
-        }
-        if (e == hipSuccess) e = launch_gemm(sc, gj);
-    }
-    // downward: x = G in + E xt, xt from the parent iteration or the body's root
-    for (int li = nl - 1; li >= 0 && e == hipSuccess; --li) {
-        const LevelFactor& f = h->lv[li];
-        const double2* in;
-        int64_t ldin;
-        stage_in(li - 1, &in, &ldin);
-        std::vector<GemmJob> g1, g2;
-        for (int q = 0; q < f.nb; ++q) {
-            const double2* xt = f.xt_root[q] ? xroot : xl[li + 1];
-            const int64_t ldxt = f.xt_root[q] ? h->Ktot : h->lv[li + 1].nu;
-            g1.push_back(gemm(f.G + f.nnoff[q], f.n[q], 1, in + f.in_off[q], 1, ldin, xl[li] + f.uoff[q], 1, f.nu,
-                              f.n[q], nrhs, f.n[q]));
-            g2.push_back(gemm(f.E + f.nkoff[q], f.k[q], 1, xt + f.xt_off[q], 1, ldxt, xl[li] + f.uoff[q], 1, f.nu,
-                              f.n[q], nrhs, f.k[q], make_double2(1.0, 0.0), make_double2(1.0, 0.0)));
-        }
-        e = launch_gemm(sc, g1);
-        if (e == hipSuccess) e = launch_gemm(sc, g2);
-    }
-    // the solution of every body in global unknown order: from the first
-    // iteration's output (its leaf boxes are contiguous and in node order), or
-    // from its root when the body was never compressed
-    if (e == hipSuccess) {
-        std::vector<CopyJob> cp;
-        const bm_problem* p = h->p;
-        for (const RootJob& r : h->roots) {
-            const int64_t lo = p->body_lo[r.body], nn2 = 2 * (p->body_lo[r.body + 1] - lo);
-            const double2* src;
-            int64_t ld;
-            if (r.stage < 0) {
-                src = xroot + r.x_off;
-                ld = h->Ktot;
-            } else {
-                // the body's first leaf box: the first box of its in iteration 0 with in_off 2*lo
-                const LevelFactor& f0 = h->lv[0];
-                int64_t off = -1;
-                for (int q = 0; q < f0.nb; ++q)
-                    if (f0.in_off[q] == 2 * lo) { off = f0.uoff[q]; break; }
-                if (off < 0) { e = hipErrorInvalidValue; break; }
-                src = xl[0] + off;
-                ld = f0.nu;
-            }
-            cp.push_back(CopyJob{src, reinterpret_cast<double2*>(x) + 2 * lo, 1, ld, 1, N2,
-                                 static_cast<int32_t>(nn2), static_cast<int32_t>(nrhs)});
-        }
-        if (e == hipSuccess) e = launch_copy(sc, cp);
-        if (e == hipSuccess) e = sc.flush();
-    }
-    // the job descriptors are staged from host memory: finish before releasing them
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    sc.synced();
-    sc.release();
-    if (e != hipSuccess) return hip_fail(e, "bm_hss_solve");
-    return BM_OK;
+    return solve_impl(h, b, x, nrhs, s, false);
+}
+
+int bm_hss_solve_transpose(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t s) {
+    clear_error();
+    if (!h || !b || !x) return fail(BM_EINVAL, "bm_hss_solve_transpose: null argument");
+    if (nrhs < 1 || nrhs > (int64_t{1} << 20))
+        return fail(BM_EINVAL, "bm_hss_solve_transpose: nrhs out of range");
+    return solve_impl(h, b, x, nrhs, s, true);
 }
 
 int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out) {

@@ -19,6 +19,7 @@ struct bm_geom {
     int32_t* curve = nullptr; // device, n
     int device = 0;
     std::vector<int64_t> curve_lo;   // host: first node of each curve (ncurves + 1)
+    double* xyd = nullptr;    // device, 6 * n: the samples x, y, x', y', x'', y'' as given
 };
 
 // A problem: one geometry split into independent bodies (consecutive runs of
@@ -32,6 +33,8 @@ struct bm_problem {
     bm::Media* d_media = nullptr;        // device copy of media
     int32_t* d_body = nullptr;           // device, body of each node (nullptr: one body)
     int64_t* d_body_lo = nullptr;        // device copy of body_lo
+    std::vector<int64_t> tile_off;       // host: first 256 x 256 pair tile of each body (nbodies + 1)
+    int64_t* d_tile_off = nullptr;       // device copy of tile_off
 };
 
 namespace bm {
@@ -95,5 +98,24 @@ int64_t matvec_work_doubles(int64_t n, int64_t max_body);
 hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* media,
                             const double* phi, const double* angles, int64_t nang, double* uinf,
                             hipStream_t s);
+
+// Adjoint kernels (adjoint.hip).
+// far-field weights g (2N complex): u_inf,b(angle) = sum over body b's unknowns of g_k phi_k
+hipError_t launch_far_weights(const NodeView& v, int64_t n, const Media* media, double angle, double* g,
+                              hipStream_t s);
+// pair tiles of a body of `nodes` nodes in the shape-derivative kernel
+int64_t pair_tiles(int64_t nodes);
+// device work buffer of the shape derivative, in doubles
+int64_t shape_work_doubles(int64_t n, int nbodies);
+// grad (6 x n) = Re(coef_b dL/d samples), L = g^T phi + lam^T (b - A phi) per body;
+// coef null: coef_b = 2 conj(u_inf,b(obs)) (J = |u_inf|^2)
+hipError_t launch_shape_derivative(const NodeView& v, const double* xyd, int64_t n, int nbodies,
+                                   const int64_t* body_lo, const int64_t* tile_off, int64_t ntiles,
+                                   const Media* media, const BesselTable* tab, const double* phi,
+                                   const double* lam, double inc, double obs, const double* coef, double* grad,
+                                   double* work, hipStream_t s);
+hipError_t launch_fourier_curve(const double* coef, int M, double R, double cx, double cy, int64_t n, double* xyd,
+                                hipStream_t s);
+hipError_t launch_fourier_chain(const double* grad, int64_t n, int M, double R, double* out, hipStream_t s);
 
 }  // namespace bm

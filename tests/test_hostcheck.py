@@ -1,8 +1,11 @@
-"""CPU checks of the kernels' arithmetic (bessel.hpp, wsbm_pair.hpp) through a
-host-compiled instance of the same headers (libbmhss_hostcheck.so, test-only).
+"""CPU checks of the kernels' arithmetic (bessel.hpp, wsbm_pair.hpp,
+wsbm_adjoint.hpp) through a host-compiled instance of the same headers
+(libbmhss_hostcheck.so, test-only).
 
 Bessel functions are checked against mpmath (40 digits) and the Wronskian;
-the 2x2 pair/diagonal blocks against the oracle at the parity bar 1e-10."""
+the 2x2 pair/diagonal blocks against the oracle at the parity bar 1e-10; the
+pair and diagonal derivatives of the shape-derivative kernel against
+Richardson central differences of the oracle's blocks (1e-8 relative)."""
 import ctypes
 import os
 
@@ -124,3 +127,132 @@ def test_pair_blocks_match_oracle(hc, case):
     got = host_blocks(hc, nd, media, rows, cols)
     ref = wsbm.system_blocks(nd, media, rows, cols).reshape(2 * len(rows), 2 * len(cols))
     assert_parity(got, ref)
+
+
+# ---------------------------------------------------------------------------
+# Shape-derivative building blocks (wsbm_adjoint.hpp) against Richardson
+# central differences of the oracle's own pair and diagonal blocks.
+
+def _richardson(f, h):
+    d1 = (f(h) - f(-h)) / (2 * h)
+    d2 = (f(h / 2) - f(-h / 2)) / h
+    return (4 * d2 - d1) / 3
+
+
+def _pair_form(media, tx, tn, sx, sn, sw, lam, ph, interior):
+    """lam_i^T A_ij phi_j from the oracle's pair block."""
+    blk = wsbm.pair_blocks(tx[None], tn[None], sx[None], sn[None], np.array([sw]), media,
+                           interior=np.array([[interior]]))[0, :, 0, :]
+    return lam @ blk @ ph
+
+
+def test_pair_adjoint_matches_oracle_differences(hc):
+    hc.bmh_pair_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    media = sc.media_from_index(40.0, 1.5)
+    md = np.array([media.k0, media.k1, media.eps0, media.eps1])
+    rng = np.random.default_rng(11)
+    cases = []
+    for r in (1e-3, 0.02, 0.1, 0.3, 1.0, 3.0, 20.0):      # z = k r from 0.04 to 1200
+        for interior in (1.0, 0.0):
+            ang = rng.uniform(0, 2 * np.pi)
+            tx = rng.standard_normal(2)
+            sx = tx - r * np.array([np.cos(ang), np.sin(ang)])
+            a1, a2 = rng.uniform(0, 2 * np.pi, 2)
+            tn, sn = np.array([np.cos(a1), np.sin(a1)]), np.array([np.cos(a2), np.sin(a2)])
+            sw = rng.uniform(0.001, 0.01)
+            lam = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+            ph = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+            cases.append((tx, tn, sx, sn, sw, lam, ph, interior))
+    inp = np.zeros((len(cases), 16))
+    phi = np.zeros((len(cases), 4))
+    for q, (tx, tn, sx, sn, sw, lam, ph, it) in enumerate(cases):
+        inp[q, :14] = [*tx, *tn, lam[0].real, lam[0].imag, lam[1].real, lam[1].imag, *sx, *sn, sw, it]
+        phi[q] = [ph[0].real, ph[0].imag, ph[1].real, ph[1].imag]
+    out = np.empty((len(cases), 14))
+    hc.bmh_pair_adjoint(inp.ctypes.data, phi.ctypes.data, len(cases), md.ctypes.data, out.ctypes.data)
+    got = out[:, 0::2] + 1j * out[:, 1::2]          # d/drho x, y; d/dn_i x, y; d/dn_j x, y; d/dw
+    for q, (tx, tn, sx, sn, sw, lam, ph, it) in enumerate(cases):
+        r = np.hypot(*(tx - sx))
+        F = lambda **kw: _pair_form(media, kw.get("tx", tx), kw.get("tn", tn), kw.get("sx", sx),
+                                    kw.get("sn", sn), kw.get("sw", sw), lam, ph, it)
+        e = np.eye(2)
+        hx, hn = 1e-3 * min(r, 1.0 / media.k1), 1e-4   # small against r and the wavelength
+        ref = [_richardson(lambda s, c=c: F(tx=tx + s * e[c]), hx) for c in range(2)]
+        ref += [_richardson(lambda s, c=c: F(tn=tn + s * e[c]), hn) for c in range(2)]
+        ref += [_richardson(lambda s, c=c: F(sn=sn + s * e[c]), hn) for c in range(2)]
+        ref += [F() / sw]                           # the pair is linear in w_j
+        src = [_richardson(lambda s, c=c: F(sx=sx + s * e[c]), hx) for c in range(2)]
+        ref, src = np.array(ref), np.array(src)
+        scale = np.abs(ref).max()
+        err = np.abs(got[q] - ref).max()
+        assert err <= 1e-8 * scale, (q, r, it, err / scale)
+        # the pair depends on x_i - x_j only: d/dx_j = -d/drho
+        assert np.abs(src + got[q, :2]).max() <= 1e-8 * scale, (q, r, it)
+
+
+def test_diag_adjoint_matches_oracle_differences(hc):
+    hc.bmh_diag_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    rng = np.random.default_rng(12)
+    for media in (sc.media_from_index(40.0, 1.5), sc.table1_media()):
+        md = np.array([media.k0, media.k1, media.eps0, media.eps1])
+        for w, kap in ((1e-3, 1.0), (0.02, -3.0), (0.3, 0.2)):
+            lam = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+            ph = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+            inp = np.array([w, kap, lam[0].real, lam[0].imag, lam[1].real, lam[1].imag, 0, 0])
+            phi = np.array([ph[0].real, ph[0].imag, ph[1].real, ph[1].imag])
+            out = np.empty(4)
+            hc.bmh_diag_adjoint(inp.ctypes.data, phi.ctypes.data, 1, md.ctypes.data, out.ctypes.data)
+
+            def F(ww, kk):
+                nd = geometry.Nodes(np.zeros((1, 2)), np.array([[1.0, 0.0]]), np.array([ww]),
+                                    np.array([kk]), np.zeros(1, dtype=np.int64))
+                return lam @ wsbm.system_blocks(nd, media, [0], [0]).reshape(2, 2) @ ph
+
+            dw = _richardson(lambda s: F(w + s, kap), 1e-3 * w)
+            dk = _richardson(lambda s: F(w, kap + s), 1e-2)
+            assert abs(out[0] + 1j * out[1] - dw) <= 1e-9 * abs(dw), (w, kap)
+            assert abs(out[2] + 1j * out[3] - dk) <= 1e-9 * max(abs(dk), abs(dw) * w), (w, kap)
+
+
+def test_shape_derivative_matches_oracle_differences(hc):
+    """The kernels' whole per-node derivative (pair sums, diagonal, right-hand
+    side, far field, chain rule to the samples) run on the host for one body of
+    two curves, against Richardson differences of the oracle's
+    L = g.phi + lam.(b - A phi) with respect to every sample of sampled nodes."""
+    vp = ctypes.c_void_p
+    hc.bmh_shape_derivative.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp, ctypes.c_double,
+                                        ctypes.c_double, vp, vp]
+    media = sc.media_from_index(8.0, 1.5)
+    xyd, s = sc.sample_curves([sc.star(0.2, 3), sc.circle(0.3, (2.5, 0.0))], [48, 40])
+    nd = geometry.discretize(xyd, s)
+    N = nd.size
+    rng = np.random.default_rng(13)
+    phi = rng.standard_normal(2 * N) + 1j * rng.standard_normal(2 * N)
+    lam = rng.standard_normal(2 * N) + 1j * rng.standard_normal(2 * N)
+    coef = np.array([0.7, -1.3])
+    inc, obs = 0.7, 2.9
+    soa = np.ascontiguousarray(np.stack([nd.x[:, 0], nd.x[:, 1], nd.n[:, 0], nd.n[:, 1], nd.w, nd.kappa]))
+    curve = np.ascontiguousarray(nd.curve.astype(np.int32))
+    md = np.array([media.k0, media.k1, media.eps0, media.eps1])
+    grad = np.empty((6, N))
+    hc.bmh_shape_derivative(soa.ctypes.data, np.ascontiguousarray(xyd).ctypes.data, curve.ctypes.data, N,
+                            md.ctypes.data, lam.ctypes.data, phi.ctypes.data, inc, obs, coef.ctypes.data,
+                            grad.ctypes.data)
+
+    def L(x):
+        n2 = geometry.discretize(x, s)
+        g = wsbm.far_field_weights(n2, media, obs)
+        b = wsbm.rhs_plane_wave(n2, media, inc)
+        return g @ phi + lam @ (b - wsbm.assemble_dense(n2, media) @ phi)
+
+    c = coef[0] + 1j * coef[1]
+    for i in (0, 5, 47, 48, 70, 87):
+        for r in range(6):
+            def f(h):
+                x = xyd.copy()
+                x[r, i] += h
+                return L(x)
+            ref = np.real(c * _richardson(f, 1e-5 if r < 4 else 1e-3))
+            assert abs(grad[r, i] - ref) <= 1e-7 * np.abs(grad).max(), (i, r, grad[r, i], ref)
