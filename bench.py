@@ -247,6 +247,83 @@ def run_batch(args):
     return out, wls[0]
 
 
+def run_large(args):
+    """The large single-GPU workload: 16 stars on a 4 x 4 grid of spacing 3 in
+    ONE body (coupled through the exterior medium; the interior operators act
+    within each star only), 16384 nodes each (N = 262144), k0 = 200, n = 2,
+    leaf 128, 96 proxy points (adaptive: max(96, ceil(2 k R_p) + 32)), tol 1e-10.
+    A step is one HSS build + plane-wave right-hand side + solve; the
+    residual |A x - b| / |b| comes from the matrix-free product."""
+    import numpy as np
+    import torch
+    import scatterers as sc
+    import paper_2607_00790_amd as bm
+
+    os.environ.setdefault("BMHSS_VERBOSE", "1")   # progress lines on stderr during the long build
+    wl = sc.grid_of_stars_workload(per_curve=args.per_curve)
+    xyd, s = wl.xyd()
+    g = bm.bm_geom_create(s, torch.from_numpy(xyd).cuda())
+    p = bm.bm_problem_create(g, wl.media.k0, wl.media.k1, wl.media.eps0, wl.media.eps1)
+    n = g.n
+    opts = dict(leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points, id_tol=wl.id_tol,
+                sketch=args.sketch, proxy_adapt=True, max_rank_ratio=args.max_rank_ratio)
+    stream = torch.cuda.current_stream()
+    b = torch.empty(2 * n, dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(b)
+    levels = []
+
+    def step():
+        h = bm.bm_hss_build(p, **opts)
+        st = bm.bm_hss_stats(h)
+        print(f"large: build {st['seconds_total']:.2f} s, root {st['root_size']}, max rank {st['max_rank']}",
+              file=sys.stderr, flush=True)
+        bm.bm_rhs_plane_wave(p, wl.theta_inc, out=b)
+        bm.bm_hss_solve(h, b, out=x)
+        if not levels:
+            levels.extend(bm.bm_hss_level(h, l) for l in range(st["compressed_levels"]))
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stats = []
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        stats.append(step())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    st = stats[-1]
+    t1 = time.perf_counter()
+    r = bm.bm_matvec(p, x) - b
+    torch.cuda.synchronize()
+    mv_s = time.perf_counter() - t1
+    res = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
+    out = {
+        "metric": "Gentries/s Burton-Miller blocks (frac FP64 peak); HSS build+solve s at N=16384",
+        "value": st["entries"] / (ms * 1e-3) / 1e9,
+        "unit": "Gentries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "wall_s_timed": wall,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"HSS build+solve, {wl.name} (one body of {len(wl.curves)} curves)",
+                   "n_nodes": n, "k0": wl.media.k0, "k1": wl.media.k1, **opts,
+                   "proxy_points_rule": f"max({wl.proxy_points}, ceil(2 k R_p) + 32)"},
+        "large": {"entries": st["entries"], "pairs": st["pairs"], "levels": st["levels"],
+                  "compressed_levels": st["compressed_levels"], "root_size": st["root_size"],
+                  "max_rank": st["max_rank"], "seconds_build_wall": st["seconds_total"],
+                  "seconds_generate": st["seconds_generate"], "seconds_compress": st["seconds_compress"],
+                  "seconds_cpqr": st["seconds_cpqr"], "seconds_factor": st["seconds_factor"],
+                  "residual": res, "matvec_s": mv_s, "per_level": levels},
+    }
+    return out, wl
+
+
 def run_hss(args):
     import torch
     import scatterers as sc
@@ -431,8 +508,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["hss", "dense", "matvec", "batch", "adjoint"], default="hss")
+    ap.add_argument("--mode", choices=["hss", "dense", "matvec", "batch", "adjoint", "large"], default="hss")
     ap.add_argument("--id-tol", type=float, default=1e-12, help="adjoint mode: HSS ID tolerance")
+    ap.add_argument("--per-curve", type=int, default=16384, help="large mode: nodes per star")
+    ap.add_argument("--max-rank-ratio", type=float, default=0.0,
+                    help="HSS: a body stops compressing once a level keeps more than this fraction of its unknowns")
     ap.add_argument("--batch", type=int, default=256, help="batch mode: number of stars")
     ap.add_argument("--proxy-adapt", type=int, choices=[0, 1], default=1,
                     help="batch mode: proxy points per circle max(64, ceil(2 k R_p) + 32)")
@@ -455,8 +535,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     out, wl = {"hss": run_hss, "dense": run_dense, "matvec": run_matvec, "batch": run_batch,
-               "adjoint": run_adjoint}[args.mode](args)
-    if not args.no_cpu_baseline:
+               "adjoint": run_adjoint, "large": run_large}[args.mode](args)
+    if not args.no_cpu_baseline and args.mode in ("hss", "dense", "matvec"):
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
     return 0

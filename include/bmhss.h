@@ -152,6 +152,12 @@ typedef struct {
     int64_t proxy_adapt;   /* 0: proxy_points on every proxy circle; 1: per box
                               max(proxy_points, ceil(2 k R_p) + 32), k the larger
                               wavenumber of the box's body, R_p the proxy radius */
+    double max_rank_ratio; /* 0: compress every body up to its top level or until a
+                              box has no far unknowns; r in (0, 1]: also stop a body
+                              (its current boxes' skeletons become its dense root)
+                              once a level's skeletons keep more than r of its
+                              unknowns -- at high frequency the ranks grow with the
+                              box size and compressing further does not pay */
 } bm_hss_opts;
 
 typedef struct {

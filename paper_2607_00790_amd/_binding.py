@@ -28,7 +28,7 @@ class _Media(ctypes.Structure):
 
 class _HssOpts(ctypes.Structure):
     _fields_ = [("leaf", c_i64), ("proxy_ratio", c_dbl), ("proxy_points", c_i64),
-                ("id_tol", c_dbl), ("sketch", c_i64), ("proxy_adapt", c_i64)]
+                ("id_tol", c_dbl), ("sketch", c_i64), ("proxy_adapt", c_i64), ("max_rank_ratio", c_dbl)]
 
 
 class _HssStats(ctypes.Structure):
@@ -295,12 +295,14 @@ def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
 
 
 def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10,
-                 sketch=0, proxy_adapt=False, stream=None) -> HSS:
+                 sketch=0, proxy_adapt=False, max_rank_ratio=0.0, stream=None) -> HSS:
     """sketch = p > 0: run the ID on a Gaussian sketch of each box's stacked
     matrix with (unknowns + p) rows, when that is fewer than the matrix has.
-    proxy_adapt: max(proxy_points, ceil(2 k R_p) + 32) points per proxy circle."""
+    proxy_adapt: max(proxy_points, ceil(2 k R_p) + 32) points per proxy circle.
+    max_rank_ratio = r > 0: a body stops compressing once a level keeps more
+    than r of its unknowns (its skeletons then form its dense root)."""
     opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol), int(sketch),
-                    int(bool(proxy_adapt)))
+                    int(bool(proxy_adapt)), float(max_rank_ratio))
     out = c_vp()
     _check(load().bm_hss_build(p._h, ctypes.byref(opts), _stream(stream), ctypes.byref(out)))
     return HSS(out, p)

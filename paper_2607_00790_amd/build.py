@@ -49,7 +49,9 @@ def build(verbose: bool = True) -> None:
         _run([hipcc(), f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, "-c", s, "-o", o])
         objs.append(o)
     tmp = LIB + ".tmp"
-    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, f"-L{rocm_lib}", "-lrocblas",
+          f"-Wl,-rpath,{rocm_lib}", "-o", tmp])
     os.replace(tmp, LIB)
     tmp = HOSTCHECK + ".tmp"
     _run([hipcc(), f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, "-shared",

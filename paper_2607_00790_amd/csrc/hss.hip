@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <cmath>
@@ -26,6 +28,10 @@
 #include <new>
 #include <random>
 #include <vector>
+
+#include <unordered_map>
+
+#include <rocblas/rocblas.h>
 
 #include "hss_internal.hpp"
 
@@ -63,6 +69,23 @@ struct RootJob {
 };
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Progress lines on stderr during long builds, when the environment variable
+// BMHSS_VERBOSE is set to a non-zero value.
+bool verbose() {
+    static const bool v = [] {
+        const char* e = std::getenv("BMHSS_VERBOSE");
+        return e && *e && std::strcmp(e, "0") != 0;
+    }();
+    return v;
+}
+
+template <class... A>
+void progress(const char* fmt, A... a) {
+    if (!verbose()) return;
+    std::fprintf(stderr, fmt, a...);
+    std::fflush(stderr);
+}
 
 // Pinned host staging chunks are expensive to allocate, so they are kept in
 // a process-wide cache and reused by later phases and builds.
@@ -243,9 +266,84 @@ hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const 
 
 hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs);
 
+// rocBLAS handle of the current device, for the large products.
+hipError_t blas_handle(rocblas_handle* out) {
+    static std::mutex mu;
+    static std::unordered_map<int, rocblas_handle> handles;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = handles.find(dev);
+    if (it == handles.end()) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return hipErrorInitializationError;
+        it = handles.emplace(dev, h).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
+// A product worth a library call: the batched tile kernel runs one 32 x 32
+// tile per workgroup without matrix cores, which is fine for the many small
+// per-box products but slow for the few large ones (the root inverse's Schur
+// recursion, large boxes), where rocBLAS's ZGEMM is used instead.
+constexpr double kBlasFlops = 4e8;
+
+bool blas_layout(int64_t rs, int64_t cs, int64_t rows, int64_t cols, rocblas_operation* op, int64_t* ld) {
+    // column-major X (rs == 1, ld = cs) or column-major X^T (cs == 1, ld = rs)
+    if (rs == 1 && cs >= std::max<int64_t>(rows, 1)) { *op = rocblas_operation_none; *ld = cs; return true; }
+    if (cs == 1 && rs >= std::max<int64_t>(cols, 1)) { *op = rocblas_operation_transpose; *ld = rs; return true; }
+    return false;
+}
+
+// C = alpha A B + beta C through rocBLAS (column-major).  A row-major C is
+// computed as C^T = B^T A^T.  Returns false if a stride pattern does not map.
+bool blas_job(const GemmJob& g, rocblas_operation* oa, rocblas_operation* ob, int64_t* lda, int64_t* ldb,
+              int64_t* ldc, bool* swap) {
+    if (g.c_rs == 1 && g.c_cs >= std::max(g.M, 1)) {
+        *swap = false;
+        *ldc = g.c_cs;
+        return blas_layout(g.a_rs, g.a_cs, g.M, g.K, oa, lda) && blas_layout(g.b_rs, g.b_cs, g.K, g.N, ob, ldb);
+    }
+    if (g.c_cs == 1 && g.c_rs >= std::max(g.N, 1)) {
+        // C^T (N x M) = B^T (N x K) A^T (K x M): B^T has strides (b_cs, b_rs), A^T (a_cs, a_rs)
+        *swap = true;
+        *ldc = g.c_rs;
+        return blas_layout(g.b_cs, g.b_rs, g.N, g.K, oa, lda) && blas_layout(g.a_cs, g.a_rs, g.K, g.M, ob, ldb);
+    }
+    return false;
+}
+
 hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
+    std::vector<GemmJob> small;
+    for (const GemmJob& g : jobs) {
+        rocblas_operation oa, ob;
+        int64_t lda, ldb, ldc;
+        bool swap;
+        const double flops = 8.0 * g.M * g.N * g.K;
+        if (flops < kBlasFlops || g.M == 0 || g.N == 0 || g.K == 0 || !blas_job(g, &oa, &ob, &lda, &ldb, &ldc, &swap)) {
+            small.push_back(g);
+            continue;
+        }
+        rocblas_handle h;
+        const hipError_t e = blas_handle(&h);
+        if (e != hipSuccess) return e;
+        hipStream_t st = sc.s;
+        const GemmJob gj = g;
+        sc.rec([=]() {
+            if (rocblas_set_stream(h, st) != rocblas_status_success) return hipErrorLaunchFailure;
+            const rocblas_double_complex al(gj.alpha.x, gj.alpha.y), be(gj.beta.x, gj.beta.y);
+            const auto* A = reinterpret_cast<const rocblas_double_complex*>(swap ? gj.b : gj.a);
+            const auto* B = reinterpret_cast<const rocblas_double_complex*>(swap ? gj.a : gj.b);
+            auto* C = reinterpret_cast<rocblas_double_complex*>(gj.c);
+            const int64_t m = swap ? gj.N : gj.M, n = swap ? gj.M : gj.N;
+            const rocblas_status r = rocblas_zgemm_64(h, oa, ob, m, n, gj.K, &al, A, lda, B, ldb, &be, C, ldc);
+            return r == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+        });
+    }
     return launch_in_groups(
-        jobs, [](const GemmJob& j) { return ceil_div(j.M, 32) * ceil_div(j.N, 32); },
+        small, [](const GemmJob& j) { return ceil_div(j.M, 32) * ceil_div(j.N, 32); },
         [&](const std::vector<GemmJob>& g) { return launch_gemm_group(sc, g); });
 }
 
@@ -678,6 +776,7 @@ struct BodyState {
     std::vector<std::vector<int32_t>> U;   // active unknowns (global ids) per current box
     std::vector<int64_t> split_slots;      // per current box above the leaves: slots of the first child
     int iter_prev = -1;        // last iteration that compressed this body's boxes
+    double last_ratio = 0;     // skeleton unknowns / unknowns over its boxes at that iteration
     int kept_prev = -1;        // index of its first box among that iteration's boxes
     std::vector<std::vector<double>> box_c;   // per level: centre x, y and proxy radius per box
     std::vector<std::vector<int32_t>> box_p;  // per level: proxy points per box
@@ -691,6 +790,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
     const double tol = h->opts.id_tol;
     const int nbodies = p->nbodies;
     EventTimer t_gen, t_cmp, t_fac;
+    const auto t_build0 = std::chrono::steady_clock::now();
 
     // bodies and their trees
     std::vector<BodyState> bodies(nbodies);
@@ -849,9 +949,19 @@ int build_impl(bm_hss* h, hipStream_t s) {
 
     int iter = 0;
     for (;; ++iter) {
-        // bodies that reached their top level become roots
+        // bodies that reached their top level become roots, and so do bodies
+        // whose last compression kept more than max_rank_ratio of their unknowns
+        // (ranks grow with the box size in wavelengths; above that the ID of the
+        // next, larger boxes would cost far more than it saves)
+        const double max_ratio = h->opts.max_rank_ratio;
         for (int q = 0; q < nbodies; ++q)
-            if (bodies[q].active && bodies[q].level == 0) make_root(q);
+            if (bodies[q].active &&
+                (bodies[q].level == 0 || (max_ratio > 0 && bodies[q].last_ratio > max_ratio))) {
+                if (bodies[q].level > 0)
+                    progress("bmhss build: body %d stops compressing at level %d (kept %.2f of its unknowns)\n", q,
+                             bodies[q].level, bodies[q].last_ratio);
+                make_root(q);
+            }
         // ---- the boxes of this iteration: every active body at its current level
         struct Box { int body, local; int64_t lo, hi; };
         std::vector<Box> boxes;
@@ -1061,6 +1171,14 @@ int build_impl(bm_hss* h, hipStream_t s) {
                             static_cast<int32_t>(Y_sk ? idm[c] : km[c])};
         if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: cpqr setup"); }
         if ((e = t_cmp.start(sc, ev)) != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "event"); }
+        {
+            int64_t mu = 0, mr = 0;
+            for (int c = 0; c < nk; ++c) { mu = std::max(mu, kn[c]); mr = std::max(mr, km[c]); }
+            progress("bmhss build: iteration %d: ID of %d boxes, <= %lld unknowns x %lld rows, %.2f s\n",
+                     static_cast<int>(h->level_info.size()), nk, static_cast<long long>(mu),
+                     static_cast<long long>(mr),
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
+        }
         CpqrJob* dcj = nullptr;
         std::vector<int32_t> ranks(nk), perm(uoff[nk]);
         hipEvent_t c0 = nullptr, c1 = nullptr;
@@ -1086,6 +1204,10 @@ int build_impl(bm_hss* h, hipStream_t s) {
                 li.max_rank = std::max<int32_t>(li.max_rank, ranks[c]);
             }
             h->level_info.push_back(li);
+            progress("bmhss build: iteration %d: %d boxes, <= %d unknowns, <= %d rows, ranks %d..%d, %.2f s\n",
+                     static_cast<int>(h->level_info.size()) - 1, li.boxes, li.max_unknowns, li.max_rows,
+                     li.min_rank, li.max_rank,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
             // algorithmic bytes of the executed CPQR steps: at step k the trailing
             // columns (n - k - 1 of them, rows k..m) are read and written once, the
             // Householder column (rows k..m) and the n norms are read, and the
@@ -1288,8 +1410,11 @@ int build_impl(bm_hss* h, hipStream_t s) {
             if (!B.active || kfirst[q] < 0) continue;
             const int nbq = 1 << B.level;
             std::vector<std::vector<int32_t>> J(nbq);
+            int64_t kept = 0, had = 0;
             for (int lb = 0; lb < nbq; ++lb) {
                 const int c = kfirst[q] + lb;
+                kept += k[c];
+                had += static_cast<int64_t>(B.U[lb].size());
                 J[lb].resize(k[c]);
                 for (int64_t i = 0; i < k[c]; ++i) J[lb][i] = B.U[lb][perm[uoff[c] + i]];
             }
@@ -1304,6 +1429,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
             }
             B.iter_prev = iter;
             B.kept_prev = kfirst[q];
+            B.last_ratio = had > 0 ? static_cast<double>(kept) / static_cast<double>(had) : 0.0;
             B.level -= 1;
         }
     }
@@ -1320,6 +1446,9 @@ int build_impl(bm_hss* h, hipStream_t s) {
         sc.rec([=]() { return hipStreamWaitEvent(s2, rready, 0); });
         h->roots = roots;
         h->Ktot = Ktot;
+        progress("bmhss build: %d roots, %lld unknowns in total, %.2f s\n", static_cast<int>(roots.size()),
+                 static_cast<long long>(Ktot),
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
         Slot* drs;
         hipError_t e = sc.upload(&drs, root_slots);
         if (e == hipSuccess) e = palloc(&h->Rinv, Rtot, s2);
@@ -1593,9 +1722,10 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
     if (!p || !opts) return fail(BM_EINVAL, "bm_hss_build: null argument");
     if (opts->leaf < 4 || !(opts->proxy_ratio > 1.0) || opts->proxy_points < 8 ||
         !(opts->id_tol > 0.0 && opts->id_tol < 1.0) || !std::isfinite(opts->proxy_ratio) ||
-        opts->sketch < 0 || opts->sketch > (int64_t{1} << 20))
+        opts->sketch < 0 || opts->sketch > (int64_t{1} << 20) ||
+        !(opts->max_rank_ratio >= 0.0 && opts->max_rank_ratio <= 1.0))
         return fail(BM_EINVAL, "bm_hss_build: need leaf >= 4, proxy_ratio > 1, proxy_points >= 8, "
-                               "0 < id_tol < 1, 0 <= sketch <= 2^20");
+                               "0 < id_tol < 1, 0 <= sketch <= 2^20, 0 <= max_rank_ratio <= 1");
     if (p->g->n > (int64_t{1} << 30)) return fail(BM_EINVAL, "bm_hss_build: N too large");
     const auto t0 = std::chrono::steady_clock::now();
     bm_hss* h = new (std::nothrow) bm_hss;

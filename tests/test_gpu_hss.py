@@ -162,6 +162,36 @@ def test_hss_adaptive_proxy_count_high_wavenumber(gpu_lib):
     assert errs[True] < errs[False]
 
 
+def test_hss_stops_compressing_when_ranks_stay_high(gpu_lib):
+    """max_rank_ratio: a body whose level keeps more than the given fraction of
+    its unknowns stops compressing; its skeletons form a dense root (inverted
+    through the Schur recursion, whose large products go to rocBLAS).  Two stars
+    in one body, N = 1400, k0 = 40."""
+    import torch
+    bm = gpu_lib
+    note("hss: stop rule on the rank ratio, two stars, N=1400")
+    media = sc.media_from_index(40.0, 1.5)
+    curves = [sc.star(0.2, 4), sc.star(0.25, 3, 1.0, (3.0, 0.0))]
+    p, nd = setup(bm, curves, [800, 600], media)
+    A = wsbm.assemble_dense(nd, media)
+    ref = wsbm.solve_dense(A, wsbm.rhs_plane_wave(nd, media, 0.5))
+    b = bm.bm_rhs_plane_wave(p, 0.5)
+    full = bm.bm_hss_build(p, leaf=32, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, proxy_adapt=True)
+    cut = bm.bm_hss_build(p, leaf=32, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, proxy_adapt=True,
+                          max_rank_ratio=0.3)
+    sf, st = bm.bm_hss_stats(full), bm.bm_hss_stats(cut)
+    note(f"  without the rule: {sf['compressed_levels']} levels, root {sf['root_size']}; "
+         f"with 0.3: {st['compressed_levels']} levels, root {st['root_size']}")
+    assert 1 <= st["compressed_levels"] < sf["compressed_levels"]
+    assert st["root_size"] > sf["root_size"]
+    bh = b.cpu().numpy()
+    for h in (full, cut):
+        x = bm.bm_hss_solve(h, b).cpu().numpy()
+        assert rel(x, ref) < HSS_BAR
+        xt = bm.bm_hss_solve_transpose(h, b).cpu().numpy()
+        assert np.linalg.norm(A.T @ xt - bh) <= 1e-7 * np.linalg.norm(bh)
+
+
 def test_hss_rejects_bad_options(gpu_lib):
     bm = gpu_lib
     media = sc.media_from_index(10.0, 1.5)
@@ -171,6 +201,9 @@ def test_hss_rejects_bad_options(gpu_lib):
             bm.bm_hss_build(p, **kw)
     with pytest.raises(bm.BmError):
         bm.bm_hss_build(p, sketch=-1)
+    for r in (-0.1, 1.5, float("nan")):
+        with pytest.raises(bm.BmError):
+            bm.bm_hss_build(p, max_rank_ratio=r)
     # the same through the C-ABI directly: nothing is built
     import ctypes
     from paper_2607_00790_amd import _binding as B
