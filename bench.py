@@ -368,6 +368,22 @@ def run_hss(args):
     def avg(key):
         return sum(q[key] for q in stats) / len(stats)
 
+    # the solve alone: eager (descriptors staged per call, synchronises) and
+    # replayed from the HIP graph captured on its first call
+    h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points,
+                        id_tol=wl.id_tol, sketch=args.sketch)
+    bm.bm_hss_solve_graph(h, b, out=x)
+    solve_ms = {}
+    for name, fn in (("eager", lambda: bm.bm_hss_solve(h, b, out=x)),
+                     ("graph", lambda: bm.bm_hss_solve_graph(h, b, out=x))):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        solve_ms[name] = (time.perf_counter() - t1) / 20 * 1e3
+    del h
+
     gen_s = avg("seconds_generate")
     entries = st["entries"]
     # dominant kernel of the step: the CPQR step kernel of the ID
@@ -398,6 +414,7 @@ def run_hss(args):
                 "seconds_cpqr": cq_s,
                 "seconds_factor": avg("seconds_factor"),
                 "generation_Gentries_s": entries / gen_s / 1e9,
+                "solve_ms_eager": solve_ms["eager"], "solve_ms_graph": solve_ms["graph"],
                 "per_level": levels},
         "roofline": {"bound": "hbm", "achieved": cq_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": cq_gbs / HBM_PEAK_GBS,

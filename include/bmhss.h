@@ -198,6 +198,20 @@ int bm_hss_solve(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipS
  * solve A^T lam = g of a shape derivative.  x may alias b.  Returns after the
  * solve has completed on the stream. */
 int bm_hss_solve_transpose(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t stream);
+/* The same solve (transpose = 0) or transposed solve (transpose = 1) replayed
+ * from a HIP graph: the first call for a given (nrhs, transpose) records the
+ * solve's level sweeps once -- job descriptors uploaded to device memory, the
+ * launches captured on a library stream -- and every call then copies b into
+ * the graph's input buffer, launches the graph on `stream` and copies the
+ * result to x.  Unlike bm_hss_solve it does not synchronise: it returns as soon
+ * as the work is enqueued.  Calls with the same (nrhs, transpose) share one
+ * input/output buffer pair, so they must be ordered on one stream (or
+ * synchronised); bm_hss_destroy waits for the last launch of every graph.  The
+ * graph holds device memory (the sweep buffers, 2N x nrhs in and out) until
+ * bm_hss_destroy.  BM_ESTATE when the solve would need rocBLAS products (a root
+ * of more than about 7000/sqrt(nrhs) unknowns), which are not captured. */
+int bm_hss_solve_graph(const bm_hss* h, const double* b, double* x, int64_t nrhs, int transpose,
+                       hipStream_t stream);
 int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out);
 
 /* Per compressed level (0 = leaves, up to compressed_levels - 1): sizes of the

@@ -27,6 +27,7 @@ from ._binding import (  # noqa: F401
     bm_hss_stats,
     bm_hss_level,
     bm_hss_solve_transpose,
+    bm_hss_solve_graph,
     bm_far_field_weights,
     bm_shape_derivative,
     bm_fourier_curve,

@@ -81,6 +81,7 @@ def load():
         "bm_hss_build": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssOpts), c_vp, ctypes.POINTER(c_vp)]),
         "bm_hss_solve": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp]),
         "bm_hss_solve_transpose": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp]),
+        "bm_hss_solve_graph": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, ctypes.c_int, c_vp]),
         "bm_far_field_weights": (ctypes.c_int, [c_vp, c_dbl, c_vp, c_vp]),
         "bm_shape_derivative": (ctypes.c_int, [c_vp, c_vp, c_vp, c_dbl, c_dbl, c_vp, c_vp, c_vp]),
         "bm_fourier_curve": (ctypes.c_int, [c_vp, ctypes.c_int, c_dbl, c_dbl, c_dbl, c_i64, c_vp, c_vp]),
@@ -340,6 +341,19 @@ def bm_hss_solve_transpose(h: HSS, b, out=None, stream=None):
         out = torch.empty_like(b)
     _check(load().bm_hss_solve_transpose(h._h, _dev_ptr(b, torch.complex128, "b"),
                                        _dev_ptr(out, torch.complex128, "out"), nrhs, _stream(stream)))
+    return out
+
+
+def bm_hss_solve_graph(h: HSS, b, out=None, transpose=False, stream=None):
+    """bm_hss_solve (or its transpose) replayed from a HIP graph captured on the
+    first call for this (nrhs, transpose); asynchronous on the stream."""
+    torch = _torch()
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    if out is None:
+        out = torch.empty_like(b)
+    _check(load().bm_hss_solve_graph(h._h, _dev_ptr(b, torch.complex128, "b"),
+                                     _dev_ptr(out, torch.complex128, "out"), nrhs, int(bool(transpose)),
+                                     _stream(stream)))
     return out
 
 

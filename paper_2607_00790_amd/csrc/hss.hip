@@ -177,7 +177,9 @@ struct Scratch {
         return hipSuccess;
     }
     void rec(std::function<hipError_t()> f) { cmds.push_back(std::move(f)); }
-    hipError_t flush() {
+    bool uses_blas = false;   // a recorded command calls rocBLAS
+    // the host-to-device copies of the uploads so far
+    hipError_t flush_uploads() {
         for (Chunk& c : chunks) {
             if (c.used > c.flushed) {
                 hipError_t e = hipMemcpyAsync(c.d + c.flushed, c.h + c.flushed, c.used - c.flushed,
@@ -187,6 +189,15 @@ struct Scratch {
                 pending = true;
             }
         }
+        return hipSuccess;
+    }
+    hipError_t flush() {
+        const hipError_t e = flush_uploads();
+        if (e != hipSuccess) return e;
+        return run_recorded();
+    }
+    // the recorded commands, in order
+    hipError_t run_recorded() {
         for (auto& f : cmds) {
             hipError_t e = f();
             if (e != hipSuccess) {
@@ -329,6 +340,7 @@ hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
         rocblas_handle h;
         const hipError_t e = blas_handle(&h);
         if (e != hipSuccess) return e;
+        sc.uses_blas = true;
         hipStream_t st = sc.s;
         const GemmJob gj = g;
         sc.rec([=]() {
@@ -638,6 +650,34 @@ struct bm_hss {
     double2* Rinv = nullptr;       // the roots' inverses, packed
     bm_hss_stats_t stats{};
     std::vector<bm_hss_level_t> level_info;   // per compressed level, leaves first
+    // captured solves (bm_hss_solve_graph), one per (nrhs, transpose)
+    struct SolvePlan {
+        int64_t nrhs = 0;
+        bool trans = false;
+        std::unique_ptr<Scratch> sc;      // device buffers and job descriptors of the graph
+        double* bin = nullptr;            // the graph's input and output, 2N x nrhs complex
+        double* xout = nullptr;
+        hipStream_t cap = nullptr;        // capture stream
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t done = nullptr;        // recorded after every launch of the graph
+        ~SolvePlan() {
+            if (done) {
+                (void)hipEventSynchronize(done);
+                (void)hipEventDestroy(done);
+            }
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (sc) {
+                if (cap) (void)hipStreamSynchronize(cap);
+                sc->release();
+                sc.reset();
+            }
+            if (cap) (void)hipStreamDestroy(cap);
+        }
+    };
+    mutable std::mutex plan_mu;
+    mutable std::vector<std::unique_ptr<SolvePlan>> plans;
 };
 
 namespace {
@@ -1534,10 +1574,9 @@ int build_impl(bm_hss* h, hipStream_t s) {
 // Every slice of a y or v vector is written by exactly one box (a parent's
 // unknowns are its children's skeletons; an iteration's output feeds either
 // the next iteration or a root), so the first write of each slice overwrites.
-int solve_impl(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t s, bool trans) {
+hipError_t record_solve(const bm_hss* h, Scratch& sc, const double* b, double* x, int64_t nrhs, bool trans) {
     const int nl = static_cast<int>(h->lv.size());
     const int64_t N2 = 2 * h->N;
-    Scratch sc(s);
     std::vector<double2*> bt(nl), xl(nl);
     hipError_t e = hipSuccess;
     for (int li = 0; li < nl && e == hipSuccess; ++li) {
@@ -1546,7 +1585,7 @@ int solve_impl(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStr
     }
     double2* xroot;
     if (e == hipSuccess) e = sc.alloc(&xroot, h->Ktot * nrhs);
-    if (e != hipSuccess) { sc.release(); return hip_fail(e, "bm_hss_solve: buffers"); }
+    if (e != hipSuccess) return e;
     const double2* bin = reinterpret_cast<const double2*>(b);
     if (trans) {
         double2* z = reinterpret_cast<double2*>(x);
@@ -1624,7 +1663,6 @@ int solve_impl(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStr
                                   ldout, f.n[q], nrhs, f.k[q], make_double2(1.0, 0.0), make_double2(1.0, 0.0)));
             e = launch_gemm(sc, gj);
         }
-        if (e == hipSuccess) e = sc.flush();
     } else {
         // input of iteration li: the right-hand side, or the previous iteration's F^T output
         auto stage_in = [&](int li, const double2** ptr, int64_t* ld) {
@@ -1700,9 +1738,15 @@ int solve_impl(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStr
                                      static_cast<int32_t>(nn2), static_cast<int32_t>(nrhs)});
             }
             if (e == hipSuccess) e = launch_copy(sc, cp);
-            if (e == hipSuccess) e = sc.flush();
         }
     }
+    return e;
+}
+
+int solve_impl(const bm_hss* h, const double* b, double* x, int64_t nrhs, hipStream_t s, bool trans) {
+    Scratch sc(s);
+    hipError_t e = record_solve(h, sc, b, x, nrhs, trans);
+    if (e == hipSuccess) e = sc.flush();
     // the job descriptors are staged from host memory: finish before releasing them
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     sc.synced();
@@ -1765,6 +1809,57 @@ int bm_hss_solve_transpose(const bm_hss* h, const double* b, double* x, int64_t 
     return solve_impl(h, b, x, nrhs, s, true);
 }
 
+int bm_hss_solve_graph(const bm_hss* h, const double* b, double* x, int64_t nrhs, int transpose, hipStream_t s) {
+    clear_error();
+    if (!h || !b || !x) return fail(BM_EINVAL, "bm_hss_solve_graph: null argument");
+    if (nrhs < 1 || nrhs > (int64_t{1} << 20)) return fail(BM_EINVAL, "bm_hss_solve_graph: nrhs out of range");
+    if (transpose != 0 && transpose != 1) return fail(BM_EINVAL, "bm_hss_solve_graph: transpose must be 0 or 1");
+    std::lock_guard<std::mutex> lk(h->plan_mu);
+    bm_hss::SolvePlan* plan = nullptr;
+    for (auto& q : h->plans)
+        if (q->nrhs == nrhs && q->trans == (transpose != 0)) plan = q.get();
+    const size_t bytes = static_cast<size_t>(2 * h->N * nrhs) * sizeof(double2);
+    if (!plan) {
+        // first call for this shape: record the solve on a capture stream, upload
+        // its job descriptors once, and capture its launches into a graph
+        auto q = std::make_unique<bm_hss::SolvePlan>();
+        q->nrhs = nrhs;
+        q->trans = transpose != 0;
+        BM_HIP(hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking));
+        q->sc = std::make_unique<Scratch>(q->cap);
+        Scratch& sc = *q->sc;
+        double2 *bi = nullptr, *xo = nullptr;
+        hipError_t e = sc.alloc(&bi, static_cast<size_t>(2 * h->N * nrhs));
+        if (e == hipSuccess) e = sc.alloc(&xo, static_cast<size_t>(2 * h->N * nrhs));
+        q->bin = reinterpret_cast<double*>(bi);
+        q->xout = reinterpret_cast<double*>(xo);
+        if (e == hipSuccess) e = record_solve(h, sc, q->bin, q->xout, nrhs, q->trans);
+        if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: record");
+        if (sc.uses_blas)
+            return fail(BM_ESTATE, "bm_hss_solve_graph: the solve needs library products (a large root "
+                                   "with many right-hand sides); use bm_hss_solve");
+        e = sc.flush_uploads();
+        if (e == hipSuccess) e = hipStreamSynchronize(q->cap);
+        sc.synced();
+        if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: upload");
+        e = hipStreamBeginCapture(q->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: begin capture");
+        const hipError_t er = sc.run_recorded();
+        e = hipStreamEndCapture(q->cap, &q->graph);
+        if (er != hipSuccess) return hip_fail(er, "bm_hss_solve_graph: capture");
+        if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: end capture");
+        BM_HIP(hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0));
+        BM_HIP(hipEventCreateWithFlags(&q->done, hipEventDisableTiming));
+        h->plans.push_back(std::move(q));
+        plan = h->plans.back().get();
+    }
+    BM_HIP(hipMemcpyAsync(plan->bin, b, bytes, hipMemcpyDeviceToDevice, s));
+    BM_HIP(hipGraphLaunch(plan->exec, s));
+    BM_HIP(hipMemcpyAsync(x, plan->xout, bytes, hipMemcpyDeviceToDevice, s));
+    BM_HIP(hipEventRecord(plan->done, s));
+    return BM_OK;
+}
+
 int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out) {
     clear_error();
     if (!h || !out) return fail(BM_EINVAL, "bm_hss_stats: null argument");
@@ -1783,6 +1878,7 @@ int bm_hss_level(const bm_hss* h, int level, bm_hss_level_t* out) {
 
 int bm_hss_destroy(bm_hss* h) {
     if (!h) return BM_OK;
+    h->plans.clear();   // waits for their last launches
     // the blocks return to the allocator tagged with the build stream, so work
     // still queued on that stream finishes before any reuse
     for (auto& f : h->lv) free_factor(f, h->stream);

@@ -192,6 +192,41 @@ def test_hss_stops_compressing_when_ranks_stay_high(gpu_lib):
         assert np.linalg.norm(A.T @ xt - bh) <= 1e-7 * np.linalg.norm(bh)
 
 
+@pytest.mark.parametrize("transpose", [False, True])
+def test_hss_solve_graph_replays_match_eager(gpu_lib, transpose):
+    """bm_hss_solve_graph: the solve captured into a HIP graph on the first call
+    and replayed; every replay (with eager solves and synchronisations in
+    between) must give the eager result.  Two stars, N = 2300, two shapes
+    (nrhs 2 and 1), three replays each."""
+    import torch
+    bm = gpu_lib
+    note(f"hss: graph-replayed solve, transpose={transpose}")
+    media = sc.media_from_index(20.0, 1.5)
+    p, nd = setup(bm, [sc.star(0.3, 5), sc.star(0.2, 3, 1.0, (3.0, 0.5))], [1500, 800], media)
+    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
+    eager = bm.bm_hss_solve_transpose if transpose else bm.bm_hss_solve
+    rng = np.random.default_rng(9)
+    for nrhs in (2, 1):
+        for rep in range(3):
+            B = rng.standard_normal((nrhs, 2 * p.n)) + 1j * rng.standard_normal((nrhs, 2 * p.n))
+            Bt = torch.from_numpy(B[0] if nrhs == 1 else B).cuda().contiguous()
+            ref = eager(h, Bt)
+            torch.cuda.synchronize()
+            got = bm.bm_hss_solve_graph(h, Bt, transpose=transpose)
+            other = eager(h, Bt.flip(-1).contiguous())      # eager work between replays
+            torch.cuda.synchronize()
+            d = (got - ref).abs().max().item()
+            note(f"  nrhs {nrhs} replay {rep}: max |graph - eager| {d:.2e}")
+            assert d <= 1e-13 * ref.abs().max().item()
+            assert other.abs().max().item() > 0
+    # the first right-hand side against the dense oracle as well
+    A = wsbm.assemble_dense(nd, media)
+    b = rng.standard_normal(2 * p.n) + 1j * rng.standard_normal(2 * p.n)
+    x = bm.bm_hss_solve_graph(h, torch.from_numpy(b).cuda(), transpose=transpose).cpu().numpy()
+    ref = np.linalg.solve(A.T if transpose else A, b)
+    assert rel(x, ref) < HSS_BAR
+
+
 def test_hss_rejects_bad_options(gpu_lib):
     bm = gpu_lib
     media = sc.media_from_index(10.0, 1.5)
