@@ -43,8 +43,10 @@ FLOP_PER_PAIR = 400.3
 # the same for the generate-and-reduce kernel (entries times x, block sums)
 FLOP_PER_PAIR_MATVEC = 456.3
 MEASURED_TRAFFIC = {
-    "k_cpqr_step": (2.0 * 1.163e7 + 1.715e7) * 1024 / 864,   # one HSS build: 864 launches
-    "k_dense": (2.0 * 5027 + 1.678e7) * 1024,                # one sweep: one launch
+    # two HSS builds (the timed one and the solve-timing one): 1728 launches of
+    # k_cpqr_step_reg<8> and <16>
+    "k_cpqr_step_reg": (2.0 * (13792507.9 + 5523989.9) + (24419051.1 + 9877921.3)) * 1024 / 1728,
+    "k_dense": (2.0 * 5036.5 + 16777709.8) * 1024,                # one sweep: one launch
 }
 
 
@@ -391,7 +393,7 @@ def run_hss(args):
     cq_s = avg("seconds_cpqr")
     cq_bytes = st["cpqr_bytes"]
     cq_gbs = cq_bytes / cq_s / 1e9
-    traffic = MEASURED_TRAFFIC.get("k_cpqr_step") if args.sketch == 0 else None
+    traffic = MEASURED_TRAFFIC.get("k_cpqr_step_reg") if args.sketch == 0 else None
     out = {
         "metric": "Gentries/s Burton-Miller blocks (frac FP64 peak); HSS build+solve s at N=16384",
         "value": entries / (ms * 1e-3) / 1e9,
@@ -418,7 +420,7 @@ def run_hss(args):
                 "per_level": levels},
         "roofline": {"bound": "hbm", "achieved": cq_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": cq_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "k_cpqr_step",
+                     "traffic": traffic, "kernel": "k_cpqr_step_reg",
                      "launches": launches, "algorithmic_bytes_per_launch": cq_bytes / launches,
                      "avg_launch_ms": cq_s / launches * 1e3},
     }

@@ -34,6 +34,7 @@
 #include <rocblas/rocblas.h>
 
 #include "hss_internal.hpp"
+#include "tuned_params.h"
 
 using namespace bm;
 using namespace bm::hss;
@@ -178,6 +179,7 @@ struct Scratch {
     }
     void rec(std::function<hipError_t()> f) { cmds.push_back(std::move(f)); }
     bool uses_blas = false;   // a recorded command calls rocBLAS
+    bool allow_blas = true;   // false: every product stays in the tile kernel (graph capture)
     // the host-to-device copies of the uploads so far
     hipError_t flush_uploads() {
         for (Chunk& c : chunks) {
@@ -295,11 +297,30 @@ hipError_t blas_handle(rocblas_handle* out) {
     return hipSuccess;
 }
 
+// Tuned parameters (tuned_params.h), overridable through the environment for
+// the tuner itself: BMHSS_TUNE_INV_BASE (32, 64 or 128) and
+// BMHSS_TUNE_BLAS_FLOPS.
+int inv_base() {
+    static const int v = [] {
+        const char* e = std::getenv("BMHSS_TUNE_INV_BASE");
+        const int b = e ? std::atoi(e) : tuned::kInvBase;
+        return (b == 32 || b == 64 || b == 128) ? b : tuned::kInvBase;
+    }();
+    return v;
+}
+
 // A product worth a library call: the batched tile kernel runs one 32 x 32
 // tile per workgroup without matrix cores, which is fine for the many small
 // per-box products but slow for the few large ones (the root inverse's Schur
 // recursion, large boxes), where rocBLAS's ZGEMM is used instead.
-constexpr double kBlasFlops = 4e8;
+double blas_flops() {
+    static const double v = [] {
+        const char* e = std::getenv("BMHSS_TUNE_BLAS_FLOPS");
+        const double f = e ? std::atof(e) : tuned::kBlasFlops;
+        return f > 0 ? f : tuned::kBlasFlops;
+    }();
+    return v;
+}
 
 bool blas_layout(int64_t rs, int64_t cs, int64_t rows, int64_t cols, rocblas_operation* op, int64_t* ld) {
     // column-major X (rs == 1, ld = cs) or column-major X^T (cs == 1, ld = rs)
@@ -333,7 +354,7 @@ hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
         int64_t lda, ldb, ldc;
         bool swap;
         const double flops = 8.0 * g.M * g.N * g.K;
-        if (flops < kBlasFlops || g.M == 0 || g.N == 0 || g.K == 0 || !blas_job(g, &oa, &ob, &lda, &ldb, &ldc, &swap)) {
+        if (!sc.allow_blas || flops < blas_flops() || g.M == 0 || g.N == 0 || g.K == 0 || !blas_job(g, &oa, &ob, &lda, &ldb, &ldc, &swap)) {
             small.push_back(g);
             continue;
         }
@@ -479,7 +500,7 @@ GemmJob gemm(const double2* a, int64_t a_rs, int64_t a_cs, const double2* b, int
     return g;
 }
 
-// Inversion of a batch of matrices.  Blocks with n <= kGjMax are inverted by
+// Inversion of a batch of matrices.  Blocks with n <= inv_base() are inverted by
 // pivoted Gauss-Jordan, one workgroup each, in a single launch.  Larger
 // matrices are split 2 x 2, [[A, B], [C, D]], and inverted through the Schur
 // complement S = D - C A^-1 B:
@@ -491,7 +512,7 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
     int nbase = 0;
     for (const InvJob& j : jobs) {
         if (j.n == 0) continue;
-        if (j.n <= kGjMax) {
+        if (j.n <= inv_base()) {
             base.push_back(j);
             nbase = std::max(nbase, j.n);
         } else {
@@ -584,8 +605,20 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
     const unsigned chunks = static_cast<unsigned>(ceil_div(std::max(nmax, 1), kThreads / 64));
     hipLaunchKernelGGL(k_cpqr_init, dim3(chunks, nb), dim3(kThreads), 0, sc.s, dcj);
     if ((e = hipEventRecord(ev0, sc.s)) != hipSuccess) return e;
+    int mmax = 0;
+    for (const CpqrJob& j : cj) mmax = std::max(mmax, j.m);
+    // register-resident columns when every box has at most 64 R rows
+    const int R = mmax <= 256 ? 4 : mmax <= 512 ? 8 : mmax <= 1024 ? 16 : mmax <= 2048 ? 32 : 0;
+    const unsigned rchunks = static_cast<unsigned>(ceil_div(std::max(nmax, 1), (kThreads / 64) * kCpqrCols));
     for (int k = 0; k <= kmax; ++k) {
-        hipLaunchKernelGGL(k_cpqr_step, dim3(chunks, nb), dim3(kThreads), 0, sc.s, dcj, k, tol);
+        const dim3 grid(R ? rchunks : chunks, nb);
+        switch (R) {
+            case 4: hipLaunchKernelGGL(k_cpqr_step_reg<4>, grid, dim3(kThreads), 0, sc.s, dcj, k, tol); break;
+            case 8: hipLaunchKernelGGL(k_cpqr_step_reg<8>, grid, dim3(kThreads), 0, sc.s, dcj, k, tol); break;
+            case 16: hipLaunchKernelGGL(k_cpqr_step_reg<16>, grid, dim3(kThreads), 0, sc.s, dcj, k, tol); break;
+            case 32: hipLaunchKernelGGL(k_cpqr_step_reg<32>, grid, dim3(kThreads), 0, sc.s, dcj, k, tol); break;
+            default: hipLaunchKernelGGL(k_cpqr_step, grid, dim3(kThreads), 0, sc.s, dcj, k, tol); break;
+        }
         ++*launches;
         if (k % 32 == 31 && k < kmax) {
             int32_t h_active = 1;
@@ -1828,6 +1861,7 @@ int bm_hss_solve_graph(const bm_hss* h, const double* b, double* x, int64_t nrhs
         BM_HIP(hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking));
         q->sc = std::make_unique<Scratch>(q->cap);
         Scratch& sc = *q->sc;
+        sc.allow_blas = false;   // library calls are not captured; the tile kernel runs every product
         double2 *bi = nullptr, *xo = nullptr;
         hipError_t e = sc.alloc(&bi, static_cast<size_t>(2 * h->N * nrhs));
         if (e == hipSuccess) e = sc.alloc(&xo, static_cast<size_t>(2 * h->N * nrhs));
@@ -1835,9 +1869,7 @@ int bm_hss_solve_graph(const bm_hss* h, const double* b, double* x, int64_t nrhs
         q->xout = reinterpret_cast<double*>(xo);
         if (e == hipSuccess) e = record_solve(h, sc, q->bin, q->xout, nrhs, q->trans);
         if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: record");
-        if (sc.uses_blas)
-            return fail(BM_ESTATE, "bm_hss_solve_graph: the solve needs library products (a large root "
-                                   "with many right-hand sides); use bm_hss_solve");
+        if (sc.uses_blas) return fail(BM_ESTATE, "bm_hss_solve_graph: internal error (library product recorded)");
         e = sc.flush_uploads();
         if (e == hipSuccess) e = hipStreamSynchronize(q->cap);
         sc.synced();

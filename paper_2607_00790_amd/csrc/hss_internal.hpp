@@ -117,9 +117,15 @@ __global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_
 __global__ void k_gauss_jordan_8(const InvJob* jobs);
 __global__ void k_gauss_jordan_16(const InvJob* jobs);
 __global__ void k_gauss_jordan_32(const InvJob* jobs);
-constexpr int kGjMax = 128;
 __global__ void k_cpqr_init(const CpqrJob* jobs);
 __global__ void k_cpqr_step(const CpqrJob* jobs, int k, double tol);
+// the same step with the trailing columns in registers, for at most 64 R rows;
+// each wave takes kCpqrCols consecutive columns (grid: n / (4 kCpqrCols) per
+// box).  One column per wave is fastest: at 4 the N = 16384 benchmark build
+// took 30 ms instead of 25 (fewer waves in flight per step).
+constexpr int kCpqrCols = 1;
+template <int R>
+__global__ void k_cpqr_step_reg(const CpqrJob* jobs, int k, double tol);
 __global__ void k_cpqr_finish(const CpqrJob* jobs);
 __global__ void k_cpqr_ranks(const CpqrJob* jobs, int nb, int32_t* ranks, int32_t* active);
 

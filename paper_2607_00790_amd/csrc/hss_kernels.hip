@@ -347,6 +347,108 @@ k_cpqr_step(const CpqrJob* __restrict__ jobs, int k, double tol) {
     if (lane == 0) nout[j] = s;
 }
 
+// The same elimination step for matrices of at most 64 R rows: the block
+// stages the Householder column (rows k..m) in LDS once, and each wave keeps
+// its trailing column in registers (R complex values per lane), so a column
+// is read from memory once and written once per step, with all R loads of a
+// lane in flight together.  Pivot choice, rank rule, logical pivoting and the
+// double-buffered norms are those of k_cpqr_step.
+template <int R>
+__global__ void __launch_bounds__(kThreads)
+k_cpqr_step_reg(const CpqrJob* __restrict__ jobs, int k, double tol) {
+    __shared__ double sv[kThreads / 64];
+    __shared__ int si[kThreads / 64];
+    __shared__ double2 ws[64 * R];
+    const CpqrJob jb = jobs[blockIdx.y];
+    CpqrState* st = jb.st;
+    if (st->done) return;
+    const int n = jb.n, m = jb.m;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (k >= (n < m ? n : m)) {
+        if (lead) { st->rank = k; st->done = 1; }
+        return;
+    }
+    const double* __restrict__ nin = jb.nrm + (k & 1) * n;
+    double* __restrict__ nout = jb.nrm + ((k + 1) & 1) * n;
+    const int prev = k > 0 ? jb.perm[k - 1] : -1;
+    double bv = -1;
+    int bi = n;
+    for (int j = threadIdx.x; j < n; j += kThreads)
+        if (!jb.used[j] && j != prev && nin[j] > bv) { bv = nin[j]; bi = j; }
+    block_argmax(bv, bi, sv, si);
+    const double ref = k == 0 ? sqrt(bv) : st->ref;
+    if (!(sqrt(bv) > tol * ref) || ref == 0 || bi >= n) {
+        if (lead) { st->rank = k; st->done = 1; }
+        return;
+    }
+    const int p = bi;
+    const double2* __restrict__ w = jb.x + static_cast<int64_t>(p) * m;
+    const double xn = sqrt(nin[p]);
+    const double2 x0 = w[k];
+    const double a0 = sqrt(cabs2(x0));
+    const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
+    const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
+    const double2 w0 = make_double2(x0.x - alpha.x, x0.y - alpha.y);
+    const double beta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
+    if (lead) {
+        jb.perm[k] = p;
+        jb.rdiag[k] = alpha;
+        if (prev >= 0) jb.used[prev] = 1;
+        if (k == 0) st->ref = ref;
+    }
+    const int mk = m - k;   // active rows, <= 64 R
+    for (int r = threadIdx.x; r < mk; r += kThreads) ws[r] = w[k + r];
+    if (threadIdx.x == 0) ws[0] = w0;   // after its own store of w[k] above
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
+    // kCpqrCols consecutive columns per wave: the pivot search and the staging
+    // of w above are paid once per kCpqrCols * 4 columns
+    for (int jj = 0; jj < kCpqrCols; ++jj) {
+        const int j = (blockIdx.x * nw + wid) * kCpqrCols + jj;
+        if (j >= n) break;
+        if (j == p || j == prev || jb.used[j]) continue;
+        double2* __restrict__ cj = jb.x + static_cast<int64_t>(j) * m + k;
+        double2 c[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int r = lane + 64 * t;
+            c[t] = r < mk ? cj[r] : make_double2(0.0, 0.0);
+        }
+        double gr = 0, gi = 0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int r = lane + 64 * t;
+            if (r < mk) {
+                const double2 v = cconj_mul(ws[r], c[t]);
+                gr += v.x;
+                gi += v.y;
+            }
+        }
+        gr = wave_sum(gr) * beta;
+        gi = wave_sum(gi) * beta;
+        double sn = 0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int r = lane + 64 * t;
+            if (r < mk) {
+                const double2 wr = ws[r];
+                double2 y = c[t];
+                y.x -= gr * wr.x - gi * wr.y;
+                y.y -= gr * wr.y + gi * wr.x;
+                cj[r] = y;
+                if (r > 0) sn += cabs2(y);
+            }
+        }
+        sn = wave_sum(sn);
+        if (lane == 0) nout[j] = sn;
+    }
+}
+
+template __global__ void k_cpqr_step_reg<4>(const CpqrJob*, int, double);
+template __global__ void k_cpqr_step_reg<8>(const CpqrJob*, int, double);
+template __global__ void k_cpqr_step_reg<16>(const CpqrJob*, int, double);
+template __global__ void k_cpqr_step_reg<32>(const CpqrJob*, int, double);
+
 // After the step-wise CPQR: mark the last pivot used and list the remaining
 // columns after the pivots, perm[rank..n) in increasing order.  One workgroup
 // per box.
