@@ -208,8 +208,10 @@ int bm_hss_solve_transpose(const bm_hss* h, const double* b, double* x, int64_t 
  * input/output buffer pair, so they must be ordered on one stream (or
  * synchronised); bm_hss_destroy waits for the last launch of every graph.  The
  * graph holds device memory (the sweep buffers, 2N x nrhs in and out) until
- * bm_hss_destroy.  BM_ESTATE when the solve would need rocBLAS products (a root
- * of more than about 7000/sqrt(nrhs) unknowns), which are not captured. */
+ * bm_hss_destroy.  Every product of the graph runs in the library's own
+ * batched GEMM kernel (library GEMM calls are not captured), so for a very
+ * large root the eager solve, which hands large products to rocBLAS, can be
+ * faster. */
 int bm_hss_solve_graph(const bm_hss* h, const double* b, double* x, int64_t nrhs, int transpose,
                        hipStream_t stream);
 int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out);
