@@ -70,7 +70,9 @@ k_far_weights(NodeView v, int64_t n, const Media* __restrict__ media, double ca,
     g[2 * j + 1] = c_scale(-m.eps0, ph);
 }
 
-__global__ void __launch_bounds__(kThreads, 2)
+// 3 waves per SIMD: the compiler then keeps the pair arithmetic in 168 VGPRs
+// with 23 spilled, which measured 9% faster than 2 waves in 194 VGPRs.
+__global__ void __launch_bounds__(kThreads, 3)
 k_shape_pairs(NodeView v, const int64_t* __restrict__ body_lo, const int64_t* __restrict__ tile_off,
               int nbodies, int64_t t0, const Media* __restrict__ media, const BesselTable* __restrict__ tab,
               const double2* __restrict__ lam, const double2* __restrict__ phi, int64_t n,

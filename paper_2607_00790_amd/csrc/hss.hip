@@ -572,9 +572,13 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
 
 // Column-pivoted QR of every box of a level, step-wise over many workgroups
 // per box; ranks[] is copied back (the caller synchronises).
+// The host does not know when every box has found its rank; it checks (one
+// round trip) first after `first_check` steps -- a guess from the previous
+// level's ranks -- and then every 16 steps.  Steps launched after a box is done
+// return at once.
 hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, int32_t* dranks,
                     double tol, std::vector<int32_t>& ranks, hipEvent_t ev0, hipEvent_t ev1,
-                    int64_t* launches) {
+                    int64_t* launches, int first_check) {
     const int nb = static_cast<int>(cj.size());
     int nmax = 0, kmax = 0;
     for (const CpqrJob& j : cj) {
@@ -620,7 +624,7 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
             default: hipLaunchKernelGGL(k_cpqr_step, grid, dim3(kThreads), 0, sc.s, dcj, k, tol); break;
         }
         ++*launches;
-        if (k % 32 == 31 && k < kmax) {
+        if (k >= first_check && (k - first_check) % 16 == 0 && k < kmax) {
             int32_t h_active = 1;
             hipLaunchKernelGGL(k_cpqr_ranks, dim3(1), dim3(64), 0, sc.s, dcj, nb, dranks, active);
             e = hipMemcpyAsync(&h_active, active, sizeof(int32_t), hipMemcpyDeviceToHost, sc.s);
@@ -1259,7 +1263,12 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = hipEventCreate(&c1);
         if (e == hipSuccess) {
             cpqr_events.emplace_back(c0, c1);
-            e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks, c0, c1, &cpqr_launches);
+            // first rank check: a little above the previous level's largest rank
+            // (ranks grow slowly from level to level), or half the unknowns
+            int64_t guess = 0;
+            for (int c = 0; c < nk; ++c) guess = std::max(guess, kn[c] / 2);
+            if (!h->level_info.empty()) guess = h->level_info.back().max_rank + h->level_info.back().max_rank / 4 + 8;
+            e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks, c0, c1, &cpqr_launches, static_cast<int>(guess));
         }
         if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
