@@ -97,3 +97,44 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(b, "lib_path", lambda: str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         b.load()
+
+
+def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
+    """The adjoint and Fourier entry points validate on the host (no GPU needed)."""
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.bm_fourier_curve.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, vp,
+                                     vp]
+    lib.bm_fourier_chain.argtypes = [vp, i64, ctypes.c_int, ctypes.c_double, vp, vp]
+    lib.bm_shape_derivative.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    lib.bm_hss_solve_graph.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp]
+    lib.bm_hss_solve_transpose.argtypes = [vp, vp, vp, i64, vp]
+    lib.bm_far_field_weights.argtypes = [vp, ctypes.c_double, vp, vp]
+    dummy = ctypes.c_void_p(16)   # never dereferenced: every call below fails validation first
+    assert lib.bm_fourier_curve(dummy, -1, 1.0, 0.0, 0.0, 64, dummy, None) == BM_EINVAL
+    assert lib.bm_fourier_curve(dummy, 4, 0.0, 0.0, 0.0, 64, dummy, None) == BM_EINVAL
+    assert lib.bm_fourier_curve(dummy, 4, 1.0, 0.0, 0.0, 0, dummy, None) == BM_EINVAL
+    assert lib.bm_fourier_curve(None, 4, 1.0, 0.0, 0.0, 64, dummy, None) == BM_EINVAL
+    assert lib.bm_fourier_chain(dummy, 64, 0, 1.0, dummy, None) == BM_EINVAL
+    assert lib.bm_fourier_chain(None, 64, 4, 1.0, dummy, None) == BM_EINVAL
+    assert lib.bm_shape_derivative(None, dummy, dummy, 0.0, 3.0, None, dummy, None) == BM_EINVAL
+    assert lib.bm_hss_solve_graph(None, dummy, dummy, 1, 0, None) == BM_EINVAL
+    assert lib.bm_hss_solve_transpose(None, dummy, dummy, 1, None) == BM_EINVAL
+    assert lib.bm_far_field_weights(None, 0.0, dummy, None) == BM_EINVAL
+
+
+def test_autotuner_writes_the_fastest_candidate(tmp_path, monkeypatch):
+    """The autotuner's selection and header writing, with a stand-in for the GPU timing."""
+    import importlib
+    at = importlib.import_module("paper_2607_00790_amd.autotune")
+    times = {(64, 1e8): 25.0}
+    monkeypatch.setattr(at, "measure", lambda b, f, steps: times.get((b, f), 26.0 + b / 1000 + f / 1e10))
+    out = tmp_path / "tuned.h"
+    monkeypatch.setattr("sys.argv", ["autotune", "--out", str(out), "--repeats", "1"])
+    assert at.main() == 0
+    text = out.read_text()
+    assert "constexpr int kInvBase = 64;" in text
+    assert "constexpr double kBlasFlops = 1e+08;" in text
+    assert text.count("median") == 9 + 1     # one line per candidate, plus the description
+    # the committed header parses the same way
+    committed = open(os.path.join(ROOT, "paper_2607_00790_amd", "csrc", "tuned_params.h")).read()
+    assert re.search(r"constexpr int kInvBase = (32|64|128);", committed)
