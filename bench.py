@@ -43,10 +43,10 @@ FLOP_PER_PAIR = 400.3
 # the same for the generate-and-reduce kernel (entries times x, block sums)
 FLOP_PER_PAIR_MATVEC = 456.3
 MEASURED_TRAFFIC = {
-    # two HSS builds (the timed one and the solve-timing one): 1728 launches of
+    # two HSS builds (the timed one and the solve-timing one): 1614 launches of
     # k_cpqr_step_reg<8> and <16>
-    "k_cpqr_step_reg": (2.0 * (13792507.9 + 5523989.9) + (24419051.1 + 9877921.3)) * 1024 / 1728,
-    "k_dense": (2.0 * 5036.5 + 16777709.8) * 1024,                # one sweep: one launch
+    "k_cpqr_step_reg": (2.0 * 19314652.2 + 34297126.3) * 1024 / 1614,
+    "k_dense": (2.0 * 5041.7 + 16777715.3) * 1024,                # one sweep: one launch
 }
 
 
@@ -430,7 +430,7 @@ def run_hss(args):
 # FP64 operations per ordered pair of the shape-derivative pair kernel, from
 # rocprofv3 --pmc SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 (FMA counted as 2),
 # profiles/pmc_counters_fourier8192.txt
-FLOP_PER_PAIR_ADJOINT = 728.6
+FLOP_PER_PAIR_ADJOINT = 729.6
 
 
 def run_adjoint(args):
