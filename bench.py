@@ -67,6 +67,49 @@ def cpu_baseline(wl, rows: int = 256):
                       f"({rows * wl.n} pairs, {dt:.1f} s; NumPy/SciPy elementwise, one thread)"}
 
 
+def entry_kernel_rates(p, n):
+    """The entry kernels on the benchmark star, outside the timed HSS step: the
+    dense sweep (N^2 pairs written to HBM) and the generate-and-reduce product
+    (the same entries, nothing stored), each as Gentries/s and as a fraction of
+    the published FP64 peak and of the FP64 FMA rate this device sustains
+    (measured by the library's FMA probe in the same run)."""
+    import torch
+    import paper_2607_00790_amd as bm
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    blocks, iters = 256 * 32, 2048
+    buf = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    probe_ms = timed(lambda: bm.bm_fp64_fma_probe(blocks, iters, out=buf), 5)
+    measured = 2.0 * 16 * iters * 256 * blocks / (probe_ms * 1e-3) / 1e12
+    pairs = n * n
+    out = {"fp64_fma_probe_tflops": measured, "fp64_spec_peak_tflops": FP64_VECTOR_PEAK_TF}
+    A = torch.empty((2 * n, 2 * n), dtype=torch.complex128, device="cuda")
+    dense_ms = timed(lambda: bm.bm_assemble_dense(p, out=A), 3)
+    del A
+    x = bm.bm_rhs_plane_wave(p, 0.3)
+    y = torch.empty_like(x)
+    mv_ms = timed(lambda: bm.bm_matvec(p, x, out=y), 3)
+    for name, ms, fpp in (("dense", dense_ms, FLOP_PER_PAIR), ("matvec", mv_ms, FLOP_PER_PAIR_MATVEC)):
+        tf = fpp * pairs / (ms * 1e-3) / 1e12
+        out[name] = {"ms": ms, "Gentries_s": 4 * pairs / (ms * 1e-3) / 1e9, "flop_per_pair": fpp, "tflops": tf,
+                     "frac_spec_peak": tf / FP64_VECTOR_PEAK_TF, "frac_measured_peak": tf / measured}
+    out["dense"]["hbm_GBs"] = BYTES_PER_PAIR * pairs / (dense_ms * 1e-3) / 1e9
+    out["dense"]["hbm_frac"] = out["dense"]["hbm_GBs"] / HBM_PEAK_GBS
+    return out
+
+
 def run_dense(args):
     import torch
     import scatterers as sc
@@ -386,6 +429,8 @@ def run_hss(args):
         solve_ms[name] = (time.perf_counter() - t1) / 20 * 1e3
     del h
 
+    entry = entry_kernel_rates(p, wl.n)
+
     gen_s = avg("seconds_generate")
     entries = st["entries"]
     # dominant kernel of the step: the CPQR step kernel of the ID
@@ -418,6 +463,7 @@ def run_hss(args):
                 "generation_Gentries_s": entries / gen_s / 1e9,
                 "solve_ms_eager": solve_ms["eager"], "solve_ms_graph": solve_ms["graph"],
                 "per_level": levels},
+        "entry_generation": entry,
         "roofline": {"bound": "hbm", "achieved": cq_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": cq_gbs / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "k_cpqr_step_reg",

@@ -266,6 +266,14 @@ int bm_fourier_curve(const double* coef, int nmodes, double radius, double cx, d
  * derivative from bm_shape_derivative turned into d/d(a_1..a_M, b_1..b_M). */
 int bm_fourier_chain(const double* grad, int64_t n, int nmodes, double radius, double* out, hipStream_t stream);
 
+/* ---- Diagnostics ----
+ * The FP64 FMA rate the device sustains: blocks x 256 threads, each running 16
+ * independent chains of `iters` fused multiply-adds (2 * 16 * iters real flops
+ * per thread), and writing one double per thread to out (device, blocks * 256
+ * doubles).  Time it with events on `stream`; the entry kernels' FP64 fraction
+ * is reported against this rate as well as against the published peak. */
+int bm_fp64_fma_probe(double* out, int64_t blocks, int64_t iters, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,7 @@ from ._binding import (  # noqa: F401
     bm_shape_derivative,
     bm_fourier_curve,
     bm_fourier_chain,
+    bm_fp64_fma_probe,
     lib_path,
     load,
 )

@@ -86,6 +86,7 @@ def load():
         "bm_shape_derivative": (ctypes.c_int, [c_vp, c_vp, c_vp, c_dbl, c_dbl, c_vp, c_vp, c_vp]),
         "bm_fourier_curve": (ctypes.c_int, [c_vp, ctypes.c_int, c_dbl, c_dbl, c_dbl, c_i64, c_vp, c_vp]),
         "bm_fourier_chain": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_dbl, c_vp, c_vp]),
+        "bm_fp64_fma_probe": (ctypes.c_int, [c_vp, c_i64, c_i64, c_vp]),
         "bm_hss_stats": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssStats)]),
         "bm_hss_level": (ctypes.c_int, [c_vp, ctypes.c_int, ctypes.POINTER(_HssLevel)]),
         "bm_hss_destroy": (ctypes.c_int, [c_vp]),
@@ -407,4 +408,13 @@ def bm_fourier_chain(grad, nmodes: int, radius: float = 1.0, out=None, stream=No
     n = grad.shape[-1]
     _check(load().bm_fourier_chain(_dev_ptr(grad, torch.float64, "grad"), int(n), int(nmodes), float(radius),
                                  _dev_ptr(out, torch.float64, "out"), _stream(stream)))
+    return out
+
+
+def bm_fp64_fma_probe(blocks: int, iters: int, out=None, stream=None):
+    """Runs the FP64 FMA probe (2 * 16 * iters * 256 * blocks flops); time it with events."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(int(blocks) * 256, dtype=torch.float64, device="cuda")
+    _check(load().bm_fp64_fma_probe(_dev_ptr(out, torch.float64, "out"), int(blocks), int(iters), _stream(stream)))
     return out

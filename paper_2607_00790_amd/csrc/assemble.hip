@@ -78,6 +78,16 @@ __device__ __forceinline__ void emit_pair(double* __restrict__ out, int64_t ld, 
 
 __device__ __forceinline__ int body_of(const NodeView& v, int64_t i) { return v.body ? v.body[i] : 0; }
 
+// The media of a body with the coefficient table taken from a kernel argument.
+// Every Media holds the same table pointer, but one read from device memory
+// leaves the compiler with a generic pointer, and the coefficient loads through
+// it then ran at half speed on some devices (the generate-and-reduce product:
+// 8.1 ms against 3.8 ms with the pointer as a kernel argument).
+__device__ __forceinline__ Media with_table(Media m, const BesselTable* __restrict__ tab) {
+    m.tab = tab;
+    return m;
+}
+
 // Zero 2x2 block (a pair in two different bodies).
 __device__ __forceinline__ void store_zero(double* __restrict__ out, int64_t ld, int64_t row, int64_t col) {
     double2* r0 = reinterpret_cast<double2*>(out) + (2 * row) * ld + 2 * col;
@@ -120,12 +130,12 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV]) {
 // [jt*kThreads, (jt+1)*kThreads), jt = b % ntj.
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_dense(NodeView v, int64_t n, int64_t ntj, const Media* __restrict__ media, double* __restrict__ A,
-        int64_t ld) {
+        int64_t ld, const BesselTable* __restrict__ tab) {
     const int64_t i = blockIdx.x / ntj;
     const int64_t j = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     if (j >= n) return;
     const int bi = body_of(v, i);   // wave-uniform: the media come through the scalar cache
-    const Media m = media[bi];
+    const Media m = with_table(media[bi], tab);
     if (body_of(v, j) != bi) {
         store_zero(A, ld, i, j);
     } else if (i == j) {
@@ -139,13 +149,14 @@ k_dense(NodeView v, int64_t n, int64_t ntj, const Media* __restrict__ media, dou
 // Block for node index lists: workgroup b covers row a = b / ntj.
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_block(NodeView v, const Media* __restrict__ media, const int64_t* __restrict__ rows,
-        const int64_t* __restrict__ cols, int64_t nc, int64_t ntj, double* __restrict__ out, int64_t ld) {
+        const int64_t* __restrict__ cols, int64_t nc, int64_t ntj, double* __restrict__ out, int64_t ld,
+        const BesselTable* __restrict__ tab) {
     const int64_t a = blockIdx.x / ntj;
     const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     if (c >= nc) return;
     const int64_t i = rows[a], j = cols[c];
     const int bi = body_of(v, i);
-    const Media m = media[bi];
+    const Media m = with_table(media[bi], tab);
     if (body_of(v, j) != bi) {
         store_zero(out, ld, a, c);
     } else if (i == j) {
@@ -161,14 +172,14 @@ k_block(NodeView v, const Media* __restrict__ media, const int64_t* __restrict__
 __global__ void __launch_bounds__(kThreads)
 k_proxy(NodeView v, const Media* __restrict__ media, const int64_t* __restrict__ nodes, int64_t n,
         const double* __restrict__ pts, int64_t P, int dir, int64_t ntj, double* __restrict__ out,
-        int64_t ld) {
+        int64_t ld, const BesselTable* __restrict__ tab) {
     const int64_t ncol = dir == 0 ? P : n;
     const int64_t a = blockIdx.x / ntj;
     const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
     if (c >= ncol) return;
     double tx, ty, tnx, tny, sx, sy, snx, sny, sw;
     // the proxy point takes the media of the node it is paired with
-    const Media m = media[body_of(v, dir == 0 ? nodes[a] : nodes[c])];
+    const Media m = with_table(media[body_of(v, dir == 0 ? nodes[a] : nodes[c])], tab);
     if (dir == 0) {
         const int64_t i = nodes[a];
         tx = v.x[i]; ty = v.y[i]; tnx = v.nx[i]; tny = v.ny[i];
@@ -201,14 +212,14 @@ k_rhs_plane_wave(NodeView v, int64_t n, const Media* __restrict__ media, double 
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_matvec_partial(NodeView v, const int64_t* __restrict__ body_lo, int64_t ntj, int64_t i0,
                  const Media* __restrict__ media, const double2* __restrict__ x,
-                 double4* __restrict__ part) {
+                 double4* __restrict__ part, const BesselTable* __restrict__ tab) {
     // tiles run over the target's own body only (the system is block diagonal);
     // the launch covers targets i0, i0 + 1, ...
     const int64_t i = i0 + blockIdx.x / ntj;
     const int bi = body_of(v, i);
     const int64_t j = body_lo[bi] + (blockIdx.x % ntj) * kThreads + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const Media m = media[bi];
+    const Media m = with_table(media[bi], tab);
     if (j < body_lo[bi + 1]) {
         Block b;
         if (i == j) {
@@ -288,31 +299,31 @@ hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurve
     return hipGetLastError();
 }
 
-hipError_t launch_dense(const NodeView& v, int64_t n, const Media* m, double* A, int64_t ld,
-                        hipStream_t s) {
+hipError_t launch_dense(const NodeView& v, int64_t n, const Media* m, const BesselTable* tab, double* A,
+                        int64_t ld, hipStream_t s) {
     const int64_t ntj = (n + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_dense, dim3(static_cast<unsigned>(n * ntj)), dim3(kThreads), 0, s, v, n,
-                       ntj, m, A, ld);
+                       ntj, m, A, ld, tab);
     return hipGetLastError();
 }
 
-hipError_t launch_block(const NodeView& v, const Media* m, const int64_t* rows, int64_t nr,
-                        const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s) {
+hipError_t launch_block(const NodeView& v, const Media* m, const BesselTable* tab, const int64_t* rows,
+                        int64_t nr, const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s) {
     if (nr == 0 || nc == 0) return hipSuccess;
     const int64_t ntj = (nc + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_block, dim3(static_cast<unsigned>(nr * ntj)), dim3(kThreads), 0, s, v, m,
-                       rows, cols, nc, ntj, out, ld);
+                       rows, cols, nc, ntj, out, ld, tab);
     return hipGetLastError();
 }
 
-hipError_t launch_proxy(const NodeView& v, const Media* m, const int64_t* nodes, int64_t n,
-                        const double* pts, int64_t P, int dir, double* out, int64_t ld,
+hipError_t launch_proxy(const NodeView& v, const Media* m, const BesselTable* tab, const int64_t* nodes,
+                        int64_t n, const double* pts, int64_t P, int dir, double* out, int64_t ld,
                         hipStream_t s) {
     if (n == 0 || P == 0) return hipSuccess;
     const int64_t ncol = dir == 0 ? P : n, nrow = dir == 0 ? n : P;
     const int64_t ntj = (ncol + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_proxy, dim3(static_cast<unsigned>(nrow * ntj)), dim3(kThreads), 0, s, v,
-                       m, nodes, n, pts, P, dir, ntj, out, ld);
+                       m, nodes, n, pts, P, dir, ntj, out, ld, tab);
     return hipGetLastError();
 }
 
@@ -324,7 +335,8 @@ hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* m, d
 }
 
 hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const int64_t* body_lo,
-                         const Media* m, const double* x, double* y, double* work, hipStream_t s) {
+                         const Media* m, const BesselTable* tab, const double* x, double* y, double* work,
+                         hipStream_t s) {
     const int64_t ntj = (max_body + kThreads - 1) / kThreads;
     double4* part = reinterpret_cast<double4*>(work);
     // at most 2^24 - 1 workgroups (2^32 - 1 work-items) per launch
@@ -332,7 +344,7 @@ hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const i
     for (int64_t i0 = 0; i0 < n; i0 += chunk) {
         const int64_t nt = std::min(chunk, n - i0);
         hipLaunchKernelGGL(k_matvec_partial, dim3(static_cast<unsigned>(nt * ntj)), dim3(kThreads), 0,
-                           s, v, body_lo, ntj, i0, m, reinterpret_cast<const double2*>(x), part);
+                           s, v, body_lo, ntj, i0, m, reinterpret_cast<const double2*>(x), part, tab);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -252,7 +252,7 @@ int bm_assemble_dense(const bm_problem* p, double* A, int64_t ld, hipStream_t st
     const int64_t n = p->g->n;
     if (ld < 2 * n) return fail(BM_EINVAL, "bm_assemble_dense: ld < 2N");
     if (n * ((n + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_dense: N too large");
-    BM_HIP(launch_dense(view(p), n, p->d_media, A, ld, stream));
+    BM_HIP(launch_dense(view(p), n, p->d_media, p->media[0].tab, A, ld, stream));
     return BM_OK;
 }
 
@@ -265,7 +265,7 @@ int bm_assemble_block(const bm_problem* p, const int64_t* rows, int64_t nr, cons
     if (!rows || !cols || !out) return fail(BM_EINVAL, "bm_assemble_block: null array");
     if (ld < 2 * nc) return fail(BM_EINVAL, "bm_assemble_block: ld < 2 nc");
     if (nr * ((nc + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_block: too large");
-    BM_HIP(launch_block(view(p), p->d_media, rows, nr, cols, nc, out, ld, stream));
+    BM_HIP(launch_block(view(p), p->d_media, p->media[0].tab, rows, nr, cols, nc, out, ld, stream));
     return BM_OK;
 }
 
@@ -280,7 +280,7 @@ int bm_assemble_proxy(const bm_problem* p, const int64_t* nodes, int64_t n, cons
     const int64_t ncol = dir == 0 ? P : n, nrow = dir == 0 ? n : P;
     if (ld < 2 * ncol) return fail(BM_EINVAL, "bm_assemble_proxy: ld too small");
     if (nrow * ((ncol + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_proxy: too large");
-    BM_HIP(launch_proxy(view(p), p->d_media, nodes, n, pts, P, dir, out, ld, stream));
+    BM_HIP(launch_proxy(view(p), p->d_media, p->media[0].tab, nodes, n, pts, P, dir, out, ld, stream));
     return BM_OK;
 }
 
@@ -294,7 +294,7 @@ int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t strea
     if ((max_body + 255) / 256 > kMaxGrid) return fail(BM_EINVAL, "bm_matvec: body too large");
     void* work = nullptr;
     BM_HIP(dev_alloc(&work, matvec_work_doubles(n, max_body) * sizeof(double), stream));
-    const hipError_t e = launch_matvec(view(p), n, max_body, p->d_body_lo, p->d_media, x, y,
+    const hipError_t e = launch_matvec(view(p), n, max_body, p->d_body_lo, p->d_media, p->media[0].tab, x, y,
                                        static_cast<double*>(work), stream);
     dev_free(work, stream);
     if (e != hipSuccess) return hip_fail(e, "bm_matvec");

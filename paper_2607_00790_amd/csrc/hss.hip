@@ -245,17 +245,19 @@ hipError_t launch_in_groups(const std::vector<Job>& jobs, Tiles tiles, Launch la
 }
 
 hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
-                            const PointTable& pt, const Media* media, double2* out);
+                            const PointTable& pt, const Media* media, const BesselTable* tab, double2* out);
 
+// `media` is the device media array, `tab` the device coefficient table every
+// Media points to (passed to the kernel as an argument of its own).
 hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
-                      const PointTable& pt, const Media* media, double2* out) {
+                      const PointTable& pt, const Media* media, const BesselTable* tab, double2* out) {
     return launch_in_groups(
         jobs, [](const GenJob& j) { return ceil_div(static_cast<int64_t>(j.nt) * j.ns, kThreads); },
-        [&](const std::vector<GenJob>& g) { return launch_gen_group(sc, g, slots, pt, media, out); });
+        [&](const std::vector<GenJob>& g) { return launch_gen_group(sc, g, slots, pt, media, tab, out); });
 }
 
 hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
-                            const PointTable& pt, const Media* media, double2* out) {
+                            const PointTable& pt, const Media* media, const BesselTable* tab, double2* out) {
     if (jobs.empty()) return hipSuccess;
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
@@ -271,7 +273,7 @@ hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const 
     const PointTable ptc = pt;
     hipStream_t st = sc.s;
     sc.rec([=]() {
-        hipLaunchKernelGGL(k_gen_jobs, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, media, out);
+        hipLaunchKernelGGL(k_gen_jobs, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, media, out, tab);
         return hipGetLastError();
     });
     return hipSuccess;
@@ -1195,7 +1197,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
             pairs += 2 * static_cast<int64_t>(na) * (nn + pb);
         }
         hipEvent_t ev;
-        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->d_media, M);
+        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->d_media, p->media[0].tab, M);
         if (e == hipSuccess) e = t_gen.stop(sc, ev);
         if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: generate M"); }
 
@@ -1421,7 +1423,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
                                          kn[c], 1, static_cast<int32_t>(kb), static_cast<int32_t>(kb)});
             }
         }
-        if ((e = t_gen.start(fs, ev)) == hipSuccess) e = launch_gen(fs, jobs, dslots, pt, p->d_media, F.G);
+        if ((e = t_gen.start(fs, ev)) == hipSuccess) e = launch_gen(fs, jobs, dslots, pt, p->d_media, p->media[0].tab, F.G);
         if (e == hipSuccess) e = t_gen.stop(fs, ev);
         if (e == hipSuccess) e = launch_copy(fs, copies);
         if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: D blocks"); }
@@ -1542,7 +1544,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
             pairs += static_cast<int64_t>(r.nslots) * r.nslots;
         }
         hipEvent_t ev;
-        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, drs, pt, p->d_media, h->Rinv);
+        if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, drs, pt, p->d_media, p->media[0].tab, h->Rinv);
         if (e == hipSuccess) e = t_gen.stop(sc, ev);
         // diagonal blocks of a root are the Dhat of the boxes it is made of
         for (size_t c = 0; c < root_copies.size(); ++c) root_copies[c].dst = h->Rinv + root_copy_dst[c];

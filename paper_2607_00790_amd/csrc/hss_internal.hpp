@@ -110,7 +110,8 @@ __global__ void k_near_list(PointTable pt, const Slot* slots, const int32_t* slo
                             const int64_t* scan_lo, const int64_t* scan_hi, const double* box_c,
                             const int64_t* slot_off, Slot* out);
 __global__ void k_gen_jobs(const GenJob* jobs, const int64_t* tile_off, int njobs,
-                           const Slot* slots, PointTable pt, const Media* media, double2* out);
+                           const Slot* slots, PointTable pt, const Media* media, double2* out,
+                           const BesselTable* tab);
 __global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
                          double2* Tbuf);
 // in-place inverse of n x n blocks, n <= 32 / 64 / 128; blockDim 64 / 256 / 1024

@@ -199,7 +199,7 @@ k_near_list(PointTable pt, const Slot* __restrict__ slots, const int32_t* __rest
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
            const Slot* __restrict__ slots, PointTable pt, const Media* __restrict__ media,
-           double2* __restrict__ out) {
+           double2* __restrict__ out, const BesselTable* __restrict__ tab) {
     int lo = 0, hi = njobs;
     const int64_t tile = blockIdx.x;
     while (hi - lo > 1) {
@@ -207,7 +207,8 @@ k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off
         if (tile_off[mid] <= tile) lo = mid; else hi = mid;
     }
     const GenJob jb = jobs[lo];
-    const Media m = media[jb.body];
+    Media m = media[jb.body];
+    m.tab = tab;   // the table through a kernel argument: scalar loads of known global memory
     const int64_t q = (tile - tile_off[lo]) * kThreads + threadIdx.x;
     if (q >= static_cast<int64_t>(jb.nt) * jb.ns) return;
     const int t = static_cast<int>(q / jb.ns);

@@ -79,12 +79,14 @@ void dev_free(void* p, hipStream_t s);
 hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurves, int64_t n,
                            double* soa, int32_t* curve, hipStream_t s);
 // `media` is the device array of per-body media (NodeView::body selects).
-hipError_t launch_dense(const NodeView& v, int64_t n, const Media* media, double* A, int64_t ld,
-                        hipStream_t s);
-hipError_t launch_block(const NodeView& v, const Media* media, const int64_t* rows, int64_t nr,
-                        const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s);
-hipError_t launch_proxy(const NodeView& v, const Media* media, const int64_t* nodes, int64_t n,
-                        const double* pts, int64_t P, int dir, double* out, int64_t ld,
+// `tab` is the device coefficient table (the one every Media points to), passed
+// to the kernels as an argument of its own.
+hipError_t launch_dense(const NodeView& v, int64_t n, const Media* media, const BesselTable* tab, double* A,
+                        int64_t ld, hipStream_t s);
+hipError_t launch_block(const NodeView& v, const Media* media, const BesselTable* tab, const int64_t* rows,
+                        int64_t nr, const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s);
+hipError_t launch_proxy(const NodeView& v, const Media* media, const BesselTable* tab, const int64_t* nodes,
+                        int64_t n, const double* pts, int64_t P, int dir, double* out, int64_t ld,
                         hipStream_t s);
 hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* media, double angle,
                                  double* rhs, hipStream_t s);
@@ -92,7 +94,8 @@ hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* medi
 // in nodes, body_lo = device node offsets of the bodies); `work` is a device
 // buffer of matvec_work_doubles(n, max_body) doubles
 hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const int64_t* body_lo,
-                         const Media* media, const double* x, double* y, double* work, hipStream_t s);
+                         const Media* media, const BesselTable* tab, const double* x, double* y, double* work,
+                         hipStream_t s);
 int64_t matvec_work_doubles(int64_t n, int64_t max_body);
 // far field of every body: uinf[b * nang + a]; body_lo = first node of each body
 hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* media,

@@ -180,3 +180,23 @@ def test_invalid_arguments_enqueue_nothing(gpu_lib):
         bm.bm_assemble_dense(p, out=torch.empty((128, 100), dtype=torch.complex128, device="cuda"))
     with pytest.raises(bm.BmError):
         bm.bm_assemble_proxy(p, torch.arange(4), torch.zeros((5, 3), dtype=torch.float64).cuda(), 2)
+
+
+def test_fp64_fma_probe_values(gpu_lib):
+    """The FMA probe computes what it claims: per thread, 16 chains of
+    a <- a x + y from a_c = 1e-3 (c + 1), x = 1 + 1e-9 (t mod 1024), y = 1e-12 (t mod 256);
+    after n steps a_n = a_0 x^n + y (x^n - 1)/(x - 1) (x = 1: a_0 + n y)."""
+    import torch
+    bm = gpu_lib
+    blocks, iters = 4, 300
+    out = bm.bm_fp64_fma_probe(blocks, iters).cpu().numpy()
+    for t in (0, 1, 255, 256, 1023, 1024 - 1, blocks * 256 - 1):
+        x = 1.0 + 1e-9 * (t & 1023)
+        y = 1e-12 * (t % 256)
+        a0 = 1e-3 * np.arange(1, 17)
+        if x == 1.0:
+            ref = np.sum(a0 + iters * y)
+        else:
+            xn = x ** iters
+            ref = np.sum(a0 * xn + y * (xn - 1.0) / (x - 1.0))
+        assert abs(out[t] - ref) <= 1e-12 * abs(ref), (t, out[t], ref)
