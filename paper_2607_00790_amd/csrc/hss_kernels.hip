@@ -32,6 +32,28 @@ __device__ __forceinline__ double2 cconj_mul(double2 a, double2 b) {   // conj(a
 }
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
+// Loads and stores through pointers known to address global memory.  Pointers
+// read from job descriptors are generic to the compiler, which then emits flat
+// memory instructions; these casts let it use global ones.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ double2 gload2(const double2* p) {
+    const gdouble* q = (const gdouble*)(const double*)p;
+    return make_double2(q[0], q[1]);
+}
+__device__ __forceinline__ void gstore2(double2* p, double2 v) {
+    gdouble* q = (gdouble*)(double*)p;
+    q[0] = v.x;
+    q[1] = v.y;
+}
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) {
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -270,7 +292,7 @@ k_cpqr_init(const CpqrJob* __restrict__ jobs) {
         jb.used[j] = 0;
     }
     double s = 0;
-    for (int r = lane; r < jb.m; r += 64) s += cabs2(jb.x[static_cast<int64_t>(j) * jb.m + r]);
+    for (int r = lane; r < jb.m; r += 64) s += cabs2(gload2(jb.x + static_cast<int64_t>(j) * jb.m + r));
     s = wave_sum(s);
     if (lane == 0) jb.nrm[j] = s;
 }
@@ -362,43 +384,43 @@ k_cpqr_step_reg(const CpqrJob* __restrict__ jobs, int k, double tol) {
     __shared__ double2 ws[64 * R];
     const CpqrJob jb = jobs[blockIdx.y];
     CpqrState* st = jb.st;
-    if (st->done) return;
+    if (gld(&st->done)) return;
     const int n = jb.n, m = jb.m;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (k >= (n < m ? n : m)) {
-        if (lead) { st->rank = k; st->done = 1; }
+        if (lead) { gst(&st->rank, k); gst(&st->done, 1); }
         return;
     }
     const double* __restrict__ nin = jb.nrm + (k & 1) * n;
     double* __restrict__ nout = jb.nrm + ((k + 1) & 1) * n;
-    const int prev = k > 0 ? jb.perm[k - 1] : -1;
+    const int prev = k > 0 ? gld(jb.perm + k - 1) : -1;
     double bv = -1;
     int bi = n;
     for (int j = threadIdx.x; j < n; j += kThreads)
-        if (!jb.used[j] && j != prev && nin[j] > bv) { bv = nin[j]; bi = j; }
+        if (!gld(jb.used + j) && j != prev && gld(nin + j) > bv) { bv = gld(nin + j); bi = j; }
     block_argmax(bv, bi, sv, si);
-    const double ref = k == 0 ? sqrt(bv) : st->ref;
+    const double ref = k == 0 ? sqrt(bv) : gld(&st->ref);
     if (!(sqrt(bv) > tol * ref) || ref == 0 || bi >= n) {
-        if (lead) { st->rank = k; st->done = 1; }
+        if (lead) { gst(&st->rank, k); gst(&st->done, 1); }
         return;
     }
     const int p = bi;
     const double2* __restrict__ w = jb.x + static_cast<int64_t>(p) * m;
-    const double xn = sqrt(nin[p]);
-    const double2 x0 = w[k];
+    const double xn = sqrt(gld(nin + p));
+    const double2 x0 = gload2(w + k);
     const double a0 = sqrt(cabs2(x0));
     const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
     const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
     const double2 w0 = make_double2(x0.x - alpha.x, x0.y - alpha.y);
     const double beta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
     if (lead) {
-        jb.perm[k] = p;
-        jb.rdiag[k] = alpha;
-        if (prev >= 0) jb.used[prev] = 1;
-        if (k == 0) st->ref = ref;
+        gst(jb.perm + k, p);
+        gstore2(jb.rdiag + k, alpha);
+        if (prev >= 0) gst(jb.used + prev, 1);
+        if (k == 0) gst(&st->ref, ref);
     }
     const int mk = m - k;   // active rows, <= 64 R
-    for (int r = threadIdx.x; r < mk; r += kThreads) ws[r] = w[k + r];
+    for (int r = threadIdx.x; r < mk; r += kThreads) ws[r] = gload2(w + k + r);
     if (threadIdx.x == 0) ws[0] = w0;   // after its own store of w[k] above
     __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
@@ -407,13 +429,13 @@ k_cpqr_step_reg(const CpqrJob* __restrict__ jobs, int k, double tol) {
     for (int jj = 0; jj < kCpqrCols; ++jj) {
         const int j = (blockIdx.x * nw + wid) * kCpqrCols + jj;
         if (j >= n) break;
-        if (j == p || j == prev || jb.used[j]) continue;
+        if (j == p || j == prev || gld(jb.used + j)) continue;
         double2* __restrict__ cj = jb.x + static_cast<int64_t>(j) * m + k;
         double2 c[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             const int r = lane + 64 * t;
-            c[t] = r < mk ? cj[r] : make_double2(0.0, 0.0);
+            c[t] = r < mk ? gload2(cj + r) : make_double2(0.0, 0.0);
         }
         double gr = 0, gi = 0;
 #pragma unroll
@@ -436,12 +458,12 @@ k_cpqr_step_reg(const CpqrJob* __restrict__ jobs, int k, double tol) {
                 double2 y = c[t];
                 y.x -= gr * wr.x - gi * wr.y;
                 y.y -= gr * wr.y + gi * wr.x;
-                cj[r] = y;
+                gstore2(cj + r, y);
                 if (r > 0) sn += cabs2(y);
             }
         }
         sn = wave_sum(sn);
-        if (lane == 0) nout[j] = sn;
+        if (lane == 0) gst(nout + j, sn);
     }
 }
 
@@ -509,28 +531,30 @@ k_interp(const CpqrJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < k; i += kThreads)
-            T[static_cast<int64_t>(jb.perm[i]) * k + i] = make_double2(1.0, 0.0);
+            gstore2(T + static_cast<int64_t>(gld(jb.perm + i)) * k + i, make_double2(1.0, 0.0));
     const int c = blockIdx.x * nw + wid;
     if (c >= n - k) return;
     // column of X holding pivot l: l after physical swaps, perm[l] with logical pivoting
     const bool logical = jb.used != nullptr;
-    const double2* rc = X + static_cast<int64_t>(logical ? jb.perm[k + c] : k + c) * m;
-    double2* z = T + static_cast<int64_t>(jb.perm[k + c]) * k;
+    const int pc = gld(jb.perm + k + c);
+    const double2* rc = X + static_cast<int64_t>(logical ? pc : k + c) * m;
+    double2* z = T + static_cast<int64_t>(pc) * k;
     for (int i = k - 1; i >= 0; --i) {
         double sr = 0, si = 0;
         for (int l = i + 1 + ((lane - i - 1) & 63); l < k; l += 64) {   // l = lane (mod 64)
-            const int64_t cl = logical ? jb.perm[l] : l;
-            const double2 t = cmul(X[cl * m + i], z[l]);
+            const int64_t cl = logical ? gld(jb.perm + l) : l;
+            const double2 t = cmul(gload2(X + cl * m + i), gload2(z + l));
             sr += t.x;
             si += t.y;
         }
         sr = wave_sum(sr);
         si = wave_sum(si);
-        const double2 num = make_double2(rc[i].x - sr, rc[i].y - si);
-        const double2 d = jb.rdiag[i];
+        const double2 ri = gload2(rc + i);
+        const double2 num = make_double2(ri.x - sr, ri.y - si);
+        const double2 d = gload2(jb.rdiag + i);
         const double dd = cabs2(d);
         if ((i & 63) == lane)
-            z[i] = make_double2((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
+            gstore2(z + i, make_double2((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd));
     }
 }
 
@@ -592,7 +616,7 @@ __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int i = r0 + r, j = c0 + c;
-            S[r][c] = (i < n && j < n) ? jb.a[i * ld + j] : make_double2(0.0, 0.0);
+            S[r][c] = (i < n && j < n) ? gload2(jb.a + i * ld + j) : make_double2(0.0, 0.0);
         }
     if (tx == 0) {
 #pragma unroll
@@ -638,7 +662,7 @@ __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
                                 __builtin_amdgcn_readlane(__double2loint(pv.y), p & 63));
         const double pd = cabs2(pv);
         if ((key >> 7) == 0 || !(pd > 0.0) || !(pd < INFINITY)) {
-            if (tid == 0) *jb.status = 1;
+            if (tid == 0) gst(jb.status, 1);
             return;   // key and pd are the same in every wave: the whole workgroup leaves
         }
         used[p >> 6] |= 1ull << (p & 63);
@@ -695,7 +719,7 @@ __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
         double2* out = jb.a + pinv[i] * ld;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-            if (c0 + c < n) out[perm[c0 + c]] = S[r][c];
+            if (c0 + c < n) gstore2(out + perm[c0 + c], S[r][c]);
     }
 }
 
@@ -753,7 +777,7 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
         for (int q = 0; q < 4; ++q) {
             const int jj = tid / 16 + 16 * q, kk = tid % 16;
             const int j = c0 + jj, l = l0 + kk;
-            Xs[kk][jj] = (j < jb.n && l < jb.m) ? jb.x[static_cast<int64_t>(j) * jb.m + l]
+            Xs[kk][jj] = (j < jb.n && l < jb.m) ? gload2(jb.x + static_cast<int64_t>(j) * jb.m + l)
                                                 : make_double2(0.0, 0.0);
         }
         __syncthreads();
@@ -782,7 +806,7 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int r = r0 + tr + 16 * a;
-            if (r < jb.l) jb.y[static_cast<int64_t>(j) * jb.l + r] = acc[a][b];
+            if (r < jb.l) gstore2(jb.y + static_cast<int64_t>(j) * jb.l + r, acc[a][b]);
         }
     }
 }
@@ -817,12 +841,12 @@ k_gemm(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, i
         for (int e = threadIdx.x; e < TM * TK; e += kThreads) {
             const int r = e / TK, c = e % TK;
             const int gi = i0 + r, gk = k0 + c;
-            As[r][c] = (gi < g.M && gk < g.K) ? g.a[gi * g.a_rs + gk * g.a_cs] : make_double2(0.0, 0.0);
+            As[r][c] = (gi < g.M && gk < g.K) ? gload2(g.a + gi * g.a_rs + gk * g.a_cs) : make_double2(0.0, 0.0);
         }
         for (int e = threadIdx.x; e < TK * TN; e += kThreads) {
             const int r = e / TN, c = e % TN;
             const int gk = k0 + r, gj = j0 + c;
-            Bs[r][c] = (gk < g.K && gj < g.N) ? g.b[gk * g.b_rs + gj * g.b_cs] : make_double2(0.0, 0.0);
+            Bs[r][c] = (gk < g.K && gj < g.N) ? gload2(g.b + gk * g.b_rs + gj * g.b_cs) : make_double2(0.0, 0.0);
         }
         __syncthreads();
 #pragma unroll 4
@@ -846,8 +870,8 @@ k_gemm(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, i
             if (gj >= g.N) continue;
             double2* cp = g.c + gi * g.c_rs + gj * g.c_cs;
             double2 r = cmul(g.alpha, acc[a][b]);
-            if (g.beta.x != 0.0 || g.beta.y != 0.0) r = cfma(g.beta, *cp, r);
-            *cp = r;
+            if (g.beta.x != 0.0 || g.beta.y != 0.0) r = cfma(g.beta, gload2(cp), r);
+            gstore2(cp, r);
         }
     }
 }
@@ -860,7 +884,7 @@ k_copy_blocks(const CopyJob* __restrict__ jobs) {
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * kThreads) {
         const int i = static_cast<int>(e / c.cols), j = static_cast<int>(e % c.cols);
-        c.dst[i * c.dst_rs + j * c.dst_cs] = c.src[i * c.src_rs + j * c.src_cs];
+        gstore2(c.dst + i * c.dst_rs + j * c.dst_cs, gload2(c.src + i * c.src_rs + j * c.src_cs));
     }
 }
 
