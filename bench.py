@@ -43,10 +43,7 @@ FLOP_PER_PAIR = 400.3
 # the same for the generate-and-reduce kernel (entries times x, block sums)
 FLOP_PER_PAIR_MATVEC = 456.3
 MEASURED_TRAFFIC = {
-    # two HSS builds (the timed one and the solve-timing one): 1614 launches of
-    # k_cpqr_step_reg<8> and <16>
-    "k_cpqr_step_reg": (2.0 * 19314652.2 + 34297126.3) * 1024 / 1614,
-    "k_dense": (2.0 * 5041.7 + 16777715.3) * 1024,                # one sweep: one launch
+    # filled from the counter runs of the current kernels (see the comment above)
 }
 
 
@@ -386,7 +383,8 @@ def run_hss(args):
 
     def step():
         h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio,
-                            proxy_points=wl.proxy_points, id_tol=wl.id_tol, sketch=args.sketch)
+                            proxy_points=wl.proxy_points, id_tol=wl.id_tol, sketch=args.sketch,
+                            max_rank_ratio=args.max_rank_ratio)
         bm.bm_rhs_plane_wave(p, wl.theta_inc, out=b)
         bm.bm_hss_solve(h, b, out=x)
         st = bm.bm_hss_stats(h)
@@ -416,7 +414,7 @@ def run_hss(args):
     # the solve alone: eager (descriptors staged per call, synchronises) and
     # replayed from the HIP graph captured on its first call
     h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points,
-                        id_tol=wl.id_tol, sketch=args.sketch)
+                        id_tol=wl.id_tol, sketch=args.sketch, max_rank_ratio=args.max_rank_ratio)
     bm.bm_hss_solve_graph(h, b, out=x)
     solve_ms = {}
     for name, fn in (("eager", lambda: bm.bm_hss_solve(h, b, out=x)),
@@ -438,7 +436,8 @@ def run_hss(args):
     cq_s = avg("seconds_cpqr")
     cq_bytes = st["cpqr_bytes"]
     cq_gbs = cq_bytes / cq_s / 1e9
-    traffic = MEASURED_TRAFFIC.get("k_cpqr_step_reg") if args.sketch == 0 else None
+    sk, ratio = st["sketch"], st["max_rank_ratio"]
+    traffic = MEASURED_TRAFFIC.get(("k_cpqr_step_reg", sk, ratio))
     out = {
         "metric": "Gentries/s Burton-Miller blocks (frac FP64 peak); HSS build+solve s at N=16384",
         "value": entries / (ms * 1e-3) / 1e9,
@@ -450,7 +449,8 @@ def run_hss(args):
         "config": {"workload": f"HSS build+solve, {wl.name}", "n_nodes": wl.n, "leaf": wl.leaf,
                    "proxy_points": wl.proxy_points, "proxy_ratio": wl.proxy_ratio,
                    "id_tol": wl.id_tol, "theta_inc": wl.theta_inc,
-                   "id": "cpqr" if args.sketch == 0 else f"gaussian sketch, unknowns+{args.sketch} rows"},
+                   "id": "cpqr" if sk == 0 else f"gaussian sketch, unknowns+{sk} rows",
+                   "max_rank_ratio": ratio},
         "hss_build_solve_s": ms * 1e-3,
         "hss": {"entries": entries, "pairs": st["pairs"], "levels": st["levels"],
                 "compressed_levels": st["compressed_levels"], "root_size": st["root_size"],
@@ -576,18 +576,26 @@ def main():
     ap.add_argument("--mode", choices=["hss", "dense", "matvec", "batch", "adjoint", "large"], default="hss")
     ap.add_argument("--id-tol", type=float, default=1e-12, help="adjoint mode: HSS ID tolerance")
     ap.add_argument("--per-curve", type=int, default=16384, help="large mode: nodes per star")
-    ap.add_argument("--max-rank-ratio", type=float, default=0.0,
-                    help="HSS: a body stops compressing once a level keeps more than this fraction of its unknowns")
+    ap.add_argument("--max-rank-ratio", type=float, default=None,
+                    help="HSS: a body stops compressing once a level keeps more than this fraction of its "
+                         "unknowns (0: never; -1: the library's tuned value; default: -1 in hss mode, "
+                         "0.8 in large mode, 0 otherwise)")
     ap.add_argument("--batch", type=int, default=256, help="batch mode: number of stars")
     ap.add_argument("--proxy-adapt", type=int, choices=[0, 1], default=1,
                     help="batch mode: proxy points per circle max(64, ceil(2 k R_p) + 32)")
-    ap.add_argument("--sketch", type=int, default=0,
-                    help="HSS: p > 0 runs the ID on a Gaussian sketch with unknowns + p rows")
+    ap.add_argument("--sketch", type=int, default=None,
+                    help="HSS: p > 0 runs the ID on a Gaussian sketch with unknowns + p rows (0: plain "
+                         "CPQR; -1: the library's tuned value; default: -1 in hss mode, 128 in large "
+                         "mode, 0 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device once (a plain copy "
                          "kernel of known size, to scale HBM traffic counters)")
     args = ap.parse_args()
+    if args.max_rank_ratio is None:
+        args.max_rank_ratio = {"hss": -1.0, "large": 0.8}.get(args.mode, 0.0)
+    if args.sketch is None:
+        args.sketch = {"hss": -1, "large": 128}.get(args.mode, 0)
     if args.gpus != 1:
         print("this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         return 2

@@ -148,7 +148,8 @@ typedef struct {
     double id_tol;         /* relative ID tolerance (0 < tol < 1) */
     int64_t sketch;        /* 0: CPQR of each box's stacked near/proxy matrix;
                               p > 0: CPQR of a Gaussian sketch of it with
-                              min(rows, unknowns + p) rows (randomized ID) */
+                              min(rows, unknowns + p) rows (randomized ID);
+                              -1: the library's tuned value */
     int64_t proxy_adapt;   /* 0: proxy_points on every proxy circle; 1: per box
                               max(proxy_points, ceil(2 k R_p) + 32), k the larger
                               wavenumber of the box's body, R_p the proxy radius */
@@ -157,7 +158,8 @@ typedef struct {
                               (its current boxes' skeletons become its dense root)
                               once a level's skeletons keep more than r of its
                               unknowns -- at high frequency the ranks grow with the
-                              box size and compressing further does not pay */
+                              box size and compressing further does not pay;
+                              -1: the library's tuned value */
 } bm_hss_opts;
 
 typedef struct {
@@ -180,6 +182,9 @@ typedef struct {
     int64_t cpqr_launches;
     double cpqr_bytes;
     double seconds_cpqr;
+    /* the sketch and max_rank_ratio the build used (tuned values resolved) */
+    int64_t sketch;
+    double max_rank_ratio;
 } bm_hss_stats_t;
 
 /* Build the factorisation; synchronises `stream` once per level to read the

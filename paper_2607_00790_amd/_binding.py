@@ -37,7 +37,8 @@ class _HssStats(ctypes.Structure):
                 ("max_rank", c_i64), ("entries", c_i64), ("pairs", c_i64),
                 ("seconds_generate", c_dbl), ("seconds_compress", c_dbl),
                 ("seconds_factor", c_dbl), ("seconds_total", c_dbl),
-                ("cpqr_launches", c_i64), ("cpqr_bytes", c_dbl), ("seconds_cpqr", c_dbl)]
+                ("cpqr_launches", c_i64), ("cpqr_bytes", c_dbl), ("seconds_cpqr", c_dbl),
+                ("sketch", c_i64), ("max_rank_ratio", c_dbl)]
 
 
 class _HssLevel(ctypes.Structure):
@@ -302,7 +303,9 @@ def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1
     matrix with (unknowns + p) rows, when that is fewer than the matrix has.
     proxy_adapt: max(proxy_points, ceil(2 k R_p) + 32) points per proxy circle.
     max_rank_ratio = r > 0: a body stops compressing once a level keeps more
-    than r of its unknowns (its skeletons then form its dense root)."""
+    than r of its unknowns (its skeletons then form its dense root).
+    sketch = -1 or max_rank_ratio = -1: the library's tuned value (the build's
+    stats report the values used)."""
     opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol), int(sketch),
                     int(bool(proxy_adapt)), float(max_rank_ratio))
     out = c_vp()

@@ -1810,10 +1810,10 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
     if (!p || !opts) return fail(BM_EINVAL, "bm_hss_build: null argument");
     if (opts->leaf < 4 || !(opts->proxy_ratio > 1.0) || opts->proxy_points < 8 ||
         !(opts->id_tol > 0.0 && opts->id_tol < 1.0) || !std::isfinite(opts->proxy_ratio) ||
-        opts->sketch < 0 || opts->sketch > (int64_t{1} << 20) ||
-        !(opts->max_rank_ratio >= 0.0 && opts->max_rank_ratio <= 1.0))
+        opts->sketch < -1 || opts->sketch > (int64_t{1} << 20) ||
+        !(opts->max_rank_ratio == -1.0 || (opts->max_rank_ratio >= 0.0 && opts->max_rank_ratio <= 1.0)))
         return fail(BM_EINVAL, "bm_hss_build: need leaf >= 4, proxy_ratio > 1, proxy_points >= 8, "
-                               "0 < id_tol < 1, 0 <= sketch <= 2^20, 0 <= max_rank_ratio <= 1");
+                               "0 < id_tol < 1, sketch -1 or 0..2^20, max_rank_ratio -1 or in [0, 1]");
     if (p->g->n > (int64_t{1} << 30)) return fail(BM_EINVAL, "bm_hss_build: N too large");
     const auto t0 = std::chrono::steady_clock::now();
     bm_hss* h = new (std::nothrow) bm_hss;
@@ -1821,6 +1821,8 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
     h->p = p;
     h->stream = stream;
     h->opts = *opts;
+    if (h->opts.sketch == -1) h->opts.sketch = tuned::kSketchRows;
+    if (h->opts.max_rank_ratio == -1.0) h->opts.max_rank_ratio = tuned::kStopRankRatio;
     h->N = p->g->n;
     int rc;
     try {
@@ -1907,6 +1909,8 @@ int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out) {
     clear_error();
     if (!h || !out) return fail(BM_EINVAL, "bm_hss_stats: null argument");
     *out = h->stats;
+    out->sketch = h->opts.sketch;
+    out->max_rank_ratio = h->opts.max_rank_ratio;
     return BM_OK;
 }
 

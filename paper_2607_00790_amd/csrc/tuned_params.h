@@ -21,6 +21,10 @@ namespace tuned {
 constexpr int kInvBase = 64;
 // Products of at least this many real flops go to rocBLAS ZGEMM.
 constexpr double kBlasFlops = 1e+08;
+// HSS build options selected by bm_hss_opts value -1 (sketch rows beyond the
+// unknowns; level rank ratio above which a body stops compressing).
+constexpr long kSketchRows = 8;
+constexpr double kStopRankRatio = 0.6;
 
 }  // namespace tuned
 }  // namespace bm

@@ -127,14 +127,31 @@ def test_autotuner_writes_the_fastest_candidate(tmp_path, monkeypatch):
     import importlib
     at = importlib.import_module("paper_2607_00790_amd.autotune")
     times = {(64, 1e8): 25.0}
-    monkeypatch.setattr(at, "measure", lambda b, f, steps: times.get((b, f), 26.0 + b / 1000 + f / 1e10))
+    seen = set()
+
+    def fake_measure(b, f, steps, sketch, ratio):
+        seen.add((sketch, ratio))
+        return times.get((b, f), 26.0 + b / 1000 + f / 1e10)
+
+    # stage 1: (median ms, sketch, ratio, residual, root); the fastest pair (sketch 32,
+    # ratio 0.5) has a residual above plain CPQR's and must not be chosen
+    stage1 = [(30.0, 0, 0.0, 2e-7, 900), (20.0, 8, 0.6, 1e-8, 1500), (18.0, 32, 0.5, 5e-7, 7000),
+              (22.0, 0, 0.6, 7e-9, 1550)]
+    monkeypatch.setattr(at, "stage1", lambda builds: stage1)
+    monkeypatch.setattr(at, "measure", fake_measure)
     out = tmp_path / "tuned.h"
     monkeypatch.setattr("sys.argv", ["autotune", "--out", str(out), "--repeats", "1"])
     assert at.main() == 0
     text = out.read_text()
     assert "constexpr int kInvBase = 64;" in text
     assert "constexpr double kBlasFlops = 1e+08;" in text
-    assert text.count("median") == 9 + 1     # one line per candidate, plus the description
+    assert "constexpr long kSketchRows = 8;" in text
+    assert "constexpr double kStopRankRatio = 0.6;" in text
+    assert seen == {(8, 0.6)}                 # stage 2 runs with the chosen options
+    assert "(residual above plain CPQR: excluded)" in text
+    assert text.count("median") == 9 + 4 + 2     # one line per candidate, plus the descriptions
     # the committed header parses the same way
     committed = open(os.path.join(ROOT, "paper_2607_00790_amd", "csrc", "tuned_params.h")).read()
     assert re.search(r"constexpr int kInvBase = (32|64|128);", committed)
+    assert re.search(r"constexpr long kSketchRows = \d+;", committed)
+    assert re.search(r"constexpr double kStopRankRatio = (0|0?\.\d+|1)(\.\d*)?;", committed)

@@ -108,19 +108,27 @@ def test_hss_tiny_problem_is_a_dense_solve(gpu_lib):
     assert rel(x, ref) < 1e-12
 
 
-@pytest.mark.parametrize("sketch", SKETCH)
-def test_hss_full_size_star_sampled_residual(gpu_lib, sketch):
+@pytest.mark.parametrize("sketch,ratio", [pytest.param(0, 0.0, id="cpqr"), pytest.param(128, 0.0, id="sketch128"),
+                                           pytest.param(-1, -1.0, id="tuned")])
+def test_hss_full_size_star_sampled_residual(gpu_lib, sketch, ratio):
     """Full star workload (N = 16384, k0 = 50, n = 1.5, leaf 64, 64 proxy points,
     tol 1e-10), the configuration the benchmark times: the residual of the HSS
-    solution on sampled rows of the oracle's matrix, and the per-level sizes."""
+    solution on sampled rows of the oracle's matrix, and the per-level sizes.
+    "tuned" takes the library's tuned sketch and stop ratio (value -1), the
+    benchmark's default."""
     bm = gpu_lib
-    note(f"hss: star N=16384 (benchmark workload), sampled residual, sketch={sketch}")
+    note(f"hss: star N=16384 (benchmark workload), sampled residual, sketch={sketch}, ratio={ratio}")
     wl = sc.star_workload()
     p, nd = setup(bm, wl.curves, wl.sizes, wl.media)
     h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points,
-                        id_tol=wl.id_tol, sketch=sketch)
+                        id_tol=wl.id_tol, sketch=sketch, max_rank_ratio=ratio)
     st = bm.bm_hss_stats(h)
     note(f"  stats {st}")
+    if sketch == -1:
+        assert st["sketch"] >= 0 and 0.0 <= st["max_rank_ratio"] <= 1.0
+        sketch = st["sketch"]
+    else:
+        assert st["sketch"] == sketch and st["max_rank_ratio"] == ratio
     for l in range(st["compressed_levels"]):
         lv = bm.bm_hss_level(h, l)
         note(f"  level {l}: {lv}")
@@ -235,8 +243,8 @@ def test_hss_rejects_bad_options(gpu_lib):
         with pytest.raises(bm.BmError):
             bm.bm_hss_build(p, **kw)
     with pytest.raises(bm.BmError):
-        bm.bm_hss_build(p, sketch=-1)
-    for r in (-0.1, 1.5, float("nan")):
+        bm.bm_hss_build(p, sketch=-2)
+    for r in (-0.1, -2.0, 1.5, float("nan")):
         with pytest.raises(bm.BmError):
             bm.bm_hss_build(p, max_rank_ratio=r)
     # the same through the C-ABI directly: nothing is built
