@@ -280,6 +280,8 @@ hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const 
 }
 
 hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs);
+hipError_t launch_gemv_group(Scratch& sc, const std::vector<GemmJob>& jobs);
+int64_t gemv_tiles(const GemmJob& j);
 
 // rocBLAS handle of the current device, for the large products.
 hipError_t blas_handle(rocblas_handle* out) {
@@ -377,9 +379,40 @@ hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
             return r == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
         });
     }
+    // products with few columns (the solves) go to the matrix-vector kernel
+    std::vector<GemmJob> tiled, narrow;
+    for (const GemmJob& g : small)
+        (g.N <= kGemvMaxN && (g.a_cs == 1 || g.a_rs == 1) ? narrow : tiled).push_back(g);
+    hipError_t e = launch_in_groups(
+        narrow, gemv_tiles, [&](const std::vector<GemmJob>& g) { return launch_gemv_group(sc, g); });
+    if (e != hipSuccess) return e;
     return launch_in_groups(
-        small, [](const GemmJob& j) { return ceil_div(j.M, 32) * ceil_div(j.N, 32); },
+        tiled, [](const GemmJob& j) { return ceil_div(j.M, 32) * ceil_div(j.N, 32); },
         [&](const std::vector<GemmJob>& g) { return launch_gemm_group(sc, g); });
+}
+
+int64_t gemv_tiles(const GemmJob& j) {
+    return j.a_cs == 1 ? ceil_div(j.M, kGemvRows) : ceil_div(j.M, kThreads);
+}
+
+hipError_t launch_gemv_group(Scratch& sc, const std::vector<GemmJob>& jobs) {
+    if (jobs.empty()) return hipSuccess;
+    std::vector<int64_t> toff(jobs.size() + 1, 0);
+    for (size_t j = 0; j < jobs.size(); ++j) toff[j + 1] = toff[j] + gemv_tiles(jobs[j]);
+    if (toff.back() == 0) return hipSuccess;
+    GemmJob* dj;
+    int64_t* dt;
+    hipError_t e = sc.upload(&dj, jobs);
+    if (e == hipSuccess) e = sc.upload(&dt, toff);
+    if (e != hipSuccess) return e;
+    const unsigned grid = static_cast<unsigned>(toff.back());
+    const int nj = static_cast<int>(jobs.size());
+    hipStream_t st = sc.s;
+    sc.rec([=]() {
+        hipLaunchKernelGGL(k_gemv, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj);
+        return hipGetLastError();
+    });
+    return hipSuccess;
 }
 
 hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs) {

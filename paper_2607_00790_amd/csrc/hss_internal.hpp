@@ -131,6 +131,11 @@ __global__ void k_cpqr_finish(const CpqrJob* jobs);
 __global__ void k_cpqr_ranks(const CpqrJob* jobs, int nb, int32_t* ranks, int32_t* active);
 
 __global__ void k_gemm(const GemmJob* jobs, const int64_t* tile_off, int njobs);
+// products with at most kGemvMaxN columns whose A has unit row or column stride;
+// a tile is kGemvRows rows (wave per row when a_cs == 1) or kThreads rows
+constexpr int kGemvMaxN = 4;
+constexpr int kGemvRows = kThreads / 64;
+__global__ void k_gemv(const GemmJob* jobs, const int64_t* tile_off, int njobs);
 // 64 x 64 tiles of Y per workgroup (kThreads threads)
 __global__ void k_sketch(const SketchJob* jobs, const int64_t* tile_off, int njobs,
                          const double* omega, int64_t ldo);

@@ -876,6 +876,66 @@ k_gemm(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, i
     }
 }
 
+// Batched strided complex products with few columns (N <= kGemvMaxN, the
+// solves): C = alpha A B + beta C.  With A's rows contiguous (a_cs == 1) one
+// wave computes one row of C: its lanes stride along the row and the partial
+// sums meet in a butterfly; with A's columns contiguous (a_rs == 1) one thread
+// computes one row, so that the lanes read consecutive elements of a column.
+// A tile is kGemvRows rows of one job.
+__global__ void __launch_bounds__(kThreads)
+k_gemv(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
+    int lo = 0, hi = njobs;
+    const int64_t tile = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= tile) lo = mid; else hi = mid;
+    }
+    const GemmJob g = jobs[lo];
+    const int64_t local = tile - tile_off[lo];
+    double2 acc[kGemvMaxN];
+#pragma unroll
+    for (int j = 0; j < kGemvMaxN; ++j) acc[j] = make_double2(0.0, 0.0);
+    int64_t i;
+    bool owner;
+    if (g.a_cs == 1) {
+        const int lane = threadIdx.x & 63;
+        i = local * kGemvRows + (threadIdx.x >> 6);
+        if (i >= g.M) return;   // the whole wave: no workgroup barrier follows
+        const double2* a = g.a + i * g.a_rs;
+        for (int k = lane; k < g.K; k += 64) {
+            const double2 av = gload2(a + k);
+#pragma unroll
+            for (int j = 0; j < kGemvMaxN; ++j)
+                if (j < g.N) acc[j] = cfma(av, gload2(g.b + k * g.b_rs + j * g.b_cs), acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kGemvMaxN; ++j) {
+            acc[j].x = wave_sum(acc[j].x);
+            acc[j].y = wave_sum(acc[j].y);
+        }
+        owner = lane == 0;
+    } else {
+        i = local * kThreads + threadIdx.x;
+        if (i >= g.M) return;
+        for (int k = 0; k < g.K; ++k) {
+            const double2 av = gload2(g.a + i + k * g.a_cs);
+#pragma unroll
+            for (int j = 0; j < kGemvMaxN; ++j)
+                if (j < g.N) acc[j] = cfma(av, gload2(g.b + k * g.b_rs + j * g.b_cs), acc[j]);
+        }
+        owner = true;
+    }
+    if (!owner) return;
+#pragma unroll
+    for (int j = 0; j < kGemvMaxN; ++j) {
+        if (j >= g.N) break;
+        double2* cp = g.c + i * g.c_rs + j * g.c_cs;
+        double2 r = cmul(g.alpha, acc[j]);
+        if (g.beta.x != 0.0 || g.beta.y != 0.0) r = cfma(g.beta, gload2(cp), r);
+        gstore2(cp, r);
+    }
+}
+
 // Strided complex block copy: dst(i, j) = src(i, j) for i < rows, j < cols.
 __global__ void __launch_bounds__(kThreads)
 k_copy_blocks(const CopyJob* __restrict__ jobs) {
