@@ -39,11 +39,15 @@ BYTES_PER_PAIR = 64             # 4 complex128 entries written per (target, sour
 # the kernels and workloads those counters were taken on.
 # FP64 operations per pair of the entry kernel, from rocprofv3 --pmc
 # SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 over the dense sweep (FMA counted as 2)
-FLOP_PER_PAIR = 400.3
+FLOP_PER_PAIR = 313.9
 # the same for the generate-and-reduce kernel (entries times x, block sums)
-FLOP_PER_PAIR_MATVEC = 456.3
+FLOP_PER_PAIR_MATVEC = 349.9
 MEASURED_TRAFFIC = {
-    # filled from the counter runs of the current kernels (see the comment above)
+    # one sweep: one launch
+    "k_dense": (2.0 * 48835.4 + 16861700.0) * 1024,
+    # two HSS builds of the default options (gaussian sketch, unknowns + 16 rows; stop
+    # ratio 0.65): 824 launches of k_cpqr_step_reg<4>
+    ("k_cpqr_step_reg", 16, 0.65): (2.0 * 5499230.0 + 8999600.0) * 1024 / 824,
 }
 
 

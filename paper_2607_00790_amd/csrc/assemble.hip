@@ -63,15 +63,15 @@ __device__ __forceinline__ void emit_pair(double* __restrict__ out, int64_t ld, 
                                           int64_t col, double tx, double ty, double tnx, double tny,
                                           double sx, double sy, double snx, double sny, double sw,
                                           const Media& m, bool interior) {
-    double2* r0 = reinterpret_cast<double2*>(out) + (2 * row) * ld + 2 * col;
-    double2* r1 = r0 + ld;
     const PairGeom g = pair_geom(tx, ty, tnx, tny, sx, sy, snx, sny);
-    const KernelParts p1 = pair_interior(g, m, interior);
+    const Hankel01 h1 = pair_interior(g, m, interior);
     double o[4];
-    pair_row0(p1, sw, m, o);
+    pair_row0(g, h1, sw, m, o);
+    double2* r0 = reinterpret_cast<double2*>(out) + (2 * row) * ld + 2 * col;
     r0[0] = make_double2(o[0], o[1]);
     r0[1] = make_double2(o[2], o[3]);
-    pair_row1(g, p1, sw, m, interior, o);
+    pair_row1(g, interior_terms(h1, m), sw, m, o);
+    double2* r1 = reinterpret_cast<double2*>(out) + (2 * row + 1) * ld + 2 * col;
     r1[0] = make_double2(o[0], o[1]);
     r1[1] = make_double2(o[2], o[3]);
 }
@@ -207,9 +207,14 @@ k_rhs_plane_wave(NodeView v, int64_t n, const Media* __restrict__ media, double 
     rhs[2 * i + 1] = make_double2(f * c, f * s);
 }
 
-// y = A x, stage 1: workgroup b covers target i = b / ntj and one source tile;
-// it writes the tile's partial sums of rows 2i, 2i+1 to part[b] (4 doubles).
-__global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
+// y = A x, stage 1: workgroup b covers target i = b / ntj and one tile of
+// kMvSources * kThreads sources (each thread takes kMvSources of them, kThreads
+// apart, so that the block reduction is paid once per kMvSources pairs); it
+// writes the tile's partial sums of rows 2i, 2i+1 to part[b] (4 doubles).
+constexpr int kMvSources = 8;
+constexpr int kMvWavesPerSimd = 4;
+
+__global__ void __launch_bounds__(kThreads, kMvWavesPerSimd)
 k_matvec_partial(NodeView v, const int64_t* __restrict__ body_lo, int64_t ntj, int64_t i0,
                  const Media* __restrict__ media, const double2* __restrict__ x,
                  double4* __restrict__ part, const BesselTable* __restrict__ tab) {
@@ -217,23 +222,28 @@ k_matvec_partial(NodeView v, const int64_t* __restrict__ body_lo, int64_t ntj, i
     // the launch covers targets i0, i0 + 1, ...
     const int64_t i = i0 + blockIdx.x / ntj;
     const int bi = body_of(v, i);
-    const int64_t j = body_lo[bi] + (blockIdx.x % ntj) * kThreads + threadIdx.x;
+    const int64_t jend = body_lo[bi + 1];
+    const int64_t j0 = body_lo[bi] + (blockIdx.x % ntj) * (kThreads * kMvSources) + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const Media m = with_table(media[bi], tab);
-    if (j < body_lo[bi + 1]) {
+    const double tx = v.x[i], ty = v.y[i], tnx = v.nx[i], tny = v.ny[i];
+    const int32_t ci = v.curve[i];
+#pragma unroll 1
+    for (int q = 0; q < kMvSources; ++q) {
+        const int64_t j = j0 + q * kThreads;
+        if (j >= jend) break;
         Block b;
         if (i == j) {
             b = diag_block(v.w[j], v.kappa[j], m);
         } else {
-            b = pair_block(v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j],
-                           v.w[j], m, v.curve[i] == v.curve[j]);
+            b = pair_block(tx, ty, tnx, tny, v.x[j], v.y[j], v.nx[j], v.ny[j], v.w[j], m, ci == v.curve[j]);
         }
         const double2 xu = x[2 * j], xq = x[2 * j + 1];
         // row 2i: A00 xu + A01 xq ; row 2i+1: A10 xu + A11 xq
-        acc[0] = b.v[0] * xu.x - b.v[1] * xu.y + b.v[2] * xq.x - b.v[3] * xq.y;
-        acc[1] = b.v[0] * xu.y + b.v[1] * xu.x + b.v[2] * xq.y + b.v[3] * xq.x;
-        acc[2] = b.v[4] * xu.x - b.v[5] * xu.y + b.v[6] * xq.x - b.v[7] * xq.y;
-        acc[3] = b.v[4] * xu.y + b.v[5] * xu.x + b.v[6] * xq.y + b.v[7] * xq.x;
+        acc[0] += b.v[0] * xu.x - b.v[1] * xu.y + b.v[2] * xq.x - b.v[3] * xq.y;
+        acc[1] += b.v[0] * xu.y + b.v[1] * xu.x + b.v[2] * xq.y + b.v[3] * xq.x;
+        acc[2] += b.v[4] * xu.x - b.v[5] * xu.y + b.v[6] * xq.x - b.v[7] * xq.y;
+        acc[3] += b.v[4] * xu.y + b.v[5] * xu.x + b.v[6] * xq.y + b.v[7] * xq.x;
     }
     block_sum<4>(acc);
     if (threadIdx.x == 0) part[i * ntj + blockIdx.x % ntj] = make_double4(acc[0], acc[1], acc[2], acc[3]);
@@ -337,7 +347,7 @@ hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* m, d
 hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const int64_t* body_lo,
                          const Media* m, const BesselTable* tab, const double* x, double* y, double* work,
                          hipStream_t s) {
-    const int64_t ntj = (max_body + kThreads - 1) / kThreads;
+    const int64_t ntj = (max_body + kThreads * kMvSources - 1) / (kThreads * kMvSources);
     double4* part = reinterpret_cast<double4*>(work);
     // at most 2^24 - 1 workgroups (2^32 - 1 work-items) per launch
     const int64_t chunk = std::max<int64_t>(1, (int64_t{0xFFFFFFFF} / kThreads) / ntj);
@@ -355,7 +365,7 @@ hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const i
 }
 
 int64_t matvec_work_doubles(int64_t n, int64_t max_body) {
-    return 4 * n * ((max_body + kThreads - 1) / kThreads);
+    return 4 * n * ((max_body + kThreads * kMvSources - 1) / (kThreads * kMvSources));
 }
 
 hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* m,

@@ -16,12 +16,13 @@ Region B, ZA <= z < ZC (piecewise local polynomials).
   [ZA, ZC) is cut into intervals of width HB; on each, J0, Y0, J1 and Y1r are
   least-squares polynomials in s = z - centre.
 
-Region C, ZC <= z < ZD, and region D, z >= ZD (Hankel's large-argument form,
-A&S 9.2.5-9.2.10 structure).
+Regions C (ZC <= z < ZD), D (ZD <= z < ZE) and E (z >= ZE): Hankel's
+large-argument form (A&S 9.2.5-9.2.10 structure).
     H_n(z) = sqrt(2/(pi z)) (P_n(z) + i Q_n(z)) exp(i (z - (2n+1) pi/4)),  n = 0, 1
-  P_n and z Q_n are smooth in u = (Z0/z)^2 on [0, 1] (Z0 = ZC or ZD) and are
-  replaced by their least-squares polynomials in u; the second region needs a
-  much lower degree, and most node pairs of a scatterer fall in it.
+  P_n and z Q_n are smooth in u = (Z0/z)^2 on [0, 1] (Z0 = ZC, ZD or ZE) and
+  are replaced by their least-squares polynomials in u; the degree falls with
+  Z0, and most node pairs of a scatterer at the frequencies of interest fall
+  in region E.
 
 Sine and cosine for the large-argument region (Cody and Waite's argument
 reduction): x = k pi/2 + r with pi/2 split into three doubles C1 + C2 + C3,
@@ -51,7 +52,9 @@ DEG_B = 11
 DEG_C = 11
 ZD = 16.0
 DEG_D = 6
-DEG_TRIG = 7
+ZE = 32.0
+DEG_E = 4
+DEG_TRIG = 5
 
 
 def _j(n, z):
@@ -147,6 +150,8 @@ def build():
         tables["C_" + name] = to_monomial(cs, c, h, 0)
         cs, c, h = lsq_poly(lambda u, n=name: fc(n, u if u > eps else eps, ZD), mp.mpf(0), mp.mpf(1), DEG_D)
         tables["D_" + name] = to_monomial(cs, c, h, 0)
+        cs, c, h = lsq_poly(lambda u, n=name: fc(n, u if u > eps else eps, ZE), mp.mpf(0), mp.mpf(1), DEG_E)
+        tables["E_" + name] = to_monomial(cs, c, h, 0)
     # sine / cosine on |r| <= pi/4, as polynomials in w = r^2
     wmax = (mp.pi / 4) ** 2
     tiny = mp.mpf("1e-30")
@@ -208,8 +213,9 @@ def eval_f64(t, z):
     z = np.asarray(z, dtype=np.float64)
     out = np.empty((2,) + z.shape, dtype=np.complex128)
     A = z < ZA
-    D = z >= ZD
-    C = (z >= ZC) & ~D
+    E = z >= ZE
+    D = (z >= ZD) & ~E
+    C = (z >= ZC) & (z < ZD)
     B = ~A & (z < ZC)
     if A.any():
         za = z[A]
@@ -247,6 +253,14 @@ def eval_f64(t, z):
         ph = ((cz + sz) + 1j * (sz - cz)) * np.sqrt(0.5)
         out[0, D] = amp * (_horner(t["D_P0"], u) + 1j * _horner(t["D_Q0"], u) / zd) * ph
         out[1, D] = amp * (_horner(t["D_P1"], u) + 1j * _horner(t["D_Q1"], u) / zd) * ph * (-1j)
+    if E.any():
+        ze = z[E]
+        u = (ZE / ze) ** 2
+        amp = np.sqrt(2 / (np.pi * ze))
+        sz, cz = model_sincos(t, ze)
+        ph = ((cz + sz) + 1j * (sz - cz)) * np.sqrt(0.5)
+        out[0, E] = amp * (_horner(t["E_P0"], u) + 1j * _horner(t["E_Q0"], u) / ze) * ph
+        out[1, E] = amp * (_horner(t["E_P1"], u) + 1j * _horner(t["E_Q1"], u) / ze) * ph * (-1j)
     return out
 
 
@@ -255,7 +269,7 @@ def report(t):
     got = eval_f64(t, zs)
     worst = {}
     for q, z in enumerate(zs):
-        reg = "A" if z < ZA else ("B" if z < ZC else ("C" if z < ZD else "D"))
+        reg = "A" if z < ZA else ("B" if z < ZC else ("C" if z < ZD else ("D" if z < ZE else "E")))
         for n in (0, 1):
             ref = complex(mp.besselj(n, z) + 1j * mp.bessely(n, z))
             e = abs(got[n, q] - ref) / abs(ref)
@@ -268,7 +282,7 @@ def emit(t, path):
         return ",\n        ".join(mp.nstr(v, 21, min_fixed=-1, max_fixed=-1) for v in vals)
 
     names = ("A_J0", "A_J1", "A_R0", "A_R1", "C_P0", "C_Q0", "C_P1", "C_Q1", "D_P0", "D_Q0", "D_P1",
-             "D_Q1", "T_SIN", "T_COS", "T_CW")
+             "D_Q1", "E_P0", "E_Q0", "E_P1", "E_Q1", "T_SIN", "T_COS", "T_CW")
     flat = []
     for row in t["B"]:
         for f in row:
@@ -279,13 +293,16 @@ def emit(t, path):
              "namespace bm_bessel_coef {", "",
              f"constexpr double ZA = {ZA!r};   // series region: 0 < z < ZA",
              f"constexpr double ZC = {ZC!r};   // large-argument region C: ZC <= z < ZD",
-             f"constexpr double ZD = {ZD!r};  // large-argument region D: z >= ZD",
+             f"constexpr double ZD = {ZD!r};  // large-argument region D: ZD <= z < ZE",
+             f"constexpr double ZE = {ZE!r};  // large-argument region E: z >= ZE",
              f"constexpr double HB = {HB!r};   // width of the piecewise intervals in [ZA, ZC)",
              f"constexpr int NB = {len(t['B'])};        // number of intervals",
              f"constexpr int DB = {DEG_B + 1};       // coefficients per interval polynomial",
              f"constexpr int NA = {DEG_A + 1};       // coefficients of the series-region polynomials",
              f"constexpr int NC = {DEG_C + 1};       // coefficients of the region-C polynomials",
-             f"constexpr int ND = {DEG_D + 1};        // coefficients of the region-D polynomials", "",
+             f"constexpr int ND = {DEG_D + 1};        // coefficients of the region-D polynomials",
+             f"constexpr int NE = {DEG_E + 1};        // coefficients of the region-E polynomials",
+             f"constexpr int NT = {DEG_TRIG + 1};        // coefficients of the sine and cosine polynomials", "",
              "// All coefficients in one table; kernels read it through a pointer.",
              "struct Table {"]
     for name in names:

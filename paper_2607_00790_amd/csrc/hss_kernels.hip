@@ -257,14 +257,14 @@ k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off
     const double sw = pt.w[j];
     const PairGeom g = pair_geom(pt.x[i], pt.y[i], pt.nx[i], pt.ny[i], pt.x[j], pt.y[j], pt.nx[j],
                                  pt.ny[j]);
-    const KernelParts p1 = pair_interior(g, m, interior);
+    const Hankel01 h1 = pair_interior(g, m, interior);
     double v[4];
     if (ts.pos0 >= 0) {
-        pair_row0(p1, sw, m, v);
+        pair_row0(g, h1, sw, m, v);
         put(ts.pos0, v);
     }
     if (ts.pos1 >= 0) {
-        pair_row1(g, p1, sw, m, interior, v);
+        pair_row1(g, interior_terms(h1, m), sw, m, v);
         put(ts.pos1, v);
     }
 }
@@ -281,20 +281,20 @@ k_cpqr_init(const CpqrJob* __restrict__ jobs) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
     const int j = blockIdx.x * nw + wid;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        jb.st->ref = 0;
-        jb.st->beta = 0;
-        jb.st->rank = 0;
-        jb.st->done = 0;
+        gst(&jb.st->ref, 0.0);
+        gst(&jb.st->beta, 0.0);
+        gst(&jb.st->rank, 0);
+        gst(&jb.st->done, 0);
     }
     if (j >= jb.n) return;
     if (lane == 0) {
-        jb.perm[j] = j;
-        jb.used[j] = 0;
+        gst(jb.perm + j, j);
+        gst(jb.used + j, 0);
     }
     double s = 0;
     for (int r = lane; r < jb.m; r += 64) s += cabs2(gload2(jb.x + static_cast<int64_t>(j) * jb.m + r));
     s = wave_sum(s);
-    if (lane == 0) jb.nrm[j] = s;
+    if (lane == 0) gst(jb.nrm + j, s);
 }
 
 // One elimination step k of the level-batched CPQR, fused into one launch.
@@ -310,48 +310,49 @@ k_cpqr_step(const CpqrJob* __restrict__ jobs, int k, double tol) {
     __shared__ int si[kThreads / 64];
     const CpqrJob jb = jobs[blockIdx.y];
     CpqrState* st = jb.st;
-    if (st->done) return;
+    if (gld(&st->done)) return;
     const int n = jb.n, m = jb.m;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (k >= (n < m ? n : m)) {
-        if (lead) { st->rank = k; st->done = 1; }
+        if (lead) { gst(&st->rank, k); gst(&st->done, 1); }
         return;
     }
     const double* __restrict__ nin = jb.nrm + (k & 1) * n;
     double* __restrict__ nout = jb.nrm + ((k + 1) & 1) * n;
-    const int prev = k > 0 ? jb.perm[k - 1] : -1;
+    const int prev = k > 0 ? gld(jb.perm + k - 1) : -1;
     double bv = -1;
     int bi = n;
     for (int j = threadIdx.x; j < n; j += kThreads)
-        if (!jb.used[j] && j != prev && nin[j] > bv) { bv = nin[j]; bi = j; }
+        if (!gld(jb.used + j) && j != prev && gld(nin + j) > bv) { bv = gld(nin + j); bi = j; }
     block_argmax(bv, bi, sv, si);
-    const double ref = k == 0 ? sqrt(bv) : st->ref;
+    const double ref = k == 0 ? sqrt(bv) : gld(&st->ref);
     if (!(sqrt(bv) > tol * ref) || ref == 0 || bi >= n) {
-        if (lead) { st->rank = k; st->done = 1; }
+        if (lead) { gst(&st->rank, k); gst(&st->done, 1); }
         return;
     }
     const int p = bi;
     const double2* __restrict__ w = jb.x + static_cast<int64_t>(p) * m;   // rows >= k
-    const double xn = sqrt(nin[p]);
-    const double2 x0 = w[k];
+    const double xn = sqrt(gld(nin + p));
+    const double2 x0 = gload2(w + k);
     const double a0 = sqrt(cabs2(x0));
     const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
     const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
     const double2 w0 = make_double2(x0.x - alpha.x, x0.y - alpha.y);   // first entry of w
     const double beta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
     if (lead) {
-        jb.perm[k] = p;
-        jb.rdiag[k] = alpha;
-        if (prev >= 0) jb.used[prev] = 1;
-        if (k == 0) st->ref = ref;
+        gst(jb.perm + k, p);
+        gstore2(jb.rdiag + k, alpha);
+        if (prev >= 0) gst(jb.used + prev, 1);
+        if (k == 0) gst(&st->ref, ref);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
     const int j = blockIdx.x * nw + wid;
-    if (j >= n || j == p || j == prev || jb.used[j]) return;
+    if (j >= n || j == p || j == prev || gld(jb.used + j)) return;
     double2* __restrict__ cj = jb.x + static_cast<int64_t>(j) * m;
     double gr = 0, gi = 0;
     for (int r = k + lane; r < m; r += 64) {
-        const double2 t = cconj_mul(r == k ? w0 : w[r], cj[r]);
+        const double2 wr = r == k ? w0 : gload2(w + r);
+        const double2 t = cconj_mul(wr, gload2(cj + r));
         gr += t.x;
         gi += t.y;
     }
@@ -359,15 +360,15 @@ k_cpqr_step(const CpqrJob* __restrict__ jobs, int k, double tol) {
     gi = wave_sum(gi) * beta;
     double s = 0;
     for (int r = k + lane; r < m; r += 64) {
-        const double2 wr = r == k ? w0 : w[r];
-        double2 y = cj[r];
+        const double2 wr = r == k ? w0 : gload2(w + r);
+        double2 y = gload2(cj + r);
         y.x -= gr * wr.x - gi * wr.y;
         y.y -= gr * wr.y + gi * wr.x;
-        cj[r] = y;
+        gstore2(cj + r, y);
         if (r > k) s += cabs2(y);
     }
     s = wave_sum(s);
-    if (lane == 0) nout[j] = s;
+    if (lane == 0) gst(nout + j, s);
 }
 
 // The same elimination step for matrices of at most 64 R rows: the block
@@ -480,13 +481,13 @@ k_cpqr_finish(const CpqrJob* __restrict__ jobs) {
     __shared__ int scan[kThreads];
     __shared__ int base;
     const CpqrJob jb = jobs[blockIdx.x];
-    const int n = jb.n, r = jb.st->rank;
+    const int n = jb.n, r = gld(&jb.st->rank);
     if (threadIdx.x == 0) base = r;
-    for (int i = threadIdx.x; i < r; i += kThreads) jb.used[jb.perm[i]] = 1;
+    for (int i = threadIdx.x; i < r; i += kThreads) gst(jb.used + gld(jb.perm + i), 1);
     __syncthreads();
     for (int j0 = 0; j0 < n; j0 += kThreads) {
         const int j = j0 + threadIdx.x;
-        const int f = (j < n && !jb.used[j]) ? 1 : 0;
+        const int f = (j < n && !gld(jb.used + j)) ? 1 : 0;
         scan[threadIdx.x] = f;
         __syncthreads();
         for (int off = 1; off < kThreads; off <<= 1) {
@@ -495,7 +496,7 @@ k_cpqr_finish(const CpqrJob* __restrict__ jobs) {
             scan[threadIdx.x] += v;
             __syncthreads();
         }
-        if (f) jb.perm[base + scan[threadIdx.x] - 1] = j;
+        if (f) gst(jb.perm + base + scan[threadIdx.x] - 1, j);
         __syncthreads();
         if (threadIdx.x == kThreads - 1) base += scan[kThreads - 1];
         __syncthreads();
@@ -507,8 +508,8 @@ __global__ void k_cpqr_ranks(const CpqrJob* __restrict__ jobs, int nb, int32_t* 
                              int32_t* __restrict__ active) {
     int cnt = 0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        ranks[b] = jobs[b].st->rank;
-        cnt += jobs[b].st->done ? 0 : 1;
+        ranks[b] = gld(&jobs[b].st->rank);
+        cnt += gld(&jobs[b].st->done) ? 0 : 1;
     }
     cnt = static_cast<int>(wave_sum(static_cast<double>(cnt)));
     if (threadIdx.x == 0) *active = cnt;

@@ -40,52 +40,18 @@ constexpr int kPairWavesPerSimd = 6;
 struct Media {
     double k0, k1, eps0, eps1;
     double ik0, ik1;              // 1/k0, 1/k1
+    double q10, q10k1, e1q10;     // k1/k0, k1^2/k0, eps1 k1/k0
     const BesselTable* tab;       // Bessel / sine-cosine coefficients (device memory in kernels)
 };
 
 inline Media make_media(double k0, double k1, double eps0, double eps1, const BesselTable* tab) {
-    return Media{k0, k1, eps0, eps1, 1.0 / k0, 1.0 / k1, tab};
+    return Media{k0, k1, eps0, eps1, 1.0 / k0, 1.0 / k1, k1 / k0, k1 * k1 / k0, eps1 * k1 / k0, tab};
 }
 
 // Output: blk[0..7] = re/im of A(2i,2j), A(2i,2j+1), A(2i+1,2j), A(2i+1,2j+1).
 struct Block {
     double v[8];
 };
-
-// Per-wavenumber pieces of the kernels (divided by w_j).
-struct KernelParts {
-    double s_re, s_im;     // S_k
-    double d_re, d_im;     // D_k
-    double ds_re, ds_im;   // D*_k
-    double nr_re, nr_im;   // Nr_k (regular part of N_k)
-};
-
-__host__ __device__ __forceinline__ KernelParts kernel_parts(double k, double ik, double r, double ir,
-                                                            double ar, double br, double cr, double abr2,
-                                                            const BesselTable* __restrict__ tab) {
-    const double z = k * r;
-    const double iz = ir * ik;                      // 1/z
-    double j0, y0, j1, y1r;
-    bessel01(z, iz, tab, j0, y0, j1, y1r);
-    const double y1 = y1r - kTwoOverPi * iz;        // Y1
-    KernelParts p;
-    p.s_re = -0.25 * y0;
-    p.s_im = 0.25 * j0;
-    const double k4 = 0.25 * k;
-    p.d_re = -k4 * br * y1;
-    p.d_im = k4 * br * j1;
-    p.ds_re = k4 * ar * y1;
-    p.ds_im = -k4 * ar * j1;
-    // X = k (c/r) H1r - k^2 (ab/r^2) H2r,  H2r = 2 H1r/z - H0 + i/pi
-    const double kk = k * k;
-    const double h2r_re = 2.0 * j1 * iz - j0;
-    const double h2r_im = 2.0 * y1r * iz - y0 + (1.0 / kPi);
-    const double x_re = k * cr * j1 - kk * abr2 * h2r_re;
-    const double x_im = k * cr * y1r - kk * abr2 * h2r_im;
-    p.nr_re = -0.25 * x_im - kk * abr2 * (0.25 / kPi);
-    p.nr_im = 0.25 * x_re;
-    return p;
-}
 
 // Geometry of one off-diagonal pair (the points must not coincide).
 struct PairGeom {
@@ -109,42 +75,88 @@ __host__ __device__ __forceinline__ PairGeom pair_geom(double tx, double ty, dou
     return g;
 }
 
-// Interior-medium (k1) parts of a pair; all zero for pairs on different curves.
-__host__ __device__ __forceinline__ KernelParts pair_interior(const PairGeom& g, const Media& m,
-                                                              bool interior) {
-    if (interior) return kernel_parts(m.k1, m.ik1, g.r, g.ir, g.ar, g.br, g.cr, g.abr2, m.tab);
-    return KernelParts{0, 0, 0, 0, 0, 0, 0, 0};
+// J0, Y0, J1, Y1 and Y1r = Y1 + 2/(pi z) of one wavenumber at z = k r.
+struct Hankel01 {
+    double j0, y0, j1, y1, y1r;
+};
+
+__host__ __device__ __forceinline__ Hankel01 hankel01(double k, double ik, const PairGeom& g,
+                                                     const BesselTable* __restrict__ tab) {
+    const double iz = g.ir * ik;
+    Hankel01 h;
+    bessel01(k * g.r, iz, tab, h.j0, h.y0, h.j1, h.y1r);
+    h.y1 = fma(-kTwoOverPi, iz, h.y1r);
+    return h;
 }
 
+// Interior-medium (k1) functions of a pair.  For a pair on different curves
+// the interior operators vanish: J0 = Y0 = J1 = Y1 = 0, and Y1r keeps only the
+// removed pole 2/(pi z1), so that the k0 - k1 combination of pole-free parts in
+// pair_row1 reduces to the k0 term with its pole.
+__host__ __device__ __forceinline__ Hankel01 pair_interior(const PairGeom& g, const Media& m,
+                                                          bool interior) {
+    if (interior) return hankel01(m.k1, m.ik1, g, m.tab);
+    return Hankel01{0.0, 0.0, 0.0, 0.0, kTwoOverPi * (g.ir * m.ik1)};
+}
+
+// The block in terms of the Hankel functions.  With alpha = i/k0 the
+// hypersingular difference alpha (N_k0 - N_k1) reduces (the i/pi parts of H2r
+// and the k^2 ab/(4 pi r^2) terms cancel) to
+//   -(1/4) [ e (H1r(z0) - (k1/k0) H1r(z1)) + (ab/r^2) (k0 H0(z0) - (k1^2/k0) H0(z1)) ],
+// e = (c - 2 ab/r^2)/r, and alpha (eps0 D*_k0 - eps1 D*_k1) to
+//   (a/(4r)) (eps0 H1(z0) - eps1 (k1/k0) H1(z1)).
+// Each output is then a short combination of the eight Bessel values.
+
 // Row 2i of the block: re/im of A(2i,2j) = D_k1 w_j and A(2i,2j+1) = -eps1 S_k1 w_j.
-__host__ __device__ __forceinline__ void pair_row0(const KernelParts& p1, double sw, const Media& m,
-                                                   double (&o)[4]) {
-    o[0] = sw * p1.d_re;
-    o[1] = sw * p1.d_im;
-    o[2] = -sw * m.eps1 * p1.s_re;
-    o[3] = -sw * m.eps1 * p1.s_im;
+__host__ __device__ __forceinline__ void pair_row0(const PairGeom& g, const Hankel01& h1, double sw,
+                                                   const Media& m, double (&o)[4]) {
+    const double sw4 = 0.25 * sw;
+    const double d = (sw4 * g.br) * m.k1;     // D_k1 = i (k1/4) H1(z1) b/r
+    o[0] = -d * h1.y1;
+    o[1] = d * h1.j1;
+    const double s = sw4 * m.eps1;            // -eps1 S_k1 = -i (eps1/4) H0(z1)
+    o[2] = s * h1.y0;
+    o[3] = -s * h1.j0;
+}
+
+// What row 2i+1 needs of the interior functions: (k1/k0) J1(z1), (k1/k0) Y1r(z1),
+// (k1^2/k0) J0(z1), (k1^2/k0) Y0(z1).  (k1/k0) Y1(z1) follows from the second,
+// since (k1/k0) 2/(pi z1) = 2/(pi z0): four values stay live across the
+// exterior Bessel evaluation instead of five.
+struct InteriorTerms {
+    double j1, y1r, j0, y0;
+};
+
+__host__ __device__ __forceinline__ InteriorTerms interior_terms(const Hankel01& h1, const Media& m) {
+    return InteriorTerms{m.q10 * h1.j1, m.q10 * h1.y1r, m.q10k1 * h1.j0, m.q10k1 * h1.y0};
 }
 
 // Row 2i+1: A(2i+1,2j) = D_k0 + alpha (N_k0 - N_k1), A(2i+1,2j+1) = -eps0 S_k0 - alpha (eps0 D*_k0 - eps1 D*_k1).
-__host__ __device__ __forceinline__ void pair_row1(const PairGeom& g, const KernelParts& p1, double sw,
-                                                   const Media& m, bool interior, double (&o)[4]) {
-    const KernelParts p0 = kernel_parts(m.k0, m.ik0, g.r, g.ir, g.ar, g.br, g.cr, g.abr2, m.tab);
-    double nd_re, nd_im;
-    if (interior) {
-        nd_re = p0.nr_re - p1.nr_re;
-        nd_im = p0.nr_im - p1.nr_im;
-    } else {
-        // N_k0 alone: add back the k-independent singular parts
-        nd_re = p0.nr_re + (0.5 / kPi) * g.cr * g.ir - (1.0 / kPi) * g.abr2 * g.ir * g.ir;
-        nd_im = p0.nr_im;
-    }
-    const double ik0 = m.ik0;   // alpha = i/k0: alpha (x + i y) = (-y + i x)/k0
-    o[0] = sw * (p0.d_re - nd_im * ik0);
-    o[1] = sw * (p0.d_im + nd_re * ik0);
-    const double t_re = m.eps0 * p0.ds_re - m.eps1 * p1.ds_re;
-    const double t_im = m.eps0 * p0.ds_im - m.eps1 * p1.ds_im;
-    o[2] = sw * (-m.eps0 * p0.s_re + t_im * ik0);
-    o[3] = sw * (-m.eps0 * p0.s_im - t_re * ik0);
+__host__ __device__ __forceinline__ void pair_row1(const PairGeom& g, const InteriorTerms& it, double sw,
+                                                   const Media& m, double (&o)[4]) {
+    const double iz0 = g.ir * m.ik0;
+    double j0, y0, j1, y1r;
+    bessel01(m.k0 * g.r, iz0, m.tab, j0, y0, j1, y1r);
+    const double y1 = fma(-kTwoOverPi, iz0, y1r);
+    const double sw4 = 0.25 * sw;
+    const double e = fma(-2.0 * g.abr2, g.ir, g.cr);
+    // pole-free J1 and Y1 differences, and the H0 combination
+    const double dj1 = j1 - it.j1;
+    const double dy1 = y1r - it.y1r;
+    const double cj0 = fma(m.k0, j0, -it.j0);
+    const double cy0 = fma(m.k0, y0, -it.y0);
+    const double kb = m.k0 * g.br;
+    double t = fma(-g.abr2, cj0, fma(-e, dj1, -kb * y1));
+    o[0] = sw4 * t;
+    t = fma(-g.abr2, cy0, fma(-e, dy1, kb * j1));
+    o[1] = sw4 * t;
+    // eps0 J1(z0) - eps1 (k1/k0) J1(z1) and the same of Y1
+    const double fj = fma(m.eps0, j1, -m.eps1 * it.j1);
+    const double fy = fma(m.eps0, y1, -m.eps1 * fma(-kTwoOverPi, iz0, it.y1r));
+    t = fma(-g.ar, fj, m.eps0 * y0);
+    o[2] = sw4 * t;
+    t = fma(-g.ar, fy, -m.eps0 * j0);
+    o[3] = sw4 * t;
 }
 
 // Whole off-diagonal block (the points must not coincide).
@@ -152,10 +164,10 @@ __host__ __device__ __forceinline__ Block pair_block(double tx, double ty, doubl
                                                      double sx, double sy, double snx, double sny,
                                                      double sw, const Media& m, bool interior) {
     const PairGeom g = pair_geom(tx, ty, tnx, tny, sx, sy, snx, sny);
-    const KernelParts p1 = pair_interior(g, m, interior);
+    const Hankel01 h1 = pair_interior(g, m, interior);
     double r0[4], r1[4];
-    pair_row0(p1, sw, m, r0);
-    pair_row1(g, p1, sw, m, interior, r1);
+    pair_row0(g, h1, sw, m, r0);
+    pair_row1(g, interior_terms(h1, m), sw, m, r1);
     Block o;
     for (int q = 0; q < 4; ++q) {
         o.v[q] = r0[q];
