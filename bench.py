@@ -463,6 +463,9 @@ def run_hss(args):
                 "seconds_generate": gen_s,
                 "seconds_compress": avg("seconds_compress"),
                 "seconds_cpqr": cq_s,
+                "seconds_cpqr_fused": avg("seconds_cpqr_fused"),
+                "cpqr_fused_launches": st["cpqr_fused_launches"],
+                "cpqr_fused_bytes": st["cpqr_fused_bytes"],
                 "seconds_factor": avg("seconds_factor"),
                 "generation_Gentries_s": entries / gen_s / 1e9,
                 "solve_ms_eager": solve_ms["eager"], "solve_ms_graph": solve_ms["graph"],

@@ -185,6 +185,14 @@ typedef struct {
     /* the sketch and max_rank_ratio the build used (tuned values resolved) */
     int64_t sketch;
     double max_rank_ratio;
+    /* levels whose boxes fit one workgroup (at most 128 unknowns and 160 ID
+     * rows) run the whole CPQR in one launch instead of the step kernels:
+     * those launches, their algorithmic bytes (each matrix read and written
+     * once, pivots and diagonal written) and their event-timed duration; the
+     * three step-wise figures above exclude them */
+    int64_t cpqr_fused_launches;
+    double cpqr_fused_bytes;
+    double seconds_cpqr_fused;
 } bm_hss_stats_t;
 
 /* Build the factorisation; synchronises `stream` once per level to read the

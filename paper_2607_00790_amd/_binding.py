@@ -38,7 +38,8 @@ class _HssStats(ctypes.Structure):
                 ("seconds_generate", c_dbl), ("seconds_compress", c_dbl),
                 ("seconds_factor", c_dbl), ("seconds_total", c_dbl),
                 ("cpqr_launches", c_i64), ("cpqr_bytes", c_dbl), ("seconds_cpqr", c_dbl),
-                ("sketch", c_i64), ("max_rank_ratio", c_dbl)]
+                ("sketch", c_i64), ("max_rank_ratio", c_dbl),
+                ("cpqr_fused_launches", c_i64), ("cpqr_fused_bytes", c_dbl), ("seconds_cpqr_fused", c_dbl)]
 
 
 class _HssLevel(ctypes.Structure):

@@ -613,7 +613,7 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
 // return at once.
 hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, int32_t* dranks,
                     double tol, std::vector<int32_t>& ranks, hipEvent_t ev0, hipEvent_t ev1,
-                    int64_t* launches, int first_check) {
+                    int64_t* launches, int first_check, bool* fused_out) {
     const int nb = static_cast<int>(cj.size());
     int nmax = 0, kmax = 0;
     for (const CpqrJob& j : cj) {
@@ -641,11 +641,27 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
     int32_t* active;
     if ((e = sc.alloc(&active, 1)) != hipSuccess) return e;
     if ((e = sc.flush()) != hipSuccess) return e;
+    int mmax = 0;
+    for (const CpqrJob& j : cj) mmax = std::max(mmax, j.m);
+    // every box small enough for one workgroup's registers: the whole CPQR in one launch
+    const int RS = mmax <= 128 ? 32 : mmax <= 144 ? 36 : mmax <= 160 ? 40 : 0;
+    *fused_out = nmax <= kFusedCols && RS > 0;
+    if (*fused_out) {
+        if ((e = hipEventRecord(ev0, sc.s)) != hipSuccess) return e;
+        switch (RS) {
+            case 32: hipLaunchKernelGGL(k_cpqr_fused<32>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
+            case 36: hipLaunchKernelGGL(k_cpqr_fused<36>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
+            default: hipLaunchKernelGGL(k_cpqr_fused<40>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
+        }
+        if ((e = hipEventRecord(ev1, sc.s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cpqr_finish, dim3(nb), dim3(kThreads), 0, sc.s, dcj);
+        hipLaunchKernelGGL(k_cpqr_ranks, dim3(1), dim3(64), 0, sc.s, dcj, nb, dranks, active);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return hipMemcpyAsync(ranks.data(), dranks, nb * sizeof(int32_t), hipMemcpyDeviceToHost, sc.s);
+    }
     const unsigned chunks = static_cast<unsigned>(ceil_div(std::max(nmax, 1), kThreads / 64));
     hipLaunchKernelGGL(k_cpqr_init, dim3(chunks, nb), dim3(kThreads), 0, sc.s, dcj);
     if ((e = hipEventRecord(ev0, sc.s)) != hipSuccess) return e;
-    int mmax = 0;
-    for (const CpqrJob& j : cj) mmax = std::max(mmax, j.m);
     // register-resident columns when every box has at most 64 R rows
     const int R = mmax <= 256 ? 4 : mmax <= 512 ? 8 : mmax <= 1024 ? 16 : mmax <= 2048 ? 32 : 0;
     const unsigned rchunks = static_cast<unsigned>(ceil_div(std::max(nmax, 1), (kThreads / 64) * kCpqrCols));
@@ -1000,9 +1016,10 @@ int build_impl(bm_hss* h, hipStream_t s) {
         for (auto q : dhat) dev_free(q, s2);
         dhat.clear();
     };
-    int64_t entries = 0, pairs = 0, max_rank = 0, cpqr_launches = 0;
-    double cpqr_bytes = 0;
+    int64_t entries = 0, pairs = 0, max_rank = 0, cpqr_launches = 0, cpqr_fused_launches = 0;
+    double cpqr_bytes = 0, cpqr_fused_bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> cpqr_events;
+    std::vector<bool> cpqr_fused;   // per entry of cpqr_events: the whole-box kernel ran
     struct EventPairs {   // destroyed on every return
         std::vector<std::pair<hipEvent_t, hipEvent_t>>& v;
         ~EventPairs() {
@@ -1303,7 +1320,9 @@ int build_impl(bm_hss* h, hipStream_t s) {
             int64_t guess = 0;
             for (int c = 0; c < nk; ++c) guess = std::max(guess, kn[c] / 2);
             if (!h->level_info.empty()) guess = h->level_info.back().max_rank + h->level_info.back().max_rank / 4 + 8;
-            e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks, c0, c1, &cpqr_launches, static_cast<int>(guess));
+            bool fused = false;
+            e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks, c0, c1, &cpqr_launches, static_cast<int>(guess), &fused);
+            cpqr_fused.push_back(fused);
         }
         if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1329,14 +1348,21 @@ int build_impl(bm_hss* h, hipStream_t s) {
             // columns (n - k - 1 of them, rows k..m) are read and written once, the
             // Householder column (rows k..m) and the n norms are read, and the
             // trailing norms written; the step that finds the rank reads the norms
+            // (the whole-box kernel reads and writes each matrix once, and writes
+            // the pivots and the diagonal of R)
             for (int c = 0; c < nk; ++c) {
                 const double rows = static_cast<double>(Y_sk ? idm[c] : km[c]), cols = static_cast<double>(kn[c]);
+                if (cpqr_fused.back()) {
+                    cpqr_fused_bytes += 32.0 * rows * cols + 20.0 * ranks[c];
+                    continue;
+                }
                 for (int64_t kk = 0; kk < ranks[c]; ++kk) {
                     const double r = rows - kk, cc = cols - kk - 1;
                     cpqr_bytes += 32.0 * r * cc + 16.0 * r + 8.0 * cols + 8.0 * cc;
                 }
                 cpqr_bytes += 8.0 * cols;
             }
+            if (cpqr_fused.back()) ++cpqr_fused_launches;
         }
         std::vector<int64_t> k(nk), koff(nk + 1, 0), nkoff(nk + 1, 0), nnoff(nk + 1, 0), kkoff(nk + 1, 0);
         for (int c = 0; c < nk; ++c) {
@@ -1630,12 +1656,16 @@ int build_impl(bm_hss* h, hipStream_t s) {
     h->stats.seconds_factor = t_fac.seconds();
     h->stats.cpqr_launches = cpqr_launches;
     h->stats.cpqr_bytes = cpqr_bytes;
-    double tcq = 0;
-    for (auto& pr : cpqr_events) {
+    double tcq = 0, tcf = 0;
+    for (size_t q = 0; q < cpqr_events.size(); ++q) {
         float ms = 0;
-        if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) tcq += ms * 1e-3;
+        if (hipEventElapsedTime(&ms, cpqr_events[q].first, cpqr_events[q].second) == hipSuccess)
+            (q < cpqr_fused.size() && cpqr_fused[q] ? tcf : tcq) += ms * 1e-3;
     }
     h->stats.seconds_cpqr = tcq;
+    h->stats.cpqr_fused_launches = cpqr_fused_launches;
+    h->stats.cpqr_fused_bytes = cpqr_fused_bytes;
+    h->stats.seconds_cpqr_fused = tcf;
     return BM_OK;
 }
 

@@ -468,6 +468,121 @@ k_cpqr_step_reg(const CpqrJob* __restrict__ jobs, int k, double tol) {
     }
 }
 
+// The whole CPQR of one box in one workgroup, for boxes of at most
+// kFusedCols columns and 4 RS rows: the matrix stays in registers for all
+// steps.  Four consecutive lanes hold one column (lane s of the group: rows
+// s, s + 4, s + 8, ...), so a column's dot product and norm need two
+// butterfly steps; the pivot column goes through LDS once per step.  Pivot
+// choice (largest remaining column norm, lowest index on ties), rank rule
+// |R_kk| > tol |R_00|, logical pivoting and the layout of the result (R in
+// the columns perm[0..rank), diagonal in rdiag) are those of the step-wise
+// kernels, so k_cpqr_finish and k_interp follow unchanged.  Grid: one
+// workgroup of kFusedThreads per box.
+template <int RS>
+__global__ void __launch_bounds__(kFusedThreads)
+k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
+    __shared__ double sv[kFusedThreads / 64];
+    __shared__ int si[kFusedThreads / 64];
+    __shared__ double2 ws[4 * RS];
+    const CpqrJob jb = jobs[blockIdx.x];
+    const int n = jb.n, m = jb.m;
+    const int j = threadIdx.x >> 2, s = threadIdx.x & 3;
+    const bool mine = j < n;
+    double2 X[RS];
+#pragma unroll
+    for (int t = 0; t < RS; ++t) {
+        const int r = s + 4 * t;
+        X[t] = (mine && r < m) ? gload2(jb.x + static_cast<int64_t>(j) * m + r) : make_double2(0.0, 0.0);
+    }
+    double nrm = 0;
+#pragma unroll
+    for (int t = 0; t < RS; ++t) nrm += cabs2(X[t]);
+    nrm += __shfl_xor(nrm, 1, 64);
+    nrm += __shfl_xor(nrm, 2, 64);
+    bool used = !mine;
+    if (mine && s == 0) gst(jb.used + j, 0);
+    const int kmax = n < m ? n : m;
+    double ref = 0;
+    int k = 0;
+    for (; k < kmax; ++k) {
+        double bv = (!used && s == 0) ? nrm : -1.0;
+        int bi = (!used && s == 0) ? j : n;
+        block_argmax(bv, bi, sv, si);
+        if (k == 0) ref = sqrt(bv);
+        if (!(sqrt(bv) > tol * ref) || ref == 0 || bi >= n) break;
+        const int p = bi;
+        if (j == p) {
+            used = true;
+#pragma unroll
+            for (int t = 0; t < RS; ++t) {
+                const int r = s + 4 * t;
+                if (r >= k && r < m) ws[r] = X[t];
+            }
+        }
+        __syncthreads();
+        const double xn = sqrt(bv);
+        const double2 x0 = ws[k];
+        const double a0 = sqrt(cabs2(x0));
+        const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
+        const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
+        const double2 w0 = make_double2(x0.x - alpha.x, x0.y - alpha.y);
+        const double beta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
+        if (threadIdx.x == 0) {
+            gst(jb.perm + k, p);
+            gstore2(jb.rdiag + k, alpha);
+        }
+        if (!used) {
+            double gr = 0, gi = 0;
+#pragma unroll
+            for (int t = 0; t < RS; ++t) {
+                if (4 * t + 3 < k) continue;   // wave-uniform: rows above the step
+                const int r = s + 4 * t;
+                if (r >= k && r < m) {
+                    const double2 v = cconj_mul(r == k ? w0 : ws[r], X[t]);
+                    gr += v.x;
+                    gi += v.y;
+                }
+            }
+            gr += __shfl_xor(gr, 1, 64);
+            gr += __shfl_xor(gr, 2, 64);
+            gi += __shfl_xor(gi, 1, 64);
+            gi += __shfl_xor(gi, 2, 64);
+            gr *= beta;
+            gi *= beta;
+            double sn = 0;
+#pragma unroll
+            for (int t = 0; t < RS; ++t) {
+                if (4 * t + 3 < k) continue;
+                const int r = s + 4 * t;
+                if (r >= k && r < m) {
+                    const double2 wr = r == k ? w0 : ws[r];
+                    X[t].x -= gr * wr.x - gi * wr.y;
+                    X[t].y -= gr * wr.y + gi * wr.x;
+                    if (r > k) sn += cabs2(X[t]);
+                }
+            }
+            sn += __shfl_xor(sn, 1, 64);
+            sn += __shfl_xor(sn, 2, 64);
+            nrm = sn;
+        }
+        __syncthreads();   // ws is rewritten by the next step
+    }
+#pragma unroll
+    for (int t = 0; t < RS; ++t) {
+        const int r = s + 4 * t;
+        if (mine && r < m) gstore2(jb.x + static_cast<int64_t>(j) * m + r, X[t]);
+    }
+    if (threadIdx.x == 0) {
+        gst(&jb.st->ref, ref);
+        gst(&jb.st->rank, k);
+        gst(&jb.st->done, 1);
+    }
+}
+
+template __global__ void k_cpqr_fused<32>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<36>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<40>(const CpqrJob*, double);
+
 template __global__ void k_cpqr_step_reg<4>(const CpqrJob*, int, double);
 template __global__ void k_cpqr_step_reg<8>(const CpqrJob*, int, double);
 template __global__ void k_cpqr_step_reg<16>(const CpqrJob*, int, double);
