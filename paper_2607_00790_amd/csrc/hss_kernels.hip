@@ -472,22 +472,26 @@ k_cpqr_step_reg(const CpqrJob* __restrict__ jobs, int k, double tol) {
 // kFusedCols columns and 4 RS rows: the matrix stays in registers for all
 // steps.  Four consecutive lanes hold one column (lane s of the group: rows
 // s, s + 4, s + 8, ...), so a column's dot product and norm need two
-// butterfly steps; the pivot column goes through LDS once per step.  Pivot
-// choice (largest remaining column norm, lowest index on ties), rank rule
-// |R_kk| > tol |R_00|, logical pivoting and the layout of the result (R in
-// the columns perm[0..rank), diagonal in rdiag) are those of the step-wise
-// kernels, so k_cpqr_finish and k_interp follow unchanged.  Grid: one
-// workgroup of kFusedThreads per box.
+// butterfly steps.  Each step stages the Householder vector in LDS as a full
+// column: zeros above row k, w0 at row k, the pivot column below, zeros from
+// row m on; the dot products and updates then run over every slot with no
+// masks or branches.  Pivot choice (largest remaining column norm, lowest
+// index on ties), rank rule |R_kk| > tol |R_00|, logical pivoting and the
+// layout of the result (R in the columns perm[0..rank), diagonal in rdiag) are
+// those of the step-wise kernels, so k_cpqr_finish and k_interp follow
+// unchanged.  Grid: one workgroup of kFusedThreads per box.
 template <int RS>
 __global__ void __launch_bounds__(kFusedThreads)
 k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
     __shared__ double sv[kFusedThreads / 64];
     __shared__ int si[kFusedThreads / 64];
     __shared__ double2 ws[4 * RS];
+    __shared__ double sbeta;
     const CpqrJob jb = jobs[blockIdx.x];
     const int n = jb.n, m = jb.m;
     const int j = threadIdx.x >> 2, s = threadIdx.x & 3;
     const bool mine = j < n;
+    for (int r = threadIdx.x; r < 4 * RS; r += kFusedThreads) ws[r] = make_double2(0.0, 0.0);
     double2 X[RS];
 #pragma unroll
     for (int t = 0; t < RS; ++t) {
@@ -496,7 +500,7 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
     }
     double nrm = 0;
 #pragma unroll
-    for (int t = 0; t < RS; ++t) nrm += cabs2(X[t]);
+    for (int t = 0; t < RS; ++t) nrm = fma(X[t].x, X[t].x, fma(X[t].y, X[t].y, nrm));
     nrm += __shfl_xor(nrm, 1, 64);
     nrm += __shfl_xor(nrm, 2, 64);
     bool used = !mine;
@@ -507,7 +511,7 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
     for (; k < kmax; ++k) {
         double bv = (!used && s == 0) ? nrm : -1.0;
         int bi = (!used && s == 0) ? j : n;
-        block_argmax(bv, bi, sv, si);
+        block_argmax(bv, bi, sv, si);   // ends with a barrier: ws is free
         if (k == 0) ref = sqrt(bv);
         if (!(sqrt(bv) > tol * ref) || ref == 0 || bi >= n) break;
         const int p = bi;
@@ -516,56 +520,53 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
 #pragma unroll
             for (int t = 0; t < RS; ++t) {
                 const int r = s + 4 * t;
-                if (r >= k && r < m) ws[r] = X[t];
+                if (r < m) ws[r] = r >= k ? X[t] : make_double2(0.0, 0.0);
             }
         }
         __syncthreads();
-        const double xn = sqrt(bv);
-        const double2 x0 = ws[k];
-        const double a0 = sqrt(cabs2(x0));
-        const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
-        const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
-        const double2 w0 = make_double2(x0.x - alpha.x, x0.y - alpha.y);
-        const double beta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
         if (threadIdx.x == 0) {
+            const double xn = sqrt(bv);
+            const double2 x0 = ws[k];
+            const double a0 = sqrt(cabs2(x0));
+            const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
+            const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
+            ws[k] = make_double2(x0.x - alpha.x, x0.y - alpha.y);
+            sbeta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
             gst(jb.perm + k, p);
             gstore2(jb.rdiag + k, alpha);
         }
-        if (!used) {
-            double gr = 0, gi = 0;
+        __syncthreads();
+        const double beta = sbeta;
+        double gr = 0, gi = 0;
 #pragma unroll
-            for (int t = 0; t < RS; ++t) {
-                if (4 * t + 3 < k) continue;   // wave-uniform: rows above the step
-                const int r = s + 4 * t;
-                if (r >= k && r < m) {
-                    const double2 v = cconj_mul(r == k ? w0 : ws[r], X[t]);
-                    gr += v.x;
-                    gi += v.y;
-                }
-            }
-            gr += __shfl_xor(gr, 1, 64);
-            gr += __shfl_xor(gr, 2, 64);
-            gi += __shfl_xor(gi, 1, 64);
-            gi += __shfl_xor(gi, 2, 64);
-            gr *= beta;
-            gi *= beta;
-            double sn = 0;
-#pragma unroll
-            for (int t = 0; t < RS; ++t) {
-                if (4 * t + 3 < k) continue;
-                const int r = s + 4 * t;
-                if (r >= k && r < m) {
-                    const double2 wr = r == k ? w0 : ws[r];
-                    X[t].x -= gr * wr.x - gi * wr.y;
-                    X[t].y -= gr * wr.y + gi * wr.x;
-                    if (r > k) sn += cabs2(X[t]);
-                }
-            }
-            sn += __shfl_xor(sn, 1, 64);
-            sn += __shfl_xor(sn, 2, 64);
-            nrm = sn;
+        for (int t = 0; t < RS; ++t) {
+            const double2 w = ws[s + 4 * t];
+            gr = fma(w.x, X[t].x, fma(w.y, X[t].y, gr));
+            gi = fma(w.x, X[t].y, fma(-w.y, X[t].x, gi));
         }
-        __syncthreads();   // ws is rewritten by the next step
+        gr += __shfl_xor(gr, 1, 64);
+        gr += __shfl_xor(gr, 2, 64);
+        gi += __shfl_xor(gi, 1, 64);
+        gi += __shfl_xor(gi, 2, 64);
+        // pivoted columns (and columns past n) stay as they are
+        gr = used ? 0.0 : gr * beta;
+        gi = used ? 0.0 : gi * beta;
+        // read w again below instead of keeping RS values live across the
+        // butterfly (a compiler barrier only: no instruction)
+        asm volatile("" ::: "memory");
+        double sn = 0;
+#pragma unroll
+        for (int t = 0; t < RS; ++t) {
+            const int r = s + 4 * t;
+            const double2 w = ws[r];
+            X[t].x = fma(-gr, w.x, fma(gi, w.y, X[t].x));
+            X[t].y = fma(-gr, w.y, fma(-gi, w.x, X[t].y));
+            const double q = fma(X[t].x, X[t].x, X[t].y * X[t].y);
+            sn += r > k ? q : 0.0;
+        }
+        sn += __shfl_xor(sn, 1, 64);
+        sn += __shfl_xor(sn, 2, 64);
+        if (!used) nrm = sn;
     }
 #pragma unroll
     for (int t = 0; t < RS; ++t) {
