@@ -502,7 +502,8 @@ def run_adjoint(args):
     crv = wl.curves[0]
     c0 = torch.from_numpy(np.concatenate([crv.a, crv.b])).cuda()
     md, n = wl.media, wl.n
-    opts = dict(leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=args.id_tol)
+    opts = dict(leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=args.id_tol, sketch=args.sketch,
+                max_rank_ratio=args.max_rank_ratio)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -542,6 +543,8 @@ def run_adjoint(args):
         return a.elapsed_time(b) / reps, r
 
     build_ms, h = timed(lambda: bm.bm_hss_build(p, **opts), 2)
+    hst = bm.bm_hss_stats(h)
+    used = dict(opts, sketch=hst["sketch"], max_rank_ratio=hst["max_rank_ratio"])
     rhs = bm.bm_rhs_plane_wave(p, wl.theta_inc)
     solve_ms, phi = timed(lambda: bm.bm_hss_solve(h, rhs), 3)
     gw = bm.bm_far_field_weights(p, obs)
@@ -558,7 +561,7 @@ def run_adjoint(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"shape gradient, {wl.name}, J = |u_inf(-d)|^2", "n_nodes": n,
-                   "coefficients": 64, "k0": md.k0, "k1": md.k1, "theta_inc": wl.theta_inc, **opts},
+                   "coefficients": 64, "k0": md.k0, "k1": md.k1, "theta_inc": wl.theta_inc, **used},
         "phases_ms": {"hss_build": build_ms, "hss_solve": solve_ms, "hss_solve_transpose": tsolve_ms,
                       "shape_derivative": deriv_ms},
     }
@@ -585,24 +588,24 @@ def main():
     ap.add_argument("--per-curve", type=int, default=16384, help="large mode: nodes per star")
     ap.add_argument("--max-rank-ratio", type=float, default=None,
                     help="HSS: a body stops compressing once a level keeps more than this fraction of its "
-                         "unknowns (0: never; -1: the library's tuned value; default: -1 in hss mode, "
-                         "0.8 in large mode, 0 otherwise)")
+                         "unknowns (0: never; -1: the library's tuned value; default: -1 in hss and adjoint "
+                         "modes, 0.8 in large mode, 0 otherwise)")
     ap.add_argument("--batch", type=int, default=256, help="batch mode: number of stars")
     ap.add_argument("--proxy-adapt", type=int, choices=[0, 1], default=1,
                     help="batch mode: proxy points per circle max(64, ceil(2 k R_p) + 32)")
     ap.add_argument("--sketch", type=int, default=None,
                     help="HSS: p > 0 runs the ID on a Gaussian sketch with unknowns + p rows (0: plain "
-                         "CPQR; -1: the library's tuned value; default: -1 in hss mode, 128 in large "
-                         "mode, 0 otherwise)")
+                         "CPQR; -1: the library's tuned value; default: -1 in hss and adjoint modes, 128 "
+                         "in large mode, 0 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device once (a plain copy "
                          "kernel of known size, to scale HBM traffic counters)")
     args = ap.parse_args()
     if args.max_rank_ratio is None:
-        args.max_rank_ratio = {"hss": -1.0, "large": 0.8}.get(args.mode, 0.0)
+        args.max_rank_ratio = {"hss": -1.0, "adjoint": -1.0, "large": 0.8}.get(args.mode, 0.0)
     if args.sketch is None:
-        args.sketch = {"hss": -1, "large": 128}.get(args.mode, 0)
+        args.sketch = {"hss": -1, "adjoint": -1, "large": 128}.get(args.mode, 0)
     if args.gpus != 1:
         print("this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         return 2

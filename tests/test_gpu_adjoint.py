@@ -211,9 +211,14 @@ def _full_workload():
 # step 1e-6 amplify to ~1e-3 of the gradient; at 1e-12 J is accurate to ~1e-9
 # and the differences resolve the gradient to ~1e-8.
 FULL_OPTS = dict(leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-12)
+# the same with the library's tuned build options (Gaussian-sketch ID, stop rule),
+# the benchmark's configuration
+TUNED_OPTS = dict(FULL_OPTS, sketch=-1, max_rank_ratio=-1)
+FULL_CASES = [pytest.param(FULL_OPTS, id="cpqr"), pytest.param(TUNED_OPTS, id="tuned")]
 
 
-def test_autograd_gradient_full_workload_central_differences(gpu_lib):
+@pytest.mark.parametrize("opts", FULL_CASES)
+def test_autograd_gradient_full_workload_central_differences(gpu_lib, opts):
     """The differentiation workload: r = 1 + sum_{j<=32} (a_j cos jt + b_j sin jt),
     coefficients ~ N(0, 0.01^2), N = 8192, k0 = 40, n = 1.5, J = |u_inf(-d)|^2:
     all 64 gradient entries against central differences of the GPU's J with
@@ -224,7 +229,7 @@ def test_autograd_gradient_full_workload_central_differences(gpu_lib):
     md, n = wl.media, wl.n
     note(f"adjoint: full workload N={n}, 64 coefficients, central differences step 1e-6")
     coef = torch.from_numpy(c0).cuda().requires_grad_(True)
-    J = bm.backscatter_intensity(coef, n, md.k0, md.k1, md.eps0, md.eps1, theta_inc=wl.theta_inc, **FULL_OPTS)
+    J = bm.backscatter_intensity(coef, n, md.k0, md.k1, md.eps0, md.eps1, theta_inc=wl.theta_inc, **opts)
     J.backward()
     got = coef.grad.cpu().numpy()
     h = 1e-6
@@ -233,7 +238,7 @@ def test_autograd_gradient_full_workload_central_differences(gpu_lib):
     def jv(c):
         with torch.no_grad():
             return bm.backscatter_intensity(torch.from_numpy(c).cuda(), n, md.k0, md.k1, md.eps0, md.eps1,
-                                            theta_inc=wl.theta_inc, **FULL_OPTS).item()
+                                            theta_inc=wl.theta_inc, **opts).item()
 
     for m in range(64):
         e = np.zeros(64)
@@ -244,7 +249,8 @@ def test_autograd_gradient_full_workload_central_differences(gpu_lib):
     assert err <= 1e-6
 
 
-def test_autograd_gradient_full_workload_dense_oracle(gpu_lib):
+@pytest.mark.parametrize("opts", FULL_CASES)
+def test_autograd_gradient_full_workload_dense_oracle(gpu_lib, opts):
     """J and directional derivatives dJ.v at the full differentiation workload
     against the dense oracle (one LU of the 16384 x 16384 system, values stored
     by tests/golden/make_shape_golden.py)."""
@@ -258,7 +264,7 @@ def test_autograd_gradient_full_workload_dense_oracle(gpu_lib):
     md, n = wl.media, wl.n
     assert (gold["n"], gold["k0"], gold["k1"], gold["theta_inc"]) == (n, md.k0, md.k1, wl.theta_inc)
     coef = torch.from_numpy(c0).cuda().requires_grad_(True)
-    J = bm.backscatter_intensity(coef, n, md.k0, md.k1, md.eps0, md.eps1, theta_inc=wl.theta_inc, **FULL_OPTS)
+    J = bm.backscatter_intensity(coef, n, md.k0, md.k1, md.eps0, md.eps1, theta_inc=wl.theta_inc, **opts)
     J.backward()
     g = coef.grad.cpu().numpy()
     note(f"adjoint: full workload vs dense oracle: J {J.item():.12e} (oracle {gold['J']:.12e})")
