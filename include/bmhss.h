@@ -242,6 +242,9 @@ typedef struct {
 } bm_hss_level_t;
 int bm_hss_level(const bm_hss* h, int level, bm_hss_level_t* out);
 
+/* Releases the factors (to the library's device-memory cache, where the next
+ * build can reuse them on any stream).  Waits for the graph-replayed solves;
+ * every other call on h returns after its device work has completed. */
 int bm_hss_destroy(bm_hss* h);
 /* ---- Shape derivatives of far-field objectives (adjoint method) ----
  * The paper solves Eq. (3) for a fixed boundary; these entry points

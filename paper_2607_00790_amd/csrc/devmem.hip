@@ -6,7 +6,10 @@
 // size-class bins after their first allocation and never returned to the
 // driver.  A freed block is tagged with the stream it was released on and is
 // only handed out again for work on that same stream, so stream order
-// guarantees its previous users have finished.
+// guarantees its previous users have finished.  A block released with no
+// work pending on it (dev_free_idle) may be handed out for any stream: the
+// factors of a destroyed HSS object are allocated on the build's second stream
+// and released on the caller's, and would otherwise never be reused.
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -21,6 +24,7 @@ namespace {
 struct CachedBlock {
     void* p;
     hipStream_t s;
+    bool idle;   // no work pending: reusable on any stream
 };
 
 struct DeviceCache {
@@ -52,7 +56,7 @@ hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
         if (it != dc.free_bins.end()) {
             std::vector<CachedBlock>& v = it->second;
             for (size_t i = v.size(); i-- > 0;) {
-                if (v[i].s == s) {
+                if (v[i].idle || v[i].s == s) {
                     *p = v[i].p;
                     v.erase(v.begin() + static_cast<std::ptrdiff_t>(i));
                     return hipSuccess;
@@ -70,7 +74,9 @@ hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
     return hipSuccess;
 }
 
-void dev_free(void* p, hipStream_t s) {
+namespace {
+
+void release_block(void* p, hipStream_t s, bool idle) {
     if (!p) return;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return;
@@ -78,7 +84,13 @@ void dev_free(void* p, hipStream_t s) {
     DeviceCache& dc = g_cache[dev];
     auto it = dc.size_of.find(p);
     if (it == dc.size_of.end()) return;   // not ours
-    dc.free_bins[it->second].push_back(CachedBlock{p, s});
+    dc.free_bins[it->second].push_back(CachedBlock{p, s, idle});
 }
+
+}  // namespace
+
+void dev_free(void* p, hipStream_t s) { release_block(p, s, false); }
+
+void dev_free_idle(void* p) { release_block(p, nullptr, true); }
 
 }  // namespace bm

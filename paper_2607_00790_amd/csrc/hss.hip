@@ -1989,10 +1989,16 @@ int bm_hss_level(const bm_hss* h, int level, bm_hss_level_t* out) {
 int bm_hss_destroy(bm_hss* h) {
     if (!h) return BM_OK;
     h->plans.clear();   // waits for their last launches
-    // the blocks return to the allocator tagged with the build stream, so work
-    // still queued on that stream finishes before any reuse
-    for (auto& f : h->lv) free_factor(f, h->stream);
-    dev_free(h->Rinv, h->stream);
+    // nothing else can still use the factors: the build and the eager solves
+    // return after completion and the graph-replayed solves were waited for
+    // above, so the blocks go back to the allocator reusable on any stream (the
+    // next build allocates its factors on its second stream)
+    for (auto& f : h->lv) {
+        dev_free_idle(f.E);
+        dev_free_idle(f.Ft);
+        dev_free_idle(f.G);
+    }
+    dev_free_idle(h->Rinv);
     delete h;
     return BM_OK;
 }

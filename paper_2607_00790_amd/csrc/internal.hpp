@@ -74,6 +74,8 @@ inline NodeView view(const bm_problem* p) { return view(p->g, p->d_body); }
 // they were released on.
 hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+// release a block that no queued or running work uses any more
+void dev_free_idle(void* p);
 
 // Kernel launchers (assemble.hip)
 hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurves, int64_t n,
