@@ -694,28 +694,28 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
 }
 
 // Slots of an unknown list (global unknown ids): one slot per node in order of
-// first appearance, with the positions of its u / q unknowns in the list.
+// first appearance, with the positions of its u / q unknowns in the list.  The
+// node -> slot map is a flat array kept across calls (entries reset after use),
+// so a call costs O(list length) with no allocation.
 void make_slots(const std::vector<int32_t>& U, std::vector<Slot>& out) {
-    std::vector<std::pair<int32_t, int32_t>> seen;   // node -> slot index (small linear map)
+    thread_local std::vector<int32_t> slot_of;   // node -> slot index, -1 when unseen
+    int32_t top = -1;
+    for (int32_t u : U) top = std::max(top, u >> 1);
+    if (static_cast<int64_t>(slot_of.size()) <= top) slot_of.resize(static_cast<size_t>(top) + 1, -1);
     const size_t first = out.size();
     for (size_t p = 0; p < U.size(); ++p) {
         const int32_t node = U[p] >> 1;
         const int comp = U[p] & 1;
-        int32_t si = -1;
-        // the u and q of one node are usually adjacent in the list
-        if (out.size() > first && out.back().pt == node) si = static_cast<int32_t>(out.size() - 1);
-        if (si < 0) {
-            for (const auto& pr : seen)
-                if (pr.first == node) { si = pr.second; break; }
-        }
+        int32_t si = slot_of[node];
         if (si < 0) {
             out.push_back(Slot{node, -1, -1});
             si = static_cast<int32_t>(out.size() - 1);
-            seen.emplace_back(node, si);
+            slot_of[node] = si;
         }
         if (comp == 0) out[si].pos0 = static_cast<int32_t>(p);
         else out[si].pos1 = static_cast<int32_t>(p);
     }
+    for (size_t q = first; q < out.size(); ++q) slot_of[out[q].pt] = -1;
 }
 
 int count_unknowns(const Slot* s, size_t n) {
