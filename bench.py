@@ -45,9 +45,11 @@ FLOP_PER_PAIR_MATVEC = 349.9
 MEASURED_TRAFFIC = {
     # one sweep: one launch
     "k_dense": (2.0 * 48835.4 + 16861700.0) * 1024,
-    # two HSS builds of the default options (gaussian sketch, unknowns + 16 rows; stop
-    # ratio 0.65): 824 launches of k_cpqr_step_reg<4>
-    ("k_cpqr_step_reg", 16, 0.65): (2.0 * 5499230.0 + 8999600.0) * 1024 / 824,
+    # two HSS builds with the tuned options (gaussian sketch, unknowns + 8 rows; stop
+    # ratio 0.6): 336 launches of k_gemm, 102 of k_gauss_jordan_16, 234 of k_cpqr_step_reg<4>
+    ("k_gemm", 8, 0.6): (2.0 * 3096210.0 + 1120110.0) * 1024 / 336,
+    ("k_gauss_jordan", 8, 0.6): (2.0 * 84847.2 + 158339.0) * 1024 / 102,
+    ("k_cpqr_step_reg", 8, 0.6): (2.0 * 326855.0 + 516938.0) * 1024 / 234,
 }
 
 
@@ -417,8 +419,12 @@ def run_hss(args):
 
     # the solve alone: eager (descriptors staged per call, synchronises) and
     # replayed from the HIP graph captured on its first call
+    # this build also times every batched GEMM and Gauss-Jordan launch with HIP
+    # events (an event pair per launch, so it is kept out of the timed steps)
     h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points,
-                        id_tol=wl.id_tol, sketch=args.sketch, max_rank_ratio=args.max_rank_ratio)
+                        id_tol=wl.id_tol, sketch=args.sketch, max_rank_ratio=args.max_rank_ratio,
+                        kernel_timing=True)
+    kst = bm.bm_hss_stats(h)
     bm.bm_hss_solve_graph(h, b, out=x)
     solve_ms = {}
     for name, fn in (("eager", lambda: bm.bm_hss_solve(h, b, out=x)),
@@ -435,13 +441,21 @@ def run_hss(args):
 
     gen_s = avg("seconds_generate")
     entries = st["entries"]
-    # dominant kernel of the step: the CPQR step kernel of the ID
+    # the step-wise CPQR of the levels too large for the whole-box kernel
     launches = st["cpqr_launches"]
     cq_s = avg("seconds_cpqr")
     cq_bytes = st["cpqr_bytes"]
-    cq_gbs = cq_bytes / cq_s / 1e9
+    cq_gbs = cq_bytes / cq_s / 1e9 if cq_s > 0 else None
     sk, ratio = st["sketch"], st["max_rank_ratio"]
-    traffic = MEASURED_TRAFFIC.get(("k_cpqr_step_reg", sk, ratio))
+    # the kernels of the step by launch time: the batched GEMM and Gauss-Jordan
+    # kernels (event-timed in the extra build above) and the ID's CPQR
+    kern = {
+        "k_gemm": (kst["seconds_gemm"], kst["gemm_launches"], kst["gemm_flops"]),
+        "k_gauss_jordan": (kst["seconds_inv"], kst["inv_launches"], kst["inv_flops"]),
+    }
+    dom = max(kern, key=lambda k: kern[k][0])
+    d_s, d_n, d_f = kern[dom]
+    d_tf = d_f / d_s / 1e12 if d_s > 0 else None
     out = {
         "metric": "Gentries/s Burton-Miller blocks (frac FP64 peak); HSS build+solve s at N=16384",
         "value": entries / (ms * 1e-3) / 1e9,
@@ -469,13 +483,22 @@ def run_hss(args):
                 "seconds_factor": avg("seconds_factor"),
                 "generation_Gentries_s": entries / gen_s / 1e9,
                 "solve_ms_eager": solve_ms["eager"], "solve_ms_graph": solve_ms["graph"],
+                "kernels_event_timed": {k: {"seconds": v[0], "launches": v[1], "flops": v[2],
+                                            "avg_launch_ms": v[0] / max(v[1], 1) * 1e3,
+                                            "tflops": v[2] / v[0] / 1e12 if v[0] > 0 else None}
+                                        for k, v in kern.items()},
+                "cpqr_step": {"seconds": cq_s, "launches": launches,
+                              "algorithmic_GBs": cq_gbs,
+                              "traffic_per_launch": MEASURED_TRAFFIC.get(("k_cpqr_step_reg", sk, ratio))},
                 "per_level": levels},
         "entry_generation": entry,
-        "roofline": {"bound": "hbm", "achieved": cq_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": cq_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "k_cpqr_step_reg",
-                     "launches": launches, "algorithmic_bytes_per_launch": cq_bytes / launches,
-                     "avg_launch_ms": cq_s / launches * 1e3},
+        # the dominant kernel: FP64 vector arithmetic (no matrix cores), latency-bound
+        # at these sizes; achieved = its algorithmic flops / its event-timed launch time
+        "roofline": {"bound": "alu", "achieved": d_tf, "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
+                     "frac": d_tf / FP64_VECTOR_PEAK_TF if d_tf else None,
+                     "traffic": MEASURED_TRAFFIC.get((dom, sk, ratio)), "kernel": dom,
+                     "launches": d_n, "algorithmic_flops_per_launch": d_f / max(d_n, 1),
+                     "avg_launch_ms": d_s / max(d_n, 1) * 1e3},
     }
     return out, wl
 

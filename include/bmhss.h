@@ -160,6 +160,9 @@ typedef struct {
                               unknowns -- at high frequency the ranks grow with the
                               box size and compressing further does not pay;
                               -1: the library's tuned value */
+    int64_t kernel_timing; /* 1: time every launch of the batched GEMM and Gauss-Jordan
+                              kernels with HIP events (bm_hss_stats_t gemm_* and
+                              inv_*; adds an event pair per launch); 0: off */
 } bm_hss_opts;
 
 typedef struct {
@@ -193,6 +196,16 @@ typedef struct {
     int64_t cpqr_fused_launches;
     double cpqr_fused_bytes;
     double seconds_cpqr_fused;
+    /* with opts.kernel_timing: launches of the batched GEMM kernel (rocBLAS
+     * calls excluded), their algorithmic flops (8 M N K per complex product)
+     * and summed event-timed durations; the same for the batched Gauss-Jordan
+     * kernels (8 n^3 flops per inverted block); zero otherwise */
+    int64_t gemm_launches;
+    double gemm_flops;
+    double seconds_gemm;
+    int64_t inv_launches;
+    double inv_flops;
+    double seconds_inv;
 } bm_hss_stats_t;
 
 /* Build the factorisation; synchronises `stream` once per level to read the

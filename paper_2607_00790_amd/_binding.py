@@ -28,7 +28,8 @@ class _Media(ctypes.Structure):
 
 class _HssOpts(ctypes.Structure):
     _fields_ = [("leaf", c_i64), ("proxy_ratio", c_dbl), ("proxy_points", c_i64),
-                ("id_tol", c_dbl), ("sketch", c_i64), ("proxy_adapt", c_i64), ("max_rank_ratio", c_dbl)]
+                ("id_tol", c_dbl), ("sketch", c_i64), ("proxy_adapt", c_i64), ("max_rank_ratio", c_dbl),
+                ("kernel_timing", c_i64)]
 
 
 class _HssStats(ctypes.Structure):
@@ -39,7 +40,9 @@ class _HssStats(ctypes.Structure):
                 ("seconds_factor", c_dbl), ("seconds_total", c_dbl),
                 ("cpqr_launches", c_i64), ("cpqr_bytes", c_dbl), ("seconds_cpqr", c_dbl),
                 ("sketch", c_i64), ("max_rank_ratio", c_dbl),
-                ("cpqr_fused_launches", c_i64), ("cpqr_fused_bytes", c_dbl), ("seconds_cpqr_fused", c_dbl)]
+                ("cpqr_fused_launches", c_i64), ("cpqr_fused_bytes", c_dbl), ("seconds_cpqr_fused", c_dbl),
+                ("gemm_launches", c_i64), ("gemm_flops", c_dbl), ("seconds_gemm", c_dbl),
+                ("inv_launches", c_i64), ("inv_flops", c_dbl), ("seconds_inv", c_dbl)]
 
 
 class _HssLevel(ctypes.Structure):
@@ -299,16 +302,17 @@ def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
 
 
 def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10,
-                 sketch=0, proxy_adapt=False, max_rank_ratio=0.0, stream=None) -> HSS:
+                 sketch=0, proxy_adapt=False, max_rank_ratio=0.0, kernel_timing=False, stream=None) -> HSS:
     """sketch = p > 0: run the ID on a Gaussian sketch of each box's stacked
     matrix with (unknowns + p) rows, when that is fewer than the matrix has.
     proxy_adapt: max(proxy_points, ceil(2 k R_p) + 32) points per proxy circle.
     max_rank_ratio = r > 0: a body stops compressing once a level keeps more
     than r of its unknowns (its skeletons then form its dense root).
     sketch = -1 or max_rank_ratio = -1: the library's tuned value (the build's
-    stats report the values used)."""
+    stats report the values used).  kernel_timing: HIP-event timing of every
+    batched GEMM and Gauss-Jordan launch (stats gemm_* and inv_*)."""
     opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol), int(sketch),
-                    int(bool(proxy_adapt)), float(max_rank_ratio))
+                    int(bool(proxy_adapt)), float(max_rank_ratio), int(bool(kernel_timing)))
     out = c_vp()
     _check(load().bm_hss_build(p._h, ctypes.byref(opts), _stream(stream), ctypes.byref(out)))
     return HSS(out, p)

@@ -280,6 +280,43 @@ hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const 
 }
 
 hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs);
+
+// Per-launch HIP-event timing of the batched GEMM and Gauss-Jordan kernels
+// during a build with opts.kernel_timing set: the launchers record an event
+// pair around each launch into the collector of the calling build.
+struct KernelTimes {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm, inv;
+    double gemm_flops = 0, inv_flops = 0;
+    ~KernelTimes() {
+        for (auto* v : {&gemm, &inv})
+            for (auto& pr : *v) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+    }
+    static double seconds(const std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+        double t = 0;
+        for (auto& pr : v) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) t += ms * 1e-3;
+        }
+        return t;
+    }
+};
+thread_local KernelTimes* g_ktimes = nullptr;
+
+// an event pair around one launch when the calling build times its kernels
+bool timed_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
+    if (hipEventCreate(a) != hipSuccess) return false;
+    if (hipEventCreate(b) != hipSuccess) {
+        (void)hipEventDestroy(*a);
+        *a = nullptr;
+        return false;
+    }
+    v.emplace_back(*a, *b);
+    return true;
+}
 hipError_t launch_gemv_group(Scratch& sc, const std::vector<GemmJob>& jobs);
 int64_t gemv_tiles(const GemmJob& j);
 
@@ -429,8 +466,13 @@ hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs) {
     const unsigned grid = static_cast<unsigned>(toff.back());
     const int nj = static_cast<int>(jobs.size());
     hipStream_t st = sc.s;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (g_ktimes && timed_pair(g_ktimes->gemm, &ea, &eb))
+        for (const GemmJob& g : jobs) g_ktimes->gemm_flops += 8.0 * g.M * g.N * g.K;
     sc.rec([=]() {
+        if (ea) (void)hipEventRecord(ea, st);
         hipLaunchKernelGGL(k_gemm, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj);
+        if (eb) (void)hipEventRecord(eb, st);
         return hipGetLastError();
     });
     return hipSuccess;
@@ -560,13 +602,18 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
         if ((e = sc.upload(&dj, base)) != hipSuccess) return e;
         const unsigned nj = static_cast<unsigned>(base.size());
         hipStream_t st = sc.s;
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (g_ktimes && timed_pair(g_ktimes->inv, &ea, &eb))
+            for (const InvJob& j : base) g_ktimes->inv_flops += 8.0 * j.n * j.n * j.n;
         sc.rec([=]() {
+            if (ea) (void)hipEventRecord(ea, st);
             if (nbase <= 32)
                 hipLaunchKernelGGL(k_gauss_jordan_8, dim3(nj), dim3(64), 0, st, dj);
             else if (nbase <= 64)
                 hipLaunchKernelGGL(k_gauss_jordan_16, dim3(nj), dim3(256), 0, st, dj);
             else
                 hipLaunchKernelGGL(k_gauss_jordan_32, dim3(nj), dim3(1024), 0, st, dj);
+            if (eb) (void)hipEventRecord(eb, st);
             return hipGetLastError();
         });
     }
@@ -1874,9 +1921,11 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
     if (opts->leaf < 4 || !(opts->proxy_ratio > 1.0) || opts->proxy_points < 8 ||
         !(opts->id_tol > 0.0 && opts->id_tol < 1.0) || !std::isfinite(opts->proxy_ratio) ||
         opts->sketch < -1 || opts->sketch > (int64_t{1} << 20) ||
-        !(opts->max_rank_ratio == -1.0 || (opts->max_rank_ratio >= 0.0 && opts->max_rank_ratio <= 1.0)))
+        !(opts->max_rank_ratio == -1.0 || (opts->max_rank_ratio >= 0.0 && opts->max_rank_ratio <= 1.0)) ||
+        opts->kernel_timing < 0 || opts->kernel_timing > 1)
         return fail(BM_EINVAL, "bm_hss_build: need leaf >= 4, proxy_ratio > 1, proxy_points >= 8, "
-                               "0 < id_tol < 1, sketch -1 or 0..2^20, max_rank_ratio -1 or in [0, 1]");
+                               "0 < id_tol < 1, sketch -1 or 0..2^20, max_rank_ratio -1 or in [0, 1], "
+                               "kernel_timing 0 or 1");
     if (p->g->n > (int64_t{1} << 30)) return fail(BM_EINVAL, "bm_hss_build: N too large");
     const auto t0 = std::chrono::steady_clock::now();
     bm_hss* h = new (std::nothrow) bm_hss;
@@ -1888,10 +1937,26 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
     if (h->opts.max_rank_ratio == -1.0) h->opts.max_rank_ratio = tuned::kStopRankRatio;
     h->N = p->g->n;
     int rc;
-    try {
-        rc = build_impl(h, stream);
-    } catch (const std::bad_alloc&) {
-        rc = fail(BM_ENOMEM, "bm_hss_build: host allocation");
+    {
+        KernelTimes kt;
+        struct Guard {
+            ~Guard() { g_ktimes = nullptr; }
+        } guard;
+        g_ktimes = opts->kernel_timing ? &kt : nullptr;
+        try {
+            rc = build_impl(h, stream);
+        } catch (const std::bad_alloc&) {
+            rc = fail(BM_ENOMEM, "bm_hss_build: host allocation");
+        }
+        // build_impl returns after the whole build has completed
+        if (rc == BM_OK && opts->kernel_timing) {
+            h->stats.gemm_launches = static_cast<int64_t>(kt.gemm.size());
+            h->stats.gemm_flops = kt.gemm_flops;
+            h->stats.seconds_gemm = KernelTimes::seconds(kt.gemm);
+            h->stats.inv_launches = static_cast<int64_t>(kt.inv.size());
+            h->stats.inv_flops = kt.inv_flops;
+            h->stats.seconds_inv = KernelTimes::seconds(kt.inv);
+        }
     }
     if (rc != BM_OK) {
         (void)hipStreamSynchronize(stream);
