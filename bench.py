@@ -232,7 +232,7 @@ def run_batch(args):
     p = bm.bm_problem_create_bodies(g, boc, media)
     n = g.n
     opts = dict(leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=args.sketch,
-                proxy_adapt=bool(args.proxy_adapt))
+                proxy_adapt=bool(args.proxy_adapt), max_rank_ratio=args.max_rank_ratio)
     stream = torch.cuda.current_stream()
     b = torch.empty(2 * n, dtype=torch.complex128, device="cuda")
     x = torch.empty_like(b)
@@ -285,7 +285,8 @@ def run_batch(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{len(wls)} independent stars (batched, one forest)", "bodies": len(wls),
                    "n_nodes": n, "leaf": 64, "proxy_points": 64, "proxy_ratio": 1.5, "id_tol": 1e-10,
-                   "id": "cpqr" if args.sketch == 0 else f"gaussian sketch, unknowns+{args.sketch} rows",
+                   "id": "cpqr" if st["sketch"] == 0 else f"gaussian sketch, unknowns+{st['sketch']} rows",
+                   "max_rank_ratio": st["max_rank_ratio"],
                    "proxy_points_rule": "max(64, ceil(2 k R_p) + 32)" if args.proxy_adapt else "64"},
         "batch": {"entries": st["entries"], "iterations": st["compressed_levels"], "roots_total": st["root_size"],
                   "max_rank": st["max_rank"], "max_body_residual": max(res), "median_body_residual": float(np.median(res)),
@@ -611,24 +612,24 @@ def main():
     ap.add_argument("--per-curve", type=int, default=16384, help="large mode: nodes per star")
     ap.add_argument("--max-rank-ratio", type=float, default=None,
                     help="HSS: a body stops compressing once a level keeps more than this fraction of its "
-                         "unknowns (0: never; -1: the library's tuned value; default: -1 in hss and adjoint "
-                         "modes, 0.8 in large mode, 0 otherwise)")
+                         "unknowns (0: never; -1: the library's tuned value; default: -1 in hss, adjoint and "
+                         "batch modes, 0.8 in large mode, 0 otherwise)")
     ap.add_argument("--batch", type=int, default=256, help="batch mode: number of stars")
     ap.add_argument("--proxy-adapt", type=int, choices=[0, 1], default=1,
                     help="batch mode: proxy points per circle max(64, ceil(2 k R_p) + 32)")
     ap.add_argument("--sketch", type=int, default=None,
                     help="HSS: p > 0 runs the ID on a Gaussian sketch with unknowns + p rows (0: plain "
-                         "CPQR; -1: the library's tuned value; default: -1 in hss and adjoint modes, 128 "
-                         "in large mode, 0 otherwise)")
+                         "CPQR; -1: the library's tuned value; default: -1 in hss, adjoint and batch modes, "
+                         "128 in large mode, 0 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device once (a plain copy "
                          "kernel of known size, to scale HBM traffic counters)")
     args = ap.parse_args()
     if args.max_rank_ratio is None:
-        args.max_rank_ratio = {"hss": -1.0, "adjoint": -1.0, "large": 0.8}.get(args.mode, 0.0)
+        args.max_rank_ratio = {"hss": -1.0, "adjoint": -1.0, "batch": -1.0, "large": 0.8}.get(args.mode, 0.0)
     if args.sketch is None:
-        args.sketch = {"hss": -1, "adjoint": -1, "large": 128}.get(args.mode, 0)
+        args.sketch = {"hss": -1, "adjoint": -1, "batch": -1, "large": 128}.get(args.mode, 0)
     if args.gpus != 1:
         print("this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         return 2
