@@ -660,7 +660,8 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
 // return at once.
 hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, int32_t* dranks,
                     double tol, std::vector<int32_t>& ranks, hipEvent_t ev0, hipEvent_t ev1,
-                    int64_t* launches, int first_check, bool* fused_out) {
+                    int64_t* launches, int first_check, bool* fused_out,
+                    const std::function<hipError_t()>& before_wait) {
     const int nb = static_cast<int>(cj.size());
     int nmax = 0, kmax = 0;
     for (const CpqrJob& j : cj) {
@@ -704,6 +705,7 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
         hipLaunchKernelGGL(k_cpqr_finish, dim3(nb), dim3(kThreads), 0, sc.s, dcj);
         hipLaunchKernelGGL(k_cpqr_ranks, dim3(1), dim3(64), 0, sc.s, dcj, nb, dranks, active);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = before_wait()) != hipSuccess) return e;
         return hipMemcpyAsync(ranks.data(), dranks, nb * sizeof(int32_t), hipMemcpyDeviceToHost, sc.s);
     }
     const unsigned chunks = static_cast<unsigned>(ceil_div(std::max(nmax, 1), kThreads / 64));
@@ -722,6 +724,7 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
             default: hipLaunchKernelGGL(k_cpqr_step, grid, dim3(kThreads), 0, sc.s, dcj, k, tol); break;
         }
         ++*launches;
+        if (k == 0 && (e = before_wait()) != hipSuccess) return e;
         if (k >= first_check && (k - first_check) % 16 == 0 && k < kmax) {
             int32_t h_active = 1;
             hipLaunchKernelGGL(k_cpqr_ranks, dim3(1), dim3(64), 0, sc.s, dcj, nb, dranks, active);
@@ -911,6 +914,7 @@ AuxStreams& aux_streams() {
 struct PendingLevel {
     std::unique_ptr<Scratch> cmp, fac;
     hipEvent_t ready = nullptr, done = nullptr;
+    bool flushed = true;   // false while fac's recorded commands wait to be issued
 };
 
 struct Pipeline {
@@ -921,6 +925,7 @@ struct Pipeline {
     void reap(bool wait) {
         for (size_t i = 0; i < pending.size();) {
             PendingLevel& pl = pending[i];
+            if (!pl.flushed) { ++i; continue; }   // its done event is not even recorded yet
             bool fin = true;
             if (pl.done) {
                 const hipError_t q = wait ? hipEventSynchronize(pl.done) : hipEventQuery(pl.done);
@@ -1053,6 +1058,16 @@ int build_impl(bm_hss* h, hipStream_t s) {
     Pipeline pl(s);
     BM_HIP(aux_streams().get(&pl.s2));
     const hipStream_t s2 = pl.s2;
+    // a level's factorisation recorded but not yet issued (at most one)
+    Scratch* deferred_fac = nullptr;
+    const std::function<hipError_t()> flush_deferred = [&]() -> hipError_t {
+        if (!deferred_fac) return hipSuccess;
+        Scratch* f = deferred_fac;
+        deferred_fac = nullptr;
+        for (PendingLevel& q : pl.pending)
+            if (q.fac.get() == f) q.flushed = true;
+        return f->flush();
+    };
 
     std::vector<double2*> dhat;             // per iteration: Dhat of every kept box (k x k, packed)
     std::vector<std::vector<int64_t>> dhat_off;
@@ -1368,7 +1383,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
             for (int c = 0; c < nk; ++c) guess = std::max(guess, kn[c] / 2);
             if (!h->level_info.empty()) guess = h->level_info.back().max_rank + h->level_info.back().max_rank / 4 + 8;
             bool fused = false;
-            e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks, c0, c1, &cpqr_launches, static_cast<int>(guess), &fused);
+            e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks, c0, c1, &cpqr_launches, static_cast<int>(guess), &fused,
+                         flush_deferred);
             cpqr_fused.push_back(fused);
         }
         if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -1590,7 +1606,12 @@ int build_impl(bm_hss* h, hipStream_t s) {
         if (e == hipSuccess) e = t_fac.stop(fs, ev);
         if (e == hipSuccess) {
             fs.rec([=]() { return hipEventRecord(done, s2); });
-            e = fs.flush();
+            // the launches of this level's factorisation are issued later, while the
+            // GPU compresses the next level (run_cpqr calls flush_deferred before it
+            // waits), so that the host's launch work overlaps that compression
+            e = flush_deferred();
+            pl.pending.back().flushed = false;
+            deferred_fac = &fs;
         }
         if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: factor"); }
 
@@ -1626,8 +1647,11 @@ int build_impl(bm_hss* h, hipStream_t s) {
     const int compressed = static_cast<int>(h->lv.size());
 
     // ---- roots: every body's reduced system, generated and inverted in one batch
-    // on the second stream after the last compression
+    // on the second stream after the last compression (and after the last
+    // level's factorisation, whose Dhat blocks the roots take)
     {
+        const hipError_t ed = flush_deferred();
+        if (ed != hipSuccess) { cleanup(); return hip_fail(ed, "bm_hss_build: factor"); }
         hipEvent_t rready = nullptr;
         BM_HIP(hipEventCreateWithFlags(&rready, hipEventDisableTiming));
         const hipError_t er = hipEventRecord(rready, s);
