@@ -254,3 +254,25 @@ def test_hss_rejects_bad_options(gpu_lib):
     out = ctypes.c_void_p()
     assert B._LIB.bm_hss_build(p._h, ctypes.byref(opts), None, ctypes.byref(out)) == 1
     assert out.value is None
+
+
+def test_hss_kernel_timing_counts_launches(gpu_lib):
+    """opts.kernel_timing: every batched GEMM and Gauss-Jordan launch of the build
+    is event-timed; the counts, flops and times are positive, the solution is the
+    same as without timing, and the fields stay zero when timing is off."""
+    bm = gpu_lib
+    note("hss: per-launch kernel timing, star N=2048")
+    media = sc.media_from_index(50.0, 1.5)
+    p, nd = setup(bm, [sc.star(0.3, 5)], [2048], media)
+    b = bm.bm_rhs_plane_wave(p, 0.2)
+    plain = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
+    timed = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, kernel_timing=True)
+    s0, s1 = bm.bm_hss_stats(plain), bm.bm_hss_stats(timed)
+    note(f"  gemm {s1['gemm_launches']} launches {s1['seconds_gemm'] * 1e3:.3f} ms {s1['gemm_flops']:.3e} flops; "
+         f"inv {s1['inv_launches']} launches {s1['seconds_inv'] * 1e3:.3f} ms {s1['inv_flops']:.3e} flops")
+    for k in ("gemm_launches", "gemm_flops", "seconds_gemm", "inv_launches", "inv_flops", "seconds_inv"):
+        assert s0[k] == 0
+        assert s1[k] > 0
+    x0 = bm.bm_hss_solve(plain, b).cpu().numpy()
+    x1 = bm.bm_hss_solve(timed, b).cpu().numpy()
+    assert np.abs(x1 - x0).max() <= 1e-13 * np.abs(x0).max()
