@@ -47,7 +47,7 @@ def bodies_problem(bm, bodies):
     return p, parts, lo
 
 
-@pytest.mark.parametrize("sketch", [0, 128])
+@pytest.mark.parametrize("sketch", [0, 128, -1])   # -1: the tuned options (with the stop rule)
 def test_hss_solve_transpose_matches_dense(gpu_lib, sketch):
     """A^T x = b on a forest of three bodies (one too small to compress)."""
     import torch
@@ -57,7 +57,8 @@ def test_hss_solve_transpose_matches_dense(gpu_lib, sketch):
               ([sc.circle(1.0)], [96], sc.media_from_index(10.0, 2.0)),
               ([sc.star(0.2, 3), sc.circle(0.3, (3.0, 0.0))], [700, 200], sc.media_from_index(20.0, 1.8))]
     p, parts, lo = bodies_problem(bm, bodies)
-    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch)
+    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch,
+                        max_rank_ratio=-1.0 if sketch == -1 else 0.0)
     rng = np.random.default_rng(3)
     B = np.stack([cplx(rng, 2 * lo[-1]) for _ in range(2)])
     X = bm.bm_hss_solve_transpose(h, torch.from_numpy(B).cuda().contiguous()).cpu().numpy()

@@ -34,7 +34,22 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-SKETCH = [pytest.param(0, id="cpqr"), pytest.param(128, id="sketch128")]
+# plain CPQR, a Gaussian sketch with 128 extra rows, and the library's tuned
+# options (sketch -1 with stop ratio -1): small sketches put every box of the
+# lower levels in the whole-box CPQR kernel
+SKETCH = [pytest.param(0, id="cpqr"), pytest.param(128, id="sketch128"), pytest.param(-1, id="tuned")]
+
+
+def ratio_for(sketch):
+    return -1.0 if sketch == -1 else 0.0
+
+
+def check_fused(bm, h, sketch):
+    st = bm.bm_hss_stats(h)
+    if sketch == -1:
+        assert st["cpqr_fused_launches"] >= 1 and st["seconds_cpqr_fused"] > 0
+    elif sketch == 0:
+        assert st["cpqr_fused_launches"] == 0
 
 
 @pytest.mark.parametrize("sketch", SKETCH)
@@ -44,10 +59,12 @@ def test_hss_circle_plain_workload(gpu_lib, sketch):
     note(f"hss: circle N=512, k0=10, n=1.5, leaf 64, sketch={sketch}")
     wl = sc.circle_workload(512)
     p, nd = setup(bm, wl.curves, wl.sizes, wl.media)
-    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch)
+    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch,
+                        max_rank_ratio=ratio_for(sketch))
     st = bm.bm_hss_stats(h)
     note(f"  stats {st}")
     assert st["compressed_levels"] >= 1
+    check_fused(bm, h, sketch)
     b = bm.bm_rhs_plane_wave(p, 0.0)
     x = bm.bm_hss_solve(h, b).cpu().numpy()
     ref = wsbm.solve_dense(wsbm.assemble_dense(nd, wl.media), wsbm.rhs_plane_wave(nd, wl.media, 0.0))
@@ -66,8 +83,10 @@ def test_hss_star_multiple_rhs_in_place(gpu_lib, sketch):
     note(f"hss: star N=2048, k0=50, n=1.5, 3 right-hand sides, x aliases b, sketch={sketch}")
     media = sc.media_from_index(50.0, 1.5)
     p, nd = setup(bm, [sc.star(0.3, 5)], [2048], media)
-    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch)
+    h = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch,
+                        max_rank_ratio=ratio_for(sketch))
     note(f"  stats {bm.bm_hss_stats(h)}")
+    check_fused(bm, h, sketch)
     angles = [0.0, 1.1, 4.0]
     B = torch.stack([bm.bm_rhs_plane_wave(p, a) for a in angles]).contiguous()
     Bh = B.cpu().numpy()
@@ -86,8 +105,10 @@ def test_hss_two_scatterers_ragged_sizes(gpu_lib, sketch):
     note(f"hss: two stars N=601+423, k0=20, n=2, sketch={sketch}")
     media = sc.media_from_index(20.0, 2.0)
     p, nd = setup(bm, [sc.star(0.2, 4), sc.star(0.25, 3, 1.0, (3.0, 0.5))], [601, 423], media)
-    h = bm.bm_hss_build(p, leaf=40, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch)
+    h = bm.bm_hss_build(p, leaf=40, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=sketch,
+                        max_rank_ratio=ratio_for(sketch))
     note(f"  stats {bm.bm_hss_stats(h)}")
+    check_fused(bm, h, sketch)
     b = bm.bm_rhs_plane_wave(p, 0.3)
     x = bm.bm_hss_solve(h, b).cpu().numpy()
     ref = wsbm.solve_dense(wsbm.assemble_dense(nd, media), wsbm.rhs_plane_wave(nd, media, 0.3))
