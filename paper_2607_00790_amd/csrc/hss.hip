@@ -1445,12 +1445,24 @@ int build_impl(bm_hss* h, hipStream_t s) {
         int64_t* dtoff;
         if (e == hipSuccess) e = sc.upload(&dtoff, std::vector<int64_t>(nkoff.begin(), nkoff.end() - 1));
         if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: T"); }
-        int64_t cmax = 1;
-        for (int c = 0; c < nk; ++c) cmax = std::max(cmax, kn[c] - k[c]);
+        int64_t cmax = 1, kmax = 0;
+        for (int c = 0; c < nk; ++c) {
+            cmax = std::max(cmax, kn[c] - k[c]);
+            kmax = std::max(kmax, k[c]);
+        }
         {
+            // rows per lane of the column-oriented substitution; the row-oriented
+            // kernel takes ranks beyond 256
+            const int rpl = kmax <= 64 ? 1 : kmax <= 128 ? 2 : kmax <= 256 ? 4 : 0;
             const unsigned cx = static_cast<unsigned>(ceil_div(cmax, kThreads / 64));
             sc.rec([=]() {
-                hipLaunchKernelGGL(k_interp, dim3(cx, nk), dim3(kThreads), 0, s, dcj, dranks, dtoff, T);
+                const dim3 g(cx, nk), b(kThreads);
+                switch (rpl) {
+                    case 1: hipLaunchKernelGGL(k_interp_wave<1>, g, b, 0, s, dcj, dranks, dtoff, T); break;
+                    case 2: hipLaunchKernelGGL(k_interp_wave<2>, g, b, 0, s, dcj, dranks, dtoff, T); break;
+                    case 4: hipLaunchKernelGGL(k_interp_wave<4>, g, b, 0, s, dcj, dranks, dtoff, T); break;
+                    default: hipLaunchKernelGGL(k_interp, g, b, 0, s, dcj, dranks, dtoff, T); break;
+                }
                 return hipGetLastError();
             });
         }

@@ -114,6 +114,10 @@ __global__ void k_gen_jobs(const GenJob* jobs, const int64_t* tile_off, int njob
                            const BesselTable* tab);
 __global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
                          double2* Tbuf);
+// the same for ranks k <= 64 RPL (RPL = 1, 2, 4), logically pivoted jobs only
+template <int RPL>
+__global__ void k_interp_wave(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
+                              double2* Tbuf);
 // in-place inverse of n x n blocks, n <= 32 / 64 / 128; blockDim 64 / 256 / 1024
 __global__ void k_gauss_jordan_8(const InvJob* jobs);
 __global__ void k_gauss_jordan_16(const InvJob* jobs);

@@ -10,7 +10,8 @@
 //   k_cpqr_*         column-pivoted Householder QR of M_b^T for all boxes of a
 //                    level, one launch per elimination step, with the relative
 //                    rank rule |R_kk| > tol |R_00|
-//   k_interp         T_b = [I; (R11^-1 R12)^T] in pivoted order
+//   k_interp_wave    T_b = [I; (R11^-1 R12)^T] in pivoted order, column-oriented
+//   k_interp         the same, row-oriented, for ranks beyond 256
 //   k_gauss_jordan_* batched in-place inverse with partial row pivoting, the
 //                    block held in registers (4 x 4 complex tile per thread)
 //   k_gemm           batched strided complex GEMM
@@ -52,6 +53,13 @@ __device__ __forceinline__ T gld(const T* p) {
 template <class T>
 __device__ __forceinline__ void gst(T* p, T v) {
     *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// x from lane l (l wave-uniform).
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -650,9 +658,9 @@ k_interp(const CpqrJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
         for (int i = threadIdx.x; i < k; i += kThreads)
             gstore2(T + static_cast<int64_t>(gld(jb.perm + i)) * k + i, make_double2(1.0, 0.0));
     const int c = blockIdx.x * nw + wid;
+    const bool logical = jb.used != nullptr;
     if (c >= n - k) return;
     // column of X holding pivot l: l after physical swaps, perm[l] with logical pivoting
-    const bool logical = jb.used != nullptr;
     const int pc = gld(jb.perm + k + c);
     const double2* rc = X + static_cast<int64_t>(logical ? pc : k + c) * m;
     double2* z = T + static_cast<int64_t>(pc) * k;
@@ -674,6 +682,85 @@ k_interp(const CpqrJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
             gstore2(z + i, make_double2((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd));
     }
 }
+
+// ---------------------------------------------------------------------------
+// T_b as k_interp, for ranks k <= 64 RPL: one wave per column c of
+// Z = R11^-1 R12, lane j keeps rows j + 64 s (s < RPL) of the right-hand side
+// R12[:, c] in registers and overwrites each with z once it is solved.  The
+// substitution is column-oriented: for l = k-1 .. 0 the owner lane forms
+// z_l = y_l / d_l, a lane broadcast hands it to the wave, and every row i < l
+// subtracts R11[i][l] z_l.  Column l of R11 is one contiguous read of X,
+// independent of the recurrence, so the unrolled loop keeps the reads of
+// several columns in flight while the dependent chain per step is a complex
+// product, the broadcast and one complex FMA.  Needs logical pivoting.
+template <int RPL>
+__global__ void __launch_bounds__(kThreads)
+k_interp_wave(const CpqrJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
+              const int64_t* __restrict__ t_off, double2* __restrict__ Tbuf) {
+    const CpqrJob jb = jobs[blockIdx.y];
+    const int n = jb.n, m = jb.m, k = ranks[blockIdx.y];
+    double2* T = Tbuf + t_off[blockIdx.y];
+    const double2* X = jb.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kThreads / 64;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < k; i += kThreads)
+            gstore2(T + static_cast<int64_t>(gld(jb.perm + i)) * k + i, make_double2(1.0, 0.0));
+    const int c = blockIdx.x * nw + wid;
+    if (c >= n - k) return;
+    const int pc = gld(jb.perm + k + c);
+    const double2 zero = make_double2(0.0, 0.0);
+    double2 y[RPL], dinv[RPL];
+    int pv[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int i = lane + 64 * s;
+        const bool in = i < k;
+        y[s] = in ? gload2(X + static_cast<int64_t>(pc) * m + i) : zero;
+        const double2 d = in ? gload2(jb.rdiag + i) : make_double2(1.0, 0.0);
+        const double id = 1.0 / cabs2(d);
+        dinv[s] = make_double2(d.x * id, -d.y * id);
+        pv[s] = in ? gld(jb.perm + i) : 0;
+    }
+    // The reads of U steps are issued before their recurrence (the compiler
+    // does not unroll a loop around lane broadcasts by itself).
+    constexpr int U = RPL == 4 ? 4 : 8;
+#pragma unroll
+    for (int s = RPL - 1; s >= 0; --s) {
+        for (int j0 = min(63, k - 1 - 64 * s); j0 >= 0; j0 -= U) {   // wave-uniform
+            double2 r[U][RPL];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 - u, l = 64 * s + j;
+                const double2* xc = X + static_cast<int64_t>(__builtin_amdgcn_readlane(pv[s], j < 0 ? 0 : j)) * m;
+#pragma unroll
+                for (int t = 0; t <= s; ++t) {
+                    const int i = lane + 64 * t;
+                    r[u][t] = (j >= 0 && i < l) ? gload2(xc + i) : zero;   // rows i < l < k <= m only
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 - u;
+                if (j < 0) break;
+                const double2 z = cmul(y[s], dinv[s]);
+                const double2 zl = make_double2(readlane_d(z.x, j), readlane_d(z.y, j));
+                if (lane == j) y[s] = zl;
+                const double2 nz = make_double2(-zl.x, -zl.y);
+#pragma unroll
+                for (int t = 0; t <= s; ++t) y[t] = cfma(r[u][t], nz, y[t]);   // r is 0 for rows >= l
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int i = lane + 64 * s;
+        if (i < k) gstore2(T + static_cast<int64_t>(pc) * k + i, y[s]);
+    }
+}
+
+template __global__ void k_interp_wave<1>(const CpqrJob*, const int32_t*, const int64_t*, double2*);
+template __global__ void k_interp_wave<2>(const CpqrJob*, const int32_t*, const int64_t*, double2*);
+template __global__ void k_interp_wave<4>(const CpqrJob*, const int32_t*, const int64_t*, double2*);
 
 // ---------------------------------------------------------------------------
 // Batched in-place inverse by Gauss-Jordan elimination with partial row
