@@ -544,23 +544,55 @@ hipError_t launch_sketch(Scratch& sc, const std::vector<SketchJob>& jobs, const 
         [&](const std::vector<SketchJob>& g) { return launch_sketch_group(sc, g, omega, ldo); });
 }
 
-hipError_t launch_sketch_group(Scratch& sc, const std::vector<SketchJob>& jobs, const double* omega,
+// Workgroups a sketch launch should reach before its K range is split: four
+// per compute unit, so that the waves of one unit hide each other's latency.
+constexpr int64_t kSketchMinBlocks = 1024;
+
+// The jobs of one group are consecutive in Y (the caller lays Y out in job
+// order), so one partial buffer of the group's Y extent serves every slice.
+hipError_t launch_sketch_group(Scratch& sc, const std::vector<SketchJob>& jobs_in, const double* omega,
                                int64_t ldo) {
-    if (jobs.empty()) return hipSuccess;
+    if (jobs_in.empty()) return hipSuccess;
+    std::vector<SketchJob> jobs = jobs_in;
+    int64_t tiles = 0, mmax = 0;
+    double2* ylo = nullptr;
+    double2* yhi = nullptr;
+    for (const SketchJob& j : jobs) {
+        tiles += ceil_div(j.l, 64) * ceil_div(j.n, 64);
+        mmax = std::max<int64_t>(mmax, j.m);
+        double2* y1 = j.y + static_cast<int64_t>(j.l) * j.n;
+        if (ylo == nullptr || j.y < ylo) ylo = j.y;
+        if (yhi == nullptr || y1 > yhi) yhi = y1;
+    }
+    if (tiles == 0) return hipSuccess;
+    // split K while the tiles alone give fewer than kSketchMinBlocks workgroups,
+    // keeping at least 64 rows of X per slice
+    const int ks = static_cast<int>(std::max<int64_t>(
+        1, std::min<int64_t>({kSketchMinBlocks / tiles, ceil_div(mmax, 64), 8})));
+    const int64_t pstride = yhi - ylo;
+    double2* part = nullptr;
+    hipError_t e = hipSuccess;
+    if (ks > 1) {
+        if ((e = sc.alloc(&part, static_cast<size_t>(ks) * pstride)) != hipSuccess) return e;
+        for (SketchJob& j : jobs) j.part = part + (j.y - ylo);
+    }
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
-        toff[j + 1] = toff[j] + ceil_div(jobs[j].l, 64) * ceil_div(jobs[j].n, 64);
-    if (toff.back() == 0) return hipSuccess;
+        toff[j + 1] = toff[j] + ceil_div(jobs[j].l, 64) * ceil_div(jobs[j].n, 64) * ks;
     SketchJob* dj;
     int64_t* dt;
-    hipError_t e = sc.upload(&dj, jobs);
+    e = sc.upload(&dj, jobs);
     if (e == hipSuccess) e = sc.upload(&dt, toff);
     if (e != hipSuccess) return e;
     const unsigned grid = static_cast<unsigned>(toff.back());
     const int nj = static_cast<int>(jobs.size());
     hipStream_t st = sc.s;
     sc.rec([=]() {
-        hipLaunchKernelGGL(k_sketch, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, omega, ldo);
+        hipLaunchKernelGGL(k_sketch, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, omega, ldo, ks, pstride);
+        if (ks > 1) {
+            const unsigned g2 = static_cast<unsigned>(std::min<int64_t>(ceil_div(pstride, kThreads), 4096));
+            hipLaunchKernelGGL(k_sum_partials, dim3(g2), dim3(kThreads), 0, st, part, ks, pstride, pstride, ylo);
+        }
         return hipGetLastError();
     });
     return hipSuccess;
@@ -1334,7 +1366,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
                 if (e == hipSuccess) e = sc.alloc(&Y_sk, yo[nk]);
                 std::vector<SketchJob> sj(nk);
                 for (int c = 0; c < nk; ++c)
-                    sj[c] = SketchJob{M + mo[c], Y_sk + yo[c], static_cast<int32_t>(km[c]),
+                    sj[c] = SketchJob{M + mo[c], Y_sk + yo[c], nullptr, static_cast<int32_t>(km[c]),
                                       static_cast<int32_t>(kn[c]), static_cast<int32_t>(idm[c])};
                 if (e == hipSuccess && (e = t_cmp.start(sc, ev)) == hipSuccess) {
                     e = launch_sketch(sc, sj, omega, ldo);

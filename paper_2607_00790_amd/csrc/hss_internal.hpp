@@ -90,6 +90,7 @@ struct GemmJob {
 struct SketchJob {
     const double2* x;
     double2* y;
+    double2* part;   // split-K: partial product s of this job at part + s * (partial stride)
     int32_t m, n, l;
 };
 
@@ -145,9 +146,13 @@ __global__ void k_gemm(const GemmJob* jobs, const int64_t* tile_off, int njobs);
 constexpr int kGemvMaxN = 4;
 constexpr int kGemvRows = kThreads / 64;
 __global__ void k_gemv(const GemmJob* jobs, const int64_t* tile_off, int njobs);
-// 64 x 64 tiles of Y per workgroup (kThreads threads)
+// 64 x 64 tiles of Y per workgroup (kThreads threads), the sum over the rows
+// of X split into ksplit slices (ksplit > 1: partial products, summed by
+// k_sum_partials)
 __global__ void k_sketch(const SketchJob* jobs, const int64_t* tile_off, int njobs,
-                         const double* omega, int64_t ldo);
+                         const double* omega, int64_t ldo, int ksplit, int64_t pstride);
+// y[e] = sum over s < ns of part[s * stride + e], e < len
+__global__ void k_sum_partials(const double2* part, int ns, int64_t stride, int64_t len, double2* y);
 __global__ void k_copy_blocks(const CopyJob* jobs);
 
 }  // namespace hss

@@ -945,9 +945,13 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan_32(const InvJob* __restri
 // Workgroup: a 64 x 64 tile of one job's Y, K in steps of 16 through LDS;
 // thread t owns rows r0 + (t % 16) + 16a and columns c0 + (t / 16) + 16b
 // (a, b < 4), so consecutive threads write consecutive rows of a column.
+// With ksplit > 1 the K range is cut into ksplit slices of whole 16-row steps,
+// one workgroup per (tile, slice), and slice s writes its partial tile to
+// part + s * pstride (the levels with few tiles, which would otherwise leave
+// most compute units idle); k_sum_partials adds the slices in a fixed order.
 __global__ void __launch_bounds__(kThreads)
 k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
-         const double* __restrict__ omega, int64_t ldo) {
+         const double* __restrict__ omega, int64_t ldo, int ksplit, int64_t pstride) {
     constexpr int T = 64, KS = 16;
     __shared__ double Os[KS][T];
     __shared__ double2 Xs[KS][T];
@@ -958,7 +962,11 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
         if (tile_off[mid] <= tile) lo = mid; else hi = mid;
     }
     const SketchJob jb = jobs[lo];
-    const int64_t local = tile - tile_off[lo];
+    const int64_t local_s = tile - tile_off[lo];
+    const int slice = static_cast<int>(local_s % ksplit);
+    const int64_t local = local_s / ksplit;
+    const int kc = ((jb.m + ksplit - 1) / ksplit + KS - 1) / KS * KS;
+    const int kb = slice * kc, ke = min(jb.m, kb + kc);   // rows [kb, ke) of X, empty for trailing slices
     const int tiles_c = (jb.n + T - 1) / T;
     const int r0 = static_cast<int>(local / tiles_c) * T;
     const int c0 = static_cast<int>(local % tiles_c) * T;
@@ -968,20 +976,20 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    for (int l0 = 0; l0 < jb.m; l0 += KS) {
+    for (int l0 = kb; l0 < ke; l0 += KS) {
         // Omega tile (64 rows x 16): thread loads rows tid/16 + 16q, column tid%16
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int rr = tid / 16 + 16 * q, kk = tid % 16;
             const int r = r0 + rr, l = l0 + kk;
-            Os[kk][rr] = (r < jb.l && l < jb.m) ? omega[static_cast<int64_t>(r) * ldo + l] : 0.0;
+            Os[kk][rr] = (r < jb.l && l < ke) ? omega[static_cast<int64_t>(r) * ldo + l] : 0.0;
         }
         // X tile (16 x 64 columns): 16 consecutive threads read one column's 16 rows
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int jj = tid / 16 + 16 * q, kk = tid % 16;
             const int j = c0 + jj, l = l0 + kk;
-            Xs[kk][jj] = (j < jb.n && l < jb.m) ? gload2(jb.x + static_cast<int64_t>(j) * jb.m + l)
+            Xs[kk][jj] = (j < jb.n && l < ke) ? gload2(jb.x + static_cast<int64_t>(j) * jb.m + l)
                                                 : make_double2(0.0, 0.0);
         }
         __syncthreads();
@@ -1003,6 +1011,7 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
         }
         __syncthreads();
     }
+    double2* dst = ksplit == 1 ? jb.y : jb.part + slice * pstride;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int j = c0 + tc + 16 * b;
@@ -1010,8 +1019,22 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int r = r0 + tr + 16 * a;
-            if (r < jb.l) gstore2(jb.y + static_cast<int64_t>(j) * jb.l + r, acc[a][b]);
+            if (r < jb.l) gstore2(dst + static_cast<int64_t>(j) * jb.l + r, acc[a][b]);
         }
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_sum_partials(const double2* __restrict__ part, int ns, int64_t stride, int64_t len, double2* __restrict__ y) {
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; e < len;
+         e += static_cast<int64_t>(gridDim.x) * kThreads) {
+        double2 v = gload2(part + e);
+        for (int s = 1; s < ns; ++s) {
+            const double2 w = gload2(part + s * stride + e);
+            v.x += w.x;
+            v.y += w.y;
+        }
+        gstore2(y + e, v);
     }
 }
 
