@@ -46,10 +46,11 @@ MEASURED_TRAFFIC = {
     # one sweep: one launch
     "k_dense": (2.0 * 48835.4 + 16861700.0) * 1024,
     # two HSS builds with the tuned options (gaussian sketch, unknowns + 8 rows; stop
-    # ratio 0.6): 336 launches of k_gemm, 102 of k_gauss_jordan_16, 234 of k_cpqr_step_reg<4>
-    ("k_gemm", 8, 0.6): (2.0 * 3096210.0 + 1120110.0) * 1024 / 336,
-    ("k_gauss_jordan", 8, 0.6): (2.0 * 84847.2 + 158339.0) * 1024 / 102,
-    ("k_cpqr_step_reg", 8, 0.6): (2.0 * 326855.0 + 516938.0) * 1024 / 234,
+    # ratio 0.6; the root inverted by panels): 160 launches of k_gemm, 86 of
+    # k_gauss_jordan_16, 234 of k_cpqr_step_reg<4>
+    ("k_gemm", 8, 0.6): (2.0 * 2944907.9375 + 1143744.9375) * 1024 / 160,
+    ("k_gauss_jordan", 8, 0.6): (2.0 * 85100.5 + 159046.0) * 1024 / 86,
+    ("k_cpqr_step_reg", 8, 0.6): (2.0 * 328911.125 + 516937.875) * 1024 / 234,
 }
 
 

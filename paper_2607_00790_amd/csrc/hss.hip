@@ -338,6 +338,19 @@ hipError_t blas_handle(rocblas_handle* out) {
     return hipSuccess;
 }
 
+// How the dense root of a one-body problem with at most kRootPanelsMax
+// unknowns is inverted: by panels of inv_base() columns (block Gauss-Jordan,
+// the default) or by the Schur recursion used for the batched blocks.  BMHSS_ROOT_PANELS=0 selects the
+// recursion (for comparison).
+constexpr int64_t kRootPanelsMax = 4096;
+bool root_panels() {
+    static const bool v = [] {
+        const char* e = std::getenv("BMHSS_ROOT_PANELS");
+        return !(e && std::atoi(e) == 0);
+    }();
+    return v;
+}
+
 // Tuned parameters (tuned_params.h), overridable through the environment for
 // the tuner itself: BMHSS_TUNE_INV_BASE (32, 64 or 128) and
 // BMHSS_TUNE_BLAS_FLOPS.
@@ -682,6 +695,54 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
     if ((e = launch_inverse(sc, Sj)) != hipSuccess) return e;
     if ((e = launch_gemm(sc, g3)) != hipSuccess) return e;
     return launch_gemm(sc, g4);
+}
+
+// Inversion of one large matrix (the dense root of a one-body problem) by
+// block Gauss-Jordan elimination over panels of b = inv_base() columns.  Per
+// panel p the diagonal block is inverted in place by the pivoted Gauss-Jordan
+// kernel, and with P = A_pp^-1 the rest of the matrix follows from one
+// product of rank b:
+//   A_pc <- P A_pc,   A_ic <- A_ic - A_ip P A_pc,   A_ip <- -A_ip P   (i, c != p).
+// As in the Schur recursion, rows are pivoted within the diagonal blocks only
+// (the same elimination, in another order); the serial chain is one
+// Gauss-Jordan launch and two products per panel instead of a deep recursion
+// of small products.  The products read copies: L = A[:, p] with its block p
+// cleared, Pt = P, and R = Pt A[p, :] taken after A_pp is set to I (so that
+// R_pp = P); A[:, p] is cleared off the diagonal block, A -= L R, and R
+// becomes row block p.
+hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
+    const int64_t K = j.n, ld = j.ld, b0 = std::min<int64_t>(inv_base(), K);
+    const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
+    double2 *L, *Pt, *R, *zero, *eye;
+    hipError_t e = hipSuccess;
+    if ((e = sc.alloc(&L, K * b0)) != hipSuccess) return e;
+    if ((e = sc.alloc(&Pt, b0 * b0)) != hipSuccess) return e;
+    if ((e = sc.alloc(&R, b0 * K)) != hipSuccess) return e;
+    {
+        std::vector<double2> z(1, make_double2(0.0, 0.0)), id(static_cast<size_t>(b0 * b0), make_double2(0.0, 0.0));
+        for (int64_t q = 0; q < b0; ++q) id[q * b0 + q] = one;
+        if ((e = sc.upload(&zero, z)) != hipSuccess) return e;
+        if ((e = sc.upload(&eye, id)) != hipSuccess) return e;
+    }
+    auto cp = [](const double2* src, double2* dst, int64_t srs, int64_t scs, int64_t drs, int64_t dcs,
+                 int64_t rows, int64_t cols) {
+        return CopyJob{src, dst, srs, scs, drs, dcs, static_cast<int32_t>(rows), static_cast<int32_t>(cols)};
+    };
+    for (int64_t o = 0; o < K; o += b0) {
+        const int64_t b = std::min(b0, K - o);
+        double2* App = j.a + o * ld + o;
+        if ((e = launch_inverse(sc, {InvJob{App, j.status, ld, static_cast<int32_t>(b)}})) != hipSuccess) return e;
+        if ((e = launch_copy(sc, {cp(j.a + o, L, ld, 1, b, 1, K, b), cp(App, Pt, ld, 1, b, 1, b, b)})) != hipSuccess)
+            return e;
+        std::vector<CopyJob> clr{cp(eye, App, b0, 1, ld, 1, b, b), cp(zero, L + o * b, 0, 0, b, 1, b, b)};
+        if (o > 0) clr.push_back(cp(zero, j.a + o, 0, 0, ld, 1, o, b));
+        if (o + b < K) clr.push_back(cp(zero, j.a + (o + b) * ld + o, 0, 0, ld, 1, K - o - b, b));
+        if ((e = launch_copy(sc, clr)) != hipSuccess) return e;
+        if ((e = launch_gemm(sc, {gemm(Pt, b, 1, j.a + o * ld, ld, 1, R, K, 1, b, K, b)})) != hipSuccess) return e;
+        if ((e = launch_gemm(sc, {gemm(L, b, 1, R, K, 1, j.a, ld, 1, K, K, b, mone, one)})) != hipSuccess) return e;
+        if ((e = launch_copy(sc, {cp(R, j.a + o * ld, K, 1, ld, 1, b, K)})) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Column-pivoted QR of every box of a level, step-wise over many workgroups
@@ -1734,7 +1795,16 @@ int build_impl(bm_hss* h, hipStream_t s) {
             std::vector<InvJob> inv;
             for (size_t q = 0; q < roots.size(); ++q)
                 inv.push_back(InvJob{h->Rinv + roots[q].r_off, st + q, roots[q].K, static_cast<int32_t>(roots[q].K)});
-            e = launch_inverse(sc, inv);
+            // one root of moderate size: panels (a serial chain of short launches
+            // either way, panels make it shorter); several roots (a forest): the
+            // recursion, batched over the roots; very large roots: the
+            // recursion, whose large square products run near the FP64 peak
+            // where the panels' rank-b updates would stream the whole matrix
+            // through memory once per panel
+            if (inv.size() == 1 && inv[0].n > inv_base() && inv[0].n <= kRootPanelsMax && root_panels())
+                e = launch_inverse_panels(sc, inv[0]);
+            else
+                e = launch_inverse(sc, inv);
             if (e == hipSuccess) e = t_fac.stop(sc, ev);
         }
         if (e == hipSuccess) e = sc.flush();
