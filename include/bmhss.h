@@ -140,7 +140,11 @@ int bm_far_field(const bm_problem* p, const double* phi, const double* angles, i
  * sketch); skeletons are sets of unknowns shared by rows and columns.
  * The factorisation is the Martinsson-Rokhlin recursion: per box
  * Dhat = (T^T D^-1 T)^-1, E = D^-1 T Dhat, F^T = Dhat T^T D^-1,
- * G = D^-1 - D^-1 T Dhat T^T D^-1, and a dense LU at the root. */
+ * G = D^-1 - D^-1 T Dhat T^T D^-1, and the inverse of the dense root
+ * system.  Inverses pivot rows inside diagonal blocks of at most 64 only:
+ * Gauss-Jordan elimination up to that size, above it a 2 x 2 Schur-complement
+ * recursion, except for the single root of a one-body problem of at most 4096
+ * unknowns, which is inverted by block Gauss-Jordan over 64-column panels. */
 typedef struct {
     int64_t leaf;          /* target leaf size in nodes (>= 4) */
     double proxy_ratio;    /* proxy circle radius / box radius (> 1) */
