@@ -199,6 +199,34 @@ def solve_dense(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     return scipy.linalg.lu_solve((lu, piv), b, check_finite=False)
 
 
+def solve_dense_inplace(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """The same solve for a matrix too large to copy: A (C-ordered) is
+    destroyed.  Its memory, read in Fortran order, is A^T, which LAPACK
+    factors in place (P L U = A^T); the solve then applies the transposed
+    factors (zgetrs with trans = 'T'), i.e. solves A phi = b."""
+    assert A.flags.c_contiguous and A.shape[0] == A.shape[1]
+    lu, piv = scipy.linalg.lu_factor(A.T, overwrite_a=True, check_finite=False)
+    return scipy.linalg.lu_solve((lu, piv), b, trans=1, check_finite=False)
+
+
+def assemble_dense_parallel(nodes: Nodes, media, mapper=map, chunk: int = 64) -> np.ndarray:
+    """assemble_dense for large N: the rows are generated in chunks of `chunk`
+    nodes by assemble_rows (mapper, e.g. a process pool's imap, may run the
+    chunks in parallel; it must return them in order) and copied into one
+    preallocated matrix."""
+    n = nodes.size
+    A = np.empty((2 * n, 2 * n), dtype=np.complex128)
+    jobs = [(nodes, media, np.arange(s, min(n, s + chunk))) for s in range(0, n, chunk)]
+    for (_, _, rows), blk in zip(jobs, mapper(_rows_job, jobs)):
+        A[2 * rows[0]:2 * rows[-1] + 2] = blk
+    return A
+
+
+def _rows_job(args):
+    nodes, media, rows = args
+    return assemble_rows(nodes, media, rows)
+
+
 def far_field(nodes: Nodes, media, phi: np.ndarray, angles) -> np.ndarray:
     """Far-field pattern u_inf(xhat) of the scattered field, defined by
     u_sc(x) ~ exp(i k0 |x|)/sqrt(|x|) u_inf(xhat), from the exterior integral

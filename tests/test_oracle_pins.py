@@ -223,3 +223,19 @@ def test_brute_force_near_diagonal_cancellation():
     B = brute.system_blocks(nd, media, rows, cols)
     scale = np.abs(B).max(axis=(0, 2), keepdims=True)
     assert np.all(np.abs(A - B) <= 1e-11 * scale)
+
+
+def test_large_matrix_helpers_match_the_plain_assembly_and_solve():
+    """The chunked assembly and the in-place (transposed-factor) LU used for the
+    N = 16384 dense golden reproduce assemble_dense and solve_dense (Mie-pinned
+    above) on a small two-curve problem; a dropped row chunk or a solve with the
+    untransposed factors fails."""
+    media = sc.media_from_index(12.0, 1.4)
+    nd = nodes_for([sc.star(0.3, 5), sc.circle(0.5, (3.0, 0.5))], [150, 50])
+    A = wsbm.assemble_dense(nd, media)
+    Ap = wsbm.assemble_dense_parallel(nd, media, chunk=37)
+    assert np.array_equal(A, Ap)
+    b = wsbm.rhs_plane_wave(nd, media, 0.4)
+    x = wsbm.solve_dense(A, b)
+    y = wsbm.solve_dense_inplace(Ap, b)
+    assert np.linalg.norm(x - y) < 1e-12 * np.linalg.norm(x)
