@@ -120,6 +120,20 @@ int bm_assemble_proxy(const bm_problem* p, const int64_t* nodes, int64_t n, cons
  * generated on the fly and reduced. */
 int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t stream);
 
+/* bm_matvec for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bit for bit, but the block partial sums go
+ * to a fixed buffer of 16 MiB (2^21 doubles) that the library holds in device
+ * memory on every GPU it runs on until the process ends, instead of a buffer
+ * it allocates.  The buffer needs 4 N ceil(B / 2048) doubles, B the largest
+ * body in nodes (one body: N <= 32768); larger problems get BM_EINVAL
+ * (use bm_matvec).  Nothing is allocated and nothing needs clearing (every
+ * partial sum is written before it is read).  All calls on one GPU share the
+ * buffer: calls that overlap on one GPU (different streams, no ordering)
+ * race and give wrong results; calls ordered on one stream are safe.
+ * x, y: device, 2N complex, must not alias.  Asynchronous on `stream`. */
+int bm_matvec_noalloc(const bm_problem* p, const double* x, double* y, hipStream_t stream);
+
 /* Far field of the scattered field from a solution phi = (u_0, q_0, u_1, ...)
  * (device, 2N complex), at nang observation angles (device FP64); uinf (device,
  * nbodies * nang complex, body b's far field at uinf[b * nang + a], each body

@@ -19,6 +19,7 @@ from ._binding import (  # noqa: F401
     bm_geom_nodes,
     bm_geom_size,
     bm_matvec,
+    bm_matvec_noalloc,
     bm_problem_create,
     bm_problem_create_bodies,
     bm_rhs_plane_wave,

@@ -80,6 +80,7 @@ def load():
         "bm_assemble_proxy": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, ctypes.c_int, c_vp,
                                              c_i64, c_vp]),
         "bm_matvec": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp]),
+        "bm_matvec_noalloc": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp]),
         "bm_far_field": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]),
     }
     sig.update({
@@ -288,6 +289,15 @@ def bm_matvec(p: Problem, x, out=None, stream=None):
         out = torch.empty(2 * p.n, dtype=torch.complex128, device="cuda")
     _check(load().bm_matvec(p._h, _dev_ptr(x, torch.complex128, "x"),
                           _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
+    return out
+
+
+def bm_matvec_noalloc(p: Problem, x, out, stream=None):
+    """bm_matvec through the library's fixed device buffer (no allocation);
+    `out` must be given (2N complex128 device tensor)."""
+    torch = _torch()
+    _check(load().bm_matvec_noalloc(p._h, _dev_ptr(x, torch.complex128, "x"),
+                                    _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
     return out
 
 

@@ -15,6 +15,8 @@
 //    (a loop lets the compiler hoist them into vector registers, which drops
 //    the occupancy to one wave per SIMD).
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 
 #include "internal.hpp"
 
@@ -366,6 +368,38 @@ hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const i
 
 int64_t matvec_work_doubles(int64_t n, int64_t max_body) {
     return 4 * n * ((max_body + kThreads * kMvSources - 1) / (kThreads * kMvSources));
+}
+
+// Fixed device buffer of the allocation-free product: the block partial sums
+// of k_matvec_partial (every slot is written before k_matvec_reduce reads it,
+// so nothing needs clearing).  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels receive the address that
+// hipGetSymbolAddress gives for the current device, looked up once per device.
+__device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::unordered_map<int, double*> g_scratch_ptr;
+}  // namespace
+
+hipError_t noalloc_scratch(double** out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    double* ptr = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (ptr == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr.emplace(dev, ptr);
+    *out = ptr;
+    return hipSuccess;
 }
 
 hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* m,

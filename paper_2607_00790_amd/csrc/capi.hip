@@ -301,6 +301,24 @@ int bm_matvec(const bm_problem* p, const double* x, double* y, hipStream_t strea
     return BM_OK;
 }
 
+int bm_matvec_noalloc(const bm_problem* p, const double* x, double* y, hipStream_t stream) {
+    clear_error();
+    if (!p || !x || !y) return fail(BM_EINVAL, "bm_matvec_noalloc: null argument");
+    if (x == y) return fail(BM_EINVAL, "bm_matvec_noalloc: x and y must not alias");
+    int64_t max_body = 0;
+    for (int b = 0; b < p->nbodies; ++b) max_body = std::max(max_body, p->body_lo[b + 1] - p->body_lo[b]);
+    const int64_t n = p->g->n;
+    const int64_t need = matvec_work_doubles(n, max_body);
+    if (need > kNoAllocScratchDoubles)
+        return fail(BM_EINVAL, "bm_matvec_noalloc: needs " + std::to_string(need) +
+                                   " doubles of partial sums, above its fixed buffer of " +
+                                   std::to_string(kNoAllocScratchDoubles) + " (use bm_matvec)");
+    double* work = nullptr;
+    BM_HIP(noalloc_scratch(&work));
+    BM_HIP(launch_matvec(view(p), n, max_body, p->d_body_lo, p->d_media, p->media[0].tab, x, y, work, stream));
+    return BM_OK;
+}
+
 int bm_far_field(const bm_problem* p, const double* phi, const double* angles, int64_t nang,
                  double* uinf, hipStream_t stream) {
     clear_error();

@@ -99,6 +99,11 @@ hipError_t launch_matvec(const NodeView& v, int64_t n, int64_t max_body, const i
                          const Media* media, const BesselTable* tab, const double* x, double* y, double* work,
                          hipStream_t s);
 int64_t matvec_work_doubles(int64_t n, int64_t max_body);
+// Size of the fixed device buffer of bm_matvec_noalloc, in doubles (16 MiB):
+// enough for one body of up to 32768 nodes.
+constexpr int64_t kNoAllocScratchDoubles = int64_t{1} << 21;
+// Address of that buffer on the current device (looked up once per device).
+hipError_t noalloc_scratch(double** out);
 // far field of every body: uinf[b * nang + a]; body_lo = first node of each body
 hipError_t launch_far_field(const NodeView& v, int nbodies, const int64_t* body_lo, const Media* media,
                             const double* phi, const double* angles, int64_t nang, double* uinf,
