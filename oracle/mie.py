@@ -33,23 +33,32 @@ def _orders(media, a, extra=40):
     return np.arange(-mmax, mmax + 1)
 
 
-def coefficients(media, a=1.0):
-    """(m, c_m, b_m) for theta_inc = 0."""
+def coefficients(media, a=1.0, src=None):
+    """(m, c_m, b_m) for theta_inc = 0.  src = rho_s > a: instead of the plane
+    wave, the field of a point source at distance rho_s on the axis theta = 0,
+    u_in = H0^(1)(k0 |x - x_s|) = sum_m H_m(k0 rho_s) J_m(k0 r) e^{i m theta}
+    for r < rho_s (Graf's addition theorem), i.e. the incident coefficient
+    H_m(k0 rho_s) in place of i^m."""
     k0, k1, e0, e1 = media.k0, media.k1, media.eps0, media.eps1
     m = _orders(media, a)
+    if src is not None:
+        assert src > a
+        m = np.arange(-(int(np.ceil(k0 * src)) + 40), int(np.ceil(k0 * src)) + 41)
     c = np.empty(m.shape, dtype=np.complex128)
     b = np.empty(m.shape, dtype=np.complex128)
     for idx, mm in enumerate(m):
         M = np.array([[jv(mm, k1 * a), -hankel1(mm, k0 * a)],
                       [(k1 / e1) * jvp(mm, k1 * a), -(k0 / e0) * h1vp(mm, k0 * a)]])
-        rhs = (1j ** mm) * np.array([jv(mm, k0 * a), (k0 / e0) * jvp(mm, k0 * a)])
+        inc = (1j ** mm) if src is None else hankel1(mm, k0 * src)
+        rhs = inc * np.array([jv(mm, k0 * a), (k0 / e0) * jvp(mm, k0 * a)])
         c[idx], b[idx] = np.linalg.solve(M, rhs)
     return m, c, b
 
 
-def boundary_values(media, theta_nodes, a=1.0, theta_inc=0.0):
-    """Exact u and q = (1/eps1) du/dn (interior side) at boundary angles."""
-    m, c, _ = coefficients(media, a)
+def boundary_values(media, theta_nodes, a=1.0, theta_inc=0.0, src=None):
+    """Exact u and q = (1/eps1) du/dn (interior side) at boundary angles;
+    src = rho_s: for a point source at (rho_s cos theta_inc, rho_s sin theta_inc)."""
+    m, c, _ = coefficients(media, a, src)
     e = np.exp(1j * np.outer(np.asarray(theta_nodes) - theta_inc, m))
     u = e @ (c * jv(m, media.k1 * a))
     q = e @ (c * (media.k1 / media.eps1) * jvp(m, media.k1 * a))

@@ -193,6 +193,25 @@ def rhs_plane_wave(nodes: Nodes, media, theta: float) -> np.ndarray:
     return b
 
 
+def rhs_incident(nodes: Nodes, media, uin: np.ndarray, dn_uin: np.ndarray) -> np.ndarray:
+    """The right-hand side of Eq. (3) for an arbitrary incident field given by
+    its values u_in and outward normal derivatives du_in/dn at the nodes:
+    b[2i] = 0, b[2i+1] = -u_in - alpha du_in/dn, alpha = i/k0."""
+    b = np.zeros(2 * nodes.size, dtype=np.complex128)
+    b[1::2] = -np.asarray(uin) - (1j / media.k0) * np.asarray(dn_uin)
+    return b
+
+
+def point_source_field(nodes: Nodes, k0: float, src) -> tuple:
+    """u_in = H0^(1)(k0 |x - x_s|) of a point source at x_s outside the
+    scatterers, and du_in/dn = -k0 H1^(1)(k0 R) ((x - x_s).n)/R, R = |x - x_s|."""
+    d = nodes.x - np.asarray(src, dtype=np.float64)[None, :]
+    R = np.sqrt(d[:, 0] ** 2 + d[:, 1] ** 2)
+    uin = hankel1(0, k0 * R)
+    dn = -k0 * hankel1(1, k0 * R) * (d[:, 0] * nodes.n[:, 0] + d[:, 1] * nodes.n[:, 1]) / R
+    return uin, dn
+
+
 def solve_dense(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     """phi = A^{-1} b by LU with partial pivoting (LAPACK zgetrf/zgetrs)."""
     lu, piv = scipy.linalg.lu_factor(A, check_finite=False)

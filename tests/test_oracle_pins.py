@@ -239,3 +239,35 @@ def test_large_matrix_helpers_match_the_plain_assembly_and_solve():
     x = wsbm.solve_dense(A, b)
     y = wsbm.solve_dense_inplace(Ap, b)
     assert np.linalg.norm(x - y) < 1e-12 * np.linalg.norm(x)
+
+
+def test_point_source_incidence_against_mie():
+    """An incident field other than a plane wave: a point source at distance 3
+    from a dielectric circle (k0 = 10, n = 1.5).  The right-hand side built from
+    its values and normal derivatives (rhs_incident) and the dense solve must
+    reproduce the separation-of-variables solution (Graf's addition theorem for
+    the incident coefficients) at the O(h^3) rate; a wrong sign of alpha, a
+    wrong normal derivative or a swapped u/q row fails the rate."""
+    media = sc.media_from_index(10.0, 1.5)
+    rho, th = 3.0, 0.8
+    src = (rho * np.cos(th), rho * np.sin(th))
+    errs = {}
+    for N in (256, 512):
+        nd = nodes_for([sc.circle(1.0)], [N])
+        uin, dn = wsbm.point_source_field(nd, media.k0, src)
+        phi = wsbm.solve_dense(wsbm.assemble_dense(nd, media), wsbm.rhs_incident(nd, media, uin, dn))
+        t = 2 * np.pi * np.arange(N) / N
+        u, q = mie.boundary_values(media, t, theta_inc=th, src=rho)
+        errs[N] = (np.linalg.norm(phi[0::2] - u) / np.linalg.norm(u), np.linalg.norm(phi[1::2] - q) / np.linalg.norm(q))
+    assert errs[512][0] < 1e-4 and errs[512][1] < 1e-4
+    for c in range(2):
+        assert 7.0 < errs[256][c] / errs[512][c] < 9.0, errs
+
+
+def test_rhs_incident_of_a_plane_wave_is_the_plane_wave_rhs():
+    media = sc.media_from_index(20.0, 1.3)
+    nd = nodes_for([sc.star(0.3, 5)], [300])
+    d = np.array([np.cos(1.1), np.sin(1.1)])
+    uin = np.exp(1j * media.k0 * (nd.x @ d))
+    dn = 1j * media.k0 * (nd.n @ d) * uin
+    assert np.allclose(wsbm.rhs_incident(nd, media, uin, dn), wsbm.rhs_plane_wave(nd, media, 1.1), rtol=1e-14, atol=0)
