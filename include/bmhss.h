@@ -94,6 +94,15 @@ int bm_problem_destroy(bm_problem* p);
  * rhs[2i] = 0, rhs[2i+1] = -u_in(x_i) - alpha du_in/dn(x_i). */
 int bm_rhs_plane_wave(const bm_problem* p, double angle, double* rhs, hipStream_t stream);
 
+/* ---- Right-hand side of Eq. (3) for any incident field ----
+ * uin, dn_uin (device, N complex): the incident field u_in and its outward
+ * normal derivative du_in/dn at the nodes, e.g. of a point source or of a sum
+ * of plane waves; rhs (device, 2N complex): rhs[2i] = 0,
+ * rhs[2i+1] = -u_in(x_i) - alpha du_in/dn(x_i), alpha = i/k0 of node i's body.
+ * rhs must not alias uin or dn_uin.  Asynchronous on `stream`. */
+int bm_rhs_incident(const bm_problem* p, const double* uin, const double* dn_uin, double* rhs,
+                    hipStream_t stream);
+
 /* ---- Matrix entries: Eq. (3) / Eq. (5), one-point corrected diagonal ----
  * Full matrix (device, 2N x 2N complex, row-major, ld >= 2N). */
 int bm_assemble_dense(const bm_problem* p, double* A, int64_t ld, hipStream_t stream);
@@ -101,10 +110,16 @@ int bm_assemble_dense(const bm_problem* p, double* A, int64_t ld, hipStream_t st
 /* Block A(rows, cols) for node index lists (device int64 arrays, values in
  * [0, N)); out (device) is 2nr x 2nc complex with leading dimension ld >= 2nc.
  * Pairs with rows[a] == cols[b] get the corrected diagonal block of Eq. (5)
- * (delta_ij = 1).  Indices are not validated on the device: out-of-range
- * values are the caller's error. */
+ * (delta_ij = 1); pairs in two different bodies are zero blocks.  Indices are
+ * not validated on the device: out-of-range values are the caller's error.
+ * prec = 0: FP64 arithmetic; prec = 1: FP32 arithmetic (coordinate
+ * differences and the phase reduction of large arguments in FP64), entries
+ * rounded to FP32 accuracy and stored as FP64 complex -- for blocks that only
+ * select skeletons.  The entries come from the same generator the HSS build
+ * runs; a small device buffer (slot lists) is allocated and released on
+ * `stream`.  nr, nc < 2^30. */
 int bm_assemble_block(const bm_problem* p, const int64_t* rows, int64_t nr, const int64_t* cols,
-                      int64_t nc, double* out, int64_t ld, hipStream_t stream);
+                      int64_t nc, double* out, int64_t ld, int prec, hipStream_t stream);
 
 /* Proxy blocks for the proxy-surface compression (Sec. I and III; the proxy
  * method of Martinsson-Rokhlin).  Proxy points are pseudo-nodes given by pts
@@ -112,9 +127,13 @@ int bm_assemble_block(const bm_problem* p, const int64_t* rows, int64_t nr, cons
  * with no diagonal term.  dir = 0: node targets x proxy sources, out is
  * 2n x 2P (ld >= 2P); dir = 1: proxy targets x node sources, out is 2P x 2n
  * (ld >= 2n).  nodes: device int64 list of node indices.  Proxy points must
- * not coincide with nodes. */
+ * not coincide with nodes.  A proxy point takes the media of the node it is
+ * paired with, and the interior (k1) terms are kept.  prec as in
+ * bm_assemble_block.  The generator's point table (the N nodes and the P
+ * proxy points) is copied into a device buffer allocated and released on
+ * `stream`. */
 int bm_assemble_proxy(const bm_problem* p, const int64_t* nodes, int64_t n, const double* pts,
-                      int64_t P, int dir, double* out, int64_t ld, hipStream_t stream);
+                      int64_t P, int dir, double* out, int64_t ld, int prec, hipStream_t stream);
 
 /* y = A x without storing A (device, 2N complex each): the matrix entries are
  * generated on the fly and reduced. */
@@ -181,13 +200,19 @@ typedef struct {
     int64_t kernel_timing; /* 1: time every launch of the batched GEMM and Gauss-Jordan
                               kernels with HIP events (bm_hss_stats_t gemm_* and
                               inv_*; adds an event pair per launch); 0: off */
+    int64_t proxy_fp32;    /* 1: node x proxy blocks in FP32 arithmetic (they only
+                              select skeletons; near, skeleton and diagonal blocks,
+                              the ID and the factors stay FP64); 0: FP64 */
 } bm_hss_opts;
 
 typedef struct {
     int32_t levels;            /* tree depth: the leaves are level `levels` */
     int32_t compressed_levels; /* levels compressed by the proxy ID */
     int32_t root_size;         /* unknowns of the dense root system */
-    int32_t reserved;
+    int32_t guard_stops;       /* bodies whose compression the ID work guard ended:
+                                  a box's stacked ID matrix above 2^26 entries, or a
+                                  body's above 2^31 at one level (its skeletons then
+                                  form its dense root) */
     int64_t max_rank;          /* largest skeleton (unknowns) over all boxes */
     int64_t entries;           /* matrix entries generated during the build */
     int64_t pairs;             /* node pairs evaluated (each gives a 2x2 block) */

@@ -23,6 +23,7 @@ from ._binding import (  # noqa: F401
     bm_problem_create,
     bm_problem_create_bodies,
     bm_rhs_plane_wave,
+    bm_rhs_incident,
     bm_hss_build,
     bm_hss_solve,
     bm_hss_stats,

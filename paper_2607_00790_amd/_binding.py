@@ -29,12 +29,12 @@ class _Media(ctypes.Structure):
 class _HssOpts(ctypes.Structure):
     _fields_ = [("leaf", c_i64), ("proxy_ratio", c_dbl), ("proxy_points", c_i64),
                 ("id_tol", c_dbl), ("sketch", c_i64), ("proxy_adapt", c_i64), ("max_rank_ratio", c_dbl),
-                ("kernel_timing", c_i64)]
+                ("kernel_timing", c_i64), ("proxy_fp32", c_i64)]
 
 
 class _HssStats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("compressed_levels", ctypes.c_int32),
-                ("root_size", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("root_size", ctypes.c_int32), ("guard_stops", ctypes.c_int32),
                 ("max_rank", c_i64), ("entries", c_i64), ("pairs", c_i64),
                 ("seconds_generate", c_dbl), ("seconds_compress", c_dbl),
                 ("seconds_factor", c_dbl), ("seconds_total", c_dbl),
@@ -76,9 +76,10 @@ def load():
         "bm_problem_create_bodies": (ctypes.c_int, [c_vp, ctypes.c_int, c_vp, c_vp, ctypes.POINTER(c_vp)]),
         "bm_rhs_plane_wave": (ctypes.c_int, [c_vp, c_dbl, c_vp, c_vp]),
         "bm_assemble_dense": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp]),
-        "bm_assemble_block": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp]),
+        "bm_rhs_incident": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+        "bm_assemble_block": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, ctypes.c_int, c_vp]),
         "bm_assemble_proxy": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, ctypes.c_int, c_vp,
-                                             c_i64, c_vp]),
+                                             c_i64, ctypes.c_int, c_vp]),
         "bm_matvec": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp]),
         "bm_matvec_noalloc": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp]),
         "bm_far_field": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]),
@@ -244,6 +245,20 @@ def bm_rhs_plane_wave(p: Problem, angle: float, out=None, stream=None):
     return out
 
 
+def bm_rhs_incident(p: Problem, uin, dn_uin, out=None, stream=None):
+    """Right-hand side of Eq. (3) from u_in and du_in/dn at the nodes
+    (each an N-vector, complex128 device tensor)."""
+    torch = _torch()
+    if uin.numel() != p.n or dn_uin.numel() != p.n:
+        raise ValueError("uin and dn_uin need one value per node")
+    if out is None:
+        out = torch.empty(2 * p.n, dtype=torch.complex128, device="cuda")
+    _check(load().bm_rhs_incident(p._h, _dev_ptr(uin, torch.complex128, "uin"),
+                                  _dev_ptr(dn_uin, torch.complex128, "dn_uin"),
+                                  _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
+    return out
+
+
 def bm_assemble_dense(p: Problem, out=None, stream=None):
     torch = _torch()
     n2 = 2 * p.n
@@ -256,7 +271,8 @@ def bm_assemble_dense(p: Problem, out=None, stream=None):
     return out
 
 
-def bm_assemble_block(p: Problem, rows, cols, out=None, stream=None):
+def bm_assemble_block(p: Problem, rows, cols, out=None, prec=0, stream=None):
+    """prec 0: FP64 entries; 1: FP32 arithmetic (stored as complex128)."""
     torch = _torch()
     rows = rows.to(device="cuda", dtype=torch.int64).contiguous()
     cols = cols.to(device="cuda", dtype=torch.int64).contiguous()
@@ -264,13 +280,13 @@ def bm_assemble_block(p: Problem, rows, cols, out=None, stream=None):
     if out is None:
         out = torch.empty((2 * nr, 2 * nc), dtype=torch.complex128, device="cuda")
     _check(load().bm_assemble_block(p._h, _dev_ptr(rows), nr, _dev_ptr(cols), nc,
-                                  _dev_ptr(out, torch.complex128, "out"), out.stride(0),
+                                  _dev_ptr(out, torch.complex128, "out"), out.stride(0), int(prec),
                                   _stream(stream)))
     return out
 
 
-def bm_assemble_proxy(p: Problem, nodes, pts, direction: int, out=None, stream=None):
-    """pts: (5, P) float64 device tensor (x, y, nx, ny, w)."""
+def bm_assemble_proxy(p: Problem, nodes, pts, direction: int, out=None, prec=0, stream=None):
+    """pts: (5, P) float64 device tensor (x, y, nx, ny, w); prec as in bm_assemble_block."""
     torch = _torch()
     nodes = nodes.to(device="cuda", dtype=torch.int64).contiguous()
     n, P = nodes.numel(), pts.shape[1]
@@ -279,7 +295,7 @@ def bm_assemble_proxy(p: Problem, nodes, pts, direction: int, out=None, stream=N
         out = torch.empty(shape, dtype=torch.complex128, device="cuda")
     _check(load().bm_assemble_proxy(p._h, _dev_ptr(nodes), n, _dev_ptr(pts, torch.float64, "pts"), P,
                                   int(direction), _dev_ptr(out, torch.complex128, "out"),
-                                  out.stride(0), _stream(stream)))
+                                  out.stride(0), int(prec), _stream(stream)))
     return out
 
 
@@ -312,7 +328,8 @@ def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
 
 
 def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10,
-                 sketch=0, proxy_adapt=False, max_rank_ratio=0.0, kernel_timing=False, stream=None) -> HSS:
+                 sketch=0, proxy_adapt=False, max_rank_ratio=0.0, kernel_timing=False, proxy_fp32=False,
+                 stream=None) -> HSS:
     """sketch = p > 0: run the ID on a Gaussian sketch of each box's stacked
     matrix with (unknowns + p) rows, when that is fewer than the matrix has.
     proxy_adapt: max(proxy_points, ceil(2 k R_p) + 32) points per proxy circle.
@@ -320,9 +337,11 @@ def bm_hss_build(p: Problem, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1
     than r of its unknowns (its skeletons then form its dense root).
     sketch = -1 or max_rank_ratio = -1: the library's tuned value (the build's
     stats report the values used).  kernel_timing: HIP-event timing of every
-    batched GEMM and Gauss-Jordan launch (stats gemm_* and inv_*)."""
+    batched GEMM and Gauss-Jordan launch (stats gemm_* and inv_*).  proxy_fp32:
+    node x proxy blocks in FP32 arithmetic (everything else FP64)."""
     opts = _HssOpts(int(leaf), float(proxy_ratio), int(proxy_points), float(id_tol), int(sketch),
-                    int(bool(proxy_adapt)), float(max_rank_ratio), int(bool(kernel_timing)))
+                    int(bool(proxy_adapt)), float(max_rank_ratio), int(bool(kernel_timing)),
+                    int(bool(proxy_fp32)))
     out = c_vp()
     _check(load().bm_hss_build(p._h, ctypes.byref(opts), _stream(stream), ctypes.byref(out)))
     return HSS(out, p)

@@ -148,53 +148,6 @@ k_dense(NodeView v, int64_t n, int64_t ntj, const Media* __restrict__ media, dou
     }
 }
 
-// Block for node index lists: workgroup b covers row a = b / ntj.
-__global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
-k_block(NodeView v, const Media* __restrict__ media, const int64_t* __restrict__ rows,
-        const int64_t* __restrict__ cols, int64_t nc, int64_t ntj, double* __restrict__ out, int64_t ld,
-        const BesselTable* __restrict__ tab) {
-    const int64_t a = blockIdx.x / ntj;
-    const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
-    if (c >= nc) return;
-    const int64_t i = rows[a], j = cols[c];
-    const int bi = body_of(v, i);
-    const Media m = with_table(media[bi], tab);
-    if (body_of(v, j) != bi) {
-        store_zero(out, ld, a, c);
-    } else if (i == j) {
-        store_block(out, ld, a, c, diag_block(v.w[j], v.kappa[j], m));
-    } else {
-        emit_pair(out, ld, a, c, v.x[i], v.y[i], v.nx[i], v.ny[i], v.x[j], v.y[j], v.nx[j], v.ny[j],
-                  v.w[j], m, v.curve[i] == v.curve[j]);
-    }
-}
-
-// Proxy blocks.  dir 0: node targets (rows) x proxy sources (cols);
-// dir 1: proxy targets (rows) x node sources (cols).
-__global__ void __launch_bounds__(kThreads)
-k_proxy(NodeView v, const Media* __restrict__ media, const int64_t* __restrict__ nodes, int64_t n,
-        const double* __restrict__ pts, int64_t P, int dir, int64_t ntj, double* __restrict__ out,
-        int64_t ld, const BesselTable* __restrict__ tab) {
-    const int64_t ncol = dir == 0 ? P : n;
-    const int64_t a = blockIdx.x / ntj;
-    const int64_t c = (blockIdx.x % ntj) * kThreads + threadIdx.x;
-    if (c >= ncol) return;
-    double tx, ty, tnx, tny, sx, sy, snx, sny, sw;
-    // the proxy point takes the media of the node it is paired with
-    const Media m = with_table(media[body_of(v, dir == 0 ? nodes[a] : nodes[c])], tab);
-    if (dir == 0) {
-        const int64_t i = nodes[a];
-        tx = v.x[i]; ty = v.y[i]; tnx = v.nx[i]; tny = v.ny[i];
-        sx = pts[c]; sy = pts[P + c]; snx = pts[2 * P + c]; sny = pts[3 * P + c];
-        sw = pts[4 * P + c];
-    } else {
-        const int64_t j = nodes[c];
-        tx = pts[a]; ty = pts[P + a]; tnx = pts[2 * P + a]; tny = pts[3 * P + a];
-        sx = v.x[j]; sy = v.y[j]; snx = v.nx[j]; sny = v.ny[j]; sw = v.w[j];
-    }
-    emit_pair(out, ld, a, c, tx, ty, tnx, tny, sx, sy, snx, sny, sw, m, true);
-}
-
 __global__ void __launch_bounds__(kThreads)
 k_rhs_plane_wave(NodeView v, int64_t n, const Media* __restrict__ media, double dx, double dy,
                  double2* __restrict__ rhs) {
@@ -207,6 +160,20 @@ k_rhs_plane_wave(NodeView v, int64_t n, const Media* __restrict__ media, double 
     const double f = -(1.0 - (dx * v.nx[i] + dy * v.ny[i]));
     rhs[2 * i] = make_double2(0.0, 0.0);
     rhs[2 * i + 1] = make_double2(f * c, f * s);
+}
+
+// Right-hand side of Eq. (3) for a given incident field: rhs[2i] = 0,
+// rhs[2i+1] = -u_in(x_i) - alpha du_in/dn(x_i), alpha = i/k0 of the node's body.
+__global__ void __launch_bounds__(kThreads)
+k_rhs_incident(NodeView v, int64_t n, const Media* __restrict__ media, const double2* __restrict__ uin,
+               const double2* __restrict__ dn_uin, double2* __restrict__ rhs) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const double ik0 = media[body_of(v, i)].ik0;
+    const double2 u = uin[i], du = dn_uin[i];
+    // alpha du = (i/k0)(du.x + i du.y) = (-du.y + i du.x)/k0
+    rhs[2 * i] = make_double2(0.0, 0.0);
+    rhs[2 * i + 1] = make_double2(-u.x + ik0 * du.y, -u.y - ik0 * du.x);
 }
 
 // y = A x, stage 1: workgroup b covers target i = b / ntj and one tile of
@@ -319,30 +286,18 @@ hipError_t launch_dense(const NodeView& v, int64_t n, const Media* m, const Bess
     return hipGetLastError();
 }
 
-hipError_t launch_block(const NodeView& v, const Media* m, const BesselTable* tab, const int64_t* rows,
-                        int64_t nr, const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s) {
-    if (nr == 0 || nc == 0) return hipSuccess;
-    const int64_t ntj = (nc + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_block, dim3(static_cast<unsigned>(nr * ntj)), dim3(kThreads), 0, s, v, m,
-                       rows, cols, nc, ntj, out, ld, tab);
-    return hipGetLastError();
-}
-
-hipError_t launch_proxy(const NodeView& v, const Media* m, const BesselTable* tab, const int64_t* nodes,
-                        int64_t n, const double* pts, int64_t P, int dir, double* out, int64_t ld,
-                        hipStream_t s) {
-    if (n == 0 || P == 0) return hipSuccess;
-    const int64_t ncol = dir == 0 ? P : n, nrow = dir == 0 ? n : P;
-    const int64_t ntj = (ncol + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_proxy, dim3(static_cast<unsigned>(nrow * ntj)), dim3(kThreads), 0, s, v,
-                       m, nodes, n, pts, P, dir, ntj, out, ld, tab);
-    return hipGetLastError();
-}
-
 hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* m, double angle,
                                  double* rhs, hipStream_t s) {
     hipLaunchKernelGGL(k_rhs_plane_wave, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, v, n,
                        m, std::cos(angle), std::sin(angle), reinterpret_cast<double2*>(rhs));
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_incident(const NodeView& v, int64_t n, const Media* m, const double* uin, const double* dn_uin,
+                               double* rhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_rhs_incident, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, v, n, m,
+                       reinterpret_cast<const double2*>(uin), reinterpret_cast<const double2*>(dn_uin),
+                       reinterpret_cast<double2*>(rhs));
     return hipGetLastError();
 }
 

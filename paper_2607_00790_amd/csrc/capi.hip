@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "wsbm_pair_f32.hpp"
 
 namespace bm {
 
@@ -53,6 +54,35 @@ hipError_t device_table(const BesselTable** out) {
         return e;
     }
     g_tables[dev] = d;
+    *out = d;
+    return hipSuccess;
+}
+
+// The FP32 copy of the table (entry for entry, rounded to nearest), for the
+// FP32 entry path; one per device.
+std::unordered_map<int, float*> g_ftables;
+
+hipError_t device_table_f32(const float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    auto it = g_ftables.find(dev);
+    if (it != g_ftables.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    std::vector<float> h(f32::kTableEntries);
+    const double* src = reinterpret_cast<const double*>(&bm_bessel_coef::kTable);
+    for (int q = 0; q < f32::kTableEntries; ++q) h[q] = static_cast<float>(src[q]);
+    float* d = nullptr;
+    e = hipMalloc(reinterpret_cast<void**>(&d), h.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return e;
+    }
+    g_ftables[dev] = d;
     *out = d;
     return hipSuccess;
 }
@@ -192,10 +222,13 @@ int bm_problem_create_bodies(const bm_geom* g, int nbodies, const int32_t* body_
     for (int b = 0; b < nbodies; ++b) tiles[b + 1] = tiles[b] + pair_tiles(lo[b + 1] - lo[b]);
     const BesselTable* tab = nullptr;
     BM_HIP(device_table(&tab));
+    const float* ftab = nullptr;
+    BM_HIP(device_table_f32(&ftab));
     bm_problem* p = new (std::nothrow) bm_problem;
     if (!p) return fail(BM_ENOMEM, "bm_problem_create: host allocation");
     p->g = g;
     p->nbodies = nbodies;
+    p->d_ftab = ftab;
     p->body_lo = lo;
     p->tile_off = tiles;
     for (int b = 0; b < nbodies; ++b)
@@ -209,12 +242,14 @@ int bm_problem_create_bodies(const bm_geom* g, int nbodies, const int32_t* body_
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_tile_off), (nbodies + 1) * sizeof(int64_t));
     if (e == hipSuccess)
         e = hipMemcpy(p->d_tile_off, tiles.data(), (nbodies + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess && nbodies > 1) {
+    if (e == hipSuccess) {
         std::vector<int32_t> nb(static_cast<size_t>(g->n));
         for (int b = 0; b < nbodies; ++b)
             for (int64_t i = lo[b]; i < lo[b + 1]; ++i) nb[i] = b;
-        e = hipMalloc(reinterpret_cast<void**>(&p->d_body), g->n * sizeof(int32_t));
-        if (e == hipSuccess) e = hipMemcpy(p->d_body, nb.data(), g->n * sizeof(int32_t), hipMemcpyHostToDevice);
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_body_all), g->n * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemcpy(p->d_body_all, nb.data(), g->n * sizeof(int32_t), hipMemcpyHostToDevice);
+        // kernels that test for one body read a null body array
+        if (e == hipSuccess && nbodies > 1) p->d_body = p->d_body_all;
     }
     if (e != hipSuccess) {
         bm_problem_destroy(p);
@@ -231,7 +266,7 @@ int bm_problem_create(const bm_geom* g, const bm_media* media, bm_problem** out)
 int bm_problem_destroy(bm_problem* p) {
     if (!p) return BM_OK;
     (void)hipFree(p->d_media);
-    (void)hipFree(p->d_body);
+    (void)hipFree(p->d_body_all);   // p->d_body is null or the same array
     (void)hipFree(p->d_body_lo);
     (void)hipFree(p->d_tile_off);
     delete p;
@@ -246,6 +281,15 @@ int bm_rhs_plane_wave(const bm_problem* p, double angle, double* rhs, hipStream_
     return BM_OK;
 }
 
+int bm_rhs_incident(const bm_problem* p, const double* uin, const double* dn_uin, double* rhs,
+                    hipStream_t stream) {
+    clear_error();
+    if (!p || !uin || !dn_uin || !rhs) return fail(BM_EINVAL, "bm_rhs_incident: null argument");
+    if (rhs == uin || rhs == dn_uin) return fail(BM_EINVAL, "bm_rhs_incident: rhs must not alias the inputs");
+    BM_HIP(launch_rhs_incident(view(p), p->g->n, p->d_media, uin, dn_uin, rhs, stream));
+    return BM_OK;
+}
+
 int bm_assemble_dense(const bm_problem* p, double* A, int64_t ld, hipStream_t stream) {
     clear_error();
     if (!p || !A) return fail(BM_EINVAL, "bm_assemble_dense: null argument");
@@ -257,30 +301,37 @@ int bm_assemble_dense(const bm_problem* p, double* A, int64_t ld, hipStream_t st
 }
 
 int bm_assemble_block(const bm_problem* p, const int64_t* rows, int64_t nr, const int64_t* cols,
-                      int64_t nc, double* out, int64_t ld, hipStream_t stream) {
+                      int64_t nc, double* out, int64_t ld, int prec, hipStream_t stream) {
     clear_error();
     if (!p) return fail(BM_EINVAL, "bm_assemble_block: null problem");
     if (nr < 0 || nc < 0) return fail(BM_EINVAL, "bm_assemble_block: negative size");
+    if (prec != 0 && prec != 1) return fail(BM_EINVAL, "bm_assemble_block: prec must be 0 (FP64) or 1 (FP32)");
     if (nr == 0 || nc == 0) return BM_OK;
     if (!rows || !cols || !out) return fail(BM_EINVAL, "bm_assemble_block: null array");
     if (ld < 2 * nc) return fail(BM_EINVAL, "bm_assemble_block: ld < 2 nc");
-    if (nr * ((nc + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_block: too large");
-    BM_HIP(launch_block(view(p), p->d_media, p->media[0].tab, rows, nr, cols, nc, out, ld, stream));
+    if (nr >= (int64_t{1} << 30) || nc >= (int64_t{1} << 30) || (nr * nc + 255) / 256 > kMaxGrid)
+        return fail(BM_EINVAL, "bm_assemble_block: too large");
+    BM_HIP(launch_block(view(p), p->d_body_all, p->d_media, p->media[0].tab, p->d_ftab, rows, nr, cols, nc, prec,
+                        out, ld, stream));
     return BM_OK;
 }
 
 int bm_assemble_proxy(const bm_problem* p, const int64_t* nodes, int64_t n, const double* pts,
-                      int64_t P, int dir, double* out, int64_t ld, hipStream_t stream) {
+                      int64_t P, int dir, double* out, int64_t ld, int prec, hipStream_t stream) {
     clear_error();
     if (!p) return fail(BM_EINVAL, "bm_assemble_proxy: null problem");
     if (n < 0 || P < 0) return fail(BM_EINVAL, "bm_assemble_proxy: negative size");
     if (dir != 0 && dir != 1) return fail(BM_EINVAL, "bm_assemble_proxy: dir must be 0 or 1");
+    if (prec != 0 && prec != 1) return fail(BM_EINVAL, "bm_assemble_proxy: prec must be 0 (FP64) or 1 (FP32)");
     if (n == 0 || P == 0) return BM_OK;
     if (!nodes || !pts || !out) return fail(BM_EINVAL, "bm_assemble_proxy: null array");
-    const int64_t ncol = dir == 0 ? P : n, nrow = dir == 0 ? n : P;
+    const int64_t ncol = dir == 0 ? P : n;
     if (ld < 2 * ncol) return fail(BM_EINVAL, "bm_assemble_proxy: ld too small");
-    if (nrow * ((ncol + 255) / 256) > kMaxGrid) return fail(BM_EINVAL, "bm_assemble_proxy: too large");
-    BM_HIP(launch_proxy(view(p), p->d_media, p->media[0].tab, nodes, n, pts, P, dir, out, ld, stream));
+    if (n >= (int64_t{1} << 30) || P >= (int64_t{1} << 30) || p->g->n + P >= (int64_t{1} << 31) ||
+        (n * P + 255) / 256 > kMaxGrid)
+        return fail(BM_EINVAL, "bm_assemble_proxy: too large");
+    BM_HIP(launch_proxy(view(p), p->g->n, p->d_media, p->media[0].tab, p->d_ftab, nodes, n, pts, P, dir, prec, out,
+                        ld, stream));
     return BM_OK;
 }
 

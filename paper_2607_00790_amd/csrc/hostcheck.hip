@@ -5,9 +5,62 @@
 #include <cstdint>
 #include <vector>
 
+#include "hss_plan.hpp"
 #include "wsbm_adjoint.hpp"
+#include "wsbm_pair_f32.hpp"
 
 extern "C" {
+
+// The ID work guard's decisions (hss_plan.hpp): bit 0 = a box of rows x
+// unknowns is over the per-box budget, bit 1 = a level total of `total`
+// entries is over the per-body budget.
+int bmh_id_guard(int64_t rows, int64_t unknowns, int64_t total) {
+    return (bm::hss::id_box_over_budget(rows, unknowns) ? 1 : 0) | (bm::hss::id_level_over_budget(total) ? 2 : 0);
+}
+
+// Blocks A(rows, cols) in FP32 arithmetic, as the FP32 entry path forms them
+// (coefficients rounded to FP32 entry by entry); arguments as
+// bmh_system_blocks, one curve per node given by `curve`.
+int bmh_system_blocks_f32(const double* soa, const int32_t* curve, int64_t N, const int64_t* rows, int64_t nr,
+                          const int64_t* cols, int64_t nc, const double* media, double* out) {
+    const bm::Media m = bm::make_media(media[0], media[1], media[2], media[3], &bm_bessel_coef::kTable);
+    const bm::f32::MediaF mf = bm::f32::media_f(m);
+    std::vector<float> ft(bm::f32::kTableEntries);
+    const double* src = reinterpret_cast<const double*>(&bm_bessel_coef::kTable);
+    for (int q = 0; q < bm::f32::kTableEntries; ++q) ft[q] = static_cast<float>(src[q]);
+    const double *x = soa, *y = soa + N, *nx = soa + 2 * N, *ny = soa + 3 * N, *w = soa + 4 * N,
+                 *kap = soa + 5 * N;
+    const int64_t ld = 2 * nc;
+    for (int64_t a = 0; a < nr; ++a) {
+        for (int64_t b = 0; b < nc; ++b) {
+            const int64_t i = rows[a], j = cols[b];
+            bm::Block blk;
+            if (i == j) {
+                blk = bm::f32::diag_block(static_cast<float>(w[j]), static_cast<float>(kap[j]), mf);
+            } else {
+                const bm::f32::PairGeomF g = bm::f32::pair_geom(
+                    x[i], y[i], static_cast<float>(nx[i]), static_cast<float>(ny[i]), x[j], y[j],
+                    static_cast<float>(nx[j]), static_cast<float>(ny[j]));
+                const bm::f32::Hankel01F h1 =
+                    bm::f32::pair_interior(g, mf, curve[i] == curve[j], &bm_bessel_coef::kTable, ft.data());
+                float r0[4], r1[4];
+                bm::f32::pair_row0(g, h1, static_cast<float>(w[j]), mf, r0);
+                bm::f32::pair_row1(g, h1, static_cast<float>(w[j]), mf, &bm_bessel_coef::kTable, ft.data(), r1);
+                for (int q = 0; q < 4; ++q) {
+                    blk.v[q] = r0[q];
+                    blk.v[4 + q] = r1[q];
+                }
+            }
+            double* o0 = out + 2 * ((2 * a) * ld + 2 * b);
+            double* o1 = out + 2 * ((2 * a + 1) * ld + 2 * b);
+            for (int q = 0; q < 4; ++q) {
+                o0[q] = blk.v[q];
+                o1[q] = blk.v[4 + q];
+            }
+        }
+    }
+    return 0;
+}
 
 // out[4*q + {0,1,2,3}] = J0, Y0, J1, Y1 + 2/(pi z) at z[q].
 int bmh_bessel01(const double* z, int64_t n, double* out) {

@@ -34,6 +34,7 @@
 #include <rocblas/rocblas.h>
 
 #include "hss_internal.hpp"
+#include "hss_plan.hpp"
 #include "tuned_params.h"
 
 using namespace bm;
@@ -245,19 +246,23 @@ hipError_t launch_in_groups(const std::vector<Job>& jobs, Tiles tiles, Launch la
 }
 
 hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
-                            const PointTable& pt, const Media* media, const BesselTable* tab, double2* out);
+                            const PointTable& pt, const Media* media, const BesselTable* tab, double2* out,
+                            const float* ftab);
 
 // `media` is the device media array, `tab` the device coefficient table every
-// Media points to (passed to the kernel as an argument of its own).
+// Media points to (passed to the kernel as an argument of its own).  ftab
+// non-null: the jobs are generated in FP32 arithmetic from that FP32 table.
 hipError_t launch_gen(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
-                      const PointTable& pt, const Media* media, const BesselTable* tab, double2* out) {
+                      const PointTable& pt, const Media* media, const BesselTable* tab, double2* out,
+                      const float* ftab = nullptr) {
     return launch_in_groups(
         jobs, [](const GenJob& j) { return ceil_div(static_cast<int64_t>(j.nt) * j.ns, kThreads); },
-        [&](const std::vector<GenJob>& g) { return launch_gen_group(sc, g, slots, pt, media, tab, out); });
+        [&](const std::vector<GenJob>& g) { return launch_gen_group(sc, g, slots, pt, media, tab, out, ftab); });
 }
 
 hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
-                            const PointTable& pt, const Media* media, const BesselTable* tab, double2* out) {
+                            const PointTable& pt, const Media* media, const BesselTable* tab, double2* out,
+                            const float* ftab) {
     if (jobs.empty()) return hipSuccess;
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
@@ -273,7 +278,12 @@ hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const 
     const PointTable ptc = pt;
     hipStream_t st = sc.s;
     sc.rec([=]() {
-        hipLaunchKernelGGL(k_gen_jobs, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, media, out, tab);
+        if (ftab)
+            hipLaunchKernelGGL(k_gen_jobs<float>, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, media, out,
+                               tab, ftab);
+        else
+            hipLaunchKernelGGL(k_gen_jobs<double>, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, media,
+                               out, tab, ftab);
         return hipGetLastError();
     });
     return hipSuccess;
@@ -878,6 +888,7 @@ struct bm_hss {
     std::vector<LevelFactor> lv;   // compressed iterations, leaves first
     std::vector<RootJob> roots;    // one per body
     int64_t Ktot = 0;              // total size of the roots
+    int32_t guard_stops = 0;       // bodies the ID work guard stopped
     double2* Rinv = nullptr;       // the roots' inverses, packed
     bm_hss_stats_t stats{};
     std::vector<bm_hss_level_t> level_info;   // per compressed level, leaves first
@@ -1323,15 +1334,31 @@ int build_impl(bm_hss* h, hipStream_t s) {
         sc.synced();
         pl.reap(false);
         if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: near counts"); }
-        // ---- a body with a box that has no far unknowns stops: its current boxes form its root
+        // ---- a body with a box that has no far unknowns stops: its current boxes form its root;
+        // so does a body whose IDs at this level would exceed the work guard (hss_plan.hpp)
         {
-            std::vector<int64_t> total_u(nbodies, 0);
-            std::vector<char> stop(nbodies, 0);
+            std::vector<int64_t> total_u(nbodies, 0), id_entries(nbodies, 0);
+            std::vector<char> stop(nbodies, 0), guard(nbodies, 0);
             for (int b = 0; b < nbox; ++b) total_u[boxes[b].body] += n[b];
-            for (int b = 0; b < nbox; ++b)
-                if (total_u[boxes[b].body] - n[b] - counts[2 * b + 1] <= 0) stop[boxes[b].body] = 1;
-            for (int q = 0; q < nbodies; ++q)
-                if (bodies[q].active && bfirst[q] >= 0 && stop[q]) make_root(q);
+            for (int b = 0; b < nbox; ++b) {
+                const int q = boxes[b].body;
+                if (total_u[q] - n[b] - counts[2 * b + 1] <= 0) stop[q] = 1;
+                const int64_t rows = 2 * counts[2 * b + 1] + 4 * static_cast<int64_t>(pcount[b]);
+                if (id_box_over_budget(rows, n[b])) guard[q] = 1;
+                id_entries[q] += rows * n[b];
+            }
+            for (int q = 0; q < nbodies; ++q) {
+                if (!bodies[q].active || bfirst[q] < 0) continue;
+                if (!stop[q] && (guard[q] || id_level_over_budget(id_entries[q]))) {
+                    progress("bmhss build: body %d stops compressing at level %d: its IDs would hold %lld "
+                             "entries (limits %lld per box, %lld per level)\n", q, bodies[q].level,
+                             static_cast<long long>(id_entries[q]), static_cast<long long>(kMaxIdEntries),
+                             static_cast<long long>(kMaxLevelIdEntries));
+                    stop[q] = 1;
+                    ++h->guard_stops;
+                }
+                if (stop[q]) make_root(q);
+            }
         }
         // ---- kept boxes: those of bodies that still compress
         std::vector<int> kept;            // kept index -> box index
@@ -1386,7 +1413,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
         // ---- M_b for every kept box in one generation launch
         double2* M;
         if ((e = sc.alloc(&M, mo[nk])) != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: M"); }
-        std::vector<GenJob> jobs;
+        std::vector<GenJob> jobs, pjobs;   // near blocks; proxy blocks (FP32 with opts.proxy_fp32)
+        std::vector<GenJob>& proxy_jobs = h->opts.proxy_fp32 ? pjobs : jobs;
         for (int c = 0; c < nk; ++c) {
             const int b = kept[c];
             const int32_t body = boxes[b].body;
@@ -1396,13 +1424,15 @@ int build_impl(bm_hss* h, hipStream_t s) {
             jobs.push_back(GenJob{soff[b], near_base + nsoff[b], base, m, 1, na, nn, body});
             jobs.push_back(GenJob{near_base + nsoff[b], soff[b], base + nearu[b], 1, m, nn, na, body});
             const int32_t pb = pcount[b];
-            jobs.push_back(GenJob{soff[b], prox_base + poff[b], base + 2 * nearu[b], m, 1, na, pb, body});
-            jobs.push_back(GenJob{prox_base + poff[b], soff[b], base + 2 * nearu[b] + 2 * pb, 1, m, pb, na, body});
+            proxy_jobs.push_back(GenJob{soff[b], prox_base + poff[b], base + 2 * nearu[b], m, 1, na, pb, body});
+            proxy_jobs.push_back(GenJob{prox_base + poff[b], soff[b], base + 2 * nearu[b] + 2 * pb, 1, m, pb, na, body});
             entries += kn[c] * m;
             pairs += 2 * static_cast<int64_t>(na) * (nn + pb);
         }
         hipEvent_t ev;
         if ((e = t_gen.start(sc, ev)) == hipSuccess) e = launch_gen(sc, jobs, dslots, pt, p->d_media, p->media[0].tab, M);
+        if (e == hipSuccess && !pjobs.empty())
+            e = launch_gen(sc, pjobs, dslots, pt, p->d_media, p->media[0].tab, M, p->d_ftab);
         if (e == hipSuccess) e = t_gen.stop(sc, ev);
         if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: generate M"); }
 
@@ -1833,6 +1863,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
     h->stats.levels = Lmax;
     h->stats.compressed_levels = compressed;
     h->stats.root_size = static_cast<int32_t>(std::min<int64_t>(Ktot, INT32_MAX));
+    h->stats.guard_stops = h->guard_stops;
     h->stats.max_rank = max_rank;
     h->stats.entries = entries;
     h->stats.pairs = pairs;
@@ -2060,10 +2091,10 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
         !(opts->id_tol > 0.0 && opts->id_tol < 1.0) || !std::isfinite(opts->proxy_ratio) ||
         opts->sketch < -1 || opts->sketch > (int64_t{1} << 20) ||
         !(opts->max_rank_ratio == -1.0 || (opts->max_rank_ratio >= 0.0 && opts->max_rank_ratio <= 1.0)) ||
-        opts->kernel_timing < 0 || opts->kernel_timing > 1)
+        opts->kernel_timing < 0 || opts->kernel_timing > 1 || opts->proxy_fp32 < 0 || opts->proxy_fp32 > 1)
         return fail(BM_EINVAL, "bm_hss_build: need leaf >= 4, proxy_ratio > 1, proxy_points >= 8, "
                                "0 < id_tol < 1, sketch -1 or 0..2^20, max_rank_ratio -1 or in [0, 1], "
-                               "kernel_timing 0 or 1");
+                               "kernel_timing 0 or 1, proxy_fp32 0 or 1");
     if (p->g->n > (int64_t{1} << 30)) return fail(BM_EINVAL, "bm_hss_build: N too large");
     const auto t0 = std::chrono::steady_clock::now();
     bm_hss* h = new (std::nothrow) bm_hss;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "internal.hpp"
+#include "wsbm_pair_f32.hpp"
 
 namespace bm {
 namespace hss {
@@ -32,7 +33,9 @@ struct Slot {
 
 // Generate A(targets, sources) for slot lists [tslot, tslot + nt) x
 // [sslot, sslot + ns); entry (row position r, column position c) goes to
-// out[off + r*rs + c*cs] (complex elements).
+// out[off + r*rs + c*cs] (complex elements).  body >= 0: every point of the
+// job belongs to that body; body < 0: each pair takes the body of its node
+// points (zero block across bodies).
 struct GenJob {
     int64_t tslot;
     int64_t sslot;
@@ -41,7 +44,7 @@ struct GenJob {
     int64_t cs;
     int32_t nt;
     int32_t ns;
-    int32_t body;   // every point of the job belongs to this body (its media)
+    int32_t body;   // the body of every point of the job (its media), or -1: per pair
 };
 
 struct CpqrState {
@@ -110,9 +113,12 @@ __global__ void k_near_count(PointTable pt, const Slot* slots, const int32_t* sl
 __global__ void k_near_list(PointTable pt, const Slot* slots, const int32_t* slot_box,
                             const int64_t* scan_lo, const int64_t* scan_hi, const double* box_c,
                             const int64_t* slot_off, Slot* out);
+// R = double: FP64 entries; R = float: FP32 arithmetic (ftab: the FP32
+// coefficient table), widened to FP64 on store
+template <class R>
 __global__ void k_gen_jobs(const GenJob* jobs, const int64_t* tile_off, int njobs,
                            const Slot* slots, PointTable pt, const Media* media, double2* out,
-                           const BesselTable* tab);
+                           const BesselTable* tab, const float* ftab);
 __global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
                          double2* Tbuf);
 // the same for ranks k <= 64 RPL (RPL = 1, 2, 4), logically pivoted jobs only

@@ -223,13 +223,32 @@ k_near_list(PointTable pt, const Slot* __restrict__ slots, const int32_t* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Entry generation for a batch of jobs.  Job j covers nt x ns slot pairs, tiles
-// of kThreads pairs; tile_off is the exclusive prefix sum of the tile counts.
-// One pair per thread, no loop (the Bessel coefficients stay scalar operands).
+// Entry generation for a batch of jobs: every WSBM block the HSS build needs
+// (near, proxy, diagonal and skeleton blocks) and the public block and proxy
+// entry points.  Job j covers nt x ns slot pairs in tiles of kThreads pairs;
+// tile_off is the exclusive prefix sum of the tile counts.  One pair per
+// thread, no loop (the Bessel coefficients stay scalar operands).
+//
+// Pair order: a wave takes 64 consecutive pairs with the source index running
+// fastest, except for jobs stored transposed (rs == 1, cs != 1: the stacked
+// matrix's A(near, U)^T and A(proxy, U)^T parts), where the target index runs
+// fastest so that the wave's stores still land on consecutive positions.  The
+// wave's first pair is split into (slow, fast) indices once per wave with an
+// FP64 reciprocal; the lanes then offset the fast index.
+//
+// Media: a job with body >= 0 uses that body's media for every pair.  With
+// body < 0 (the public entry points) each pair takes the body of its node
+// points -- a proxy point (body < 0 in the point table) takes its partner's --
+// and a pair of nodes in two different bodies is a zero block.
+//
+// R = double: FP64 arithmetic.  R = float: the FP32 formulas of
+// wsbm_pair_f32.hpp (ftab the FP32 coefficient table), results widened to
+// FP64 on store.
+template <class R>
 __global__ void __launch_bounds__(kThreads, kPairWavesPerSimd)
 k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
            const Slot* __restrict__ slots, PointTable pt, const Media* __restrict__ media,
-           double2* __restrict__ out, const BesselTable* __restrict__ tab) {
+           double2* __restrict__ out, const BesselTable* __restrict__ tab, const float* __restrict__ ftab) {
     int lo = 0, hi = njobs;
     const int64_t tile = blockIdx.x;
     while (hi - lo > 1) {
@@ -237,12 +256,24 @@ k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off
         if (tile_off[mid] <= tile) lo = mid; else hi = mid;
     }
     const GenJob jb = jobs[lo];
-    Media m = media[jb.body];
-    m.tab = tab;   // the table through a kernel argument: scalar loads of known global memory
-    const int64_t q = (tile - tile_off[lo]) * kThreads + threadIdx.x;
-    if (q >= static_cast<int64_t>(jb.nt) * jb.ns) return;
-    const int t = static_cast<int>(q / jb.ns);
-    const int s = static_cast<int>(q - static_cast<int64_t>(t) * jb.ns);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t q0 = (tile - tile_off[lo]) * kThreads + 64 * wave;   // the wave's first pair
+    if (q0 + lane >= static_cast<int64_t>(jb.nt) * jb.ns) return;
+    const bool tfast = jb.rs == 1 && jb.cs != 1;
+    const int32_t nf = tfast ? jb.nt : jb.ns;
+    int64_t slow = static_cast<int64_t>(static_cast<double>(q0) * recip(static_cast<double>(nf)));
+    int64_t rem = q0 - slow * nf;
+    if (rem < 0) { --slow; rem += nf; } else if (rem >= nf) { ++slow; rem -= nf; }
+    int32_t fast = static_cast<int32_t>(rem) + lane;
+    if (nf >= 64) {
+        if (fast >= nf) { fast -= nf; ++slow; }
+    } else {
+        slow += fast / nf;
+        fast = fast % nf;
+    }
+    const int32_t t = tfast ? fast : static_cast<int32_t>(slow);
+    const int32_t s = tfast ? static_cast<int32_t>(slow) : fast;
     const Slot ts = slots[jb.tslot + t];
     const Slot ss = slots[jb.sslot + s];
     const int32_t i = ts.pt, j = ss.pt;
@@ -252,30 +283,71 @@ k_gen_jobs(const GenJob* __restrict__ jobs, const int64_t* __restrict__ tile_off
         if (ss.pos0 >= 0) o[row * jb.rs + ss.pos0 * jb.cs] = make_double2(v[0], v[1]);
         if (ss.pos1 >= 0) o[row * jb.rs + ss.pos1 * jb.cs] = make_double2(v[2], v[3]);
     };
-    if (i == j) {
-        const Block b = diag_block(pt.w[j], pt.kappa[j], m);
-        if (ts.pos0 >= 0) put(ts.pos0, {b.v[0], b.v[1], b.v[2], b.v[3]});
-        if (ts.pos1 >= 0) put(ts.pos1, {b.v[4], b.v[5], b.v[6], b.v[7]});
-        return;
+    int body = jb.body;
+    if (body < 0) {
+        const int bi = pt.body[i], bj = pt.body[j];
+        if (bi >= 0 && bj >= 0 && bi != bj) {
+            if (ts.pos0 >= 0) put(ts.pos0, {0.0, 0.0, 0.0, 0.0});
+            if (ts.pos1 >= 0) put(ts.pos1, {0.0, 0.0, 0.0, 0.0});
+            return;
+        }
+        body = bi >= 0 ? bi : bj;
     }
-    // Rows are formed separately: row 2i needs only the interior kernels, and
-    // when a skeleton keeps row 2i alone the exterior ones are never evaluated.
+    Media m = media[body];
+    m.tab = tab;   // the table through a kernel argument: scalar loads of known global memory
     const int32_t ci = pt.curve[i], cj = pt.curve[j];
     const bool interior = ci == cj || ci < 0 || cj < 0;
-    const double sw = pt.w[j];
-    const PairGeom g = pair_geom(pt.x[i], pt.y[i], pt.nx[i], pt.ny[i], pt.x[j], pt.y[j], pt.nx[j],
-                                 pt.ny[j]);
-    const Hankel01 h1 = pair_interior(g, m, interior);
-    double v[4];
-    if (ts.pos0 >= 0) {
-        pair_row0(g, h1, sw, m, v);
-        put(ts.pos0, v);
-    }
-    if (ts.pos1 >= 0) {
-        pair_row1(g, interior_terms(h1, m), sw, m, v);
-        put(ts.pos1, v);
+    if constexpr (sizeof(R) == sizeof(double)) {
+        if (i == j) {
+            const Block b = diag_block(pt.w[j], pt.kappa[j], m);
+            if (ts.pos0 >= 0) put(ts.pos0, {b.v[0], b.v[1], b.v[2], b.v[3]});
+            if (ts.pos1 >= 0) put(ts.pos1, {b.v[4], b.v[5], b.v[6], b.v[7]});
+            return;
+        }
+        // Rows are formed separately: row 2i needs only the interior kernels, and
+        // when a skeleton keeps row 2i alone the exterior ones are never evaluated.
+        const double sw = pt.w[j];
+        const PairGeom g = pair_geom(pt.x[i], pt.y[i], pt.nx[i], pt.ny[i], pt.x[j], pt.y[j], pt.nx[j],
+                                     pt.ny[j]);
+        const Hankel01 h1 = pair_interior(g, m, interior);
+        double v[4];
+        if (ts.pos0 >= 0) {
+            pair_row0(g, h1, sw, m, v);
+            put(ts.pos0, v);
+        }
+        if (ts.pos1 >= 0) {
+            pair_row1(g, interior_terms(h1, m), sw, m, v);
+            put(ts.pos1, v);
+        }
+    } else {
+        const f32::MediaF mf = f32::media_f(m);
+        if (i == j) {
+            const Block b = f32::diag_block(static_cast<float>(pt.w[j]), static_cast<float>(pt.kappa[j]), mf);
+            if (ts.pos0 >= 0) put(ts.pos0, {b.v[0], b.v[1], b.v[2], b.v[3]});
+            if (ts.pos1 >= 0) put(ts.pos1, {b.v[4], b.v[5], b.v[6], b.v[7]});
+            return;
+        }
+        const float sw = static_cast<float>(pt.w[j]);
+        const f32::PairGeomF g = f32::pair_geom(pt.x[i], pt.y[i], static_cast<float>(pt.nx[i]),
+                                                static_cast<float>(pt.ny[i]), pt.x[j], pt.y[j],
+                                                static_cast<float>(pt.nx[j]), static_cast<float>(pt.ny[j]));
+        const f32::Hankel01F h1 = f32::pair_interior(g, mf, interior, tab, ftab);
+        float vf[4];
+        if (ts.pos0 >= 0) {
+            f32::pair_row0(g, h1, sw, mf, vf);
+            put(ts.pos0, {vf[0], vf[1], vf[2], vf[3]});
+        }
+        if (ts.pos1 >= 0) {
+            f32::pair_row1(g, h1, sw, mf, tab, ftab, vf);
+            put(ts.pos1, {vf[0], vf[1], vf[2], vf[3]});
+        }
     }
 }
+
+template __global__ void k_gen_jobs<double>(const GenJob*, const int64_t*, int, const Slot*, PointTable,
+                                            const Media*, double2*, const BesselTable*, const float*);
+template __global__ void k_gen_jobs<float>(const GenJob*, const int64_t*, int, const Slot*, PointTable,
+                                           const Media*, double2*, const BesselTable*, const float*);
 
 // ---------------------------------------------------------------------------
 // Level-batched CPQR by steps, for levels with few, large boxes: per

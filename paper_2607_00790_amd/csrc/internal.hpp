@@ -35,6 +35,8 @@ struct bm_problem {
     int64_t* d_body_lo = nullptr;        // device copy of body_lo
     std::vector<int64_t> tile_off;       // host: first 256 x 256 pair tile of each body (nbodies + 1)
     int64_t* d_tile_off = nullptr;       // device copy of tile_off
+    int32_t* d_body_all = nullptr;       // device, body of each node (zeros for one body)
+    const float* d_ftab = nullptr;       // device FP32 copy of the coefficient table
 };
 
 namespace bm {
@@ -85,13 +87,21 @@ hipError_t launch_geometry(const double* xyd, const int64_t* offsets, int ncurve
 // to the kernels as an argument of its own.
 hipError_t launch_dense(const NodeView& v, int64_t n, const Media* media, const BesselTable* tab, double* A,
                         int64_t ld, hipStream_t s);
-hipError_t launch_block(const NodeView& v, const Media* media, const BesselTable* tab, const int64_t* rows,
-                        int64_t nr, const int64_t* cols, int64_t nc, double* out, int64_t ld, hipStream_t s);
-hipError_t launch_proxy(const NodeView& v, const Media* media, const BesselTable* tab, const int64_t* nodes,
-                        int64_t n, const double* pts, int64_t P, int dir, double* out, int64_t ld,
-                        hipStream_t s);
 hipError_t launch_rhs_plane_wave(const NodeView& v, int64_t n, const Media* media, double angle,
                                  double* rhs, hipStream_t s);
+// rhs (2N complex) from u_in and du_in/dn at the nodes (N complex each)
+hipError_t launch_rhs_incident(const NodeView& v, int64_t n, const Media* media, const double* uin,
+                               const double* dn_uin, double* rhs, hipStream_t s);
+
+// Public block and proxy entry points through the HSS entry generator
+// (gen_api.hip).  body_all: device body of every node (zeros for one body);
+// ftab: the device FP32 coefficient table; prec 0 = FP64, 1 = FP32 arithmetic.
+hipError_t launch_block(const NodeView& v, const int32_t* body_all, const Media* media, const BesselTable* tab,
+                        const float* ftab, const int64_t* rows, int64_t nr, const int64_t* cols, int64_t nc,
+                        int prec, double* out, int64_t ld, hipStream_t s);
+hipError_t launch_proxy(const NodeView& v, int64_t n_nodes, const Media* media, const BesselTable* tab,
+                        const float* ftab, const int64_t* nodes, int64_t n, const double* pts, int64_t P, int dir,
+                        int prec, double* out, int64_t ld, hipStream_t s);
 // matrix-free product over the bodies' diagonal blocks (max_body = largest body
 // in nodes, body_lo = device node offsets of the bodies); `work` is a device
 // buffer of matvec_work_doubles(n, max_body) doubles

@@ -102,6 +102,64 @@ def test_block_index_lists(gpu_lib):
     assert out.shape == (0, 2 * len(cols))
 
 
+def test_block_index_lists_across_bodies(gpu_lib):
+    """Two bodies with their own media: pairs within a body are that body's
+    entries (diagonal pairs corrected), pairs across bodies are zero blocks."""
+    import torch
+    bm = gpu_lib
+    note("block parity: two bodies, cross-body zero blocks")
+    curves = [sc.star(0.3, 5), sc.star(0.2, 3, 1.0, (3.0, 0.5))]
+    sizes = [400, 300]
+    media = [sc.media_from_index(30.0, 1.5), sc.media_from_index(12.0, 1.8)]
+    xyd, s = sc.sample_curves(curves, sizes)
+    g = bm.bm_geom_create(s, xyd)
+    p = bm.bm_problem_create_bodies(g, [0, 1], [(m.k0, m.k1, m.eps0, m.eps1) for m in media])
+    rng = np.random.default_rng(4)
+    rows = np.concatenate([np.arange(390, 420), rng.integers(0, 700, 41)])
+    cols = np.concatenate([np.arange(380, 430), rng.integers(0, 700, 157)])
+    got = to_np(bm.bm_assemble_block(p, torch.from_numpy(rows), torch.from_numpy(cols)))
+    ref = np.zeros((len(rows), 2, len(cols), 2), dtype=np.complex128)
+    lo = [0, 400, 700]
+    for b in range(2):
+        nd = geometry.discretize(*sc.sample_curves([curves[b]], [sizes[b]]))
+        ri = np.nonzero((rows >= lo[b]) & (rows < lo[b + 1]))[0]
+        ci = np.nonzero((cols >= lo[b]) & (cols < lo[b + 1]))[0]
+        blk = wsbm.system_blocks(nd, media[b], rows[ri] - lo[b], cols[ci] - lo[b])
+        ref[np.ix_(ri, [0, 1], ci, [0, 1])] = blk
+    assert_parity(got, ref.reshape(2 * len(rows), 2 * len(cols)))
+
+
+def fp32_error(got, ref):
+    """Largest |diff| / max|ref| over the four 2x2 components."""
+    g = got.reshape(got.shape[0] // 2, 2, got.shape[1] // 2, 2)
+    r = ref.reshape(g.shape)
+    return max(np.abs(g[:, a, :, b] - r[:, a, :, b]).max() / np.abs(r[:, a, :, b]).max()
+               for a in range(2) for b in range(2))
+
+
+# FP32 arithmetic: per 2x2 component, max|diff| <= FP32_BAR max|ref| (entries
+# carry ~1e-7 relative rounding; the near-singular D-type entries, which are
+# small, lose more, which the component-wise max norm allows).
+FP32_BAR = 1e-6
+
+
+def test_block_index_lists_fp32(gpu_lib):
+    import torch
+    bm = gpu_lib
+    note("block parity, FP32 arithmetic (prec 1)")
+    xyd, s, nd = case([sc.star(0.3, 5)], [2000])
+    media = sc.media_from_index(50.0, 1.5)
+    p = gpu_problem(bm, xyd, s, media)
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([np.arange(100, 140), rng.integers(0, 2000, 27)])
+    cols = np.concatenate([np.arange(90, 150), rng.integers(0, 2000, 300)])
+    got = to_np(bm.bm_assemble_block(p, torch.from_numpy(rows), torch.from_numpy(cols), prec=1))
+    ref = wsbm.system_blocks(nd, media, rows, cols).reshape(2 * len(rows), 2 * len(cols))
+    err = fp32_error(got, ref)
+    note(f"  FP32 block: max component error {err:.2e} of max|A|")
+    assert err <= FP32_BAR
+
+
 @pytest.mark.parametrize("direction", [0, 1])
 def test_proxy_blocks(gpu_lib, direction):
     import torch
@@ -127,6 +185,39 @@ def test_proxy_blocks(gpu_lib, direction):
         ref = wsbm.pair_blocks(px, pn, nd.x[box], nd.n[box], nd.w[box], media)
         ref = ref.reshape(2 * P, 2 * len(box))
     assert_parity(got, ref)
+    got32 = to_np(bm.bm_assemble_proxy(p, torch.from_numpy(box), pts, direction, prec=1))
+    err = fp32_error(got32, ref)
+    note(f"  FP32 proxy dir {direction}: max component error {err:.2e} of max|A|")
+    assert err <= FP32_BAR
+
+
+def test_rhs_incident_point_source(gpu_lib):
+    """bm_rhs_incident from a point source's field and normal derivative (the
+    oracle's values) against the oracle's right-hand side, on two bodies."""
+    import torch
+    bm = gpu_lib
+    note("rhs parity: point-source incident field, two bodies")
+    curves = [sc.star(0.3, 5), sc.circle(0.5, (3.0, 0.0))]
+    sizes = [700, 129]
+    media = [sc.media_from_index(30.0, 1.5), sc.media_from_index(15.0, 1.2)]
+    xyd, s = sc.sample_curves(curves, sizes)
+    g = bm.bm_geom_create(s, xyd)
+    p = bm.bm_problem_create_bodies(g, [0, 1], [(m.k0, m.k1, m.eps0, m.eps1) for m in media])
+    ref, uins, dns = [], [], []
+    for b in range(2):
+        nd = geometry.discretize(*sc.sample_curves([curves[b]], [sizes[b]]))
+        uin, dn = wsbm.point_source_field(nd, media[b].k0, (1.2, 2.1))
+        uins.append(uin)
+        dns.append(dn)
+        ref.append(wsbm.rhs_incident(nd, media[b], uin, dn))
+    ref = np.concatenate(ref)
+    uin = torch.from_numpy(np.concatenate(uins)).cuda()
+    dn = torch.from_numpy(np.concatenate(dns)).cuda()
+    got = to_np(bm.bm_rhs_incident(p, uin, dn))
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+    with pytest.raises(bm.BmError) as ei:
+        bm.bm_rhs_incident(p, uin, dn, out=uin)
+    assert ei.value.code == 1
 
 
 def test_rhs_matvec_far_field(gpu_lib):
@@ -180,6 +271,8 @@ def test_invalid_arguments_enqueue_nothing(gpu_lib):
         bm.bm_assemble_dense(p, out=torch.empty((128, 100), dtype=torch.complex128, device="cuda"))
     with pytest.raises(bm.BmError):
         bm.bm_assemble_proxy(p, torch.arange(4), torch.zeros((5, 3), dtype=torch.float64).cuda(), 2)
+    with pytest.raises(bm.BmError):
+        bm.bm_assemble_block(p, torch.arange(4), torch.arange(4), prec=2)
 
 
 def test_fp64_fma_probe_values(gpu_lib):

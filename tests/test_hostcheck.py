@@ -30,6 +30,8 @@ def hc():
     lib.bmh_bessel01.argtypes = [vp, i64, vp]
     lib.bmh_sincos.argtypes = [vp, i64, vp]
     lib.bmh_system_blocks.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
+    lib.bmh_system_blocks_f32.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
+    lib.bmh_id_guard.argtypes = [i64, i64, i64]
     return lib
 
 
@@ -127,6 +129,59 @@ def test_pair_blocks_match_oracle(hc, case):
     got = host_blocks(hc, nd, media, rows, cols)
     ref = wsbm.system_blocks(nd, media, rows, cols).reshape(2 * len(rows), 2 * len(cols))
     assert_parity(got, ref)
+
+
+@pytest.mark.parametrize("case", ["star1000", "two_curves", "star16384_rows"])
+def test_fp32_pair_blocks_match_oracle(hc, case):
+    """The FP32 entry path (wsbm_pair_f32.hpp, compiled for the host) against
+    the FP64 oracle: per 2x2 component, max|diff| <= 1e-6 max|ref| -- FP32
+    rounding of ~1e-7 relative per entry (r and the phase k r are FP64),
+    amplified in the D-type entries of close pairs, which are small."""
+    if case == "star1000":
+        nd, media = nodes_for([sc.star(0.3, 5)], [1000]), sc.media_from_index(50.0, 1.5)
+        rows = cols = np.arange(1000)
+    elif case == "two_curves":
+        nd = nodes_for([sc.star(0.2, 4), sc.star(0.25, 3, 1.0, (3.0, 0.5))], [300, 200])
+        media = sc.media_from_index(20.0, 2.0)
+        rows = cols = np.arange(500)
+    else:
+        wl = sc.star_workload()
+        nd, media = nodes_for(wl.curves, wl.sizes), wl.media
+        rng = np.random.default_rng(1)
+        rows = np.concatenate([[0, 1, 16383], rng.integers(0, 16384, 13)])
+        cols = np.arange(16384)
+    soa = np.ascontiguousarray(np.stack([nd.x[:, 0], nd.x[:, 1], nd.n[:, 0], nd.n[:, 1], nd.w, nd.kappa]))
+    curve = np.ascontiguousarray(nd.curve.astype(np.int32))
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    c = np.ascontiguousarray(cols, dtype=np.int64)
+    md = np.array([media.k0, media.k1, media.eps0, media.eps1])
+    got = np.empty((2 * len(r), 2 * len(c)), dtype=np.complex128)
+    hc.bmh_system_blocks_f32(soa.ctypes.data, curve.ctypes.data, nd.size, r.ctypes.data, len(r), c.ctypes.data,
+                             len(c), md.ctypes.data, got.ctypes.data)
+    ref = wsbm.system_blocks(nd, media, rows, cols).reshape(2 * len(rows), 2 * len(cols))
+    g = got.reshape(len(r), 2, len(c), 2)
+    f = ref.reshape(g.shape)
+    for a in range(2):
+        for b in range(2):
+            err = np.abs(g[:, a, :, b] - f[:, a, :, b]).max() / np.abs(f[:, a, :, b]).max()
+            assert err <= 1e-6, (a, b, err)
+    # cross-curve pairs keep no interior terms: the first row is exactly zero
+    if case == "two_curves":
+        assert np.all(g[:300, 0, 300:, :] == 0)
+
+
+def test_id_work_guard_decisions(hc):
+    """The ID work guard (host-side planning from sizes): the top-level ID that
+    never finished (two boxes of 19096 unknowns x 62236 rows) is stopped; the
+    levels the benchmark and the large workload compress are not."""
+    g = hc.bmh_id_guard
+    assert g(62236, 19096, 2 * 62236 * 19096) == 3
+    assert g(684, 188, 72 * 684 * 188) == 0           # leaf level of the batched forest
+    assert g(760, 260, 4 * 760 * 260) == 0
+    assert g(4000, 1400, 256 * 4000 * 1400) == 0      # the large workload's last compressed level
+    assert g(12000, 4096, 64 * 12000 * 4096) == 2     # fine per box, too much for one level
+    assert g(2 ** 26, 1, 2 ** 26) == 0 and g(2 ** 26 + 1, 1, 2 ** 26 + 1) == 1
+    assert g(0, 0, 0) == 0
 
 
 # ---------------------------------------------------------------------------
