@@ -179,6 +179,7 @@ struct Scratch {
         return hipSuccess;
     }
     void rec(std::function<hipError_t()> f) { cmds.push_back(std::move(f)); }
+    std::vector<hipEvent_t> events;   // events the recorded commands use, destroyed on release
     bool uses_blas = false;   // a recorded command calls rocBLAS
     bool allow_blas = true;   // false: every product stays in the tile kernel (graph capture)
     // the host-to-device copies of the uploads so far
@@ -223,6 +224,8 @@ struct Scratch {
         dev.clear();
         for (Chunk& c : chunks) pinned_cache().put(c.h, c.cap);
         chunks.clear();
+        for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
+        events.clear();
     }
 };
 
@@ -290,6 +293,7 @@ hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const 
 }
 
 hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs);
+int gemm_tile_for(const std::vector<GemmJob>& jobs);
 
 // Per-launch HIP-event timing of the batched GEMM and Gauss-Jordan kernels
 // during a build with opts.kernel_timing set: the launchers record an event
@@ -447,8 +451,26 @@ hipError_t launch_gemm(Scratch& sc, const std::vector<GemmJob>& jobs) {
         narrow, gemv_tiles, [&](const std::vector<GemmJob>& g) { return launch_gemv_group(sc, g); });
     if (e != hipSuccess) return e;
     return launch_in_groups(
-        tiled, [](const GemmJob& j) { return ceil_div(j.M, 32) * ceil_div(j.N, 32); },
+        tiled, [](const GemmJob& j) { return ceil_div(j.M, 16) * ceil_div(j.N, 16); },
         [&](const std::vector<GemmJob>& g) { return launch_gemm_group(sc, g); });
+}
+
+// The tile of the matrix-core GEMM for a launch: 64 x 64 (four waves) when the
+// products are large enough to keep the device busy with them (the operands
+// are then read half as often), else 32 x 32, else 16 x 16 when even 32 x 32
+// tiles would leave most compute units idle (short, wide products such as a
+// 64-row panel times the whole root).
+int gemm_tile_for(const std::vector<GemmJob>& jobs) {
+    int64_t t32 = 0, t64 = 0;
+    int mn = INT32_MAX;
+    for (const GemmJob& g : jobs) {
+        t32 += ceil_div(g.M, 32) * ceil_div(g.N, 32);
+        t64 += ceil_div(g.M, 64) * ceil_div(g.N, 64);
+        mn = std::min(mn, std::min(g.M, g.N));
+    }
+    if (mn >= 64 && t64 >= 512) return 64;
+    if (t32 >= 512) return 32;
+    return 16;
 }
 
 int64_t gemv_tiles(const GemmJob& j) {
@@ -477,9 +499,10 @@ hipError_t launch_gemv_group(Scratch& sc, const std::vector<GemmJob>& jobs) {
 
 hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs) {
     if (jobs.empty()) return hipSuccess;
+    const int tt = gemm_tile_for(jobs);
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
-        toff[j + 1] = toff[j] + ceil_div(jobs[j].M, 32) * ceil_div(jobs[j].N, 32);
+        toff[j + 1] = toff[j] + ceil_div(jobs[j].M, tt) * ceil_div(jobs[j].N, tt);
     if (toff.back() == 0) return hipSuccess;
     GemmJob* dj;
     int64_t* dt;
@@ -494,7 +517,12 @@ hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs) {
         for (const GemmJob& g : jobs) g_ktimes->gemm_flops += 8.0 * g.M * g.N * g.K;
     sc.rec([=]() {
         if (ea) (void)hipEventRecord(ea, st);
-        hipLaunchKernelGGL(k_gemm, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj);
+        if (tt == 64)
+            hipLaunchKernelGGL(k_gemm_t64, dim3(grid), dim3(256), 0, st, dj, dt, nj);
+        else if (tt == 32)
+            hipLaunchKernelGGL(k_gemm, dim3(grid), dim3(64), 0, st, dj, dt, nj);
+        else
+            hipLaunchKernelGGL(k_gemm_t16, dim3(grid), dim3(64), 0, st, dj, dt, nj);
         if (eb) (void)hipEventRecord(eb, st);
         return hipGetLastError();
     });
@@ -707,6 +735,25 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
     return launch_gemm(sc, g4);
 }
 
+// A second stream per device for the look-ahead of the panel inverse
+// (non-blocking, default priority, kept for the life of the process).
+hipError_t lookahead_stream(hipStream_t* out) {
+    static std::mutex mu;
+    static std::unordered_map<int, hipStream_t> streams;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it == streams.end()) {
+        hipStream_t st = nullptr;
+        if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
+        it = streams.emplace(dev, st).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
 // Inversion of one large matrix (the dense root of a one-body problem) by
 // block Gauss-Jordan elimination over panels of b = inv_base() columns.  Per
 // panel p the diagonal block is inverted in place by the pivoted Gauss-Jordan
@@ -714,43 +761,106 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
 // product of rank b:
 //   A_pc <- P A_pc,   A_ic <- A_ic - A_ip P A_pc,   A_ip <- -A_ip P   (i, c != p).
 // As in the Schur recursion, rows are pivoted within the diagonal blocks only
-// (the same elimination, in another order); the serial chain is one
-// Gauss-Jordan launch and two products per panel instead of a deep recursion
-// of small products.  The products read copies: L = A[:, p] with its block p
-// cleared, Pt = P, and R = Pt A[p, :] taken after A_pp is set to I (so that
-// R_pp = P); A[:, p] is cleared off the diagonal block, A -= L R, and R
-// becomes row block p.
+// (the same elimination, in another order).  Per panel: the diagonal block's
+// inverse; k_panel_prep (L = A[:, p] without rows p, Pt = P, A[:, p] =
+// [0; I; 0]); R = Pt A[p, :] (which holds P in its columns p); then
+// A[i, :] -= L_i R above and below the panel and A[p, :] = I R, products on
+// the matrix cores.
+// Look-ahead: that update is split.  The caller's stream updates only the
+// next panel's block column, so the next diagonal inverse can start at once;
+// a second stream updates every other column meanwhile.  The next panel's R
+// waits for it (it reads the whole row block).  L and R alternate between two
+// buffers: a buffer is written again only after the second stream's update
+// that read it is known complete.
 hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
     const int64_t K = j.n, ld = j.ld, b0 = std::min<int64_t>(inv_base(), K);
-    const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
-    double2 *L, *Pt, *R, *zero, *eye;
+    const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0), zero = make_double2(0.0, 0.0);
+    double2 *L[2], *Pt, *R[2], *eye;
     hipError_t e = hipSuccess;
-    if ((e = sc.alloc(&L, K * b0)) != hipSuccess) return e;
+    for (int q = 0; q < 2; ++q) {
+        if ((e = sc.alloc(&L[q], K * b0)) != hipSuccess) return e;
+        if ((e = sc.alloc(&R[q], b0 * K)) != hipSuccess) return e;
+    }
     if ((e = sc.alloc(&Pt, b0 * b0)) != hipSuccess) return e;
-    if ((e = sc.alloc(&R, b0 * K)) != hipSuccess) return e;
     {
-        std::vector<double2> z(1, make_double2(0.0, 0.0)), id(static_cast<size_t>(b0 * b0), make_double2(0.0, 0.0));
+        std::vector<double2> id(static_cast<size_t>(b0 * b0), zero);
         for (int64_t q = 0; q < b0; ++q) id[q * b0 + q] = one;
-        if ((e = sc.upload(&zero, z)) != hipSuccess) return e;
         if ((e = sc.upload(&eye, id)) != hipSuccess) return e;
     }
-    auto cp = [](const double2* src, double2* dst, int64_t srs, int64_t scs, int64_t drs, int64_t dcs,
-                 int64_t rows, int64_t cols) {
-        return CopyJob{src, dst, srs, scs, drs, dcs, static_cast<int32_t>(rows), static_cast<int32_t>(cols)};
+    hipStream_t sa = sc.s, sb = nullptr;
+    if ((e = lookahead_stream(&sb)) != hipSuccess) return e;
+    // every product of the panels stays in the library's matrix-core kernel
+    struct Restore {
+        Scratch& sc;
+        bool blas;
+        hipStream_t s;
+        ~Restore() {
+            sc.allow_blas = blas;
+            sc.s = s;
+        }
+    } restore{sc, sc.allow_blas, sc.s};
+    sc.allow_blas = false;
+    // the update jobs of panel (o, b) for the columns [c0, c1): rows above and
+    // below the panel, and the panel's own rows (= R)
+    auto update_jobs = [&](std::vector<GemmJob>& jobs, int64_t o, int64_t b, const double2* Lp, const double2* Rp,
+                           int64_t c0, int64_t c1) {
+        if (c1 <= c0) return;
+        const int64_t nc = c1 - c0;
+        if (o > 0) jobs.push_back(gemm(Lp, b, 1, Rp + c0, K, 1, j.a + c0, ld, 1, o, nc, b, mone, one));
+        if (o + b < K)
+            jobs.push_back(gemm(Lp + (o + b) * b, b, 1, Rp + c0, K, 1, j.a + (o + b) * ld + c0, ld, 1, K - o - b, nc,
+                                b, mone, one));
+        jobs.push_back(gemm(eye, b0, 1, Rp + c0, K, 1, j.a + o * ld + c0, ld, 1, b, nc, b, one, zero));
     };
-    for (int64_t o = 0; o < K; o += b0) {
+    hipEvent_t upd_done = nullptr;   // the second stream's update of the previous panel
+    int buf = 0;
+    for (int64_t o = 0; o < K; o += b0, buf ^= 1) {
         const int64_t b = std::min(b0, K - o);
         double2* App = j.a + o * ld + o;
         if ((e = launch_inverse(sc, {InvJob{App, j.status, ld, static_cast<int32_t>(b)}})) != hipSuccess) return e;
-        if ((e = launch_copy(sc, {cp(j.a + o, L, ld, 1, b, 1, K, b), cp(App, Pt, ld, 1, b, 1, b, b)})) != hipSuccess)
-            return e;
-        std::vector<CopyJob> clr{cp(eye, App, b0, 1, ld, 1, b, b), cp(zero, L + o * b, 0, 0, b, 1, b, b)};
-        if (o > 0) clr.push_back(cp(zero, j.a + o, 0, 0, ld, 1, o, b));
-        if (o + b < K) clr.push_back(cp(zero, j.a + (o + b) * ld + o, 0, 0, ld, 1, K - o - b, b));
-        if ((e = launch_copy(sc, clr)) != hipSuccess) return e;
-        if ((e = launch_gemm(sc, {gemm(Pt, b, 1, j.a + o * ld, ld, 1, R, K, 1, b, K, b)})) != hipSuccess) return e;
-        if ((e = launch_gemm(sc, {gemm(L, b, 1, R, K, 1, j.a, ld, 1, K, K, b, mone, one)})) != hipSuccess) return e;
-        if ((e = launch_copy(sc, {cp(R, j.a + o * ld, K, 1, ld, 1, b, K)})) != hipSuccess) return e;
+        {
+            double2* a = j.a;
+            double2* Lp = L[buf];
+            const unsigned grid = static_cast<unsigned>(std::min<int64_t>(ceil_div(K * b, kThreads), 2048));
+            const int bb = static_cast<int>(b);
+            sc.rec([=]() {
+                hipLaunchKernelGGL(k_panel_prep, dim3(grid), dim3(kThreads), 0, sa, a, ld, K, o, bb, Lp, Pt);
+                return hipGetLastError();
+            });
+        }
+        if (upd_done) {
+            hipEvent_t ev = upd_done;
+            sc.rec([=]() { return hipStreamWaitEvent(sa, ev, 0); });
+        }
+        if ((e = launch_gemm(sc, {gemm(Pt, b, 1, j.a + o * ld, ld, 1, R[buf], K, 1, b, K, b)})) != hipSuccess) return e;
+        const int64_t on = o + b, bn = std::min(b0, K - on);   // the next panel
+        if (bn <= 0) {
+            std::vector<GemmJob> upd;
+            update_jobs(upd, o, b, L[buf], R[buf], 0, K);
+            if ((e = launch_gemm(sc, upd)) != hipSuccess) return e;
+            break;
+        }
+        std::vector<GemmJob> next, rest;
+        update_jobs(next, o, b, L[buf], R[buf], on, on + bn);
+        if ((e = launch_gemm(sc, next)) != hipSuccess) return e;
+        hipEvent_t ready = nullptr, done = nullptr;
+        if ((e = hipEventCreateWithFlags(&ready, hipEventDisableTiming)) != hipSuccess) return e;
+        sc.events.push_back(ready);
+        if ((e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess) return e;
+        sc.events.push_back(done);
+        sc.rec([=]() {
+            hipError_t r = hipEventRecord(ready, sa);
+            if (r == hipSuccess) r = hipStreamWaitEvent(sb, ready, 0);
+            return r;
+        });
+        update_jobs(rest, o, b, L[buf], R[buf], 0, on);
+        update_jobs(rest, o, b, L[buf], R[buf], on + bn, K);
+        sc.s = sb;   // these products go to the second stream
+        e = launch_gemm(sc, rest);
+        sc.s = sa;
+        if (e != hipSuccess) return e;
+        sc.rec([=]() { return hipEventRecord(done, sb); });
+        upd_done = done;
     }
     return hipSuccess;
 }

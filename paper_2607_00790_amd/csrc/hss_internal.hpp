@@ -146,7 +146,12 @@ __global__ void k_cpqr_fused(const CpqrJob* jobs, double tol);
 __global__ void k_cpqr_finish(const CpqrJob* jobs);
 __global__ void k_cpqr_ranks(const CpqrJob* jobs, int nb, int32_t* ranks, int32_t* active);
 
+// batched strided complex GEMM on the FP64 matrix cores, one tile of C per
+// workgroup: 16 x 16 (k_gemm_t16, one wave), 32 x 32 (k_gemm, one wave) or
+// 64 x 64 (k_gemm_t64, four waves)
+__global__ void k_gemm_t16(const GemmJob* jobs, const int64_t* tile_off, int njobs);
 __global__ void k_gemm(const GemmJob* jobs, const int64_t* tile_off, int njobs);
+__global__ void k_gemm_t64(const GemmJob* jobs, const int64_t* tile_off, int njobs);
 // products with at most kGemvMaxN columns whose A has unit row or column stride;
 // a tile is kGemvRows rows (wave per row when a_cs == 1) or kThreads rows
 constexpr int kGemvMaxN = 4;
@@ -160,6 +165,9 @@ __global__ void k_sketch(const SketchJob* jobs, const int64_t* tile_off, int njo
 // y[e] = sum over s < ns of part[s * stride + e], e < len
 __global__ void k_sum_partials(const double2* part, int ns, int64_t stride, int64_t len, double2* y);
 __global__ void k_copy_blocks(const CopyJob* jobs);
+// the panel step of the block Gauss-Jordan inverse (after the diagonal block's
+// inverse): L = A[:, p] without rows p, Pt = A_pp, A[:, p] = [0; I; 0]
+__global__ void k_panel_prep(double2* A, int64_t ld, int64_t K, int64_t o, int b, double2* L, double2* Pt);
 
 }  // namespace hss
 }  // namespace bm

@@ -1001,11 +1001,211 @@ __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Blocked Gauss-Jordan inverse of an n x n block, n <= 64, one workgroup of
+// 256 threads (thread (ty, tx) keeps the 4 x 4 complex tile of rows 4ty..,
+// columns 4tx..).  The same elimination as gauss_jordan_tiles (partial row
+// pivoting over the whole block, logical pivoting, the same result layout),
+// reordered into macro-steps of kGjPanel columns so that the serial part runs
+// in one wave without barriers:
+//   1. the tiles of the panel (columns k0..k0+3) go to LDS;
+//   2. wave 0 holds the panel by rows (lane = row) and eliminates its columns
+//      one by one -- pivot search (a wave maximum), scaled pivot
+//      row, rank-1 update of the panel only -- giving F: at the pivot rows P
+//      the inverse of A[P, panel], elsewhere -A[i, panel] A[P, panel]^-1;
+//   3. the pivot rows of every other column go to LDS (T = X[P]);
+//   4. every tile outside the panel becomes X[i] = (i in P ? 0 : X[i]) + F[i] T,
+//      a rank-4 update; the panel's tiles take F.
+// Three barriers per four columns instead of two per column.  The pivot search
+// compares |a|^2 scaled by the block's largest |a_ij|^2, rounded to FP32 (one
+// DPP maximum per step; magnitudes within 6e-8 of each other count as ties,
+// which go to the lowest row).  A pivot with |a|^2 <= (64 eps)^2 max |a_ij|^2
+// of the input block, or a non-finite one, sets the job's status flag; the
+// whole workgroup then leaves without writing the block.  The LDS rows are
+// padded (panel, F) or laid out by column (T) so that the lanes' 16-byte
+// accesses fall on distinct banks.
+namespace {
+constexpr int kGjPanel = 4;
+
+__device__ __forceinline__ double2 readlane2(double2 v, int l) {
+    return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
+}
+
+// max(v, v from the lane DPP control CTRL selects), lanes without a source
+// keeping v: one step of a wave maximum (VOP2 with a DPP source).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_fmax(float v) {
+    const int o = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+    return fmaxf(v, __int_as_float(o));
+}
+
+// The lowest lane holding the wave's largest value of `mag` (wave-uniform);
+// -1 if no lane holds a positive value.
+__device__ __forceinline__ int wave_argmax_f32(float mag) {
+    float m = dpp_fmax<0x111, 0xF>(mag);   // row_shr:1
+    m = dpp_fmax<0x112, 0xF>(m);           // row_shr:2
+    m = dpp_fmax<0x114, 0xF>(m);           // row_shr:4
+    m = dpp_fmax<0x118, 0xF>(m);           // row_shr:8   -> lane 15 of each row
+    m = dpp_fmax<0x142, 0xA>(m);           // row_bcast:15
+    m = dpp_fmax<0x143, 0xC>(m);           // row_bcast:31 -> lane 63: the maximum
+    const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 63));
+    if (!(mx > 0.0f)) return -1;
+    const uint64_t hit = __builtin_amdgcn_ballot_w64(mag == mx);
+    return static_cast<int>(__builtin_ctzll(hit));
+}
+
+__device__ void gauss_jordan_blocked64(const InvJob& jb) {
+    constexpr int TG = 16, NMAX = 64, PADP = kGjPanel + 1;
+    __shared__ double2 panel[NMAX][PADP];
+    __shared__ double2 fpan[NMAX][PADP];
+    __shared__ double2 trow[kGjPanel][4][TG];   // T[m][4 tx + c] at trow[m][c][tx]
+    __shared__ int4 piv4;
+    __shared__ int perm[NMAX], pinv[NMAX];
+    __shared__ int flag;
+    __shared__ double wmax[kThreads / 64];
+    const int n = jb.n;
+    const int64_t ld = jb.ld;
+    const int tid = threadIdx.x, ty = tid / TG, tx = tid % TG, lane = tid & 63, wave = tid >> 6;
+    const int r0 = 4 * ty, c0 = 4 * tx;
+    double2 S[4][4];
+    double m2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = r0 + r, j = c0 + c;
+            S[r][c] = (i < n && j < n) ? gload2(jb.a + i * ld + j) : make_double2(0.0, 0.0);
+            m2 = fmax(m2, cabs2(S[r][c]));
+        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m2 = fmax(m2, __shfl_xor(m2, off, 64));
+    if (lane == 0) wmax[wave] = m2;
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    m2 = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    const double tiny2 = (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16) * m2;
+    const double rscale = m2 > 0.0 ? recip(m2) : 0.0;
+    uint64_t used = 0;   // pivot rows so far (the same value in every thread)
+    for (int k0 = 0; k0 < n; k0 += kGjPanel) {
+        const int kb = k0 / kGjPanel, nb = min(kGjPanel, n - k0);
+        if (tx == kb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) panel[r0 + r][c] = S[r][c];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double2 pr[kGjPanel];
+#pragma unroll
+            for (int c = 0; c < kGjPanel; ++c) pr[c] = panel[lane][c];
+            bool bad = false;
+#pragma unroll
+            for (int m = 0; m < kGjPanel; ++m) {
+                if (m >= nb || bad) continue;   // uniform; no break, so the loop unrolls fully
+                const bool cand = lane < n && !((used >> lane) & 1);
+                const float mag = cand ? static_cast<float>(cabs2(pr[m]) * rscale) : -1.0f;
+                const int p = wave_argmax_f32(mag);
+                const double2 pv = readlane2(pr[m], p < 0 ? 0 : p);
+                const double pd = cabs2(pv);
+                if (p < 0 || !(pd > tiny2) || !(pd < INFINITY)) {
+                    bad = true;
+                    continue;
+                }
+                used |= 1ull << p;
+                const double rpd = recip(pd);
+                const double2 inv = make_double2(pv.x * rpd, -pv.y * rpd);
+                double2 u[kGjPanel];
+#pragma unroll
+                for (int c = 0; c < kGjPanel; ++c) u[c] = (c == m) ? inv : cmul(readlane2(pr[c], p), inv);
+                const double2 f = pr[m];
+                const bool isp = lane == p;
+#pragma unroll
+                for (int c = 0; c < kGjPanel; ++c) {
+                    const double2 base = (c == m) ? make_double2(0.0, 0.0) : pr[c];
+                    const double2 upd = make_double2(fma(-f.x, u[c].x, fma(f.y, u[c].y, base.x)),
+                                                     fma(-f.x, u[c].y, fma(-f.y, u[c].x, base.y)));
+                    pr[c] = isp ? u[c] : upd;
+                }
+                if (lane == 0) {
+                    (&piv4.x)[m] = p;
+                    perm[k0 + m] = p;
+                    pinv[p] = k0 + m;
+                }
+            }
+            if (bad && lane == 0) flag = 1;
+#pragma unroll
+            for (int c = 0; c < kGjPanel; ++c) fpan[lane][c] = pr[c];
+        }
+        __syncthreads();
+        if (flag) {
+            if (tid == 0) gst(jb.status, 1);
+            return;   // every thread read the same flag after the barrier
+        }
+        uint64_t pmask = 0;   // this macro-step's pivot rows
+        const int4 pv4 = piv4;
+        const int pvs[kGjPanel] = {pv4.x, pv4.y, pv4.z, pv4.w};
+#pragma unroll
+        for (int m = 0; m < kGjPanel; ++m) {
+            if (m >= nb) continue;
+            const int p = pvs[m];
+            pmask |= 1ull << p;
+            const int rp = p - r0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r == rp) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) trow[m][c][tx] = S[r][c];
+                }
+        }
+        used |= pmask;
+        __syncthreads();
+        if (tx == kb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) S[r][c] = fpan[r0 + r][c];
+        } else {
+            double2 T[kGjPanel][4];
+#pragma unroll
+            for (int m = 0; m < kGjPanel; ++m)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) T[m][c] = m < nb ? trow[m][c][tx] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double2 F[kGjPanel];
+#pragma unroll
+                for (int m = 0; m < kGjPanel; ++m) F[m] = m < nb ? fpan[r0 + r][m] : make_double2(0.0, 0.0);
+                const bool inp = (pmask >> (r0 + r)) & 1;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double2 acc = inp ? make_double2(0.0, 0.0) : S[r][c];
+#pragma unroll
+                    for (int m = 0; m < kGjPanel; ++m) acc = cfma(F[m], T[m][c], acc);
+                    S[r][c] = acc;
+                }
+            }
+        }
+    }
+    __syncthreads();   // perm / pinv complete
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = r0 + r;
+        if (i >= n) continue;
+        double2* out = jb.a + pinv[i] * ld;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c0 + c < n) gstore2(out + perm[c0 + c], S[r][c]);
+    }
+}
+
+}  // namespace
+
 __global__ void __launch_bounds__(64) k_gauss_jordan_8(const InvJob* __restrict__ jobs) {
     gauss_jordan_tiles<8>(jobs[blockIdx.x]);
 }
 __global__ void __launch_bounds__(256) k_gauss_jordan_16(const InvJob* __restrict__ jobs) {
-    gauss_jordan_tiles<16>(jobs[blockIdx.x]);
+    gauss_jordan_blocked64(jobs[blockIdx.x]);
 }
 __global__ void __launch_bounds__(1024) k_gauss_jordan_32(const InvJob* __restrict__ jobs) {
     gauss_jordan_tiles<32>(jobs[blockIdx.x]);
@@ -1111,14 +1311,37 @@ k_sum_partials(const double2* __restrict__ part, int ns, int64_t stride, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Batched strided complex GEMM: C = alpha A B + beta C with element (i, j) of X
-// at X[i*rs + j*cs].  32 x 32 output tile per workgroup, K in steps of 16.
-constexpr int TM = 32, TN = 32, TK = 16;
+// Batched strided complex GEMM on the FP64 matrix cores: C = alpha A B + beta C
+// with element (i, j) of X at X[i*rs + j*cs].  A workgroup of NW waves (1, or 4
+// as 2 x 2) computes one TT x TT tile of C, TT = WT sqrt(NW); each wave owns a
+// WT x WT part of it as (WT/16)^2 blocks of 16 x 16, updated by
+// v_mfma_f64_16x16x4f64: per 4-deep step of K and block, four real products
+// (re re, -im im into the real part; re im, im re into the imaginary part).
+// K runs in chunks of kGemmK through LDS, real and imaginary parts in separate
+// arrays, the next chunk's loads issued before the current chunk's products.
+// Small tiles give the many small per-box products (and short, wide ones) enough
+// waves; the 64 x 64 tiles halve the operand traffic of the large products.
+//
+// Operand layout of v_mfma_f64_16x16x4f64 (one double per lane; taken from a
+// probe on the device that fed unit vectors through every lane pair): lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l
+// holds D[4 r + l / 16][l % 16].
+namespace {
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kGemmK = 8;
 
-__global__ void __launch_bounds__(kThreads)
-k_gemm(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
-    __shared__ double2 As[TM][TK + 1];
-    __shared__ double2 Bs[TK][TN + 1];
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int WT, int NW>
+__device__ __forceinline__ void gemm_tile(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off,
+                                          int njobs) {
+    constexpr int SQ = NW == 4 ? 2 : 1, TT = WT * SQ, BL = WT / 16, THREADS = 64 * NW;
+    constexpr int LOADS = TT * kGemmK / THREADS;   // elements of each operand per thread and chunk
+    static_assert(LOADS * THREADS == TT * kGemmK && THREADS % TT == 0, "tile shape");
+    __shared__ double Ar[kGemmK][TT], Ai[kGemmK][TT];   // A tile, k-major
+    __shared__ double Br[kGemmK][TT], Bi[kGemmK][TT];   // B tile, k-major
     int lo = 0, hi = njobs;
     const int64_t tile = blockIdx.x;
     while (hi - lo > 1) {
@@ -1127,52 +1350,103 @@ k_gemm(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, i
     }
     const GemmJob g = jobs[lo];
     const int64_t local = tile - tile_off[lo];
-    const int tiles_n = (g.N + TN - 1) / TN;
-    const int i0 = static_cast<int>(local / tiles_n) * TM;
-    const int j0 = static_cast<int>(local % tiles_n) * TN;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;   // 16 x 16 threads, 2 x 2 outputs
-    double2 acc[2][2];
+    const int tiles_n = (g.N + TT - 1) / TT;
+    const int i0 = static_cast<int>(local / tiles_n) * TT;
+    const int j0 = static_cast<int>(local % tiles_n) * TT;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w / SQ) * WT, wc = (w % SQ) * WT;   // the wave's part of the tile
+    const int fl = lane & 15, fk = lane >> 4;           // fragment row/column and k index
+    // chunk loads: consecutive threads along the contiguous index of each operand;
+    // element q of a thread is (base index + q * step) of the tile
+    const bool a_kfast = g.a_cs == 1, b_kfast = g.b_rs == 1;
+    const int ia0 = a_kfast ? tid / kGemmK : tid % TT, ka0 = a_kfast ? tid % kGemmK : tid / TT;
+    const int jb0 = b_kfast ? tid / kGemmK : tid % TT, kb0 = b_kfast ? tid % kGemmK : tid / TT;
+    const int ia_step = a_kfast ? THREADS / kGemmK : 0, ka_step = a_kfast ? 0 : THREADS / TT;
+    const int jb_step = b_kfast ? THREADS / kGemmK : 0, kb_step = b_kfast ? 0 : THREADS / TT;
+    double2 pa[LOADS], pb[LOADS];
+    auto load_chunk = [&](int k0) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
-        for (int e = threadIdx.x; e < TM * TK; e += kThreads) {
-            const int r = e / TK, c = e % TK;
-            const int gi = i0 + r, gk = k0 + c;
-            As[r][c] = (gi < g.M && gk < g.K) ? gload2(g.a + gi * g.a_rs + gk * g.a_cs) : make_double2(0.0, 0.0);
+        for (int q = 0; q < LOADS; ++q) {
+            const int gi = i0 + ia0 + q * ia_step, gk = k0 + ka0 + q * ka_step;
+            pa[q] = (gi < g.M && gk < g.K)
+                        ? gload2(g.a + static_cast<int64_t>(gi) * g.a_rs + static_cast<int64_t>(gk) * g.a_cs)
+                        : make_double2(0.0, 0.0);
+            const int gj = j0 + jb0 + q * jb_step, gkb = k0 + kb0 + q * kb_step;
+            pb[q] = (gj < g.N && gkb < g.K)
+                        ? gload2(g.b + static_cast<int64_t>(gkb) * g.b_rs + static_cast<int64_t>(gj) * g.b_cs)
+                        : make_double2(0.0, 0.0);
         }
-        for (int e = threadIdx.x; e < TK * TN; e += kThreads) {
-            const int r = e / TN, c = e % TN;
-            const int gk = k0 + r, gj = j0 + c;
-            Bs[r][c] = (gk < g.K && gj < g.N) ? gload2(g.b + gk * g.b_rs + gj * g.b_cs) : make_double2(0.0, 0.0);
+    };
+    v4d accr[BL][BL], acci[BL][BL];
+#pragma unroll
+    for (int x = 0; x < BL; ++x)
+#pragma unroll
+        for (int y = 0; y < BL; ++y) {
+            accr[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+            acci[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+        }
+    load_chunk(0);
+    for (int k0 = 0; k0 < g.K; k0 += kGemmK) {
+        __syncthreads();   // the previous chunk's fragment reads are done
+#pragma unroll
+        for (int q = 0; q < LOADS; ++q) {
+            Ar[ka0 + q * ka_step][ia0 + q * ia_step] = pa[q].x;
+            Ai[ka0 + q * ka_step][ia0 + q * ia_step] = pa[q].y;
+            Br[kb0 + q * kb_step][jb0 + q * jb_step] = pb[q].x;
+            Bi[kb0 + q * kb_step][jb0 + q * jb_step] = pb[q].y;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < TK; ++kk) {
-            const double2 a0 = As[ty][kk], a1 = As[ty + 16][kk];
-            const double2 b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
-            acc[0][0] = cfma(a0, b0, acc[0][0]);
-            acc[0][1] = cfma(a0, b1, acc[0][1]);
-            acc[1][0] = cfma(a1, b0, acc[1][0]);
-            acc[1][1] = cfma(a1, b1, acc[1][1]);
-        }
-        __syncthreads();
-    }
+        if (k0 + kGemmK < g.K) load_chunk(k0 + kGemmK);   // in flight during the products
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int gi = i0 + ty + 16 * a;
-        if (gi >= g.M) continue;
+        for (int kk = 0; kk < kGemmK; kk += 4) {
+            double ar[BL], ai[BL], nai[BL], br[BL], bi[BL];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int gj = j0 + tx + 16 * b;
-            if (gj >= g.N) continue;
-            double2* cp = g.c + gi * g.c_rs + gj * g.c_cs;
-            double2 r = cmul(g.alpha, acc[a][b]);
-            if (g.beta.x != 0.0 || g.beta.y != 0.0) r = cfma(g.beta, gload2(cp), r);
-            gstore2(cp, r);
+            for (int x = 0; x < BL; ++x) {
+                ar[x] = Ar[kk + fk][wr + 16 * x + fl];
+                ai[x] = Ai[kk + fk][wr + 16 * x + fl];
+                nai[x] = -ai[x];
+                br[x] = Br[kk + fk][wc + 16 * x + fl];
+                bi[x] = Bi[kk + fk][wc + 16 * x + fl];
+            }
+#pragma unroll
+            for (int x = 0; x < BL; ++x)
+#pragma unroll
+                for (int y = 0; y < BL; ++y) {
+                    accr[x][y] = mfma16(ar[x], br[y], accr[x][y]);
+                    accr[x][y] = mfma16(nai[x], bi[y], accr[x][y]);
+                    acci[x][y] = mfma16(ar[x], bi[y], acci[x][y]);
+                    acci[x][y] = mfma16(ai[x], br[y], acci[x][y]);
+                }
         }
     }
+    const bool has_beta = g.beta.x != 0.0 || g.beta.y != 0.0;
+#pragma unroll
+    for (int x = 0; x < BL; ++x)
+#pragma unroll
+        for (int y = 0; y < BL; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = i0 + wr + 16 * x + 4 * r + fk, gj = j0 + wc + 16 * y + fl;
+                if (gi >= g.M || gj >= g.N) continue;
+                double2* cp = g.c + static_cast<int64_t>(gi) * g.c_rs + static_cast<int64_t>(gj) * g.c_cs;
+                double2 v = cmul(g.alpha, make_double2(accr[x][y][r], acci[x][y][r]));
+                if (has_beta) v = cfma(g.beta, gload2(cp), v);
+                gstore2(cp, v);
+            }
+}
+}  // namespace
+
+__global__ void __launch_bounds__(64)
+k_gemm_t16(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
+    gemm_tile<16, 1>(jobs, tile_off, njobs);
+}
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+k_gemm(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
+    gemm_tile<32, 1>(jobs, tile_off, njobs);
+}
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_gemm_t64(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
+    gemm_tile<32, 4>(jobs, tile_off, njobs);
 }
 
 // Batched strided complex products with few columns (N <= kGemvMaxN, the
@@ -1232,6 +1506,35 @@ k_gemv(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, i
         double2 r = cmul(g.alpha, acc[j]);
         if (g.beta.x != 0.0 || g.beta.y != 0.0) r = cfma(g.beta, gload2(cp), r);
         gstore2(cp, r);
+    }
+}
+
+// One panel of the block Gauss-Jordan inverse of a large matrix (K x K,
+// leading dimension ld), after its diagonal block A_pp (rows and columns
+// [o, o + b)) has been inverted in place: L = A[:, p] with its rows p cleared,
+// Pt = A_pp (the inverse), then A[:, p] = 0 off the diagonal block and A_pp = I,
+// so that R = Pt A[p, :] holds Pt in its columns p.  L: K x b, Pt: b x b,
+// row-major.  Grid-stride over the K x b elements of the panel.
+__global__ void __launch_bounds__(kThreads)
+k_panel_prep(double2* __restrict__ A, int64_t ld, int64_t K, int64_t o, int b, double2* __restrict__ L,
+             double2* __restrict__ Pt) {
+    const int64_t total = K * b;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const int64_t i = e / b;
+        const int c = static_cast<int>(e - i * b);
+        double2* a = A + i * ld + o + c;
+        const double2 v = gload2(a);
+        const bool in_p = i >= o && i < o + b;
+        if (in_p) {
+            const int r = static_cast<int>(i - o);
+            gstore2(Pt + r * b + c, v);
+            gstore2(L + i * b + c, make_double2(0.0, 0.0));
+            gstore2(a, make_double2(r == c ? 1.0 : 0.0, 0.0));
+        } else {
+            gstore2(L + i * b + c, v);
+            gstore2(a, make_double2(0.0, 0.0));
+        }
     }
 }
 

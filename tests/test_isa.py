@@ -5,8 +5,9 @@ assembly from hipcc -S, no GPU needed).
   a pointer whose address space the compiler cannot see (one read from memory,
   or passed through inline asm) turns its loads into flat loads, which halved
   the throughput of the entry kernels once.
-* No register spills in the kernels on the hot paths (entry generation for the
-  HSS levels, the matrix-free product, the CPQR step, the batched products).
+* No register spills and no scratch arrays in the kernels on the hot paths
+  (entry generation for the HSS levels, the matrix-free product, the CPQR
+  step, the batched products, the Gauss-Jordan inverses).
   The shape-derivative pair kernel is the exception on purpose: at three waves
   per SIMD it spills 23 VGPRs and runs in 2.20 ms on the N = 8192 gradient
   workload, against 2.46 ms at two waves per SIMD without spills."""
@@ -72,4 +73,8 @@ def test_hot_kernels_do_not_spill(asm):
             spill = re.search(r"\.vgpr_spill_count:\s+(\d+)", meta)
             assert spill is not None, name
             assert int(spill.group(1)) == 0, f"{name} spills {spill.group(1)} VGPRs"
+            # no private (scratch) arrays either: a register array indexed at run
+            # time lands there, which once made the Gauss-Jordan kernel 3x slower
+            priv = re.search(r"\.private_segment_fixed_size:\s+(\d+)", meta)
+            assert priv is not None and int(priv.group(1)) == 0, f"{name} uses {priv.group(1)} B of scratch"
     assert seen == set(NO_SPILL)
