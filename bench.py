@@ -46,29 +46,99 @@ MEASURED_TRAFFIC = {
     # one sweep: one launch
     "k_dense": (2.0 * 48835.4 + 16861700.0) * 1024,
     # two HSS builds with the tuned options (gaussian sketch, unknowns + 8 rows; stop
-    # ratio 0.6; the root inverted by panels): 160 launches of k_gemm, 86 of
-    # k_gauss_jordan_16, 234 of k_cpqr_step_reg<4>
-    ("k_gemm", 8, 0.6): (2.0 * 2944907.9375 + 1143744.9375) * 1024 / 160,
-    ("k_gauss_jordan", 8, 0.6): (2.0 * 85100.5 + 159046.0) * 1024 / 86,
+    # ratio 0.6; the root inverted by panels): 234 launches of k_cpqr_step_reg<4>
     ("k_cpqr_step_reg", 8, 0.6): (2.0 * 328911.125 + 516937.875) * 1024 / 234,
 }
 
 
-def cpu_baseline(wl, rows: int = 256):
-    """Oracle (NumPy/SciPy, single thread) on a bounded sample: `rows` target
-    nodes against all N sources of the same workload."""
-    import numpy as np
+def _cpu_rows(args):
+    """Oracle rows for a chunk of target nodes (one worker of the baseline pool)."""
     from oracle import geometry, wsbm
-    xyd, sizes = wl.xyd()
+    xyd, sizes, media, rows = args
     nd = geometry.discretize(xyd, sizes)
-    idx = np.linspace(0, wl.n - 1, rows).astype(np.int64)
-    t0 = time.perf_counter()
-    wsbm.assemble_rows(nd, wl.media, idx)
-    dt = time.perf_counter() - t0
-    entries = 4 * rows * wl.n
-    return {"value": entries / dt / 1e9, "unit": "Gentries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows} target rows x {wl.n} sources of the same star workload "
-                      f"({rows * wl.n} pairs, {dt:.1f} s; NumPy/SciPy elementwise, one thread)"}
+    wsbm.assemble_rows(nd, media, rows)
+    return len(rows)
+
+
+def cpu_baseline_run(chunks: int = 2, chunk_rows: int = 64, lu_n: int = 6144):
+    """The oracle on the host (run in a child process that never touches the
+    GPU): (a) the dense assembly of the benchmark star, a process pool over row
+    chunks, every worker assembling `chunk_rows` target nodes against all N
+    sources, `chunks` chunks per core; (b) the dense LU (LAPACK zgetrf through
+    SciPy, BLAS threads = cores) of an lu_n x lu_n complex matrix, timed and
+    extrapolated by n^3 to the benchmark's 2N x 2N system.  Cores: the host's,
+    at most 16 (the host share of one GPU)."""
+    import multiprocessing as mp
+    import numpy as np
+    import scipy.linalg
+    from threadpoolctl import threadpool_limits
+    import scatterers as sc
+    wl = sc.star_workload()
+    xyd, sizes = wl.xyd()
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    nrows = cores * chunks * chunk_rows
+    starts = np.linspace(0, wl.n - chunk_rows, cores * chunks).astype(np.int64)
+    jobs = [(xyd, sizes, wl.media, np.arange(s0, s0 + chunk_rows)) for s0 in starts]
+    # the LU first: OpenBLAS's thread pool is not safe to start again in a
+    # process that has forked workers
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((lu_n, lu_n)) + 1j * rng.standard_normal((lu_n, lu_n))
+    A = np.asfortranarray(A)
+    with threadpool_limits(cores):
+        t0 = time.perf_counter()
+        scipy.linalg.lu_factor(A, overwrite_a=True, check_finite=False)
+        t_lu = time.perf_counter() - t0
+    del A
+    with threadpool_limits(1):
+        with mp.get_context("fork").Pool(cores) as pool:
+            pool.map(_cpu_rows, jobs[:cores])   # warm-up: imports, geometry
+            t0 = time.perf_counter()
+            done = sum(pool.map(_cpu_rows, jobs))
+            t_asm = time.perf_counter() - t0
+    pairs = done * wl.n
+    rate = pairs / t_asm
+    n2 = 2 * wl.n
+    lu_full = t_lu * (n2 / lu_n) ** 3
+    asm_full = wl.n * wl.n / rate
+    return {"value": 4 * rate / 1e9, "unit": "Gentries/s", "cores": cores, "kind": "oracle",
+            "sample": f"(a) assembly: {done} target rows x {wl.n} sources of the benchmark star ({pairs} pairs, "
+                      f"{t_asm:.1f} s, a pool of {cores} processes over row chunks, NumPy/SciPy elementwise); "
+                      f"(b) dense LU of a {lu_n} x {lu_n} complex matrix ({t_lu:.1f} s, LAPACK with {cores} "
+                      f"BLAS threads), extrapolated by n^3 to 2N = {n2}",
+            "assembly_Gentries_s": 4 * rate / 1e9, "assembly_pairs_s": rate,
+            "assembly_seconds_full_matrix": asm_full,
+            "lu_n": lu_n, "lu_seconds": t_lu, "lu_seconds_2N_extrapolated": lu_full,
+            "dense_solve_seconds_estimate": asm_full + lu_full,
+            "note": "the oracle has no HSS solver: its build+solve equivalent is dense assembly + LU of the "
+                    "2N x 2N system (dense_solve_seconds_estimate = full assembly at the measured rate + the "
+                    "extrapolated LU)"}
+
+
+def cpu_baseline(wl):
+    """cpu_baseline_run in a child process (it forks a process pool; the
+    benchmark process itself has initialised the GPU)."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only"], capture_output=True,
+                       text=True, timeout=600)
+    if r.returncode != 0:
+        return {"value": None, "unit": "Gentries/s", "cores": None, "kind": "oracle",
+                "sample": "failed: " + r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def fma_probe(blocks, iters, out):
+    """The FP64 FMA-rate probe of the benchmark-only library libbmhss_probe.so
+    (16 independent FMA chains per thread, blocks x 256 threads)."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2607_00790_amd", "libbmhss_probe.so"))
+    lib.fma_probe.restype = ctypes.c_int
+    lib.fma_probe.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+    rc = lib.fma_probe(ctypes.c_void_p(out.data_ptr()), int(blocks), int(iters),
+                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"fma_probe: HIP error {rc}")
+    return out
 
 
 def entry_kernel_rates(p, n):
@@ -76,7 +146,7 @@ def entry_kernel_rates(p, n):
     dense sweep (N^2 pairs written to HBM) and the generate-and-reduce product
     (the same entries, nothing stored), each as Gentries/s and as a fraction of
     the published FP64 peak and of the FP64 FMA rate this device sustains
-    (measured by the library's FMA probe in the same run)."""
+    (measured by the benchmark's FMA probe in the same run)."""
     import torch
     import paper_2607_00790_amd as bm
     stream = torch.cuda.current_stream()
@@ -95,7 +165,7 @@ def entry_kernel_rates(p, n):
 
     blocks, iters = 256 * 32, 2048
     buf = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
-    probe_ms = timed(lambda: bm.bm_fp64_fma_probe(blocks, iters, out=buf), 5)
+    probe_ms = timed(lambda: fma_probe(blocks, iters, buf), 5)
     measured = 2.0 * 16 * iters * 256 * blocks / (probe_ms * 1e-3) / 1e12
     pairs = n * n
     out = {"fp64_fma_probe_tflops": measured, "fp64_spec_peak_tflops": FP64_VECTOR_PEAK_TF}
@@ -449,15 +519,42 @@ def run_hss(args):
     cq_bytes = st["cpqr_bytes"]
     cq_gbs = cq_bytes / cq_s / 1e9 if cq_s > 0 else None
     sk, ratio = st["sketch"], st["max_rank_ratio"]
-    # the kernels of the step by launch time: the batched GEMM and Gauss-Jordan
-    # kernels (event-timed in the extra build above) and the ID's CPQR
+    # every kernel class of the step with its launch time (HIP events): the
+    # batched GEMM, Gauss-Jordan, sketch and entry-generation launches are
+    # event-timed one by one in the extra build above, the CPQR per level in
+    # every build.  Each class carries its bound and its algorithmic work.
     kern = {
-        "k_gemm": (kst["seconds_gemm"], kst["gemm_launches"], kst["gemm_flops"]),
-        "k_gauss_jordan": (kst["seconds_inv"], kst["inv_launches"], kst["inv_flops"]),
+        "k_gemm": dict(seconds=kst["seconds_gemm"], launches=kst["gemm_launches"], work=kst["gemm_flops"],
+                       bound="mfma", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TF),
+        "k_gauss_jordan": dict(seconds=kst["seconds_inv"], launches=kst["inv_launches"], work=kst["inv_flops"],
+                               bound="alu", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TF),
+        "k_sketch": dict(seconds=kst["seconds_sketch"], launches=kst["sketch_launches"],
+                         work=kst["sketch_flops"], bound="alu", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TF),
+        "k_gen_jobs": dict(seconds=kst["seconds_gen"], launches=kst["gen_launches"],
+                           work=kst["gen_pairs"] * FLOP_PER_PAIR, bound="alu", unit="TFLOP/s",
+                           peak=FP64_VECTOR_PEAK_TF),
+        "k_cpqr_step_reg": dict(seconds=kst["seconds_cpqr"], launches=kst["cpqr_launches"],
+                                work=kst["cpqr_bytes"], bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS),
+        "k_cpqr_fused": dict(seconds=kst["seconds_cpqr_fused"], launches=kst["cpqr_fused_launches"],
+                             work=kst["cpqr_fused_bytes"], bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS),
     }
-    dom = max(kern, key=lambda k: kern[k][0])
-    d_s, d_n, d_f = kern[dom]
-    d_tf = d_f / d_s / 1e12 if d_s > 0 else None
+    for v in kern.values():
+        scale = 1e12 if v["unit"] == "TFLOP/s" else 1e9
+        v["achieved"] = v["work"] / v["seconds"] / scale if v["seconds"] > 0 else None
+        v["frac"] = v["achieved"] / v["peak"] if v["achieved"] else None
+        v["avg_launch_ms"] = v["seconds"] / max(v["launches"], 1) * 1e3
+    # the HSS build's own entry generator, beside the dense sweep and the matrix-free product
+    g_s, g_pairs = kst["seconds_gen"], kst["gen_pairs"]
+    if g_s > 0:
+        g_tf = FLOP_PER_PAIR * g_pairs / g_s / 1e12
+        entry["gen_jobs"] = {"seconds_per_build": g_s, "launches": kst["gen_launches"], "pairs": g_pairs,
+                             "Gpairs_s": g_pairs / g_s / 1e9, "flop_per_pair": FLOP_PER_PAIR, "tflops": g_tf,
+                             "frac_spec_peak": g_tf / FP64_VECTOR_PEAK_TF,
+                             "frac_measured_peak": g_tf / entry["fp64_fma_probe_tflops"]}
+    dom = max(kern, key=lambda k: kern[k]["seconds"])
+    d = kern[dom]
+    d_work = d["work"] / max(d["launches"], 1)
+    traffic = MEASURED_TRAFFIC.get((dom, sk, ratio))
     out = {
         "metric": "Gentries/s Burton-Miller blocks (frac FP64 peak); HSS build+solve s at N=16384",
         "value": entries / (ms * 1e-3) / 1e9,
@@ -485,22 +582,19 @@ def run_hss(args):
                 "seconds_factor": avg("seconds_factor"),
                 "generation_Gentries_s": entries / gen_s / 1e9,
                 "solve_ms_eager": solve_ms["eager"], "solve_ms_graph": solve_ms["graph"],
-                "kernels_event_timed": {k: {"seconds": v[0], "launches": v[1], "flops": v[2],
-                                            "avg_launch_ms": v[0] / max(v[1], 1) * 1e3,
-                                            "tflops": v[2] / v[0] / 1e12 if v[0] > 0 else None}
-                                        for k, v in kern.items()},
+                "kernels_event_timed": kern,
                 "cpqr_step": {"seconds": cq_s, "launches": launches,
                               "algorithmic_GBs": cq_gbs,
                               "traffic_per_launch": MEASURED_TRAFFIC.get(("k_cpqr_step_reg", sk, ratio))},
                 "per_level": levels},
         "entry_generation": entry,
-        # the dominant kernel: FP64 vector arithmetic (no matrix cores), latency-bound
-        # at these sizes; achieved = its algorithmic flops / its event-timed launch time
-        "roofline": {"bound": "alu", "achieved": d_tf, "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
-                     "frac": d_tf / FP64_VECTOR_PEAK_TF if d_tf else None,
-                     "traffic": MEASURED_TRAFFIC.get((dom, sk, ratio)), "kernel": dom,
-                     "launches": d_n, "algorithmic_flops_per_launch": d_f / max(d_n, 1),
-                     "avg_launch_ms": d_s / max(d_n, 1) * 1e3},
+        # the kernel class with the largest launch time in the step; achieved =
+        # its algorithmic work per launch / its average event-timed launch time
+        "roofline": {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+                     "frac": d["frac"], "traffic": traffic, "kernel": dom, "launches": d["launches"],
+                     ("algorithmic_flops_per_launch" if d["unit"] == "TFLOP/s" else "algorithmic_bytes_per_launch"):
+                         d_work,
+                     "avg_launch_ms": d["avg_launch_ms"]},
     }
     return out, wl
 
@@ -623,10 +717,14 @@ def main():
                          "CPQR; -1: the library's tuned value; default: -1 in hss, adjoint and batch modes, "
                          "128 in large mode, 0 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device once (a plain copy "
                          "kernel of known size, to scale HBM traffic counters)")
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline_run()), flush=True)
+        return 0
     if args.max_rank_ratio is None:
         args.max_rank_ratio = {"hss": -1.0, "adjoint": -1.0, "batch": -1.0, "large": 0.8}.get(args.mode, 0.0)
     if args.sketch is None:

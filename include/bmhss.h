@@ -249,6 +249,16 @@ typedef struct {
     int64_t inv_launches;
     double inv_flops;
     double seconds_inv;
+    /* with opts.kernel_timing: the sketch launches (their algorithmic flops,
+     * 4 l m n for an l-row sketch of an m x n complex matrix, and summed
+     * durations) and the FP64 entry-generation launches (pairs evaluated and
+     * summed durations); zero otherwise */
+    int64_t sketch_launches;
+    double sketch_flops;
+    double seconds_sketch;
+    int64_t gen_launches;
+    double gen_pairs;
+    double seconds_gen;
 } bm_hss_stats_t;
 
 /* Build the factorisation; synchronises `stream` once per level to read the
@@ -284,6 +294,35 @@ int bm_hss_solve_transpose(const bm_hss* h, const double* b, double* x, int64_t 
 int bm_hss_solve_graph(const bm_hss* h, const double* b, double* x, int64_t nrhs, int transpose,
                        hipStream_t stream);
 int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out);
+
+/* In-place inverse of one dense complex n x n matrix on the device, by the
+ * method the HSS factorisation uses for its diagonal blocks and its dense root
+ * (the inverses in the Martinsson-Rokhlin factors of the direct solver, paper
+ * Sec. III): Gauss-Jordan with partial row pivoting for n <= 64; above that
+ * block Gauss-Jordan over 64-column panels (n <= 4096), or the 2 x 2
+ * Schur-complement recursion, rows pivoted within the 64 x 64 diagonal blocks.
+ * a: device, interleaved complex128, element (i, j) at a[2 (i ld + j)],
+ * overwritten by the inverse; 1 <= n <= 16384, n <= ld.  Returns after the
+ * inverse has completed on the stream.  BM_ESINGULAR if a pivot is zero, not
+ * finite or below 64 eps times the largest magnitude in its 64 x 64 diagonal
+ * block (the kernels end normally; for n <= 64 the matrix is then left as it
+ * was, above that its contents are unspecified).  Test hook: with
+ * BMHSS_TEST_SINGULAR_ROOT=1 in the environment, bm_hss_build zeroes the first
+ * row of its dense root before inverting it (and so returns BM_ESINGULAR). */
+int bm_dense_inverse(double* a, int64_t n, int64_t ld, hipStream_t stream);
+
+/* The sketch of the randomized interpolative decomposition (the ID of a box
+ * then runs on Y instead of on its stacked near-field and proxy matrix, paper
+ * Sec. III): Y = Omega X for a real l x m matrix Omega (row-major, leading
+ * dimension ldo >= m) and a complex m x n matrix X (column j at x + 2 j m,
+ * interleaved complex128), giving the complex l x n matrix Y (column j at
+ * y + 2 j l).  All device pointers; the product runs on the FP64 matrix
+ * cores, with the K range split over several workgroups (and the partial
+ * products summed in a fixed order) when the tiles alone would leave most
+ * compute units idle.  Returns after Y has been written.  EINVAL for sizes
+ * out of range. */
+int bm_sketch(const double* omega, int64_t ldo, const double* x, int64_t m, int64_t n, int64_t l, double* y,
+              hipStream_t stream);
 
 /* Per compressed level (0 = leaves, up to compressed_levels - 1): sizes of the
  * ID problems and the ranks found.  EINVAL for a level out of range. */
@@ -337,14 +376,6 @@ int bm_fourier_curve(const double* coef, int nmodes, double radius, double cx, d
  * grad[q*n + i] d xyd[q*n + i] / d coef_m (device, 2M FP64), e.g. a shape
  * derivative from bm_shape_derivative turned into d/d(a_1..a_M, b_1..b_M). */
 int bm_fourier_chain(const double* grad, int64_t n, int nmodes, double radius, double* out, hipStream_t stream);
-
-/* ---- Diagnostics ----
- * The FP64 FMA rate the device sustains: blocks x 256 threads, each running 16
- * independent chains of `iters` fused multiply-adds (2 * 16 * iters real flops
- * per thread), and writing one double per thread to out (device, blocks * 256
- * doubles).  Time it with events on `stream`; the entry kernels' FP64 fraction
- * is reported against this rate as well as against the published peak. */
-int bm_fp64_fma_probe(double* out, int64_t blocks, int64_t iters, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,8 @@ from ._binding import (  # noqa: F401
     bm_geom_size,
     bm_matvec,
     bm_matvec_noalloc,
+    bm_dense_inverse,
+    bm_sketch,
     bm_problem_create,
     bm_problem_create_bodies,
     bm_rhs_plane_wave,
@@ -34,7 +36,6 @@ from ._binding import (  # noqa: F401
     bm_shape_derivative,
     bm_fourier_curve,
     bm_fourier_chain,
-    bm_fp64_fma_probe,
     lib_path,
     load,
 )

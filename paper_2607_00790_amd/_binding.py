@@ -42,7 +42,9 @@ class _HssStats(ctypes.Structure):
                 ("sketch", c_i64), ("max_rank_ratio", c_dbl),
                 ("cpqr_fused_launches", c_i64), ("cpqr_fused_bytes", c_dbl), ("seconds_cpqr_fused", c_dbl),
                 ("gemm_launches", c_i64), ("gemm_flops", c_dbl), ("seconds_gemm", c_dbl),
-                ("inv_launches", c_i64), ("inv_flops", c_dbl), ("seconds_inv", c_dbl)]
+                ("inv_launches", c_i64), ("inv_flops", c_dbl), ("seconds_inv", c_dbl),
+                ("sketch_launches", c_i64), ("sketch_flops", c_dbl), ("seconds_sketch", c_dbl),
+                ("gen_launches", c_i64), ("gen_pairs", c_dbl), ("seconds_gen", c_dbl)]
 
 
 class _HssLevel(ctypes.Structure):
@@ -93,10 +95,11 @@ def load():
         "bm_shape_derivative": (ctypes.c_int, [c_vp, c_vp, c_vp, c_dbl, c_dbl, c_vp, c_vp, c_vp]),
         "bm_fourier_curve": (ctypes.c_int, [c_vp, ctypes.c_int, c_dbl, c_dbl, c_dbl, c_i64, c_vp, c_vp]),
         "bm_fourier_chain": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_dbl, c_vp, c_vp]),
-        "bm_fp64_fma_probe": (ctypes.c_int, [c_vp, c_i64, c_i64, c_vp]),
         "bm_hss_stats": (ctypes.c_int, [c_vp, ctypes.POINTER(_HssStats)]),
         "bm_hss_level": (ctypes.c_int, [c_vp, ctypes.c_int, ctypes.POINTER(_HssLevel)]),
         "bm_hss_destroy": (ctypes.c_int, [c_vp]),
+        "bm_dense_inverse": (ctypes.c_int, [c_vp, c_i64, c_i64, c_vp]),
+        "bm_sketch": (ctypes.c_int, [c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_vp, c_vp]),
     })
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -317,6 +320,32 @@ def bm_matvec_noalloc(p: Problem, x, out, stream=None):
     return out
 
 
+def bm_dense_inverse(a, stream=None):
+    """In-place inverse of a square complex128 device matrix (row-major,
+    contiguous); returns a."""
+    torch = _torch()
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must be a square matrix")
+    _check(load().bm_dense_inverse(_dev_ptr(a, torch.complex128, "a"), a.shape[0], a.shape[0], _stream(stream)))
+    return a
+
+
+def bm_sketch(omega, x, out=None, stream=None):
+    """Y = omega @ x for a real (l, m) float64 device matrix omega (row-major)
+    and a complex (m, n) matrix x stored by columns: pass x as the (n, m)
+    complex128 tensor x^T (contiguous), and receive Y^T as an (n, l) tensor."""
+    torch = _torch()
+    if omega.dim() != 2 or x.dim() != 2 or omega.shape[1] != x.shape[1]:
+        raise ValueError("omega must be (l, m) and x^T (n, m)")
+    l, m = omega.shape
+    n = x.shape[0]
+    if out is None:
+        out = torch.empty((n, l), dtype=torch.complex128, device="cuda")
+    _check(load().bm_sketch(_dev_ptr(omega, torch.float64, "omega"), m, _dev_ptr(x, torch.complex128, "x"), m, n, l,
+                            _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
+    return out
+
+
 def bm_far_field(p: Problem, phi, angles, out=None, stream=None):
     torch = _torch()
     angles = angles.to(device="cuda", dtype=torch.float64).contiguous()
@@ -445,13 +474,4 @@ def bm_fourier_chain(grad, nmodes: int, radius: float = 1.0, out=None, stream=No
     n = grad.shape[-1]
     _check(load().bm_fourier_chain(_dev_ptr(grad, torch.float64, "grad"), int(n), int(nmodes), float(radius),
                                  _dev_ptr(out, torch.float64, "out"), _stream(stream)))
-    return out
-
-
-def bm_fp64_fma_probe(blocks: int, iters: int, out=None, stream=None):
-    """Runs the FP64 FMA probe (2 * 16 * iters * 256 * blocks flops); time it with events."""
-    torch = _torch()
-    if out is None:
-        out = torch.empty(int(blocks) * 256, dtype=torch.float64, device="cuda")
-    _check(load().bm_fp64_fma_probe(_dev_ptr(out, torch.float64, "out"), int(blocks), int(iters), _stream(stream)))
     return out

@@ -12,9 +12,11 @@ residual is no larger than that of plain CPQR on every level.  The fastest
 admissible pair wins.
 
 Stage 2 then times, with the chosen options, every pair (Gauss-Jordan base
-block 32 / 64 / 128, rocBLAS threshold 1e8 / 4e8 / 2e9 flops) through
-bench.py in a child process with the candidate in BMHSS_TUNE_INV_BASE /
-BMHSS_TUNE_BLAS_FLOPS, and keeps the median step time over the repeats.
+block 32 / 64 / 128, rocBLAS threshold 1e8 / 4e8 / 2e9 flops): a child
+process of this module per candidate (the library reads BMHSS_TUNE_INV_BASE /
+BMHSS_TUNE_BLAS_FLOPS once per process) runs warm-up steps and then times
+`steps` build + right-hand side + solve steps with HIP events, and the median
+step time over the repeats is kept.
 
 The result is a tuned_params.h that makes the winners the compiled defaults,
 with every measurement in its comments.  Copy it to csrc/tuned_params.h and
@@ -81,13 +83,47 @@ def stage1(builds: int) -> list:
     return [tuple(r) for r in json.loads([l for l in out.splitlines() if l.startswith("[")][-1])]
 
 
+def time_steps(steps: int, sketch: int, ratio: float) -> float:
+    """Stage 2, run in a child process: ms per build + right-hand side + solve
+    step on the benchmark workload (2 warm-up steps, then `steps` timed with
+    HIP events on the current stream)."""
+    import torch
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import scatterers as sc
+    import paper_2607_00790_amd as bm
+    wl = sc.star_workload()
+    xyd, sizes = wl.xyd()
+    g = bm.bm_geom_create(sizes, torch.from_numpy(xyd).cuda())
+    p = bm.bm_problem_create(g, wl.media.k0, wl.media.k1, wl.media.eps0, wl.media.eps1)
+    b = torch.empty(2 * wl.n, dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(b)
+
+    def step():
+        h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points,
+                            id_tol=wl.id_tol, sketch=sketch, max_rank_ratio=ratio)
+        bm.bm_rhs_plane_wave(p, wl.theta_inc, out=b)
+        bm.bm_hss_solve(h, b, out=x)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def measure(base: int, flops: float, steps: int, sketch: int, ratio: float) -> float:
     env = dict(os.environ, BMHSS_TUNE_INV_BASE=str(base), BMHSS_TUNE_BLAS_FLOPS=repr(flops))
-    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", str(steps), "--warmup", "2",
-           "--no-cpu-baseline", "--sketch", str(sketch), "--max-rank-ratio", repr(ratio)]
-    out = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True).stdout
-    line = [l for l in out.splitlines() if l.startswith("{")][-1]
-    return json.loads(line)["ms_per_step"]
+    cmd = [sys.executable, "-m", "paper_2607_00790_amd.autotune", "--stage2-child", "--steps", str(steps),
+           "--sketch", str(sketch), "--ratio", repr(ratio)]
+    out = subprocess.run(cmd, env=env, cwd=ROOT, capture_output=True, text=True, check=True).stdout
+    return json.loads([l for l in out.splitlines() if l.strip()][-1])
 
 
 def main() -> int:
@@ -97,9 +133,15 @@ def main() -> int:
     ap.add_argument("--repeats", type=int, default=2)
     ap.add_argument("--builds", type=int, default=6, help="stage 1: builds per option pair")
     ap.add_argument("--stage1-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--stage2-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--sketch", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--ratio", type=float, default=0.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.stage1_child:
         print(json.dumps(build_options_sweep(args.builds)), flush=True)
+        return 0
+    if args.stage2_child:
+        print(json.dumps(time_steps(args.steps, args.sketch, args.ratio)), flush=True)
         return 0
     opts = stage1(args.builds)
     ref = [r for r in opts if r[1] == 0 and r[2] == 0.0][0]
@@ -126,8 +168,8 @@ def main() -> int:
 // Stage 1, build options: median of {args.builds} build+solve runs per pair; the
 // residual |A x - b| / |b| may not exceed that of plain CPQR on every level:
 {t_opts}
-// Stage 2, with those options: median bench.py step (--steps {args.steps} --warmup 2,
-// {args.repeats} runs each):
+// Stage 2, with those options: median step time (build + right-hand side +
+// solve, {args.steps} steps after 2 warm-up steps, {args.repeats} runs each):
 {t_inv}
 #pragma once
 

@@ -6,6 +6,8 @@ Produces (next to this file):
   libbmhss.so            -- the product library (C-ABI of include/bmhss.h)
   libbmhss_hostcheck.so  -- host-compiled instances of the device math, loaded
                             only by the CPU unit tests
+  libbmhss_probe.so      -- the benchmark's FP64 FMA-rate probe (benchsrc/), loaded
+                            only by bench.py and its test
 """
 from __future__ import annotations
 
@@ -20,6 +22,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbmhss.so")
 HOSTCHECK = os.path.join(HERE, "libbmhss_hostcheck.so")
+PROBE = os.path.join(HERE, "libbmhss_probe.so")
 
 ARCH = "gfx950"
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
@@ -57,6 +60,10 @@ def build(verbose: bool = True) -> None:
     _run([hipcc(), f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, "-shared",
           os.path.join(CSRC, "hostcheck.hip"), "-o", tmp])
     os.replace(tmp, HOSTCHECK)
+    tmp = PROBE + ".tmp"
+    _run([hipcc(), f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, "-shared",
+          os.path.join(HERE, "benchsrc", "fma_probe.hip"), "-o", tmp])
+    os.replace(tmp, PROBE)
 
 
 if __name__ == "__main__":

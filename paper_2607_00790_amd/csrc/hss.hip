@@ -248,6 +248,44 @@ hipError_t launch_in_groups(const std::vector<Job>& jobs, Tiles tiles, Launch la
     return hipSuccess;
 }
 
+// Per-launch HIP-event timing of the batched GEMM, Gauss-Jordan, sketch and
+// entry-generation kernels during a build with opts.kernel_timing set: the
+// launchers record an event pair around each launch into the collector of the
+// calling build.
+struct KernelTimes {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm, inv, sketch, gen;
+    double gemm_flops = 0, inv_flops = 0, sketch_flops = 0, gen_pairs = 0;
+    ~KernelTimes() {
+        for (auto* v : {&gemm, &inv, &sketch, &gen})
+            for (auto& pr : *v) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+    }
+    static double seconds(const std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+        double t = 0;
+        for (auto& pr : v) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) t += ms * 1e-3;
+        }
+        return t;
+    }
+};
+thread_local KernelTimes* g_ktimes = nullptr;
+
+// an event pair around one launch when the calling build times its kernels
+bool timed_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
+    if (hipEventCreate(a) != hipSuccess) return false;
+    if (hipEventCreate(b) != hipSuccess) {
+        (void)hipEventDestroy(*a);
+        *a = nullptr;
+        return false;
+    }
+    v.emplace_back(*a, *b);
+    return true;
+}
+
 hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const Slot* slots,
                             const PointTable& pt, const Media* media, const BesselTable* tab, double2* out,
                             const float* ftab);
@@ -280,13 +318,18 @@ hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const 
     const int nj = static_cast<int>(jobs.size());
     const PointTable ptc = pt;
     hipStream_t st = sc.s;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (g_ktimes && !ftab && timed_pair(g_ktimes->gen, &ea, &eb))
+        for (const GenJob& j : jobs) g_ktimes->gen_pairs += static_cast<double>(j.nt) * j.ns;
     sc.rec([=]() {
+        if (ea) (void)hipEventRecord(ea, st);
         if (ftab)
             hipLaunchKernelGGL(k_gen_jobs<float>, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, media, out,
                                tab, ftab);
         else
             hipLaunchKernelGGL(k_gen_jobs<double>, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, slots, ptc, media,
                                out, tab, ftab);
+        if (eb) (void)hipEventRecord(eb, st);
         return hipGetLastError();
     });
     return hipSuccess;
@@ -295,42 +338,6 @@ hipError_t launch_gen_group(Scratch& sc, const std::vector<GenJob>& jobs, const 
 hipError_t launch_gemm_group(Scratch& sc, const std::vector<GemmJob>& jobs);
 int gemm_tile_for(const std::vector<GemmJob>& jobs);
 
-// Per-launch HIP-event timing of the batched GEMM and Gauss-Jordan kernels
-// during a build with opts.kernel_timing set: the launchers record an event
-// pair around each launch into the collector of the calling build.
-struct KernelTimes {
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm, inv;
-    double gemm_flops = 0, inv_flops = 0;
-    ~KernelTimes() {
-        for (auto* v : {&gemm, &inv})
-            for (auto& pr : *v) {
-                (void)hipEventDestroy(pr.first);
-                (void)hipEventDestroy(pr.second);
-            }
-    }
-    static double seconds(const std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
-        double t = 0;
-        for (auto& pr : v) {
-            float ms = 0;
-            if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) t += ms * 1e-3;
-        }
-        return t;
-    }
-};
-thread_local KernelTimes* g_ktimes = nullptr;
-
-// an event pair around one launch when the calling build times its kernels
-bool timed_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipEvent_t* a, hipEvent_t* b) {
-    *a = *b = nullptr;
-    if (hipEventCreate(a) != hipSuccess) return false;
-    if (hipEventCreate(b) != hipSuccess) {
-        (void)hipEventDestroy(*a);
-        *a = nullptr;
-        return false;
-    }
-    v.emplace_back(*a, *b);
-    return true;
-}
 hipError_t launch_gemv_group(Scratch& sc, const std::vector<GemmJob>& jobs);
 int64_t gemv_tiles(const GemmJob& j);
 
@@ -357,12 +364,22 @@ hipError_t blas_handle(rocblas_handle* out) {
 // the default) or by the Schur recursion used for the batched blocks.  BMHSS_ROOT_PANELS=0 selects the
 // recursion (for comparison).
 constexpr int64_t kRootPanelsMax = 4096;
+// largest matrix bm_dense_inverse accepts
+constexpr int64_t kDenseInverseMax = 16384;
 bool root_panels() {
     static const bool v = [] {
         const char* e = std::getenv("BMHSS_ROOT_PANELS");
         return !(e && std::atoi(e) == 0);
     }();
     return v;
+}
+
+// Test hook: with BMHSS_TEST_SINGULAR_ROOT=1 in the environment when a build
+// starts, the first row of its (first) dense root is zeroed before the root is
+// inverted, so that the build must end with BM_ESINGULAR.
+bool singular_root_hook() {
+    const char* e = std::getenv("BMHSS_TEST_SINGULAR_ROOT");
+    return e && std::atoi(e) == 1;
 }
 
 // Tuned parameters (tuned_params.h), overridable through the environment for
@@ -591,7 +608,7 @@ hipError_t launch_sketch_group(Scratch& sc, const std::vector<SketchJob>& jobs, 
 
 hipError_t launch_sketch(Scratch& sc, const std::vector<SketchJob>& jobs, const double* omega, int64_t ldo) {
     return launch_in_groups(
-        jobs, [](const SketchJob& j) { return ceil_div(j.l, 64) * ceil_div(j.n, 64); },
+        jobs, [](const SketchJob& j) { return ceil_div(j.l, 64) * ceil_div(j.n, 32); },
         [&](const std::vector<SketchJob>& g) { return launch_sketch_group(sc, g, omega, ldo); });
 }
 
@@ -609,7 +626,7 @@ hipError_t launch_sketch_group(Scratch& sc, const std::vector<SketchJob>& jobs_i
     double2* ylo = nullptr;
     double2* yhi = nullptr;
     for (const SketchJob& j : jobs) {
-        tiles += ceil_div(j.l, 64) * ceil_div(j.n, 64);
+        tiles += ceil_div(j.l, 64) * ceil_div(j.n, 32);
         mmax = std::max<int64_t>(mmax, j.m);
         double2* y1 = j.y + static_cast<int64_t>(j.l) * j.n;
         if (ylo == nullptr || j.y < ylo) ylo = j.y;
@@ -629,7 +646,7 @@ hipError_t launch_sketch_group(Scratch& sc, const std::vector<SketchJob>& jobs_i
     }
     std::vector<int64_t> toff(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j)
-        toff[j + 1] = toff[j] + ceil_div(jobs[j].l, 64) * ceil_div(jobs[j].n, 64) * ks;
+        toff[j + 1] = toff[j] + ceil_div(jobs[j].l, 64) * ceil_div(jobs[j].n, 32) * ks;
     SketchJob* dj;
     int64_t* dt;
     e = sc.upload(&dj, jobs);
@@ -638,12 +655,17 @@ hipError_t launch_sketch_group(Scratch& sc, const std::vector<SketchJob>& jobs_i
     const unsigned grid = static_cast<unsigned>(toff.back());
     const int nj = static_cast<int>(jobs.size());
     hipStream_t st = sc.s;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (g_ktimes && timed_pair(g_ktimes->sketch, &ea, &eb))
+        for (const SketchJob& j : jobs) g_ktimes->sketch_flops += 4.0 * j.l * j.m * j.n;
     sc.rec([=]() {
+        if (ea) (void)hipEventRecord(ea, st);
         hipLaunchKernelGGL(k_sketch, dim3(grid), dim3(kThreads), 0, st, dj, dt, nj, omega, ldo, ks, pstride);
         if (ks > 1) {
             const unsigned g2 = static_cast<unsigned>(std::min<int64_t>(ceil_div(pstride, kThreads), 4096));
             hipLaunchKernelGGL(k_sum_partials, dim3(g2), dim3(kThreads), 0, st, part, ks, pstride, pstride, ylo);
         }
+        if (eb) (void)hipEventRecord(eb, st);
         return hipGetLastError();
     });
     return hipSuccess;
@@ -690,10 +712,8 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
             for (const InvJob& j : base) g_ktimes->inv_flops += 8.0 * j.n * j.n * j.n;
         sc.rec([=]() {
             if (ea) (void)hipEventRecord(ea, st);
-            if (nbase <= 32)
-                hipLaunchKernelGGL(k_gauss_jordan_8, dim3(nj), dim3(64), 0, st, dj);
-            else if (nbase <= 64)
-                hipLaunchKernelGGL(k_gauss_jordan_16, dim3(nj), dim3(256), 0, st, dj);
+            if (nbase <= 64)
+                hipLaunchKernelGGL(k_gauss_jordan_cols<8>, dim3(nj), dim3(512), 0, st, dj);
             else
                 hipLaunchKernelGGL(k_gauss_jordan_32, dim3(nj), dim3(1024), 0, st, dj);
             if (eb) (void)hipEventRecord(eb, st);
@@ -1931,6 +1951,11 @@ int build_impl(bm_hss* h, hipStream_t s) {
             const size_t nr = roots.size();
             sc.rec([=]() { return hipMemsetAsync(st, 0, nr * sizeof(int32_t), s2); });
         }
+        if (e == hipSuccess && singular_root_hook()) {
+            double2* r0 = h->Rinv + roots[0].r_off;
+            const size_t bytes = static_cast<size_t>(roots[0].K) * sizeof(double2);
+            sc.rec([=]() { return hipMemsetAsync(r0, 0, bytes, s2); });
+        }
         if (e == hipSuccess && (e = t_fac.start(sc, ev)) == hipSuccess) {
             std::vector<InvJob> inv;
             for (size_t q = 0; q < roots.size(); ++q)
@@ -2235,6 +2260,12 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
             h->stats.inv_launches = static_cast<int64_t>(kt.inv.size());
             h->stats.inv_flops = kt.inv_flops;
             h->stats.seconds_inv = KernelTimes::seconds(kt.inv);
+            h->stats.sketch_launches = static_cast<int64_t>(kt.sketch.size());
+            h->stats.sketch_flops = kt.sketch_flops;
+            h->stats.seconds_sketch = KernelTimes::seconds(kt.sketch);
+            h->stats.gen_launches = static_cast<int64_t>(kt.gen.size());
+            h->stats.gen_pairs = kt.gen_pairs;
+            h->stats.seconds_gen = KernelTimes::seconds(kt.gen);
         }
     }
     if (rc != BM_OK) {
@@ -2244,6 +2275,58 @@ int bm_hss_build(const bm_problem* p, const bm_hss_opts* opts, hipStream_t strea
     }
     h->stats.seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = h;
+    return BM_OK;
+}
+
+int bm_dense_inverse(double* a, int64_t n, int64_t ld, hipStream_t stream) {
+    clear_error();
+    if (!a) return fail(BM_EINVAL, "bm_dense_inverse: a is null");
+    if (n < 1 || n > kDenseInverseMax || ld < n || ld > (int64_t{1} << 30))
+        return fail(BM_EINVAL, "bm_dense_inverse: need 1 <= n <= 16384 and n <= ld <= 2^30");
+    int32_t hs = 0;
+    hipError_t e = hipSuccess;
+    {
+        Scratch sc(stream);
+        int32_t* st = nullptr;
+        e = sc.alloc(&st, 1);
+        if (e == hipSuccess) {
+            sc.rec([=]() { return hipMemsetAsync(st, 0, sizeof(int32_t), stream); });
+            const InvJob j{reinterpret_cast<double2*>(a), st, ld, static_cast<int32_t>(n)};
+            e = (n > inv_base() && n <= kRootPanelsMax && root_panels()) ? launch_inverse_panels(sc, j)
+                                                                         : launch_inverse(sc, {j});
+        }
+        if (e == hipSuccess) e = sc.flush();
+        if (e == hipSuccess) e = hipMemcpyAsync(&hs, st, sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) sc.synced();
+    }
+    if (e != hipSuccess) return hip_fail(e, "bm_dense_inverse");
+    if (hs) return fail(BM_ESINGULAR, "bm_dense_inverse: singular or tiny pivot");
+    return BM_OK;
+}
+
+int bm_sketch(const double* omega, int64_t ldo, const double* x, int64_t m, int64_t n, int64_t l, double* y,
+              hipStream_t stream) {
+    clear_error();
+    if (!omega || !x || !y) return fail(BM_EINVAL, "bm_sketch: null argument");
+    if (m < 1 || n < 1 || l < 1 || m > (int64_t{1} << 30) || n > (int64_t{1} << 30) || l > (int64_t{1} << 30) ||
+        ldo < m || l * n > (int64_t{1} << 34))
+        return fail(BM_EINVAL, "bm_sketch: need 1 <= m, n, l <= 2^30, m <= ldo and l n <= 2^34");
+    hipError_t e = hipSuccess;
+    {
+        Scratch sc(stream);
+        SketchJob j{};
+        j.x = reinterpret_cast<const double2*>(x);
+        j.y = reinterpret_cast<double2*>(y);
+        j.m = static_cast<int32_t>(m);
+        j.n = static_cast<int32_t>(n);
+        j.l = static_cast<int32_t>(l);
+        e = launch_sketch(sc, {j}, omega, ldo);
+        if (e == hipSuccess) e = sc.flush();
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) sc.synced();
+    }
+    if (e != hipSuccess) return hip_fail(e, "bm_sketch");
     return BM_OK;
 }
 

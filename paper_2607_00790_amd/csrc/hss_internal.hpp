@@ -125,9 +125,10 @@ __global__ void k_interp(const CpqrJob* jobs, const int32_t* ranks, const int64_
 template <int RPL>
 __global__ void k_interp_wave(const CpqrJob* jobs, const int32_t* ranks, const int64_t* t_off,
                               double2* Tbuf);
-// in-place inverse of n x n blocks, n <= 32 / 64 / 128; blockDim 64 / 256 / 1024
-__global__ void k_gauss_jordan_8(const InvJob* jobs);
-__global__ void k_gauss_jordan_16(const InvJob* jobs);
+// in-place inverse of n x n blocks: n <= 64, a row per lane, blockDim 64 NW
+// (NW = 8); n <= 128, 4 x 4 register tiles, blockDim 1024
+template <int NW>
+__global__ void k_gauss_jordan_cols(const InvJob* jobs);
 __global__ void k_gauss_jordan_32(const InvJob* jobs);
 __global__ void k_cpqr_init(const CpqrJob* jobs);
 __global__ void k_cpqr_step(const CpqrJob* jobs, int k, double tol);

@@ -12,9 +12,11 @@
 //                    rank rule |R_kk| > tol |R_00|
 //   k_interp_wave    T_b = [I; (R11^-1 R12)^T] in pivoted order, column-oriented
 //   k_interp         the same, row-oriented, for ranks beyond 256
+//   k_sketch         Y = Omega X of the randomized ID on the matrix cores
 //   k_gauss_jordan_* batched in-place inverse with partial row pivoting, the
-//                    block held in registers (4 x 4 complex tile per thread)
-//   k_gemm           batched strided complex GEMM
+//                    block held in registers (a row per lane up to 64, 4 x 4
+//                    complex tiles per thread up to 128)
+//   k_gemm           batched strided complex GEMM on the matrix cores
 #include "hss_internal.hpp"
 
 namespace bm {
@@ -874,6 +876,33 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t key) {
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+__device__ __forceinline__ double2 readlane2(double2 v, int l) {
+    return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
+}
+
+// max(v, v from the lane DPP control CTRL selects), lanes without a source
+// keeping v: one step of a wave maximum (VOP2 with a DPP source).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_fmax(float v) {
+    const int o = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+    return fmaxf(v, __int_as_float(o));
+}
+
+// The lowest lane holding the wave's largest value of `mag` (wave-uniform);
+// -1 if no lane holds a positive value.
+__device__ __forceinline__ int wave_argmax_f32(float mag) {
+    float m = dpp_fmax<0x111, 0xF>(mag);   // row_shr:1
+    m = dpp_fmax<0x112, 0xF>(m);           // row_shr:2
+    m = dpp_fmax<0x114, 0xF>(m);           // row_shr:4
+    m = dpp_fmax<0x118, 0xF>(m);           // row_shr:8   -> lane 15 of each row
+    m = dpp_fmax<0x142, 0xA>(m);           // row_bcast:15
+    m = dpp_fmax<0x143, 0xC>(m);           // row_bcast:31 -> lane 63: the maximum
+    const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 63));
+    if (!(mx > 0.0f)) return -1;
+    const uint64_t hit = __builtin_amdgcn_ballot_w64(mag == mx);
+    return static_cast<int>(__builtin_ctzll(hit));
+}
+
 template <int TG>
 __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
     constexpr int NMAX = 4 * TG;
@@ -882,23 +911,35 @@ __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
     __shared__ double2 colbuf[2][NMAX];
     __shared__ double2 urow[NMAX];
     __shared__ int perm[NMAX], pinv[NMAX];
+    __shared__ double wmax[(TG * TG + 63) / 64];
     const int n = jb.n;
     const int64_t ld = jb.ld;
     const int tid = threadIdx.x, ty = tid / TG, tx = tid % TG, lane = tid & 63;
     const int r0 = 4 * ty, c0 = 4 * tx;
     double2 S[4][4];
+    double m2 = 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int i = r0 + r, j = c0 + c;
             S[r][c] = (i < n && j < n) ? gload2(jb.a + i * ld + j) : make_double2(0.0, 0.0);
+            m2 = fmax(m2, cabs2(S[r][c]));
         }
     if (tx == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) colbuf[0][r0 + r] = S[r][0];
     }
+    {
+        const int q = wave_argmax_f32(static_cast<float>(m2));
+        const double wm = q < 0 ? 0.0 : readlane_d(m2, q);
+        if (lane == 0) wmax[tid >> 6] = wm;
+    }
     __syncthreads();
+    m2 = wmax[0];
+    for (int w = 1; w < (TG * TG + 63) / 64; ++w) m2 = fmax(m2, wmax[w]);
+    // pivots at or below 64 eps of the block's largest magnitude are singular
+    const double tiny2 = (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16) * m2;
     uint64_t used[NWORD];
 #pragma unroll
     for (int q = 0; q < NWORD; ++q) used[q] = 0;
@@ -937,7 +978,7 @@ __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
         pv.y = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(pv.y), p & 63),
                                 __builtin_amdgcn_readlane(__double2loint(pv.y), p & 63));
         const double pd = cabs2(pv);
-        if ((key >> 7) == 0 || !(pd > 0.0) || !(pd < INFINITY)) {
+        if ((key >> 7) == 0 || !(pd > tiny2) || !(pd < INFINITY)) {
             if (tid == 0) gst(jb.status, 1);
             return;   // key and pd are the same in every wave: the whole workgroup leaves
         }
@@ -1001,232 +1042,155 @@ __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Blocked Gauss-Jordan inverse of an n x n block, n <= 64, one workgroup of
-// 256 threads (thread (ty, tx) keeps the 4 x 4 complex tile of rows 4ty..,
-// columns 4tx..).  The same elimination as gauss_jordan_tiles (partial row
-// pivoting over the whole block, logical pivoting, the same result layout),
-// reordered into macro-steps of kGjPanel columns so that the serial part runs
-// in one wave without barriers:
-//   1. the tiles of the panel (columns k0..k0+3) go to LDS;
-//   2. wave 0 holds the panel by rows (lane = row) and eliminates its columns
-//      one by one -- pivot search (a wave maximum), scaled pivot
-//      row, rank-1 update of the panel only -- giving F: at the pivot rows P
-//      the inverse of A[P, panel], elsewhere -A[i, panel] A[P, panel]^-1;
-//   3. the pivot rows of every other column go to LDS (T = X[P]);
-//   4. every tile outside the panel becomes X[i] = (i in P ? 0 : X[i]) + F[i] T,
-//      a rank-4 update; the panel's tiles take F.
-// Three barriers per four columns instead of two per column.  The pivot search
-// compares |a|^2 scaled by the block's largest |a_ij|^2, rounded to FP32 (one
-// DPP maximum per step; magnitudes within 6e-8 of each other count as ties,
-// which go to the lowest row).  A pivot with |a|^2 <= (64 eps)^2 max |a_ij|^2
-// of the input block, or a non-finite one, sets the job's status flag; the
-// whole workgroup then leaves without writing the block.  The LDS rows are
-// padded (panel, F) or laid out by column (T) so that the lanes' 16-byte
-// accesses fall on distinct banks.
 namespace {
-constexpr int kGjPanel = 4;
 
-__device__ __forceinline__ double2 readlane2(double2 v, int l) {
-    return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
-}
-
-// max(v, v from the lane DPP control CTRL selects), lanes without a source
-// keeping v: one step of a wave maximum (VOP2 with a DPP source).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_fmax(float v) {
-    const int o = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
-    return fmaxf(v, __int_as_float(o));
-}
-
-// The lowest lane holding the wave's largest value of `mag` (wave-uniform);
-// -1 if no lane holds a positive value.
-__device__ __forceinline__ int wave_argmax_f32(float mag) {
-    float m = dpp_fmax<0x111, 0xF>(mag);   // row_shr:1
-    m = dpp_fmax<0x112, 0xF>(m);           // row_shr:2
-    m = dpp_fmax<0x114, 0xF>(m);           // row_shr:4
-    m = dpp_fmax<0x118, 0xF>(m);           // row_shr:8   -> lane 15 of each row
-    m = dpp_fmax<0x142, 0xA>(m);           // row_bcast:15
-    m = dpp_fmax<0x143, 0xC>(m);           // row_bcast:31 -> lane 63: the maximum
-    const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 63));
-    if (!(mx > 0.0f)) return -1;
-    const uint64_t hit = __builtin_amdgcn_ballot_w64(mag == mx);
-    return static_cast<int>(__builtin_ctzll(hit));
-}
-
-__device__ void gauss_jordan_blocked64(const InvJob& jb) {
-    constexpr int TG = 16, NMAX = 64, PADP = kGjPanel + 1;
-    __shared__ double2 panel[NMAX][PADP];
-    __shared__ double2 fpan[NMAX][PADP];
-    __shared__ double2 trow[kGjPanel][4][TG];   // T[m][4 tx + c] at trow[m][c][tx]
-    __shared__ int4 piv4;
-    __shared__ int perm[NMAX], pinv[NMAX];
-    __shared__ int flag;
-    __shared__ double wmax[kThreads / 64];
+// Gauss-Jordan exchange steps for blocks of up to 64 x 64 with a row per lane:
+// a workgroup of NW waves per block, wave w holding the columns
+// [w NC, (w + 1) NC) of every row in registers (NC = 64 / NW).  Step j pivots
+// on column j: the wave that owns it has chosen the pivot row p (the largest
+// |a_ij| among rows not yet used) and published column j and p in LDS, double
+// buffered, so one barrier per step suffices.  Each wave then reads its slice
+// of row p from lane p (v_readlane, into scalar registers) and applies the
+// exchange to its own columns:
+//   row p:        a_pc <- a_pc / a_pj,    a_pj <- 1 / a_pj
+//   other rows:   a_ic <- a_ic - a_ij a_pc / a_pj,    a_ij <- -a_ij / a_pj
+// and the owner of column j + 1 picks the next pivot.  The pivot row's new
+// values come from the same fused update with its own old values multiplied
+// by zero (so they are rounded once, as a_pc / a_pj).  Rows are not swapped:
+// the inverse is written out through the recorded pivot order.  A pivot with
+// |a_pj| <= 64 eps max |a| (or none, or not finite) ends the block with
+// status 1 after the barrier, every wave leaving together.
+template <int NW>
+__device__ void gauss_jordan_cols(const InvJob& jb) {
+    constexpr int NC = 64 / NW;
+    __shared__ double2 colv[2][64];   // column j before its step, by row
+    __shared__ int pj[2];             // its pivot row (-1: singular)
+    __shared__ int perm[64], pinv[64];
+    __shared__ double wmax[NW];
     const int n = jb.n;
     const int64_t ld = jb.ld;
-    const int tid = threadIdx.x, ty = tid / TG, tx = tid % TG, lane = tid & 63, wave = tid >> 6;
-    const int r0 = 4 * ty, c0 = 4 * tx;
-    double2 S[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c0 = wave * NC;
+    const bool rowok = lane < n;
+    double2 a[NC];
     double m2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = r0 + r, j = c0 + c;
-            S[r][c] = (i < n && j < n) ? gload2(jb.a + i * ld + j) : make_double2(0.0, 0.0);
-            m2 = fmax(m2, cabs2(S[r][c]));
-        }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m2 = fmax(m2, __shfl_xor(m2, off, 64));
-    if (lane == 0) wmax[wave] = m2;
-    if (tid == 0) flag = 0;
+    for (int c = 0; c < NC; ++c) {
+        a[c] = (rowok && c0 + c < n) ? gload2(jb.a + lane * ld + c0 + c) : make_double2(0.0, 0.0);
+        m2 = fmax(m2, cabs2(a[c]));
+    }
+    {
+        const int q = wave_argmax_f32(static_cast<float>(m2));
+        const double wm = q < 0 ? 0.0 : readlane_d(m2, q);
+        if (lane == 0) wmax[wave] = wm;
+    }
     __syncthreads();
-    m2 = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    m2 = wmax[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) m2 = fmax(m2, wmax[w]);
     const double tiny2 = (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16) * m2;
     const double rscale = m2 > 0.0 ? recip(m2) : 0.0;
     uint64_t used = 0;   // pivot rows so far (the same value in every thread)
-    for (int k0 = 0; k0 < n; k0 += kGjPanel) {
-        const int kb = k0 / kGjPanel, nb = min(kGjPanel, n - k0);
-        if (tx == kb) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) panel[r0 + r][c] = S[r][c];
+    // the owner of column j chooses its pivot row and publishes column j
+    auto choose = [&](const double2 v, const int j, const int b) {
+        const bool cand = rowok && !((used >> lane) & 1);
+        const float mag = cand ? static_cast<float>(cabs2(v) * rscale) : -1.0f;
+        int p = wave_argmax_f32(mag);
+        if (p >= 0) {
+            const double pd = cabs2(readlane2(v, p));
+            if (!(pd > tiny2) || !(pd < INFINITY)) p = -1;
         }
-        __syncthreads();
-        if (wave == 0) {
-            double2 pr[kGjPanel];
-#pragma unroll
-            for (int c = 0; c < kGjPanel; ++c) pr[c] = panel[lane][c];
-            bool bad = false;
-#pragma unroll
-            for (int m = 0; m < kGjPanel; ++m) {
-                if (m >= nb || bad) continue;   // uniform; no break, so the loop unrolls fully
-                const bool cand = lane < n && !((used >> lane) & 1);
-                const float mag = cand ? static_cast<float>(cabs2(pr[m]) * rscale) : -1.0f;
-                const int p = wave_argmax_f32(mag);
-                const double2 pv = readlane2(pr[m], p < 0 ? 0 : p);
-                const double pd = cabs2(pv);
-                if (p < 0 || !(pd > tiny2) || !(pd < INFINITY)) {
-                    bad = true;
-                    continue;
-                }
-                used |= 1ull << p;
-                const double rpd = recip(pd);
-                const double2 inv = make_double2(pv.x * rpd, -pv.y * rpd);
-                double2 u[kGjPanel];
-#pragma unroll
-                for (int c = 0; c < kGjPanel; ++c) u[c] = (c == m) ? inv : cmul(readlane2(pr[c], p), inv);
-                const double2 f = pr[m];
-                const bool isp = lane == p;
-#pragma unroll
-                for (int c = 0; c < kGjPanel; ++c) {
-                    const double2 base = (c == m) ? make_double2(0.0, 0.0) : pr[c];
-                    const double2 upd = make_double2(fma(-f.x, u[c].x, fma(f.y, u[c].y, base.x)),
-                                                     fma(-f.x, u[c].y, fma(-f.y, u[c].x, base.y)));
-                    pr[c] = isp ? u[c] : upd;
-                }
-                if (lane == 0) {
-                    (&piv4.x)[m] = p;
-                    perm[k0 + m] = p;
-                    pinv[p] = k0 + m;
-                }
-            }
-            if (bad && lane == 0) flag = 1;
-#pragma unroll
-            for (int c = 0; c < kGjPanel; ++c) fpan[lane][c] = pr[c];
-        }
-        __syncthreads();
-        if (flag) {
-            if (tid == 0) gst(jb.status, 1);
-            return;   // every thread read the same flag after the barrier
-        }
-        uint64_t pmask = 0;   // this macro-step's pivot rows
-        const int4 pv4 = piv4;
-        const int pvs[kGjPanel] = {pv4.x, pv4.y, pv4.z, pv4.w};
-#pragma unroll
-        for (int m = 0; m < kGjPanel; ++m) {
-            if (m >= nb) continue;
-            const int p = pvs[m];
-            pmask |= 1ull << p;
-            const int rp = p - r0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (r == rp) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) trow[m][c][tx] = S[r][c];
-                }
-        }
-        used |= pmask;
-        __syncthreads();
-        if (tx == kb) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) S[r][c] = fpan[r0 + r][c];
-        } else {
-            double2 T[kGjPanel][4];
-#pragma unroll
-            for (int m = 0; m < kGjPanel; ++m)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) T[m][c] = m < nb ? trow[m][c][tx] : make_double2(0.0, 0.0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double2 F[kGjPanel];
-#pragma unroll
-                for (int m = 0; m < kGjPanel; ++m) F[m] = m < nb ? fpan[r0 + r][m] : make_double2(0.0, 0.0);
-                const bool inp = (pmask >> (r0 + r)) & 1;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double2 acc = inp ? make_double2(0.0, 0.0) : S[r][c];
-#pragma unroll
-                    for (int m = 0; m < kGjPanel; ++m) acc = cfma(F[m], T[m][c], acc);
-                    S[r][c] = acc;
-                }
+        colv[b][lane] = v;
+        if (lane == 0) {
+            pj[b] = p;
+            if (p >= 0) {
+                perm[j] = p;
+                pinv[p] = j;
             }
         }
-    }
-    __syncthreads();   // perm / pinv complete
+    };
+    if (wave == 0) choose(a[0], 0, 0);
+    __syncthreads();
+    int b = 0;
+    for (int j0 = 0; j0 < n; j0 += NC) {
+        const int owner = j0 / NC;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = r0 + r;
-        if (i >= n) continue;
-        double2* out = jb.a + pinv[i] * ld;
+        for (int cc = 0; cc < NC; ++cc) {
+            const int j = j0 + cc;
+            if (j >= n) break;
+            const int p = __builtin_amdgcn_readfirstlane(pj[b]);
+            if (p < 0) {
+                if (threadIdx.x == 0) gst(jb.status, 1);
+                return;   // every wave read the same p after the barrier
+            }
+            const double2 f = colv[b][lane];
+            const double2 pv = colv[b][p];
+            const double rpd = recip(cabs2(pv));
+            const double2 inv = make_double2(pv.x * rpd, -pv.y * rpd);
+            const bool isp = lane == p;
+
+            // g = a_ij / a_pj for the other rows; -1 / a_pj for row p, whose
+            // old values are multiplied by s = 0
+            const double2 g = isp ? make_double2(-inv.x, -inv.y) : cmul(f, inv);
+            const double s = isp ? 0.0 : 1.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c0 + c < n) gstore2(out + perm[c0 + c], S[r][c]);
+            for (int c = 0; c < NC; ++c) {
+                const double2 r = readlane2(a[c], p);   // row p of this column
+                a[c] = make_double2(fma(-g.x, r.x, fma(g.y, r.y, a[c].x * s)),
+                                    fma(-g.x, r.y, fma(-g.y, r.x, a[c].y * s)));
+            }
+            if (wave == owner) a[cc] = make_double2(-g.x, -g.y);
+            used |= 1ull << p;
+            b ^= 1;
+            if (j + 1 < n) {
+                if (cc + 1 < NC) {
+                    if (wave == owner) choose(a[cc + 1 < NC ? cc + 1 : 0], j + 1, b);
+                } else if (wave == owner + 1) {
+                    choose(a[0], j + 1, b);
+                }
+            }
+            __syncthreads();
+        }
     }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (rowok && c0 + c < n) gstore2(jb.a + pinv[lane] * ld + perm[c0 + c], a[c]);
 }
 
 }  // namespace
 
-__global__ void __launch_bounds__(64) k_gauss_jordan_8(const InvJob* __restrict__ jobs) {
-    gauss_jordan_tiles<8>(jobs[blockIdx.x]);
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_gauss_jordan_cols(const InvJob* __restrict__ jobs) {
+    gauss_jordan_cols<NW>(jobs[blockIdx.x]);
 }
-__global__ void __launch_bounds__(256) k_gauss_jordan_16(const InvJob* __restrict__ jobs) {
-    gauss_jordan_blocked64(jobs[blockIdx.x]);
-}
+template __global__ void k_gauss_jordan_cols<8>(const InvJob*);
 __global__ void __launch_bounds__(1024) k_gauss_jordan_32(const InvJob* __restrict__ jobs) {
     gauss_jordan_tiles<32>(jobs[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
 // Batched sketch Y = Omega X with a real Omega and complex X (randomized ID:
-// the CPQR then runs on the l x n sketch instead of the m x n stacked matrix).
-// Workgroup: a 64 x 64 tile of one job's Y, K in steps of 16 through LDS;
-// thread t owns rows r0 + (t % 16) + 16a and columns c0 + (t / 16) + 16b
-// (a, b < 4), so consecutive threads write consecutive rows of a column.
-// With ksplit > 1 the K range is cut into ksplit slices of whole 16-row steps,
-// one workgroup per (tile, slice), and slice s writes its partial tile to
-// part + s * pstride (the levels with few tiles, which would otherwise leave
-// most compute units idle); k_sum_partials adds the slices in a fixed order.
+// the CPQR then runs on the l x n sketch instead of the m x n stacked matrix),
+// on the FP64 matrix cores: X is read as a real m x 2n matrix (column 2j the
+// real part of complex column j, 2j + 1 its imaginary part), so that Y is one
+// real product.  Workgroup: 4 waves (2 x 2) on a 64 x 64 real tile of Y (64
+// rows, 32 complex columns); each wave owns 32 x 32 as 2 x 2 blocks of
+// 16 x 16, updated by v_mfma_f64_16x16x4f64 (operand layout at gemm_tile
+// below).  K runs in stages of 16 rows of X through LDS, the next stage's
+// loads in flight during the current stage's products.  With ksplit > 1 the K
+// range is cut into ksplit slices of whole 16-row stages, one workgroup per
+// (tile, slice), and slice s writes its partial tile to part + s * pstride
+// (the levels with few tiles, which would otherwise leave most compute units
+// idle); k_sum_partials adds the slices in a fixed order.
+namespace {
+typedef double v4d_s __attribute__((ext_vector_type(4)));
+}  // namespace
+
 __global__ void __launch_bounds__(kThreads)
 k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
          const double* __restrict__ omega, int64_t ldo, int ksplit, int64_t pstride) {
-    constexpr int T = 64, KS = 16;
-    __shared__ double Os[KS][T];
-    __shared__ double2 Xs[KS][T];
+    constexpr int TR = 64, TC = 32, KS = 16;   // tile rows, complex columns, K stage
+    __shared__ double Os[KS][TR];              // Omega tile, k-major
+    __shared__ double2 Xs[KS][TC];             // X tile, k-major
     int lo = 0, hi = njobs;
     const int64_t tile = blockIdx.x;
     while (hi - lo > 1) {
@@ -1239,61 +1203,73 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
     const int64_t local = local_s / ksplit;
     const int kc = ((jb.m + ksplit - 1) / ksplit + KS - 1) / KS * KS;
     const int kb = slice * kc, ke = min(jb.m, kb + kc);   // rows [kb, ke) of X, empty for trailing slices
-    const int tiles_c = (jb.n + T - 1) / T;
-    const int r0 = static_cast<int>(local / tiles_c) * T;
-    const int c0 = static_cast<int>(local % tiles_c) * T;
-    const int tid = threadIdx.x, tr = tid % 16, tc = tid / 16;
-    double2 acc[4][4];
+    const int tiles_c = (jb.n + TC - 1) / TC;
+    const int r0 = static_cast<int>(local / tiles_c) * TR;
+    const int c0 = static_cast<int>(local % tiles_c) * TC;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;   // the wave's rows and real columns in the tile
+    const int fl = lane & 15, fk = lane >> 4;
+    // stage loads: 16 consecutive threads read 16 consecutive k of one row of
+    // Omega (4 rows each) or of one column of X (2 columns each)
+    const int lk = tid & 15, lr = tid >> 4;
+    double po[4];
+    double2 px[2];
+    auto load_stage = [&](int l0) {
+        const int l = l0 + lk;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 + lr + 16 * q;
+            po[q] = (r < jb.l && l < ke) ? omega[static_cast<int64_t>(r) * ldo + l] : 0.0;
+        }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+        for (int q = 0; q < 2; ++q) {
+            const int j = c0 + lr + 16 * q;
+            px[q] = (j < jb.n && l < ke) ? gload2(jb.x + static_cast<int64_t>(j) * jb.m + l) : make_double2(0.0, 0.0);
+        }
+    };
+    v4d_s acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = v4d_s{0.0, 0.0, 0.0, 0.0};
+    if (kb < ke) load_stage(kb);
     for (int l0 = kb; l0 < ke; l0 += KS) {
-        // Omega tile (64 rows x 16): thread loads rows tid/16 + 16q, column tid%16
+        __syncthreads();   // the previous stage's fragment reads are done
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int rr = tid / 16 + 16 * q, kk = tid % 16;
-            const int r = r0 + rr, l = l0 + kk;
-            Os[kk][rr] = (r < jb.l && l < ke) ? omega[static_cast<int64_t>(r) * ldo + l] : 0.0;
-        }
-        // X tile (16 x 64 columns): 16 consecutive threads read one column's 16 rows
+        for (int q = 0; q < 4; ++q) Os[lk][lr + 16 * q] = po[q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int jj = tid / 16 + 16 * q, kk = tid % 16;
-            const int j = c0 + jj, l = l0 + kk;
-            Xs[kk][jj] = (j < jb.n && l < ke) ? gload2(jb.x + static_cast<int64_t>(j) * jb.m + l)
-                                                : make_double2(0.0, 0.0);
-        }
+        for (int q = 0; q < 2; ++q) Xs[lk][lr + 16 * q] = px[q];
         __syncthreads();
+        if (l0 + KS < ke) load_stage(l0 + KS);   // in flight during the products
+        const double* xs = reinterpret_cast<const double*>(&Xs[0][0]);
 #pragma unroll
-        for (int kk = 0; kk < KS; ++kk) {
-            double o[4];
-            double2 xv[4];
+        for (int kk = 0; kk < KS; kk += 4) {
+            double av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) o[a] = Os[kk][tr + 16 * a];
+            for (int x = 0; x < 2; ++x) av[x] = Os[kk + fk][wr + 16 * x + fl];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xv[b] = Xs[kk][tc + 16 * b];
+            for (int y = 0; y < 2; ++y) bv[y] = xs[(kk + fk) * (2 * TC) + wc + 16 * y + fl];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    acc[a][b].x = fma(o[a], xv[b].x, acc[a][b].x);
-                    acc[a][b].y = fma(o[a], xv[b].y, acc[a][b].y);
-                }
-        }
-        __syncthreads();
-    }
-    double2* dst = ksplit == 1 ? jb.y : jb.part + slice * pstride;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int j = c0 + tc + 16 * b;
-        if (j >= jb.n) continue;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = r0 + tr + 16 * a;
-            if (r < jb.l) gstore2(dst + static_cast<int64_t>(j) * jb.l + r, acc[a][b]);
+                for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
         }
     }
+    // result register q of lane l: row 4 q + l / 16 of the block, real column
+    // l % 16 (complex column (l % 16) / 2, part l % 2)
+    double* dst = reinterpret_cast<double*>(ksplit == 1 ? jb.y : jb.part + slice * pstride);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + wr + 16 * x + 4 * q + fk;
+                const int rc = wc + 16 * y + fl;   // real column within the tile
+                const int j = c0 + (rc >> 1);
+                if (r < jb.l && j < jb.n)
+                    gst(dst + 2 * (static_cast<int64_t>(j) * jb.l + r) + (rc & 1), acc[x][y][q]);
+            }
 }
 
 __global__ void __launch_bounds__(kThreads)

@@ -416,7 +416,7 @@ def test_hss_rejects_bad_options(gpu_lib):
 
 
 def test_hss_kernel_timing_counts_launches(gpu_lib):
-    """opts.kernel_timing: every batched GEMM and Gauss-Jordan launch of the build
+    """opts.kernel_timing: every batched GEMM, Gauss-Jordan, sketch and entry-generation launch of the build
     is event-timed; the counts, flops and times are positive, the solution is the
     same as without timing, and the fields stay zero when timing is off."""
     bm = gpu_lib
@@ -424,12 +424,16 @@ def test_hss_kernel_timing_counts_launches(gpu_lib):
     media = sc.media_from_index(50.0, 1.5)
     p, nd = setup(bm, [sc.star(0.3, 5)], [2048], media)
     b = bm.bm_rhs_plane_wave(p, 0.2)
-    plain = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10)
-    timed = bm.bm_hss_build(p, leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, kernel_timing=True)
+    opts = dict(leaf=64, proxy_ratio=1.5, proxy_points=64, id_tol=1e-10, sketch=-1, max_rank_ratio=-1.0)
+    plain = bm.bm_hss_build(p, **opts)
+    timed = bm.bm_hss_build(p, kernel_timing=True, **opts)
     s0, s1 = bm.bm_hss_stats(plain), bm.bm_hss_stats(timed)
     note(f"  gemm {s1['gemm_launches']} launches {s1['seconds_gemm'] * 1e3:.3f} ms {s1['gemm_flops']:.3e} flops; "
-         f"inv {s1['inv_launches']} launches {s1['seconds_inv'] * 1e3:.3f} ms {s1['inv_flops']:.3e} flops")
-    for k in ("gemm_launches", "gemm_flops", "seconds_gemm", "inv_launches", "inv_flops", "seconds_inv"):
+         f"inv {s1['inv_launches']} launches {s1['seconds_inv'] * 1e3:.3f} ms {s1['inv_flops']:.3e} flops; "
+         f"sketch {s1['sketch_launches']} launches {s1['seconds_sketch'] * 1e3:.3f} ms; "
+         f"gen {s1['gen_launches']} launches {s1['seconds_gen'] * 1e3:.3f} ms {s1['gen_pairs']:.3e} pairs")
+    for k in ("gemm_launches", "gemm_flops", "seconds_gemm", "inv_launches", "inv_flops", "seconds_inv",
+              "sketch_launches", "sketch_flops", "seconds_sketch", "gen_launches", "gen_pairs", "seconds_gen"):
         assert s0[k] == 0
         assert s1[k] > 0
     x0 = bm.bm_hss_solve(plain, b).cpu().numpy()

@@ -276,13 +276,16 @@ def test_invalid_arguments_enqueue_nothing(gpu_lib):
 
 
 def test_fp64_fma_probe_values(gpu_lib):
-    """The FMA probe computes what it claims: per thread, 16 chains of
+    """The benchmark's FMA probe (libbmhss_probe.so, not part of the product
+    library) computes what it claims: per thread, 16 chains of
     a <- a x + y from a_c = 1e-3 (c + 1), x = 1 + 1e-9 (t mod 1024), y = 1e-12 (t mod 256);
     after n steps a_n = a_0 x^n + y (x^n - 1)/(x - 1) (x = 1: a_0 + n y)."""
     import torch
-    bm = gpu_lib
+    import bench
     blocks, iters = 4, 300
-    out = bm.bm_fp64_fma_probe(blocks, iters).cpu().numpy()
+    out = bench.fma_probe(blocks, iters, torch.empty(blocks * 256, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
     for t in (0, 1, 255, 256, 1023, 1024 - 1, blocks * 256 - 1):
         x = 1.0 + 1e-9 * (t & 1023)
         y = 1e-12 * (t % 256)
