@@ -925,14 +925,14 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
     int mmax = 0;
     for (const CpqrJob& j : cj) mmax = std::max(mmax, j.m);
     // every box small enough for one workgroup's registers: the whole CPQR in one launch
-    const int RS = mmax <= 128 ? 32 : mmax <= 144 ? 36 : mmax <= 160 ? 40 : 0;
+    const int RS = mmax <= 128 ? 8 : mmax <= 144 ? 9 : mmax <= 160 ? 10 : 0;   // rows per lane / 16
     *fused_out = nmax <= kFusedCols && RS > 0;
     if (*fused_out) {
         if ((e = hipEventRecord(ev0, sc.s)) != hipSuccess) return e;
         switch (RS) {
-            case 32: hipLaunchKernelGGL(k_cpqr_fused<32>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
-            case 36: hipLaunchKernelGGL(k_cpqr_fused<36>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
-            default: hipLaunchKernelGGL(k_cpqr_fused<40>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
+            case 8: hipLaunchKernelGGL(k_cpqr_fused<8>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
+            case 9: hipLaunchKernelGGL(k_cpqr_fused<9>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
+            default: hipLaunchKernelGGL(k_cpqr_fused<10>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
         }
         if ((e = hipEventRecord(ev1, sc.s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_cpqr_finish, dim3(nb), dim3(kThreads), 0, sc.s, dcj);

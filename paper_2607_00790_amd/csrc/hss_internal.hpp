@@ -139,10 +139,11 @@ __global__ void k_cpqr_step(const CpqrJob* jobs, int k, double tol);
 constexpr int kCpqrCols = 1;
 template <int R>
 __global__ void k_cpqr_step_reg(const CpqrJob* jobs, int k, double tol);
-// whole-box CPQR in registers: n <= kFusedCols columns, m <= 4 RS rows
+// whole-box CPQR in registers: n <= kFusedCols columns (4 per lane, 16 lanes
+// per column group), m <= 16 R rows
 constexpr int kFusedThreads = 512;
 constexpr int kFusedCols = kFusedThreads / 4;
-template <int RS>
+template <int R>
 __global__ void k_cpqr_fused(const CpqrJob* jobs, double tol);
 __global__ void k_cpqr_finish(const CpqrJob* jobs);
 __global__ void k_cpqr_ranks(const CpqrJob* jobs, int nb, int32_t* ranks, int32_t* active);

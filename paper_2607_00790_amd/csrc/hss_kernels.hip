@@ -64,6 +64,55 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// Maximum over the wave of an unsigned 64-bit key, by DPP row shifts and row
+// broadcasts (no LDS traffic); the result is wave-uniform.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp_max_step(uint64_t key) {
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(key), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(key >> 32), CTRL, ROW_MASK, 0xF, false);
+    const uint64_t o = (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+    return o > key ? o : key;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t key) {
+    key = dpp_max_step<0x111, 0xF>(key);   // row_shr:1
+    key = dpp_max_step<0x112, 0xF>(key);   // row_shr:2
+    key = dpp_max_step<0x114, 0xF>(key);   // row_shr:4
+    key = dpp_max_step<0x118, 0xF>(key);   // row_shr:8   -> lane 15 of each row: row maximum
+    key = dpp_max_step<0x142, 0xA>(key);   // row_bcast:15 -> lanes 31, 63: two rows each
+    key = dpp_max_step<0x143, 0xC>(key);   // row_bcast:31 -> lane 63: all four rows
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(key), 63);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(key >> 32), 63);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ double2 readlane2(double2 v, int l) {
+    return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
+}
+
+// max(v, v from the lane DPP control CTRL selects), lanes without a source
+// keeping v: one step of a wave maximum (VOP2 with a DPP source).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_fmax(float v) {
+    const int o = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+    return fmaxf(v, __int_as_float(o));
+}
+
+// The lowest lane holding the wave's largest value of `mag` (wave-uniform);
+// -1 if no lane holds a positive value.
+__device__ __forceinline__ int wave_argmax_f32(float mag) {
+    float m = dpp_fmax<0x111, 0xF>(mag);   // row_shr:1
+    m = dpp_fmax<0x112, 0xF>(m);           // row_shr:2
+    m = dpp_fmax<0x114, 0xF>(m);           // row_shr:4
+    m = dpp_fmax<0x118, 0xF>(m);           // row_shr:8   -> lane 15 of each row
+    m = dpp_fmax<0x142, 0xA>(m);           // row_bcast:15
+    m = dpp_fmax<0x143, 0xC>(m);           // row_bcast:31 -> lane 63: the maximum
+    const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 63));
+    if (!(mx > 0.0f)) return -1;
+    const uint64_t hit = __builtin_amdgcn_ballot_w64(mag == mx);
+    return static_cast<int>(__builtin_ctzll(hit));
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -550,111 +599,190 @@ k_cpqr_step_reg(const CpqrJob* __restrict__ jobs, int k, double tol) {
     }
 }
 
+// Sum over the 16 lanes of each DPP row (every lane of the row gets the total):
+// xor 1 and xor 2 by quad permutations, the other quad of the half-row by a
+// shift of 4 in the direction that stays inside it, the other half-row by a
+// rotation of 8.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    const double up = dpp_d<0x104>(v), dn = dpp_d<0x114>(v);   // row_shl:4, row_shr:4
+    v += (threadIdx.x & 4) ? dn : up;
+    v += dpp_d<0x128>(v);  // row_ror:8
+    return v;
+}
+
 // The whole CPQR of one box in one workgroup, for boxes of at most
-// kFusedCols columns and 4 RS rows: the matrix stays in registers for all
-// steps.  Four consecutive lanes hold one column (lane s of the group: rows
-// s, s + 4, s + 8, ...), so a column's dot product and norm need two
-// butterfly steps.  Each step stages the Householder vector in LDS as a full
-// column: zeros above row k, w0 at row k, the pivot column below, zeros from
-// row m on; the dot products and updates then run over every slot with no
-// masks or branches.  Pivot choice (largest remaining column norm, lowest
-// index on ties), rank rule |R_kk| > tol |R_00|, logical pivoting and the
-// layout of the result (R in the columns perm[0..rank), diagonal in rdiag) are
-// those of the step-wise kernels, so k_cpqr_finish and k_interp follow
-// unchanged.  Grid: one workgroup of kFusedThreads per box.
-template <int RS>
+// kFusedCols columns and 16 R rows: the matrix stays in registers for all
+// steps.  Lane (c, g) of a wave, c = lane / 16, g = lane % 16, holds rows
+// g, g + 16, ..., g + 16 (R - 1) of the four columns 4 (4 w + c) .. + 3 (w the
+// wave), so a column lives in one 16-lane DPP row and its dot products and
+// norms need four DPP steps, and each lane reads the Householder vector (R
+// values from LDS, once for the dot products and once for the update) for four
+// columns.  Per step: the pivot (largest
+// remaining column norm, lowest index on ties: an exact maximum of the norm's
+// bit pattern, per wave by DPP, then over the waves through LDS), then the
+// lanes of the pivot column stage the Householder vector in LDS (zeros above
+// row k; the lane of row k writes w0 = x_k - alpha and the scalars alpha and
+// beta), then every lane applies it to its columns.  Blocks of 16 rows
+// entirely above row k are skipped.  Rank rule |R_kk| > tol |R_00|, logical
+// pivoting and the layout of the result (R in the columns perm[0..rank),
+// diagonal in rdiag) are those of the step-wise kernels, so k_cpqr_finish and
+// k_interp follow unchanged.  Grid: one workgroup of kFusedThreads per box.
+template <int R>
 __global__ void __launch_bounds__(kFusedThreads)
 k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
-    __shared__ double sv[kFusedThreads / 64];
-    __shared__ int si[kFusedThreads / 64];
-    __shared__ double2 ws[4 * RS];
+    constexpr int NW = kFusedThreads / 64;
+    __shared__ double2 ws[16 * R];
+    __shared__ uint64_t wkey[NW];
+    __shared__ int wcol[NW];
     __shared__ double sbeta;
+    __shared__ double2 salpha;
     const CpqrJob jb = jobs[blockIdx.x];
     const int n = jb.n, m = jb.m;
-    const int j = threadIdx.x >> 2, s = threadIdx.x & 3;
-    const bool mine = j < n;
-    for (int r = threadIdx.x; r < 4 * RS; r += kFusedThreads) ws[r] = make_double2(0.0, 0.0);
-    double2 X[RS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane & 15, c0 = 4 * (4 * wave + (lane >> 4));   // first of this lane's four columns
+    double2 X[R][4];
 #pragma unroll
-    for (int t = 0; t < RS; ++t) {
-        const int r = s + 4 * t;
-        X[t] = (mine && r < m) ? gload2(jb.x + static_cast<int64_t>(j) * m + r) : make_double2(0.0, 0.0);
+    for (int t = 0; t < R; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int r = g + 16 * t;
+            X[t][c] = (c0 + c < n && r < m) ? gload2(jb.x + static_cast<int64_t>(c0 + c) * m + r)
+                                            : make_double2(0.0, 0.0);
+        }
+    double nrm[4];
+    bool used[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double q = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) q = fma(X[t][c].x, X[t][c].x, fma(X[t][c].y, X[t][c].y, q));
+        nrm[c] = row16_sum(q);
+        used[c] = c0 + c >= n;
+        if (!used[c] && g == 0) gst(jb.used + c0 + c, 0);
     }
-    double nrm = 0;
-#pragma unroll
-    for (int t = 0; t < RS; ++t) nrm = fma(X[t].x, X[t].x, fma(X[t].y, X[t].y, nrm));
-    nrm += __shfl_xor(nrm, 1, 64);
-    nrm += __shfl_xor(nrm, 2, 64);
-    bool used = !mine;
-    if (mine && s == 0) gst(jb.used + j, 0);
     const int kmax = n < m ? n : m;
     double ref = 0;
     int k = 0;
     for (; k < kmax; ++k) {
-        double bv = (!used && s == 0) ? nrm : -1.0;
-        int bi = (!used && s == 0) ? j : n;
-        block_argmax(bv, bi, sv, si);   // ends with a barrier: ws is free
-        if (k == 0) ref = sqrt(bv);
-        if (!(sqrt(bv) > tol * ref) || ref == 0 || bi >= n) break;
-        const int p = bi;
-        if (j == p) {
-            used = true;
+        // the pivot: per lane the best of its columns (as norm bits + 1, 0 for
+        // none), per wave the lowest lane holding the maximum, then the waves
+        uint64_t key = 0;
+        int bj = 0;
 #pragma unroll
-            for (int t = 0; t < RS; ++t) {
-                const int r = s + 4 * t;
-                if (r < m) ws[r] = r >= k ? X[t] : make_double2(0.0, 0.0);
+        for (int c = 3; c >= 0; --c) {
+            const uint64_t kc = used[c] ? 0 : static_cast<uint64_t>(__double_as_longlong(nrm[c])) + 1;
+            if (kc >= key && kc > 0) {
+                key = kc;
+                bj = c0 + c;
+            }
+        }
+        uint64_t mk = wave_max_u64(key);
+        {
+            const uint64_t hit = __builtin_amdgcn_ballot_w64(key == mk && mk > 0);
+            const int l = hit ? static_cast<int>(__builtin_ctzll(hit)) : 0;
+            const int wj = __builtin_amdgcn_readlane(bj, l);
+            if (lane == 0) {
+                wkey[wave] = mk;
+                wcol[wave] = wj;
+            }
+        }
+        __syncthreads();   // also: every read of ws of the previous step is done
+        const uint64_t ek = lane < NW ? wkey[lane] : 0;
+        const int ej = lane < NW ? wcol[lane] : 0;
+        mk = wave_max_u64(ek);
+        const uint64_t hit = __builtin_amdgcn_ballot_w64(ek == mk && mk > 0);
+        const int p = hit ? __builtin_amdgcn_readlane(ej, static_cast<int>(__builtin_ctzll(hit))) : n;
+        const double bv = mk > 0 ? __longlong_as_double(static_cast<long long>(mk - 1)) : 0.0;
+        if (k == 0) ref = sqrt(bv);
+        if (!(sqrt(bv) > tol * ref) || ref == 0 || p >= n) break;   // uniform
+        const int kb = k >> 4;   // blocks of 16 rows below kb lie above row k
+        if (c0 == (p & ~3)) {
+            const int pc = p & 3;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c != pc) continue;   // uniform
+                used[c] = true;
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    if (t < kb) continue;   // uniform
+                    const int r = g + 16 * t;
+                    double2 v = r >= k && r < m ? X[t][c] : make_double2(0.0, 0.0);
+                    if (r == k) {
+                        const double xn = sqrt(bv);
+                        const double a0 = sqrt(cabs2(v));
+                        const double ia = a0 > 0 ? recip(a0) : 0.0;
+                        const double2 ph = a0 > 0 ? make_double2(v.x * ia, v.y * ia) : make_double2(1.0, 0.0);
+                        const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
+                        v = make_double2(v.x - alpha.x, v.y - alpha.y);
+                        sbeta = xn > 0 ? recip(xn * (xn + a0)) : 0.0;
+                        salpha = alpha;
+                    }
+                    ws[r] = v;
+                }
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const double xn = sqrt(bv);
-            const double2 x0 = ws[k];
-            const double a0 = sqrt(cabs2(x0));
-            const double2 ph = a0 > 0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
-            const double2 alpha = make_double2(-ph.x * xn, -ph.y * xn);
-            ws[k] = make_double2(x0.x - alpha.x, x0.y - alpha.y);
-            sbeta = xn > 0 ? 1.0 / (xn * (xn + a0)) : 0.0;
-            gst(jb.perm + k, p);
-            gstore2(jb.rdiag + k, alpha);
-        }
-        __syncthreads();
         const double beta = sbeta;
-        double gr = 0, gi = 0;
-#pragma unroll
-        for (int t = 0; t < RS; ++t) {
-            const double2 w = ws[s + 4 * t];
-            gr = fma(w.x, X[t].x, fma(w.y, X[t].y, gr));
-            gi = fma(w.x, X[t].y, fma(-w.y, X[t].x, gi));
+        if (threadIdx.x == 0) {
+            gst(jb.perm + k, p);
+            gstore2(jb.rdiag + k, salpha);
         }
-        gr += __shfl_xor(gr, 1, 64);
-        gr += __shfl_xor(gr, 2, 64);
-        gi += __shfl_xor(gi, 1, 64);
-        gi += __shfl_xor(gi, 2, 64);
-        // pivoted columns (and columns past n) stay as they are
-        gr = used ? 0.0 : gr * beta;
-        gi = used ? 0.0 : gi * beta;
-        // read w again below instead of keeping RS values live across the
-        // butterfly (a compiler barrier only: no instruction)
+        double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if (t < kb) continue;   // uniform
+            const double2 w = ws[g + 16 * t];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ar[c] = fma(w.x, X[t][c].x, fma(w.y, X[t][c].y, ar[c]));
+                ai[c] = fma(w.x, X[t][c].y, fma(-w.y, X[t][c].x, ai[c]));
+            }
+        }
+        double gr[4], gi[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            // pivoted columns (and columns past n) stay as they are
+            gr[c] = used[c] ? 0.0 : row16_sum(ar[c]) * beta;
+            gi[c] = used[c] ? 0.0 : row16_sum(ai[c]) * beta;
+        }
+        // w is read again below instead of being kept in R more registers
+        // across the reductions (a compiler barrier only: no instruction)
         asm volatile("" ::: "memory");
-        double sn = 0;
+        double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < RS; ++t) {
-            const int r = s + 4 * t;
-            const double2 w = ws[r];
-            X[t].x = fma(-gr, w.x, fma(gi, w.y, X[t].x));
-            X[t].y = fma(-gr, w.y, fma(-gi, w.x, X[t].y));
-            const double q = fma(X[t].x, X[t].x, X[t].y * X[t].y);
-            sn += r > k ? q : 0.0;
+        for (int t = 0; t < R; ++t) {
+            if (t < kb) continue;   // uniform
+            const double2 w = ws[g + 16 * t];
+            const bool below = g + 16 * t > k;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                X[t][c].x = fma(-gr[c], w.x, fma(gi[c], w.y, X[t][c].x));
+                X[t][c].y = fma(-gr[c], w.y, fma(-gi[c], w.x, X[t][c].y));
+                const double e = fma(X[t][c].x, X[t][c].x, X[t][c].y * X[t][c].y);
+                q[c] += below ? e : 0.0;
+            }
         }
-        sn += __shfl_xor(sn, 1, 64);
-        sn += __shfl_xor(sn, 2, 64);
-        if (!used) nrm = sn;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double sn = row16_sum(q[c]);
+            if (!used[c]) nrm[c] = sn;
+        }
     }
 #pragma unroll
-    for (int t = 0; t < RS; ++t) {
-        const int r = s + 4 * t;
-        if (mine && r < m) gstore2(jb.x + static_cast<int64_t>(j) * m + r, X[t]);
-    }
+    for (int t = 0; t < R; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int r = g + 16 * t;
+            if (c0 + c < n && r < m) gstore2(jb.x + static_cast<int64_t>(c0 + c) * m + r, X[t][c]);
+        }
     if (threadIdx.x == 0) {
         gst(&jb.st->ref, ref);
         gst(&jb.st->rank, k);
@@ -662,9 +790,9 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
     }
 }
 
-template __global__ void k_cpqr_fused<32>(const CpqrJob*, double);
-template __global__ void k_cpqr_fused<36>(const CpqrJob*, double);
-template __global__ void k_cpqr_fused<40>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<8>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<9>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<10>(const CpqrJob*, double);
 
 template __global__ void k_cpqr_step_reg<4>(const CpqrJob*, int, double);
 template __global__ void k_cpqr_step_reg<8>(const CpqrJob*, int, double);
@@ -853,55 +981,6 @@ template __global__ void k_interp_wave<4>(const CpqrJob*, const int32_t*, const 
 // relative 2^-45 count as ties and ties go to the lowest row.  A zero or
 // non-finite pivot sets the job's status flag and leaves the block unspecified.
 namespace {
-
-// Maximum over the wave of an unsigned 64-bit key, by DPP row shifts and row
-// broadcasts (no LDS traffic); the result is wave-uniform.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint64_t dpp_max_step(uint64_t key) {
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(key), CTRL, ROW_MASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(key >> 32), CTRL, ROW_MASK, 0xF, false);
-    const uint64_t o = (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
-    return o > key ? o : key;
-}
-
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t key) {
-    key = dpp_max_step<0x111, 0xF>(key);   // row_shr:1
-    key = dpp_max_step<0x112, 0xF>(key);   // row_shr:2
-    key = dpp_max_step<0x114, 0xF>(key);   // row_shr:4
-    key = dpp_max_step<0x118, 0xF>(key);   // row_shr:8   -> lane 15 of each row: row maximum
-    key = dpp_max_step<0x142, 0xA>(key);   // row_bcast:15 -> lanes 31, 63: two rows each
-    key = dpp_max_step<0x143, 0xC>(key);   // row_bcast:31 -> lane 63: all four rows
-    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(key), 63);
-    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(key >> 32), 63);
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-__device__ __forceinline__ double2 readlane2(double2 v, int l) {
-    return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
-}
-
-// max(v, v from the lane DPP control CTRL selects), lanes without a source
-// keeping v: one step of a wave maximum (VOP2 with a DPP source).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_fmax(float v) {
-    const int o = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
-    return fmaxf(v, __int_as_float(o));
-}
-
-// The lowest lane holding the wave's largest value of `mag` (wave-uniform);
-// -1 if no lane holds a positive value.
-__device__ __forceinline__ int wave_argmax_f32(float mag) {
-    float m = dpp_fmax<0x111, 0xF>(mag);   // row_shr:1
-    m = dpp_fmax<0x112, 0xF>(m);           // row_shr:2
-    m = dpp_fmax<0x114, 0xF>(m);           // row_shr:4
-    m = dpp_fmax<0x118, 0xF>(m);           // row_shr:8   -> lane 15 of each row
-    m = dpp_fmax<0x142, 0xA>(m);           // row_bcast:15
-    m = dpp_fmax<0x143, 0xC>(m);           // row_bcast:31 -> lane 63: the maximum
-    const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 63));
-    if (!(mx > 0.0f)) return -1;
-    const uint64_t hit = __builtin_amdgcn_ballot_w64(mag == mx);
-    return static_cast<int>(__builtin_ctzll(hit));
-}
 
 template <int TG>
 __device__ __forceinline__ void gauss_jordan_tiles(const InvJob& jb) {
