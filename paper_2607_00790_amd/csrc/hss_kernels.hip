@@ -1268,8 +1268,11 @@ __global__ void __launch_bounds__(kThreads)
 k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs,
          const double* __restrict__ omega, int64_t ldo, int ksplit, int64_t pstride) {
     constexpr int TR = 64, TC = 32, KS = 16;   // tile rows, complex columns, K stage
-    __shared__ double Os[KS][TR];              // Omega tile, k-major
-    __shared__ double2 Xs[KS][TC];             // X tile, k-major
+    // k-fast in LDS with rows padded to KS + 1: the stage stores (16 lanes along
+    // k) and the fragment reads (16 lanes along rows or columns) then fall on
+    // distinct banks
+    __shared__ double Os[TR][KS + 1];          // Omega tile by rows
+    __shared__ double2 Xs[TC][KS + 1];         // X tile by columns
     int lo = 0, hi = njobs;
     const int64_t tile = blockIdx.x;
     while (hi - lo > 1) {
@@ -1315,9 +1318,9 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
     for (int l0 = kb; l0 < ke; l0 += KS) {
         __syncthreads();   // the previous stage's fragment reads are done
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Os[lk][lr + 16 * q] = po[q];
+        for (int q = 0; q < 4; ++q) Os[lr + 16 * q][lk] = po[q];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) Xs[lk][lr + 16 * q] = px[q];
+        for (int q = 0; q < 2; ++q) Xs[lr + 16 * q][lk] = px[q];
         __syncthreads();
         if (l0 + KS < ke) load_stage(l0 + KS);   // in flight during the products
         const double* xs = reinterpret_cast<const double*>(&Xs[0][0]);
@@ -1325,9 +1328,12 @@ k_sketch(const SketchJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
         for (int kk = 0; kk < KS; kk += 4) {
             double av[2], bv[2];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) av[x] = Os[kk + fk][wr + 16 * x + fl];
+            for (int x = 0; x < 2; ++x) av[x] = Os[wr + 16 * x + fl][kk + fk];
 #pragma unroll
-            for (int y = 0; y < 2; ++y) bv[y] = xs[(kk + fk) * (2 * TC) + wc + 16 * y + fl];
+            for (int y = 0; y < 2; ++y) {
+                const int rc = wc + 16 * y + fl;   // real column: complex column rc / 2, part rc % 2
+                bv[y] = xs[((rc >> 1) * (KS + 1) + kk + fk) * 2 + (rc & 1)];
+            }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -1395,8 +1401,12 @@ __device__ __forceinline__ void gemm_tile(const GemmJob* __restrict__ jobs, cons
     constexpr int SQ = NW == 4 ? 2 : 1, TT = WT * SQ, BL = WT / 16, THREADS = 64 * NW;
     constexpr int LOADS = TT * kGemmK / THREADS;   // elements of each operand per thread and chunk
     static_assert(LOADS * THREADS == TT * kGemmK && THREADS % TT == 0, "tile shape");
-    __shared__ double Ar[kGemmK][TT], Ai[kGemmK][TT];   // A tile, k-major
-    __shared__ double Br[kGemmK][TT], Bi[kGemmK][TT];   // B tile, k-major
+    // k-major tiles with rows padded by two doubles: the chunk stores of an
+    // operand whose k index is contiguous in memory (8 lanes along k, then the
+    // next row or column) and the fragment reads (16 lanes along a row) then
+    // fall on distinct banks
+    __shared__ double Ar[kGemmK][TT + 2], Ai[kGemmK][TT + 2];   // A tile, k-major
+    __shared__ double Br[kGemmK][TT + 2], Bi[kGemmK][TT + 2];   // B tile, k-major
     int lo = 0, hi = njobs;
     const int64_t tile = blockIdx.x;
     while (hi - lo > 1) {
