@@ -394,6 +394,16 @@ int inv_base() {
     return v;
 }
 
+// Gauss-Jordan for blocks up to 64: two elimination steps per barrier (the
+// default) or one (BMHSS_TUNE_GJ_PAIRS=0).
+bool gj_pairs() {
+    static const bool v = [] {
+        const char* e = std::getenv("BMHSS_TUNE_GJ_PAIRS");
+        return !(e && std::atoi(e) == 0);
+    }();
+    return v;
+}
+
 // A product worth a library call: the batched tile kernel runs one 32 x 32
 // tile per workgroup without matrix cores, which is fine for the many small
 // per-box products but slow for the few large ones (the root inverse's Schur
@@ -712,7 +722,9 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
             for (const InvJob& j : base) g_ktimes->inv_flops += 8.0 * j.n * j.n * j.n;
         sc.rec([=]() {
             if (ea) (void)hipEventRecord(ea, st);
-            if (nbase <= 64)
+            if (nbase <= 64 && gj_pairs())
+                hipLaunchKernelGGL(k_gauss_jordan_pairs<8>, dim3(nj), dim3(512), 0, st, dj);
+            else if (nbase <= 64)
                 hipLaunchKernelGGL(k_gauss_jordan_cols<8>, dim3(nj), dim3(512), 0, st, dj);
             else
                 hipLaunchKernelGGL(k_gauss_jordan_32, dim3(nj), dim3(1024), 0, st, dj);

@@ -129,6 +129,9 @@ __global__ void k_interp_wave(const CpqrJob* jobs, const int32_t* ranks, const i
 // (NW = 8); n <= 128, 4 x 4 register tiles, blockDim 1024
 template <int NW>
 __global__ void k_gauss_jordan_cols(const InvJob* jobs);
+// the same, two elimination steps per barrier
+template <int NW>
+__global__ void k_gauss_jordan_pairs(const InvJob* jobs);
 __global__ void k_gauss_jordan_32(const InvJob* jobs);
 __global__ void k_cpqr_init(const CpqrJob* jobs);
 __global__ void k_cpqr_step(const CpqrJob* jobs, int k, double tol);

@@ -1235,6 +1235,141 @@ __device__ void gauss_jordan_cols(const InvJob& jb) {
         if (rowok && c0 + c < n) gstore2(jb.a + pinv[lane] * ld + perm[c0 + c], a[c]);
 }
 
+// One Gauss-Jordan exchange of gauss_jordan_cols on this lane's columns:
+// pivot row p, f = this row's value in the pivot column, pv = the pivot; the
+// column at register index ownc (-1: none here) becomes -g.
+template <int NC>
+__device__ __forceinline__ void gj_exchange(double2 (&a)[NC], const int p, const double2 f, const double2 pv,
+                                            const int ownc, const int lane) {
+    const double rpd = recip(cabs2(pv));
+    const double2 inv = make_double2(pv.x * rpd, -pv.y * rpd);
+    const bool isp = lane == p;
+    const double2 g = isp ? make_double2(-inv.x, -inv.y) : cmul(f, inv);
+    const double s = isp ? 0.0 : 1.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double2 r = readlane2(a[c], p);   // row p of this column
+        a[c] = make_double2(fma(-g.x, r.x, fma(g.y, r.y, a[c].x * s)),
+                            fma(-g.x, r.y, fma(-g.y, r.x, a[c].y * s)));
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (c == ownc) a[c] = make_double2(-g.x, -g.y);
+}
+
+// The exchanges of gauss_jordan_cols two columns at a time: the wave that owns
+// columns j and j + 1 chooses both pivots by itself (column j + 1's pivot from
+// a copy of that column with step j applied) and publishes both columns and
+// both pivot rows; every wave then applies the two exchanges in turn, and one
+// barrier covers two elimination steps.  The copy is made by the same
+// arithmetic as the update that follows.  NC = 64 / NW columns per wave
+// (even, so that a pair never straddles two waves).
+template <int NW>
+__device__ void gauss_jordan_pairs(const InvJob& jb) {
+    constexpr int NC = 64 / NW;
+    static_assert(NC % 2 == 0, "pairs of columns per wave");
+    __shared__ double2 colv[2][2][64];   // column j before step j, column j + 1 after it
+    __shared__ int pj[2][2];             // their pivot rows (-1: singular; -2: no column j + 1)
+    __shared__ int perm[64], pinv[64];
+    __shared__ double wmax[NW];
+    const int n = jb.n;
+    const int64_t ld = jb.ld;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c0 = wave * NC;
+    const bool rowok = lane < n;
+    double2 a[NC];
+    double m2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        a[c] = (rowok && c0 + c < n) ? gload2(jb.a + lane * ld + c0 + c) : make_double2(0.0, 0.0);
+        m2 = fmax(m2, cabs2(a[c]));
+    }
+    {
+        const int q = wave_argmax_f32(static_cast<float>(m2));
+        const double wm = q < 0 ? 0.0 : readlane_d(m2, q);
+        if (lane == 0) wmax[wave] = wm;
+    }
+    __syncthreads();
+    m2 = wmax[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) m2 = fmax(m2, wmax[w]);
+    const double tiny2 = (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16) * m2;
+    const double rscale = m2 > 0.0 ? recip(m2) : 0.0;
+    uint64_t used = 0;   // pivot rows so far (the same value in every thread)
+    // the largest candidate of column v (rows below n not in `u`), or -1
+    auto pivot_of = [&](const double2 v, const uint64_t u) {
+        const bool cand = rowok && !((u >> lane) & 1);
+        const float mag = cand ? static_cast<float>(cabs2(v) * rscale) : -1.0f;
+        int p = wave_argmax_f32(mag);
+        if (p >= 0) {
+            const double pd = cabs2(readlane2(v, p));
+            if (!(pd > tiny2) || !(pd < INFINITY)) p = -1;
+        }
+        return p;
+    };
+    // the owner of columns j, j + 1 (values va, vb in registers) chooses both
+    // pivots and publishes them in buffer b
+    auto choose2 = [&](const double2 va, const double2 vb, const int j, const int b) {
+        const int pa = pivot_of(va, used);
+        int pb = -2;
+        double2 wb = vb;
+        if (pa >= 0 && j + 1 < n) {
+            double2 t[1] = {vb};
+            gj_exchange<1>(t, pa, va, readlane2(va, pa), -1, lane);
+            wb = t[0];
+            pb = pivot_of(wb, used | (1ull << pa));
+        }
+        colv[b][0][lane] = va;
+        colv[b][1][lane] = wb;
+        if (lane == 0) {
+            pj[b][0] = pa;
+            pj[b][1] = pb;
+            if (pa >= 0) {
+                perm[j] = pa;
+                pinv[pa] = j;
+            }
+            if (pb >= 0) {
+                perm[j + 1] = pb;
+                pinv[pb] = j + 1;
+            }
+        }
+    };
+    if (wave == 0) choose2(a[0], a[1], 0, 0);
+    __syncthreads();
+    int b = 0;
+    for (int j0 = 0; j0 < n; j0 += NC) {
+        const int owner = j0 / NC;
+#pragma unroll
+        for (int cc = 0; cc < NC; cc += 2) {
+            const int j = j0 + cc;
+            if (j >= n) break;
+            const int pa = __builtin_amdgcn_readfirstlane(pj[b][0]);
+            const int pb = __builtin_amdgcn_readfirstlane(pj[b][1]);
+            if (pa < 0 || pb == -1) {
+                if (threadIdx.x == 0) gst(jb.status, 1);
+                return;   // every wave read the same pivots after the barrier
+            }
+            gj_exchange<NC>(a, pa, colv[b][0][lane], colv[b][0][pa], wave == owner ? cc : -1, lane);
+            used |= 1ull << pa;
+            if (pb >= 0) {
+                gj_exchange<NC>(a, pb, colv[b][1][lane], colv[b][1][pb], wave == owner ? cc + 1 : -1, lane);
+                used |= 1ull << pb;
+            }
+            b ^= 1;
+            if (j + 2 < n) {
+                if (cc + 2 < NC) {
+                    if (wave == owner) choose2(a[cc + 2 < NC ? cc + 2 : 0], a[cc + 3 < NC ? cc + 3 : 1], j + 2, b);
+                } else if (wave == owner + 1) {
+                    choose2(a[0], a[1], j + 2, b);
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (rowok && c0 + c < n) gstore2(jb.a + pinv[lane] * ld + perm[c0 + c], a[c]);
+}
+
 }  // namespace
 
 template <int NW>
@@ -1242,6 +1377,11 @@ __global__ void __launch_bounds__(64 * NW) k_gauss_jordan_cols(const InvJob* __r
     gauss_jordan_cols<NW>(jobs[blockIdx.x]);
 }
 template __global__ void k_gauss_jordan_cols<8>(const InvJob*);
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_gauss_jordan_pairs(const InvJob* __restrict__ jobs) {
+    gauss_jordan_pairs<NW>(jobs[blockIdx.x]);
+}
+template __global__ void k_gauss_jordan_pairs<8>(const InvJob*);
 __global__ void __launch_bounds__(1024) k_gauss_jordan_32(const InvJob* __restrict__ jobs) {
     gauss_jordan_tiles<32>(jobs[blockIdx.x]);
 }
