@@ -113,30 +113,60 @@ __device__ __forceinline__ int wave_argmax_f32(float mag) {
     return static_cast<int>(__builtin_ctzll(hit));
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+// DPP move of a double (two 32-bit moves); rows outside ROW_MASK receive `old`
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_mov_d(double v, double old) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
-// Block-wide argmax of (value, index); ties go to the lowest index.
+// Sum over the wave, returned to every lane (wave-uniform): four DPP steps
+// within each 16-lane row, two row broadcasts to lane 63, one lane read.
+__device__ __forceinline__ double wave_sum(double x) {
+    x += dpp_mov_d<0xB1, 0xF>(x, x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_mov_d<0x4E, 0xF>(x, x);   // quad_perm [2, 3, 0, 1]
+    {
+        const double up = dpp_mov_d<0x104, 0xF>(x, x), dn = dpp_mov_d<0x114, 0xF>(x, x);   // row_shl/shr:4
+        x += (threadIdx.x & 4) ? dn : up;
+    }
+    x += dpp_mov_d<0x128, 0xF>(x, x);  // row_ror:8 -> every lane holds its row's sum
+    x += dpp_mov_d<0x142, 0xA>(x, 0.0);  // row_bcast:15 -> rows 1, 3 add rows 0, 2
+    x += dpp_mov_d<0x143, 0xC>(x, 0.0);  // row_bcast:31 -> rows 2, 3 add rows 0 + 1
+    return readlane_d(x, 63);
+}
+
+// Block-wide argmax of (value, index) for values >= 0 or a negative value
+// for "none"; ties go to the lowest index.  The wave maximum is exact (the
+// bit pattern of a non-negative double orders like the value), the lowest
+// index among the lanes that hold it a second DPP maximum.
 __device__ void block_argmax(double& v, int& idx, double* sv, int* si) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int oi = __shfl_xor(idx, off, 64);
-        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    {
+        const uint64_t key = v >= 0.0 ? static_cast<uint64_t>(__double_as_longlong(v)) + 1 : 0;
+        const uint64_t mk = wave_max_u64(key);
+        // lowest index among the maxima: the largest complement
+        const uint64_t ik = key == mk ? static_cast<uint64_t>(0x7FFFFFFF - idx) : 0;
+        const uint64_t mi = wave_max_u64(ik);
+        if (lane == 0) {
+            sv[wid] = mk > 0 ? __longlong_as_double(static_cast<long long>(mk - 1)) : -1.0;
+            si[wid] = 0x7FFFFFFF - static_cast<int>(mi);
+        }
     }
-    if (lane == 0) { sv[wid] = v; si[wid] = idx; }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w)
-            if (sv[w] > sv[0] || (sv[w] == sv[0] && si[w] < si[0])) { sv[0] = sv[w]; si[0] = si[w]; }
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    double bv = sv[0];
+    int bi = si[0];
+    for (int w = 1; w < nw; ++w) {
+        const double ov = sv[w];
+        const int oi = si[w];
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
     }
-    __syncthreads();
-    v = sv[0];
-    idx = si[0];
+    v = bv;
+    idx = bi;
     __syncthreads();
 }
 
