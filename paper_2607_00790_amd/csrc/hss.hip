@@ -404,6 +404,16 @@ bool gj_pairs() {
     return v;
 }
 
+// Whole-box CPQR for boxes of 129..160 unknowns (five columns per lane);
+// BMHSS_TUNE_CPQR_WIDE=0 leaves them to the step-wise kernels.
+bool fused_wide() {
+    static const bool v = [] {
+        const char* e = std::getenv("BMHSS_TUNE_CPQR_WIDE");
+        return !(e && std::atoi(e) == 0);
+    }();
+    return v;
+}
+
 // A product worth a library call: the batched tile kernel runs one 32 x 32
 // tile per workgroup without matrix cores, which is fine for the many small
 // per-box products but slow for the few large ones (the root inverse's Schur
@@ -938,13 +948,22 @@ hipError_t run_cpqr(Scratch& sc, std::vector<CpqrJob>& cj, CpqrJob** dcj_out, in
     for (const CpqrJob& j : cj) mmax = std::max(mmax, j.m);
     // every box small enough for one workgroup's registers: the whole CPQR in one launch
     const int RS = mmax <= 128 ? 8 : mmax <= 144 ? 9 : mmax <= 160 ? 10 : 0;   // rows per lane / 16
-    *fused_out = nmax <= kFusedCols && RS > 0;
+    const bool wide = nmax > kFusedCols && nmax <= kFusedWideCols && RS > 0 && fused_wide();
+    *fused_out = (nmax <= kFusedCols && RS > 0) || wide;
     if (*fused_out) {
         if ((e = hipEventRecord(ev0, sc.s)) != hipSuccess) return e;
-        switch (RS) {
-            case 8: hipLaunchKernelGGL(k_cpqr_fused<8>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
-            case 9: hipLaunchKernelGGL(k_cpqr_fused<9>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
-            default: hipLaunchKernelGGL(k_cpqr_fused<10>, dim3(nb), dim3(kFusedThreads), 0, sc.s, dcj, tol); break;
+        if (wide) {
+            hipLaunchKernelGGL((k_cpqr_fused<10, kFusedWideC, kFusedThreads>), dim3(nb), dim3(kFusedThreads), 0, sc.s,
+                               dcj, tol);
+        } else {
+            switch (RS) {
+                case 8: hipLaunchKernelGGL((k_cpqr_fused<8, 4, kFusedThreads>), dim3(nb), dim3(kFusedThreads), 0,
+                                           sc.s, dcj, tol); break;
+                case 9: hipLaunchKernelGGL((k_cpqr_fused<9, 4, kFusedThreads>), dim3(nb), dim3(kFusedThreads), 0,
+                                           sc.s, dcj, tol); break;
+                default: hipLaunchKernelGGL((k_cpqr_fused<10, 4, kFusedThreads>), dim3(nb), dim3(kFusedThreads), 0,
+                                            sc.s, dcj, tol); break;
+            }
         }
         if ((e = hipEventRecord(ev1, sc.s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_cpqr_finish, dim3(nb), dim3(kThreads), 0, sc.s, dcj);

@@ -142,11 +142,14 @@ __global__ void k_cpqr_step(const CpqrJob* jobs, int k, double tol);
 constexpr int kCpqrCols = 1;
 template <int R>
 __global__ void k_cpqr_step_reg(const CpqrJob* jobs, int k, double tol);
-// whole-box CPQR in registers: n <= kFusedCols columns (4 per lane, 16 lanes
-// per column group), m <= 16 R rows
+// whole-box CPQR in registers, rows g + 16 t (t < R) of C columns per lane,
+// NT threads: n <= kFusedCols columns (C = 4) or kFusedWideCols (C = 5, rows
+// up to 160 only: all 256 registers), m <= 16 R rows
 constexpr int kFusedThreads = 512;
-constexpr int kFusedCols = kFusedThreads / 4;
-template <int R>
+constexpr int kFusedCols = 4 * kFusedThreads / 16;
+constexpr int kFusedWideC = 5;
+constexpr int kFusedWideCols = kFusedWideC * kFusedThreads / 16;
+template <int R, int C, int NT>
 __global__ void k_cpqr_fused(const CpqrJob* jobs, double tol);
 __global__ void k_cpqr_finish(const CpqrJob* jobs);
 __global__ void k_cpqr_ranks(const CpqrJob* jobs, int nb, int32_t* ranks, int32_t* active);

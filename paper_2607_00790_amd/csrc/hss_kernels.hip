@@ -648,27 +648,30 @@ __device__ __forceinline__ double row16_sum(double v) {
     return v;
 }
 
-// The whole CPQR of one box in one workgroup, for boxes of at most
-// kFusedCols columns and 16 R rows: the matrix stays in registers for all
+// The whole CPQR of one box in one workgroup of NT threads, for boxes of at
+// most C NT / 16 columns and 16 R rows: the matrix stays in registers for all
 // steps.  Lane (c, g) of a wave, c = lane / 16, g = lane % 16, holds rows
-// g, g + 16, ..., g + 16 (R - 1) of the four columns 4 (4 w + c) .. + 3 (w the
-// wave), so a column lives in one 16-lane DPP row and its dot products and
+// g, g + 16, ..., g + 16 (R - 1) of the C columns C (4 w + c) .. + C - 1 (w
+// the wave), so a column lives in one 16-lane DPP row and its dot products and
 // norms need four DPP steps, and each lane reads the Householder vector (R
-// values from LDS, once for the dot products and once for the update) for four
-// columns.  Per step: the pivot (largest
+// values from LDS, once for the dot products and once for the update) for C
+// columns at a time (for C = 5, in two chunks of at most three columns: the
+// 160 x 160 box takes 200 of the 256 registers).  Per step: the pivot (largest
 // remaining column norm, lowest index on ties: an exact maximum of the norm's
 // bit pattern, per wave by DPP, then over the waves through LDS), then the
 // lanes of the pivot column stage the Householder vector in LDS (zeros above
 // row k; the lane of row k writes w0 = x_k - alpha and the scalars alpha and
-// beta), then every lane applies it to its columns.  Blocks of 16 rows
-// entirely above row k are skipped.  Rank rule |R_kk| > tol |R_00|, logical
-// pivoting and the layout of the result (R in the columns perm[0..rank),
-// diagonal in rdiag) are those of the step-wise kernels, so k_cpqr_finish and
-// k_interp follow unchanged.  Grid: one workgroup of kFusedThreads per box.
-template <int R>
-__global__ void __launch_bounds__(kFusedThreads)
+// beta), then every lane applies it to its columns and recomputes their
+// norms below row k.  Blocks of 16 rows entirely above row k are skipped.
+// Rank rule |R_kk| > tol |R_00|, logical pivoting and the layout of the
+// result (R in the columns perm[0..rank), diagonal in rdiag) are those of the
+// step-wise kernels, so k_cpqr_finish and k_interp follow unchanged.  Grid:
+// one workgroup per box.
+template <int R, int C, int NT>
+__global__ void __launch_bounds__(NT)
 k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
-    constexpr int NW = kFusedThreads / 64;
+    constexpr int NW = NT / 64;
+    constexpr int CB = C <= 4 ? C : (C + 1) / 2;
     __shared__ double2 ws[16 * R];
     __shared__ uint64_t wkey[NW];
     __shared__ int wcol[NW];
@@ -677,26 +680,26 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
     const CpqrJob jb = jobs[blockIdx.x];
     const int n = jb.n, m = jb.m;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane & 15, c0 = 4 * (4 * wave + (lane >> 4));   // first of this lane's four columns
-    double2 X[R][4];
+    const int g = lane & 15, c0 = C * (4 * wave + (lane >> 4));   // first of this lane's C columns
+    double2 X[R][C];
 #pragma unroll
     for (int t = 0; t < R; ++t)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < C; ++c) {
             const int r = g + 16 * t;
             X[t][c] = (c0 + c < n && r < m) ? gload2(jb.x + static_cast<int64_t>(c0 + c) * m + r)
                                             : make_double2(0.0, 0.0);
         }
-    double nrm[4];
-    bool used[4];
+    double nrm[C];
+    uint32_t used = 0;   // bit c: column c0 + c pivoted (or past n)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < C; ++c) {
         double q = 0.0;
 #pragma unroll
         for (int t = 0; t < R; ++t) q = fma(X[t][c].x, X[t][c].x, fma(X[t][c].y, X[t][c].y, q));
         nrm[c] = row16_sum(q);
-        used[c] = c0 + c >= n;
-        if (!used[c] && g == 0) gst(jb.used + c0 + c, 0);
+        if (c0 + c >= n) used |= 1u << c;
+        else if (g == 0) gst(jb.used + c0 + c, 0);
     }
     const int kmax = n < m ? n : m;
     double ref = 0;
@@ -707,8 +710,8 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
         uint64_t key = 0;
         int bj = 0;
 #pragma unroll
-        for (int c = 3; c >= 0; --c) {
-            const uint64_t kc = used[c] ? 0 : static_cast<uint64_t>(__double_as_longlong(nrm[c])) + 1;
+        for (int c = C - 1; c >= 0; --c) {
+            const uint64_t kc = (used >> c) & 1 ? 0 : static_cast<uint64_t>(__double_as_longlong(nrm[c])) + 1;
             if (kc >= key && kc > 0) {
                 key = kc;
                 bj = c0 + c;
@@ -734,12 +737,12 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
         if (k == 0) ref = sqrt(bv);
         if (!(sqrt(bv) > tol * ref) || ref == 0 || p >= n) break;   // uniform
         const int kb = k >> 4;   // blocks of 16 rows below kb lie above row k
-        if (c0 == (p & ~3)) {
-            const int pc = p & 3;
+        if (c0 == p / C * C) {
+            const int pc = p % C;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < C; ++c) {
                 if (c != pc) continue;   // uniform
-                used[c] = true;
+                used |= 1u << c;
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
                     if (t < kb) continue;   // uniform
@@ -765,51 +768,65 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
             gst(jb.perm + k, p);
             gstore2(jb.rdiag + k, salpha);
         }
-        double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+        // the columns in chunks of CB (all at once for C <= 4; more chunks
+        // read w more often but hold fewer projections)
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-            if (t < kb) continue;   // uniform
-            const double2 w = ws[g + 16 * t];
+        for (int cb = 0; cb < C; cb += CB) {
+            double ar[CB], ai[CB];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                ar[c] = fma(w.x, X[t][c].x, fma(w.y, X[t][c].y, ar[c]));
-                ai[c] = fma(w.x, X[t][c].y, fma(-w.y, X[t][c].x, ai[c]));
+            for (int c = 0; c < CB; ++c) ar[c] = ai[c] = 0.0;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                if (t < kb) continue;   // uniform
+                const double2 w = ws[g + 16 * t];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    if (cb + c >= C) continue;
+                    ar[c] = fma(w.x, X[t][cb + c].x, fma(w.y, X[t][cb + c].y, ar[c]));
+                    ai[c] = fma(w.x, X[t][cb + c].y, fma(-w.y, X[t][cb + c].x, ai[c]));
+                }
             }
+            // the projections, in place: pivoted columns (and columns past n) stay as they are
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const bool u = cb + c >= C || ((used >> (cb + c)) & 1);
+                ar[c] = u ? 0.0 : row16_sum(ar[c]) * beta;
+                ai[c] = u ? 0.0 : row16_sum(ai[c]) * beta;
+            }
+            // w is read again below instead of being kept in R more registers
+            // across the reductions (a compiler barrier only: no instruction)
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                if (t < kb) continue;   // uniform
+                const double2 w = ws[g + 16 * t];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    if (cb + c >= C) continue;
+                    X[t][cb + c].x = fma(-ar[c], w.x, fma(ai[c], w.y, X[t][cb + c].x));
+                    X[t][cb + c].y = fma(-ar[c], w.y, fma(-ai[c], w.x, X[t][cb + c].y));
+                }
+            }
+            asm volatile("" ::: "memory");
         }
-        double gr[4], gi[4];
+        // the norms of the rows below k, after the update (not during it, so
+        // that the norms and the projections are never live together)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            // pivoted columns (and columns past n) stay as they are
-            gr[c] = used[c] ? 0.0 : row16_sum(ar[c]) * beta;
-            gi[c] = used[c] ? 0.0 : row16_sum(ai[c]) * beta;
-        }
-        // w is read again below instead of being kept in R more registers
-        // across the reductions (a compiler barrier only: no instruction)
-        asm volatile("" ::: "memory");
-        double q[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < C; ++c) {
+            double q = 0.0;
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-            if (t < kb) continue;   // uniform
-            const double2 w = ws[g + 16 * t];
-            const bool below = g + 16 * t > k;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                X[t][c].x = fma(-gr[c], w.x, fma(gi[c], w.y, X[t][c].x));
-                X[t][c].y = fma(-gr[c], w.y, fma(-gi[c], w.x, X[t][c].y));
+            for (int t = 0; t < R; ++t) {
+                if (t < kb) continue;   // uniform
                 const double e = fma(X[t][c].x, X[t][c].x, X[t][c].y * X[t][c].y);
-                q[c] += below ? e : 0.0;
+                q += g + 16 * t > k ? e : 0.0;
             }
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double sn = row16_sum(q[c]);
-            if (!used[c]) nrm[c] = sn;
+            nrm[c] = row16_sum(q);
         }
     }
 #pragma unroll
     for (int t = 0; t < R; ++t)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < C; ++c) {
             const int r = g + 16 * t;
             if (c0 + c < n && r < m) gstore2(jb.x + static_cast<int64_t>(c0 + c) * m + r, X[t][c]);
         }
@@ -820,9 +837,10 @@ k_cpqr_fused(const CpqrJob* __restrict__ jobs, double tol) {
     }
 }
 
-template __global__ void k_cpqr_fused<8>(const CpqrJob*, double);
-template __global__ void k_cpqr_fused<9>(const CpqrJob*, double);
-template __global__ void k_cpqr_fused<10>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<8, 4, kFusedThreads>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<9, 4, kFusedThreads>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<10, 4, kFusedThreads>(const CpqrJob*, double);
+template __global__ void k_cpqr_fused<10, kFusedWideC, kFusedThreads>(const CpqrJob*, double);
 
 template __global__ void k_cpqr_step_reg<4>(const CpqrJob*, int, double);
 template __global__ void k_cpqr_step_reg<8>(const CpqrJob*, int, double);
