@@ -324,6 +324,30 @@ int bm_dense_inverse(double* a, int64_t n, int64_t ld, hipStream_t stream);
 int bm_sketch(const double* omega, int64_t ldo, const double* x, int64_t m, int64_t n, int64_t l, double* y,
               hipStream_t stream);
 
+/* The interpolative decomposition that picks each box's skeleton (the ID of
+ * the proxy-surface compression, paper Sec. III; skeleton indices as in
+ * Martinsson and Rokhlin), for a batch of nb complex matrices at once: the
+ * kernels of bm_hss_build's ID step, on caller-given matrices.  Matrix b is
+ * m[b] x n[b] (host arrays), stored by columns (column j at x + 2 (o_b + j m[b]),
+ * interleaved complex128, device, o_b = sum over a < b of m[a] n[a]); it is
+ * factored by Householder QR with column pivoting (at step k the remaining
+ * column of largest 2-norm over rows k.., lowest index on ties) until
+ * |R_kk| <= tol |R_00| or min(m, n) steps; the number of steps taken is the
+ * rank k_b, written to ranks[b] (host).  x is overwritten by the factorisation.
+ * perm + p_b (device, n[b] entries, p_b = sum over a < b of n[a]) receives the
+ * pivot order: the skeleton columns perm[0..k_b), then the other columns in
+ * increasing order.  T + 2 t_b (device, room for n[b]^2 complex values,
+ * t_b = sum over a < b of n[a]^2) receives the n[b] x k_b interpolation
+ * matrix, row-major with row stride k_b: row perm[i] is e_i for i < k_b and
+ * row perm[k_b + c] is column c of R11^-1 R12, so that column j of the matrix
+ * is approximated by sum_i X[:, perm[i]] T[j][i]; the rest of each slot is
+ * zeroed.  One workgroup factors a whole matrix when n <= 160 and m <= 160,
+ * otherwise one launch per elimination step.  Returns after every output has
+ * been written.  EINVAL: a null pointer, nb outside 1..65535, a size outside
+ * 1..4096, tol outside [0, 1). */
+int bm_interp_decomp(int32_t nb, const int32_t* m, const int32_t* n, double* x, double tol, int32_t* ranks,
+                     int32_t* perm, double* T, hipStream_t stream);
+
 /* Per compressed level (0 = leaves, up to compressed_levels - 1): sizes of the
  * ID problems and the ranks found.  EINVAL for a level out of range. */
 typedef struct {

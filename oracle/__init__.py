@@ -17,11 +17,15 @@ Contents (each function cites the passage of the paper it follows):
   shape     -- the backscatter intensity of a Fourier-parametrised boundary and
                its derivative with respect to the coefficients, by Richardson
                central differences of J or of the pieces of the adjoint identity
+  idecomp   -- the interpolative decomposition that picks a box's skeleton
+               (Sec. III): Householder QR with column pivoting, relative rank
+               rule, interpolation matrix from one triangular solve
 
 Readings where the paper is silent (fundamental solution, normal-derivative
 definitions, the meaning of q, the one-point correction constants, the
 multi-scatterer coupling) are listed in the module docstrings; every one of
 them is pinned by a closed form in tests/test_oracle_pins.py; the shape
 derivative's readings are in oracle/shape.py, pinned in
-tests/test_oracle_shape_pins.py.
+tests/test_oracle_shape_pins.py; the ID's in oracle/idecomp.py, pinned in
+tests/test_oracle_id_pins.py.
 """

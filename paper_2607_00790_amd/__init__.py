@@ -22,6 +22,7 @@ from ._binding import (  # noqa: F401
     bm_matvec_noalloc,
     bm_dense_inverse,
     bm_sketch,
+    bm_interp_decomp,
     bm_problem_create,
     bm_problem_create_bodies,
     bm_rhs_plane_wave,

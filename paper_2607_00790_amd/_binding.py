@@ -100,6 +100,7 @@ def load():
         "bm_hss_destroy": (ctypes.c_int, [c_vp]),
         "bm_dense_inverse": (ctypes.c_int, [c_vp, c_i64, c_i64, c_vp]),
         "bm_sketch": (ctypes.c_int, [c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_vp, c_vp]),
+        "bm_interp_decomp": (ctypes.c_int, [ctypes.c_int32, c_vp, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp]),
     })
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -344,6 +345,40 @@ def bm_sketch(omega, x, out=None, stream=None):
     _check(load().bm_sketch(_dev_ptr(omega, torch.float64, "omega"), m, _dev_ptr(x, torch.complex128, "x"), m, n, l,
                             _dev_ptr(out, torch.complex128, "out"), _stream(stream)))
     return out
+
+
+def bm_interp_decomp(mats, tol, stream=None):
+    """Interpolative decomposition of a batch of complex matrices. mats: a list
+    of (m_b, n_b) complex128 device tensors (not modified). Returns
+    (ranks, perms, Ts): per matrix its rank k, the pivot order (n,) int32
+    device tensor, and the (n, k) interpolation matrix T with
+    mats[b] ~= mats[b][:, perm[:k]] @ T.T."""
+    import numpy as np
+    torch = _torch()
+    if not mats:
+        raise ValueError("mats must not be empty")
+    ms = np.array([a.shape[0] for a in mats], dtype=np.int32)
+    ns = np.array([a.shape[1] for a in mats], dtype=np.int32)
+    for a in mats:
+        if a.dim() != 2 or a.dtype != torch.complex128 or not a.is_cuda:
+            raise ValueError("every matrix must be a 2-D complex128 device tensor")
+    # stored by columns: the transposes, packed
+    x = torch.cat([a.t().contiguous().reshape(-1) for a in mats])
+    perm = torch.empty(int(ns.sum()), dtype=torch.int32, device="cuda")
+    T = torch.empty(int((ns.astype(np.int64) ** 2).sum()), dtype=torch.complex128, device="cuda")
+    ranks = np.zeros(len(mats), dtype=np.int32)
+    _check(load().bm_interp_decomp(len(mats), ms.ctypes.data, ns.ctypes.data, _dev_ptr(x, torch.complex128, "x"),
+                                   float(tol), ranks.ctypes.data, _dev_ptr(perm, torch.int32, "perm"),
+                                   _dev_ptr(T, torch.complex128, "T"), _stream(stream)))
+    perms, Ts = [], []
+    po = to = 0
+    for b in range(len(mats)):
+        nb, kb = int(ns[b]), int(ranks[b])
+        perms.append(perm[po:po + nb])
+        Ts.append(T[to:to + nb * kb].reshape(nb, kb))
+        po += nb
+        to += nb * nb
+    return [int(r) for r in ranks], perms, Ts
 
 
 def bm_far_field(p: Problem, phi, angles, out=None, stream=None):

@@ -366,6 +366,9 @@ hipError_t blas_handle(rocblas_handle* out) {
 constexpr int64_t kRootPanelsMax = 4096;
 // largest matrix bm_dense_inverse accepts
 constexpr int64_t kDenseInverseMax = 16384;
+// bm_interp_decomp: matrices per call (a grid dimension) and rows / columns
+constexpr int32_t kInterpDecompMaxBatch = 65535;
+constexpr int32_t kInterpDecompMaxDim = 4096;
 bool root_panels() {
     static const bool v = [] {
         const char* e = std::getenv("BMHSS_ROOT_PANELS");
@@ -2358,6 +2361,80 @@ int bm_sketch(const double* omega, int64_t ldo, const double* x, int64_t m, int6
         if (e == hipSuccess) sc.synced();
     }
     if (e != hipSuccess) return hip_fail(e, "bm_sketch");
+    return BM_OK;
+}
+
+int bm_interp_decomp(int32_t nb, const int32_t* m, const int32_t* n, double* x, double tol, int32_t* ranks,
+                     int32_t* perm, double* T, hipStream_t stream) {
+    clear_error();
+    if (!m || !n || !x || !ranks || !perm || !T) return fail(BM_EINVAL, "bm_interp_decomp: null argument");
+    if (nb < 1 || nb > kInterpDecompMaxBatch || !(tol >= 0.0 && tol < 1.0))
+        return fail(BM_EINVAL, "bm_interp_decomp: need 1 <= nb <= 65535 and 0 <= tol < 1");
+    for (int32_t b = 0; b < nb; ++b)
+        if (m[b] < 1 || n[b] < 1 || m[b] > kInterpDecompMaxDim || n[b] > kInterpDecompMaxDim)
+            return fail(BM_EINVAL, "bm_interp_decomp: need 1 <= m, n <= 4096 for every matrix");
+    std::vector<CpqrJob> cj(nb);
+    std::vector<int64_t> toff(nb);
+    int64_t xo = 0, po = 0, to = 0, nmax = 1;
+    hipError_t e = hipSuccess;
+    std::vector<int32_t> rk(nb);
+    {
+        Scratch sc(stream);
+        double2* rdiag = nullptr;
+        int32_t* dranks = nullptr;
+        for (int32_t b = 0; b < nb; ++b) po += n[b];
+        e = sc.alloc(&rdiag, po);
+        if (e == hipSuccess) e = sc.alloc(&dranks, nb);
+        po = 0;
+        for (int32_t b = 0; b < nb; ++b) {
+            cj[b] = CpqrJob{reinterpret_cast<double2*>(x) + xo, perm + po, rdiag + po, nullptr, nullptr, nullptr,
+                            n[b], m[b]};
+            toff[b] = to;
+            xo += static_cast<int64_t>(m[b]) * n[b];
+            po += n[b];
+            to += static_cast<int64_t>(n[b]) * n[b];
+            nmax = std::max<int64_t>(nmax, n[b]);
+        }
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (e == hipSuccess) e = hipEventCreate(&ev0);
+        if (e == hipSuccess) e = hipEventCreate(&ev1);
+        if (ev0) sc.events.push_back(ev0);
+        if (ev1) sc.events.push_back(ev1);
+        CpqrJob* dcj = nullptr;
+        int64_t launches = 0;
+        bool fused = false;
+        if (e == hipSuccess)
+            e = run_cpqr(sc, cj, &dcj, dranks, tol, rk, ev0, ev1, &launches, static_cast<int>(nmax / 2), &fused,
+                         []() { return hipSuccess; });
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) sc.synced();
+        // T = [I; (R11^-1 R12)^T] in pivoted order, each in its n x n slot
+        int64_t* dtoff = nullptr;
+        if (e == hipSuccess) e = sc.upload(&dtoff, toff);
+        if (e == hipSuccess) e = sc.flush();
+        if (e == hipSuccess) e = hipMemsetAsync(T, 0, static_cast<size_t>(to) * sizeof(double2), stream);
+        int64_t cmax = 1, kmax = 0;
+        for (int32_t b = 0; b < nb; ++b) {
+            cmax = std::max<int64_t>(cmax, n[b] - rk[b]);
+            kmax = std::max<int64_t>(kmax, rk[b]);
+        }
+        if (e == hipSuccess) {
+            const int rpl = kmax <= 64 ? 1 : kmax <= 128 ? 2 : kmax <= 256 ? 4 : 0;
+            const dim3 g(static_cast<unsigned>(ceil_div(cmax, kThreads / 64)), static_cast<unsigned>(nb)), bl(kThreads);
+            double2* Td = reinterpret_cast<double2*>(T);
+            switch (rpl) {
+                case 1: hipLaunchKernelGGL(k_interp_wave<1>, g, bl, 0, stream, dcj, dranks, dtoff, Td); break;
+                case 2: hipLaunchKernelGGL(k_interp_wave<2>, g, bl, 0, stream, dcj, dranks, dtoff, Td); break;
+                case 4: hipLaunchKernelGGL(k_interp_wave<4>, g, bl, 0, stream, dcj, dranks, dtoff, Td); break;
+                default: hipLaunchKernelGGL(k_interp, g, bl, 0, stream, dcj, dranks, dtoff, Td); break;
+            }
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) sc.synced();
+    }
+    if (e != hipSuccess) return hip_fail(e, "bm_interp_decomp");
+    std::copy(rk.begin(), rk.end(), ranks);
     return BM_OK;
 }
 

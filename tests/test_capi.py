@@ -155,3 +155,34 @@ def test_autotuner_writes_the_fastest_candidate(tmp_path, monkeypatch):
     assert re.search(r"constexpr int kInvBase = (32|64|128);", committed)
     assert re.search(r"constexpr long kSketchRows = \d+;", committed)
     assert re.search(r"constexpr double kStopRankRatio = (0|0?\.\d+|1)(\.\d*)?;", committed)
+
+
+def test_interp_decomp_rejects_bad_arguments_on_the_host(lib):
+    """bm_interp_decomp checks its sizes and pointers before any device work:
+    an empty batch, a zero size, a size above 4096, tol outside [0, 1) and a
+    null pointer are BM_EINVAL (the pointers passed are never dereferenced)."""
+    vp = ctypes.c_void_p
+    f = lib.bm_interp_decomp
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp]
+    lib.bm_last_error.restype = ctypes.c_char_p
+    m = np.array([4, 3], dtype=np.int32)
+    n = np.array([2, 5], dtype=np.int32)
+    ranks = np.zeros(2, dtype=np.int32)
+    fake = vp(0x1000)   # a device address stand-in: rejected before use
+
+    def call(nb=2, mm=m, nn=n, x=fake, tol=1e-10, r=ranks, p=fake, t=fake):
+        return f(nb, mm.ctypes.data if mm is not None else None, nn.ctypes.data if nn is not None else None,
+                 x, tol, r.ctypes.data if r is not None else None, p, t, None)
+
+    assert call(nb=0) == BM_EINVAL
+    assert call(nb=70000) == BM_EINVAL
+    assert call(mm=np.array([4, 0], dtype=np.int32)) == BM_EINVAL
+    assert call(nn=np.array([2, 4097], dtype=np.int32)) == BM_EINVAL
+    assert call(tol=1.0) == BM_EINVAL
+    assert call(tol=-1e-3) == BM_EINVAL
+    assert call(tol=float("nan")) == BM_EINVAL
+    assert call(x=None) == BM_EINVAL
+    assert call(r=None) == BM_EINVAL
+    assert call(mm=None) == BM_EINVAL
+    assert b"bm_interp_decomp" in lib.bm_last_error()
