@@ -465,11 +465,16 @@ def run_hss(args):
     levels = []
 
     def step():
+        # the build records the one-right-hand-side solve graph while the GPU
+        # inverts the root; the step's solve replays it
         h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio,
                             proxy_points=wl.proxy_points, id_tol=wl.id_tol, sketch=args.sketch,
                             max_rank_ratio=args.max_rank_ratio)
         bm.bm_rhs_plane_wave(p, wl.theta_inc, out=b)
-        bm.bm_hss_solve(h, b, out=x)
+        if args.solve == "graph":
+            bm.bm_hss_solve_graph(h, b, out=x)
+        else:
+            bm.bm_hss_solve(h, b, out=x)
         st = bm.bm_hss_stats(h)
         if not levels:
             levels.extend(bm.bm_hss_level(h, l) for l in range(st["compressed_levels"]))
@@ -572,7 +577,7 @@ def run_hss(args):
                    "proxy_points": wl.proxy_points, "proxy_ratio": wl.proxy_ratio,
                    "id_tol": wl.id_tol, "theta_inc": wl.theta_inc,
                    "id": "cpqr" if sk == 0 else f"gaussian sketch, unknowns+{sk} rows",
-                   "max_rank_ratio": ratio},
+                   "max_rank_ratio": ratio, "solve": args.solve},
         "hss_build_solve_s": ms * 1e-3,
         "hss": {"entries": entries, "pairs": st["pairs"], "levels": st["levels"],
                 "compressed_levels": st["compressed_levels"], "root_size": st["root_size"],
@@ -705,8 +710,8 @@ def run_adjoint(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["hss", "dense", "matvec", "batch", "adjoint", "large"], default="hss")
     ap.add_argument("--id-tol", type=float, default=1e-12, help="adjoint mode: HSS ID tolerance")
     ap.add_argument("--per-curve", type=int, default=16384, help="large mode: nodes per star")
@@ -721,6 +726,8 @@ def main():
                     help="HSS: p > 0 runs the ID on a Gaussian sketch with unknowns + p rows (0: plain "
                          "CPQR; -1: the library's tuned value; default: -1 in hss, adjoint and batch modes, "
                          "128 in large mode, 0 otherwise)")
+    ap.add_argument("--solve", choices=["graph", "eager"], default="graph",
+                    help="hss mode: the step's solve replays the graph the build records, or runs eagerly")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,

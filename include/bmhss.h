@@ -290,7 +290,9 @@ int bm_hss_solve_transpose(const bm_hss* h, const double* b, double* x, int64_t 
  * bm_hss_destroy.  Every product of the graph runs in the library's own
  * batched GEMM kernel (library GEMM calls are not captured), so for a very
  * large root the eager solve, which hands large products to rocBLAS, can be
- * faster. */
+ * faster.  bm_hss_build records the (nrhs = 1, transpose = 0) graph itself,
+ * on the host while the GPU inverts the dense root, so that the first such
+ * call only replays it. */
 int bm_hss_solve_graph(const bm_hss* h, const double* b, double* x, int64_t nrhs, int transpose,
                        hipStream_t stream);
 int bm_hss_stats(const bm_hss* h, bm_hss_stats_t* out);

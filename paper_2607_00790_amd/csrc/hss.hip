@@ -1230,6 +1230,53 @@ struct BodyState {
     std::vector<std::vector<int32_t>> box_p;  // per level: proxy points per box
 };
 
+hipError_t record_solve(const bm_hss* h, Scratch& sc, const double* b, double* x, int64_t nrhs, bool trans);
+
+// The captured solve of bm_hss_solve_graph for (nrhs, trans): record the
+// solve on a capture stream, upload its job descriptors once, and capture its
+// launches into a graph, appended to h->plans (the caller holds plan_mu, or
+// is the build).  Needs the factors' addresses only, not their values.  On
+// failure *where names the step.
+hipError_t make_solve_plan(const bm_hss* h, int64_t nrhs, bool trans, bm_hss::SolvePlan** out, const char** where) {
+    *out = nullptr;
+    auto q = std::make_unique<bm_hss::SolvePlan>();
+    q->nrhs = nrhs;
+    q->trans = trans;
+    *where = "bm_hss_solve_graph: stream";
+    hipError_t e = hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    q->sc = std::make_unique<Scratch>(q->cap);
+    Scratch& sc = *q->sc;
+    sc.allow_blas = false;   // library calls are not captured; the tile kernel runs every product
+    double2 *bi = nullptr, *xo = nullptr;
+    e = sc.alloc(&bi, static_cast<size_t>(2 * h->N * nrhs));
+    if (e == hipSuccess) e = sc.alloc(&xo, static_cast<size_t>(2 * h->N * nrhs));
+    q->bin = reinterpret_cast<double*>(bi);
+    q->xout = reinterpret_cast<double*>(xo);
+    *where = "bm_hss_solve_graph: record";
+    if (e == hipSuccess) e = record_solve(h, sc, q->bin, q->xout, nrhs, q->trans);
+    if (e != hipSuccess) return e;
+    if (sc.uses_blas) return hipErrorNotSupported;   // cannot happen: allow_blas is off
+    *where = "bm_hss_solve_graph: upload";
+    e = sc.flush_uploads();
+    if (e == hipSuccess) e = hipStreamSynchronize(q->cap);
+    sc.synced();
+    if (e != hipSuccess) return e;
+    *where = "bm_hss_solve_graph: capture";
+    e = hipStreamBeginCapture(q->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t er = sc.run_recorded();
+    e = hipStreamEndCapture(q->cap, &q->graph);
+    if (er != hipSuccess) return er;
+    if (e != hipSuccess) return e;
+    *where = "bm_hss_solve_graph: instantiate";
+    if ((e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&q->done, hipEventDisableTiming)) != hipSuccess) return e;
+    h->plans.push_back(std::move(q));
+    *out = h->plans.back().get();
+    return hipSuccess;
+}
+
 int build_impl(bm_hss* h, hipStream_t s) {
     const bm_problem* p = h->p;
     const bm_geom* g = p->g;
@@ -1340,11 +1387,20 @@ int build_impl(bm_hss* h, hipStream_t s) {
     std::vector<double2*> dhat;             // per iteration: Dhat of every kept box (k x k, packed)
     std::vector<std::vector<int64_t>> dhat_off;
     std::vector<int32_t*> status_bufs;
+    std::vector<int64_t> status_cnt;    // entries of each status buffer
+    int64_t status_tot = 0;
+    int32_t* status_host = nullptr;     // pinned copy of every status
+    size_t status_cap = 0;
     auto cleanup = [&]() {
         for (auto q : status_bufs) dev_free(q, s2);
         status_bufs.clear();
         for (auto q : dhat) dev_free(q, s2);
         dhat.clear();
+        if (status_host) {
+            (void)hipStreamSynchronize(s2);   // no copy into it may be pending
+            pinned_cache().put(reinterpret_cast<char*>(status_host), status_cap);
+            status_host = nullptr;
+        }
     };
     int64_t entries = 0, pairs = 0, max_rank = 0, cpqr_launches = 0, cpqr_fused_launches = 0;
     double cpqr_bytes = 0, cpqr_fused_bytes = 0;
@@ -2007,6 +2063,32 @@ int build_impl(bm_hss* h, hipStream_t s) {
             if (e == hipSuccess) e = t_fac.stop(sc, ev);
         }
         if (e == hipSuccess) e = sc.flush();
+        // every inversion's status, copied behind the root on the second stream
+        // into pinned memory, so that one wait covers them all
+        for (size_t q = 0; q < status_bufs.size(); ++q) {
+            const int64_t cnt = (q + 1 == status_bufs.size()) ? static_cast<int64_t>(roots.size()) : 2 * h->lv[q].nb;
+            status_cnt.push_back(cnt);
+            status_tot += cnt;
+        }
+        if (e == hipSuccess) {
+            status_host = reinterpret_cast<int32_t*>(
+                pinned_cache().get(static_cast<size_t>(std::max<int64_t>(status_tot, 1)) * sizeof(int32_t), &status_cap));
+            if (!status_host) e = hipErrorOutOfMemory;
+        }
+        for (size_t q = 0, o = 0; q < status_bufs.size() && e == hipSuccess; o += status_cnt[q], ++q)
+            e = hipMemcpyAsync(status_host + o, status_bufs[q], status_cnt[q] * sizeof(int32_t), hipMemcpyDeviceToHost, s2);
+        // while the GPU inverts the root: capture the one-right-hand-side solve
+        // for bm_hss_solve_graph (host work; a failure only leaves it to the
+        // first call)
+        if (e == hipSuccess) {
+            std::lock_guard<std::mutex> lk(h->plan_mu);
+            bm_hss::SolvePlan* plan = nullptr;
+            const char* where = nullptr;
+            if (make_solve_plan(h, 1, false, &plan, &where) != hipSuccess) {
+                (void)hipGetLastError();
+                h->plans.clear();
+            }
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(s2);
         sc.synced();
         sc.release();
@@ -2018,16 +2100,9 @@ int build_impl(bm_hss* h, hipStream_t s) {
     for (const LevelFactor& f : h->lv)
         for (int8_t r : f.xt_root)
             if (r < 0) { cleanup(); return fail(BM_ESTATE, "bm_hss_build: internal error (unlinked box)"); }
-    // ---- statuses of every inversion
-    for (size_t q = 0; q < status_bufs.size(); ++q) {
-        const int64_t cnt = (q + 1 == status_bufs.size()) ? static_cast<int64_t>(roots.size()) : 2 * h->lv[q].nb;
-        std::vector<int32_t> hs(cnt);
-        hipError_t e = hipMemcpyAsync(hs.data(), status_bufs[q], cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { cleanup(); return hip_fail(e, "bm_hss_build: status"); }
-        for (int32_t v : hs)
-            if (v) { cleanup(); return fail(BM_ESINGULAR, "bm_hss_build: singular block in the HSS factorisation"); }
-    }
+    // ---- statuses of every inversion (copied before the last wait)
+    for (int64_t i = 0; i < status_tot; ++i)
+        if (status_host[i]) { cleanup(); return fail(BM_ESINGULAR, "bm_hss_build: singular block in the HSS factorisation"); }
     cleanup();
     h->stats.levels = Lmax;
     h->stats.compressed_levels = compressed;
@@ -2464,37 +2539,9 @@ int bm_hss_solve_graph(const bm_hss* h, const double* b, double* x, int64_t nrhs
         if (q->nrhs == nrhs && q->trans == (transpose != 0)) plan = q.get();
     const size_t bytes = static_cast<size_t>(2 * h->N * nrhs) * sizeof(double2);
     if (!plan) {
-        // first call for this shape: record the solve on a capture stream, upload
-        // its job descriptors once, and capture its launches into a graph
-        auto q = std::make_unique<bm_hss::SolvePlan>();
-        q->nrhs = nrhs;
-        q->trans = transpose != 0;
-        BM_HIP(hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking));
-        q->sc = std::make_unique<Scratch>(q->cap);
-        Scratch& sc = *q->sc;
-        sc.allow_blas = false;   // library calls are not captured; the tile kernel runs every product
-        double2 *bi = nullptr, *xo = nullptr;
-        hipError_t e = sc.alloc(&bi, static_cast<size_t>(2 * h->N * nrhs));
-        if (e == hipSuccess) e = sc.alloc(&xo, static_cast<size_t>(2 * h->N * nrhs));
-        q->bin = reinterpret_cast<double*>(bi);
-        q->xout = reinterpret_cast<double*>(xo);
-        if (e == hipSuccess) e = record_solve(h, sc, q->bin, q->xout, nrhs, q->trans);
-        if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: record");
-        if (sc.uses_blas) return fail(BM_ESTATE, "bm_hss_solve_graph: internal error (library product recorded)");
-        e = sc.flush_uploads();
-        if (e == hipSuccess) e = hipStreamSynchronize(q->cap);
-        sc.synced();
-        if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: upload");
-        e = hipStreamBeginCapture(q->cap, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: begin capture");
-        const hipError_t er = sc.run_recorded();
-        e = hipStreamEndCapture(q->cap, &q->graph);
-        if (er != hipSuccess) return hip_fail(er, "bm_hss_solve_graph: capture");
-        if (e != hipSuccess) return hip_fail(e, "bm_hss_solve_graph: end capture");
-        BM_HIP(hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0));
-        BM_HIP(hipEventCreateWithFlags(&q->done, hipEventDisableTiming));
-        h->plans.push_back(std::move(q));
-        plan = h->plans.back().get();
+        const char* where = nullptr;
+        const hipError_t e = make_solve_plan(h, nrhs, transpose != 0, &plan, &where);
+        if (e != hipSuccess) return hip_fail(e, where);
     }
     BM_HIP(hipMemcpyAsync(plan->bin, b, bytes, hipMemcpyDeviceToDevice, s));
     BM_HIP(hipGraphLaunch(plan->exec, s));
