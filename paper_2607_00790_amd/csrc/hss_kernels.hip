@@ -1577,13 +1577,17 @@ k_sum_partials(const double2* __restrict__ part, int ns, int64_t stride, int64_t
 // holds D[4 r + l / 16][l % 16].
 namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int kGemmK = 8;
+// K chunk per LDS stage of each tile size
+#ifndef BMHSS_GEMM_KC
+#define BMHSS_GEMM_KC 16
+#endif
+constexpr int kGemmK16 = 8, kGemmK32 = 8, kGemmK64 = BMHSS_GEMM_KC;
 
 __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int WT, int NW>
+template <int WT, int NW, int kGemmK>
 __device__ __forceinline__ void gemm_tile(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off,
                                           int njobs) {
     constexpr int SQ = NW == 4 ? 2 : 1, TT = WT * SQ, BL = WT / 16, THREADS = 64 * NW;
@@ -1691,15 +1695,15 @@ __device__ __forceinline__ void gemm_tile(const GemmJob* __restrict__ jobs, cons
 
 __global__ void __launch_bounds__(64)
 k_gemm_t16(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
-    gemm_tile<16, 1>(jobs, tile_off, njobs);
+    gemm_tile<16, 1, kGemmK16>(jobs, tile_off, njobs);
 }
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
 k_gemm(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
-    gemm_tile<32, 1>(jobs, tile_off, njobs);
+    gemm_tile<32, 1, kGemmK32>(jobs, tile_off, njobs);
 }
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_gemm_t64(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_off, int njobs) {
-    gemm_tile<32, 4>(jobs, tile_off, njobs);
+    gemm_tile<32, 4, kGemmK64>(jobs, tile_off, njobs);
 }
 
 // Batched strided complex products with few columns (N <= kGemvMaxN, the
