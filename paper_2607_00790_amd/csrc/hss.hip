@@ -1043,6 +1043,13 @@ int count_unknowns(const Slot* s, size_t n) {
 
 }  // namespace
 
+// Library streams (non-blocking, default priority) are costly to create and
+// destroy (hundreds of microseconds each on this runtime), so they are kept in
+// a per-device pool: the build's second stream and the capture stream of each
+// recorded solve come from it and go back to it.
+hipError_t aux_stream_get(hipStream_t* out);
+void aux_stream_put(hipStream_t st);
+
 struct bm_hss {
     const bm_problem* p = nullptr;
     hipStream_t stream = nullptr;   // build stream: the factors' memory is tied to it
@@ -1079,7 +1086,7 @@ struct bm_hss {
                 sc->release();
                 sc.reset();
             }
-            if (cap) (void)hipStreamDestroy(cap);
+            if (cap) aux_stream_put(cap);
         }
     };
     mutable std::mutex plan_mu;
@@ -1175,6 +1182,12 @@ AuxStreams& aux_streams() {
     static AuxStreams* a = new AuxStreams;
     return *a;
 }
+}  // namespace
+
+hipError_t aux_stream_get(hipStream_t* out) { return aux_streams().get(out); }
+void aux_stream_put(hipStream_t st) { aux_streams().put(st); }
+
+namespace {
 
 // Buffers of a level whose factorisation may still be running on the second
 // stream: the compression scratch (T, slot lists, read by the factorisation)
@@ -1243,7 +1256,7 @@ hipError_t make_solve_plan(const bm_hss* h, int64_t nrhs, bool trans, bm_hss::So
     q->nrhs = nrhs;
     q->trans = trans;
     *where = "bm_hss_solve_graph: stream";
-    hipError_t e = hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking);
+    hipError_t e = aux_stream_get(&q->cap);
     if (e != hipSuccess) return e;
     q->sc = std::make_unique<Scratch>(q->cap);
     Scratch& sc = *q->sc;
@@ -1708,7 +1721,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
         {
             int64_t mu = 0, mr = 0;
             for (int c = 0; c < nk; ++c) { mu = std::max(mu, kn[c]); mr = std::max(mr, km[c]); }
-            progress("bmhss build: iteration %d: ID of %d boxes, <= %lld unknowns x %lld rows, %.2f s\n",
+            progress("bmhss build: iteration %d: ID of %d boxes, <= %lld unknowns x %lld rows, %.4f s\n",
                      static_cast<int>(h->level_info.size()), nk, static_cast<long long>(mu),
                      static_cast<long long>(mr),
                      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
@@ -1746,7 +1759,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
                 li.max_rank = std::max<int32_t>(li.max_rank, ranks[c]);
             }
             h->level_info.push_back(li);
-            progress("bmhss build: iteration %d: %d boxes, <= %d unknowns, <= %d rows, ranks %d..%d, %.2f s\n",
+            progress("bmhss build: iteration %d: %d boxes, <= %d unknowns, <= %d rows, ranks %d..%d, %.4f s\n",
                      static_cast<int>(h->level_info.size()) - 1, li.boxes, li.max_unknowns, li.max_rows,
                      li.min_rank, li.max_rank,
                      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
@@ -2015,7 +2028,7 @@ int build_impl(bm_hss* h, hipStream_t s) {
         sc.rec([=]() { return hipStreamWaitEvent(s2, rready, 0); });
         h->roots = roots;
         h->Ktot = Ktot;
-        progress("bmhss build: %d roots, %lld unknowns in total, %.2f s\n", static_cast<int>(roots.size()),
+        progress("bmhss build: %d roots, %lld unknowns in total, %.4f s\n", static_cast<int>(roots.size()),
                  static_cast<long long>(Ktot),
                  std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
         Slot* drs;
@@ -2063,6 +2076,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
             if (e == hipSuccess) e = t_fac.stop(sc, ev);
         }
         if (e == hipSuccess) e = sc.flush();
+        progress("bmhss build: root inversion enqueued, %.4f s\n",
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
         // every inversion's status, copied behind the root on the second stream
         // into pinned memory, so that one wait covers them all
         for (size_t q = 0; q < status_bufs.size(); ++q) {
@@ -2088,8 +2103,12 @@ int build_impl(bm_hss* h, hipStream_t s) {
                 (void)hipGetLastError();
                 h->plans.clear();
             }
+            progress("bmhss build: solve graph recorded, %.4f s\n",
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s2);
+        progress("bmhss build: root inverted, %.4f s\n",
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
         sc.synced();
         sc.release();
         (void)hipEventDestroy(rready);
@@ -2104,6 +2123,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
     for (int64_t i = 0; i < status_tot; ++i)
         if (status_host[i]) { cleanup(); return fail(BM_ESINGULAR, "bm_hss_build: singular block in the HSS factorisation"); }
     cleanup();
+    progress("bmhss build: done, %.4f s\n",
+             std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build0).count());
     h->stats.levels = Lmax;
     h->stats.compressed_levels = compressed;
     h->stats.root_size = static_cast<int32_t>(std::min<int64_t>(Ktot, INT32_MAX));
