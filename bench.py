@@ -44,15 +44,15 @@ FLOP_PER_PAIR = 313.9
 FLOP_PER_PAIR_MATVEC = 349.9
 MEASURED_TRAFFIC = {
     # one sweep: one launch
-    "k_dense": (2.0 * 48835.4 + 16861700.0) * 1024,
+    "k_dense": (2.0 * 48516.6 + 16864326) * 1024,
     # two HSS builds with the tuned options (gaussian sketch, unknowns + 8 rows; stop
-    # ratio 0.6; the root inverted by panels): 86 launches of k_gauss_jordan_cols<8>,
-    # 254 of the MFMA GEMM (k_gemm_t16 / k_gemm / k_gemm_t64), 8 of k_cpqr_fused,
-    # 234 of k_cpqr_step_reg<4>
-    ("k_gauss_jordan", 8, 0.6): (2.0 * 88230.9 + 159673.0) * 1024 / 86,
-    ("k_gemm", 8, 0.6): (2.0 * (2120150.0 + 1588660.0 + 770850.0) + (877144.0 + 1792310.0 + 249422.0)) * 1024 / 254,
-    ("k_cpqr_fused", 8, 0.6): (2.0 * (37010.4 + 78585.2) + (72882.4 + 156153.0)) * 1024 / 8,
-    ("k_cpqr_step_reg", 8, 0.6): (2.0 * 328784.0 + 516938.0) * 1024 / 234,
+    # ratio 0.6; the root inverted by panels): 86 launches of k_gauss_jordan_pairs<8>,
+    # 254 of the MFMA GEMM (k_gemm_t16 / k_gemm / k_gemm_t64), 10 of k_cpqr_fused
+    ("k_gauss_jordan", 8, 0.6): (2.0 * 88099.375 + 159644.0) * 1024 / 86,
+    ("k_gemm", 8, 0.6): (2.0 * (2110946.9375 + 1587614.9375 + 769759.8125)
+                         + (877782.6875 + 1789656.59375 + 249421.6875)) * 1024 / 254,
+    ("k_cpqr_fused", 8, 0.6): (2.0 * (37028.375 + 78610.0625 + 6049.75)
+                               + (72882.375 + 156152.59375 + 10894.5)) * 1024 / 10,
 }
 
 
