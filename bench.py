@@ -46,9 +46,8 @@ MEASURED_TRAFFIC = {
     # one sweep: one launch
     "k_dense": (2.0 * 48516.6 + 16864326) * 1024,
     # two HSS builds with the tuned options (gaussian sketch, unknowns + 8 rows; stop
-    # ratio 0.6; the root inverted by panels): 86 launches of k_gauss_jordan_pairs<8>,
-    # 254 of the MFMA GEMM (k_gemm_t16 / k_gemm / k_gemm_t64), 10 of k_cpqr_fused
-    ("k_gauss_jordan", 8, 0.6): (2.0 * 88099.375 + 159644.0) * 1024 / 86,
+    # ratio 0.6; the root inverted by panels): 254 launches of the MFMA GEMM
+    # (k_gemm_t16 / k_gemm / k_gemm_t64), 10 of k_cpqr_fused
     ("k_gemm", 8, 0.6): (2.0 * (2110946.9375 + 1587614.9375 + 769759.8125)
                          + (877782.6875 + 1789656.59375 + 249421.6875)) * 1024 / 254,
     ("k_cpqr_fused", 8, 0.6): (2.0 * (37028.375 + 78610.0625 + 6049.75)

@@ -397,12 +397,18 @@ int inv_base() {
     return v;
 }
 
-// Gauss-Jordan for blocks up to 64: two elimination steps per barrier (the
-// default) or one (BMHSS_TUNE_GJ_PAIRS=0).
-bool gj_pairs() {
-    static const bool v = [] {
+// Gauss-Jordan for blocks up to 64: batches whose largest block has at least
+// kGjBlockedMin rows run by panels of eight with the rank-8 updates on the
+// matrix cores, smaller ones two elimination steps per barrier (the default,
+// BMHSS_TUNE_GJ_PAIRS=1), or one step per barrier for every size
+// (BMHSS_TUNE_GJ_PAIRS=0); BMHSS_TUNE_GJ_PAIRS=2 takes the two-step kernel
+// for every size.
+constexpr int kGjBlockedMin = 48;
+int gj_pairs() {
+    static const int v = [] {
         const char* e = std::getenv("BMHSS_TUNE_GJ_PAIRS");
-        return !(e && std::atoi(e) == 0);
+        const int q = e ? std::atoi(e) : 1;
+        return (q >= 0 && q <= 2) ? q : 1;
     }();
     return v;
 }
@@ -735,7 +741,9 @@ hipError_t launch_inverse(Scratch& sc, const std::vector<InvJob>& jobs) {
             for (const InvJob& j : base) g_ktimes->inv_flops += 8.0 * j.n * j.n * j.n;
         sc.rec([=]() {
             if (ea) (void)hipEventRecord(ea, st);
-            if (nbase <= 64 && gj_pairs())
+            if (nbase <= 64 && nbase >= kGjBlockedMin && gj_pairs() == 1)
+                hipLaunchKernelGGL(k_gauss_jordan_blk, dim3(nj), dim3(512), kGjbLdsBytes, st, dj);
+            else if (nbase <= 64 && gj_pairs())
                 hipLaunchKernelGGL(k_gauss_jordan_pairs<8>, dim3(nj), dim3(512), 0, st, dj);
             else if (nbase <= 64)
                 hipLaunchKernelGGL(k_gauss_jordan_cols<8>, dim3(nj), dim3(512), 0, st, dj);

@@ -1706,6 +1706,158 @@ k_gemm_t64(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
     gemm_tile<32, 4, kGemmK64>(jobs, tile_off, njobs);
 }
 
+// ---------------------------------------------------------------------------
+// Gauss-Jordan of one block of n <= 64 by panels of eight columns, the block
+// held in LDS.  Wave 0 loads a panel (a row per lane) and runs its eight
+// elimination steps on those eight columns alone, with the pivot rule and
+// exchange arithmetic of gauss_jordan_cols; the panel then holds W = M E_P
+// (M the product of the eight exchanges, E_P the unit columns of the pivot
+// rows p_0..p_7), since an exchange fixes every unit vector but its own
+// pivot's.  Every other column follows from one rank-8 product,
+//   a_new = (a with rows p_k zeroed) + W a[P, :],
+// which the eight waves compute on the FP64 matrix cores, a 16-row block of
+// two 16-column blocks each (four real products per 4-deep step, the operand
+// layout of gemm_tile).  The rows p_k are read by every wave before any wave
+// writes (a barrier between), the panel's own columns are not overwritten.
+// Pivoting is logical and the result is stored permuted, as in the other
+// kernels; a tiny or missing pivot ends the block with status 1 after the
+// barrier, leaving the matrix unwritten.
+namespace {
+constexpr int kGjbLd = 65;   // complex values per LDS row (one of padding)
+
+__device__ void gauss_jordan_blocked(const InvJob& jb) {
+    extern __shared__ double2 gjb_lds[];
+    double2* A = gjb_lds;                       // 64 x kGjbLd
+    __shared__ int pvt[8];                       // the panel's pivot rows
+    __shared__ int perm[64], pinv[64];
+    __shared__ int bad;
+    __shared__ double wmax[8];
+    const int n = jb.n;
+    const int64_t ld = jb.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double m2 = 0.0;
+    for (int idx = tid; idx < 64 * 64; idx += 512) {
+        const int i = idx >> 6, j = idx & 63;
+        const double2 v = (i < n && j < n) ? gload2(jb.a + i * ld + j) : make_double2(0.0, 0.0);
+        A[i * kGjbLd + j] = v;
+        m2 = fmax(m2, cabs2(v));
+    }
+    {
+        const int q = wave_argmax_f32(static_cast<float>(m2));
+        const double wm = q < 0 ? 0.0 : readlane_d(m2, q);
+        if (lane == 0) wmax[wave] = wm;
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    m2 = wmax[0];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) m2 = fmax(m2, wmax[w]);
+    const double tiny2 = (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16) * m2;
+    const double rscale = m2 > 0.0 ? recip(m2) : 0.0;
+    const bool rowok = lane < n;
+    uint64_t used = 0;   // pivot rows so far (kept by wave 0)
+    const int rb = wave & 3, cb0 = 2 * (wave >> 2);   // this wave's output blocks
+    const int fl = lane & 15, fk = lane >> 4;
+    for (int p0 = 0; p0 < n; p0 += 8) {
+        const int np = n - p0 < 8 ? n - p0 : 8;
+        if (wave == 0) {
+            double2 c[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) c[t] = A[lane * kGjbLd + p0 + t];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t >= np) break;   // uniform
+                const bool cand = rowok && !((used >> lane) & 1);
+                const float mag = cand ? static_cast<float>(cabs2(c[t]) * rscale) : -1.0f;
+                int p = wave_argmax_f32(mag);
+                double2 pv = make_double2(0.0, 0.0);
+                if (p >= 0) {
+                    pv = readlane2(c[t], p);
+                    const double pd = cabs2(pv);
+                    if (!(pd > tiny2) || !(pd < INFINITY)) p = -1;
+                }
+                if (p < 0) {
+                    if (lane == 0) bad = 1;
+                    break;
+                }
+                gj_exchange<8>(c, p, c[t], pv, t, lane);
+                used |= 1ull << p;
+                if (lane == 0) {
+                    pvt[t] = p;
+                    perm[p0 + t] = p;
+                    pinv[p] = p0 + t;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) A[lane * kGjbLd + p0 + t] = c[t];
+        }
+        __syncthreads();
+        if (bad) {
+            if (tid == 0) gst(jb.status, 1);
+            return;   // every wave read the flag after the barrier
+        }
+        // operands of the rank-np product: W (panel columns) and the pivot rows
+        uint64_t pmask = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < np) pmask |= 1ull << pvt[k];
+        double war[2], wai[2];   // W[16 rb + fl][4 s + fk]
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double2 w = A[(16 * rb + fl) * kGjbLd + p0 + 4 * s + fk];
+            war[s] = w.x;
+            wai[s] = w.y;
+        }
+        double br[2][2], bi[2][2];   // [block][s]: a[p_{4s+fk}][16 cb + fl]
+        v4d accr[2], acci[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int cb = cb0 + x;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int k = 4 * s + fk;
+                const double2 r = k < np ? A[pvt[k] * kGjbLd + 16 * cb + fl] : make_double2(0.0, 0.0);
+                br[x][s] = r.x;
+                bi[x][s] = r.y;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rb + 4 * r + fk;
+                const double2 cv = (pmask >> row) & 1 ? make_double2(0.0, 0.0) : A[row * kGjbLd + 16 * cb + fl];
+                accr[x][r] = cv.x;
+                acci[x][r] = cv.y;
+            }
+        }
+        __syncthreads();   // every pivot row read before any is overwritten
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                accr[x] = mfma16(war[s], br[x][s], accr[x]);
+                accr[x] = mfma16(-wai[s], bi[x][s], accr[x]);
+                acci[x] = mfma16(war[s], bi[x][s], acci[x]);
+                acci[x] = mfma16(wai[s], br[x][s], acci[x]);
+            }
+            const int col = 16 * (cb0 + x) + fl;
+            if (col < p0 || col >= p0 + 8) {   // the panel keeps W
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    A[(16 * rb + 4 * r + fk) * kGjbLd + col] = make_double2(accr[x][r], acci[x][r]);
+            }
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < 64 * 64; idx += 512) {
+        const int i = idx >> 6, j = idx & 63;
+        if (i < n && j < n) gstore2(jb.a + static_cast<int64_t>(pinv[i]) * ld + perm[j], A[i * kGjbLd + j]);
+    }
+}
+}  // namespace
+
+__global__ void __launch_bounds__(512) k_gauss_jordan_blk(const InvJob* __restrict__ jobs) {
+    gauss_jordan_blocked(jobs[blockIdx.x]);
+}
+
 // Batched strided complex products with few columns (N <= kGemvMaxN, the
 // solves): C = alpha A B + beta C.  With A's rows contiguous (a_cs == 1) one
 // wave computes one row of C: its lanes stride along the row and the partial
