@@ -135,7 +135,7 @@ __global__ void k_gauss_jordan_pairs(const InvJob* jobs);
 // the same inverse by panels of eight columns, the block in LDS (dynamic
 // shared memory: kGjbLdsBytes), the rank-8 updates on the matrix cores
 __global__ void k_gauss_jordan_blk(const InvJob* jobs);
-constexpr int kGjbLdsBytes = 64 * 65 * 16;
+constexpr int kGjbLdsBytes = (64 * 65 + 8 * 64) * 16;
 __global__ void k_gauss_jordan_32(const InvJob* jobs);
 __global__ void k_cpqr_init(const CpqrJob* jobs);
 __global__ void k_cpqr_step(const CpqrJob* jobs, int k, double tol);

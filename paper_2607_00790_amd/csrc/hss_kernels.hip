@@ -1717,19 +1717,38 @@ k_gemm_t64(const GemmJob* __restrict__ jobs, const int64_t* __restrict__ tile_of
 //   a_new = (a with rows p_k zeroed) + W a[P, :],
 // which the eight waves compute on the FP64 matrix cores, a 16-row block of
 // two 16-column blocks each (four real products per 4-deep step, the operand
-// layout of gemm_tile).  The rows p_k are read by every wave before any wave
-// writes (a barrier between), the panel's own columns are not overwritten.
-// Pivoting is logical and the result is stored permuted, as in the other
-// kernels; a tiny or missing pivot ends the block with status 1 after the
-// barrier, leaving the matrix unwritten.
+// layout of gemm_tile).  Wave 0 copies the rows p_k, before the product, into
+// a buffer of their own, so that the waves need not wait for each other
+// between reading them and overwriting the block; the panel's own columns
+// are not overwritten.  The eight steps are straight-line code (no branch
+// depends on the data): each step updates the next column first, so that the
+// next pivot search can overlap the update of the other columns.  Pivoting
+// is logical and the result is stored permuted, as in the other kernels; a
+// tiny or missing pivot ends the block with status 1 after the barrier,
+// leaving the matrix unwritten.
 namespace {
-constexpr int kGjbLd = 65;   // complex values per LDS row (one of padding)
+constexpr int kGjbLd = 65;   // complex values per LDS row of the block (one of padding)
+
+// The lowest lane holding the wave's largest positive `mag`, or -1 (as
+// wave_argmax_f32, without a branch)
+__device__ __forceinline__ int wave_argmax_f32_nb(float mag) {
+    float m = dpp_fmax<0x111, 0xF>(mag);
+    m = dpp_fmax<0x112, 0xF>(m);
+    m = dpp_fmax<0x114, 0xF>(m);
+    m = dpp_fmax<0x118, 0xF>(m);
+    m = dpp_fmax<0x142, 0xA>(m);
+    m = dpp_fmax<0x143, 0xC>(m);
+    const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 63));
+    const uint64_t hit = __builtin_amdgcn_ballot_w64(mag == mx);
+    return mx > 0.0f && hit ? static_cast<int>(__builtin_ctzll(hit)) : -1;
+}
 
 __device__ void gauss_jordan_blocked(const InvJob& jb) {
     extern __shared__ double2 gjb_lds[];
-    double2* A = gjb_lds;                       // 64 x kGjbLd
-    __shared__ int pvt[8];                       // the panel's pivot rows
+    double2* A = gjb_lds;                        // 64 x kGjbLd
+    double2* Rb = gjb_lds + 64 * kGjbLd;         // the panel's pivot rows, 8 x 64
     __shared__ int perm[64], pinv[64];
+    __shared__ uint64_t pmask_s;
     __shared__ int bad;
     __shared__ double wmax[8];
     const int n = jb.n;
@@ -1764,43 +1783,67 @@ __device__ void gauss_jordan_blocked(const InvJob& jb) {
             double2 c[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) c[t] = A[lane * kGjbLd + p0 + t];
+            int pk[8];
+            bool fail = false;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                if (t >= np) break;   // uniform
+                const bool act = t < np;   // uniform
                 const bool cand = rowok && !((used >> lane) & 1);
                 const float mag = cand ? static_cast<float>(cabs2(c[t]) * rscale) : -1.0f;
-                int p = wave_argmax_f32(mag);
-                double2 pv = make_double2(0.0, 0.0);
-                if (p >= 0) {
-                    pv = readlane2(c[t], p);
-                    const double pd = cabs2(pv);
-                    if (!(pd > tiny2) || !(pd < INFINITY)) p = -1;
+                const int q = wave_argmax_f32_nb(mag);
+                const double2 pq = readlane2(c[t], q < 0 ? 0 : q);
+                const double pd = cabs2(pq);
+                const bool ok = q >= 0 && pd > tiny2 && pd < INFINITY;
+                fail = fail || (act && !ok);
+                const bool go = act && ok;   // uniform
+                const int p = go ? q : 0;
+                const double2 pv = go ? pq : make_double2(1.0, 0.0);
+                const double rpd = recip(cabs2(pv));
+                const double2 inv = make_double2(pv.x * rpd, -pv.y * rpd);
+                const bool isp = go && lane == p;
+                const double2 g = isp ? make_double2(-inv.x, -inv.y) : (go ? cmul(c[t], inv) : make_double2(0.0, 0.0));
+                const double sc = isp ? 0.0 : 1.0;
+                // the next column first, then the others; column t becomes -g
+#pragma unroll
+                for (int k = 1; k < 8; ++k) {
+                    const int u = (t + k) & 7;
+                    const double2 r = readlane2(c[u], p);
+                    c[u] = make_double2(fma(-g.x, r.x, fma(g.y, r.y, c[u].x * sc)),
+                                        fma(-g.x, r.y, fma(-g.y, r.x, c[u].y * sc)));
                 }
-                if (p < 0) {
-                    if (lane == 0) bad = 1;
-                    break;
-                }
-                gj_exchange<8>(c, p, c[t], pv, t, lane);
-                used |= 1ull << p;
-                if (lane == 0) {
-                    pvt[t] = p;
-                    perm[p0 + t] = p;
-                    pinv[p] = p0 + t;
-                }
+                if (go) c[t] = make_double2(-g.x, -g.y);   // uniform select
+                used |= go ? (1ull << p) : 0ull;
+                pk[t] = go ? p : -1;
             }
+            // W back into the block; the pivot rows' current values (outside the
+            // panel: before this panel's product) into their buffer
 #pragma unroll
             for (int t = 0; t < 8; ++t) A[lane * kGjbLd + p0 + t] = c[t];
+            uint64_t pm = 0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int q = pk[t] < 0 ? 0 : pk[t];
+                Rb[t * 64 + lane] = pk[t] < 0 ? make_double2(0.0, 0.0) : A[q * kGjbLd + lane];
+                pm |= pk[t] < 0 ? 0ull : (1ull << q);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (pk[t] >= 0) {
+                        perm[p0 + t] = pk[t];
+                        pinv[pk[t]] = p0 + t;
+                    }
+                pmask_s = pm;
+                if (fail) bad = 1;
+            }
         }
         __syncthreads();
         if (bad) {
             if (tid == 0) gst(jb.status, 1);
             return;   // every wave read the flag after the barrier
         }
-        // operands of the rank-np product: W (panel columns) and the pivot rows
-        uint64_t pmask = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (k < np) pmask |= 1ull << pvt[k];
+        // the rank-np product: W (the panel's columns) times the pivot rows
+        const uint64_t pmask = pmask_s;
         double war[2], wai[2];   // W[16 rb + fl][4 s + fk]
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -1808,27 +1851,26 @@ __device__ void gauss_jordan_blocked(const InvJob& jb) {
             war[s] = w.x;
             wai[s] = w.y;
         }
-        double br[2][2], bi[2][2];   // [block][s]: a[p_{4s+fk}][16 cb + fl]
+        double br[2][2], bi[2][2];   // [block][s]: row p_{4s+fk}, column 16 cb + fl
         v4d accr[2], acci[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
             const int cb = cb0 + x;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const int k = 4 * s + fk;
-                const double2 r = k < np ? A[pvt[k] * kGjbLd + 16 * cb + fl] : make_double2(0.0, 0.0);
+                const double2 r = Rb[(4 * s + fk) * 64 + 16 * cb + fl];
                 br[x][s] = r.x;
                 bi[x][s] = r.y;
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * rb + 4 * r + fk;
-                const double2 cv = (pmask >> row) & 1 ? make_double2(0.0, 0.0) : A[row * kGjbLd + 16 * cb + fl];
-                accr[x][r] = cv.x;
-                acci[x][r] = cv.y;
+                const double2 cv = A[row * kGjbLd + 16 * cb + fl];
+                const bool z = (pmask >> row) & 1;
+                accr[x][r] = z ? 0.0 : cv.x;
+                acci[x][r] = z ? 0.0 : cv.y;
             }
         }
-        __syncthreads();   // every pivot row read before any is overwritten
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
 #pragma unroll
