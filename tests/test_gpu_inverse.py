@@ -1,8 +1,9 @@
 """GPU tests of the dense inverse the HSS factorisation uses (bm_dense_inverse:
-Gauss-Jordan for blocks up to 64, block Gauss-Jordan over 64-column panels
-with look-ahead up to 4096, the Schur recursion above), against NumPy's
-LAPACK inverse, and of its singular-pivot reporting, directly and through the
-build's test hook.
+Gauss-Jordan for blocks up to 64 -- by panels of eight columns with the
+rank-8 updates on the matrix cores from 48 rows, two elimination steps per
+barrier below --, block Gauss-Jordan over 64-column panels with look-ahead up
+to 4096, the Schur recursion above), against NumPy's LAPACK inverse, and of
+its singular-pivot reporting, directly and through the build's test hook.
 
 The bar: the inverse of a matrix with condition number kappa is determined
 to about kappa * eps; these matrices have kappa below ~100 (a Gaussian matrix
@@ -45,7 +46,7 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 31, 32, 33, 47, 63, 64])
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 31, 32, 33, 47, 48, 55, 63, 64])
 def test_gauss_jordan_blocks_vs_lapack(gpu_lib, n):
     """Blocks up to 64: one workgroup, pivoting over every row (a plain Gaussian
     matrix, no diagonal shift, so the pivot order is not the identity)."""
@@ -88,7 +89,7 @@ def test_schur_recursion_inverse_residual(gpu_lib):
     assert res <= BAR
 
 
-@pytest.mark.parametrize("n", [5, 40, 64])
+@pytest.mark.parametrize("n", [5, 40, 56, 64])
 def test_singular_block_reported_and_left_unchanged(gpu_lib, n):
     """A zero row: the kernel ends normally with BM_ESINGULAR, the matrix is
     left as it was (no NaN), and the next call on a good matrix succeeds."""
