@@ -870,8 +870,24 @@ hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
     for (int64_t o = 0; o < K; o += b0, buf ^= 1) {
         const int64_t b = std::min(b0, K - o);
         double2* App = j.a + o * ld + o;
-        if ((e = launch_inverse(sc, {InvJob{App, j.status, ld, static_cast<int32_t>(b)}})) != hipSuccess) return e;
-        {
+        const InvJob diag{App, j.status, ld, static_cast<int32_t>(b)};
+        if (b >= kGjBlockedMin && b <= 64 && gj_pairs() == 1) {
+            // the diagonal block's inverse and the panel preparation in one launch
+            double2* a = j.a;
+            double2* Lp = L[buf];
+            const unsigned grid = 1 + static_cast<unsigned>(std::min<int64_t>(ceil_div(K * b, 512), 2048));
+            const int bb = static_cast<int>(b);
+            hipEvent_t ea = nullptr, eb = nullptr;
+            if (g_ktimes && timed_pair(g_ktimes->inv, &ea, &eb)) g_ktimes->inv_flops += 8.0 * b * b * b;
+            sc.rec([=]() {
+                if (ea) (void)hipEventRecord(ea, sa);
+                hipLaunchKernelGGL(k_gauss_jordan_blk_panel, dim3(grid), dim3(512), kGjbLdsBytes, sa, diag, a, ld, K,
+                                   o, bb, Lp, Pt);
+                if (eb) (void)hipEventRecord(eb, sa);
+                return hipGetLastError();
+            });
+        } else {
+            if ((e = launch_inverse(sc, {diag})) != hipSuccess) return e;
             double2* a = j.a;
             double2* Lp = L[buf];
             const unsigned grid = static_cast<unsigned>(std::min<int64_t>(ceil_div(K * b, kThreads), 2048));

@@ -1743,7 +1743,11 @@ __device__ __forceinline__ int wave_argmax_f32_nb(float mag) {
     return mx > 0.0f && hit ? static_cast<int>(__builtin_ctzll(hit)) : -1;
 }
 
-__device__ void gauss_jordan_blocked(const InvJob& jb) {
+// PANEL = false: the inverse is stored in place; true: it goes to pt
+// (row-major, row stride n) and the block itself becomes the identity (the
+// panel inverse's diagonal block, see k_gauss_jordan_blk_panel).
+template <bool PANEL>
+__device__ __forceinline__ void gauss_jordan_blocked(const InvJob& jb, double2* __restrict__ pt) {
     extern __shared__ double2 gjb_lds[];
     double2* A = gjb_lds;                        // 64 x kGjbLd
     double2* Rb = gjb_lds + 64 * kGjbLd;         // the panel's pivot rows, 8 x 64
@@ -1891,13 +1895,47 @@ __device__ void gauss_jordan_blocked(const InvJob& jb) {
     }
     for (int idx = tid; idx < 64 * 64; idx += 512) {
         const int i = idx >> 6, j = idx & 63;
-        if (i < n && j < n) gstore2(jb.a + static_cast<int64_t>(pinv[i]) * ld + perm[j], A[i * kGjbLd + j]);
+        if (i >= n || j >= n) continue;
+        if constexpr (PANEL) {
+            gstore2(pt + pinv[i] * n + perm[j], A[i * kGjbLd + j]);
+            gstore2(jb.a + i * ld + j, make_double2(i == j ? 1.0 : 0.0, 0.0));
+        } else {
+            gstore2(jb.a + static_cast<int64_t>(pinv[i]) * ld + perm[j], A[i * kGjbLd + j]);
+        }
     }
 }
 }  // namespace
 
 __global__ void __launch_bounds__(512) k_gauss_jordan_blk(const InvJob* __restrict__ jobs) {
-    gauss_jordan_blocked(jobs[blockIdx.x]);
+    gauss_jordan_blocked<false>(jobs[blockIdx.x], nullptr);
+}
+
+// One panel step of the panel inverse in one launch: workgroup 0 inverts the
+// diagonal block A[o:o+b, o:o+b] (the blocked Gauss-Jordan, b >= 48), writing
+// the inverse to Pt (b x b) and the identity into the block; the other
+// workgroups move the rest of the panel's column block to L (K x b, its rows
+// o..o+b zero) and zero it in A -- what k_panel_prep does after the separate
+// inverse, on rows the inverse never touches.
+__global__ void __launch_bounds__(512)
+k_gauss_jordan_blk_panel(InvJob diag, double2* __restrict__ A, int64_t ld, int64_t K, int64_t o, int b,
+                         double2* __restrict__ L, double2* __restrict__ Pt) {
+    if (blockIdx.x == 0) {
+        gauss_jordan_blocked<true>(diag, Pt);
+        return;
+    }
+    const int64_t total = K * b;
+    const int64_t stride = static_cast<int64_t>(gridDim.x - 1) * 512;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x - 1) * 512 + threadIdx.x; e < total; e += stride) {
+        const int64_t i = e / b;
+        const int c = static_cast<int>(e - i * b);
+        if (i >= o && i < o + b) {
+            gstore2(L + i * b + c, make_double2(0.0, 0.0));
+        } else {
+            double2* a = A + i * ld + o + c;
+            gstore2(L + i * b + c, gload2(a));
+            gstore2(a, make_double2(0.0, 0.0));
+        }
+    }
 }
 
 // Batched strided complex products with few columns (N <= kGemvMaxN, the
