@@ -865,6 +865,72 @@ hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
                                 b, mone, one));
         jobs.push_back(gemm(eye, b0, 1, Rp + c0, K, 1, j.a + o * ld + c0, ld, 1, b, nc, b, one, zero));
     };
+    if (b0 == 64 && gj_pairs() == 1) {
+        // One stream, no events: each panel's launch (k_gauss_jordan_blk_panel)
+        // inverts its diagonal block, moves its column block to L and applies
+        // the previous panel's trailing update to every other column panel; the
+        // R product and the next block column's update follow.  A last panel
+        // narrower than the blocked kernel takes the separate launches.
+        const int npan = static_cast<int>(ceil_div(K, 64));
+        int64_t po = -1;   // the previous panel, whose trailing update is pending
+        int pb = 0;
+        int buf = 0;
+        for (int64_t o = 0; o < K; o += b0, buf ^= 1) {
+            const int64_t b = std::min(b0, K - o);
+            double2* App = j.a + o * ld + o;
+            const InvJob diag{App, j.status, ld, static_cast<int32_t>(b)};
+            const double2* Lq = L[buf ^ 1];
+            const double2* Rq = R[buf ^ 1];
+            if (b >= kGjBlockedMin) {
+                double2* a = j.a;
+                double2* Lc = L[buf];
+                const int ncopy = static_cast<int>(std::min<int64_t>(ceil_div(K * b, 512), 2048));
+                const int ntile = po >= 0 ? npan * (npan - 1) : 0;
+                const unsigned grid = 1 + static_cast<unsigned>(ncopy + ntile);
+                const int bb = static_cast<int>(b);
+                const int64_t pq = po;
+                const int pw = pb;
+                // timed with the matrix-core products: its work is the trailing
+                // update's 8 K^2 pb flops and the inverse's 8 b^3
+                hipEvent_t ea = nullptr, eb = nullptr;
+                if (g_ktimes && timed_pair(g_ktimes->gemm, &ea, &eb))
+                    g_ktimes->gemm_flops += 8.0 * b * b * b + (po >= 0 ? 8.0 * K * K * pb : 0.0);
+                sc.rec([=]() {
+                    if (ea) (void)hipEventRecord(ea, sa);
+                    hipLaunchKernelGGL(k_gauss_jordan_blk_panel, dim3(grid), dim3(512), kGjbLdsBytes, sa, diag, a, ld,
+                                       K, o, bb, Lc, Pt, ncopy, pq, pw, Lq, Rq, npan);
+                    if (eb) (void)hipEventRecord(eb, sa);
+                    return hipGetLastError();
+                });
+            } else {
+                if (po >= 0) {
+                    std::vector<GemmJob> rest;
+                    update_jobs(rest, po, pb, Lq, Rq, 0, o);
+                    update_jobs(rest, po, pb, Lq, Rq, o + b, K);
+                    if ((e = launch_gemm(sc, rest)) != hipSuccess) return e;
+                }
+                if ((e = launch_inverse(sc, {diag})) != hipSuccess) return e;
+                double2* a = j.a;
+                double2* Lc = L[buf];
+                const unsigned grid = static_cast<unsigned>(std::min<int64_t>(ceil_div(K * b, kThreads), 2048));
+                const int bb = static_cast<int>(b);
+                sc.rec([=]() {
+                    hipLaunchKernelGGL(k_panel_prep, dim3(grid), dim3(kThreads), 0, sa, a, ld, K, o, bb, Lc, Pt);
+                    return hipGetLastError();
+                });
+            }
+            if ((e = launch_gemm(sc, {gemm(Pt, b, 1, j.a + o * ld, ld, 1, R[buf], K, 1, b, K, b)})) != hipSuccess)
+                return e;
+            const int64_t on = o + b, bn = std::min(b0, K - on);   // the next panel
+            std::vector<GemmJob> upd;
+            update_jobs(upd, o, b, L[buf], R[buf], bn <= 0 ? 0 : on, bn <= 0 ? K : on + bn);
+            if ((e = launch_gemm(sc, upd)) != hipSuccess) return e;
+            if (bn <= 0) break;
+            po = o;
+            pb = static_cast<int>(b);
+        }
+        return hipSuccess;
+    }
     hipEvent_t upd_done = nullptr;   // the second stream's update of the previous panel
     int buf = 0;
     for (int64_t o = 0; o < K; o += b0, buf ^= 1) {
@@ -882,7 +948,8 @@ hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
             sc.rec([=]() {
                 if (ea) (void)hipEventRecord(ea, sa);
                 hipLaunchKernelGGL(k_gauss_jordan_blk_panel, dim3(grid), dim3(512), kGjbLdsBytes, sa, diag, a, ld, K,
-                                   o, bb, Lp, Pt);
+                                   o, bb, Lp, Pt, static_cast<int>(grid - 1), int64_t{-1}, 0,
+                                   static_cast<const double2*>(nullptr), static_cast<const double2*>(nullptr), 1);
                 if (eb) (void)hipEventRecord(eb, sa);
                 return hipGetLastError();
             });

@@ -135,10 +135,12 @@ __global__ void k_gauss_jordan_pairs(const InvJob* jobs);
 // the same inverse by panels of eight columns, the block in LDS (dynamic
 // shared memory: kGjbLdsBytes), the rank-8 updates on the matrix cores
 __global__ void k_gauss_jordan_blk(const InvJob* jobs);
-// the panel inverse's step: the diagonal block's inverse into Pt (workgroup 0)
-// and the panel preparation of k_panel_prep (the other workgroups)
+// the panel inverse's step: the diagonal block's inverse into Pt (workgroup 0),
+// the panel preparation of k_panel_prep (ncopy workgroups) and the previous
+// panel's trailing update (64 x 64 tiles, (npan - 1) npan of them)
 __global__ void k_gauss_jordan_blk_panel(InvJob diag, double2* A, int64_t ld, int64_t K, int64_t o, int b,
-                                         double2* L, double2* Pt);
+                                         double2* L, double2* Pt, int ncopy, int64_t po, int pb,
+                                         const double2* Lp, const double2* Rp, int npan);
 constexpr int kGjbLdsBytes = (64 * 65 + 8 * 64) * 16;
 __global__ void k_gauss_jordan_32(const InvJob* jobs);
 __global__ void k_cpqr_init(const CpqrJob* jobs);

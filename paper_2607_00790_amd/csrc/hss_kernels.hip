@@ -1910,32 +1910,105 @@ __global__ void __launch_bounds__(512) k_gauss_jordan_blk(const InvJob* __restri
     gauss_jordan_blocked<false>(jobs[blockIdx.x], nullptr);
 }
 
-// One panel step of the panel inverse in one launch: workgroup 0 inverts the
-// diagonal block A[o:o+b, o:o+b] (the blocked Gauss-Jordan, b >= 48), writing
-// the inverse to Pt (b x b) and the identity into the block; the other
-// workgroups move the rest of the panel's column block to L (K x b, its rows
-// o..o+b zero) and zero it in A -- what k_panel_prep does after the separate
-// inverse, on rows the inverse never touches.
+namespace {
+// One 64 x 64 tile (rows i0.., columns j0..) of the previous panel's trailing
+// update in the panel inverse: rows outside that panel (po, pb) get
+// A -= Lp_i Rp_j, its own rows A = Rp (Lp: K x pb row-major with zeros in the
+// panel's rows, Rp: pb x K row-major).  Eight waves, each 16 rows by two
+// 16-column blocks, the operands read straight from memory (L2) in the
+// MFMA layout of gemm_tile, four real products per 4-deep step.
+__device__ __forceinline__ void panel_rest_tile(double2* __restrict__ A, int64_t ld, int64_t K, int64_t po, int pb,
+                                                const double2* __restrict__ Lp, const double2* __restrict__ Rp,
+                                                int64_t i0, int64_t j0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fl = lane & 15, fk = lane >> 4;
+    const int64_t r0 = i0 + 16 * (wave & 3), c0 = j0 + 32 * (wave >> 2);
+    v4d accr[2], acci[2];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) accr[y] = acci[y] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t lrow = r0 + fl;
+    for (int kc = 0; kc < pb; kc += 16) {
+        double2 lv[4], rv[2][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kc + 4 * s + fk;
+            lv[s] = (lrow < K && k < pb) ? gload2(Lp + lrow * pb + k) : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int64_t col = c0 + 16 * y + fl;
+                rv[y][s] = (col < K && k < pb) ? gload2(Rp + static_cast<int64_t>(k) * K + col) : make_double2(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                accr[y] = mfma16(lv[s].x, rv[y][s].x, accr[y]);
+                accr[y] = mfma16(-lv[s].y, rv[y][s].y, accr[y]);
+                acci[y] = mfma16(lv[s].x, rv[y][s].y, acci[y]);
+                acci[y] = mfma16(lv[s].y, rv[y][s].x, acci[y]);
+            }
+    }
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+        const int64_t col = c0 + 16 * y + fl;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = r0 + 4 * r + fk;
+            if (row >= K || col >= K) continue;
+            double2* a = A + row * ld + col;
+            if (row >= po && row < po + pb) {
+                gstore2(a, gload2(Rp + (row - po) * K + col));
+            } else {
+                const double2 v = gload2(a);
+                gstore2(a, make_double2(v.x - accr[y][r], v.y - acci[y][r]));
+            }
+        }
+    }
+}
+}  // namespace
+
+// One panel step of the panel inverse in one launch (panels of 64 columns):
+//  - workgroup 0 inverts the diagonal block A[o:o+b, o:o+b] (the blocked
+//    Gauss-Jordan, b >= 48), writing the inverse to Pt (b x b) and the
+//    identity into the block;
+//  - the next ncopy workgroups move the rest of the panel's column block to L
+//    (K x b, its rows o..o+b zero) and zero it in A (what k_panel_prep does);
+//  - the remaining workgroups, if the previous panel (po >= 0, width pb, its
+//    Lp and Rp) is given, apply its trailing update to every column panel but
+//    this one, a 64 x 64 tile each (npan panels in all).
+// The three touch disjoint parts of A: the block; this panel's columns
+// outside it; the other panels' columns.
 __global__ void __launch_bounds__(512)
 k_gauss_jordan_blk_panel(InvJob diag, double2* __restrict__ A, int64_t ld, int64_t K, int64_t o, int b,
-                         double2* __restrict__ L, double2* __restrict__ Pt) {
+                         double2* __restrict__ L, double2* __restrict__ Pt, int ncopy, int64_t po, int pb,
+                         const double2* __restrict__ Lp, const double2* __restrict__ Rp, int npan) {
     if (blockIdx.x == 0) {
         gauss_jordan_blocked<true>(diag, Pt);
         return;
     }
-    const int64_t total = K * b;
-    const int64_t stride = static_cast<int64_t>(gridDim.x - 1) * 512;
-    for (int64_t e = static_cast<int64_t>(blockIdx.x - 1) * 512 + threadIdx.x; e < total; e += stride) {
-        const int64_t i = e / b;
-        const int c = static_cast<int>(e - i * b);
-        if (i >= o && i < o + b) {
-            gstore2(L + i * b + c, make_double2(0.0, 0.0));
-        } else {
-            double2* a = A + i * ld + o + c;
-            gstore2(L + i * b + c, gload2(a));
-            gstore2(a, make_double2(0.0, 0.0));
+    if (static_cast<int>(blockIdx.x) <= ncopy) {
+        const int64_t total = K * b;
+        const int64_t stride = static_cast<int64_t>(ncopy) * 512;
+        for (int64_t e = static_cast<int64_t>(blockIdx.x - 1) * 512 + threadIdx.x; e < total; e += stride) {
+            const int64_t i = e / b;
+            const int c = static_cast<int>(e - i * b);
+            if (i >= o && i < o + b) {
+                gstore2(L + i * b + c, make_double2(0.0, 0.0));
+            } else {
+                double2* a = A + i * ld + o + c;
+                gstore2(L + i * b + c, gload2(a));
+                gstore2(a, make_double2(0.0, 0.0));
+            }
         }
+        return;
     }
+    if (po < 0) return;
+    const int t = static_cast<int>(blockIdx.x) - 1 - ncopy;   // tile of the previous panel's update
+    const int cur = static_cast<int>(o / 64);
+    const int I = t / (npan - 1), Jx = t % (npan - 1);
+    const int J = Jx < cur ? Jx : Jx + 1;
+    panel_rest_tile(A, ld, K, po, pb, Lp, Rp, static_cast<int64_t>(I) * 64, static_cast<int64_t>(J) * 64);
 }
 
 // Batched strided complex products with few columns (N <= kGemvMaxN, the
