@@ -46,10 +46,11 @@ MEASURED_TRAFFIC = {
     # one sweep: one launch
     "k_dense": (2.0 * 48516.6 + 16864326) * 1024,
     # two HSS builds with the tuned options (gaussian sketch, unknowns + 8 rows; stop
-    # ratio 0.6; the root inverted by panels): 254 launches of the MFMA GEMM
-    # (k_gemm_t16 / k_gemm / k_gemm_t64), 10 of k_cpqr_fused
-    ("k_gemm", 8, 0.6): (2.0 * (2110946.9375 + 1587614.9375 + 769759.8125)
-                         + (877782.6875 + 1789656.59375 + 249421.6875)) * 1024 / 254,
+    # ratio 0.6; the root inverted by panels on one stream): 256 launches of the
+    # matrix-core class (k_gemm_t16 x154, k_gemm x46, k_gemm_t64 x8 and the panel
+    # steps k_gauss_jordan_blk_panel x48), 10 of k_cpqr_fused
+    ("k_gemm", 8, 0.6): (2.0 * (770917.0625 + 1994889.8125 + 386684.3125 + 1506995.0625)
+                         + (249421.8125 + 735561.28125 + 305524.125 + 1821347.71875)) * 1024 / 256,
     ("k_cpqr_fused", 8, 0.6): (2.0 * (37028.375 + 78610.0625 + 6049.75)
                                + (72882.375 + 156152.59375 + 10894.5)) * 1024 / 10,
 }
@@ -533,10 +534,15 @@ def run_hss(args):
     # event-timed one by one in the extra build above, the CPQR per level in
     # every build.  Each class carries its bound and its algorithmic work.
     kern = {
+        # the matrix-core products, with the root's panel steps (each inverts a
+        # diagonal block and applies the previous panel's trailing update; its
+        # work is both, 8 K^2 b + 8 b^3 flops)
         "k_gemm": dict(seconds=kst["seconds_gemm"], launches=kst["gemm_launches"], work=kst["gemm_flops"],
-                       bound="mfma", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TF),
+                       bound="mfma", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TF,
+                       kernels=["k_gemm_t16", "k_gemm", "k_gemm_t64", "k_gauss_jordan_blk_panel"]),
         "k_gauss_jordan": dict(seconds=kst["seconds_inv"], launches=kst["inv_launches"], work=kst["inv_flops"],
-                               bound="alu", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TF),
+                               bound="alu", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TF,
+                               kernels=["k_gauss_jordan_blk", "k_gauss_jordan_pairs<8>", "k_gauss_jordan_32"]),
         "k_sketch": dict(seconds=kst["seconds_sketch"], launches=kst["sketch_launches"],
                          work=kst["sketch_flops"], bound="alu", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TF),
         "k_gen_jobs": dict(seconds=kst["seconds_gen"], launches=kst["gen_launches"],
@@ -600,7 +606,8 @@ def run_hss(args):
         # the kernel class with the largest launch time in the step; achieved =
         # its algorithmic work per launch / its average event-timed launch time
         "roofline": {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
-                     "frac": d["frac"], "traffic": traffic, "kernel": dom, "launches": d["launches"],
+                     "frac": d["frac"], "traffic": traffic, "kernel": dom,
+                     "kernels": d.get("kernels", [dom]), "launches": d["launches"],
                      ("algorithmic_flops_per_launch" if d["unit"] == "TFLOP/s" else "algorithmic_bytes_per_launch"):
                          d_work,
                      "avg_launch_ms": d["avg_launch_ms"]},
