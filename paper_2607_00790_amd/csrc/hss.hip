@@ -413,6 +413,24 @@ int gj_pairs() {
     return v;
 }
 
+// LDS requested by each panel step of the panel inverse.  The blocked
+// Gauss-Jordan needs 74 KB, which admits two of the launch's workgroups per
+// CU: a copy or trailing-update workgroup then shares the inverting
+// workgroup's SIMDs and stretches its serial chain (65-67 against 52-54 us
+// per panel step on the N = 16384 star's root).  96 KB (more than half of a
+// CU's 160 KB) keeps every CU to one workgroup of the launch; the others run
+// in more rounds, still within the inversion.  BMHSS_TUNE_PANEL_LDS_KB=0
+// requests only the 74 KB, 81..160 another size.
+size_t panel_lds_bytes() {
+    static const size_t v = [] {
+        const char* e = std::getenv("BMHSS_TUNE_PANEL_LDS_KB");
+        const int q = e ? std::atoi(e) : 96;
+        if (q == 0) return static_cast<size_t>(kGjbLdsBytes);
+        return static_cast<size_t>((q >= 81 && q <= 160) ? q : 96) * 1024;
+    }();
+    return v;
+}
+
 // Whole-box CPQR for boxes of 129..160 unknowns (five columns per lane);
 // BMHSS_TUNE_CPQR_WIDE=0 leaves them to the step-wise kernels.
 bool fused_wide() {
@@ -890,6 +908,7 @@ hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
                 const int bb = static_cast<int>(b);
                 const int64_t pq = po;
                 const int pw = pb;
+                const size_t lds = panel_lds_bytes();
                 // timed with the matrix-core products: its work is the trailing
                 // update's 8 K^2 pb flops and the inverse's 8 b^3
                 hipEvent_t ea = nullptr, eb = nullptr;
@@ -897,7 +916,7 @@ hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
                     g_ktimes->gemm_flops += 8.0 * b * b * b + (po >= 0 ? 8.0 * K * K * pb : 0.0);
                 sc.rec([=]() {
                     if (ea) (void)hipEventRecord(ea, sa);
-                    hipLaunchKernelGGL(k_gauss_jordan_blk_panel, dim3(grid), dim3(512), kGjbLdsBytes, sa, diag, a, ld,
+                    hipLaunchKernelGGL(k_gauss_jordan_blk_panel, dim3(grid), dim3(512), lds, sa, diag, a, ld,
                                        K, o, bb, Lc, Pt, ncopy, pq, pw, Lq, Rq, npan);
                     if (eb) (void)hipEventRecord(eb, sa);
                     return hipGetLastError();
@@ -943,11 +962,12 @@ hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
             double2* Lp = L[buf];
             const unsigned grid = 1 + static_cast<unsigned>(std::min<int64_t>(ceil_div(K * b, 512), 2048));
             const int bb = static_cast<int>(b);
+            const size_t lds = panel_lds_bytes();
             hipEvent_t ea = nullptr, eb = nullptr;
             if (g_ktimes && timed_pair(g_ktimes->inv, &ea, &eb)) g_ktimes->inv_flops += 8.0 * b * b * b;
             sc.rec([=]() {
                 if (ea) (void)hipEventRecord(ea, sa);
-                hipLaunchKernelGGL(k_gauss_jordan_blk_panel, dim3(grid), dim3(512), kGjbLdsBytes, sa, diag, a, ld, K,
+                hipLaunchKernelGGL(k_gauss_jordan_blk_panel, dim3(grid), dim3(512), lds, sa, diag, a, ld, K,
                                    o, bb, Lp, Pt, static_cast<int>(grid - 1), int64_t{-1}, 0,
                                    static_cast<const double2*>(nullptr), static_cast<const double2*>(nullptr), 1);
                 if (eb) (void)hipEventRecord(eb, sa);
