@@ -149,6 +149,7 @@ int bm_geom_create(int ncurves, const int64_t* n_per_curve, const double* xyd, i
     g->n = n;
     g->ncurves = ncurves;
     g->curve_lo = offsets;
+    g->host_xy.assign(h.begin(), h.begin() + 2 * n);   // the nodes are the samples themselves
     (void)hipGetDevice(&g->device);
     double* d_xyd = nullptr;
     int64_t* d_off = nullptr;

@@ -121,6 +121,40 @@ PinnedCache& pinned_cache() {
     return *c;
 }
 
+// One device-to-host read through a pinned buffer of the cache: a pageable
+// destination makes HIP stage the copy and block on it.  read() enqueues the
+// copy on s (straight into dst if no pinned buffer is to be had); after the
+// caller has synchronised s, finish() moves the bytes to dst.  The buffer goes
+// back to the cache on destruction, after s has drained if a copy may still
+// be writing it (an error between read() and finish()).
+struct PinnedRead {
+    hipStream_t s;
+    char* p = nullptr;
+    size_t cap = 0, bytes = 0;
+    void* dst = nullptr;
+    bool pending = false;
+    explicit PinnedRead(hipStream_t st) : s(st) {}
+    PinnedRead(const PinnedRead&) = delete;
+    PinnedRead& operator=(const PinnedRead&) = delete;
+    hipError_t read(void* d, const void* src, size_t n) {
+        dst = d;
+        bytes = n;
+        p = pinned_cache().get(std::max<size_t>(n, 1), &cap);
+        if (!p) return hipMemcpyAsync(d, src, n, hipMemcpyDeviceToHost, s);
+        pending = true;
+        return hipMemcpyAsync(p, src, n, hipMemcpyDeviceToHost, s);
+    }
+    void finish() {
+        if (p && pending && bytes) std::memcpy(dst, p, bytes);
+        pending = false;
+    }
+    ~PinnedRead() {
+        if (!p) return;
+        if (pending) (void)hipStreamSynchronize(s);
+        pinned_cache().put(p, cap);
+    }
+};
+
 // Device temporaries, staged descriptor uploads and recorded stream commands
 // of one phase of the build or solve.  upload() copies a host array into a
 // staging chunk whose device address is known at once; stream work is recorded
@@ -1436,39 +1470,58 @@ int build_impl(bm_hss* h, hipStream_t s) {
     h->levels = Lmax;
 
     // box centres (node means), proxy radii (proxy_ratio x the largest node
-    // distance) and proxy counts of every level of every body, from the nodes
-    std::vector<double> hx(static_cast<size_t>(N)), hy(static_cast<size_t>(N));
-    BM_HIP(hipMemcpyAsync(hx.data(), g->soa, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    BM_HIP(hipMemcpyAsync(hy.data(), g->soa + N, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    BM_HIP(hipStreamSynchronize(s));
+    // distance) and proxy counts of one level of one body, from the nodes
+    // (kept on the host by the geometry).  Each level costs a pass over the
+    // body's nodes, so a level is computed when the build first needs it: the
+    // leaves now, every other level while the GPU runs the previous level's
+    // ID (or all of them now when the proxy counts depend on the radii, which
+    // the point table's size needs).
+    std::vector<double> hxy_copy;
+    const double* hx = g->host_xy.data();
+    if (static_cast<int64_t>(g->host_xy.size()) != 2 * N) {
+        hxy_copy.resize(2 * static_cast<size_t>(N));
+        BM_HIP(hipMemcpyAsync(hxy_copy.data(), g->soa, 2 * N * sizeof(double), hipMemcpyDeviceToHost, s));
+        BM_HIP(hipStreamSynchronize(s));
+        hx = hxy_copy.data();
+    }
+    const double* hy = hx + N;
+    auto level_geometry = [&](int q, int l) {
+        BodyState& B = bodies[q];
+        if (l < 1 || l > B.L || !B.box_c[l].empty()) return;
+        const double kmax = std::max(p->media[q].k0, p->media[q].k1);
+        const int64_t nb = int64_t{1} << l;
+        B.box_c[l].resize(3 * nb);
+        B.box_p[l].resize(nb);
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t lo = B.nlo + ((b * B.nn) >> l), hi = B.nlo + (((b + 1) * B.nn) >> l);
+            double cx = 0, cy = 0;
+            for (int64_t i = lo; i < hi; ++i) { cx += hx[i]; cy += hy[i]; }
+            cx /= static_cast<double>(hi - lo);
+            cy /= static_cast<double>(hi - lo);
+            double r2 = 0;
+            for (int64_t i = lo; i < hi; ++i)
+                r2 = std::max(r2, (hx[i] - cx) * (hx[i] - cx) + (hy[i] - cy) * (hy[i] - cy));
+            const double rp = h->opts.proxy_ratio * std::sqrt(r2);
+            B.box_c[l][3 * b] = cx;
+            B.box_c[l][3 * b + 1] = cy;
+            B.box_c[l][3 * b + 2] = rp;
+            int64_t pb = P;
+            if (h->opts.proxy_adapt) pb = std::max<int64_t>(P, static_cast<int64_t>(std::ceil(2.0 * kmax * rp)) + 32);
+            B.box_p[l][b] = static_cast<int32_t>(std::min<int64_t>(pb, int64_t{1} << 20));
+        }
+    };
     std::vector<int64_t> proxies_at(Lmax + 1, 0);   // proxy points of iteration t (upper bound)
     for (int q = 0; q < nbodies; ++q) {
         BodyState& B = bodies[q];
-        const Media& md = p->media[q];
-        const double kmax = std::max(md.k0, md.k1);
         B.box_c.resize(B.L + 1);
         B.box_p.resize(B.L + 1);
         for (int l = 1; l <= B.L; ++l) {
             const int64_t nb = int64_t{1} << l;
-            B.box_c[l].resize(3 * nb);
-            B.box_p[l].resize(nb);
-            for (int64_t b = 0; b < nb; ++b) {
-                const int64_t lo = B.nlo + ((b * B.nn) >> l), hi = B.nlo + (((b + 1) * B.nn) >> l);
-                double cx = 0, cy = 0;
-                for (int64_t i = lo; i < hi; ++i) { cx += hx[i]; cy += hy[i]; }
-                cx /= static_cast<double>(hi - lo);
-                cy /= static_cast<double>(hi - lo);
-                double r2 = 0;
-                for (int64_t i = lo; i < hi; ++i)
-                    r2 = std::max(r2, (hx[i] - cx) * (hx[i] - cx) + (hy[i] - cy) * (hy[i] - cy));
-                const double rp = h->opts.proxy_ratio * std::sqrt(r2);
-                B.box_c[l][3 * b] = cx;
-                B.box_c[l][3 * b + 1] = cy;
-                B.box_c[l][3 * b + 2] = rp;
-                int64_t pb = P;
-                if (h->opts.proxy_adapt) pb = std::max<int64_t>(P, static_cast<int64_t>(std::ceil(2.0 * kmax * rp)) + 32);
-                B.box_p[l][b] = static_cast<int32_t>(std::min<int64_t>(pb, int64_t{1} << 20));
-                proxies_at[B.L - l] += B.box_p[l][b];
+            if (h->opts.proxy_adapt || l == B.L) {
+                level_geometry(q, l);
+                for (int64_t b = 0; b < nb; ++b) proxies_at[B.L - l] += B.box_p[l][b];
+            } else {
+                proxies_at[B.L - l] += nb * std::min<int64_t>(P, int64_t{1} << 20);
             }
         }
     }
@@ -1621,6 +1674,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
         std::vector<int32_t> box_body(nbox), pcount(nbox);
         std::vector<int64_t> poff(nbox + 1, 0);
         std::vector<double> hbox_c(3 * static_cast<size_t>(nbox));
+        for (int q = 0; q < nbodies; ++q)
+            if (bodies[q].active) level_geometry(q, bodies[q].level);
         for (int b = 0; b < nbox; ++b) {
             const BodyState& B = bodies[boxes[b].body];
             box_body[b] = boxes[b].body;
@@ -1673,8 +1728,12 @@ int build_impl(bm_hss* h, hipStream_t s) {
         });
         std::vector<int64_t> counts(2 * nbox);
         e = sc.flush();
-        if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), dcounts, counts.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        {
+            PinnedRead rd(s);
+            if (e == hipSuccess) e = rd.read(counts.data(), dcounts, counts.size() * sizeof(int64_t));
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess) rd.finish();
+        }
         sc.synced();
         pl.reap(false);
         if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: near counts"); }
@@ -1850,12 +1909,24 @@ int build_impl(bm_hss* h, hipStream_t s) {
             for (int c = 0; c < nk; ++c) guess = std::max(guess, kn[c] / 2);
             if (!h->level_info.empty()) guess = h->level_info.back().max_rank + h->level_info.back().max_rank / 4 + 8;
             bool fused = false;
+            // while the GPU runs the ID: issue the deferred factorisation, and
+            // compute the next level's box geometry
+            const std::function<hipError_t()> before_wait = [&]() -> hipError_t {
+                const hipError_t fe = flush_deferred();
+                for (int q = 0; q < nbodies; ++q)
+                    if (bodies[q].active) level_geometry(q, bodies[q].level - 1);
+                return fe;
+            };
             e = run_cpqr(sc, cj, &dcj, dranks, tol, ranks, c0, c1, &cpqr_launches, static_cast<int>(guess), &fused,
-                         flush_deferred);
+                         before_wait);
             cpqr_fused.push_back(fused);
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        {
+            PinnedRead rd(s);
+            if (e == hipSuccess) e = rd.read(perm.data(), dperm, perm.size() * sizeof(int32_t));
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess) rd.finish();
+        }
         sc.synced();
         if (e != hipSuccess) { sc.release(); cleanup(); return hip_fail(e, "bm_hss_build: cpqr"); }
         {

@@ -20,6 +20,7 @@ struct bm_geom {
     int device = 0;
     std::vector<int64_t> curve_lo;   // host: first node of each curve (ncurves + 1)
     double* xyd = nullptr;    // device, 6 * n: the samples x, y, x', y', x'', y'' as given
+    std::vector<double> host_xy;   // host, 2 * n: the node coordinates x then y (the HSS tree's box geometry)
 };
 
 // A problem: one geometry split into independent bodies (consecutive runs of
