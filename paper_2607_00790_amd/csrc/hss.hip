@@ -871,12 +871,17 @@ hipError_t lookahead_stream(hipStream_t* out) {
 // [0; I; 0]); R = Pt A[p, :] (which holds P in its columns p); then
 // A[i, :] -= L_i R above and below the panel and A[p, :] = I R, products on
 // the matrix cores.
-// Look-ahead: that update is split.  The caller's stream updates only the
-// next panel's block column, so the next diagonal inverse can start at once;
-// a second stream updates every other column meanwhile.  The next panel's R
-// waits for it (it reads the whole row block).  L and R alternate between two
-// buffers: a buffer is written again only after the second stream's update
-// that read it is known complete.
+// With 64-column panels and the blocked Gauss-Jordan (the default), all of it
+// runs on the caller's stream: each panel's one launch inverts its diagonal
+// block, moves its column block to L and applies the previous panel's update
+// to every column panel but its own; the R product and the next block
+// column's update follow, so the next inverse never waits for the rest.
+// Otherwise the update is split across two streams (look-ahead): the caller's
+// stream updates only the next panel's block column, so the next diagonal
+// inverse can start at once, and a second stream updates every other column
+// meanwhile; the next panel's R waits for it (it reads the whole row block).
+// In both, L and R alternate between two buffers: a buffer is written again
+// only after the update that read it is known complete.
 hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
     const int64_t K = j.n, ld = j.ld, b0 = std::min<int64_t>(inv_base(), K);
     const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0), zero = make_double2(0.0, 0.0);
@@ -893,7 +898,6 @@ hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
         if ((e = sc.upload(&eye, id)) != hipSuccess) return e;
     }
     hipStream_t sa = sc.s, sb = nullptr;
-    if ((e = lookahead_stream(&sb)) != hipSuccess) return e;
     // every product of the panels stays in the library's matrix-core kernel
     struct Restore {
         Scratch& sc;
@@ -984,6 +988,7 @@ hipError_t launch_inverse_panels(Scratch& sc, const InvJob& j) {
         }
         return hipSuccess;
     }
+    if ((e = lookahead_stream(&sb)) != hipSuccess) return e;
     hipEvent_t upd_done = nullptr;   // the second stream's update of the previous panel
     int buf = 0;
     for (int64_t o = 0; o < K; o += b0, buf ^= 1) {
