@@ -64,9 +64,12 @@ const char* bm_last_error(void);
  * row-major FP64 array: rows x, y, x'(t), y'(t), x''(t), y''(t); curves are
  * concatenated.  xyd is a device pointer if on_device != 0, else a host pointer.
  * The library computes, on the device, outward normals n = (y', -x')/|x'|,
- * weights w = (2 pi/n_c)|x'| and curvature, and keeps them.  Validation (finite
- * values, non-degenerate speed, counter-clockwise orientation) is done on the
- * host; this call synchronises `stream`.  Returns BM_EINVAL on bad input. */
+ * weights w = (2 pi/n_c)|x'| and curvature, and keeps them; it also keeps a
+ * host copy of the node coordinates x, y (16 bytes per node), from which the
+ * HSS build lays out its tree without reading the device back.  Validation
+ * (finite values, non-degenerate speed, counter-clockwise orientation) is done
+ * on the host; this call synchronises `stream`.  Returns BM_EINVAL on bad
+ * input. */
 int bm_geom_create(int ncurves, const int64_t* n_per_curve, const double* xyd, int on_device,
                    hipStream_t stream, bm_geom** out);
 int bm_geom_destroy(bm_geom* g);
