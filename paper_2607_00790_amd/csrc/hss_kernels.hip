@@ -1819,16 +1819,24 @@ __device__ __forceinline__ void gauss_jordan_blocked(const InvJob& jb, double2* 
                 used |= go ? (1ull << p) : 0ull;
                 pk[t] = go ? p : -1;
             }
-            // W back into the block; the pivot rows' current values (outside the
-            // panel: before this panel's product) into their buffer
+            // the pivot rows' current values (before this panel's product) into
+            // their buffer, and W back into the block.  All eight rows are read
+            // before anything is written, so that the reads need not wait for
+            // the writes; in the panel's columns they are then the values before
+            // the steps, which only enter products that the panel does not keep.
+            double2 rbv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int q = pk[t] < 0 ? 0 : pk[t];
+                rbv[t] = pk[t] < 0 ? make_double2(0.0, 0.0) : A[q * kGjbLd + lane];
+            }
 #pragma unroll
             for (int t = 0; t < 8; ++t) A[lane * kGjbLd + p0 + t] = c[t];
             uint64_t pm = 0;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const int q = pk[t] < 0 ? 0 : pk[t];
-                Rb[t * 64 + lane] = pk[t] < 0 ? make_double2(0.0, 0.0) : A[q * kGjbLd + lane];
-                pm |= pk[t] < 0 ? 0ull : (1ull << q);
+                Rb[t * 64 + lane] = rbv[t];
+                pm |= pk[t] < 0 ? 0ull : (1ull << pk[t]);
             }
             if (lane == 0) {
 #pragma unroll
