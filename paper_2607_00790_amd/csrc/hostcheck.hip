@@ -18,6 +18,13 @@ int bmh_id_guard(int64_t rows, int64_t unknowns, int64_t total) {
     return (bm::hss::id_box_over_budget(rows, unknowns) ? 1 : 0) | (bm::hss::id_level_over_budget(total) ? 2 : 0);
 }
 
+// The boxes of one level of a body's tree (hss_plan.hpp): centre, proxy
+// radius (box_c, 3 per box) and proxy points (box_p) of its 2^l boxes.
+void bmh_level_box_geometry(const double* x, const double* y, int64_t nlo, int64_t nn, int l, double proxy_ratio,
+                            int64_t P, int adapt, double kmax, double* box_c, int32_t* box_p) {
+    bm::hss::level_box_geometry(x, y, nlo, nn, l, proxy_ratio, P, adapt != 0, kmax, box_c, box_p);
+}
+
 // Blocks A(rows, cols) in FP32 arithmetic, as the FP32 entry path forms them
 // (coefficients rounded to FP32 entry by entry); arguments as
 // bmh_system_blocks, one curve per node given by `curve`.

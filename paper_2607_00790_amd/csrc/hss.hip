@@ -1497,23 +1497,8 @@ int build_impl(bm_hss* h, hipStream_t s) {
         const int64_t nb = int64_t{1} << l;
         B.box_c[l].resize(3 * nb);
         B.box_p[l].resize(nb);
-        for (int64_t b = 0; b < nb; ++b) {
-            const int64_t lo = B.nlo + ((b * B.nn) >> l), hi = B.nlo + (((b + 1) * B.nn) >> l);
-            double cx = 0, cy = 0;
-            for (int64_t i = lo; i < hi; ++i) { cx += hx[i]; cy += hy[i]; }
-            cx /= static_cast<double>(hi - lo);
-            cy /= static_cast<double>(hi - lo);
-            double r2 = 0;
-            for (int64_t i = lo; i < hi; ++i)
-                r2 = std::max(r2, (hx[i] - cx) * (hx[i] - cx) + (hy[i] - cy) * (hy[i] - cy));
-            const double rp = h->opts.proxy_ratio * std::sqrt(r2);
-            B.box_c[l][3 * b] = cx;
-            B.box_c[l][3 * b + 1] = cy;
-            B.box_c[l][3 * b + 2] = rp;
-            int64_t pb = P;
-            if (h->opts.proxy_adapt) pb = std::max<int64_t>(P, static_cast<int64_t>(std::ceil(2.0 * kmax * rp)) + 32);
-            B.box_p[l][b] = static_cast<int32_t>(std::min<int64_t>(pb, int64_t{1} << 20));
-        }
+        level_box_geometry(hx, hy, B.nlo, B.nn, l, h->opts.proxy_ratio, P, h->opts.proxy_adapt != 0, kmax,
+                           B.box_c[l].data(), B.box_p[l].data());
     };
     std::vector<int64_t> proxies_at(Lmax + 1, 0);   // proxy points of iteration t (upper bound)
     for (int q = 0; q < nbodies; ++q) {

@@ -32,6 +32,9 @@ def hc():
     lib.bmh_system_blocks.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
     lib.bmh_system_blocks_f32.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
     lib.bmh_id_guard.argtypes = [i64, i64, i64]
+    lib.bmh_level_box_geometry.argtypes = [vp, vp, i64, i64, ctypes.c_int, ctypes.c_double, i64, ctypes.c_int,
+                                           ctypes.c_double, vp, vp]
+    lib.bmh_level_box_geometry.restype = None
     return lib
 
 
@@ -182,6 +185,43 @@ def test_id_work_guard_decisions(hc):
     assert g(12000, 4096, 64 * 12000 * 4096) == 2     # fine per box, too much for one level
     assert g(2 ** 26, 1, 2 ** 26) == 0 and g(2 ** 26 + 1, 1, 2 ** 26 + 1) == 1
     assert g(0, 0, 0) == 0
+
+
+def test_level_box_geometry_matches_its_definition(hc):
+    """The tree's boxes and proxy circles (paper Sec. III, Fig. 2; the build's
+    host planning, hss_plan.hpp) on the nodes of the N = 16384 star, for the
+    whole curve and for a body of 5000 nodes starting at node 1000: level l has
+    2^l boxes of consecutive nodes that partition the body, each box's centre is
+    the mean of its nodes, its proxy radius 1.5 times the largest node distance
+    from the centre, so that every node lies strictly inside the circle, and its
+    proxy count is P = 64, or with adaptive counts max(P, ceil(2 k r) + 32),
+    capped at 2^20 (k = 2e6 reaches the cap on level 1)."""
+    xyd, s = sc.sample_curves([sc.star(0.3, 5)], [16384])
+    nd = geometry.discretize(xyd, s)
+    x = np.ascontiguousarray(nd.x[:, 0])
+    y = np.ascontiguousarray(nd.x[:, 1])
+    for nlo, nn in ((0, 16384), (1000, 5000)):
+        for lev in (1, 4, 8):
+            nb = 1 << lev
+            bounds = [nlo + (b * nn) // nb for b in range(nb + 1)]
+            assert bounds[0] == nlo and bounds[-1] == nlo + nn and min(np.diff(bounds)) > 0
+            for adapt, kmax in ((0, 50.0), (1, 75.0), (1, 2e6)):
+                bc = np.zeros(3 * nb)
+                bp = np.zeros(nb, dtype=np.int32)
+                hc.bmh_level_box_geometry(x.ctypes.data, y.ctypes.data, nlo, nn, lev, 1.5, 64, adapt, kmax,
+                                          bc.ctypes.data, bp.ctypes.data)
+                bc = bc.reshape(nb, 3)
+                for b in range(nb):
+                    lo, hi = bounds[b], bounds[b + 1]
+                    cx, cy = x[lo:hi].mean(), y[lo:hi].mean()
+                    dist = np.hypot(x[lo:hi] - bc[b, 0], y[lo:hi] - bc[b, 1])
+                    assert abs(bc[b, 0] - cx) <= 1e-14 and abs(bc[b, 1] - cy) <= 1e-14
+                    assert abs(bc[b, 2] - 1.5 * np.hypot(x[lo:hi] - cx, y[lo:hi] - cy).max()) <= 1e-13 * bc[b, 2]
+                    assert dist.max() < bc[b, 2]
+                    want = 64 if not adapt else min(max(64, int(np.ceil(2.0 * kmax * bc[b, 2])) + 32), 2 ** 20)
+                    assert bp[b] == want, (nlo, lev, b, adapt, bp[b], want)
+            if lev == 1:
+                assert (bp == 2 ** 20).all()   # the last case: k = 2e6 on the two largest boxes
 
 
 # ---------------------------------------------------------------------------
