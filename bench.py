@@ -748,7 +748,7 @@ def main():
     if args.sketch is None:
         args.sketch = {"hss": -1, "adjoint": -1, "batch": -1, "large": 128}.get(args.mode, 0)
     if args.gpus != 1:
-        print("this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("the library runs on one GPU (it has no multi-GPU path); --gpus must be 1", file=sys.stderr)
         return 2
     if args.calib_copy_mib > 0:
         import torch

@@ -186,3 +186,15 @@ def test_interp_decomp_rejects_bad_arguments_on_the_host(lib):
     assert call(r=None) == BM_EINVAL
     assert call(mm=None) == BM_EINVAL
     assert b"bm_interp_decomp" in lib.bm_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 ends with status 2 and says
+    why, before anything touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, env={**os.environ, "HIP_VISIBLE_DEVICES": ""})
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
