@@ -501,8 +501,9 @@ def run_hss(args):
 
     # the solve alone: eager (descriptors staged per call, synchronises) and
     # replayed from the HIP graph captured on its first call
-    # this build also times every batched GEMM and Gauss-Jordan launch with HIP
-    # events (an event pair per launch, so it is kept out of the timed steps)
+    # the HSS build below (kernel_timing) also times every batched GEMM and
+    # Gauss-Jordan launch with HIP events (an event pair per launch, so it is
+    # kept out of the timed steps)
     h = bm.bm_hss_build(p, leaf=wl.leaf, proxy_ratio=wl.proxy_ratio, proxy_points=wl.proxy_points,
                         id_tol=wl.id_tol, sketch=args.sketch, max_rank_ratio=args.max_rank_ratio,
                         kernel_timing=True)
